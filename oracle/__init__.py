@@ -1,0 +1,207 @@
+"""ORACLE -- test infrastructure only.
+
+ctypes wrapper around ``ged_oracle.c``: a plain single-threaded FP64 CPU
+implementation of GED-Walk scoring (Section 3.1, Algorithm "GED-Walk
+Computation") and lazy greedy maximisation (Section 3.2.2, Algorithm "lazy
+greedy", with the initialisation of Lemma "initialize").  Only ``tests/``, the
+smoke check and the benchmark's CPU-baseline leg use it; the GPU library never
+imports, links or calls anything here.
+
+Graphs are passed as any object with ``n``, ``row_ptr`` (int64[n+1]) and
+``col_idx`` (int32[nnz]) attributes, rows listing in-neighbours.  For directed
+graphs the reverse graph (rows = out-neighbours) must be given as ``rev``.
+
+Parity pinning: every function here is checked by ``tests/test_oracle_pins.py``
+against brute-force walk enumeration in exact rational arithmetic, the
+closed-form value of the infinite series, the paper's structural properties
+(monotonicity, submodularity, GED(V) = sum of Katz scores, vertex covers) and
+the greedy approximation guarantee.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libged_oracle.so")
+_lib = None
+
+P_I64 = ctypes.POINTER(ctypes.c_int64)
+P_I32 = ctypes.POINTER(ctypes.c_int32)
+P_F64 = ctypes.POINTER(ctypes.c_double)
+P_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+ERRORS = {-1: "bad argument", -2: "vertex out of range", -3: "alpha out of range",
+          -4: "eps out of range", -6: "out of memory", -9: "walk length limit reached"}
+
+
+def build():
+    """Compile the oracle with gcc (used by the build step; never by the GPU path)."""
+    import subprocess
+    src = os.path.join(_HERE, "ged_oracle.c")
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", src, "-o", _LIB_PATH + ".tmp",
+           "-lm"]
+    print("+", " ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} missing: run __graft_entry__.build()")
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.or_max_out_degree.argtypes = [ctypes.c_int64, P_I64, P_I32]
+    lib.or_max_out_degree.restype = ctypes.c_int64
+    lib.or_walk_totals.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_double, ctypes.c_int32,
+                                   P_F64]
+    lib.or_comb_bound.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_double]
+    lib.or_comb_bound.restype = ctypes.c_double
+    lib.or_score.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I32, ctypes.c_int32, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_int32, P_F64, P_I32, P_F64, P_F64]
+    lib.or_score_fixed.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I32, ctypes.c_int32,
+                                   ctypes.c_double, ctypes.c_int32, P_F64, P_F64]
+    lib.or_gain_ext.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I32, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P_F64]
+    lib.or_pinit_ext.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I64, P_I32, P_I32,
+                                 ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P_F64]
+    lib.or_greedy.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I64, P_I32, ctypes.c_int32,
+                              ctypes.c_double, ctypes.c_double, ctypes.c_int32, P_I32,
+                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P_I32, P_I32,
+                              P_F64, P_F64, P_F64, P_F64, P_I64, P_F64, P_I32]
+    for f in ("or_walk_totals", "or_score", "or_score_fixed", "or_gain_ext", "or_pinit_ext",
+              "or_greedy"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ck(rc):
+    if rc != 0:
+        raise ValueError(f"oracle error {rc}: {ERRORS.get(rc, '?')}")
+
+
+def _arrs(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    if ci.size == 0:
+        ci = np.zeros(1, dtype=np.int32)
+    return rp, ci
+
+
+def _grp(S):
+    S = np.ascontiguousarray(np.asarray(S, dtype=np.int32).reshape(-1))
+    buf = S if S.size else np.zeros(1, dtype=np.int32)
+    return buf, int(S.size)
+
+
+def max_out_degree(g) -> int:
+    rp, ci = _arrs(g)
+    return int(_load().or_max_out_degree(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32)))
+
+
+def default_alpha(g) -> float:
+    return 1.0 / (max_out_degree(g) + 1)
+
+
+def walk_totals(g, alpha: float, ell: int) -> np.ndarray:
+    """W[i] = alpha^i * sum_x omega_i(x), i = 0..ell."""
+    rp, ci = _arrs(g)
+    W = np.zeros(ell + 1)
+    _ck(_load().or_walk_totals(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32), alpha,
+                               ell, W.ctypes.data_as(P_F64)))
+    return W
+
+
+def comb_bound(g, alpha: float, ell: int) -> float:
+    """B_ell(V), the combinatorial tail bound (Section 3.1.2, Eq. comb-bound)."""
+    W = walk_totals(g, alpha, ell)
+    return float(_load().or_comb_bound(alpha, max_out_degree(g), W[ell]))
+
+
+def score(g, S, alpha: float, eps: float, max_ell: int = 100000):
+    """GED_{<=ell*}(S) by the paper's score algorithm.
+
+    Returns (c, ell*, B_ell*, phi) with phi[i] = alpha^i phi_i(S), i = 0..ell*.
+    """
+    rp, ci = _arrs(g)
+    Sb, sl = _grp(S)
+    c = ctypes.c_double()
+    ell = ctypes.c_int32()
+    B = ctypes.c_double()
+    phi = np.zeros(max_ell + 1)
+    _ck(_load().or_score(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                         Sb.ctypes.data_as(P_I32), sl, alpha, eps, max_ell, ctypes.byref(c),
+                         ctypes.byref(ell), ctypes.byref(B), phi.ctypes.data_as(P_F64)))
+    return c.value, ell.value, B.value, phi[: ell.value + 1].copy()
+
+
+def score_fixed(g, S, alpha: float, ell: int):
+    """GED_{<=ell}(S) at a fixed walk length; returns (c, phi[0..ell])."""
+    rp, ci = _arrs(g)
+    Sb, sl = _grp(S)
+    c = ctypes.c_double()
+    phi = np.zeros(ell + 1)
+    _ck(_load().or_score_fixed(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                               Sb.ctypes.data_as(P_I32), sl, alpha, ell, ctypes.byref(c),
+                               phi.ctypes.data_as(P_F64)))
+    return c.value, phi
+
+
+def gain(g, S, x: int, alpha: float, ell: int) -> float:
+    """L_ell(S, x) = GED_{<=ell}(S + x) - GED_{<=ell}(S), walk-counted."""
+    rp, ci = _arrs(g)
+    Sb, sl = _grp(S)
+    out = ctypes.c_double()
+    _ck(_load().or_gain_ext(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                            Sb.ctypes.data_as(P_I32), sl, int(x), alpha, ell, ctypes.byref(out)))
+    return out.value
+
+
+def pinit(g, S, alpha: float, ell: int, rev=None) -> np.ndarray:
+    """I(x) = sum_{i=1}^{ell} alpha^i P_i(S, x) for every x (0 for x in S)."""
+    rp, ci = _arrs(g)
+    rr, cr = _arrs(rev if rev is not None else g)
+    Sb, sl = _grp(S)
+    out = np.zeros(g.n)
+    _ck(_load().or_pinit_ext(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                             rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32),
+                             Sb.ctypes.data_as(P_I32), sl, alpha, ell, out.ctypes.data_as(P_F64)))
+    return out
+
+
+def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
+           forced_ell: int = 1, max_ell: int = 1 << 16, rev=None, with_score: bool = True):
+    """Greedy GED-Walk maximisation (lazy greedy with P-initialisation).
+
+    Returns a dict: group (pick order), ell/L1/U2/L2/B/evals per pick, score
+    (GED_{<=ell*} of the final group) and score_ell.
+    """
+    rp, ci = _arrs(g)
+    rr, cr = _arrs(rev if rev is not None else g)
+    fb, nf = _grp(forced if forced is not None else [])
+    grp = np.zeros(k, dtype=np.int32)
+    t_ell = np.zeros(k, dtype=np.int32)
+    t_L1 = np.zeros(k)
+    t_U2 = np.zeros(k)
+    t_L2 = np.zeros(k)
+    t_B = np.zeros(k)
+    t_ev = np.zeros(k, dtype=np.int64)
+    sc = ctypes.c_double(math.nan)
+    sc_ell = ctypes.c_int32(0)
+    _ck(_load().or_greedy(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                          rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32), k, alpha, eps,
+                          1 if lazy else 0, fb.ctypes.data_as(P_I32), nf, forced_ell, max_ell,
+                          grp.ctypes.data_as(P_I32), t_ell.ctypes.data_as(P_I32),
+                          t_L1.ctypes.data_as(P_F64), t_U2.ctypes.data_as(P_F64),
+                          t_L2.ctypes.data_as(P_F64), t_B.ctypes.data_as(P_F64),
+                          t_ev.ctypes.data_as(P_I64),
+                          ctypes.byref(sc) if with_score else None,
+                          ctypes.byref(sc_ell) if with_score else None))
+    return {"group": grp, "ell": t_ell, "L1": t_L1, "U2": t_U2, "L2": t_L2, "B": t_B,
+            "evals": t_ev, "score": sc.value, "score_ell": sc_ell.value}
