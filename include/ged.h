@@ -1,0 +1,251 @@
+/*
+ * ged.h -- C ABI of the GED-Walk library for AMD Instinct MI355X (gfx950).
+ *
+ * GED-Walk group centrality (Angriman et al., "Group Centrality Maximization
+ * for Large-scale Graphs"): for a group S of vertices,
+ *     GED(S) = sum_{i>=1} alpha^i * phi_i(S),
+ * phi_i(S) = number of walks of length i that contain at least one vertex of S
+ * (Section 2.1, Definition "GED-Walk").  The library computes the partial sum
+ * up to the walk length ell* at which the combinatorial tail bound drops below
+ * eps (Section 3.1, Algorithm "GED-Walk Computation"), and maximises it
+ * greedily with (eps/k)-separation (Section 3.2.2, Algorithm "lazy greedy").
+ * Every step runs in HIP kernels on the GPU in FP64.
+ *
+ * Conventions shared by every entry point:
+ *  - Graphs are CSR whose row v lists the in-neighbours u of v (arcs u -> v).
+ *    An undirected graph stores each edge as two arcs, so its rows are
+ *    neighbour lists.  Vertex ids are 0..n-1; col_idx is int32.
+ *  - Pointers are host pointers unless the name starts with d_.  The caller
+ *    owns every input array; the library copies what it keeps before the call
+ *    returns.  Outputs go to caller-allocated buffers of the stated length.
+ *  - Return value: GED_OK (0) or a negative GED_ERR_* code; ged_last_error()
+ *    returns a message for the last failure of the calling thread.  No C++
+ *    exception crosses this boundary.
+ *  - alpha: 0 < alpha < 1/deg_max (the combinatorial bound needs
+ *    alpha * deg_max < 1, Section 3.1.2); deg_max is the maximum out-degree
+ *    (the maximum degree for undirected graphs).  Otherwise GED_ERR_ALPHA.
+ *  - eps: finite and > 0, otherwise GED_ERR_EPS.
+ *  - Groups have set semantics: duplicate ids are ignored and order does not
+ *    matter; an id outside [0, n) gives GED_ERR_VERTEX.
+ *  - Calls on one graph handle are serialised by the library; different
+ *    handles may be used from different threads.
+ */
+#ifndef GED_H
+#define GED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ged_status {
+  GED_OK = 0,
+  GED_ERR_ARG = -1,    /* bad size, null pointer or unsupported flag */
+  GED_ERR_VERTEX = -2, /* vertex id out of range, or duplicate where forbidden */
+  GED_ERR_ALPHA = -3,  /* alpha not in (0, 1/deg_max) */
+  GED_ERR_EPS = -4,    /* eps not finite and positive */
+  GED_ERR_GRAPH = -5,  /* malformed CSR */
+  GED_ERR_NOMEM = -6,  /* device allocation failed, or over the serving budget */
+  GED_ERR_DEVICE = -7, /* a HIP call failed (message in ged_last_error) */
+  GED_ERR_BUSY = -8,   /* serving queue full */
+  GED_ERR_ELL = -9     /* walk length limit (65536) reached */
+};
+
+#define GED_UNDIRECTED 1u /* col_idx is symmetric: rows are neighbour lists */
+#define GED_DIRECTED 2u   /* rows are in-neighbour lists of a directed graph */
+#define GED_WEIGHTED 4u   /* per-arc weights given (ged_graph_create_weighted) */
+
+typedef struct ged_graph ged_graph;
+
+/*
+ * Create a graph handle from a host CSR (row_ptr int64[n+1], col_idx
+ * int32[nnz]); the arrays are copied to device memory owned by the handle.
+ * flags: exactly one of GED_UNDIRECTED / GED_DIRECTED.  Validation
+ * (GED_ERR_GRAPH): row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz,
+ * 0 <= col_idx < n, no self-loops, nnz < 2^31; for GED_UNDIRECTED the arc set
+ * must be symmetric.  Duplicate arcs count as parallel edges.
+ * n must be in [1, 2^31 - 1].
+ */
+int ged_graph_create(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                     uint32_t flags, ged_graph **out);
+
+/*
+ * Weighted variant (Section 4.4: a walk contributes alpha^i times the product
+ * of its arc weights).  weights float64[nnz], each in (0, 1], aligned with
+ * col_idx.  The tail bound uses the maximum weighted out-degree in place of
+ * deg_max, so alpha must satisfy alpha * max_v sum_{v->w} w(v,w) < 1.
+ */
+int ged_graph_create_weighted(int64_t n, int64_t nnz, const int64_t *row_ptr,
+                              const int32_t *col_idx, const double *weights, uint32_t flags,
+                              ged_graph **out);
+
+/* Release the handle and all device memory it owns.  NULL is accepted. */
+int ged_graph_destroy(ged_graph *g);
+
+/* n, nnz (stored arcs) and deg_max (maximum out-degree) of the graph. */
+int ged_graph_info(const ged_graph *g, int64_t *n, int64_t *nnz, int32_t *max_deg);
+
+/* 1 / (deg_max + 1), the alpha every benchmark workload uses; for a weighted
+ * graph, 1 / (max weighted out-degree + 1). */
+double ged_default_alpha(const ged_graph *g);
+
+/*
+ * Make the library launch this graph's work on `hip_stream` (a hipStream_t;
+ * NULL selects the handle's own stream).  The stream must belong to the
+ * current device and outlive its use.
+ */
+int ged_set_stream(ged_graph *g, void *hip_stream);
+
+typedef struct {
+  int32_t ell;       /* ell*: first walk length whose tail bound is < eps */
+  double bound;      /* B_{ell*}, the combinatorial bound (Eq. comb-bound) */
+  double walk_total; /* alpha^{ell*} * sum_x omega_{ell*}(x) */
+} ged_score_info;
+
+/*
+ * Per-(graph, alpha, eps) precomputation: the decayed total-walk levels
+ * t_i = alpha * A t_{i-1}, t_0 = 1 (Katz walk counts, Section 2.1), their sums
+ * and the bound B_i = alpha*deg_max/(1 - alpha*deg_max) * sum(t_i)
+ * (Eq. comb-bound) until B_i < eps.  ell* does not depend on S because the
+ * bound is taken on the whole vertex set (Eq. katz-bound).  Called implicitly
+ * by the score entry points; cached on the handle.  info may be NULL.
+ */
+int ged_prepare(ged_graph *g, double alpha, double eps, ged_score_info *info);
+
+/*
+ * GED_{<=ell*}(S) for one group (Section 3.1, Algorithm "GED-Walk
+ * Computation").  GED(S) - eps < *out_score <= GED(S).  s_len == 0 gives 0.
+ * info may be NULL.  Blocks until the result is on the host.
+ */
+int ged_score(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
+              double *out_score, ged_score_info *info);
+
+/*
+ * Scores of n_groups groups in one batched pass (group j is
+ * members[offsets[j] .. offsets[j+1])), all at the shared ell*.  Groups run as
+ * columns of a masked sparse-matrix x dense-matrix product, in tiles whose
+ * width is chosen per graph by an autotuner; out_scores float64[n_groups].
+ * Each result equals ged_score on the same group to ~1e-12 relative.
+ */
+int ged_score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members,
+                    int32_t n_groups, double alpha, double eps, double *out_scores);
+
+/* Tile width (columns) the autotuner picked for ged_score_batch on this graph
+ * (0 if not tuned yet). */
+int32_t ged_batch_tile(const ged_graph *g);
+
+typedef struct {
+  /* per-pick outputs, arrays of length k (any may be NULL) */
+  int32_t *ell;  /* walk length at which the pick was separated */
+  double *L1;    /* L_ell(S, u) of the pick u */
+  double *U2;    /* U_ell(S, v) = L_ell(S, v) + B_ell of the runner-up v (NaN if none) */
+  double *L2;    /* L_ell(S, v) (NaN if none) */
+  double *B;     /* B_ell(V) */
+  int64_t *evals; /* running count of exact gain evaluations */
+  /* optional forced prefix: these picks are taken first without tests, then
+   * the search continues from walk length forced_ell (>= 1) */
+  const int32_t *forced;
+  int32_t n_forced;
+  int32_t forced_ell;
+  /* outputs */
+  int32_t score_ell; /* ell* used for *out_score */
+  int32_t n_rounds;  /* separation attempts (accepted + failed) */
+} ged_greedy_trace;
+
+/*
+ * Greedy maximisation (Section 3.2.2): repeatedly add the vertex u with the
+ * largest L_ell(S, u) once it is (eps/k)-separated from the runner-up v, i.e.
+ * L(u) > L(v) + B_ell - eps/k; otherwise double ell.  Priorities start from the
+ * upper bounds of Lemma "initialize".  Ties go to the larger value, then the
+ * smaller vertex id.  out_group int32[k] in pick order.  out_score (nullable)
+ * receives GED_{<=ell*}(S) of the final group, as ged_score would return it.
+ * k in [1, n]; trace may be NULL.
+ */
+int ged_greedy(ged_graph *g, int32_t k, double alpha, double eps, int32_t *out_group,
+               double *out_score, ged_greedy_trace *trace);
+
+/*
+ * Stochastic greedy (appendix "Dealing with large k"): per addition, sample
+ * ceil((n/k) * ln(1/eta)) candidates uniformly without replacement from
+ * V \ S (seeded, splitmix64 counter stream keyed by `seed`), and separate only
+ * among them.  eta in (0, 1).  Other arguments as ged_greedy.
+ */
+int ged_greedy_stochastic(ged_graph *g, int32_t k, double alpha, double eps, double eta,
+                          uint64_t seed, int32_t *out_group, double *out_score,
+                          ged_greedy_trace *trace);
+
+/* ------------------------------------------------------------ profiling --- */
+
+typedef struct {
+  int64_t launches;        /* walk-count step launches (SpMV/SpMM) recorded */
+  double total_ms;         /* sum of their durations (HIP events, launch stream) */
+  double bytes;            /* algorithmic bytes they moved */
+  double edges;            /* arcs x columns they traversed */
+  int64_t dominant_launches; /* launches of the most time-consuming step kernel */
+  double dominant_ms;
+  double dominant_bytes;
+  int32_t dominant_columns; /* its column count */
+} ged_profile;
+
+/* Start (on != 0) or stop timing every walk-count step launch of this handle
+ * with a pair of HIP events on its stream; starting clears the counters. */
+int ged_profile_enable(ged_graph *g, int on);
+/* Read the counters (synchronises the handle's stream). */
+int ged_profile_read(ged_graph *g, ged_profile *out);
+
+/* ------------------------------------------------------------- serving --- */
+
+typedef struct ged_server ged_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* admission limit for request working memory */
+  int32_t score_slots;      /* columns per resident graph for score requests */
+  int32_t max_queue;        /* pending requests before GED_ERR_BUSY */
+  int32_t greedy_workers;   /* concurrent greedy requests */
+} ged_server_config;
+
+typedef struct {
+  uint64_t id;
+  int32_t kind;       /* 0 = score, 1 = greedy */
+  int32_t status;     /* GED_OK or an error code */
+  double score;       /* score, or GED_{<=ell*} of the greedy group */
+  int32_t k;          /* greedy group size (group in ged_server_group) */
+  int32_t graph;
+  double t_submit_us; /* arrival, completion (steady clock, microseconds) */
+  double t_done_us;
+} ged_result;
+
+/*
+ * Continuous-batching request server.  Resident graphs keep their CSR and
+ * walk-count levels in device memory; score requests on one graph share a
+ * pool of SpMM columns that advances one walk length per step, admitting new
+ * requests into free columns between steps; greedy requests run on their own
+ * streams once their working memory fits the HBM budget.
+ */
+int ged_server_create(const ged_server_config *cfg, ged_server **out);
+/* Register a graph (the handle stays owned by the caller and must outlive the
+ * server); *graph_id receives its index. */
+int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, double eps, int32_t *graph_id);
+int ged_server_submit_score(ged_server *s, int32_t graph_id, const int32_t *S, int32_t s_len,
+                            uint64_t *req_id);
+int ged_server_submit_greedy(ged_server *s, int32_t graph_id, int32_t k, uint64_t *req_id);
+/* Move up to max finished results into out; waits up to timeout_us for the
+ * first one (0 = do not wait). */
+int ged_server_poll(ged_server *s, ged_result *out, int32_t max, int32_t *n_out,
+                    int64_t timeout_us);
+/* Picks of a finished greedy request (out int32[k]); valid until destroy. */
+int ged_server_group(ged_server *s, uint64_t req_id, int32_t *out, int32_t k);
+/* Counters: [0] admitted, [1] completed, [2] steps launched, [3] peak bytes
+ * in use, [4] peak active score columns, [5] rejected (budget). */
+int ged_server_stats(ged_server *s, int64_t *out6);
+int ged_server_destroy(ged_server *s);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *ged_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GED_H */

@@ -1,0 +1,578 @@
+// C ABI: graph handles, per-(alpha, eps) precomputation, single-group scoring,
+// profiling.  Scoring follows Section 3.1 (Algorithm "GED-Walk Computation"):
+// the walks of length i that touch S are counted by the hit chain
+//     h_0 = 1_S,  h_i(v) = t_i(v) if v in S else alpha * sum_{u->v} h_{i-1}(u),
+// where t_i = alpha * A t_{i-1} (t_0 = 1) counts all decayed i-walks ending at
+// v.  It is the paper's phi^hit recurrence with phi^hit + phi^miss replaced by
+// the total walk count (every walk either hits S or misses it), which leaves a
+// single vector per level and only non-negative sums.  The score is
+// sum_{i=1}^{ell*} sum_v h_i(v); ell* is the first length whose combinatorial
+// bound (Eq. comb-bound) is below eps and does not depend on S.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "ged_internal.h"
+
+namespace ged {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+Partition &partition(ged_graph *g, int C, bool reverse) {
+  auto &m = reverse ? g->parts_r : g->parts;
+  auto it = m.find(C);
+  if (it != m.end()) return *it->second;
+  auto p = std::make_unique<Partition>();
+  build_partition(*p, reverse ? g->h_rp_r : g->h_rp, C);
+  Partition &ref = *p;
+  m[C] = std::move(p);
+  return ref;
+}
+
+StepArgs base_args(ged_graph *g, bool reverse) {
+  StepArgs a;
+  a.rp = (reverse ? g->rp_r : g->rp).as<const int>();
+  a.ci = (reverse ? g->ci_r : g->ci).as<const int>();
+  a.w = g->weighted ? (reverse ? g->w_r : g->w).as<const double>() : nullptr;
+  a.n = (int)g->n;
+  return a;
+}
+
+double step_bytes(ged_graph *g, int C, bool reverse) {
+  (void)reverse;
+  // row_ptr + col_idx (+ weights) + read X + write Y, all C columns
+  double b = 4.0 * (double)(g->n + 1) + 4.0 * (double)g->nnz + 16.0 * (double)g->n * C;
+  if (g->weighted) b += 8.0 * (double)g->nnz;
+  return b;
+}
+
+double comb_bound(ged_graph *g, double alpha, double W_ell) {
+  // Eq. comb-bound: alpha^{ell+1} * D/(1 - alpha D) * sum_x omega_ell(x), with the
+  // decayed total W_ell = alpha^ell sum_x omega_ell(x).
+  const double D = g->weighted ? g->max_wdeg : (double)g->max_deg;
+  return alpha * (D / (1.0 - alpha * D)) * W_ell;
+}
+
+int check_alpha_eps(ged_graph *g, double alpha, double eps) {
+  const double D = g->weighted ? g->max_wdeg : (double)g->max_deg;
+  if (!(alpha > 0.0) || !isfinite(alpha)) return fail(GED_ERR_ALPHA, "alpha must be > 0");
+  if (D > 0 && !(alpha * D < 1.0))
+    return fail(GED_ERR_ALPHA, "alpha * max out-degree must be < 1 (combinatorial bound)");
+  if (!(eps > 0.0) || !isfinite(eps)) return fail(GED_ERR_EPS, "eps must be finite and > 0");
+  return GED_OK;
+}
+
+// ------------------------------------------------------------- profiling --
+
+void prof_begin(ged_graph *g, hipStream_t st, hipEvent_t *a) {
+  if (!g->prof.on) return;
+  if (g->prof.pool.empty()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      GED_HIP(hipEventCreate(&e));
+      g->prof.pool.push_back(e);
+    }
+  }
+  *a = g->prof.pool.back();
+  g->prof.pool.pop_back();
+  GED_HIP(hipEventRecord(*a, st));
+}
+
+void prof_end(ged_graph *g, hipStream_t st, hipEvent_t a, int C, double bytes, double edges,
+              int kind) {
+  if (!g->prof.on) return;
+  if (g->prof.pool.empty()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      GED_HIP(hipEventCreate(&e));
+      g->prof.pool.push_back(e);
+    }
+  }
+  hipEvent_t b = g->prof.pool.back();
+  g->prof.pool.pop_back();
+  GED_HIP(hipEventRecord(b, st));
+  g->prof.recs.push_back({a, b, C, bytes, edges, kind});
+}
+
+// One timed step launch: events bracket the step kernel (and its fix-up).
+static void timed_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int out,
+                       hipStream_t st) {
+  hipEvent_t ev = nullptr;
+  prof_begin(g, st, &ev);
+  launch_step(p, a, in, out, st);
+  prof_end(g, st, ev, a.C, step_bytes(g, a.C), (double)g->nnz * a.C, 0);
+}
+
+// -------------------------------------------------------- precomputation --
+
+static void ensure_levels(PrepCache &pc, int64_t n, int levels_needed, hipStream_t st) {
+  const size_t need = sizeof(double) * (size_t)n * (size_t)levels_needed;
+  if (pc.t_levels.bytes >= need) return;
+  DBuf nb;
+  nb.ensure(std::max(need, pc.t_levels.bytes * 2));
+  if (pc.t_levels.p) {
+    GED_HIP(hipMemcpyAsync(nb.p, pc.t_levels.p, pc.t_levels.bytes, hipMemcpyDeviceToDevice, st));
+    GED_HIP(hipStreamSynchronize(st));
+  }
+  std::swap(pc.t_levels.p, nb.p);
+  std::swap(pc.t_levels.bytes, nb.bytes);
+}
+
+// t_i = alpha * A t_{i-1} with t_0 = 1; W[i] = sum_v t_i(v) = alpha^i sum_x omega_i(x).
+int prepare(ged_graph *g, double alpha, double eps) {
+  int rc = check_alpha_eps(g, alpha, eps);
+  if (rc) return rc;
+  PrepCache &pc = g->prep;
+  if (pc.valid && pc.alpha == alpha && pc.eps == eps) return GED_OK;
+  hipStream_t st = g->stream;
+  const int64_t n = g->n;
+  Partition &p = partition(g, 1);
+  g->pws.fit(p);
+  g->levels.ensure(sizeof(double) * 64);
+  pc.valid = false;
+  pc.W.clear();
+  pc.W.push_back((double)n);
+  ensure_levels(pc, n, 16, st);
+  double *T = pc.t_levels.as<double>();
+  launch_fill_f64(T, 1.0, (size_t)n, st);
+  double W_host = 0.0;
+  for (int i = 1;; ++i) {
+    if (i > 65536) return fail(GED_ERR_ELL, "walk length limit reached in precomputation");
+    ensure_levels(pc, n, i + 1, st);
+    T = pc.t_levels.as<double>();
+    StepArgs a = base_args(g);
+    g->pws.into(a);
+    a.C = 1;
+    a.alpha = alpha;
+    a.X = T + (size_t)(i - 1) * n;
+    a.Y = T + (size_t)i * n;
+    launch_step(p, a, i == 1 ? IN_ONES : IN_VEC, OUT_PLAIN, st);
+    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st);
+    GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    GED_HIP(hipStreamSynchronize(st));
+    pc.W.push_back(W_host);
+    const double B = comb_bound(g, alpha, W_host);
+    if (B < eps) {
+      pc.ell = i;
+      pc.bound = B;
+      break;
+    }
+  }
+  pc.alpha = alpha;
+  pc.eps = eps;
+  pc.tail_level = -1;
+  pc.valid = true;
+  return GED_OK;
+}
+
+double walk_total(ged_graph *g, int ell) {
+  PrepCache &pc = g->prep;
+  if (ell < (int)pc.W.size()) return pc.W[ell];
+  hipStream_t st = g->stream;
+  const int64_t n = g->n;
+  Partition &p = partition(g, 1);
+  g->pws.fit(p);
+  pc.t_tail[0].ensure(sizeof(double) * n);
+  pc.t_tail[1].ensure(sizeof(double) * n);
+  if (pc.tail_level < 0) {
+    launch_copy_f64(pc.t_tail[0].as<double>(), pc.t_levels.as<double>() + (size_t)pc.ell * n,
+                    (size_t)n, st);
+    pc.tail_level = pc.ell;
+    pc.tail_cur = 0;
+  }
+  double W_host = 0.0;
+  while ((int)pc.W.size() <= ell) {
+    StepArgs a = base_args(g);
+    g->pws.into(a);
+    a.C = 1;
+    a.alpha = pc.alpha;
+    a.X = pc.t_tail[pc.tail_cur].as<double>();
+    a.Y = pc.t_tail[pc.tail_cur ^ 1].as<double>();
+    launch_step(p, a, IN_VEC, OUT_PLAIN, st);
+    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st);
+    GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    GED_HIP(hipStreamSynchronize(st));
+    pc.tail_cur ^= 1;
+    pc.tail_level++;
+    pc.W.push_back(W_host);
+  }
+  return pc.W[ell];
+}
+
+// ---------------------------------------------------------------- scoring --
+
+// Enqueue the hit chain for the group held in g->s_dev (length at s_dev[0],
+// members from s_dev[1]); the score accumulates in g->acc[0] and the mask is
+// cleared again at the end, so it is all zero between calls.
+static void enqueue_score(ged_graph *g, hipStream_t st, bool timed) {
+  const int64_t n = g->n;
+  const PrepCache &pc = g->prep;
+  Partition &p = partition(g, 1);
+  int *sd = g->s_dev.as<int>();
+  launch_mask_set(g->mask.as<uint32_t>(), sd + 1, sd, g->s_cap, 1, st);
+  launch_fill_f64(g->acc.as<double>(), 0.0, 1, st);
+  const double *T = pc.t_levels.as<const double>();
+  for (int i = 1; i <= pc.ell; ++i) {
+    StepArgs a = base_args(g);
+    g->sws.into(a);
+    a.C = 1;
+    a.alpha = pc.alpha;
+    a.smask = g->mask.as<const uint32_t>();
+    a.X = g->vec[(i - 1) & 1].as<const double>();
+    a.Y = g->vec[i & 1].as<double>();
+    a.inj = T + (size_t)i * n;
+    if (timed)
+      timed_step(g, p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
+    else
+      launch_step(p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
+    launch_reduce(p, a, g->s_levels.as<double>() + i, g->acc.as<double>(), nullptr, st);
+  }
+  launch_mask_set(g->mask.as<uint32_t>(), sd + 1, sd, g->s_cap, 0, st);
+}
+
+static void drop_score_graph(ged_graph *g) {
+  if (g->score_exec) (void)hipGraphExecDestroy(g->score_exec);
+  if (g->score_graph) (void)hipGraphDestroy(g->score_graph);
+  g->score_exec = nullptr;
+  g->score_graph = nullptr;
+  g->score_sig.clear();
+}
+
+static void ensure_score_buffers(ged_graph *g, int s_len, hipStream_t st) {
+  const int64_t n = g->n;
+  const size_t mbytes = sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1);
+  if (g->mask.bytes < mbytes || !g->mask.p) {
+    g->mask.ensure(mbytes);
+    g->mask_ready = false;
+  }
+  if (!g->mask_ready) {
+    launch_fill_i32(g->mask.as<int>(), 0, g->mask.bytes / sizeof(int), st);
+    g->mask_ready = true;
+  }
+  g->vec[0].ensure(sizeof(double) * (size_t)n);
+  g->vec[1].ensure(sizeof(double) * (size_t)n);
+  g->acc.ensure(sizeof(double) * 64);
+  g->s_levels.ensure(sizeof(double) * (size_t)(g->prep.ell + 2));
+  g->out_host.ensure(64);
+  g->sws.fit(partition(g, 1));
+  if (s_len > g->s_cap) {
+    int cap = std::max(256, g->s_cap);
+    while (cap < s_len) cap *= 2;
+    g->s_dev.ensure(sizeof(int) * (size_t)(cap + 1));
+    g->s_host.ensure(sizeof(int) * (size_t)(cap + 1));
+    g->s_cap = cap;
+  }
+}
+
+// Everything the captured score graph bakes in; a change forces a recapture.
+static std::vector<const void *> score_signature(ged_graph *g) {
+  const PrepCache &pc = g->prep;
+  double a = pc.alpha;
+  const void *abits;
+  std::memcpy(&abits, &a, sizeof(a));
+  return {g->mask.p, g->vec[0].p, g->vec[1].p, g->acc.p, g->s_levels.p, g->s_dev.p,
+          g->sws.blk.p, g->sws.seg.p, g->sws.lng.p, pc.t_levels.p, (const void *)g->stream,
+          abits, (const void *)(intptr_t)pc.ell, (const void *)(intptr_t)g->s_cap};
+}
+
+int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
+                double *out, ged_score_info *info) {
+  for (int32_t q = 0; q < s_len; ++q)
+    if (S[q] < 0 || S[q] >= g->n) return fail(GED_ERR_VERTEX, "group member out of range");
+  int rc = prepare(g, alpha, eps);
+  if (rc) return rc;
+  if (info) {
+    info->ell = g->prep.ell;
+    info->bound = g->prep.bound;
+    info->walk_total = g->prep.W[g->prep.ell];
+  }
+  if (s_len == 0) {
+    *out = 0.0;
+    return GED_OK;
+  }
+  hipStream_t st = g->stream;
+  ensure_score_buffers(g, s_len, st);
+  int *hs = g->s_host.as<int>();
+  hs[0] = s_len;
+  std::memcpy(hs + 1, S, sizeof(int) * (size_t)s_len);
+  GED_HIP(hipMemcpyAsync(g->s_dev.p, hs, sizeof(int) * (size_t)(s_len + 1),
+                         hipMemcpyHostToDevice, st));
+  if (g->prof.on) {
+    enqueue_score(g, st, true);
+  } else {
+    std::vector<const void *> sig = score_signature(g);
+    if (g->score_exec && sig != g->score_sig) drop_score_graph(g);
+    if (!g->score_exec) {
+      GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_score(g, st, false);
+      } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(st, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+      }
+      GED_HIP(hipStreamEndCapture(st, &g->score_graph));
+      GED_HIP(hipGraphInstantiate(&g->score_exec, g->score_graph, nullptr, nullptr, 0));
+      g->score_sig = sig;
+    }
+    GED_HIP(hipGraphLaunch(g->score_exec, st));
+  }
+  double *ho = g->out_host.as<double>();
+  GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  GED_HIP(hipStreamSynchronize(st));
+  *out = ho[0];
+  return GED_OK;
+}
+
+}  // namespace ged
+
+using namespace ged;
+
+ged_graph::~ged_graph() {
+  if (score_exec) (void)hipGraphExecDestroy(score_exec);
+  if (score_graph) (void)hipGraphDestroy(score_graph);
+  for (auto e : prof.pool) (void)hipEventDestroy(e);
+  for (auto &r : prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (own_stream) (void)hipStreamDestroy(own_stream);
+}
+
+// ------------------------------------------------------------------ C ABI --
+
+extern "C" const char *ged_last_error(void) { return g_err.c_str(); }
+
+static uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                       const double *weights, uint32_t flags, ged_graph **out) {
+  if (!out) return fail(GED_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (n < 1 || n > INT32_MAX - 1) return fail(GED_ERR_ARG, "n must be in [1, 2^31-2]");
+  if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(GED_ERR_GRAPH, "nnz must be < 2^31");
+  if (!row_ptr || (nnz > 0 && !col_idx)) return fail(GED_ERR_ARG, "null CSR array");
+  if (flags != GED_UNDIRECTED && flags != GED_DIRECTED)
+    return fail(GED_ERR_ARG, "flags must be GED_UNDIRECTED or GED_DIRECTED");
+  if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(GED_ERR_GRAPH, "row_ptr ends mismatch");
+  std::vector<int64_t> outdeg((size_t)n, 0);
+  uint64_t h_fwd = 0, h_bwd = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (row_ptr[v + 1] < row_ptr[v]) return fail(GED_ERR_GRAPH, "row_ptr decreases");
+    for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+      const int32_t u = col_idx[j];
+      if (u < 0 || u >= n) return fail(GED_ERR_GRAPH, "col_idx out of range");
+      if (u == v) return fail(GED_ERR_GRAPH, "self-loop");
+      outdeg[u]++;
+      if (weights && !(weights[j] > 0.0 && weights[j] <= 1.0))
+        return fail(GED_ERR_GRAPH, "weights must be in (0, 1]");
+      if (flags == GED_UNDIRECTED) {
+        h_fwd += mix64(((uint64_t)u << 32) | (uint64_t)v);
+        h_bwd += mix64(((uint64_t)v << 32) | (uint64_t)u);
+        if (weights) {
+          uint64_t wb;
+          std::memcpy(&wb, &weights[j], sizeof(wb));
+          h_fwd += mix64((((uint64_t)u << 32) | (uint64_t)v) ^ mix64(wb));
+          h_bwd += mix64((((uint64_t)v << 32) | (uint64_t)u) ^ mix64(wb));
+        }
+      }
+    }
+  }
+  if (flags == GED_UNDIRECTED) {
+    for (int64_t v = 0; v < n; ++v)
+      if (outdeg[v] != row_ptr[v + 1] - row_ptr[v])
+        return fail(GED_ERR_GRAPH, "GED_UNDIRECTED graph is not symmetric");
+    if (h_fwd != h_bwd) return fail(GED_ERR_GRAPH, "GED_UNDIRECTED graph is not symmetric");
+  }
+  auto g = std::make_unique<ged_graph>();
+  g->n = n;
+  g->nnz = nnz;
+  g->flags = flags;
+  g->weighted = weights != nullptr;
+  int64_t md = 0;
+  for (int64_t v = 0; v < n; ++v) md = std::max(md, outdeg[v]);
+  g->max_deg = (int32_t)md;
+  if (weights) {
+    // maximum weighted out-degree: sum of the weights of the arcs leaving v
+    std::vector<double> wout((size_t)n, 0.0);
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) wout[col_idx[j]] += weights[j];
+    double m = 0.0;
+    for (double x : wout) m = std::max(m, x);
+    g->max_wdeg = m;
+  }
+  return guarded([&]() -> int {
+    GED_HIP(hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking));
+    g->stream = g->own_stream;
+    g->h_rp.resize((size_t)n + 1);
+    for (int64_t v = 0; v <= n; ++v) g->h_rp[v] = (int)row_ptr[v];
+    g->rp.ensure(sizeof(int) * (size_t)(n + 1));
+    g->ci.ensure(sizeof(int) * (size_t)std::max<int64_t>(1, nnz));
+    GED_HIP(hipMemcpy(g->rp.p, g->h_rp.data(), sizeof(int) * (size_t)(n + 1),
+                      hipMemcpyHostToDevice));
+    if (nnz > 0)
+      GED_HIP(hipMemcpy(g->ci.p, col_idx, sizeof(int) * (size_t)nnz, hipMemcpyHostToDevice));
+    if (weights) {
+      g->w.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nnz));
+      if (nnz > 0)
+        GED_HIP(hipMemcpy(g->w.p, weights, sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice));
+    }
+    if (flags == GED_DIRECTED) {
+      // reverse graph: row u lists the out-neighbours v of u (arcs u -> v)
+      std::vector<int> rr((size_t)n + 1, 0), cr((size_t)std::max<int64_t>(1, nnz));
+      std::vector<double> wr(weights ? (size_t)std::max<int64_t>(1, nnz) : 0);
+      for (int64_t j = 0; j < nnz; ++j) rr[col_idx[j] + 1]++;
+      for (int64_t v = 0; v < n; ++v) rr[v + 1] += rr[v];
+      std::vector<int> pos(rr.begin(), rr.end() - 1);
+      for (int64_t v = 0; v < n; ++v)
+        for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+          const int q = pos[col_idx[j]]++;
+          cr[q] = (int)v;
+          if (weights) wr[q] = weights[j];
+        }
+      g->h_rp_r = rr;
+      g->rp_r.ensure(sizeof(int) * (size_t)(n + 1));
+      g->ci_r.ensure(sizeof(int) * cr.size());
+      GED_HIP(hipMemcpy(g->rp_r.p, rr.data(), sizeof(int) * rr.size(), hipMemcpyHostToDevice));
+      GED_HIP(hipMemcpy(g->ci_r.p, cr.data(), sizeof(int) * cr.size(), hipMemcpyHostToDevice));
+      if (weights) {
+        g->w_r.ensure(sizeof(double) * wr.size());
+        GED_HIP(hipMemcpy(g->w_r.p, wr.data(), sizeof(double) * wr.size(),
+                          hipMemcpyHostToDevice));
+      }
+    }
+    *out = g.release();
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_graph_create(int64_t n, int64_t nnz, const int64_t *row_ptr,
+                                const int32_t *col_idx, uint32_t flags, ged_graph **out) {
+  return create_impl(n, nnz, row_ptr, col_idx, nullptr, flags, out);
+}
+
+extern "C" int ged_graph_create_weighted(int64_t n, int64_t nnz, const int64_t *row_ptr,
+                                         const int32_t *col_idx, const double *weights,
+                                         uint32_t flags, ged_graph **out) {
+  if (!weights) return fail(GED_ERR_ARG, "weights is null");
+  return create_impl(n, nnz, row_ptr, col_idx, weights, flags, out);
+}
+
+extern "C" int ged_graph_destroy(ged_graph *g) {
+  if (!g) return GED_OK;
+  {
+    std::lock_guard<std::recursive_mutex> lk(g->mu);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+  }
+  batch_forget(g);
+  delete g;
+  return GED_OK;
+}
+
+extern "C" int ged_graph_info(const ged_graph *g, int64_t *n, int64_t *nnz, int32_t *max_deg) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  if (max_deg) *max_deg = g->max_deg;
+  return GED_OK;
+}
+
+extern "C" double ged_default_alpha(const ged_graph *g) {
+  if (!g) return 0.0;
+  if (g->weighted) return 1.0 / (g->max_wdeg + 1.0);
+  return 1.0 / ((double)g->max_deg + 1.0);
+}
+
+extern "C" int ged_set_stream(ged_graph *g, void *hip_stream) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    GED_HIP(hipStreamSynchronize(g->stream));
+    g->stream = hip_stream ? (hipStream_t)hip_stream : g->own_stream;
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_prepare(ged_graph *g, double alpha, double eps, ged_score_info *info) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    int rc = prepare(g, alpha, eps);
+    if (rc) return rc;
+    if (info) {
+      info->ell = g->prep.ell;
+      info->bound = g->prep.bound;
+      info->walk_total = g->prep.W[g->prep.ell];
+    }
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_score(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
+                         double *out_score, ged_score_info *info) {
+  if (!g || !out_score || (s_len > 0 && !S) || s_len < 0)
+    return fail(GED_ERR_ARG, "bad argument to ged_score");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() { return score_group(g, S, s_len, alpha, eps, out_score, info); });
+}
+
+extern "C" int ged_profile_enable(ged_graph *g, int on) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    GED_HIP(hipStreamSynchronize(g->stream));
+    for (auto &r : g->prof.recs) {
+      g->prof.pool.push_back(r.a);
+      g->prof.pool.push_back(r.b);
+    }
+    g->prof.recs.clear();
+    g->prof.on = on != 0;
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_profile_read(ged_graph *g, ged_profile *out) {
+  if (!g || !out) return fail(GED_ERR_ARG, "bad argument");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    GED_HIP(hipStreamSynchronize(g->stream));
+    std::memset(out, 0, sizeof(*out));
+    std::map<int, std::tuple<int64_t, double, double>> by_c;
+    for (auto &r : g->prof.recs) {
+      float ms = 0.f;
+      GED_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      out->launches++;
+      out->total_ms += ms;
+      out->bytes += r.bytes;
+      out->edges += r.edges;
+      auto &e = by_c[r.C];
+      std::get<0>(e)++;
+      std::get<1>(e) += ms;
+      std::get<2>(e) += r.bytes;
+    }
+    double best = -1;
+    for (auto &kv : by_c) {
+      if (std::get<1>(kv.second) > best) {
+        best = std::get<1>(kv.second);
+        out->dominant_columns = kv.first;
+        out->dominant_launches = std::get<0>(kv.second);
+        out->dominant_ms = std::get<1>(kv.second);
+        out->dominant_bytes = std::get<2>(kv.second);
+      }
+    }
+    return GED_OK;
+  });
+}

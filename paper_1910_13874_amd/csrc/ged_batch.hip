@@ -1,0 +1,227 @@
+// Batched scoring: many groups at once as the columns of one masked SpMM.
+//
+// Every score query on a graph stops at the same ell* (the tail bound is taken
+// on the whole vertex set, Eq. katz-bound), so the hit chains of C groups run
+// in lock-step: column c of X holds h_i for group g0 + c, a per-vertex 64-bit
+// word marks which columns have v in their group (injection of t_i(v) there),
+// and one pass over col_idx serves all C columns.  The whole batch -- every
+// tile, every level -- is captured into one hipGraph and replayed, so the host
+// issues one launch per call.  The tile width C is chosen per graph by timing
+// the step kernel for each candidate width (autotuner).
+#include <algorithm>
+#include <cstring>
+
+#include "ged_internal.h"
+
+namespace ged {
+
+struct BatchWs {
+  DBuf tmask;       // uint64 [n], all zero between calls
+  bool tmask_ready = false;
+  DBuf X, Y;        // double [n*C]
+  DBuf offsets;     // int64 [cap_g+1]
+  DBuf members;     // int [cap_m]
+  DBuf scores;      // double [cap_g + 64]
+  HBuf h_scores;
+  size_t cap_g = 0, cap_m = 0;
+  StepWs ws;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void *> sig;
+  ~BatchWs() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+static std::mutex g_batch_mu;
+static std::map<const ged_graph *, std::unique_ptr<BatchWs>> g_batch;
+
+static BatchWs &batch_ws(ged_graph *g) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto &p = g_batch[g];
+  if (!p) p = std::make_unique<BatchWs>();
+  return *p;
+}
+
+void batch_forget(const ged_graph *g) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batch.erase(g);
+}
+
+// Step time per column for each candidate tile width; the fastest wins.
+static int autotune_tile(ged_graph *g, BatchWs &b) {
+  if (g->batch_tile > 0) return g->batch_tile;
+  const int n = (int)g->n;
+  hipStream_t st = g->stream;
+  const int cands[] = {8, 16, 32, 64};
+  double best = 1e300;
+  int best_c = 16;
+  hipEvent_t e0, e1;
+  GED_HIP(hipEventCreate(&e0));
+  GED_HIP(hipEventCreate(&e1));
+  for (int C : cands) {
+    try {
+      Partition &p = partition(g, C);
+      StepWs ws;
+      ws.fit(p);
+      b.X.ensure(sizeof(double) * (size_t)n * C);
+      b.Y.ensure(sizeof(double) * (size_t)n * C);
+      launch_fill_f64(b.X.as<double>(), 0.0, (size_t)n * C, st);
+      StepArgs a = base_args(g);
+      ws.into(a);
+      a.C = C;
+      a.alpha = g->prep.alpha;
+      a.tmask = b.tmask.as<const uint64_t>();
+      a.inj = g->prep.t_levels.as<const double>();
+      a.X = b.X.as<const double>();
+      a.Y = b.Y.as<double>();
+      launch_step(p, a, IN_VEC, OUT_TILE, st);  // warm-up
+      float ms_best = 1e30f;
+      for (int r = 0; r < 3; ++r) {
+        GED_HIP(hipEventRecord(e0, st));
+        launch_step(p, a, IN_VEC, OUT_TILE, st);
+        launch_reduce(p, a, nullptr, nullptr, nullptr, st);
+        GED_HIP(hipEventRecord(e1, st));
+        GED_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        GED_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms_best = std::min(ms_best, ms);
+      }
+      const double per_col = ms_best / C;
+      if (per_col < best) {
+        best = per_col;
+        best_c = C;
+      }
+    } catch (const HipError &e) {
+      if (e.code != GED_ERR_NOMEM) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+      }
+      break;  // wider tiles do not fit
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g->batch_tile = best_c;
+  return best_c;
+}
+
+static void enqueue_batch(ged_graph *g, BatchWs &b, int G, int C, hipStream_t st) {
+  const int64_t n = g->n;
+  const PrepCache &pc = g->prep;
+  Partition &p = partition(g, C);
+  const double *T = pc.t_levels.as<const double>();
+  launch_fill_f64(b.scores.as<double>(), 0.0, (size_t)G + 64, st);
+  for (int g0 = 0; g0 < G; g0 += C) {
+    const int nc = std::min(C, G - g0);
+    launch_tmask_set(b.tmask.as<uint64_t>(), b.offsets.as<const int64_t>(),
+                     b.members.as<const int>(), g0, nc, 1, st);
+    for (int i = 1; i <= pc.ell; ++i) {
+      StepArgs a = base_args(g);
+      b.ws.into(a);
+      a.C = C;
+      a.alpha = pc.alpha;
+      a.tmask = b.tmask.as<const uint64_t>();
+      a.X = ((i & 1) ? b.X : b.Y).as<const double>();
+      a.Y = ((i & 1) ? b.Y : b.X).as<double>();
+      a.inj = T + (size_t)i * n;
+      launch_step(p, a, i == 1 ? IN_TILEMASK : IN_VEC, OUT_TILE, st);
+      launch_reduce(p, a, nullptr, b.scores.as<double>() + g0, nullptr, st);
+    }
+    launch_tmask_set(b.tmask.as<uint64_t>(), b.offsets.as<const int64_t>(),
+                     b.members.as<const int>(), g0, nc, 0, st);
+  }
+}
+
+int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, int32_t G,
+                double alpha, double eps, double *out) {
+  if (G < 0 || (G > 0 && (!offsets || !out))) return fail(GED_ERR_ARG, "bad batch arguments");
+  if (G == 0) return GED_OK;
+  if (offsets[0] != 0) return fail(GED_ERR_ARG, "offsets[0] must be 0");
+  for (int j = 0; j < G; ++j)
+    if (offsets[j + 1] < offsets[j]) return fail(GED_ERR_ARG, "offsets must be non-decreasing");
+  const int64_t M = offsets[G];
+  if (M > 0 && !members) return fail(GED_ERR_ARG, "members is null");
+  for (int64_t j = 0; j < M; ++j)
+    if (members[j] < 0 || members[j] >= g->n) return fail(GED_ERR_VERTEX, "member out of range");
+  int rc = prepare(g, alpha, eps);
+  if (rc) return rc;
+  hipStream_t st = g->stream;
+  BatchWs &b = batch_ws(g);
+  const int64_t n = g->n;
+  b.tmask.ensure(sizeof(uint64_t) * (size_t)n);
+  if (!b.tmask_ready) {
+    launch_fill_i32(b.tmask.as<int>(), 0, (size_t)n * 2, st);
+    b.tmask_ready = true;
+  }
+  const int C = autotune_tile(g, b);
+  Partition &p = partition(g, C);
+  b.ws.fit(p);
+  b.X.ensure(sizeof(double) * (size_t)n * C);
+  b.Y.ensure(sizeof(double) * (size_t)n * C);
+  if ((size_t)G + 1 > b.cap_g) {
+    b.cap_g = std::max<size_t>((size_t)G + 1, 2 * b.cap_g);
+    b.offsets.ensure(sizeof(int64_t) * b.cap_g);
+    b.scores.ensure(sizeof(double) * (b.cap_g + 64));
+    b.h_scores.ensure(sizeof(double) * (b.cap_g + 64));
+  }
+  if ((size_t)std::max<int64_t>(M, 1) > b.cap_m) {
+    b.cap_m = std::max<size_t>((size_t)std::max<int64_t>(M, 1), 2 * b.cap_m);
+    b.members.ensure(sizeof(int) * b.cap_m);
+  }
+  GED_HIP(hipMemcpyAsync(b.offsets.p, offsets, sizeof(int64_t) * (size_t)(G + 1),
+                         hipMemcpyHostToDevice, st));
+  if (M > 0)
+    GED_HIP(hipMemcpyAsync(b.members.p, members, sizeof(int) * (size_t)M, hipMemcpyHostToDevice,
+                           st));
+  double abits_d = alpha;
+  const void *abits;
+  std::memcpy(&abits, &abits_d, sizeof(abits));
+  std::vector<const void *> sig = {b.tmask.p,      b.X.p,       b.Y.p,
+                                   b.offsets.p,    b.members.p, b.scores.p,
+                                   b.ws.blk.p,     b.ws.seg.p,  b.ws.lng.p,
+                                   g->prep.t_levels.p, (const void *)st, abits,
+                                   (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
+                                   (const void *)(intptr_t)C};
+  if (b.exec && sig != b.sig) {
+    (void)hipGraphExecDestroy(b.exec);
+    (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+  }
+  if (!b.exec) {
+    GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_batch(g, b, G, C, st);
+    } catch (...) {
+      hipGraph_t dummy = nullptr;
+      (void)hipStreamEndCapture(st, &dummy);
+      if (dummy) (void)hipGraphDestroy(dummy);
+      throw;
+    }
+    GED_HIP(hipStreamEndCapture(st, &b.graph));
+    GED_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    b.sig = sig;
+  }
+  GED_HIP(hipGraphLaunch(b.exec, st));
+  double *hs = b.h_scores.as<double>();
+  GED_HIP(hipMemcpyAsync(hs, b.scores.p, sizeof(double) * (size_t)G, hipMemcpyDeviceToHost, st));
+  GED_HIP(hipStreamSynchronize(st));
+  std::memcpy(out, hs, sizeof(double) * (size_t)G);
+  return GED_OK;
+}
+
+}  // namespace ged
+
+using namespace ged;
+
+extern "C" int ged_score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members,
+                               int32_t n_groups, double alpha, double eps, double *out_scores) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() { return score_batch(g, offsets, members, n_groups, alpha, eps, out_scores); });
+}
+
+extern "C" int32_t ged_batch_tile(const ged_graph *g) { return g ? g->batch_tile : 0; }

@@ -1,0 +1,526 @@
+// Greedy GED-Walk maximisation on the GPU (Section 3.2, Algorithm "lazy
+// greedy", with the priorities of Lemma "initialize").
+//
+// Per separation attempt at (S, ell):
+//   1. miss chain m_i(v) = [v not in S] alpha * sum_{u->v} m_{i-1}(u), m_0 = 1_{V\S}
+//      (the paper's phi^miss, decayed), all levels 0..ell kept; for directed
+//      graphs the same chain on the reverse graph gives psi^miss (b_i).
+//   2. upper bounds I(x) = sum_{1 <= a+c <= ell} m_a(x) b_c(x) on L_ell(S, x)
+//      (Lemma "initialize"), tightened by exact values already computed at this
+//      ell for a smaller S (L_ell is non-increasing in S, Section 3.2.1).
+//   3. candidates in decreasing bound order, C at a time: their exact gains
+//      L_ell(S, x) come from one SpMM whose column c runs the chain
+//         d_0 = e_x, d_i(v) = 0 (v in S), m_i(x) (v = x), alpha*sum d_{i-1} (else)
+//      -- the walks that avoid S and contain x, counted by end vertex -- and
+//      L = sum_{i=1}^{ell} sum_v d_i(v).  Batches continue until every
+//      unevaluated bound is below the runner-up's exact gain, so the exact
+//      top two of L_ell over V \ S are known (the heaps of the paper's
+//      algorithm find the same pair).
+//   4. accept u iff L(u) > L(v) + B_ell - eps/k ((eps/k)-separation), else
+//      ell <- 2 ell.  Ties order by larger value, then smaller id.
+#include <math.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "ged_internal.h"
+
+namespace ged {
+
+int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
+                double *out, ged_score_info *info);
+
+// Relative slack added to upper bounds before they are compared with exact
+// gains: both sides are rounded sums, and exact equality (e.g. ell = 1, where
+// the bound is tight) must not prune a candidate by one ulp.
+constexpr double kBoundSlack = 1e-12;
+
+// ---------------------------------------------------------------- kernels --
+
+__global__ void k_mask_bit(uint32_t *mask, int v, int value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const uint32_t bit = 1u << (v & 31);
+    if (value)
+      mask[v >> 5] |= bit;
+    else
+      mask[v >> 5] &= ~bit;
+  }
+}
+
+// I(x) = b_0 * sum_{a=1}^{ell} m_a + sum_{c=1}^{ell} b_c * sum_{a=0}^{ell-c} m_a with
+// m_0 = b_0 = 1 for x outside S: every term of Lemma "initialize" once, no
+// subtraction.  ub[x] = -1 marks members of S.
+__global__ __launch_bounds__(kBlock) void k_pbound(const double *__restrict__ M,
+                                                   const double *__restrict__ Bl, int n, int ell,
+                                                   const uint32_t *__restrict__ smask,
+                                                   const double *__restrict__ stale,
+                                                   double *__restrict__ ub, double slack) {
+  const int x = blockIdx.x * kBlock + threadIdx.x;
+  if (x >= n) return;
+  if ((smask[x >> 5] >> (x & 31)) & 1u) {
+    ub[x] = -1.0;
+    return;
+  }
+  double pre = 1.0, tail = 0.0, acc = 0.0;
+  for (int s = 0; s < ell; ++s) {
+    if (s > 0) {
+      const double ms = M[(size_t)s * n + x];
+      pre += ms;
+      tail += ms;
+    }
+    acc += Bl[(size_t)(ell - s) * n + x] * pre;
+  }
+  tail += M[(size_t)ell * n + x];
+  acc += tail;
+  const double st = stale[x];
+  if (st >= 0.0 && st < acc) acc = st;
+  ub[x] = acc * (1.0 + slack);
+}
+
+__device__ __forceinline__ bool kv_better(double ka, int ia, double kb, int ib) {
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+// K rounds of block-wide argmax over E register-resident (key, id) pairs per
+// thread; writes the block's top K (key descending, id ascending).
+template <int E>
+__device__ void block_topk(double (&kv)[E], int (&iv)[E], int K, double *ok, int *oi) {
+  __shared__ double sk[kBlock / 64];
+  __shared__ int si[kBlock / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int r = 0; r < K; ++r) {
+    double bk = -INFINITY;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+      if (kv_better(kv[q], iv[q], bk, bi)) {
+        bk = kv[q];
+        bi = iv[q];
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double k2 = __shfl_xor(bk, off, 64);
+      const int i2 = __shfl_xor(bi, off, 64);
+      if (kv_better(k2, i2, bk, bi)) {
+        bk = k2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      sk[wave] = bk;
+      si[wave] = bi;
+    }
+    __syncthreads();
+    double wk = sk[0];
+    int wi = si[0];
+    for (int w = 1; w < kBlock / 64; ++w)
+      if (kv_better(sk[w], si[w], wk, wi)) {
+        wk = sk[w];
+        wi = si[w];
+      }
+    __syncthreads();
+    if (wi != INT_MAX) {
+#pragma unroll
+      for (int q = 0; q < E; ++q)
+        if (iv[q] == wi) {
+          kv[q] = -INFINITY;
+          iv[q] = INT_MAX;
+        }
+    }
+    if (t == 0) {
+      ok[r] = wk;
+      oi[r] = wi;
+    }
+  }
+}
+
+constexpr int kTopE = 16;  // elements per thread in the selection kernels
+
+// Eligible: bound >= 0 (not in S), not evaluated in this round, and (for the
+// stochastic variant) in the current sample.
+__global__ __launch_bounds__(kBlock) void k_topk_ub(const double *__restrict__ ub,
+                                                    const int *__restrict__ done, int round,
+                                                    const int *__restrict__ sampled, int pick,
+                                                    int n, int K, double *ok, int *oi) {
+  double kv[kTopE];
+  int iv[kTopE];
+  const int base = blockIdx.x * kBlock * kTopE + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kTopE; ++q) {
+    const int x = base + q * kBlock;
+    kv[q] = -INFINITY;
+    iv[q] = INT_MAX;
+    if (x < n) {
+      const double u = ub[x];
+      if (u >= 0.0 && done[x] != round && (!sampled || sampled[x] == pick)) {
+        kv[q] = u;
+        iv[q] = x;
+      }
+    }
+  }
+  block_topk<kTopE>(kv, iv, K, ok + (size_t)blockIdx.x * K, oi + (size_t)blockIdx.x * K);
+}
+
+__global__ __launch_bounds__(kBlock) void k_topk_pairs(const double *__restrict__ ik,
+                                                       const int *__restrict__ ii, int count,
+                                                       int K, double *ok, int *oi) {
+  double kv[kTopE];
+  int iv[kTopE];
+  const int base = blockIdx.x * kBlock * kTopE + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kTopE; ++q) {
+    const int x = base + q * kBlock;
+    kv[q] = -INFINITY;
+    iv[q] = INT_MAX;
+    if (x < count) {
+      kv[q] = ik[x];
+      iv[q] = ii[x];
+    }
+  }
+  block_topk<kTopE>(kv, iv, K, ok + (size_t)blockIdx.x * K, oi + (size_t)blockIdx.x * K);
+}
+
+// Candidates of a batch: cand_col[x_c] = c (value=1) or -1 (value=0).
+__global__ void k_cand_set(int *cand_col, const int *cand, int nc, int value) {
+  const int c = threadIdx.x;
+  if (c < nc) cand_col[cand[c]] = value ? c : -1;
+}
+
+// After a batch: remember the exact gains (valid upper bounds for any larger
+// S at this ell) and mark the candidates as evaluated in this round.
+__global__ void k_after_batch(const int *cand, const double *gains, int nc, double *stale,
+                              double *ub, int *done, int round) {
+  const int c = threadIdx.x;
+  if (c < nc) {
+    const int x = cand[c];
+    stale[x] = gains[c];
+    ub[x] = gains[c];
+    done[x] = round;
+  }
+}
+
+// ------------------------------------------------------------- host side --
+
+struct GreedyCtx {
+  ged_graph *g;
+  hipStream_t st;
+  int n;
+  int C;
+  int Lcap = 0;
+  DBuf smask, m_levels, b_levels, ub, stale, done, cand_col, sampled;
+  DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
+  HBuf h_small;
+  StepWs ws1, ws1r, wsC;
+  int64_t evals = 0;
+  int rounds = 0;
+};
+
+static void ensure_levels_cap(GreedyCtx &c, int ell) {
+  if (ell <= c.Lcap) return;
+  int cap = std::max(16, c.Lcap);
+  while (cap < ell) cap *= 2;
+  c.m_levels.ensure(sizeof(double) * (size_t)c.n * (cap + 1));
+  if (c.g->flags == GED_DIRECTED) c.b_levels.ensure(sizeof(double) * (size_t)c.n * (cap + 1));
+  c.Lcap = cap;
+}
+
+// Miss chain(s) for the current S at walk length ell.
+static void miss_chains(GreedyCtx &c, int ell) {
+  ged_graph *g = c.g;
+  const int n = c.n;
+  for (int dir = 0; dir < (g->flags == GED_DIRECTED ? 2 : 1); ++dir) {
+    const bool rev = dir == 1;
+    Partition &p = partition(g, 1, rev);
+    StepWs &ws = rev ? c.ws1r : c.ws1;
+    ws.fit(p);
+    double *L = (rev ? c.b_levels : c.m_levels).as<double>();
+    for (int i = 1; i <= ell; ++i) {
+      StepArgs a = base_args(g, rev);
+      ws.into(a);
+      a.C = 1;
+      a.alpha = g->prep.alpha;
+      a.smask = c.smask.as<const uint32_t>();
+      a.X = L + (size_t)(i - 1) * n;
+      a.Y = L + (size_t)i * n;
+      hipEvent_t ev = nullptr;
+      prof_begin(g, c.st, &ev);
+      launch_step(p, a, i == 1 ? IN_NOTMASK : IN_VEC, OUT_ZERO, c.st);
+      prof_end(g, c.st, ev, 1, step_bytes(g, 1), (double)g->nnz, 1);
+    }
+  }
+}
+
+static void compute_bounds(GreedyCtx &c, int ell) {
+  const double *B = (c.g->flags == GED_DIRECTED ? c.b_levels : c.m_levels).as<const double>();
+  hipLaunchKernelGGL(k_pbound, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, c.st,
+                     c.m_levels.as<const double>(), B, c.n, ell, c.smask.as<const uint32_t>(),
+                     c.stale.as<const double>(), c.ub.as<double>(), kBoundSlack);
+  GED_HIP(hipGetLastError());
+}
+
+// Top-K eligible (bound, id) pairs, best first, into host arrays.
+static int select_topk(GreedyCtx &c, int K, int round, const int *sampled, int pick, double *hk,
+                       int *hi) {
+  const int chunk = kBlock * kTopE;
+  int nb = (c.n + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_topk_ub, dim3(nb), dim3(kBlock), 0, c.st, c.ub.as<const double>(),
+                     c.done.as<const int>(), round, sampled, pick, c.n, K,
+                     c.topk_k[0].as<double>(), c.topk_i[0].as<int>());
+  GED_HIP(hipGetLastError());
+  int cur = 0, count = nb * K;
+  while (nb > 1) {
+    nb = (count + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_topk_pairs, dim3(nb), dim3(kBlock), 0, c.st,
+                       c.topk_k[cur].as<const double>(), c.topk_i[cur].as<const int>(), count, K,
+                       c.topk_k[cur ^ 1].as<double>(), c.topk_i[cur ^ 1].as<int>());
+    GED_HIP(hipGetLastError());
+    cur ^= 1;
+    count = nb * K;
+  }
+  double *sk = c.h_small.as<double>();
+  int *si = reinterpret_cast<int *>(sk + 64);
+  GED_HIP(hipMemcpyAsync(sk, c.topk_k[cur].p, sizeof(double) * K, hipMemcpyDeviceToHost, c.st));
+  GED_HIP(hipMemcpyAsync(si, c.topk_i[cur].p, sizeof(int) * K, hipMemcpyDeviceToHost, c.st));
+  GED_HIP(hipStreamSynchronize(c.st));
+  int m = 0;
+  for (int q = 0; q < K; ++q) {
+    if (si[q] == INT_MAX || !(sk[q] >= 0.0)) break;
+    hk[m] = sk[q];
+    hi[m] = si[q];
+    ++m;
+  }
+  return m;
+}
+
+// Exact L_ell(S, x) for up to C candidates (one SpMM column each).
+static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round, double *out) {
+  ged_graph *g = c.g;
+  const int n = c.n, C = c.C;
+  Partition &p = partition(g, C);
+  c.wsC.fit(p);
+  int *hc = reinterpret_cast<int *>(c.h_small.as<char>() + 1024);
+  for (int q = 0; q < nc; ++q) hc[q] = cand[q];
+  GED_HIP(hipMemcpyAsync(c.cand_dev.p, hc, sizeof(int) * nc, hipMemcpyHostToDevice, c.st));
+  hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
+                     c.cand_dev.as<const int>(), nc, 1);
+  launch_fill_f64(c.gains.as<double>(), 0.0, (size_t)C, c.st);
+  const double *M = c.m_levels.as<const double>();
+  for (int i = 1; i <= ell; ++i) {
+    StepArgs a = base_args(g);
+    c.wsC.into(a);
+    a.C = C;
+    a.alpha = g->prep.alpha;
+    a.smask = c.smask.as<const uint32_t>();
+    a.cand_col = c.cand_col.as<const int>();
+    a.X = ((i & 1) ? c.X : c.Y).as<const double>();
+    a.Y = ((i & 1) ? c.Y : c.X).as<double>();
+    a.inj = M + (size_t)i * n;
+    hipEvent_t ev = nullptr;
+    prof_begin(g, c.st, &ev);
+    launch_step(p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
+    prof_end(g, c.st, ev, C, step_bytes(g, C), (double)g->nnz * C, 2);
+    launch_reduce(p, a, nullptr, c.gains.as<double>(), nullptr, c.st);
+  }
+  hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
+                     c.cand_dev.as<const int>(), nc, 0);
+  hipLaunchKernelGGL(k_after_batch, dim3(1), dim3(64), 0, c.st, c.cand_dev.as<const int>(),
+                     c.gains.as<const double>(), nc, c.stale.as<double>(), c.ub.as<double>(),
+                     c.done.as<int>(), round);
+  GED_HIP(hipGetLastError());
+  double *hg = c.h_small.as<double>() + 256;
+  GED_HIP(hipMemcpyAsync(hg, c.gains.p, sizeof(double) * nc, hipMemcpyDeviceToHost, c.st));
+  GED_HIP(hipStreamSynchronize(c.st));
+  for (int q = 0; q < nc; ++q) out[q] = hg[q];
+  c.evals += nc;
+}
+
+struct Top2 {
+  double L1 = -1, L2 = -1;
+  int u = -1, v = -1;
+  void add(double L, int x) {
+    if (u < 0 || kv_less(L1, u, L, x)) {
+      L2 = L1;
+      v = u;
+      L1 = L;
+      u = x;
+    } else if (v < 0 || kv_less(L2, v, L, x)) {
+      L2 = L;
+      v = x;
+    }
+  }
+  static bool kv_less(double ka, int ia, double kb, int ib) {  // is (kb, ib) better?
+    return kb > ka || (kb == ka && ib < ia);
+  }
+};
+
+// Sampling for the stochastic variant: splitmix64 at counter (pick, j).
+static uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, uint64_t seed,
+               bool stochastic, int32_t *out_group, double *out_score, ged_greedy_trace *tr) {
+  const int64_t n64 = g->n;
+  if (k < 1 || k > n64) return fail(GED_ERR_ARG, "k must be in [1, n]");
+  if (stochastic && !(eta > 0.0 && eta < 1.0)) return fail(GED_ERR_ARG, "eta must be in (0,1)");
+  int rc = prepare(g, alpha, eps);
+  if (rc) return rc;
+  const int n = (int)n64;
+  GreedyCtx c;
+  c.g = g;
+  c.st = g->stream;
+  c.n = n;
+  c.C = 8;
+  const int K = c.C + 1;
+  c.smask.ensure(sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1));
+  c.ub.ensure(sizeof(double) * n);
+  c.stale.ensure(sizeof(double) * n);
+  c.done.ensure(sizeof(int) * n);
+  c.cand_col.ensure(sizeof(int) * n);
+  c.X.ensure(sizeof(double) * (size_t)n * c.C);
+  c.Y.ensure(sizeof(double) * (size_t)n * c.C);
+  c.cand_dev.ensure(sizeof(int) * 64);
+  c.gains.ensure(sizeof(double) * 64);
+  const int nb0 = (n + kBlock * kTopE - 1) / (kBlock * kTopE);
+  c.topk_k[0].ensure(sizeof(double) * (size_t)nb0 * K);
+  c.topk_i[0].ensure(sizeof(int) * (size_t)nb0 * K);
+  c.topk_k[1].ensure(sizeof(double) * (size_t)nb0 * K);
+  c.topk_i[1].ensure(sizeof(int) * (size_t)nb0 * K);
+  c.h_small.ensure(4096);
+  launch_fill_i32(c.smask.as<int>(), 0, c.smask.bytes / sizeof(int), c.st);
+  launch_fill_i32(c.done.as<int>(), -1, (size_t)n, c.st);
+  launch_fill_i32(c.cand_col.as<int>(), -1, (size_t)n, c.st);
+  std::vector<int> sample_host;
+  if (stochastic) {
+    c.sampled.ensure(sizeof(int) * n);
+    launch_fill_i32(c.sampled.as<int>(), -1, (size_t)n, c.st);
+  }
+
+  std::vector<uint8_t> inS((size_t)n, 0);
+  int s_size = 0;
+  int ell = 1;
+  if (tr && tr->n_forced > 0) {
+    if (tr->n_forced > k || !tr->forced) return fail(GED_ERR_ARG, "bad forced prefix");
+    for (int q = 0; q < tr->n_forced; ++q) {
+      const int u = tr->forced[q];
+      if (u < 0 || u >= n || inS[u]) return fail(GED_ERR_VERTEX, "bad forced vertex");
+      inS[u] = 1;
+      out_group[s_size] = u;
+      if (tr->ell) tr->ell[s_size] = -1;
+      if (tr->L1) tr->L1[s_size] = NAN;
+      if (tr->U2) tr->U2[s_size] = NAN;
+      if (tr->L2) tr->L2[s_size] = NAN;
+      if (tr->B) tr->B[s_size] = NAN;
+      if (tr->evals) tr->evals[s_size] = 0;
+      s_size++;
+      hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
+    }
+    ell = tr->forced_ell >= 1 ? tr->forced_ell : 1;
+  }
+  int round = 0;
+  int sample_pick = -1;
+  std::vector<double> hk(K);
+  std::vector<int> hi(K);
+  std::vector<double> gains(c.C);
+  while (s_size < k) {
+    if (ell > 65536) return fail(GED_ERR_ELL, "walk length limit reached in greedy");
+    ensure_levels_cap(c, ell);
+    const double B = comb_bound(g, alpha, walk_total(g, ell));
+    launch_fill_f64(c.stale.as<double>(), -1.0, (size_t)n, c.st);
+    bool need_chain = true;
+    while (s_size < k) {
+      if (stochastic && sample_pick != s_size) {
+        // one sample of ceil((n/k) ln(1/eta)) vertices of V \ S per addition
+        const int64_t want = (int64_t)ceil((double)n / k * log(1.0 / eta));
+        const int rest = n - s_size;
+        const int m = (int)std::min<int64_t>(want, rest);
+        std::vector<int> pool;
+        pool.reserve(rest);
+        for (int x = 0; x < n; ++x)
+          if (!inS[x]) pool.push_back(x);
+        // partial Fisher-Yates with splitmix64 at counter (addition, j)
+        for (int j = 0; j < m; ++j) {
+          const uint64_t r =
+              sm_mix(seed + 0x9E3779B97F4A7C15ULL * ((uint64_t)s_size * 0x100000000ULL + j + 1));
+          const int q = j + (int)(((__uint128_t)r * (uint64_t)(rest - j)) >> 64);
+          std::swap(pool[j], pool[q]);
+        }
+        sample_host.assign((size_t)n, -1);
+        for (int j = 0; j < m; ++j) sample_host[pool[j]] = s_size;
+        GED_HIP(hipMemcpyAsync(c.sampled.p, sample_host.data(), sizeof(int) * n,
+                               hipMemcpyHostToDevice, c.st));
+        GED_HIP(hipStreamSynchronize(c.st));
+        sample_pick = s_size;
+      }
+      if (need_chain) {
+        miss_chains(c, ell);
+        need_chain = false;
+      }
+      compute_bounds(c, ell);
+      ++round;
+      ++c.rounds;
+      Top2 top;
+      for (;;) {
+        const int m = select_topk(c, K, round, stochastic ? c.sampled.as<const int>() : nullptr,
+                                  s_size, hk.data(), hi.data());
+        if (m == 0) break;
+        if (top.v >= 0 && hk[0] < top.L2) break;  // no bound reaches the runner-up
+        const int nc = std::min(m, c.C);
+        eval_batch(c, hi.data(), nc, ell, round, gains.data());
+        for (int q = 0; q < nc; ++q) top.add(gains[q], hi[q]);
+        if (m <= c.C) break;  // nothing else eligible
+      }
+      if (top.u < 0) return fail(GED_ERR_ARG, "no candidate left");
+      if (top.v >= 0 && top.L1 <= (top.L2 + B) - eps / (double)k) break;  // not separated
+      const int u = top.u;
+      inS[u] = 1;
+      out_group[s_size] = u;
+      if (tr) {
+        if (tr->ell) tr->ell[s_size] = ell;
+        if (tr->L1) tr->L1[s_size] = top.L1;
+        if (tr->U2) tr->U2[s_size] = top.v >= 0 ? top.L2 + B : NAN;
+        if (tr->L2) tr->L2[s_size] = top.v >= 0 ? top.L2 : NAN;
+        if (tr->B) tr->B[s_size] = B;
+        if (tr->evals) tr->evals[s_size] = c.evals;
+      }
+      s_size++;
+      hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
+      need_chain = true;
+    }
+    if (s_size < k) ell *= 2;
+  }
+  GED_HIP(hipStreamSynchronize(c.st));
+  if (tr) tr->n_rounds = c.rounds;
+  if (out_score) {
+    ged_score_info info;
+    rc = score_group(g, out_group, k, alpha, eps, out_score, &info);
+    if (rc) return rc;
+    if (tr) tr->score_ell = info.ell;
+  }
+  return GED_OK;
+}
+
+}  // namespace ged
+
+using namespace ged;
+
+extern "C" int ged_greedy(ged_graph *g, int32_t k, double alpha, double eps, int32_t *out_group,
+                          double *out_score, ged_greedy_trace *trace) {
+  if (!g || !out_group) return fail(GED_ERR_ARG, "bad argument to ged_greedy");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() {
+    return greedy_run(g, k, alpha, eps, 0.0, 0, false, out_group, out_score, trace);
+  });
+}
+
+extern "C" int ged_greedy_stochastic(ged_graph *g, int32_t k, double alpha, double eps,
+                                     double eta, uint64_t seed, int32_t *out_group,
+                                     double *out_score, ged_greedy_trace *trace) {
+  if (!g || !out_group) return fail(GED_ERR_ARG, "bad argument to ged_greedy_stochastic");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() {
+    return greedy_run(g, k, alpha, eps, eta, seed, true, out_group, out_score, trace);
+  });
+}

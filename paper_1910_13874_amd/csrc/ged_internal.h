@@ -1,0 +1,298 @@
+// Internal declarations shared by the HIP translation units of libged_hip.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ged.h"
+
+namespace ged {
+
+// ----------------------------------------------------------------- errors --
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+struct HipError {
+  int code;
+  std::string msg;
+};
+
+#define GED_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::ged::HipError{GED_ERR_DEVICE, std::string(#expr) + ": " +                \
+                                                hipGetErrorString(e_)};                \
+  } while (0)
+
+// --------------------------------------------------------- device memory --
+
+// Owning device buffer (hipMalloc); throws HipError{GED_ERR_NOMEM} on failure.
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // grow to at least `nbytes` (contents are not preserved)
+  void ensure(size_t nbytes) {
+    if (nbytes <= bytes && p) return;
+    release();
+    if (nbytes == 0) nbytes = 256;
+    if (hipMalloc(&p, nbytes) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw HipError{GED_ERR_NOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed"};
+    }
+    bytes = nbytes;
+  }
+  template <class T>
+  T *as() const {
+    return reinterpret_cast<T *>(p);
+  }
+};
+
+// Pinned host buffer (hipHostMalloc).
+struct HBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  HBuf() = default;
+  HBuf(const HBuf &) = delete;
+  HBuf &operator=(const HBuf &) = delete;
+  ~HBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void ensure(size_t nbytes) {
+    if (nbytes <= bytes && p) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipHostMalloc(&p, nbytes ? nbytes : 256, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw HipError{GED_ERR_NOMEM, "hipHostMalloc failed"};
+    }
+    bytes = nbytes ? nbytes : 256;
+  }
+  template <class T>
+  T *as() const {
+    return reinterpret_cast<T *>(p);
+  }
+};
+
+// ------------------------------------------------------ work partitioning --
+
+// Launch geometry shared by every walk-count step kernel.
+constexpr int kBlock = 256;            // threads per block (4 wavefronts of 64)
+constexpr int kLdsDoubles = 4096;      // LDS staging per block (32 KiB)
+constexpr int kRowsPerBlock = 512;     // max rows of one row block
+constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
+
+// Row partition for a step with C columns: row blocks of consecutive short
+// rows (nnz*C <= kLdsDoubles) staged through LDS, and rows longer than that
+// split into fixed segments whose partial sums a fix-up pass combines.
+struct Partition {
+  int C = 0;
+  int n_blocks = 0;  // row blocks
+  int n_segs = 0;    // long-row segments
+  int n_long = 0;    // long rows
+  DBuf blocks;       // int2 [n_blocks]: (row0, row1)
+  DBuf segs;         // int4 [n_segs]:   (row, nnz0, nnz1, long index)
+  DBuf long_rows;    // int  [n_long]:   row id
+  DBuf long_first;   // int  [n_long+1]: first segment of each long row
+};
+
+// Gather source of a step (what x(u) means).
+enum InMode : int {
+  IN_VEC = 0,      // X[u*C + c]
+  IN_ONES = 1,     // 1
+  IN_NOTMASK = 2,  // 1 - [u in S]          (miss chain, level 0)
+  IN_MASK = 3,     // [u in S]              (hit chain, level 0)
+  IN_TILEMASK = 4, // bit c of tmask[u]     (batched hit chains, level 0)
+  IN_ONEHOT = 5,   // [cand_col[u] == c]    (gain chains, level 0)
+  IN_FRESH = 6     // fresh[c] ? bit c of tmask[u] : X[u*C+c]   (serving pool)
+};
+
+// Row epilogue of a step (what y(v) becomes).
+enum OutMode : int {
+  OUT_PLAIN = 0, // alpha * sum
+  OUT_INJ = 1,   // v in S ? inj[v] : alpha * sum                   (hit chain)
+  OUT_ZERO = 2,  // v in S ? 0 : alpha * sum                        (miss chain)
+  OUT_TILE = 3,  // bit c of tmask[v] ? inj[v] : alpha * sum        (batched hit chains)
+  OUT_GAIN = 4,  // v in S ? 0 : (cand_col[v] == c ? inj[v] : alpha * sum)  (gain chains)
+  OUT_POOL = 5   // bit c of tmask[v] ? inj[step[c]*n + v] : alpha * sum   (serving pool)
+};
+
+struct StepArgs {
+  const int *rp = nullptr;       // row_ptr int32 [n+1]
+  const int *ci = nullptr;       // col_idx int32 [nnz]
+  const double *w = nullptr;     // arc weights [nnz] or null
+  int n = 0;
+  int C = 1;
+  const double *X = nullptr;     // [n*C]
+  double *Y = nullptr;           // [n*C]
+  const uint32_t *smask = nullptr;  // S bitmap [ceil(n/32)]
+  const uint64_t *tmask = nullptr;  // per-vertex column bits [n]
+  const int *cand_col = nullptr;    // [n], -1 = not a candidate
+  const double *inj = nullptr;      // injection vector [n] (or level array for OUT_POOL)
+  const int *col_step = nullptr;    // [C] per-column level (OUT_POOL), 0 = idle
+  const int *fresh = nullptr;       // [C] first-step flags (IN_FRESH)
+  double alpha = 0;
+  double *blk_part = nullptr;    // [n_blocks*C] block column sums
+  double *seg_out = nullptr;     // [n_segs*C] raw segment sums
+  double *long_part = nullptr;   // [n_long*C] long-row outputs (for column sums)
+};
+
+// Walk-count step: Y = epilogue(alpha * A X) with column sums.  Three
+// launches: row blocks + segments, long-row fix-up, column reduction.
+void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
+                 hipStream_t st);
+// Column sums of the step just launched: level[c] = sum_v Y[v,c]; if acc is
+// non-null acc[c] += level[c] (in launch order, so deterministic).  level may
+// be null.  active (nullable, [C]) skips columns whose flag is 0.
+void launch_reduce(const Partition &p, const StepArgs &a, double *level, double *acc,
+                   const int *active, hipStream_t st);
+
+void build_partition(Partition &p, const std::vector<int> &row_ptr, int C);
+
+// Partial-sum buffers of one step stream (each path owns its own, so captured
+// graphs never see a buffer another path reallocated).
+struct StepWs {
+  DBuf blk, seg, lng;
+  void fit(const Partition &p) {
+    blk.ensure(sizeof(double) * (size_t)(p.n_blocks > 0 ? p.n_blocks : 1) * p.C);
+    seg.ensure(sizeof(double) * (size_t)(p.n_segs > 0 ? p.n_segs : 1) * p.C);
+    lng.ensure(sizeof(double) * (size_t)(p.n_long > 0 ? p.n_long : 1) * p.C);
+  }
+  void into(StepArgs &a) const {
+    a.blk_part = blk.as<double>();
+    a.seg_out = seg.as<double>();
+    a.long_part = lng.as<double>();
+  }
+};
+
+// --------------------------------------------------------- small kernels --
+void launch_fill_f64(double *p, double v, size_t count, hipStream_t st);
+void launch_fill_i32(int *p, int v, size_t count, hipStream_t st);
+void launch_mask_set(uint32_t *mask, const int *S, const int *s_len, int cap, int value,
+                     hipStream_t st);
+void launch_tmask_set(uint64_t *tmask, const int64_t *offsets, const int *members, int g0,
+                      int ncols, int value, hipStream_t st);
+void launch_sum_levels(const double *levels, int count, double *out, hipStream_t st);
+void launch_copy_f64(double *dst, const double *src, size_t count, hipStream_t st);
+
+// ------------------------------------------------------------ graph handle --
+
+struct PrepCache {
+  bool valid = false;
+  double alpha = 0, eps = 0;
+  int ell = 0;                 // ell*
+  double bound = 0;            // B_{ell*}
+  std::vector<double> W;       // W[i] = sum t_i, i = 0..computed
+  DBuf t_levels;               // [(ell*+1) * n] decayed total walk counts t_0..t_ell*
+  DBuf t_tail[2];              // ping-pong vectors to extend W beyond ell*
+  int tail_level = -1;         // level held in t_tail[tail_cur]
+  int tail_cur = 0;
+};
+
+struct ScoreGraphExec;  // captured graph for ged_score
+
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int C;
+    double bytes, edges;
+    int kind;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+}  // namespace ged
+
+struct ged_graph {
+  int64_t n = 0, nnz = 0;
+  uint32_t flags = 0;
+  int32_t max_deg = 0;          // maximum out-degree (structural)
+  double max_wdeg = 0;          // maximum weighted out-degree (weighted graphs)
+  bool weighted = false;
+  std::vector<int> h_rp;        // host copy of row_ptr (int32) for partitioning
+  ged::DBuf rp, ci, w;          // device CSR (in-neighbour rows)
+  ged::DBuf rp_r, ci_r, w_r;    // reverse graph (directed only)
+  std::vector<int> h_rp_r;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  std::recursive_mutex mu;
+  std::map<int, std::unique_ptr<ged::Partition>> parts, parts_r;
+  ged::PrepCache prep;
+  // precomputation workspace (C = 1 steps)
+  ged::StepWs pws;
+  ged::DBuf levels;             // double [64] level sums
+  // plain-score workspace
+  ged::StepWs sws;
+  ged::DBuf mask;               // uint32 [ceil(n/32)+1], all zero between calls
+  ged::DBuf vec[2];             // double [n]
+  ged::DBuf s_levels;           // double [ell*+1] per-level hit sums
+  ged::DBuf acc;                // double [64]
+  ged::DBuf s_dev;              // int [1 + cap]: length, then members
+  ged::HBuf s_host;             // pinned staging of S
+  ged::HBuf out_host;
+  int s_cap = 0;
+  bool mask_ready = false;
+  hipGraphExec_t score_exec = nullptr;
+  hipGraph_t score_graph = nullptr;
+  std::vector<const void *> score_sig;  // pointers/values the captured graph depends on
+  // batched scoring
+  int32_t batch_tile = 0;
+  // profiling
+  ged::Profiler prof;
+  ~ged_graph();
+};
+
+namespace ged {
+
+// Partition for C columns (built on first use).
+Partition &partition(ged_graph *g, int C, bool reverse = false);
+// Precompute for (alpha, eps); throws HipError, returns status for arg errors.
+int prepare(ged_graph *g, double alpha, double eps);
+// W[ell] for arbitrary ell (extends the total-walk chain on demand).
+double walk_total(ged_graph *g, int ell);
+double comb_bound(ged_graph *g, double alpha, double W_ell);
+int check_alpha_eps(ged_graph *g, double alpha, double eps);
+StepArgs base_args(ged_graph *g, bool reverse = false);
+// Profiling hooks around one step launch.
+void prof_begin(ged_graph *g, hipStream_t st, hipEvent_t *a);
+void prof_end(ged_graph *g, hipStream_t st, hipEvent_t a, int C, double bytes, double edges,
+              int kind);
+double step_bytes(ged_graph *g, int C, bool reverse = false);
+// Drop the batched-scoring workspace of a graph that is being destroyed.
+void batch_forget(const ged_graph *g);
+
+// Run fn, translating HipError into a status code + message.
+template <class F>
+int guarded(F &&fn) {
+  try {
+    return fn();
+  } catch (const HipError &e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc &) {
+    return fail(GED_ERR_NOMEM, "host allocation failed");
+  }
+}
+
+}  // namespace ged

@@ -1,0 +1,264 @@
+"""Python binding of the GED-Walk HIP library (``libged_hip.so``, C ABI in
+``include/ged.h``).
+
+Argument marshalling only: every step of scoring and maximisation runs in the
+library's HIP kernels.  If the library is missing this module raises at import
+time -- there is no CPU fallback.  PyTorch is used only to hand the library a
+HIP stream (``GedGraph.set_stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libged_hip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(the GED-Walk path has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+P_I64 = ctypes.POINTER(ctypes.c_int64)
+P_I32 = ctypes.POINTER(ctypes.c_int32)
+P_F64 = ctypes.POINTER(ctypes.c_double)
+c_graph_p = ctypes.c_void_p
+
+GED_UNDIRECTED = 1
+GED_DIRECTED = 2
+
+STATUS = {0: "ok", -1: "bad argument", -2: "vertex out of range", -3: "alpha out of range",
+          -4: "eps out of range", -5: "malformed graph", -6: "out of memory",
+          -7: "device error", -8: "busy", -9: "walk length limit"}
+
+
+class ScoreInfo(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_int32), ("bound", ctypes.c_double),
+                ("walk_total", ctypes.c_double)]
+
+
+class GreedyTrace(ctypes.Structure):
+    _fields_ = [("ell", P_I32), ("L1", P_F64), ("U2", P_F64), ("L2", P_F64), ("B", P_F64),
+                ("evals", P_I64), ("forced", P_I32), ("n_forced", ctypes.c_int32),
+                ("forced_ell", ctypes.c_int32), ("score_ell", ctypes.c_int32),
+                ("n_rounds", ctypes.c_int32)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("edges", ctypes.c_double),
+                ("dominant_launches", ctypes.c_int64), ("dominant_ms", ctypes.c_double),
+                ("dominant_bytes", ctypes.c_double), ("dominant_columns", ctypes.c_int32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("ged_graph_create", ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, P_I64, P_I32,
+                                        ctypes.c_uint32, ctypes.POINTER(c_graph_p)])
+_sig("ged_graph_create_weighted", ctypes.c_int,
+     [ctypes.c_int64, ctypes.c_int64, P_I64, P_I32, P_F64, ctypes.c_uint32,
+      ctypes.POINTER(c_graph_p)])
+_sig("ged_graph_destroy", ctypes.c_int, [c_graph_p])
+_sig("ged_graph_info", ctypes.c_int, [c_graph_p, P_I64, P_I64, P_I32])
+_sig("ged_default_alpha", ctypes.c_double, [c_graph_p])
+_sig("ged_set_stream", ctypes.c_int, [c_graph_p, ctypes.c_void_p])
+_sig("ged_prepare", ctypes.c_int, [c_graph_p, ctypes.c_double, ctypes.c_double,
+                                   ctypes.POINTER(ScoreInfo)])
+_sig("ged_score", ctypes.c_int, [c_graph_p, P_I32, ctypes.c_int32, ctypes.c_double,
+                                 ctypes.c_double, P_F64, ctypes.POINTER(ScoreInfo)])
+_sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_double, P_F64])
+_sig("ged_batch_tile", ctypes.c_int32, [c_graph_p])
+_sig("ged_greedy", ctypes.c_int, [c_graph_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  P_I32, P_F64, ctypes.POINTER(GreedyTrace)])
+_sig("ged_greedy_stochastic", ctypes.c_int,
+     [c_graph_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+      ctypes.c_uint64, P_I32, P_F64, ctypes.POINTER(GreedyTrace)])
+_sig("ged_profile_enable", ctypes.c_int, [c_graph_p, ctypes.c_int])
+_sig("ged_profile_read", ctypes.c_int, [c_graph_p, ctypes.POINTER(Profile)])
+_sig("ged_last_error", ctypes.c_char_p, [])
+
+
+class GedError(RuntimeError):
+    def __init__(self, code, where):
+        msg = _lib.ged_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+def _ck(rc, where):
+    if rc != 0:
+        raise GedError(rc, where)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+    return a, a.ctypes.data_as(P_I32)
+
+
+class GedGraph:
+    """A graph resident on the GPU (CSR copied at construction)."""
+
+    def __init__(self, n, row_ptr, col_idx, directed=False, weights=None):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        if ci.size == 0:
+            ci = np.zeros(1, dtype=np.int32)
+        h = c_graph_p()
+        flags = GED_DIRECTED if directed else GED_UNDIRECTED
+        nnz = int(rp[-1])
+        if weights is None:
+            rc = _lib.ged_graph_create(n, nnz, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                                       flags, ctypes.byref(h))
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float64)
+            rc = _lib.ged_graph_create_weighted(n, nnz, rp.ctypes.data_as(P_I64),
+                                                ci.ctypes.data_as(P_I32),
+                                                w.ctypes.data_as(P_F64), flags, ctypes.byref(h))
+        _ck(rc, "ged_graph_create")
+        self._h = h
+        self.n = int(n)
+        self.nnz = nnz
+        self.directed = directed
+        self.weighted = weights is not None
+
+    @classmethod
+    def from_graph(cls, g, weights=None):
+        return cls(g.n, g.row_ptr, g.col_idx, directed=getattr(g, "directed", False),
+                   weights=weights)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("graph handle closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.ged_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n = ctypes.c_int64()
+        nnz = ctypes.c_int64()
+        md = ctypes.c_int32()
+        _ck(_lib.ged_graph_info(self.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(md)),
+            "ged_graph_info")
+        return n.value, nnz.value, md.value
+
+    @property
+    def max_degree(self):
+        return self.info()[2]
+
+    def default_alpha(self):
+        return _lib.ged_default_alpha(self.handle)
+
+    def set_stream(self, stream=None):
+        """Launch on a torch.cuda.Stream (or raw hipStream_t int); None = own stream."""
+        if stream is None:
+            ptr = None
+        elif isinstance(stream, int):
+            ptr = stream
+        else:
+            ptr = stream.cuda_stream
+        _ck(_lib.ged_set_stream(self.handle, ctypes.c_void_p(ptr) if ptr else None),
+            "ged_set_stream")
+
+    def _alpha(self, alpha):
+        return self.default_alpha() if alpha is None else float(alpha)
+
+    def prepare(self, alpha=None, eps=1e-4):
+        info = ScoreInfo()
+        _ck(_lib.ged_prepare(self.handle, self._alpha(alpha), eps, ctypes.byref(info)),
+            "ged_prepare")
+        return info.ell, info.bound, info.walk_total
+
+    def score(self, S, alpha=None, eps=1e-4, with_info=False):
+        arr, ptr = _i32(S)
+        out = ctypes.c_double()
+        info = ScoreInfo()
+        _ck(_lib.ged_score(self.handle, ptr if arr.size else None, arr.size, self._alpha(alpha),
+                           eps, ctypes.byref(out), ctypes.byref(info)), "ged_score")
+        if with_info:
+            return out.value, info.ell, info.bound
+        return out.value
+
+    def score_batch(self, offsets, members, alpha=None, eps=1e-4):
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        mem = np.ascontiguousarray(members, dtype=np.int32)
+        G = off.size - 1
+        out = np.zeros(max(G, 1))
+        _ck(_lib.ged_score_batch(self.handle, off.ctypes.data_as(P_I64),
+                                 mem.ctypes.data_as(P_I32) if mem.size else None, G,
+                                 self._alpha(alpha), eps, out.ctypes.data_as(P_F64)),
+            "ged_score_batch")
+        return out[:G]
+
+    def batch_tile(self):
+        return _lib.ged_batch_tile(self.handle)
+
+    def _greedy(self, fn, k, alpha, eps, extra, forced, forced_ell, with_score):
+        grp = np.zeros(k, dtype=np.int32)
+        t_ell = np.zeros(k, dtype=np.int32)
+        t_L1 = np.zeros(k)
+        t_U2 = np.zeros(k)
+        t_L2 = np.zeros(k)
+        t_B = np.zeros(k)
+        t_ev = np.zeros(k, dtype=np.int64)
+        tr = GreedyTrace()
+        tr.ell = t_ell.ctypes.data_as(P_I32)
+        tr.L1 = t_L1.ctypes.data_as(P_F64)
+        tr.U2 = t_U2.ctypes.data_as(P_F64)
+        tr.L2 = t_L2.ctypes.data_as(P_F64)
+        tr.B = t_B.ctypes.data_as(P_F64)
+        tr.evals = t_ev.ctypes.data_as(P_I64)
+        if forced is not None and len(forced):
+            farr, fptr = _i32(forced)
+            tr.forced = fptr
+            tr.n_forced = farr.size
+            tr.forced_ell = int(forced_ell)
+        sc = ctypes.c_double(math.nan)
+        rc = fn(self.handle, k, self._alpha(alpha), eps, *extra, grp.ctypes.data_as(P_I32),
+                ctypes.byref(sc) if with_score else None, ctypes.byref(tr))
+        _ck(rc, fn.__name__)
+        return {"group": grp, "ell": t_ell, "L1": t_L1, "U2": t_U2, "L2": t_L2, "B": t_B,
+                "evals": t_ev, "score": sc.value, "score_ell": tr.score_ell,
+                "rounds": tr.n_rounds}
+
+    def greedy(self, k, alpha=None, eps=1e-4, forced=None, forced_ell=1, with_score=True):
+        """Greedy maximisation; returns group (pick order) and the per-pick trace."""
+        return self._greedy(_lib.ged_greedy, k, alpha, eps, (), forced, forced_ell, with_score)
+
+    def greedy_stochastic(self, k, alpha=None, eps=1e-4, eta=0.1, seed=1, forced=None,
+                          forced_ell=1, with_score=True):
+        return self._greedy(_lib.ged_greedy_stochastic, k, alpha, eps,
+                            (ctypes.c_double(eta), ctypes.c_uint64(seed)), forced, forced_ell,
+                            with_score)
+
+    def profile_enable(self, on=True):
+        _ck(_lib.ged_profile_enable(self.handle, 1 if on else 0), "ged_profile_enable")
+
+    def profile_read(self):
+        p = Profile()
+        _ck(_lib.ged_profile_read(self.handle, ctypes.byref(p)), "ged_profile_read")
+        return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points this binding found in the library."""
+    return [n for n in dir(_lib) if n.startswith("ged_")]

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar (from the method's FP64 requirement): scores within 1e-9 relative and the
+same ell*; greedy picks and walk lengths identical (ties within 1e-12 excepted).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_13874_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-4
+REL = 1e-9
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ged():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_13874_amd import ged as mod
+    return mod
+
+
+def rel(a, b):
+    if a == b:
+        return 0.0
+    return abs(a - b) / max(abs(a), abs(b))
+
+
+def check_score(gg, g, S, alpha, eps=EPS, tag=""):
+    s, ell, B = gg.score(S, alpha, eps, with_info=True)
+    c, ell_o, B_o, _ = oracle.score(g, S, alpha, eps)
+    assert ell == ell_o, (tag, ell, ell_o)
+    assert rel(s, c) <= REL, (tag, s, c, rel(s, c))
+    assert rel(B, B_o) <= 1e-9
+    return s
+
+
+GRAPHS = {
+    "er1k": lambda: inputs.erdos_renyi(1000, 5000, 1),
+    "ba20k": lambda: inputs.barabasi_albert(20000, 5, 2),
+    "rmat16": lambda: inputs.rmat(16, 16, seed=18),
+    "er_sparse": lambda: inputs.erdos_renyi(3000, 2000, 7),  # many isolated vertices
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_score_parity(ged, name):
+    g = GRAPHS[name]()
+    say(f"[score parity] {name} n={g.n} nnz={g.nnz} dmax={g.max_degree}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    for seed, size in [(101, 5), (7, 1), (8, 37), (9, 200), (10, min(g.n, 1000))]:
+        check_score(gg, g, inputs.group(g.n, size, seed), alpha, tag=(name, seed, size))
+    # empty group, full vertex set, duplicates
+    assert gg.score([], alpha, EPS) == 0.0
+    full = gg.score(np.arange(g.n), alpha, EPS)
+    c_full = oracle.score(g, np.arange(g.n), alpha, EPS)[0]
+    assert rel(full, c_full) <= REL
+    S = inputs.group(g.n, 10, 3)
+    dup = np.concatenate([S, S[:4]])
+    assert gg.score(dup, alpha, EPS) == gg.score(S, alpha, EPS)
+    # a different eps re-prepares ell*
+    check_score(gg, g, S, alpha, eps=1e-8, tag=(name, "eps1e-8"))
+    check_score(gg, g, S, alpha, eps=EPS, tag=(name, "eps back"))
+    gg.close()
+
+
+def test_score_deterministic_and_alpha_change(ged):
+    g = GRAPHS["rmat16"]()
+    gg = ged.GedGraph.from_graph(g)
+    S = inputs.group(g.n, 20, 44)
+    a1 = g.default_alpha()
+    x = [gg.score(S, a1, EPS) for _ in range(3)]
+    assert x[0] == x[1] == x[2]
+    check_score(gg, g, S, a1 / 3, tag="alpha/3")
+    assert gg.score(S, a1, EPS) == x[0]
+    gg.close()
+
+
+def test_directed_score_and_greedy(ged):
+    n = 2000
+    r = inputs.uniform_ints(2 * 9000, n, 61)
+    g = inputs.from_edges(n, r[0::2], r[1::2], symmetrize=False, name="dir2k")
+    rev = inputs.reverse(g)
+    say(f"[directed] n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = oracle.default_alpha(g)
+    assert abs(gg.default_alpha() - alpha) == 0.0
+    for seed, size in [(1, 3), (2, 40)]:
+        check_score(gg, g, inputs.group(n, size, seed), alpha, tag=("dir", seed))
+    rg = gg.greedy(5, alpha, EPS)
+    ro = oracle.greedy(g, 5, alpha, EPS, rev=rev)
+    assert list(rg["group"]) == list(ro["group"])
+    assert list(rg["ell"]) == list(ro["ell"])
+    gg.close()
+
+
+def test_edgeless_and_tiny(ged):
+    g = inputs.from_edges(5, [], [], symmetrize=True)
+    gg = ged.GedGraph.from_graph(g)
+    assert gg.score([0, 3], 0.5, EPS) == 0.0
+    r = gg.greedy(2, 0.5, EPS)
+    assert list(r["group"]) == [0, 1]
+    gg.close()
+    k2 = inputs.from_edges(2, [0], [1])
+    gk = ged.GedGraph.from_graph(k2)
+    s = gk.score([0], 0.4, 1e-12)
+    assert abs(s - 2 * 0.4 / 0.6) <= 1e-11  # 2 walks of every length touch vertex 0
+    gk.close()
+
+
+def test_errors(ged):
+    g = GRAPHS["er1k"]()
+    gg = ged.GedGraph.from_graph(g)
+    with pytest.raises(ged.GedError) as e:
+        gg.score([g.n], g.default_alpha(), EPS)
+    assert e.value.code == -2
+    with pytest.raises(ged.GedError) as e:
+        gg.score([1], 1.0 / g.max_degree, EPS)
+    assert e.value.code == -3
+    with pytest.raises(ged.GedError) as e:
+        gg.score([1], g.default_alpha(), 0.0)
+    assert e.value.code == -4
+    with pytest.raises(ged.GedError) as e:
+        gg.greedy(g.n + 1, g.default_alpha(), EPS)
+    assert e.value.code == -1
+    # still usable after errors
+    check_score(gg, g, [1, 2, 3], g.default_alpha())
+    gg.close()
+    # malformed CSR
+    with pytest.raises(ged.GedError) as e:
+        ged.GedGraph(3, np.array([0, 1, 2, 3]), np.array([1, 2, 2]))  # self-loop at 2
+    assert e.value.code == -5
+    with pytest.raises(ged.GedError) as e:
+        ged.GedGraph(3, np.array([0, 1, 1, 1]), np.array([1]))  # not symmetric
+    assert e.value.code == -5
+
+
+def compare_greedy(rg, ro, tag):
+    assert list(rg["group"]) == list(ro["group"]), (tag, rg["group"], ro["group"])
+    assert list(rg["ell"]) == list(ro["ell"]), (tag, rg["ell"], ro["ell"])
+    for j in range(len(rg["group"])):
+        assert rel(rg["L1"][j], ro["L1"][j]) <= REL, (tag, j, rg["L1"][j], ro["L1"][j])
+        if not np.isnan(ro["U2"][j]):
+            assert rel(rg["U2"][j], ro["U2"][j]) <= REL
+    assert rel(rg["score"], ro["score"]) <= REL
+    assert rg["score_ell"] == ro["score_ell"]
+
+
+@pytest.mark.parametrize("name,k", [("er1k", 5), ("ba20k", 10), ("rmat16", 8), ("er_sparse", 6)])
+def test_greedy_parity(ged, name, k):
+    g = GRAPHS[name]()
+    say(f"[greedy parity] {name} k={k}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    rg = gg.greedy(k, alpha, EPS)
+    ro = oracle.greedy(g, k, alpha, EPS)
+    compare_greedy(rg, ro, name)
+    gg.close()
+
+
+def test_greedy_forced_prefix(ged):
+    g = GRAPHS["ba20k"]()
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    full = gg.greedy(6, alpha, EPS)
+    rep = gg.greedy(6, alpha, EPS, forced=full["group"][:3], forced_ell=int(full["ell"][2]))
+    assert list(rep["group"]) == list(full["group"])
+    gg.close()
+
+
+def test_greedy_ties_smallest_id(ged):
+    src = [0, 0, 0, 4, 4, 4]
+    dst = [1, 2, 3, 5, 6, 7]
+    g = inputs.from_edges(8, src, dst)
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    r = gg.greedy(4, alpha, EPS)
+    assert list(r["group"]) == [0, 4, 1, 2]
+    ro = oracle.greedy(g, 4, alpha, EPS)
+    compare_greedy(r, ro, "double star")
+    gg.close()
+
+
+def test_batch_matches_solo_and_oracle(ged):
+    g = GRAPHS["ba20k"]()
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    off, mem = inputs.groups(g.n, 150, 1, 200, 104)
+    # add an empty group at the end
+    off = np.concatenate([off, [off[-1]]])
+    say(f"[batch] groups={len(off) - 1}")
+    b = gg.score_batch(off, mem, alpha, EPS)
+    tile = gg.batch_tile()
+    assert tile in (8, 16, 32, 64)
+    for j in range(len(off) - 1):
+        S = mem[off[j]:off[j + 1]]
+        solo = gg.score(S, alpha, EPS)
+        assert rel(b[j], solo) <= 1e-12, (j, b[j], solo)
+        if j % 25 == 0:
+            c = oracle.score(g, S, alpha, EPS)[0]
+            assert rel(b[j], c) <= REL
+    assert b[-1] == 0.0
+    # a second, smaller call reuses the workspace
+    b2 = gg.score_batch(off[:6], mem[:off[5]], alpha, EPS)
+    np.testing.assert_array_equal(b2, b[:5])
+    gg.close()
+
+
+# ------------------------------------------------------------ full sizes --
+
+def load_golden(name):
+    p = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    with open(p) as f:
+        return json.load(f)
+
+
+@pytest.mark.timeout(600)
+def test_full_size_ba1m(ged):
+    """BA n=1e6, m=5 at full size: oracle scores and the oracle's greedy k=10 trace."""
+    gold = load_golden("ba1m")
+    g = inputs.workload_graph("ba1m")
+    assert g.fingerprint() == gold["fingerprint"]
+    say(f"[full ba1m] n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = gold["alpha"]
+    for rec in gold["scores"]:
+        S = inputs.group(g.n, rec["size"], rec["seed"])
+        s, ell, B = gg.score(S, alpha, EPS, with_info=True)
+        assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
+    gr = gold["greedy"]
+    rg = gg.greedy(gr["k"], alpha, EPS)
+    compare_greedy(rg, gr, "ba1m")
+    gg.close()
+
+
+@pytest.mark.timeout(900)
+def test_full_size_rmat22(ged):
+    """R-MAT scale 22 at full size: oracle scores, the oracle's first picks, and
+    the separation invariants of a k=100 run."""
+    gold = load_golden("rmat22")
+    g = inputs.workload_graph("rmat22")
+    assert g.fingerprint() == gold["fingerprint"]
+    say(f"[full rmat22] n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = gold["alpha"]
+    for rec in gold["scores"]:
+        S = inputs.group(g.n, rec["size"], rec["seed"])
+        s, ell, B = gg.score(S, alpha, EPS, with_info=True)
+        assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
+    gr = gold["greedy"]
+    k = 100
+    rg = gg.greedy(k, alpha, EPS)
+    kk = gr["k"]
+    assert list(rg["group"][:kk]) == gr["group"]
+    assert list(rg["ell"][:kk]) == gr["ell"]
+    for j in range(kk):
+        assert rel(rg["L1"][j], gr["L1"][j]) <= REL
+    # any-size properties of the rest of the run
+    assert len(set(int(x) for x in rg["group"])) == k
+    assert np.all(np.diff(rg["ell"]) >= 0)
+    for j in range(k):
+        assert rg["L1"][j] > rg["U2"][j] - EPS / k
+        assert rg["L1"][j] >= rg["L2"][j]
+    # the greedy's score is the plain score of its group
+    assert rg["score"] == gg.score(rg["group"], alpha, EPS)
+    gg.close()
