@@ -1,0 +1,291 @@
+#!/usr/bin/env python
+"""GED-Walk benchmark on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints ONE JSON line.  `value` is whole-step walk-count throughput in GTEPS:
+arcs x columns traversed by every walk-count step kernel of the timed steps,
+divided by the wall time of those steps (inputs resident in HBM, graph CSR
+uploaded before timing).  `roofline` reports the dominant step kernel's
+algorithmic bytes per launch over its average HIP-event duration, against the
+8 TB/s HBM peak; `cpu_baseline` times the CPU oracle on a bounded sample of the
+same workload.
+
+Workloads (a "step" is one pass of the hot path over one batch of input):
+  ba1m    (default) Barabasi-Albert n=1,000,000, m=5: per step the per-graph
+          precompute (t-levels, ell*), 16 single-group scores (|S|=5), greedy
+          k=10 and a batched scoring of 256 groups (|S| ~ U[1,200]).
+  rmat22  R-MAT scale 22, edge factor 16: precompute, 16 scores, greedy k=100.
+  er1k    Erdos-Renyi n=1,000, average degree 10: precompute, score |S|=5,
+          greedy k=5.
+  batch   Barabasi-Albert n=2,000,000, m=8: 4,096 groups (|S| ~ U[1,200])
+          scored batched vs 4,096 sequential single-group calls.
+  serve   request stream over 8 resident graphs (see paper_1910_13874_amd/serve.py).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walk-count SpMV GTEPS (%HBM roofline); greedy k=100 s; p50/p99 score ms"
+HBM_PEAK_GBS = 8000.0
+EPS = 1e-4
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ged_kernels.hip", "ged_internal.h"):
+        with open(os.path.join(ROOT, "paper_1910_13874_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    if there is none or the step kernels changed since it was taken."""
+    p = os.path.join(PROFILES, f"traffic_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(g, alpha, groups, budget_s=12.0):
+    """The oracle's single-group score, timed on this host (one core)."""
+    import oracle
+    done = 0
+    edges = 0.0
+    t0 = time.perf_counter()
+    for S in groups:
+        c, ell, B, _ = oracle.score(g, S, alpha, EPS)
+        edges += ell * g.nnz
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": edges / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{done} single-group scores (|S|={len(groups[0])}) of the same graph "
+                      f"by the single-threaded FP64 oracle, {dt:.1f} s",
+            "seconds_per_score": dt / done}
+
+
+def roofline(prof, ged, workload):
+    ms = prof["dominant_ms"] / max(1, prof["dominant_launches"])
+    bytes_per = prof["dominant_bytes"] / max(1, prof["dominant_launches"])
+    achieved = bytes_per / (ms * 1e-3) / 1e9
+    kname = ged.kernel_name(prof["dominant_columns"], prof["dominant_kind"])
+    tr = traffic_for(workload, kname)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
+            "avg_launch_us": ms * 1e3, "algorithmic_bytes_per_launch": bytes_per,
+            "launches": prof["dominant_launches"]}
+
+
+def run_steps(step, K, W, gg, torch):
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    gg.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        step()
+        log(f"step {i + 1}/{K} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = gg.profile_read()
+    gg.profile_enable(False)
+    return dt, prof
+
+
+def score_latency(gg, groups, alpha, torch, reps=200):
+    lat = []
+    for j in range(reps):
+        S = groups[j % len(groups)]
+        t = time.perf_counter()
+        gg.score(S, alpha, EPS)
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat)
+    return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+
+def bench_graph_workload(args, torch, ged, inputs):
+    name = args.workload
+    spec = {
+        "ba1m": dict(graph="ba1m", k=10, n_scores=16, batch=256,
+                     desc="Barabasi-Albert n=1,000,000 m=5, CSR int32, FP64, alpha=1/(maxdeg+1), "
+                          "eps=1e-4: precompute + 16 scores |S|=5 + greedy k=10 + batch of 256 "
+                          "groups |S|~U[1,200]"),
+        "rmat22": dict(graph="rmat22", k=100, n_scores=16, batch=0,
+                       desc="R-MAT scale 22 edge factor 16 (0.57,0.19,0.19,0.05) symmetrized, "
+                            "FP64, alpha=1/(maxdeg+1), eps=1e-4: precompute + 16 scores |S|=5 + "
+                            "greedy k=100"),
+        "er1k": dict(graph="er1k", k=5, n_scores=1, batch=0,
+                     desc="Erdos-Renyi n=1,000 avg degree 10, FP64, alpha=1/(maxdeg+1), "
+                          "eps=1e-4: precompute + score |S|=5 + greedy k=5"),
+    }[name]
+    t_gen = time.perf_counter()
+    g = inputs.workload_graph(spec["graph"])
+    log(f"graph {name}: n={g.n} nnz={g.nnz} dmax={g.max_degree} "
+        f"({time.perf_counter() - t_gen:.1f}s)")
+    gg = ged.GedGraph.from_graph(g)
+    stream = torch.cuda.Stream()
+    gg.set_stream(stream)
+    alpha = gg.default_alpha()
+    groups = [inputs.group(g.n, 5, 1000 + j) for j in range(max(spec["n_scores"], 16))]
+    if spec["batch"]:
+        off, mem = inputs.groups(g.n, spec["batch"], 1, 200, 104)
+    info = {}
+
+    def step():
+        gg.invalidate()
+        info["ell"] = gg.prepare(alpha, EPS)[0]
+        for S in groups[:spec["n_scores"]]:
+            gg.score(S, alpha, EPS)
+        t = time.perf_counter()
+        r = gg.greedy(spec["k"], alpha, EPS)
+        info["greedy_s"] = time.perf_counter() - t
+        info["greedy"] = r
+        if spec["batch"]:
+            gg.score_batch(off, mem, alpha, EPS)
+
+    dt, prof = run_steps(step, args.steps, args.warmup, gg, torch)
+    p50, p99 = score_latency(gg, groups, alpha, torch)
+    # greedy alone, untimed by the profiler (its own wall clock)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rg = gg.greedy(spec["k"], alpha, EPS)
+    greedy_s = time.perf_counter() - t
+    out = {
+        "metric": METRIC, "value": prof["edges"] / dt / 1e9, "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": spec["desc"], "graph": spec["graph"], "n": g.n, "nnz": g.nnz,
+                   "max_degree": g.max_degree, "alpha": alpha, "eps": EPS, "ell_star": info["ell"],
+                   "greedy_k": spec["k"], "score_groups": spec["n_scores"],
+                   "batch_groups": spec["batch"], "parallelism": "single GPU"},
+        "roofline": roofline(prof, ged, name),
+        "greedy_s": greedy_s,
+        "greedy_ells": [int(x) for x in rg["ell"]],
+        "greedy_evals": int(rg["evals"][-1]),
+        "score_ms_p50": p50, "score_ms_p99": p99,
+        "step_kernels_ms": prof["total_ms"] / args.steps,
+        "step_kernels_frac_of_step": prof["total_ms"] / (dt * 1e3),
+        "batch_tile": gg.batch_tile() if spec["batch"] else None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, alpha, groups)
+    gg.close()
+    return out
+
+
+def bench_batch(args, torch, ged, inputs):
+    """Batched scoring of 4,096 groups vs 4,096 sequential single-group calls."""
+    g = inputs.workload_graph("ba2m")
+    log(f"graph ba2m: n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g)
+    stream = torch.cuda.Stream()
+    gg.set_stream(stream)
+    alpha = gg.default_alpha()
+    G = args.groups
+    off, mem = inputs.groups(g.n, G, 1, 200, 104)
+    gg.prepare(alpha, EPS)
+
+    def step():
+        gg.score_batch(off, mem, alpha, EPS)
+
+    dt, prof = run_steps(step, args.steps, args.warmup, gg, torch)
+    batch_qps = G * args.steps / dt
+    # sequential plain calls on the same GPU (the one-at-a-time baseline)
+    n_seq = min(G, args.seq_sample)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    seq = np.zeros(n_seq)
+    for j in range(n_seq):
+        seq[j] = gg.score(mem[off[j]:off[j + 1]], alpha, EPS)
+    torch.cuda.synchronize()
+    seq_dt = time.perf_counter() - t
+    plain_qps = n_seq / seq_dt
+    b = gg.score_batch(off, mem, alpha, EPS)
+    maxrel = float(np.max(np.abs(b[:n_seq] - seq) / np.maximum(np.abs(seq), 1e-300)))
+    out = {
+        "metric": METRIC, "value": prof["edges"] / dt / 1e9, "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched scoring: {G} groups |S|~U[1,200] on Barabasi-Albert "
+                               "n=2,000,000 m=8, FP64, eps=1e-4", "n": g.n, "nnz": g.nnz,
+                   "groups": G, "tile": gg.batch_tile(), "parallelism": "single GPU"},
+        "roofline": roofline(prof, ged, "batch"),
+        "batch_queries_per_s": batch_qps, "plain_queries_per_s": plain_qps,
+        "batch_speedup": batch_qps / plain_qps, "plain_sample": n_seq,
+        "batch_vs_plain_max_rel": maxrel,
+    }
+    if not args.no_cpu:
+        groups = [mem[off[j]:off[j + 1]] for j in range(8)]
+        out["cpu_baseline"] = cpu_baseline(g, alpha, groups)
+    gg.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ba1m",
+                    choices=["ba1m", "rmat22", "er1k", "batch", "serve"])
+    ap.add_argument("--groups", type=int, default=4096)
+    ap.add_argument("--seq-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (single-GPU hot path); "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(3)
+    torch.cuda.set_device(0)
+    from paper_1910_13874_amd import ged, inputs
+    if args.copy_calib:
+        a = torch.empty(256 * 2 ** 20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.workload == "batch":
+        out = bench_batch(args, torch, ged, inputs)
+    elif args.workload == "serve":
+        from paper_1910_13874_amd import serve
+        out = serve.bench(args, torch, ged, inputs, METRIC)
+    else:
+        out = bench_graph_workload(args, torch, ged, inputs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,13 +55,18 @@ enum ged_status {
 #define GED_UNDIRECTED 1u /* col_idx is symmetric: rows are neighbour lists */
 #define GED_DIRECTED 2u   /* rows are in-neighbour lists of a directed graph */
 #define GED_WEIGHTED 4u   /* per-arc weights given (ged_graph_create_weighted) */
+#define GED_KEEP_ORDER 8u /* keep the caller's vertex order on the device (default:
+                             vertices are stored by decreasing out-degree, which
+                             concentrates the gathers of hub values in cache;
+                             results and ids seen by the caller are unchanged) */
 
 typedef struct ged_graph ged_graph;
 
 /*
  * Create a graph handle from a host CSR (row_ptr int64[n+1], col_idx
  * int32[nnz]); the arrays are copied to device memory owned by the handle.
- * flags: exactly one of GED_UNDIRECTED / GED_DIRECTED.  Validation
+ * flags: exactly one of GED_UNDIRECTED / GED_DIRECTED, optionally OR-ed with
+ * GED_KEEP_ORDER.  Validation
  * (GED_ERR_GRAPH): row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz,
  * 0 <= col_idx < n, no self-loops, nnz < 2^31; for GED_UNDIRECTED the arc set
  * must be symmetric.  Duplicate arcs count as parallel edges.
@@ -112,6 +117,9 @@ typedef struct {
  * by the score entry points; cached on the handle.  info may be NULL.
  */
 int ged_prepare(ged_graph *g, double alpha, double eps, ged_score_info *info);
+
+/* Drop the cached per-(alpha, eps) precomputation; the next call recomputes it. */
+int ged_invalidate(ged_graph *g);
 
 /*
  * GED_{<=ell*}(S) for one group (Section 3.1, Algorithm "GED-Walk
@@ -183,9 +191,10 @@ typedef struct {
   double bytes;            /* algorithmic bytes they moved */
   double edges;            /* arcs x columns they traversed */
   int64_t dominant_launches; /* launches of the most time-consuming step kernel */
-  double dominant_ms;
-  double dominant_bytes;
-  int32_t dominant_columns; /* its column count */
+  double dominant_ms;        /* their summed duration */
+  double dominant_bytes;     /* their summed algorithmic bytes */
+  int32_t dominant_columns;  /* its column count C */
+  int32_t dominant_kind;     /* its gather/epilogue variant (input mode * 8 + output mode) */
 } ged_profile;
 
 /* Start (on != 0) or stop timing every walk-count step launch of this handle

@@ -46,11 +46,27 @@ StepArgs base_args(ged_graph *g, bool reverse) {
   return a;
 }
 
-double step_bytes(ged_graph *g, int C, bool reverse) {
-  (void)reverse;
-  // row_ptr + col_idx (+ weights) + read X + write Y, all C columns
-  double b = 4.0 * (double)(g->n + 1) + 4.0 * (double)g->nnz + 16.0 * (double)g->n * C;
-  if (g->weighted) b += 8.0 * (double)g->nnz;
+double algo_bytes(const ged_graph *g, int C, int in, int out) {
+  const double n = (double)g->n, nnz = (double)g->nnz;
+  double b = 4.0 * (n + 1) + 4.0 * nnz + 8.0 * n * C;  // row_ptr, col_idx, Y
+  if (g->weighted) b += 8.0 * nnz;
+  switch (in) {
+    case IN_VEC: b += 8.0 * n * C; break;
+    case IN_MASK:
+    case IN_NOTMASK: b += n / 8.0; break;
+    case IN_TILEMASK: b += 8.0 * n; break;
+    case IN_ONEHOT: b += 4.0 * n; break;
+    case IN_FRESH: b += 8.0 * n * C + 8.0 * n; break;
+    default: break;  // IN_ONES reads nothing
+  }
+  switch (out) {
+    case OUT_INJ:
+    case OUT_ZERO: b += n / 8.0; break;
+    case OUT_TILE:
+    case OUT_POOL: b += 8.0 * n; break;
+    case OUT_GAIN: b += n / 8.0 + 4.0 * n; break;
+    default: break;
+  }
   return b;
 }
 
@@ -72,8 +88,7 @@ int check_alpha_eps(ged_graph *g, double alpha, double eps) {
 
 // ------------------------------------------------------------- profiling --
 
-void prof_begin(ged_graph *g, hipStream_t st, hipEvent_t *a) {
-  if (!g->prof.on) return;
+static hipEvent_t prof_event(ged_graph *g) {
   if (g->prof.pool.empty()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
@@ -81,34 +96,22 @@ void prof_begin(ged_graph *g, hipStream_t st, hipEvent_t *a) {
       g->prof.pool.push_back(e);
     }
   }
-  *a = g->prof.pool.back();
+  hipEvent_t e = g->prof.pool.back();
   g->prof.pool.pop_back();
-  GED_HIP(hipEventRecord(*a, st));
+  return e;
 }
 
-void prof_end(ged_graph *g, hipStream_t st, hipEvent_t a, int C, double bytes, double edges,
-              int kind) {
-  if (!g->prof.on) return;
-  if (g->prof.pool.empty()) {
-    for (int i = 0; i < 64; ++i) {
-      hipEvent_t e;
-      GED_HIP(hipEventCreate(&e));
-      g->prof.pool.push_back(e);
-    }
+void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int out,
+              hipStream_t st) {
+  if (!g->prof.on) {
+    launch_step(p, a, in, out, st);
+    return;
   }
-  hipEvent_t b = g->prof.pool.back();
-  g->prof.pool.pop_back();
-  GED_HIP(hipEventRecord(b, st));
-  g->prof.recs.push_back({a, b, C, bytes, edges, kind});
-}
-
-// One timed step launch: events bracket the step kernel (and its fix-up).
-static void timed_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int out,
-                       hipStream_t st) {
-  hipEvent_t ev = nullptr;
-  prof_begin(g, st, &ev);
-  launch_step(p, a, in, out, st);
-  prof_end(g, st, ev, a.C, step_bytes(g, a.C), (double)g->nnz * a.C, 0);
+  hipEvent_t e0 = prof_event(g), e1 = prof_event(g);
+  GED_HIP(hipEventRecord(e0, st));
+  launch_step(p, a, in, out, st, e1);
+  g->prof.recs.push_back(
+      {e0, e1, a.C, algo_bytes(g, a.C, in, out), (double)g->nnz * a.C, in * 8 + out});
 }
 
 // -------------------------------------------------------- precomputation --
@@ -154,7 +157,7 @@ int prepare(ged_graph *g, double alpha, double eps) {
     a.alpha = alpha;
     a.X = T + (size_t)(i - 1) * n;
     a.Y = T + (size_t)i * n;
-    launch_step(p, a, i == 1 ? IN_ONES : IN_VEC, OUT_PLAIN, st);
+    run_step(g, p, a, i == 1 ? IN_ONES : IN_VEC, OUT_PLAIN, st);
     launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st);
     GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
     GED_HIP(hipStreamSynchronize(st));
@@ -196,7 +199,7 @@ double walk_total(ged_graph *g, int ell) {
     a.alpha = pc.alpha;
     a.X = pc.t_tail[pc.tail_cur].as<double>();
     a.Y = pc.t_tail[pc.tail_cur ^ 1].as<double>();
-    launch_step(p, a, IN_VEC, OUT_PLAIN, st);
+    run_step(g, p, a, IN_VEC, OUT_PLAIN, st);
     launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st);
     GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
     GED_HIP(hipStreamSynchronize(st));
@@ -230,7 +233,7 @@ static void enqueue_score(ged_graph *g, hipStream_t st, bool timed) {
     a.Y = g->vec[i & 1].as<double>();
     a.inj = T + (size_t)i * n;
     if (timed)
-      timed_step(g, p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
+      run_step(g, p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
     else
       launch_step(p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
     launch_reduce(p, a, g->s_levels.as<double>() + i, g->acc.as<double>(), nullptr, st);
@@ -302,7 +305,7 @@ int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, dou
   ensure_score_buffers(g, s_len, st);
   int *hs = g->s_host.as<int>();
   hs[0] = s_len;
-  std::memcpy(hs + 1, S, sizeof(int) * (size_t)s_len);
+  for (int32_t q = 0; q < s_len; ++q) hs[1 + q] = g->new_id[S[q]];
   GED_HIP(hipMemcpyAsync(g->s_dev.p, hs, sizeof(int) * (size_t)(s_len + 1),
                          hipMemcpyHostToDevice, st));
   if (g->prof.on) {
@@ -365,8 +368,10 @@ static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int
   if (n < 1 || n > INT32_MAX - 1) return fail(GED_ERR_ARG, "n must be in [1, 2^31-2]");
   if (nnz < 0 || nnz >= (int64_t)INT32_MAX) return fail(GED_ERR_GRAPH, "nnz must be < 2^31");
   if (!row_ptr || (nnz > 0 && !col_idx)) return fail(GED_ERR_ARG, "null CSR array");
+  const bool keep_order = (flags & GED_KEEP_ORDER) != 0;
+  flags &= ~GED_KEEP_ORDER;
   if (flags != GED_UNDIRECTED && flags != GED_DIRECTED)
-    return fail(GED_ERR_ARG, "flags must be GED_UNDIRECTED or GED_DIRECTED");
+    return fail(GED_ERR_ARG, "flags must be GED_UNDIRECTED or GED_DIRECTED (| GED_KEEP_ORDER)");
   if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(GED_ERR_GRAPH, "row_ptr ends mismatch");
   std::vector<int64_t> outdeg((size_t)n, 0);
   uint64_t h_fwd = 0, h_bwd = 0;
@@ -414,43 +419,85 @@ static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int
     for (double x : wout) m = std::max(m, x);
     g->max_wdeg = m;
   }
+  // ---- internal vertex order: stable counting sort by decreasing out-degree
+  const int N = (int)n;
+  g->new_id.resize((size_t)N);
+  g->old_id.resize((size_t)N);
+  if (keep_order) {
+    for (int v = 0; v < N; ++v) g->new_id[v] = g->old_id[v] = v;
+  } else {
+    std::vector<int64_t> cnt((size_t)md + 2, 0);
+    for (int v = 0; v < N; ++v) cnt[(size_t)(md - outdeg[v]) + 1]++;
+    for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
+    for (int v = 0; v < N; ++v) {
+      const int pos = (int)cnt[(size_t)(md - outdeg[v])]++;
+      g->new_id[v] = pos;
+      g->old_id[pos] = v;
+    }
+  }
+  // ---- CSR in internal ids with sorted rows, built by two scatter passes:
+  // scattering the arcs of rows taken in increasing order into buckets keyed
+  // by the other endpoint yields the transposed matrix with sorted rows.
+  // out-rows (reverse graph): row nu lists nv for every arc u -> v.
+  std::vector<int> orp((size_t)N + 1, 0), oci((size_t)std::max<int64_t>(1, nnz));
+  std::vector<double> ow(weights ? (size_t)std::max<int64_t>(1, nnz) : 0);
+  for (int v = 0; v < N; ++v) orp[(size_t)g->new_id[v] + 1] = (int)outdeg[v];
+  for (int v = 0; v < N; ++v) orp[(size_t)v + 1] += orp[v];
+  {
+    std::vector<int> pos(orp.begin(), orp.end() - 1);
+    for (int nv = 0; nv < N; ++nv) {
+      const int v = g->old_id[nv];
+      for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+        const int nu = g->new_id[col_idx[j]];
+        const int q = pos[nu]++;
+        oci[q] = nv;
+        if (weights) ow[q] = weights[j];
+      }
+    }
+  }
+  // in-rows: row nv lists nu for every arc u -> v (scatter the out-rows back)
+  std::vector<int> irp((size_t)N + 1, 0), ici((size_t)std::max<int64_t>(1, nnz));
+  std::vector<double> iw(weights ? (size_t)std::max<int64_t>(1, nnz) : 0);
+  for (int nv = 0; nv < N; ++nv) {
+    const int v = g->old_id[nv];
+    irp[(size_t)nv + 1] = (int)(row_ptr[v + 1] - row_ptr[v]);
+  }
+  for (int v = 0; v < N; ++v) irp[(size_t)v + 1] += irp[v];
+  {
+    std::vector<int> pos(irp.begin(), irp.end() - 1);
+    for (int nu = 0; nu < N; ++nu)
+      for (int q = orp[nu]; q < orp[nu + 1]; ++q) {
+        const int r = pos[oci[q]]++;
+        ici[r] = nu;
+        if (weights) iw[r] = ow[q];
+      }
+  }
   return guarded([&]() -> int {
     GED_HIP(hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking));
     g->stream = g->own_stream;
-    g->h_rp.resize((size_t)n + 1);
-    for (int64_t v = 0; v <= n; ++v) g->h_rp[v] = (int)row_ptr[v];
+    g->h_rp = irp;
     g->rp.ensure(sizeof(int) * (size_t)(n + 1));
     g->ci.ensure(sizeof(int) * (size_t)std::max<int64_t>(1, nnz));
-    GED_HIP(hipMemcpy(g->rp.p, g->h_rp.data(), sizeof(int) * (size_t)(n + 1),
-                      hipMemcpyHostToDevice));
+    GED_HIP(hipMemcpy(g->rp.p, irp.data(), sizeof(int) * (size_t)(n + 1), hipMemcpyHostToDevice));
     if (nnz > 0)
-      GED_HIP(hipMemcpy(g->ci.p, col_idx, sizeof(int) * (size_t)nnz, hipMemcpyHostToDevice));
+      GED_HIP(hipMemcpy(g->ci.p, ici.data(), sizeof(int) * (size_t)nnz, hipMemcpyHostToDevice));
     if (weights) {
       g->w.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, nnz));
       if (nnz > 0)
-        GED_HIP(hipMemcpy(g->w.p, weights, sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice));
+        GED_HIP(hipMemcpy(g->w.p, iw.data(), sizeof(double) * (size_t)nnz, hipMemcpyHostToDevice));
     }
+    g->d_old_id.ensure(sizeof(int) * (size_t)n);
+    GED_HIP(hipMemcpy(g->d_old_id.p, g->old_id.data(), sizeof(int) * (size_t)n,
+                      hipMemcpyHostToDevice));
     if (flags == GED_DIRECTED) {
-      // reverse graph: row u lists the out-neighbours v of u (arcs u -> v)
-      std::vector<int> rr((size_t)n + 1, 0), cr((size_t)std::max<int64_t>(1, nnz));
-      std::vector<double> wr(weights ? (size_t)std::max<int64_t>(1, nnz) : 0);
-      for (int64_t j = 0; j < nnz; ++j) rr[col_idx[j] + 1]++;
-      for (int64_t v = 0; v < n; ++v) rr[v + 1] += rr[v];
-      std::vector<int> pos(rr.begin(), rr.end() - 1);
-      for (int64_t v = 0; v < n; ++v)
-        for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
-          const int q = pos[col_idx[j]]++;
-          cr[q] = (int)v;
-          if (weights) wr[q] = weights[j];
-        }
-      g->h_rp_r = rr;
+      g->h_rp_r = orp;
       g->rp_r.ensure(sizeof(int) * (size_t)(n + 1));
-      g->ci_r.ensure(sizeof(int) * cr.size());
-      GED_HIP(hipMemcpy(g->rp_r.p, rr.data(), sizeof(int) * rr.size(), hipMemcpyHostToDevice));
-      GED_HIP(hipMemcpy(g->ci_r.p, cr.data(), sizeof(int) * cr.size(), hipMemcpyHostToDevice));
+      g->ci_r.ensure(sizeof(int) * oci.size());
+      GED_HIP(hipMemcpy(g->rp_r.p, orp.data(), sizeof(int) * orp.size(), hipMemcpyHostToDevice));
+      GED_HIP(hipMemcpy(g->ci_r.p, oci.data(), sizeof(int) * oci.size(), hipMemcpyHostToDevice));
       if (weights) {
-        g->w_r.ensure(sizeof(double) * wr.size());
-        GED_HIP(hipMemcpy(g->w_r.p, wr.data(), sizeof(double) * wr.size(),
+        g->w_r.ensure(sizeof(double) * ow.size());
+        GED_HIP(hipMemcpy(g->w_r.p, ow.data(), sizeof(double) * ow.size(),
                           hipMemcpyHostToDevice));
       }
     }
@@ -521,6 +568,18 @@ extern "C" int ged_prepare(ged_graph *g, double alpha, double eps, ged_score_inf
   });
 }
 
+extern "C" int ged_invalidate(ged_graph *g) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    GED_HIP(hipStreamSynchronize(g->stream));
+    g->prep.valid = false;
+    g->prep.W.clear();
+    g->prep.tail_level = -1;
+    return GED_OK;
+  });
+}
+
 extern "C" int ged_score(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
                          double *out_score, ged_score_info *info) {
   if (!g || !out_score || (s_len > 0 && !S) || s_len < 0)
@@ -550,7 +609,7 @@ extern "C" int ged_profile_read(ged_graph *g, ged_profile *out) {
   return guarded([&]() -> int {
     GED_HIP(hipStreamSynchronize(g->stream));
     std::memset(out, 0, sizeof(*out));
-    std::map<int, std::tuple<int64_t, double, double>> by_c;
+    std::map<std::pair<int, int>, std::tuple<int64_t, double, double>> by_kernel;
     for (auto &r : g->prof.recs) {
       float ms = 0.f;
       GED_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -558,16 +617,17 @@ extern "C" int ged_profile_read(ged_graph *g, ged_profile *out) {
       out->total_ms += ms;
       out->bytes += r.bytes;
       out->edges += r.edges;
-      auto &e = by_c[r.C];
+      auto &e = by_kernel[{r.C, r.kind}];
       std::get<0>(e)++;
       std::get<1>(e) += ms;
       std::get<2>(e) += r.bytes;
     }
     double best = -1;
-    for (auto &kv : by_c) {
+    for (auto &kv : by_kernel) {
       if (std::get<1>(kv.second) > best) {
         best = std::get<1>(kv.second);
-        out->dominant_columns = kv.first;
+        out->dominant_columns = kv.first.first;
+        out->dominant_kind = kv.first.second;
         out->dominant_launches = std::get<0>(kv.second);
         out->dominant_ms = std::get<1>(kv.second);
         out->dominant_bytes = std::get<2>(kv.second);

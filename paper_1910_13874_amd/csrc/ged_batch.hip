@@ -20,7 +20,8 @@ struct BatchWs {
   bool tmask_ready = false;
   DBuf X, Y;        // double [n*C]
   DBuf offsets;     // int64 [cap_g+1]
-  DBuf members;     // int [cap_m]
+  DBuf members;     // int [cap_m] (internal ids)
+  std::vector<int> h_members;
   DBuf scores;      // double [cap_g + 64]
   HBuf h_scores;
   size_t cap_g = 0, cap_m = 0;
@@ -127,7 +128,7 @@ static void enqueue_batch(ged_graph *g, BatchWs &b, int G, int C, hipStream_t st
       a.X = ((i & 1) ? b.X : b.Y).as<const double>();
       a.Y = ((i & 1) ? b.Y : b.X).as<double>();
       a.inj = T + (size_t)i * n;
-      launch_step(p, a, i == 1 ? IN_TILEMASK : IN_VEC, OUT_TILE, st);
+      run_step(g, p, a, i == 1 ? IN_TILEMASK : IN_VEC, OUT_TILE, st);
       launch_reduce(p, a, nullptr, b.scores.as<double>() + g0, nullptr, st);
     }
     launch_tmask_set(b.tmask.as<uint64_t>(), b.offsets.as<const int64_t>(),
@@ -173,9 +174,12 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
   }
   GED_HIP(hipMemcpyAsync(b.offsets.p, offsets, sizeof(int64_t) * (size_t)(G + 1),
                          hipMemcpyHostToDevice, st));
-  if (M > 0)
-    GED_HIP(hipMemcpyAsync(b.members.p, members, sizeof(int) * (size_t)M, hipMemcpyHostToDevice,
-                           st));
+  if (M > 0) {
+    b.h_members.resize((size_t)M);
+    for (int64_t j = 0; j < M; ++j) b.h_members[j] = g->new_id[members[j]];
+    GED_HIP(hipMemcpyAsync(b.members.p, b.h_members.data(), sizeof(int) * (size_t)M,
+                           hipMemcpyHostToDevice, st));
+  }
   double abits_d = alpha;
   const void *abits;
   std::memcpy(&abits, &abits_d, sizeof(abits));

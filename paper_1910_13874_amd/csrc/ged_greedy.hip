@@ -28,9 +28,6 @@
 
 namespace ged {
 
-int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
-                double *out, ged_score_info *info);
-
 // Relative slack added to upper bounds before they are compared with exact
 // gains: both sides are rounded sums, and exact equality (e.g. ell = 1, where
 // the bound is tight) must not prune a candidate by one ulp.
@@ -138,10 +135,13 @@ constexpr int kTopE = 16;  // elements per thread in the selection kernels
 
 // Eligible: bound >= 0 (not in S), not evaluated in this round, and (for the
 // stochastic variant) in the current sample.
+// Keys carry the caller's vertex id, so ties break by it whatever the
+// internal vertex order is.
 __global__ __launch_bounds__(kBlock) void k_topk_ub(const double *__restrict__ ub,
                                                     const int *__restrict__ done, int round,
                                                     const int *__restrict__ sampled, int pick,
-                                                    int n, int K, double *ok, int *oi) {
+                                                    const int *__restrict__ orig, int n, int K,
+                                                    double *ok, int *oi) {
   double kv[kTopE];
   int iv[kTopE];
   const int base = blockIdx.x * kBlock * kTopE + threadIdx.x;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_topk_ub(const double *__restrict__ u
       const double u = ub[x];
       if (u >= 0.0 && done[x] != round && (!sampled || sampled[x] == pick)) {
         kv[q] = u;
-        iv[q] = x;
+        iv[q] = orig[x];
       }
     }
   }
@@ -242,10 +242,7 @@ static void miss_chains(GreedyCtx &c, int ell) {
       a.smask = c.smask.as<const uint32_t>();
       a.X = L + (size_t)(i - 1) * n;
       a.Y = L + (size_t)i * n;
-      hipEvent_t ev = nullptr;
-      prof_begin(g, c.st, &ev);
-      launch_step(p, a, i == 1 ? IN_NOTMASK : IN_VEC, OUT_ZERO, c.st);
-      prof_end(g, c.st, ev, 1, step_bytes(g, 1), (double)g->nnz, 1);
+      run_step(g, p, a, i == 1 ? IN_NOTMASK : IN_VEC, OUT_ZERO, c.st);
     }
   }
 }
@@ -258,14 +255,14 @@ static void compute_bounds(GreedyCtx &c, int ell) {
   GED_HIP(hipGetLastError());
 }
 
-// Top-K eligible (bound, id) pairs, best first, into host arrays.
+// Top-K eligible (bound, caller id) pairs, best first, into host arrays.
 static int select_topk(GreedyCtx &c, int K, int round, const int *sampled, int pick, double *hk,
                        int *hi) {
   const int chunk = kBlock * kTopE;
   int nb = (c.n + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_topk_ub, dim3(nb), dim3(kBlock), 0, c.st, c.ub.as<const double>(),
-                     c.done.as<const int>(), round, sampled, pick, c.n, K,
-                     c.topk_k[0].as<double>(), c.topk_i[0].as<int>());
+                     c.done.as<const int>(), round, sampled, pick, c.g->d_old_id.as<const int>(),
+                     c.n, K, c.topk_k[0].as<double>(), c.topk_i[0].as<int>());
   GED_HIP(hipGetLastError());
   int cur = 0, count = nb * K;
   while (nb > 1) {
@@ -315,10 +312,7 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
     a.X = ((i & 1) ? c.X : c.Y).as<const double>();
     a.Y = ((i & 1) ? c.Y : c.X).as<double>();
     a.inj = M + (size_t)i * n;
-    hipEvent_t ev = nullptr;
-    prof_begin(g, c.st, &ev);
-    launch_step(p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
-    prof_end(g, c.st, ev, C, step_bytes(g, C), (double)g->nnz * C, 2);
+    run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
     launch_reduce(p, a, nullptr, c.gains.as<double>(), nullptr, c.st);
   }
   hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
@@ -404,10 +398,12 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   if (tr && tr->n_forced > 0) {
     if (tr->n_forced > k || !tr->forced) return fail(GED_ERR_ARG, "bad forced prefix");
     for (int q = 0; q < tr->n_forced; ++q) {
-      const int u = tr->forced[q];
-      if (u < 0 || u >= n || inS[u]) return fail(GED_ERR_VERTEX, "bad forced vertex");
+      const int f = tr->forced[q];
+      if (f < 0 || f >= n) return fail(GED_ERR_VERTEX, "bad forced vertex");
+      const int u = g->new_id[f];
+      if (inS[u]) return fail(GED_ERR_VERTEX, "repeated forced vertex");
       inS[u] = 1;
-      out_group[s_size] = u;
+      out_group[s_size] = f;
       if (tr->ell) tr->ell[s_size] = -1;
       if (tr->L1) tr->L1[s_size] = NAN;
       if (tr->U2) tr->U2[s_size] = NAN;
@@ -424,6 +420,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   std::vector<double> hk(K);
   std::vector<int> hi(K);
   std::vector<double> gains(c.C);
+  std::vector<int> internal(c.C);
   while (s_size < k) {
     if (ell > 65536) return fail(GED_ERR_ELL, "walk length limit reached in greedy");
     ensure_levels_cap(c, ell);
@@ -436,10 +433,10 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
         const int64_t want = (int64_t)ceil((double)n / k * log(1.0 / eta));
         const int rest = n - s_size;
         const int m = (int)std::min<int64_t>(want, rest);
-        std::vector<int> pool;
+        std::vector<int> pool;  // caller ids outside S, increasing
         pool.reserve(rest);
         for (int x = 0; x < n; ++x)
-          if (!inS[x]) pool.push_back(x);
+          if (!inS[g->new_id[x]]) pool.push_back(x);
         // partial Fisher-Yates with splitmix64 at counter (addition, j)
         for (int j = 0; j < m; ++j) {
           const uint64_t r =
@@ -448,7 +445,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
           std::swap(pool[j], pool[q]);
         }
         sample_host.assign((size_t)n, -1);
-        for (int j = 0; j < m; ++j) sample_host[pool[j]] = s_size;
+        for (int j = 0; j < m; ++j) sample_host[g->new_id[pool[j]]] = s_size;
         GED_HIP(hipMemcpyAsync(c.sampled.p, sample_host.data(), sizeof(int) * n,
                                hipMemcpyHostToDevice, c.st));
         GED_HIP(hipStreamSynchronize(c.st));
@@ -468,15 +465,16 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
         if (m == 0) break;
         if (top.v >= 0 && hk[0] < top.L2) break;  // no bound reaches the runner-up
         const int nc = std::min(m, c.C);
-        eval_batch(c, hi.data(), nc, ell, round, gains.data());
+        for (int q = 0; q < nc; ++q) internal[q] = g->new_id[hi[q]];
+        eval_batch(c, internal.data(), nc, ell, round, gains.data());
         for (int q = 0; q < nc; ++q) top.add(gains[q], hi[q]);
         if (m <= c.C) break;  // nothing else eligible
       }
       if (top.u < 0) return fail(GED_ERR_ARG, "no candidate left");
       if (top.v >= 0 && top.L1 <= (top.L2 + B) - eps / (double)k) break;  // not separated
-      const int u = top.u;
+      const int u = g->new_id[top.u];
       inS[u] = 1;
-      out_group[s_size] = u;
+      out_group[s_size] = top.u;
       if (tr) {
         if (tr->ell) tr->ell[s_size] = ell;
         if (tr->L1) tr->L1[s_size] = top.L1;

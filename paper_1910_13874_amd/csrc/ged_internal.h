@@ -98,8 +98,8 @@ struct HBuf {
 
 // Launch geometry shared by every walk-count step kernel.
 constexpr int kBlock = 256;            // threads per block (4 wavefronts of 64)
-constexpr int kLdsDoubles = 4096;      // LDS staging per block (32 KiB)
-constexpr int kRowsPerBlock = 512;     // max rows of one row block
+constexpr int kLdsDoubles = 2048;      // LDS staging per block (16 KiB)
+constexpr int kRowsPerBlock = 511;     // max rows of one row block (row_ptr slice: 2 loads per thread)
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 
 // Row partition for a step with C columns: row blocks of consecutive short
@@ -110,7 +110,7 @@ struct Partition {
   int n_blocks = 0;  // row blocks
   int n_segs = 0;    // long-row segments
   int n_long = 0;    // long rows
-  DBuf blocks;       // int2 [n_blocks]: (row0, row1)
+  DBuf blocks;       // int4 [n_blocks]: (row0, row1, nnz0, nnz1)
   DBuf segs;         // int4 [n_segs]:   (row, nnz0, nnz1, long index)
   DBuf long_rows;    // int  [n_long]:   row id
   DBuf long_first;   // int  [n_long+1]: first segment of each long row
@@ -159,8 +159,10 @@ struct StepArgs {
 
 // Walk-count step: Y = epilogue(alpha * A X) with column sums.  Three
 // launches: row blocks + segments, long-row fix-up, column reduction.
+// If `after_main` is non-null it is recorded right after the main step kernel
+// (before the fix-up), so profiling brackets exactly that kernel.
 void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
-                 hipStream_t st);
+                 hipStream_t st, hipEvent_t after_main = nullptr);
 // Column sums of the step just launched: level[c] = sum_v Y[v,c]; if acc is
 // non-null acc[c] += level[c] (in launch order, so deterministic).  level may
 // be null.  active (nullable, [C]) skips columns whose flag is 0.
@@ -217,7 +219,7 @@ struct Profiler {
     hipEvent_t a, b;
     int C;
     double bytes, edges;
-    int kind;
+    int kind;  // in_mode * 8 + out_mode: one kernel instantiation per (C, kind)
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -232,6 +234,11 @@ struct ged_graph {
   double max_wdeg = 0;          // maximum weighted out-degree (weighted graphs)
   bool weighted = false;
   std::vector<int> h_rp;        // host copy of row_ptr (int32) for partitioning
+  // Vertices are stored in degree-descending order (stable by id) unless
+  // GED_KEEP_ORDER is given: internal id = new_id[caller id],
+  // caller id = old_id[internal id].
+  std::vector<int> new_id, old_id;
+  ged::DBuf d_old_id;           // int [n] caller ids, for tie-breaking on the device
   ged::DBuf rp, ci, w;          // device CSR (in-neighbour rows)
   ged::DBuf rp_r, ci_r, w_r;    // reverse graph (directed only)
   std::vector<int> h_rp_r;
@@ -275,11 +282,15 @@ double walk_total(ged_graph *g, int ell);
 double comb_bound(ged_graph *g, double alpha, double W_ell);
 int check_alpha_eps(ged_graph *g, double alpha, double eps);
 StepArgs base_args(ged_graph *g, bool reverse = false);
-// Profiling hooks around one step launch.
-void prof_begin(ged_graph *g, hipStream_t st, hipEvent_t *a);
-void prof_end(ged_graph *g, hipStream_t st, hipEvent_t a, int C, double bytes, double edges,
-              int kind);
-double step_bytes(ged_graph *g, int C, bool reverse = false);
+// Step launch, timed with HIP events around the main kernel when profiling is
+// on for the graph (the only way library code launches walk-count steps).
+void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in_mode, int out_mode,
+              hipStream_t st);
+// Algorithmic bytes of one step launch: row_ptr, col_idx (+ weights), the
+// gathered input, the written output and the epilogue's mask reads.
+double algo_bytes(const ged_graph *g, int C, int in_mode, int out_mode);
+int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
+                double *out, ged_score_info *info);
 // Drop the batched-scoring workspace of a graph that is being destroyed.
 void batch_forget(const ged_graph *g);
 

@@ -49,64 +49,131 @@ __device__ __forceinline__ double load_in(const StepArgs &a, int u, int c) {
   }
 }
 
+// Row epilogue given the row's membership bit (S), column bits (tile/pool
+// masks) and candidate column, which the caller has already fetched.
 template <int C, int OUT>
-__device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
+__device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, double sum,
+                                             bool inS, uint64_t tbits, int cand) {
   const double y = a.alpha * sum;
   if constexpr (OUT == OUT_PLAIN) {
     return y;
   } else if constexpr (OUT == OUT_INJ) {
-    return bit_of(a.smask, v) ? a.inj[v] : y;
+    return inS ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_ZERO) {
-    return bit_of(a.smask, v) ? 0.0 : y;
+    return inS ? 0.0 : y;
   } else if constexpr (OUT == OUT_TILE) {
-    return ((a.tmask[v] >> c) & 1ull) ? a.inj[v] : y;
+    return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN) {
-    return bit_of(a.smask, v) ? 0.0 : (a.cand_col[v] == c ? a.inj[v] : y);
+    return inS ? 0.0 : (cand == c ? a.inj[v] : y);
   } else {  // OUT_POOL
     const int s = a.col_step[c];
     if (s <= 0) return 0.0;
-    return ((a.tmask[v] >> c) & 1ull) ? a.inj[(size_t)s * a.n + v] : y;
+    return ((tbits >> c) & 1ull) ? a.inj[(size_t)s * a.n + v] : y;
   }
 }
 
+template <int C, int OUT>
+__device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL;
+  return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
+                            TM ? a.tmask[v] : 0ull, OUT == OUT_GAIN ? a.cand_col[v] : -1);
+}
+
+// Column sums of a block: lanes holding the same column are combined with
+// butterfly shuffles inside each wavefront, then the four wavefront partials
+// are added in a fixed order.  The thread -> column map is
+// c = (t / tpr) & (C - 1) with tpr lanes per (row, column) pair; only lanes
+// with s = t % tpr == 0 carry values.  red must hold 4*C zeros (or every
+// column of every wavefront must be written, which holds for tpr == 1).
+template <int C>
+__device__ __forceinline__ void block_colsum(double v, int tpr, double *red, double *out) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int o = 1; o < tpr; o <<= 1) v += __shfl_xor(v, o, 64);
+  const int G = tpr * C;
+  for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  if ((lane & (tpr - 1)) == 0 && lane < G) red[w * C + ((t / tpr) & (C - 1))] = v;
+  __syncthreads();
+  if (t < C) *(out + t) = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
+}
+
 template <int C, int IN, int OUT, bool WGT>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int2 *__restrict__ blocks,
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
-  __shared__ double vals[kLdsDoubles];
-  __shared__ double red[kBlock];
-  constexpr int LPC = kBlock / C;  // lanes per column in reductions
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL;
+  constexpr bool CA = OUT == OUT_GAIN;
+  constexpr int PT = kLdsDoubles / kBlock;   // gathered values per thread
+  constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
+  // vals has one spare slot per thread so every phase-1 store is unconditional
+  __shared__ double vals[kLdsDoubles + kBlock];
+  __shared__ int rps[kRowsPerBlock + 1];
+  __shared__ double red[(kBlock / 64) * C];
+  __shared__ uint32_t mw[M1 ? kRowsPerBlock / 32 + 2 : 1];
+  __shared__ uint64_t tmw[TM ? kRowsPerBlock : 1];
+  __shared__ int cw[CA ? kRowsPerBlock : 1];
+  constexpr int LPC = kBlock / C;  // lanes per column in a segment
   const int t = threadIdx.x;
   const int b = blockIdx.x;
   if (b < n_blocks) {
-    const int2 rr = blocks[b];
-    const int r0 = rr.x, r1 = rr.y;
-    const int p0 = a.rp[r0];
-    const int tot = (a.rp[r1] - p0) * C;
-    // Phase 1: coalesced col_idx stream, gather x(u, c) into LDS.  Four
-    // independent gathers per thread are kept in flight.
-    int f = t;
-    for (; f + 3 * kBlock < tot; f += 4 * kBlock) {
-      double v[4];
+    // descriptor: rows [r0, r0 + nrows), arcs [p0, p1)
+    const int4 d = blocks[b];
+    const int r0 = d.x, nrows = d.y - d.x, p0 = d.z;
+    const int tot = (d.w - d.z) * C;
+    if (t < (kBlock / 64) * C) red[t] = 0.0;
+    // Phase 1.  Load order matters: the col_idx stream first, then the row
+    // pointers and epilogue masks of the block, then the gathers (which wait
+    // only for col_idx), so a block pays two dependent memory round trips.
+    // Every index is clamped into range and every load is unconditional.
+    // A block whose rows have no arcs may start at p0 == nnz: its loads are
+    // redirected to entry 0 (always allocated) and its gathers to vertex 0.
+    const int jlo = tot > 0 ? p0 : 0;
+    const int jmax = tot > 0 ? d.w - 1 : 0;
+    int u[PT];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int ff = f + q * kBlock;
-        const int j = p0 + ff / C;
-        v[q] = load_in<C, IN>(a, a.ci[j], ff & (C - 1));
-        if constexpr (WGT) v[q] *= a.w[j];
+    for (int q = 0; q < PT; ++q) {
+      u[q] = a.ci[min(jlo + (t + q * kBlock) / C, jmax)];
+      if (tot == 0) u[q] = 0;
+    }
+    int rv[RT];
+#pragma unroll
+    for (int k = 0; k < RT; ++k) rv[k] = a.rp[r0 + min(t + k * kBlock, nrows)];
+    const int nw = ((r0 + nrows - 1) >> 5) - (r0 >> 5) + 1;
+    uint32_t mv = 0;
+    if constexpr (M1) mv = a.smask[(r0 >> 5) + min(t, nw - 1)];
+    uint64_t tv[2] = {0, 0};
+    int cv[2] = {-1, -1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int rr = r0 + min(t + k * kBlock, nrows - 1);
+      if constexpr (TM) tv[k] = a.tmask[rr];
+      if constexpr (CA) cv[k] = a.cand_col[rr];
+    }
+    double v[PT];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      v[q] = load_in<C, IN>(a, u[q], (t + q * kBlock) & (C - 1));
+      if constexpr (WGT) v[q] *= a.w[min(jlo + (t + q * kBlock) / C, jmax)];
+    }
+#pragma unroll
+    for (int k = 0; k < RT; ++k)
+      if (t + k * kBlock <= nrows) rps[t + k * kBlock] = rv[k] - p0;
+    if constexpr (M1)
+      if (t < nw) mw[t] = mv;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (t + k * kBlock < nrows) {
+        if constexpr (TM) tmw[t + k * kBlock] = tv[k];
+        if constexpr (CA) cw[t + k * kBlock] = cv[k];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) vals[f + q * kBlock] = v[q];
-    }
-    for (; f < tot; f += kBlock) {
-      const int j = p0 + f / C;
-      double v = load_in<C, IN>(a, a.ci[j], f & (C - 1));
-      if constexpr (WGT) v *= a.w[j];
-      vals[f] = v;
+    for (int q = 0; q < PT; ++q) {
+      const int f = t + q * kBlock;
+      vals[f < tot ? f : kLdsDoubles + t] = v[q];
     }
     __syncthreads();
-    // Phase 2: tpr lanes per (row, column).
-    const int nrows = r1 - r0;
-    int tpr = (LPC < 64) ? LPC : 64;
+    // Phase 2: tpr lanes per (row, column), as many as the row count allows.
+    int tpr = (kBlock / C < 64) ? kBlock / C : 64;
     while (tpr > 1 && nrows * C * tpr > kBlock) tpr >>= 1;
     const int s = t & (tpr - 1);
     const int pair = t / tpr;
@@ -114,55 +181,42 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int2 *__restr
     const int rstep = (kBlock / tpr) / C;
     double colsum = 0.0;
     for (int rl = pair / C; rl < nrows; rl += rstep) {
-      const int r = r0 + rl;
-      const int j0 = a.rp[r] - p0, j1 = a.rp[r + 1] - p0;
+      const int j0 = rps[rl], j1 = rps[rl + 1];
       double acc = 0.0;
       for (int j = j0 + s; j < j1; j += tpr) acc += vals[j * C + c];
       for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
       if (s == 0) {
-        const double y = epilogue<C, OUT>(a, r, c, acc);
+        const int r = r0 + rl;
+        bool inS = false;
+        if constexpr (M1) inS = (mw[(r >> 5) - (r0 >> 5)] >> (r & 31)) & 1u;
+        const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
+                                            CA ? cw[rl] : -1);
         a.Y[(size_t)r * C + c] = y;
         colsum += y;
       }
     }
-    // Column partials: each column's 256/C lanes reduced in a fixed tree.
-    const int k = (pair / C) * tpr + s;
-    red[c * LPC + k] = colsum;
-    __syncthreads();
-    for (int st = LPC >> 1; st > 0; st >>= 1) {
-      if (k < st) red[c * LPC + k] += red[c * LPC + k + st];
-      __syncthreads();
-    }
-    if (k == 0) a.blk_part[(size_t)b * C + c] = red[c * LPC];
+    block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C);
   } else {
     // One segment of a long row: LPC lanes per column stride over its arcs.
     const int4 sd = segs[b - n_blocks];
     const int c = t & (C - 1);
     const int s = t / C;
-    double acc0 = 0.0, acc1 = 0.0;
-    int j = sd.y + s;
-    for (; j + LPC < sd.z; j += 2 * LPC) {
-      double v0 = load_in<C, IN>(a, a.ci[j], c);
-      double v1 = load_in<C, IN>(a, a.ci[j + LPC], c);
-      if constexpr (WGT) {
-        v0 *= a.w[j];
-        v1 *= a.w[j + LPC];
+    constexpr int U = 8;  // arcs in flight per lane
+    double acc = 0.0;
+    for (int j0 = sd.y + s; j0 < sd.z; j0 += U * LPC) {
+      int u[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) u[q] = a.ci[min(j0 + q * LPC, sd.z - 1)];
+      double v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        v[q] = load_in<C, IN>(a, u[q], c);
+        if constexpr (WGT) v[q] *= a.w[min(j0 + q * LPC, sd.z - 1)];
       }
-      acc0 += v0;
-      acc1 += v1;
+#pragma unroll
+      for (int q = 0; q < U; ++q) acc += (j0 + q * LPC < sd.z) ? v[q] : 0.0;
     }
-    if (j < sd.z) {
-      double v0 = load_in<C, IN>(a, a.ci[j], c);
-      if constexpr (WGT) v0 *= a.w[j];
-      acc0 += v0;
-    }
-    red[c * LPC + s] = acc0 + acc1;
-    __syncthreads();
-    for (int st = LPC >> 1; st > 0; st >>= 1) {
-      if (s < st) red[c * LPC + s] += red[c * LPC + s + st];
-      __syncthreads();
-    }
-    if (s == 0) a.seg_out[(size_t)(b - n_blocks) * C + c] = red[c * LPC];
+    block_colsum<C>(acc, 1, red, a.seg_out + (size_t)(b - n_blocks) * C);
   }
 }
 
@@ -191,10 +245,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ bl
   const int c = blockIdx.x;
   if (active && active[c] == 0) return;
   const int t = threadIdx.x;
-  double s = 0.0;
-  for (int i = t; i < nb; i += kBlock) s += blk_part[(size_t)i * C + c];
+  // eight independent accumulators keep eight loads in flight per thread
+  double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = t;
+  for (; i + 7 * kBlock < nb; i += 8 * kBlock) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] += blk_part[(size_t)(i + q * kBlock) * C + c];
+  }
+  for (; i < nb; i += kBlock) r[0] += blk_part[(size_t)i * C + c];
+  double s = ((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]));
   double s2 = 0.0;
-  for (int i = t; i < nl; i += kBlock) s2 += long_part[(size_t)i * C + c];
+  for (int l = t; l < nl; l += kBlock) s2 += long_part[(size_t)l * C + c];
   red[t] = s + s2;
   __syncthreads();
   for (int st = kBlock / 2; st > 0; st >>= 1) {
@@ -211,11 +272,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ bl
 // ------------------------------------------------------------ dispatch --
 
 template <int C, int IN, int OUT, bool WGT>
-static void launch_t(const Partition &p, const StepArgs &a, hipStream_t st) {
+static void launch_t(const Partition &p, const StepArgs &a, hipStream_t st, hipEvent_t ev) {
   const int grid = p.n_blocks + p.n_segs;
   if (grid > 0)
     hipLaunchKernelGGL((k_step<C, IN, OUT, WGT>), dim3(grid), dim3(kBlock), 0, st, a,
-                       p.blocks.as<const int2>(), p.segs.as<const int4>(), p.n_blocks);
+                       p.blocks.as<const int4>(), p.segs.as<const int4>(), p.n_blocks);
+  if (ev) GED_HIP(hipEventRecord(ev, st));
   if (p.n_long > 0) {
     const int thr = p.n_long * C;
     hipLaunchKernelGGL((k_fixup<C, OUT>), dim3((thr + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
@@ -225,11 +287,11 @@ static void launch_t(const Partition &p, const StepArgs &a, hipStream_t st) {
 
 template <int C, bool WGT>
 static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &a,
-                           hipStream_t st) {
-#define GED_CASE(I, O)                  \
-  if (in == I && out == O) {            \
-    launch_t<C, I, O, WGT>(p, a, st);   \
-    return true;                        \
+                           hipStream_t st, hipEvent_t ev) {
+#define GED_CASE(I, O)                      \
+  if (in == I && out == O) {                \
+    launch_t<C, I, O, WGT>(p, a, st, ev);   \
+    return true;                            \
   }
   GED_CASE(IN_TILEMASK, OUT_TILE)
   GED_CASE(IN_VEC, OUT_TILE)
@@ -250,24 +312,24 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
 
 template <bool WGT>
 static bool dispatch_c(int C, int in, int out, const Partition &p, const StepArgs &a,
-                       hipStream_t st) {
+                       hipStream_t st, hipEvent_t ev) {
   switch (C) {
-    case 1: return dispatch_multi<1, WGT>(in, out, p, a, st);
-    case 2: return dispatch_multi<2, WGT>(in, out, p, a, st);
-    case 4: return dispatch_multi<4, WGT>(in, out, p, a, st);
-    case 8: return dispatch_multi<8, WGT>(in, out, p, a, st);
-    case 16: return dispatch_multi<16, WGT>(in, out, p, a, st);
-    case 32: return dispatch_multi<32, WGT>(in, out, p, a, st);
-    case 64: return dispatch_multi<64, WGT>(in, out, p, a, st);
+    case 1: return dispatch_multi<1, WGT>(in, out, p, a, st, ev);
+    case 2: return dispatch_multi<2, WGT>(in, out, p, a, st, ev);
+    case 4: return dispatch_multi<4, WGT>(in, out, p, a, st, ev);
+    case 8: return dispatch_multi<8, WGT>(in, out, p, a, st, ev);
+    case 16: return dispatch_multi<16, WGT>(in, out, p, a, st, ev);
+    case 32: return dispatch_multi<32, WGT>(in, out, p, a, st, ev);
+    case 64: return dispatch_multi<64, WGT>(in, out, p, a, st, ev);
     default: return false;
   }
 }
 
 void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
-                 hipStream_t st) {
+                 hipStream_t st, hipEvent_t after_main) {
   if (a.C != p.C) throw HipError{GED_ERR_ARG, "step column count does not match partition"};
-  const bool ok = a.w ? dispatch_c<true>(a.C, in_mode, out_mode, p, a, st)
-                      : dispatch_c<false>(a.C, in_mode, out_mode, p, a, st);
+  const bool ok = a.w ? dispatch_c<true>(a.C, in_mode, out_mode, p, a, st, after_main)
+                      : dispatch_c<false>(a.C, in_mode, out_mode, p, a, st, after_main);
   if (!ok)
     throw HipError{GED_ERR_ARG, "no step kernel for C=" + std::to_string(a.C) + " in=" +
                                     std::to_string(in_mode) + " out=" + std::to_string(out_mode)};
@@ -287,7 +349,7 @@ void build_partition(Partition &p, const std::vector<int> &rp, int C) {
   const int n = (int)rp.size() - 1;
   const int nnz_blk = kLdsDoubles / C;
   const int seg_len = std::max(1, kSegDoubles / C);
-  std::vector<int2> blocks;
+  std::vector<int4> blocks;
   std::vector<int4> segs;
   std::vector<int> lrows, lfirst;
   int r = 0;
@@ -310,19 +372,19 @@ void build_partition(Partition &p, const std::vector<int> &rp, int C) {
       acc += d;
       ++r;
     }
-    blocks.push_back(make_int2(r0, r));
+    blocks.push_back(make_int4(r0, r, rp[r0], rp[r]));
   }
   lfirst.push_back((int)segs.size());
   p.C = C;
   p.n_blocks = (int)blocks.size();
   p.n_segs = (int)segs.size();
   p.n_long = (int)lrows.size();
-  p.blocks.ensure(sizeof(int2) * std::max<size_t>(1, blocks.size()));
+  p.blocks.ensure(sizeof(int4) * std::max<size_t>(1, blocks.size()));
   p.segs.ensure(sizeof(int4) * std::max<size_t>(1, segs.size()));
   p.long_rows.ensure(sizeof(int) * std::max<size_t>(1, lrows.size()));
   p.long_first.ensure(sizeof(int) * lfirst.size());
   if (!blocks.empty())
-    GED_HIP(hipMemcpy(p.blocks.p, blocks.data(), sizeof(int2) * blocks.size(),
+    GED_HIP(hipMemcpy(p.blocks.p, blocks.data(), sizeof(int4) * blocks.size(),
                       hipMemcpyHostToDevice));
   if (!segs.empty())
     GED_HIP(hipMemcpy(p.segs.p, segs.data(), sizeof(int4) * segs.size(), hipMemcpyHostToDevice));

@@ -52,7 +52,8 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("edges", ctypes.c_double),
                 ("dominant_launches", ctypes.c_int64), ("dominant_ms", ctypes.c_double),
-                ("dominant_bytes", ctypes.c_double), ("dominant_columns", ctypes.c_int32)]
+                ("dominant_bytes", ctypes.c_double), ("dominant_columns", ctypes.c_int32),
+                ("dominant_kind", ctypes.c_int32)]
 
 
 def _sig(name, res, args):
@@ -73,6 +74,7 @@ _sig("ged_default_alpha", ctypes.c_double, [c_graph_p])
 _sig("ged_set_stream", ctypes.c_int, [c_graph_p, ctypes.c_void_p])
 _sig("ged_prepare", ctypes.c_int, [c_graph_p, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(ScoreInfo)])
+_sig("ged_invalidate", ctypes.c_int, [c_graph_p])
 _sig("ged_score", ctypes.c_int, [c_graph_p, P_I32, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double, P_F64, ctypes.POINTER(ScoreInfo)])
 _sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, ctypes.c_double,
@@ -188,6 +190,10 @@ class GedGraph:
             "ged_prepare")
         return info.ell, info.bound, info.walk_total
 
+    def invalidate(self):
+        """Drop the cached per-(alpha, eps) precomputation."""
+        _ck(_lib.ged_invalidate(self.handle), "ged_invalidate")
+
     def score(self, S, alpha=None, eps=1e-4, with_info=False):
         arr, ptr = _i32(S)
         out = ctypes.c_double()
@@ -257,6 +263,16 @@ class GedGraph:
         p = Profile()
         _ck(_lib.ged_profile_read(self.handle, ctypes.byref(p)), "ged_profile_read")
         return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh"]
+OUT_MODES = ["plain", "inj", "zero", "tile", "gain", "pool"]
+
+
+def kernel_name(columns, kind, weighted=False):
+    """Symbol of the step-kernel instantiation a profile record refers to."""
+    return (f"ged::k_step<{columns}, {kind // 8}, {kind % 8}, "
+            f"{'true' if weighted else 'false'}>")
 
 
 def exported_symbols():
