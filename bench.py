@@ -257,6 +257,9 @@ def main():
     ap.add_argument("--groups", type=int, default=4096)
     ap.add_argument("--seq-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the stream")
+    ap.add_argument("--qps", type=float, default=2000.0, help="serve: arrival rate")
+    ap.add_argument("--serve-small", action="store_true", help="serve: only the 3 small graphs")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()

@@ -210,7 +210,7 @@ typedef struct ged_server ged_server;
 typedef struct {
   int64_t hbm_budget_bytes; /* admission limit for request working memory */
   int32_t score_slots;      /* columns per resident graph for score requests */
-  int32_t max_queue;        /* pending requests before GED_ERR_BUSY */
+  int32_t max_queue;        /* requests waiting for a column or a worker before GED_ERR_BUSY */
   int32_t greedy_workers;   /* concurrent greedy requests */
 } ged_server_config;
 

@@ -17,6 +17,7 @@ HIP_SOURCES = [
     "ged_api.hip",
     "ged_batch.hip",
     "ged_greedy.hip",
+    "ged_server.hip",
 ]
 
 HIP_FLAGS = [

@@ -158,7 +158,7 @@ int prepare(ged_graph *g, double alpha, double eps) {
     a.X = T + (size_t)(i - 1) * n;
     a.Y = T + (size_t)i * n;
     run_step(g, p, a, i == 1 ? IN_ONES : IN_VEC, OUT_PLAIN, st);
-    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st);
+    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st, g->pws.scratch());
     GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
     GED_HIP(hipStreamSynchronize(st));
     pc.W.push_back(W_host);
@@ -200,7 +200,7 @@ double walk_total(ged_graph *g, int ell) {
     a.X = pc.t_tail[pc.tail_cur].as<double>();
     a.Y = pc.t_tail[pc.tail_cur ^ 1].as<double>();
     run_step(g, p, a, IN_VEC, OUT_PLAIN, st);
-    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st);
+    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st, g->pws.scratch());
     GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
     GED_HIP(hipStreamSynchronize(st));
     pc.tail_cur ^= 1;
@@ -221,13 +221,13 @@ static void enqueue_score(ged_graph *g, hipStream_t st, bool timed) {
   Partition &p = partition(g, 1);
   int *sd = g->s_dev.as<int>();
   launch_mask_set(g->mask.as<uint32_t>(), sd + 1, sd, g->s_cap, 1, st);
-  launch_fill_f64(g->acc.as<double>(), 0.0, 1, st);
   const double *T = pc.t_levels.as<const double>();
+  StepArgs a = base_args(g);
+  g->sws.into(a);
   for (int i = 1; i <= pc.ell; ++i) {
-    StepArgs a = base_args(g);
-    g->sws.into(a);
     a.C = 1;
     a.alpha = pc.alpha;
+    a.accum = i > 1;  // block partials of all levels add up to the score
     a.smask = g->mask.as<const uint32_t>();
     a.X = g->vec[(i - 1) & 1].as<const double>();
     a.Y = g->vec[i & 1].as<double>();
@@ -236,8 +236,8 @@ static void enqueue_score(ged_graph *g, hipStream_t st, bool timed) {
       run_step(g, p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
     else
       launch_step(p, a, i == 1 ? IN_MASK : IN_VEC, OUT_INJ, st);
-    launch_reduce(p, a, g->s_levels.as<double>() + i, g->acc.as<double>(), nullptr, st);
   }
+  launch_reduce(p, a, g->acc.as<double>(), nullptr, nullptr, st, g->sws.scratch());
   launch_mask_set(g->mask.as<uint32_t>(), sd + 1, sd, g->s_cap, 0, st);
 }
 
@@ -282,7 +282,8 @@ static std::vector<const void *> score_signature(ged_graph *g) {
   const void *abits;
   std::memcpy(&abits, &a, sizeof(a));
   return {g->mask.p, g->vec[0].p, g->vec[1].p, g->acc.p, g->s_levels.p, g->s_dev.p,
-          g->sws.blk.p, g->sws.seg.p, g->sws.lng.p, pc.t_levels.p, (const void *)g->stream,
+          g->sws.blk.p, g->sws.seg.p, g->sws.lng.p, g->sws.red2.p, pc.t_levels.p,
+          (const void *)g->stream,
           abits, (const void *)(intptr_t)pc.ell, (const void *)(intptr_t)g->s_cap};
 }
 

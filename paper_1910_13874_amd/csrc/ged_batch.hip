@@ -82,7 +82,7 @@ static int autotune_tile(ged_graph *g, BatchWs &b) {
       for (int r = 0; r < 3; ++r) {
         GED_HIP(hipEventRecord(e0, st));
         launch_step(p, a, IN_VEC, OUT_TILE, st);
-        launch_reduce(p, a, nullptr, nullptr, nullptr, st);
+        launch_reduce(p, a, nullptr, nullptr, nullptr, st, ws.scratch());
         GED_HIP(hipEventRecord(e1, st));
         GED_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -114,23 +114,24 @@ static void enqueue_batch(ged_graph *g, BatchWs &b, int G, int C, hipStream_t st
   const PrepCache &pc = g->prep;
   Partition &p = partition(g, C);
   const double *T = pc.t_levels.as<const double>();
-  launch_fill_f64(b.scores.as<double>(), 0.0, (size_t)G + 64, st);
   for (int g0 = 0; g0 < G; g0 += C) {
     const int nc = std::min(C, G - g0);
     launch_tmask_set(b.tmask.as<uint64_t>(), b.offsets.as<const int64_t>(),
                      b.members.as<const int>(), g0, nc, 1, st);
+    StepArgs a = base_args(g);
+    b.ws.into(a);
     for (int i = 1; i <= pc.ell; ++i) {
-      StepArgs a = base_args(g);
-      b.ws.into(a);
       a.C = C;
       a.alpha = pc.alpha;
+      a.accum = i > 1;  // all levels add into the block partials
       a.tmask = b.tmask.as<const uint64_t>();
       a.X = ((i & 1) ? b.X : b.Y).as<const double>();
       a.Y = ((i & 1) ? b.Y : b.X).as<double>();
       a.inj = T + (size_t)i * n;
       run_step(g, p, a, i == 1 ? IN_TILEMASK : IN_VEC, OUT_TILE, st);
-      launch_reduce(p, a, nullptr, b.scores.as<double>() + g0, nullptr, st);
     }
+    // scores of this tile's columns (the buffer has C entries of slack)
+    launch_reduce(p, a, b.scores.as<double>() + g0, nullptr, nullptr, st, b.ws.scratch());
     launch_tmask_set(b.tmask.as<uint64_t>(), b.offsets.as<const int64_t>(),
                      b.members.as<const int>(), g0, nc, 0, st);
   }
@@ -185,10 +186,14 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
   std::memcpy(&abits, &abits_d, sizeof(abits));
   std::vector<const void *> sig = {b.tmask.p,      b.X.p,       b.Y.p,
                                    b.offsets.p,    b.members.p, b.scores.p,
-                                   b.ws.blk.p,     b.ws.seg.p,  b.ws.lng.p,
+                                   b.ws.blk.p,     b.ws.seg.p,  b.ws.lng.p, b.ws.red2.p,
                                    g->prep.t_levels.p, (const void *)st, abits,
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
                                    (const void *)(intptr_t)C};
+  if (g->prof.on) {
+    // profiling times every step launch with events: run the batch eagerly
+    enqueue_batch(g, b, G, C, st);
+  } else {
   if (b.exec && sig != b.sig) {
     (void)hipGraphExecDestroy(b.exec);
     (void)hipGraphDestroy(b.graph);
@@ -210,6 +215,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
     b.sig = sig;
   }
   GED_HIP(hipGraphLaunch(b.exec, st));
+  }
   double *hs = b.h_scores.as<double>();
   GED_HIP(hipMemcpyAsync(hs, b.scores.p, sizeof(double) * (size_t)G, hipMemcpyDeviceToHost, st));
   GED_HIP(hipStreamSynchronize(st));

@@ -300,21 +300,21 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
   GED_HIP(hipMemcpyAsync(c.cand_dev.p, hc, sizeof(int) * nc, hipMemcpyHostToDevice, c.st));
   hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
                      c.cand_dev.as<const int>(), nc, 1);
-  launch_fill_f64(c.gains.as<double>(), 0.0, (size_t)C, c.st);
   const double *M = c.m_levels.as<const double>();
+  StepArgs a = base_args(g);
+  c.wsC.into(a);
   for (int i = 1; i <= ell; ++i) {
-    StepArgs a = base_args(g);
-    c.wsC.into(a);
     a.C = C;
     a.alpha = g->prep.alpha;
+    a.accum = i > 1;  // L = sum over all levels of the column sums
     a.smask = c.smask.as<const uint32_t>();
     a.cand_col = c.cand_col.as<const int>();
     a.X = ((i & 1) ? c.X : c.Y).as<const double>();
     a.Y = ((i & 1) ? c.Y : c.X).as<double>();
     a.inj = M + (size_t)i * n;
     run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
-    launch_reduce(p, a, nullptr, c.gains.as<double>(), nullptr, c.st);
   }
+  launch_reduce(p, a, c.gains.as<double>(), nullptr, nullptr, c.st, c.wsC.scratch());
   hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
                      c.cand_dev.as<const int>(), nc, 0);
   hipLaunchKernelGGL(k_after_batch, dim3(1), dim3(64), 0, c.st, c.cand_dev.as<const int>(),

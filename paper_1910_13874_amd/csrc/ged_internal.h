@@ -152,6 +152,7 @@ struct StepArgs {
   const int *col_step = nullptr;    // [C] per-column level (OUT_POOL), 0 = idle
   const int *fresh = nullptr;       // [C] first-step flags (IN_FRESH)
   double alpha = 0;
+  int accum = 0;                 // 1: add this step's column sums to blk_part/long_part
   double *blk_part = nullptr;    // [n_blocks*C] block column sums
   double *seg_out = nullptr;     // [n_segs*C] raw segment sums
   double *long_part = nullptr;   // [n_long*C] long-row outputs (for column sums)
@@ -163,23 +164,28 @@ struct StepArgs {
 // (before the fix-up), so profiling brackets exactly that kernel.
 void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
                  hipStream_t st, hipEvent_t after_main = nullptr);
-// Column sums of the step just launched: level[c] = sum_v Y[v,c]; if acc is
-// non-null acc[c] += level[c] (in launch order, so deterministic).  level may
-// be null.  active (nullable, [C]) skips columns whose flag is 0.
+// Column sums of the partials in a (one step, or a chain of steps launched
+// with accum = 1): level[c] = the sum; if acc is non-null acc[c] += level[c].
+// level may be null.  active (nullable, [C]) skips columns whose flag is 0.
+// Two passes of fixed order, so the result is deterministic.  ws2 is a
+// scratch buffer of at least kReduceBlocks * C doubles.
+constexpr int kReduceBlocks = 256;
 void launch_reduce(const Partition &p, const StepArgs &a, double *level, double *acc,
-                   const int *active, hipStream_t st);
+                   const int *active, hipStream_t st, double *ws2);
 
 void build_partition(Partition &p, const std::vector<int> &row_ptr, int C);
 
 // Partial-sum buffers of one step stream (each path owns its own, so captured
 // graphs never see a buffer another path reallocated).
 struct StepWs {
-  DBuf blk, seg, lng;
+  DBuf blk, seg, lng, red2;
   void fit(const Partition &p) {
     blk.ensure(sizeof(double) * (size_t)(p.n_blocks > 0 ? p.n_blocks : 1) * p.C);
     seg.ensure(sizeof(double) * (size_t)(p.n_segs > 0 ? p.n_segs : 1) * p.C);
     lng.ensure(sizeof(double) * (size_t)(p.n_long > 0 ? p.n_long : 1) * p.C);
+    red2.ensure(sizeof(double) * (size_t)kReduceBlocks * p.C);
   }
+  double *scratch() const { return red2.as<double>(); }
   void into(StepArgs &a) const {
     a.blk_part = blk.as<double>();
     a.seg_out = seg.as<double>();

@@ -87,14 +87,18 @@ __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, doub
 // with s = t % tpr == 0 carry values.  red must hold 4*C zeros (or every
 // column of every wavefront must be written, which holds for tpr == 1).
 template <int C>
-__device__ __forceinline__ void block_colsum(double v, int tpr, double *red, double *out) {
+__device__ __forceinline__ void block_colsum(double v, int tpr, double *red, double *out,
+                                             int accum) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int o = 1; o < tpr; o <<= 1) v += __shfl_xor(v, o, 64);
   const int G = tpr * C;
   for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
   if ((lane & (tpr - 1)) == 0 && lane < G) red[w * C + ((t / tpr) & (C - 1))] = v;
   __syncthreads();
-  if (t < C) *(out + t) = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
+  if (t < C) {
+    const double bs = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
+    out[t] = accum ? out[t] + bs : bs;
+  }
 }
 
 template <int C, int IN, int OUT, bool WGT>
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     int u[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-      u[q] = a.ci[min(jlo + (t + q * kBlock) / C, jmax)];
+      u[q] = __builtin_nontemporal_load(a.ci + min(jlo + (t + q * kBlock) / C, jmax));
       if (tot == 0) u[q] = 0;
     }
     int rv[RT];
@@ -195,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         colsum += y;
       }
     }
-    block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C);
+    block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C, a.accum);
   } else {
     // One segment of a long row: LPC lanes per column stride over its arcs.
     const int4 sd = segs[b - n_blocks];
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     for (int j0 = sd.y + s; j0 < sd.z; j0 += U * LPC) {
       int u[U];
 #pragma unroll
-      for (int q = 0; q < U; ++q) u[q] = a.ci[min(j0 + q * LPC, sd.z - 1)];
+      for (int q = 0; q < U; ++q) u[q] = __builtin_nontemporal_load(a.ci + min(j0 + q * LPC, sd.z - 1));
       double v[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
       for (int q = 0; q < U; ++q) acc += (j0 + q * LPC < sd.z) ? v[q] : 0.0;
     }
-    block_colsum<C>(acc, 1, red, a.seg_out + (size_t)(b - n_blocks) * C);
+    block_colsum<C>(acc, 1, red, a.seg_out + (size_t)(b - n_blocks) * C, 0);
   }
 }
 
@@ -229,34 +233,58 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   const int l = gid / C, c = gid & (C - 1);
   if (l >= n_long) return;
   const int r = long_rows[l];
-  double acc = 0.0;
-  for (int q = long_first[l]; q < long_first[l + 1]; ++q) acc += a.seg_out[(size_t)q * C + c];
+  const int q0 = long_first[l], q1 = long_first[l + 1];
+  // four independent partial sums keep four loads in flight; combined in a
+  // fixed order
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  int q = q0;
+  for (; q + 3 < q1; q += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s4[k] += a.seg_out[(size_t)(q + k) * C + c];
+  }
+  for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
+  const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   const double y = epilogue<C, OUT>(a, r, c, acc);
   a.Y[(size_t)r * C + c] = y;
-  a.long_part[(size_t)l * C + c] = y;
+  double *lp = a.long_part + (size_t)l * C + c;
+  *lp = a.accum ? *lp + y : y;
 }
 
-// One block per column: fixed-order sum of block and long-row partials.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ blk_part, int nb,
-                                                   const double *__restrict__ long_part, int nl,
-                                                   int C, double *level, double *acc,
-                                                   const int *active) {
+// Pass 1: block g sums rows [g*R, (g+1)*R) of the concatenation of blk_part
+// (nb rows) and long_part (nl rows), all C columns, lanes mapped as
+// (row offset t / C, column t % C) so every load is coalesced.  Columns are
+// combined across lanes with butterflies (offsets C .. 32) and across the
+// four wavefronts in a fixed order.  Pass 2: one block per column adds the
+// kReduceBlocks pass-1 values in order.
+template <int C>
+__global__ __launch_bounds__(kBlock) void k_reduce1(const double *__restrict__ blk_part, int nb,
+                                                    const double *__restrict__ long_part, int nl,
+                                                    int R, double *out2) {
+  __shared__ double red[(kBlock / 64) * C];
+  const int t = threadIdx.x, c = t & (C - 1), q = t / C;
+  constexpr int RPP = kBlock / C;  // rows per pass
+  const int r0 = blockIdx.x * R, r1 = min(r0 + R, nb + nl);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int r = r0 + q;
+  for (; r + 3 * RPP < r1; r += 4 * RPP) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int rr = r + k * RPP;
+      s[k] += rr < nb ? blk_part[(size_t)rr * C + c] : long_part[(size_t)(rr - nb) * C + c];
+    }
+  }
+  for (; r < r1; r += RPP) s[0] += r < nb ? blk_part[(size_t)r * C + c] : long_part[(size_t)(r - nb) * C + c];
+  block_colsum<C>((s[0] + s[1]) + (s[2] + s[3]), 1, red, out2 + (size_t)blockIdx.x * C, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce2(const double *__restrict__ in2, int C,
+                                                    double *level, double *acc,
+                                                    const int *active) {
   __shared__ double red[kBlock];
   const int c = blockIdx.x;
   if (active && active[c] == 0) return;
   const int t = threadIdx.x;
-  // eight independent accumulators keep eight loads in flight per thread
-  double r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int i = t;
-  for (; i + 7 * kBlock < nb; i += 8 * kBlock) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] += blk_part[(size_t)(i + q * kBlock) * C + c];
-  }
-  for (; i < nb; i += kBlock) r[0] += blk_part[(size_t)i * C + c];
-  double s = ((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]));
-  double s2 = 0.0;
-  for (int l = t; l < nl; l += kBlock) s2 += long_part[(size_t)l * C + c];
-  red[t] = s + s2;
+  red[t] = t < kReduceBlocks ? in2[(size_t)t * C + c] : 0.0;
   __syncthreads();
   for (int st = kBlock / 2; st > 0; st >>= 1) {
     if (t < st) red[t] += red[t + st];
@@ -336,10 +364,28 @@ void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mod
   GED_HIP(hipGetLastError());
 }
 
+template <int C>
+static void launch_reduce1(const Partition &p, const StepArgs &a, hipStream_t st, double *ws2) {
+  const int rows = p.n_blocks + p.n_long;
+  const int R = (rows + kReduceBlocks - 1) / kReduceBlocks;
+  hipLaunchKernelGGL((k_reduce1<C>), dim3(kReduceBlocks), dim3(kBlock), 0, st, a.blk_part,
+                     p.n_blocks, a.long_part, p.n_long, R > 0 ? R : 1, ws2);
+}
+
 void launch_reduce(const Partition &p, const StepArgs &a, double *level, double *acc,
-                   const int *active, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(a.C), dim3(kBlock), 0, st, a.blk_part, p.n_blocks,
-                     a.long_part, p.n_long, a.C, level, acc, active);
+                   const int *active, hipStream_t st, double *ws2) {
+  switch (a.C) {
+    case 1: launch_reduce1<1>(p, a, st, ws2); break;
+    case 2: launch_reduce1<2>(p, a, st, ws2); break;
+    case 4: launch_reduce1<4>(p, a, st, ws2); break;
+    case 8: launch_reduce1<8>(p, a, st, ws2); break;
+    case 16: launch_reduce1<16>(p, a, st, ws2); break;
+    case 32: launch_reduce1<32>(p, a, st, ws2); break;
+    case 64: launch_reduce1<64>(p, a, st, ws2); break;
+    default: throw HipError{GED_ERR_ARG, "bad column count"};
+  }
+  GED_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce2, dim3(a.C), dim3(kBlock), 0, st, ws2, a.C, level, acc, active);
   GED_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,532 @@
+// Continuous-batching request server.
+//
+// Every score query on a graph runs the same number of walk-count levels
+// (ell*, fixed per graph), and a level is one step over the whole graph.  So
+// the server keeps, per resident graph, a pool of SpMM columns ("slots"): one
+// launch advances every occupied column by one level, each column at its own
+// level (the injection reads t_{level(c)}), and a column whose request has run
+// ell* levels is harvested and refilled with the next waiting request before
+// the following step.  Requests therefore join and leave between steps while
+// others are mid-flight, and the pools of different graphs run on their own
+// streams, so their steps overlap on the device.
+//
+// Greedy requests run whole (ged_greedy) on worker threads; each needs
+// working memory proportional to n * (walk length), so they are admitted only
+// while the sum of their estimated footprints stays within the configured HBM
+// budget, and wait otherwise.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+#include "ged_internal.h"
+
+namespace ged {
+
+int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, uint64_t seed,
+               bool stochastic, int32_t *out_group, double *out_score, ged_greedy_trace *tr);
+
+static double now_us() {
+  using namespace std::chrono;
+  return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
+}
+
+// (vertex, column) pairs: set (value=1) or clear bit `column` of tmask[vertex].
+__global__ void k_tmask_pairs(unsigned long long *tmask, const int2 *pairs, int count, int value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int2 p = pairs[i];
+  const unsigned long long bit = 1ull << p.y;
+  if (value)
+    atomicOr(&tmask[p.x], bit);
+  else
+    atomicAnd(&tmask[p.x], ~bit);
+}
+
+// acc[c] = 0 for columns that start this step.
+__global__ void k_pool_start(double *acc, const int *fresh, int C) {
+  const int c = threadIdx.x;
+  if (c < C && fresh[c]) acc[c] = 0.0;
+}
+
+struct Req {
+  uint64_t id = 0;
+  int kind = 0;  // 0 score, 1 greedy
+  int graph = 0;
+  std::vector<int> S;  // internal ids (score)
+  int k = 0;
+  double t_submit = 0;
+  size_t footprint = 0;
+};
+
+struct Done {
+  ged_result r;
+  std::vector<int> group;
+};
+
+struct Lane {
+  ged_graph *g = nullptr;
+  int gid = 0;
+  double alpha = 0, eps = 0;
+  int ell = 0;
+  int C = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  bool inflight = false;
+  DBuf X, Y, tmask, acc, state, pairs;
+  HBuf h_state, h_acc, h_pairs;
+  StepWs ws;
+  std::vector<int> step;     // level the column computes next (0 = idle)
+  std::vector<int> fresh;
+  std::vector<int> launched; // level computed by the step in flight
+  std::vector<Req> slot;     // request in each column
+  std::vector<int> done_cols;  // columns finished by the previous step (bits to clear)
+  std::deque<Req> pending;
+  int cur = 0;
+  size_t bytes = 0;
+};
+
+}  // namespace ged
+
+struct ged_server {
+  ged_server_config cfg{};
+  std::vector<std::unique_ptr<ged::Lane>> lanes;
+  std::mutex mu;  // guards inbox, results, counters, greedy queue
+  std::condition_variable cv_work, cv_done, cv_greedy;
+  std::deque<ged::Req> inbox;
+  std::deque<ged::Req> greedy_q;
+  std::deque<ged::Done> results;
+  std::unordered_map<uint64_t, std::vector<int>> groups;
+  uint64_t next_id = 1;
+  int64_t admitted = 0, completed = 0, steps = 0, rejected = 0, peak_cols = 0;
+  int64_t waiting = 0;  // submitted, not yet in a column or on a worker
+  size_t bytes_lanes = 0, bytes_greedy = 0, peak_bytes = 0;
+  bool stop = false;
+  std::thread sched;
+  std::vector<std::thread> workers;
+  bool started = false;
+};
+
+namespace ged {
+
+static void lane_setup(Lane &L, int C) {
+  ged_graph *g = L.g;
+  const int64_t n = g->n;
+  L.C = C;
+  Partition &p = partition(g, C);
+  L.ws.fit(p);
+  // everything the greedy path may need, so no partition is built while the
+  // pool runs on another thread
+  partition(g, 1);
+  partition(g, 8);
+  if (g->flags == GED_DIRECTED) partition(g, 1, true);
+  L.X.ensure(sizeof(double) * (size_t)n * C);
+  L.Y.ensure(sizeof(double) * (size_t)n * C);
+  L.tmask.ensure(sizeof(uint64_t) * (size_t)n);
+  L.acc.ensure(sizeof(double) * 64);
+  L.state.ensure(sizeof(int) * 128);
+  L.h_state.ensure(sizeof(int) * 128);
+  L.h_acc.ensure(sizeof(double) * 64);
+  GED_HIP(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
+  GED_HIP(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+  launch_fill_f64(L.X.as<double>(), 0.0, (size_t)n * C, L.st);
+  launch_fill_f64(L.Y.as<double>(), 0.0, (size_t)n * C, L.st);
+  launch_fill_i32(L.tmask.as<int>(), 0, (size_t)n * 2, L.st);
+  GED_HIP(hipStreamSynchronize(L.st));
+  L.step.assign(C, 0);
+  L.fresh.assign(C, 0);
+  L.launched.assign(C, 0);
+  L.slot.assign(C, Req());
+  L.bytes = L.X.bytes + L.Y.bytes + L.tmask.bytes + L.ws.blk.bytes + L.ws.seg.bytes +
+            L.ws.lng.bytes;
+}
+
+static void emit(ged_server *s, const Req &q, int status, double score, std::vector<int> group,
+                 double t_done) {
+  Done d;
+  d.r.id = q.id;
+  d.r.kind = q.kind;
+  d.r.status = status;
+  d.r.score = score;
+  d.r.k = q.k;
+  d.r.graph = q.graph;
+  d.r.t_submit_us = q.t_submit;
+  d.r.t_done_us = t_done;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (q.kind == 1) s->groups[q.id] = group;
+    d.group = std::move(group);
+    s->results.push_back(std::move(d));
+    s->completed++;
+  }
+  s->cv_done.notify_all();
+}
+
+// Harvest the step that just finished: columns that ran level ell* are done.
+static void lane_harvest(ged_server *s, Lane &L) {
+  const double t = now_us();
+  const double *acc = L.h_acc.as<double>();
+  for (int c = 0; c < L.C; ++c) {
+    if (L.launched[c] == 0) continue;
+    if (L.launched[c] == L.ell) {
+      emit(s, L.slot[c], GED_OK, acc[c], {}, t);
+      L.done_cols.push_back(c);
+      L.step[c] = 0;
+    } else {
+      L.step[c] = L.launched[c] + 1;
+    }
+    L.fresh[c] = 0;
+  }
+}
+
+// Admit waiting requests into free columns and launch one step.
+static bool lane_launch(ged_server *s, Lane &L) {
+  ged_graph *g = L.g;
+  const int C = L.C;
+  // bit updates: clear finished columns' members, set new members
+  std::vector<int2> clr, set;
+  for (int c : L.done_cols)
+    for (int v : L.slot[c].S) clr.push_back(make_int2(v, c));
+  L.done_cols.clear();
+  int took = 0;
+  for (int c = 0; c < C && !L.pending.empty(); ++c) {
+    if (L.step[c] != 0) continue;
+    L.slot[c] = std::move(L.pending.front());
+    L.pending.pop_front();
+    L.step[c] = 1;
+    L.fresh[c] = 1;
+    ++took;
+    for (int v : L.slot[c].S) set.push_back(make_int2(v, c));
+  }
+  if (took) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->waiting -= took;
+  }
+  int active = 0;
+  for (int c = 0; c < C; ++c) active += L.step[c] > 0;
+  if (active == 0) {
+    if (!clr.empty()) {
+      const size_t need = clr.size();
+      L.pairs.ensure(sizeof(int2) * need);
+      L.h_pairs.ensure(sizeof(int2) * need);
+      std::memcpy(L.h_pairs.p, clr.data(), sizeof(int2) * need);
+      GED_HIP(hipMemcpyAsync(L.pairs.p, L.h_pairs.p, sizeof(int2) * need,
+                             hipMemcpyHostToDevice, L.st));
+      hipLaunchKernelGGL(k_tmask_pairs, dim3(((int)need + 255) / 256), dim3(256), 0, L.st,
+                         L.tmask.as<unsigned long long>(), L.pairs.as<const int2>(), (int)need, 0);
+      GED_HIP(hipStreamSynchronize(L.st));
+    }
+    return false;
+  }
+  const size_t np = clr.size() + set.size();
+  if (np > 0) {
+    L.pairs.ensure(sizeof(int2) * np);
+    L.h_pairs.ensure(sizeof(int2) * np);
+    std::memcpy(L.h_pairs.p, clr.data(), sizeof(int2) * clr.size());
+    std::memcpy(L.h_pairs.as<int2>() + clr.size(), set.data(), sizeof(int2) * set.size());
+    GED_HIP(hipMemcpyAsync(L.pairs.p, L.h_pairs.p, sizeof(int2) * np, hipMemcpyHostToDevice,
+                           L.st));
+    if (!clr.empty())
+      hipLaunchKernelGGL(k_tmask_pairs, dim3(((int)clr.size() + 255) / 256), dim3(256), 0, L.st,
+                         L.tmask.as<unsigned long long>(), L.pairs.as<const int2>(),
+                         (int)clr.size(), 0);
+    if (!set.empty())
+      hipLaunchKernelGGL(k_tmask_pairs, dim3(((int)set.size() + 255) / 256), dim3(256), 0, L.st,
+                         L.tmask.as<unsigned long long>(),
+                         L.pairs.as<const int2>() + clr.size(), (int)set.size(), 1);
+  }
+  int *hs = L.h_state.as<int>();
+  for (int c = 0; c < C; ++c) {
+    hs[c] = L.step[c];
+    hs[64 + c] = L.fresh[c];
+    L.launched[c] = L.step[c];
+  }
+  GED_HIP(hipMemcpyAsync(L.state.p, hs, sizeof(int) * 128, hipMemcpyHostToDevice, L.st));
+  const int *d_step = L.state.as<const int>();
+  const int *d_fresh = d_step + 64;
+  hipLaunchKernelGGL(k_pool_start, dim3(1), dim3(64), 0, L.st, L.acc.as<double>(), d_fresh, C);
+  Partition &p = partition(g, C);
+  StepArgs a = base_args(g);
+  L.ws.into(a);
+  a.C = C;
+  a.alpha = L.alpha;
+  a.tmask = L.tmask.as<const uint64_t>();
+  a.col_step = d_step;
+  a.fresh = d_fresh;
+  a.inj = g->prep.t_levels.as<const double>();
+  a.X = (L.cur ? L.Y : L.X).as<const double>();
+  a.Y = (L.cur ? L.X : L.Y).as<double>();
+  launch_step(p, a, IN_FRESH, OUT_POOL, L.st);
+  launch_reduce(p, a, nullptr, L.acc.as<double>(), d_step, L.st, L.ws.scratch());
+  GED_HIP(hipMemcpyAsync(L.h_acc.p, L.acc.p, sizeof(double) * C, hipMemcpyDeviceToHost, L.st));
+  GED_HIP(hipEventRecord(L.ev, L.st));
+  L.cur ^= 1;
+  L.inflight = true;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->steps++;
+    s->peak_cols = std::max<int64_t>(s->peak_cols, active);
+  }
+  return true;
+}
+
+static void sched_loop(ged_server *s) {
+  for (;;) {
+    std::vector<Req> incoming;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      bool busy = false;
+      for (auto &L : s->lanes) busy = busy || L->inflight || !L->pending.empty();
+      if (!busy && s->inbox.empty() && !s->stop)
+        s->cv_work.wait_for(lk, std::chrono::microseconds(200));
+      if (s->stop) break;
+      while (!s->inbox.empty()) {
+        incoming.push_back(std::move(s->inbox.front()));
+        s->inbox.pop_front();
+      }
+    }
+    for (auto &q : incoming) s->lanes[q.graph]->pending.push_back(std::move(q));
+    bool progressed = false;
+    for (auto &Lp : s->lanes) {
+      Lane &L = *Lp;
+      try {
+        if (L.inflight) {
+          const hipError_t e = hipEventQuery(L.ev);
+          if (e == hipErrorNotReady) continue;
+          GED_HIP(e);
+          L.inflight = false;
+          lane_harvest(s, L);
+          progressed = true;
+        }
+        if (lane_launch(s, L)) progressed = true;
+      } catch (const HipError &err) {
+        // fail every request of this lane and drop it from service
+        const double t = now_us();
+        for (int c = 0; c < L.C; ++c)
+          if (L.step[c] > 0) emit(s, L.slot[c], err.code, 0.0, {}, t);
+        for (auto &q : L.pending) emit(s, q, err.code, 0.0, {}, t);
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          s->waiting -= (int64_t)L.pending.size();
+        }
+        L.pending.clear();
+        std::fill(L.step.begin(), L.step.end(), 0);
+        L.inflight = false;
+      }
+    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+static void greedy_worker(ged_server *s) {
+  for (;;) {
+    Req q;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      // admission: the head of the queue starts once its footprint fits
+      s->cv_greedy.wait(lk, [&] {
+        return s->stop || (!s->greedy_q.empty() &&
+                           s->bytes_lanes + s->bytes_greedy + s->greedy_q.front().footprint <=
+                               (size_t)s->cfg.hbm_budget_bytes);
+      });
+      if (s->stop) return;
+      q = std::move(s->greedy_q.front());
+      s->greedy_q.pop_front();
+      s->waiting--;
+      s->bytes_greedy += q.footprint;
+      s->peak_bytes = std::max(s->peak_bytes, s->bytes_lanes + s->bytes_greedy);
+    }
+    Lane &L = *s->lanes[q.graph];
+    std::vector<int> grp(q.k);
+    double score = 0.0;
+    int rc;
+    {
+      std::lock_guard<std::recursive_mutex> lk(L.g->mu);
+      rc = guarded([&]() {
+        return greedy_run(L.g, q.k, L.alpha, L.eps, 0.0, 0, false, grp.data(), &score, nullptr);
+      });
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->bytes_greedy -= q.footprint;
+    }
+    s->cv_greedy.notify_all();
+    emit(s, q, rc, score, rc == GED_OK ? grp : std::vector<int>(), now_us());
+  }
+}
+
+static void start(ged_server *s) {
+  if (s->started) return;
+  s->started = true;
+  s->sched = std::thread(sched_loop, s);
+  for (int i = 0; i < std::max(1, s->cfg.greedy_workers); ++i)
+    s->workers.emplace_back(greedy_worker, s);
+}
+
+}  // namespace ged
+
+using namespace ged;
+
+extern "C" int ged_server_create(const ged_server_config *cfg, ged_server **out) {
+  if (!cfg || !out) return fail(GED_ERR_ARG, "null argument");
+  if (cfg->hbm_budget_bytes <= 0 || cfg->max_queue <= 0 || cfg->score_slots < 0 ||
+      cfg->score_slots > 64 || (cfg->score_slots & (cfg->score_slots - 1)) != 0)
+    return fail(GED_ERR_ARG, "bad server config (score_slots must be 0 or a power of two <= 64)");
+  auto s = std::make_unique<ged_server>();
+  s->cfg = *cfg;
+  *out = s.release();
+  return GED_OK;
+}
+
+extern "C" int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, double eps,
+                                    int32_t *graph_id) {
+  if (!s || !g || !graph_id) return fail(GED_ERR_ARG, "null argument");
+  if (s->started) return fail(GED_ERR_ARG, "graphs must be added before the first request");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    int rc = prepare(g, alpha, eps);
+    if (rc) return rc;
+    auto L = std::make_unique<Lane>();
+    L->g = g;
+    L->gid = (int)s->lanes.size();
+    L->alpha = alpha;
+    L->eps = eps;
+    L->ell = g->prep.ell;
+    int C = s->cfg.score_slots;
+    if (C == 0) {
+      const int64_t n = g->n;
+      C = n <= 200000 ? 64 : n <= 1000000 ? 32 : n <= 2000000 ? 16 : 8;
+    }
+    lane_setup(*L, C);
+    if (s->bytes_lanes + L->bytes > (size_t)s->cfg.hbm_budget_bytes)
+      return fail(GED_ERR_NOMEM, "graph pool exceeds the HBM budget");
+    s->bytes_lanes += L->bytes;
+    s->peak_bytes = std::max(s->peak_bytes, s->bytes_lanes);
+    *graph_id = L->gid;
+    s->lanes.push_back(std::move(L));
+    return GED_OK;
+  });
+}
+
+static int submit(ged_server *s, Req &&q, uint64_t *req_id) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->waiting >= s->cfg.max_queue) return fail(GED_ERR_BUSY, "request queue full");
+  s->waiting++;
+  q.id = s->next_id++;
+  q.t_submit = now_us();
+  if (req_id) *req_id = q.id;
+  s->admitted++;
+  if (q.kind == 0) {
+    s->inbox.push_back(std::move(q));
+    s->cv_work.notify_one();
+  } else {
+    s->greedy_q.push_back(std::move(q));
+    s->cv_greedy.notify_all();
+  }
+  return GED_OK;
+}
+
+extern "C" int ged_server_submit_score(ged_server *s, int32_t graph_id, const int32_t *S,
+                                       int32_t s_len, uint64_t *req_id) {
+  if (!s || graph_id < 0 || graph_id >= (int)s->lanes.size() || s_len < 0 || (s_len > 0 && !S))
+    return fail(GED_ERR_ARG, "bad score request");
+  ged_graph *g = s->lanes[graph_id]->g;
+  Req q;
+  q.kind = 0;
+  q.graph = graph_id;
+  q.S.reserve(s_len);
+  for (int i = 0; i < s_len; ++i) {
+    if (S[i] < 0 || S[i] >= g->n) return fail(GED_ERR_VERTEX, "group member out of range");
+    q.S.push_back(g->new_id[S[i]]);
+  }
+  std::sort(q.S.begin(), q.S.end());
+  q.S.erase(std::unique(q.S.begin(), q.S.end()), q.S.end());
+  start(s);
+  return submit(s, std::move(q), req_id);
+}
+
+extern "C" int ged_server_submit_greedy(ged_server *s, int32_t graph_id, int32_t k,
+                                        uint64_t *req_id) {
+  if (!s || graph_id < 0 || graph_id >= (int)s->lanes.size())
+    return fail(GED_ERR_ARG, "bad greedy request");
+  ged_graph *g = s->lanes[graph_id]->g;
+  if (k < 1 || k > g->n) return fail(GED_ERR_ARG, "k must be in [1, n]");
+  Req q;
+  q.kind = 1;
+  q.graph = graph_id;
+  q.k = k;
+  // miss levels (walk length up to 4 ell*), 8 gain columns twice, bounds and
+  // bookkeeping vectors
+  const size_t n = (size_t)g->n;
+  q.footprint = 8 * n * (size_t)(4 * s->lanes[graph_id]->ell + 1) + 2 * 8 * n * 8 + 40 * n;
+  if (s->bytes_lanes + q.footprint > (size_t)s->cfg.hbm_budget_bytes) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->rejected++;
+    return fail(GED_ERR_NOMEM, "greedy request exceeds the HBM budget");
+  }
+  start(s);
+  return submit(s, std::move(q), req_id);
+}
+
+extern "C" int ged_server_poll(ged_server *s, ged_result *out, int32_t max, int32_t *n_out,
+                               int64_t timeout_us) {
+  if (!s || !n_out || max < 0 || (max > 0 && !out)) return fail(GED_ERR_ARG, "bad poll");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->results.empty() && timeout_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us),
+                        [&] { return !s->results.empty(); });
+  int m = 0;
+  while (m < max && !s->results.empty()) {
+    out[m++] = s->results.front().r;
+    s->results.pop_front();
+  }
+  *n_out = m;
+  return GED_OK;
+}
+
+extern "C" int ged_server_group(ged_server *s, uint64_t req_id, int32_t *out, int32_t k) {
+  if (!s || !out) return fail(GED_ERR_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->groups.find(req_id);
+  if (it == s->groups.end()) return fail(GED_ERR_ARG, "no greedy result with this id");
+  if ((int)it->second.size() != k) return fail(GED_ERR_ARG, "k does not match the request");
+  std::memcpy(out, it->second.data(), sizeof(int) * k);
+  return GED_OK;
+}
+
+extern "C" int ged_server_stats(ged_server *s, int64_t *out6) {
+  if (!s || !out6) return fail(GED_ERR_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  out6[0] = s->admitted;
+  out6[1] = s->completed;
+  out6[2] = s->steps;
+  out6[3] = (int64_t)s->peak_bytes;
+  out6[4] = s->peak_cols;
+  out6[5] = s->rejected;
+  return GED_OK;
+}
+
+extern "C" int ged_server_destroy(ged_server *s) {
+  if (!s) return GED_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  s->cv_greedy.notify_all();
+  if (s->sched.joinable()) s->sched.join();
+  for (auto &w : s->workers)
+    if (w.joinable()) w.join();
+  for (auto &L : s->lanes) {
+    if (L->st) {
+      (void)hipStreamSynchronize(L->st);
+      (void)hipStreamDestroy(L->st);
+    }
+    if (L->ev) (void)hipEventDestroy(L->ev);
+  }
+  delete s;
+  return GED_OK;
+}

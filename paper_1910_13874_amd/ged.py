@@ -90,6 +90,32 @@ _sig("ged_profile_read", ctypes.c_int, [c_graph_p, ctypes.POINTER(Profile)])
 _sig("ged_last_error", ctypes.c_char_p, [])
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("score_slots", ctypes.c_int32),
+                ("max_queue", ctypes.c_int32), ("greedy_workers", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("kind", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("score", ctypes.c_double), ("k", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("t_submit_us", ctypes.c_double), ("t_done_us", ctypes.c_double)]
+
+
+c_server_p = ctypes.c_void_p
+_sig("ged_server_create", ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(c_server_p)])
+_sig("ged_server_add_graph", ctypes.c_int, [c_server_p, c_graph_p, ctypes.c_double,
+                                            ctypes.c_double, P_I32])
+_sig("ged_server_submit_score", ctypes.c_int, [c_server_p, ctypes.c_int32, P_I32, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_uint64)])
+_sig("ged_server_submit_greedy", ctypes.c_int, [c_server_p, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_uint64)])
+_sig("ged_server_poll", ctypes.c_int, [c_server_p, ctypes.POINTER(Result), ctypes.c_int32, P_I32,
+                                       ctypes.c_int64])
+_sig("ged_server_group", ctypes.c_int, [c_server_p, ctypes.c_uint64, P_I32, ctypes.c_int32])
+_sig("ged_server_stats", ctypes.c_int, [c_server_p, P_I64])
+_sig("ged_server_destroy", ctypes.c_int, [c_server_p])
+
+
 class GedError(RuntimeError):
     def __init__(self, code, where):
         msg = _lib.ged_last_error().decode(errors="replace")
@@ -263,6 +289,69 @@ class GedGraph:
         p = Profile()
         _ck(_lib.ged_profile_read(self.handle, ctypes.byref(p)), "ged_profile_read")
         return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+class Server:
+    """Continuous-batching request server over resident graphs (C ABI ged_server_*)."""
+
+    def __init__(self, hbm_budget_bytes=64 << 30, score_slots=0, max_queue=1 << 20,
+                 greedy_workers=2):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(score_slots), int(max_queue),
+                           int(greedy_workers))
+        h = c_server_p()
+        _ck(_lib.ged_server_create(ctypes.byref(cfg), ctypes.byref(h)), "ged_server_create")
+        self._h = h
+        self.graphs = []
+
+    def add_graph(self, gg, alpha=None, eps=1e-4):
+        gid = ctypes.c_int32()
+        a = gg.default_alpha() if alpha is None else float(alpha)
+        _ck(_lib.ged_server_add_graph(self._h, gg.handle, a, eps, ctypes.byref(gid)),
+            "ged_server_add_graph")
+        self.graphs.append(gg)
+        return gid.value
+
+    def submit_score(self, gid, S):
+        arr, ptr = _i32(S)
+        rid = ctypes.c_uint64()
+        _ck(_lib.ged_server_submit_score(self._h, gid, ptr if arr.size else None, arr.size,
+                                         ctypes.byref(rid)), "ged_server_submit_score")
+        return rid.value
+
+    def submit_greedy(self, gid, k):
+        rid = ctypes.c_uint64()
+        _ck(_lib.ged_server_submit_greedy(self._h, gid, int(k), ctypes.byref(rid)),
+            "ged_server_submit_greedy")
+        return rid.value
+
+    def poll(self, max_results=1024, timeout_us=0):
+        buf = (Result * max_results)()
+        n = ctypes.c_int32()
+        _ck(_lib.ged_server_poll(self._h, buf, max_results, ctypes.byref(n), int(timeout_us)),
+            "ged_server_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def group(self, rid, k):
+        out = np.zeros(k, dtype=np.int32)
+        _ck(_lib.ged_server_group(self._h, rid, out.ctypes.data_as(P_I32), k), "ged_server_group")
+        return out
+
+    def stats(self):
+        out = np.zeros(6, dtype=np.int64)
+        _ck(_lib.ged_server_stats(self._h, out.ctypes.data_as(P_I64)), "ged_server_stats")
+        keys = ["admitted", "completed", "steps", "peak_bytes", "peak_columns", "rejected"]
+        return dict(zip(keys, (int(x) for x in out)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.ged_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh"]

@@ -1,0 +1,75 @@
+"""Serving (continuous batching): every result equals the same request run alone."""
+import numpy as np
+import pytest
+
+from paper_1910_13874_amd import inputs
+
+pytestmark = pytest.mark.gpu
+EPS = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ged():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1910_13874_amd import ged as mod
+    return mod
+
+
+def test_mix_equals_alone(ged):
+    from paper_1910_13874_amd import serve
+    gs = [inputs.erdos_renyi(20000, 100000, 21), inputs.barabasi_albert(50000, 5, 22)]
+    ggs = [ged.GedGraph.from_graph(g) for g in gs]
+    alphas = [gg.default_alpha() for gg in ggs]
+    print("[serving mix] graphs", [g.n for g in gs], flush=True)
+    srv = ged.Server(hbm_budget_bytes=8 << 30, score_slots=16, greedy_workers=2)
+    gids = [srv.add_graph(gg, a, EPS) for gg, a in zip(ggs, alphas)]
+    reqs = serve.make_requests([g.n for g in gs], 300, 5e4, seed=9, greedy_frac=0.03)
+    reqs += [{"t": 0.0, "g": 0, "kind": 0, "S": np.zeros(0, dtype=np.int32)}]  # empty group
+    out, wall = serve.run_server(srv, gids, reqs)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["peak_columns"] > 1
+    for j, q in enumerate(reqs):
+        kind, status, score, lat, grp = out[j]
+        assert status == 0
+        if q["kind"] == 0:
+            alone = ggs[q["g"]].score(q["S"], alphas[q["g"]], EPS)
+            assert abs(score - alone) <= 1e-12 * max(abs(alone), 1e-300), (j, score, alone)
+        else:
+            alone = ggs[q["g"]].greedy(q["k"], alphas[q["g"]], EPS)
+            assert list(grp) == list(alone["group"])
+            assert abs(score - alone["score"]) <= 1e-12 * abs(alone["score"])
+    srv.close()
+    for gg in ggs:
+        gg.close()
+
+
+def test_admission_and_queue_limits(ged):
+    g = inputs.barabasi_albert(200000, 4, 23)
+    gg = ged.GedGraph.from_graph(g)
+    # a budget that holds the score pool but no greedy working memory
+    srv = ged.Server(hbm_budget_bytes=60 << 20, score_slots=8, max_queue=4, greedy_workers=1)
+    gid = srv.add_graph(gg, None, EPS)
+    with pytest.raises(ged.GedError) as e:
+        srv.submit_greedy(gid, 5)
+    assert e.value.code == -6
+    with pytest.raises(ged.GedError) as e:
+        srv.submit_score(gid, [g.n])
+    assert e.value.code == -2
+    assert srv.stats()["rejected"] == 1
+    srv.close()
+    srv2 = ged.Server(hbm_budget_bytes=4 << 30, score_slots=8, max_queue=2, greedy_workers=1)
+    gid = srv2.add_graph(gg, None, EPS)
+    busy = 0
+    for j in range(64):
+        try:
+            srv2.submit_score(gid, [j])
+        except ged.GedError as err:
+            assert err.code == -8
+            busy += 1
+    assert busy > 0
+    got = 0
+    while got < 64 - busy:
+        got += len(srv2.poll(64, 200000))
+    srv2.close()
+    gg.close()
