@@ -209,6 +209,8 @@ def bench_batch(args, torch, ged, inputs):
     G = args.groups
     off, mem = inputs.groups(g.n, G, 1, 200, 104)
     gg.prepare(alpha, EPS)
+    if args.tile:
+        gg.set_batch_tile(args.tile)
 
     def step():
         gg.score_batch(off, mem, alpha, EPS)
@@ -255,6 +257,7 @@ def main():
     ap.add_argument("--workload", default="ba1m",
                     choices=["ba1m", "rmat22", "er1k", "batch", "serve"])
     ap.add_argument("--groups", type=int, default=4096)
+    ap.add_argument("--tile", type=int, default=0, help="batch: fix the tile width (0 = autotune)")
     ap.add_argument("--seq-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the stream")

@@ -143,6 +143,10 @@ int ged_score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members
  * (0 if not tuned yet). */
 int32_t ged_batch_tile(const ged_graph *g);
 
+/* Fix the tile width of ged_score_batch (a power of two <= 64), or 0 to let
+ * the autotuner choose on the next call. */
+int ged_set_batch_tile(ged_graph *g, int32_t tile);
+
 typedef struct {
   /* per-pick outputs, arrays of length k (any may be NULL) */
   int32_t *ell;  /* walk length at which the pick was separated */

@@ -60,7 +60,17 @@ def _load():
     lib.or_max_out_degree.restype = ctypes.c_int64
     lib.or_walk_totals.argtypes = [ctypes.c_int64, P_I64, P_I32, ctypes.c_double, ctypes.c_int32,
                                    P_F64]
-    lib.or_comb_bound.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_double]
+    lib.or_comb_bound.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.or_set_weights.argtypes = [P_F64, P_F64]
+    lib.or_set_weights.restype = None
+    lib.or_max_weighted_out_degree.argtypes = [ctypes.c_int64, P_I64, P_I32, P_F64]
+    lib.or_max_weighted_out_degree.restype = ctypes.c_double
+    lib.or_greedy_ex.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I64, P_I32, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.c_uint64, P_I32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, P_I32, P_I32, P_F64, P_F64,
+                                 P_F64, P_F64, P_I64, P_F64, P_I32]
+    lib.or_greedy_ex.restype = ctypes.c_int
     lib.or_comb_bound.restype = ctypes.c_double
     lib.or_score.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I32, ctypes.c_int32, ctypes.c_double,
                              ctypes.c_double, ctypes.c_int32, P_F64, P_I32, P_F64, P_F64]
@@ -79,6 +89,23 @@ def _load():
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+class _Weights:
+    """Install arc weights (aligned with col_idx; rev aligned with the reverse
+    graph's col_idx) for the duration of one oracle call."""
+
+    def __init__(self, w, w_rev):
+        self.w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        self.w_rev = None if w_rev is None else np.ascontiguousarray(w_rev, dtype=np.float64)
+
+    def __enter__(self):
+        lib = _load()
+        lib.or_set_weights(self.w.ctypes.data_as(P_F64) if self.w is not None else None,
+                           self.w_rev.ctypes.data_as(P_F64) if self.w_rev is not None else None)
+
+    def __exit__(self, *a):
+        _load().or_set_weights(None, None)
 
 
 def _ck(rc):
@@ -105,7 +132,17 @@ def max_out_degree(g) -> int:
     return int(_load().or_max_out_degree(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32)))
 
 
-def default_alpha(g) -> float:
+def max_weighted_out_degree(g, w) -> float:
+    rp, ci = _arrs(g)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    return float(_load().or_max_weighted_out_degree(g.n, rp.ctypes.data_as(P_I64),
+                                                    ci.ctypes.data_as(P_I32),
+                                                    w.ctypes.data_as(P_F64)))
+
+
+def default_alpha(g, w=None) -> float:
+    if w is not None:
+        return 1.0 / (max_weighted_out_degree(g, w) + 1.0)
     return 1.0 / (max_out_degree(g) + 1)
 
 
@@ -118,13 +155,15 @@ def walk_totals(g, alpha: float, ell: int) -> np.ndarray:
     return W
 
 
-def comb_bound(g, alpha: float, ell: int) -> float:
+def comb_bound(g, alpha: float, ell: int, w=None) -> float:
     """B_ell(V), the combinatorial tail bound (Section 3.1.2, Eq. comb-bound)."""
-    W = walk_totals(g, alpha, ell)
-    return float(_load().or_comb_bound(alpha, max_out_degree(g), W[ell]))
+    with _Weights(w, None):
+        W = walk_totals(g, alpha, ell)
+    D = max_weighted_out_degree(g, w) if w is not None else max_out_degree(g)
+    return float(_load().or_comb_bound(alpha, float(D), W[ell]))
 
 
-def score(g, S, alpha: float, eps: float, max_ell: int = 100000):
+def score(g, S, alpha: float, eps: float, max_ell: int = 100000, w=None):
     """GED_{<=ell*}(S) by the paper's score algorithm.
 
     Returns (c, ell*, B_ell*, phi) with phi[i] = alpha^i phi_i(S), i = 0..ell*.
@@ -135,48 +174,59 @@ def score(g, S, alpha: float, eps: float, max_ell: int = 100000):
     ell = ctypes.c_int32()
     B = ctypes.c_double()
     phi = np.zeros(max_ell + 1)
-    _ck(_load().or_score(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+    with _Weights(w, None):
+        rc = _load().or_score(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
                          Sb.ctypes.data_as(P_I32), sl, alpha, eps, max_ell, ctypes.byref(c),
-                         ctypes.byref(ell), ctypes.byref(B), phi.ctypes.data_as(P_F64)))
+                         ctypes.byref(ell), ctypes.byref(B), phi.ctypes.data_as(P_F64))
+    _ck(rc)
     return c.value, ell.value, B.value, phi[: ell.value + 1].copy()
 
 
-def score_fixed(g, S, alpha: float, ell: int):
+def score_fixed(g, S, alpha: float, ell: int, w=None):
     """GED_{<=ell}(S) at a fixed walk length; returns (c, phi[0..ell])."""
     rp, ci = _arrs(g)
     Sb, sl = _grp(S)
     c = ctypes.c_double()
     phi = np.zeros(ell + 1)
-    _ck(_load().or_score_fixed(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
-                               Sb.ctypes.data_as(P_I32), sl, alpha, ell, ctypes.byref(c),
-                               phi.ctypes.data_as(P_F64)))
+    with _Weights(w, None):
+        rc = _load().or_score_fixed(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                                    Sb.ctypes.data_as(P_I32), sl, alpha, ell, ctypes.byref(c),
+                                    phi.ctypes.data_as(P_F64))
+    _ck(rc)
     return c.value, phi
 
 
-def gain(g, S, x: int, alpha: float, ell: int) -> float:
+def gain(g, S, x: int, alpha: float, ell: int, w=None) -> float:
     """L_ell(S, x) = GED_{<=ell}(S + x) - GED_{<=ell}(S), walk-counted."""
     rp, ci = _arrs(g)
     Sb, sl = _grp(S)
     out = ctypes.c_double()
-    _ck(_load().or_gain_ext(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
-                            Sb.ctypes.data_as(P_I32), sl, int(x), alpha, ell, ctypes.byref(out)))
+    with _Weights(w, None):
+        rc = _load().or_gain_ext(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                                 Sb.ctypes.data_as(P_I32), sl, int(x), alpha, ell,
+                                 ctypes.byref(out))
+    _ck(rc)
     return out.value
 
 
-def pinit(g, S, alpha: float, ell: int, rev=None) -> np.ndarray:
+def pinit(g, S, alpha: float, ell: int, rev=None, w=None, w_rev=None) -> np.ndarray:
     """I(x) = sum_{i=1}^{ell} alpha^i P_i(S, x) for every x (0 for x in S)."""
     rp, ci = _arrs(g)
     rr, cr = _arrs(rev if rev is not None else g)
     Sb, sl = _grp(S)
     out = np.zeros(g.n)
-    _ck(_load().or_pinit_ext(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
-                             rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32),
-                             Sb.ctypes.data_as(P_I32), sl, alpha, ell, out.ctypes.data_as(P_F64)))
+    with _Weights(w, w_rev if w_rev is not None else (w if rev is None else None)):
+        rc = _load().or_pinit_ext(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                                  rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32),
+                                  Sb.ctypes.data_as(P_I32), sl, alpha, ell,
+                                  out.ctypes.data_as(P_F64))
+    _ck(rc)
     return out
 
 
 def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
-           forced_ell: int = 1, max_ell: int = 1 << 16, rev=None, with_score: bool = True):
+           forced_ell: int = 1, max_ell: int = 1 << 16, rev=None, with_score: bool = True,
+           stochastic: bool = False, eta: float = 0.1, seed: int = 1, w=None, w_rev=None):
     """Greedy GED-Walk maximisation (lazy greedy with P-initialisation).
 
     Returns a dict: group (pick order), ell/L1/U2/L2/B/evals per pick, score
@@ -194,14 +244,20 @@ def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
     t_ev = np.zeros(k, dtype=np.int64)
     sc = ctypes.c_double(math.nan)
     sc_ell = ctypes.c_int32(0)
-    _ck(_load().or_greedy(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+    if w is not None and rev is not None and w_rev is None:
+        raise ValueError("a weighted directed graph needs the reverse graph's weights")
+    with _Weights(w, w_rev if w_rev is not None else w):
+        rc = _load().or_greedy_ex(
+                          g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
                           rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32), k, alpha, eps,
-                          1 if lazy else 0, fb.ctypes.data_as(P_I32), nf, forced_ell, max_ell,
+                          1 if lazy else 0, 1 if stochastic else 0, eta, seed,
+                          fb.ctypes.data_as(P_I32), nf, forced_ell, max_ell,
                           grp.ctypes.data_as(P_I32), t_ell.ctypes.data_as(P_I32),
                           t_L1.ctypes.data_as(P_F64), t_U2.ctypes.data_as(P_F64),
                           t_L2.ctypes.data_as(P_F64), t_B.ctypes.data_as(P_F64),
                           t_ev.ctypes.data_as(P_I64),
                           ctypes.byref(sc) if with_score else None,
-                          ctypes.byref(sc_ell) if with_score else None))
+                          ctypes.byref(sc_ell) if with_score else None)
+    _ck(rc)
     return {"group": grp, "ell": t_ell, "L1": t_L1, "U2": t_U2, "L2": t_L2, "B": t_B,
             "evals": t_ev, "score": sc.value, "score_ell": sc_ell.value}

@@ -69,11 +69,34 @@ static double vec_sum(int64_t n, const double *x) {
   return nsum_get(&acc);
 }
 
-/* sum of x[u] over the in-neighbours u of v */
-static inline double row_sum(const int64_t *rp, const int32_t *ci, int64_t v, const double *x) {
+/*
+ * Arc weights for the weighted variant (Section 4.4: a walk contributes
+ * alpha^i times the product of its arc weights; the recurrences only gain a
+ * coefficient per arc).  NULL means every weight is 1.  Set for the duration
+ * of one public call by or_set_weights (single-threaded oracle).
+ */
+static const double *g_w = NULL;
+static const double *g_w_rev = NULL;
+
+void or_set_weights(const double *w, const double *w_rev) {
+  g_w = w;
+  g_w_rev = w_rev;
+}
+
+/* sum of w(u,v) x[u] over the in-neighbours u of v */
+static inline double row_sum_w(const int64_t *rp, const int32_t *ci, const double *w, int64_t v,
+                               const double *x) {
   nsum acc = {0, 0};
-  for (int64_t j = rp[v]; j < rp[v + 1]; ++j) nsum_add(&acc, x[ci[j]]);
+  if (w) {
+    for (int64_t j = rp[v]; j < rp[v + 1]; ++j) nsum_add(&acc, w[j] * x[ci[j]]);
+  } else {
+    for (int64_t j = rp[v]; j < rp[v + 1]; ++j) nsum_add(&acc, x[ci[j]]);
+  }
   return nsum_get(&acc);
+}
+
+static inline double row_sum(const int64_t *rp, const int32_t *ci, int64_t v, const double *x) {
+  return row_sum_w(rp, ci, g_w, v, x);
 }
 
 /* ---------------------------------------------------------- graph facts --- */
@@ -84,6 +107,25 @@ static inline double row_sum(const int64_t *rp, const int32_t *ci, int64_t v, co
  * maximum out-degree; with in-neighbour rows that is the largest number of
  * occurrences of a vertex in ci.
  */
+/*
+ * Weighted graphs: the same walk-extension argument with arc weights bounds
+ * sum_x omega_{l+1}(x) by max_v (sum of the weights of the arcs leaving v)
+ * times sum_x omega_l(x); that maximum replaces deg_max (the paper states the
+ * bound for unweighted graphs only; this is the reading used here).
+ */
+double or_max_weighted_out_degree(int64_t n, const int64_t *rp, const int32_t *ci,
+                                  const double *w) {
+  double *acc = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  if (!acc) return -1.0;
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t j = rp[v]; j < rp[v + 1]; ++j) acc[ci[j]] += w ? w[j] : 1.0;
+  double m = 0.0;
+  for (int64_t v = 0; v < n; ++v)
+    if (acc[v] > m) m = acc[v];
+  free(acc);
+  return m;
+}
+
 int64_t or_max_out_degree(int64_t n, const int64_t *rp, const int32_t *ci) {
   int64_t *cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
   if (!cnt) return -1;
@@ -130,15 +172,21 @@ int or_walk_totals(int64_t n, const int64_t *rp, const int32_t *ci, double alpha
  * comb-bound): alpha^{ell+1} * deg_max / (1 - alpha*deg_max) * sum_x omega_ell(x).
  * W_ell is the decayed total alpha^ell * sum_x omega_ell(x).
  */
-double or_comb_bound(double alpha, int64_t deg_max, double W_ell) {
-  double ad = alpha * (double)deg_max;
-  return alpha * ((double)deg_max / (1.0 - ad)) * W_ell;
+double or_comb_bound(double alpha, double deg_max, double W_ell) {
+  double ad = alpha * deg_max;
+  return alpha * (deg_max / (1.0 - ad)) * W_ell;
 }
 
-static int check_alpha(double alpha, int64_t deg_max) {
+static int check_alpha(double alpha, double deg_max) {
   if (!(alpha > 0.0) || !isfinite(alpha)) return OR_ERR_ALPHA;
-  if (deg_max > 0 && !(alpha * (double)deg_max < 1.0)) return OR_ERR_ALPHA;
+  if (deg_max > 0 && !(alpha * deg_max < 1.0)) return OR_ERR_ALPHA;
   return OR_OK;
+}
+
+/* deg_max of the bound: structural, or weighted when weights are set */
+static double bound_degree(int64_t n, const int64_t *rp, const int32_t *ci) {
+  if (g_w) return or_max_weighted_out_degree(n, rp, ci, g_w);
+  return (double)or_max_out_degree(n, rp, ci);
 }
 
 /* ------------------------------------------------------------- scoring --- */
@@ -163,7 +211,7 @@ int or_score(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *S, 
              double *out_bound, double *phi) {
   if (n < 1 || s_len < 0 || max_ell < 1) return OR_ERR_ARG;
   if (!(eps > 0.0) || !isfinite(eps)) return OR_ERR_EPS;
-  int64_t deg_max = or_max_out_degree(n, rp, ci);
+  double deg_max = bound_degree(n, rp, ci);
   int rc = check_alpha(alpha, deg_max);
   if (rc) return rc;
   uint8_t *inS = (uint8_t *)calloc((size_t)n, 1);
@@ -373,13 +421,14 @@ int or_gain_ext(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *
  * alpha^j psi^miss_j(v, S), the walks that start at v and avoid S (Lemma
  * "initialize").
  */
-static void miss_levels(int64_t n, const int64_t *rp, const int32_t *ci, const uint8_t *inS,
-                        double alpha, int32_t ell, double *M) {
+static void miss_levels(int64_t n, const int64_t *rp, const int32_t *ci, const double *w,
+                        const uint8_t *inS, double alpha, int32_t ell, double *M) {
   for (int64_t v = 0; v < n; ++v) M[v] = inS[v] ? 0.0 : 1.0;
   for (int32_t i = 1; i <= ell; ++i) {
     const double *prev = M + (int64_t)(i - 1) * n;
     double *cur = M + (int64_t)i * n;
-    for (int64_t v = 0; v < n; ++v) cur[v] = inS[v] ? 0.0 : alpha * row_sum(rp, ci, v, prev);
+    for (int64_t v = 0; v < n; ++v)
+      cur[v] = inS[v] ? 0.0 : alpha * row_sum_w(rp, ci, w, v, prev);
   }
 }
 
@@ -399,8 +448,8 @@ int or_pinit(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_
     free(b);
     return OR_ERR_NOMEM;
   }
-  miss_levels(n, rp, ci, inS, alpha, ell, m);
-  miss_levels(n, rp_r, ci_r, inS, alpha, ell, b);
+  miss_levels(n, rp, ci, g_w, inS, alpha, ell, m);
+  miss_levels(n, rp_r, ci_r, g_w ? g_w_rev : NULL, inS, alpha, ell, b);
   for (int64_t x = 0; x < n; ++x) {
     if (inS[x]) {
       I[x] = 0.0;
@@ -566,14 +615,62 @@ static int32_t lazy_update(gstate *g, iheap *Q) {
  * runner-up exists), L(v), the bound B_ell and the running number of gain
  * evaluations.  out_score is GED_{<=ell*}(S) of the final group via or_score.
  */
+/*
+ * Stochastic greedy sample (appendix "Dealing with large k"): for addition p
+ * (|S| = p), m = ceil((n/k) ln(1/eta)) vertices (at most |V \ S|) drawn
+ * without replacement from V \ S by a partial Fisher-Yates shuffle (Durstenfeld
+ * 1964) of the vertices outside S in increasing id order.  Draw j uses the
+ * splitmix64 output (Steele, Lea, Flood 2014) at position (p << 32) + j + 1 of
+ * the stream keyed by seed, scaled into [j, rest) by a 64x64->128-bit multiply.
+ * mark[v] = p for sampled v.
+ */
+static void draw_sample(int64_t n, const uint8_t *inS, int32_t k, double eta, uint64_t seed,
+                        int32_t p, int32_t *pool, int32_t *mark) {
+  int64_t rest = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (!inS[v]) pool[rest++] = (int32_t)v;
+  int64_t m = (int64_t)ceil((double)n / k * log(1.0 / eta));
+  if (m > rest) m = rest;
+  for (int64_t j = 0; j < m; ++j) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ULL * (((uint64_t)p << 32) + (uint64_t)j + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z = z ^ (z >> 31);
+    int64_t q = j + (int64_t)(((__uint128_t)z * (uint64_t)(rest - j)) >> 64);
+    int32_t t = pool[j];
+    pool[j] = pool[q];
+    pool[q] = t;
+  }
+  for (int64_t j = 0; j < m; ++j) mark[pool[j]] = p;
+}
+
+int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
+                 const int32_t *ci_r, int32_t k, double alpha, double eps, int32_t lazy,
+                 int32_t stochastic, double eta, uint64_t seed, const int32_t *forced,
+                 int32_t n_forced, int32_t forced_ell, int32_t max_ell, int32_t *out_group,
+                 int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2, double *tr_B,
+                 int64_t *tr_evals, double *out_score, int32_t *out_score_ell);
+
 int or_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
               const int32_t *ci_r, int32_t k, double alpha, double eps, int32_t lazy,
               const int32_t *forced, int32_t n_forced, int32_t forced_ell, int32_t max_ell,
               int32_t *out_group, int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2,
               double *tr_B, int64_t *tr_evals, double *out_score, int32_t *out_score_ell) {
+  return or_greedy_ex(n, rp, ci, rp_r, ci_r, k, alpha, eps, lazy, 0, 0.0, 0, forced, n_forced,
+                      forced_ell, max_ell, out_group, tr_ell, tr_L1, tr_U2, tr_L2, tr_B, tr_evals,
+                      out_score, out_score_ell);
+}
+
+int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
+                 const int32_t *ci_r, int32_t k, double alpha, double eps, int32_t lazy,
+                 int32_t stochastic, double eta, uint64_t seed, const int32_t *forced,
+                 int32_t n_forced, int32_t forced_ell, int32_t max_ell, int32_t *out_group,
+                 int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2, double *tr_B,
+                 int64_t *tr_evals, double *out_score, int32_t *out_score_ell) {
   if (n < 1 || k < 1 || k > n || n_forced < 0 || n_forced > k || max_ell < 1) return OR_ERR_ARG;
+  if (stochastic && !(eta > 0.0 && eta < 1.0)) return OR_ERR_ARG;
   if (!(eps > 0.0) || !isfinite(eps)) return OR_ERR_EPS;
-  int64_t deg_max = or_max_out_degree(n, rp, ci);
+  double deg_max = bound_degree(n, rp, ci);
   int rc = check_alpha(alpha, deg_max);
   if (rc) return rc;
 
@@ -596,13 +693,19 @@ int or_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp
   g.QU.pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   g.QL.key = g.L;
   g.QU.key = g.U;
+  int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t sampled_for = -1;
   int32_t s_size = 0;
   if (!g.inS || !cand || !g.L || !g.U || !g.fresh || !g.work || !W || !g.QL.h || !g.QL.pos ||
-      !g.QU.h || !g.QU.pos) {
+      !g.QU.h || !g.QU.pos || !pool || !mark) {
     rc = OR_ERR_NOMEM;
     goto done;
   }
-  for (int64_t v = 0; v < n; ++v) g.fresh[v] = -1;
+  for (int64_t v = 0; v < n; ++v) {
+    g.fresh[v] = -1;
+    mark[v] = -1;
+  }
   g.stamp = 0;
 
   for (int32_t p = 0; p < n_forced; ++p) {
@@ -636,15 +739,23 @@ int or_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp
     if (lazy) {
       rc = or_pinit(n, rp, ci, rp_r, ci_r, g.inS, alpha, g.ell, g.L);
       if (rc) goto done;
-      for (int64_t v = 0; v < n; ++v) {
-        cand[v] = g.inS[v] ? 0 : 1;
-        g.U[v] = g.L[v] + g.B;
-      }
-      hrebuild(&g.QL, n, cand);
-      hrebuild(&g.QU, n, cand);
+      for (int64_t v = 0; v < n; ++v) g.U[v] = g.L[v] + g.B;
     }
+    int32_t heaps_for = -1; /* addition whose candidate set the heaps hold */
     for (;;) {
       if (s_size == k) break;
+      if (stochastic && sampled_for != s_size) {
+        draw_sample(n, g.inS, k, eta, seed, s_size, pool, mark);
+        sampled_for = s_size;
+      }
+      if (lazy && heaps_for != s_size) {
+        /* stale L, U stay valid upper bounds (non-increasing in S) */
+        for (int64_t v = 0; v < n; ++v)
+          cand[v] = (!g.inS[v] && (!stochastic || mark[v] == s_size)) ? 1 : 0;
+        hrebuild(&g.QL, n, cand);
+        hrebuild(&g.QU, n, cand);
+        heaps_for = s_size;
+      }
       int32_t u = -1, v = -1;
       if (lazy) {
         u = lazy_update(&g, &g.QL);
@@ -653,7 +764,7 @@ int or_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp
         v = lazy_update(&g, &g.QU);
       } else {
         for (int64_t x = 0; x < n; ++x) {
-          if (g.inS[x]) continue;
+          if (g.inS[x] || (stochastic && mark[x] != s_size)) continue;
           if (g.fresh[x] != g.stamp) evaluate(&g, (int32_t)x);
           if (u < 0 || g.L[x] > g.L[u] || (g.L[x] == g.L[u] && x < u)) {
             v = u;
@@ -705,5 +816,7 @@ done:
   free(g.QL.pos);
   free(g.QU.h);
   free(g.QU.pos);
+  free(pool);
+  free(mark);
   return rc;
 }

@@ -50,12 +50,15 @@ void batch_forget(const ged_graph *g) {
   g_batch.erase(g);
 }
 
-// Step time per column for each candidate tile width; the fastest wins.
+// Step time per column for each candidate tile width; the fastest wins.  Each
+// candidate runs three ping-pong steps (X -> Y -> X -> Y) and the last two
+// are timed, so the cache state (the dense tiles of a step stay in the
+// Infinity Cache only when they fit) is that of a running batch.
 static int autotune_tile(ged_graph *g, BatchWs &b) {
   if (g->batch_tile > 0) return g->batch_tile;
   const int n = (int)g->n;
   hipStream_t st = g->stream;
-  const int cands[] = {8, 16, 32, 64};
+  const int cands[] = {4, 8, 16, 32, 64};
   double best = 1e300;
   int best_c = 16;
   hipEvent_t e0, e1;
@@ -75,21 +78,19 @@ static int autotune_tile(ged_graph *g, BatchWs &b) {
       a.alpha = g->prep.alpha;
       a.tmask = b.tmask.as<const uint64_t>();
       a.inj = g->prep.t_levels.as<const double>();
-      a.X = b.X.as<const double>();
-      a.Y = b.Y.as<double>();
-      launch_step(p, a, IN_VEC, OUT_TILE, st);  // warm-up
-      float ms_best = 1e30f;
       for (int r = 0; r < 3; ++r) {
-        GED_HIP(hipEventRecord(e0, st));
+        if (r == 1) GED_HIP(hipEventRecord(e0, st));
+        a.X = ((r & 1) ? b.Y : b.X).as<const double>();
+        a.Y = ((r & 1) ? b.X : b.Y).as<double>();
+        a.accum = r > 0;
         launch_step(p, a, IN_VEC, OUT_TILE, st);
-        launch_reduce(p, a, nullptr, nullptr, nullptr, st, ws.scratch());
-        GED_HIP(hipEventRecord(e1, st));
-        GED_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        GED_HIP(hipEventElapsedTime(&ms, e0, e1));
-        ms_best = std::min(ms_best, ms);
       }
-      const double per_col = ms_best / C;
+      launch_reduce(p, a, nullptr, nullptr, nullptr, st, ws.scratch());
+      GED_HIP(hipEventRecord(e1, st));
+      GED_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      GED_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double per_col = ms / C;
       if (per_col < best) {
         best = per_col;
         best_c = C;
@@ -235,3 +236,12 @@ extern "C" int ged_score_batch(ged_graph *g, const int64_t *offsets, const int32
 }
 
 extern "C" int32_t ged_batch_tile(const ged_graph *g) { return g ? g->batch_tile : 0; }
+
+extern "C" int ged_set_batch_tile(ged_graph *g, int32_t tile) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  if (tile != 0 && (tile < 1 || tile > 64 || (tile & (tile - 1)) != 0))
+    return fail(GED_ERR_ARG, "tile must be 0 (autotune) or a power of two <= 64");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  g->batch_tile = tile;
+  return GED_OK;
+}

@@ -98,12 +98,16 @@ struct HBuf {
 
 // Launch geometry shared by every walk-count step kernel.
 constexpr int kBlock = 256;            // threads per block (4 wavefronts of 64)
-constexpr int kLdsDoubles = 2048;      // LDS staging per block (16 KiB)
+constexpr int kLdsDoubles = 2048;      // LDS staging per block, one column (16 KiB)
+constexpr int kLdsDoublesWide = 8192;  // LDS staging per block, C >= 2 (64 KiB)
+// Values a block stages in LDS for a C-column step: wide steps use fat blocks
+// so the per-block fixed cost (descriptor, barriers) is paid for 4x more arcs.
+__host__ __device__ constexpr int lds_values(int C) { return C == 1 ? kLdsDoubles : kLdsDoublesWide; }
 constexpr int kRowsPerBlock = 511;     // max rows of one row block (row_ptr slice: 2 loads per thread)
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 
 // Row partition for a step with C columns: row blocks of consecutive short
-// rows (nnz*C <= kLdsDoubles) staged through LDS, and rows longer than that
+// rows (nnz*C <= lds_values(C)) staged through LDS, and rows longer than that
 // split into fixed segments whose partial sums a fix-up pass combines.
 struct Partition {
   int C = 0;

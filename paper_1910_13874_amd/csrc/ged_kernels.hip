@@ -107,10 +107,11 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
   constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL;
   constexpr bool CA = OUT == OUT_GAIN;
-  constexpr int PT = kLdsDoubles / kBlock;   // gathered values per thread
+  constexpr int LV = lds_values(C);          // values staged per block
+  constexpr int PT = LV / kBlock;            // gathered values per thread
   constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
   // vals has one spare slot per thread so every phase-1 store is unconditional
-  __shared__ double vals[kLdsDoubles + kBlock];
+  __shared__ double vals[LV + kBlock];
   __shared__ int rps[kRowsPerBlock + 1];
   __shared__ double red[(kBlock / 64) * C];
   __shared__ uint32_t mw[M1 ? kRowsPerBlock / 32 + 2 : 1];
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int f = t + q * kBlock;
-      vals[f < tot ? f : kLdsDoubles + t] = v[q];
+      vals[f < tot ? f : LV + t] = v[q];
     }
     __syncthreads();
     // Phase 2: tpr lanes per (row, column), as many as the row count allows.
@@ -393,7 +394,7 @@ void launch_reduce(const Partition &p, const StepArgs &a, double *level, double 
 
 void build_partition(Partition &p, const std::vector<int> &rp, int C) {
   const int n = (int)rp.size() - 1;
-  const int nnz_blk = kLdsDoubles / C;
+  const int nnz_blk = lds_values(C) / C;
   const int seg_len = std::max(1, kSegDoubles / C);
   std::vector<int4> blocks;
   std::vector<int4> segs;

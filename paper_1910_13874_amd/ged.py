@@ -80,6 +80,7 @@ _sig("ged_score", ctypes.c_int, [c_graph_p, P_I32, ctypes.c_int32, ctypes.c_doub
 _sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_double, P_F64])
 _sig("ged_batch_tile", ctypes.c_int32, [c_graph_p])
+_sig("ged_set_batch_tile", ctypes.c_int, [c_graph_p, ctypes.c_int32])
 _sig("ged_greedy", ctypes.c_int, [c_graph_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                   P_I32, P_F64, ctypes.POINTER(GreedyTrace)])
 _sig("ged_greedy_stochastic", ctypes.c_int,
@@ -243,6 +244,10 @@ class GedGraph:
 
     def batch_tile(self):
         return _lib.ged_batch_tile(self.handle)
+
+    def set_batch_tile(self, tile):
+        """Fix the batched-scoring tile width (0 = autotune on the next call)."""
+        _ck(_lib.ged_set_batch_tile(self.handle, int(tile)), "ged_set_batch_tile")
 
     def _greedy(self, fn, k, alpha, eps, extra, forced, forced_ell, with_score):
         grp = np.zeros(k, dtype=np.int32)
