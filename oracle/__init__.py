@@ -71,6 +71,9 @@ def _load():
                                  ctypes.c_int32, ctypes.c_int32, P_I32, P_I32, P_F64, P_F64,
                                  P_F64, P_F64, P_I64, P_F64, P_I32]
     lib.or_greedy_ex.restype = ctypes.c_int
+    lib.or_sample.argtypes = [ctypes.c_int64, P_I32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, P_I32]
+    lib.or_sample.restype = ctypes.c_int64
     lib.or_comb_bound.restype = ctypes.c_double
     lib.or_score.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I32, ctypes.c_int32, ctypes.c_double,
                              ctypes.c_double, ctypes.c_int32, P_F64, P_I32, P_F64, P_F64]
@@ -261,3 +264,14 @@ def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
     _ck(rc)
     return {"group": grp, "ell": t_ell, "L1": t_L1, "U2": t_U2, "L2": t_L2, "B": t_B,
             "evals": t_ev, "score": sc.value, "score_ell": sc_ell.value}
+
+
+def stochastic_sample(g, S, k: int, eta: float, seed: int, p: int) -> np.ndarray:
+    """Vertices the stochastic greedy samples for addition p with group S."""
+    Sb, sl = _grp(S)
+    out = np.zeros(g.n, dtype=np.int32)
+    m = _load().or_sample(g.n, Sb.ctypes.data_as(P_I32), sl, k, eta, seed, p,
+                          out.ctypes.data_as(P_I32))
+    if m < 0:
+        raise ValueError("oracle error (out of memory)")
+    return out[:m].copy()

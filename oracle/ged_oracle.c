@@ -651,6 +651,31 @@ int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t 
                  int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2, double *tr_B,
                  int64_t *tr_evals, double *out_score, int32_t *out_score_ell);
 
+/* The sample of addition p for group S (test helper): writes the sampled ids
+ * (increasing) to out and returns their number. */
+int64_t or_sample(int64_t n, const int32_t *S, int32_t s_len, int32_t k, double eta, uint64_t seed,
+                  int32_t p, int32_t *out) {
+  uint8_t *inS = (uint8_t *)calloc((size_t)n, 1);
+  int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *mark = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!inS || !pool || !mark) {
+    free(inS);
+    free(pool);
+    free(mark);
+    return -1;
+  }
+  for (int32_t q = 0; q < s_len; ++q) inS[S[q]] = 1;
+  for (int64_t v = 0; v < n; ++v) mark[v] = -1;
+  draw_sample(n, inS, k, eta, seed, p, pool, mark);
+  int64_t m = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (mark[v] == p) out[m++] = (int32_t)v;
+  free(inS);
+  free(pool);
+  free(mark);
+  return m;
+}
+
 int or_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
               const int32_t *ci_r, int32_t k, double alpha, double eps, int32_t lazy,
               const int32_t *forced, int32_t n_forced, int32_t forced_ell, int32_t max_ell,

@@ -98,11 +98,10 @@ struct HBuf {
 
 // Launch geometry shared by every walk-count step kernel.
 constexpr int kBlock = 256;            // threads per block (4 wavefronts of 64)
-constexpr int kLdsDoubles = 2048;      // LDS staging per block, one column (16 KiB)
-constexpr int kLdsDoublesWide = 8192;  // LDS staging per block, C >= 2 (64 KiB)
-// Values a block stages in LDS for a C-column step: wide steps use fat blocks
-// so the per-block fixed cost (descriptor, barriers) is paid for 4x more arcs.
-__host__ __device__ constexpr int lds_values(int C) { return C == 1 ? kLdsDoubles : kLdsDoublesWide; }
+constexpr int kLdsDoubles = 2048;      // LDS staging per block (16 KiB)
+// Values a block stages in LDS for a C-column step.  (64 KiB blocks for wide
+// steps were measured slower on BA n=2e6: 816 vs 764 us at C = 16.)
+__host__ __device__ constexpr int lds_values(int C) { return C > 0 ? kLdsDoubles : kLdsDoubles; }
 constexpr int kRowsPerBlock = 511;     // max rows of one row block (row_ptr slice: 2 loads per thread)
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 

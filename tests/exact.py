@@ -221,3 +221,50 @@ def exact_greedy(n, arcs, k, alpha, eps, delta, max_ell=1 << 12, follow=None):
         if len(S) < k:
             ell *= 2
     return S, ells, ties
+
+
+def weighted_arcs(n, row_ptr, col_idx, w):
+    """(u, v, weight) for every arc u -> v (row v lists u), weights as Fractions."""
+    return [(int(col_idx[j]), v, Fraction(float(w[j])))
+            for v in range(n) for j in range(int(row_ptr[v]), int(row_ptr[v + 1]))]
+
+
+def weighted_walk_sums(n, warcs, S, L):
+    """phi^w_i(S) = sum over i-walks touching S of the product of arc weights,
+    i = 0..L, by explicit enumeration."""
+    out = {u: [] for u in range(n)}
+    for (u, v, wt) in warcs:
+        out[u].append((v, wt))
+    Sset = set(int(s) for s in S)
+    res = [Fraction(0)] * (L + 1)
+    for s in range(n):
+        stack = [(s, s in Sset, Fraction(1), 0)]
+        while stack:
+            v, hit, prod, ln = stack.pop()
+            if hit:
+                res[ln] += prod
+            if ln < L:
+                for (w2, wt) in out[v]:
+                    stack.append((w2, hit or (w2 in Sset), prod * wt, ln + 1))
+    return res
+
+
+def weighted_ged_exact(n, warcs, S, alpha):
+    """Closed form with the weighted adjacency: 1^T[(I-aW)^-1 - I]1 minus the
+    same over the subgraph induced on V \\ S."""
+    a = Fraction(alpha)
+
+    def katz(vertices):
+        idx = {v: i for i, v in enumerate(vertices)}
+        m = len(vertices)
+        if m == 0:
+            return Fraction(0)
+        M = [[Fraction(int(i == j)) for j in range(m)] for i in range(m)]
+        for (u, v, wt) in warcs:
+            if u in idx and v in idx:
+                M[idx[u]][idx[v]] -= a * wt
+        x = _solve(M, [1] * m)
+        return sum(x) - m
+
+    Sset = set(int(s) for s in S)
+    return katz(list(range(n))) - katz([v for v in range(n) if v not in Sset])

@@ -409,3 +409,113 @@ def test_ties_go_to_the_smallest_id():
         assert [int(v) for v in r["group"]] == [0, 4, 1, 2]
         # a pick tied with its runner-up is only accepted once B_ell < eps/k
         assert r["B"][0] < EPS / 4 and r["L1"][0] == r["L2"][0]
+
+
+# ------------------------------------------------------------- weighted --
+
+def sym_weights(g, seed):
+    """Symmetric dyadic weights in (0, 1]: w(u,v) = w(v,u), exact in binary."""
+    vals = np.array([0.25, 0.5, 0.75, 1.0])
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    a = np.minimum(rows, g.col_idx).astype(np.int64)
+    b = np.maximum(rows, g.col_idx).astype(np.int64)
+    h = (a * 1000003 + b * 7919 + seed * 31) % 4
+    return vals[h]
+
+
+@pytest.mark.parametrize("g", tiny_graphs()[:10], ids=lambda g: g.name)
+def test_weighted_levels_and_series(g):
+    w = sym_weights(g, 5)
+    alpha = oracle.default_alpha(g, w)
+    warcs = exact.weighted_arcs(g.n, g.row_ptr, g.col_idx, w)
+    L = 5
+    for S in groups_of(g.n, 1)[:-1] + [list(range(g.n))]:
+        c, phi = oracle.score_fixed(g, S, alpha, L, w=w)
+        want = exact.weighted_walk_sums(g.n, warcs, S, L)
+        for i in range(1, L + 1):
+            assert rel(phi[i], Fraction(alpha) ** i * want[i]) <= 1e-14, (g.name, S, i)
+        c2, ell, B, _ = oracle.score(g, S, alpha, EPS, w=w)
+        ex = exact.weighted_ged_exact(g.n, warcs, S, alpha)
+        assert float(ex) - EPS < c2 <= float(ex) * (1 + 1e-13) + 1e-300
+
+
+def test_weighted_special_cases():
+    g = inputs.barabasi_albert(300, 3, 61)
+    alpha = oracle.default_alpha(g)
+    S = [1, 7, 30]
+    # unit weights are the unweighted method, bit for bit
+    ones = np.ones(g.nnz)
+    assert oracle.score(g, S, alpha, EPS, w=ones)[0] == oracle.score(g, S, alpha, EPS)[0]
+    # constant weights c: every i-walk gains c^i, i.e. alpha -> alpha*c, same ell*
+    c = 0.5
+    a, ell_a, _, _ = oracle.score(g, S, alpha, EPS, w=np.full(g.nnz, c))
+    b, ell_b, _, _ = oracle.score(g, S, alpha * c, EPS)
+    assert ell_a == ell_b and rel(a, b) <= 1e-14
+    # bound validity with weights, exactly, on a tiny graph
+    t = tiny_graphs()[8]
+    w = sym_weights(t, 2)
+    al = oracle.default_alpha(t, w)
+    warcs = exact.weighted_arcs(t.n, t.row_ptr, t.col_idx, w)
+    tot = exact.weighted_ged_exact(t.n, warcs, range(t.n), al)
+    sums = exact.weighted_walk_sums(t.n, warcs, range(t.n), 8)
+    part = Fraction(0)
+    for ell in range(1, 9):
+        part += Fraction(al) ** ell * sums[ell]
+        assert tot - part <= Fraction(oracle.comb_bound(t, al, ell, w=w)) * (1 + Fraction(1, 10**12))
+
+
+def test_weighted_greedy_is_greedy():
+    g = inputs.erdos_renyi(9, 16, 77)
+    w = sym_weights(g, 3)
+    alpha = oracle.default_alpha(g, w)
+    warcs = exact.weighted_arcs(g.n, g.row_ptr, g.col_idx, w)
+    r = oracle.greedy(g, 3, alpha, EPS, w=w)
+    lz = oracle.greedy(g, 3, alpha, EPS, w=w, lazy=False)
+    assert list(r["group"]) == list(lz["group"])
+    S = []
+    for u in r["group"]:
+        base = exact.weighted_ged_exact(g.n, warcs, S, alpha)
+        gains = {x: exact.weighted_ged_exact(g.n, warcs, S + [x], alpha) - base
+                 for x in range(g.n) if x not in S}
+        assert gains[int(u)] >= max(gains.values()) - Fraction(EPS) / 3
+        S.append(int(u))
+
+
+# ----------------------------------------------------------- stochastic --
+
+def test_stochastic_sample_properties():
+    g = inputs.barabasi_albert(500, 3, 71)
+    S = [3, 9, 100]
+    k, eta = 20, 0.1
+    smp = oracle.stochastic_sample(g, S, k, eta, 5, 3)
+    assert len(smp) == math.ceil(g.n / k * math.log(1 / eta))
+    assert len(set(smp.tolist())) == len(smp) and not set(S) & set(smp.tolist())
+    # different additions draw different samples; a tiny eta takes all of V \ S
+    assert not np.array_equal(smp, oracle.stochastic_sample(g, S, k, eta, 5, 4))
+    assert len(oracle.stochastic_sample(g, S, k, 1e-300, 5, 3)) == g.n - len(S)
+
+
+def test_stochastic_tiny_eta_is_lazy_greedy():
+    g = inputs.barabasi_albert(150, 2, 300)
+    alpha = oracle.default_alpha(g)
+    a = oracle.greedy(g, 6, alpha, EPS)
+    b = oracle.greedy(g, 6, alpha, EPS, stochastic=True, eta=1e-300, seed=9)
+    assert list(a["group"]) == list(b["group"]) and list(a["ell"]) == list(b["ell"])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_stochastic_picks_best_of_sample(seed):
+    g = inputs.erdos_renyi(10, 18, 80 + seed)
+    alpha = oracle.default_alpha(g)
+    k, eta = 3, 0.4
+    for lazy in (True, False):
+        r = oracle.greedy(g, k, alpha, EPS, stochastic=True, eta=eta, seed=seed, lazy=lazy)
+        S = []
+        for p, u in enumerate(r["group"]):
+            smp = oracle.stochastic_sample(g, S, k, eta, seed, p).tolist()
+            assert int(u) in smp
+            base = exact.ged_exact(g.n, g.row_ptr, g.col_idx, S, alpha)
+            gains = {x: exact.ged_exact(g.n, g.row_ptr, g.col_idx, S + [x], alpha) - base
+                     for x in smp}
+            assert gains[int(u)] >= max(gains.values()) - Fraction(EPS) / k
+            S.append(int(u))
