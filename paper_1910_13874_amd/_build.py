@@ -16,6 +16,7 @@ HIP_SOURCES = [
     "ged_kernels.hip",
     "ged_api.hip",
     "ged_batch.hip",
+    "ged_split.hip",
     "ged_greedy.hip",
     "ged_server.hip",
 ]

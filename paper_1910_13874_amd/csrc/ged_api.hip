@@ -46,12 +46,14 @@ StepArgs base_args(ged_graph *g, bool reverse) {
   return a;
 }
 
-double algo_bytes(const ged_graph *g, int C, int in, int out) {
+double algo_bytes(const ged_graph *g, int C, int in, int out, int extra_rows) {
   const double n = (double)g->n, nnz = (double)g->nnz;
-  double b = 4.0 * (n + 1) + 4.0 * nnz + 8.0 * n * C;  // row_ptr, col_idx, Y
+  double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
+  if (out != OUT_COMBINE) b += 8.0 * n * C;  // Y
   if (g->weighted) b += 8.0 * nnz;
   switch (in) {
-    case IN_VEC: b += 8.0 * n * C; break;
+    case IN_VEC:
+    case IN_CNT: b += 8.0 * n * C; break;
     case IN_MASK:
     case IN_NOTMASK: b += n / 8.0; break;
     case IN_TILEMASK: b += 8.0 * n; break;
@@ -65,9 +67,10 @@ double algo_bytes(const ged_graph *g, int C, int in, int out) {
     case OUT_TILE:
     case OUT_POOL: b += 8.0 * n; break;
     case OUT_GAIN: b += n / 8.0 + 4.0 * n; break;
+    case OUT_COMBINE: b += 8.0 * n * 3; break;  // tmask, t_a, tr
     default: break;
   }
-  return b;
+  return b + 8.0 * n * C * extra_rows;
 }
 
 double comb_bound(ged_graph *g, double alpha, double W_ell) {
@@ -102,7 +105,7 @@ static hipEvent_t prof_event(ged_graph *g) {
 }
 
 void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int out,
-              hipStream_t st) {
+              hipStream_t st, int extra_rows) {
   if (!g->prof.on) {
     launch_step(p, a, in, out, st);
     return;
@@ -110,8 +113,8 @@ void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int o
   hipEvent_t e0 = prof_event(g), e1 = prof_event(g);
   GED_HIP(hipEventRecord(e0, st));
   launch_step(p, a, in, out, st, e1);
-  g->prof.recs.push_back(
-      {e0, e1, a.C, algo_bytes(g, a.C, in, out), (double)g->nnz * a.C, in * 8 + out});
+  g->prof.recs.push_back({e0, e1, a.C, algo_bytes(g, a.C, in, out, extra_rows),
+                          (double)g->nnz * a.C, in * 8 + out});
 }
 
 // -------------------------------------------------------- precomputation --
@@ -141,6 +144,7 @@ int prepare(ged_graph *g, double alpha, double eps) {
   g->pws.fit(p);
   g->levels.ensure(sizeof(double) * 64);
   pc.valid = false;
+  pc.tr_r = -1;
   pc.W.clear();
   pc.W.push_back((double)n);
   ensure_levels(pc, n, 16, st);
@@ -284,7 +288,8 @@ static std::vector<const void *> score_signature(ged_graph *g) {
   return {g->mask.p, g->vec[0].p, g->vec[1].p, g->acc.p, g->s_levels.p, g->s_dev.p,
           g->sws.blk.p, g->sws.seg.p, g->sws.lng.p, g->sws.red2.p, pc.t_levels.p,
           (const void *)g->stream,
-          abits, (const void *)(intptr_t)pc.ell, (const void *)(intptr_t)g->s_cap};
+          abits, (const void *)(intptr_t)pc.ell, (const void *)(intptr_t)g->s_cap,
+          (const void *)(intptr_t)0 /* level-by-level chain */};
 }
 
 int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
@@ -302,6 +307,7 @@ int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, dou
     *out = 0.0;
     return GED_OK;
   }
+  if (split_ok(g)) return split_score(g, S, s_len, out);
   hipStream_t st = g->stream;
   ensure_score_buffers(g, s_len, st);
   int *hs = g->s_host.as<int>();
@@ -575,6 +581,7 @@ extern "C" int ged_invalidate(ged_graph *g) {
   return guarded([&]() -> int {
     GED_HIP(hipStreamSynchronize(g->stream));
     g->prep.valid = false;
+    g->prep.tr_r = -1;
     g->prep.W.clear();
     g->prep.tail_level = -1;
     return GED_OK;

@@ -20,8 +20,11 @@ struct BatchWs {
   bool tmask_ready = false;
   DBuf X, Y;        // double [n*C]
   DBuf offsets;     // int64 [cap_g+1]
-  DBuf members;     // int [cap_m] (internal ids)
-  std::vector<int> h_members;
+  DBuf members;     // int [cap_m] (internal ids, duplicates dropped)
+  DBuf mcol;        // int [cap_m] group of each member
+  std::vector<int64_t> h_offsets;
+  std::vector<int> h_members, h_mcol;
+  SplitWs sw;       // split scoring (undirected graphs)
   DBuf scores;      // double [cap_g + 64]
   HBuf h_scores;
   size_t cap_g = 0, cap_m = 0;
@@ -160,66 +163,118 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
     b.tmask_ready = true;
   }
   const int C = autotune_tile(g, b);
+  const bool split = split_ok(g);
   Partition &p = partition(g, C);
   b.ws.fit(p);
-  b.X.ensure(sizeof(double) * (size_t)n * C);
-  b.Y.ensure(sizeof(double) * (size_t)n * C);
+  // internal ids, duplicates inside a group dropped; column of every member
+  std::vector<int64_t> &hoff = b.h_offsets;
+  std::vector<int> &hmem = b.h_members;
+  std::vector<int> &hcol = b.h_mcol;
+  hoff.assign((size_t)G + 1, 0);
+  hmem.clear();
+  hmem.reserve((size_t)M);
+  std::vector<int64_t> degsum((size_t)G);
+  for (int j = 0; j < G; ++j) {
+    hoff[j] = (int64_t)hmem.size();
+    degsum[j] = map_group(g, members + offsets[j], offsets[j + 1] - offsets[j], hmem);
+  }
+  hoff[G] = (int64_t)hmem.size();
+  const int64_t Md = hoff[G];
+  hcol.resize((size_t)Md);
+  for (int j = 0; j < G; ++j)
+    for (int64_t q = hoff[j]; q < hoff[j + 1]; ++q) hcol[q] = j;
   if ((size_t)G + 1 > b.cap_g) {
     b.cap_g = std::max<size_t>((size_t)G + 1, 2 * b.cap_g);
     b.offsets.ensure(sizeof(int64_t) * b.cap_g);
     b.scores.ensure(sizeof(double) * (b.cap_g + 64));
     b.h_scores.ensure(sizeof(double) * (b.cap_g + 64));
   }
-  if ((size_t)std::max<int64_t>(M, 1) > b.cap_m) {
-    b.cap_m = std::max<size_t>((size_t)std::max<int64_t>(M, 1), 2 * b.cap_m);
+  if ((size_t)std::max<int64_t>(Md, 1) > b.cap_m) {
+    b.cap_m = std::max<size_t>((size_t)std::max<int64_t>(Md, 1), 2 * b.cap_m);
     b.members.ensure(sizeof(int) * b.cap_m);
+    b.mcol.ensure(sizeof(int) * b.cap_m);
   }
-  GED_HIP(hipMemcpyAsync(b.offsets.p, offsets, sizeof(int64_t) * (size_t)(G + 1),
+  GED_HIP(hipMemcpyAsync(b.offsets.p, hoff.data(), sizeof(int64_t) * (size_t)(G + 1),
                          hipMemcpyHostToDevice, st));
-  if (M > 0) {
-    b.h_members.resize((size_t)M);
-    for (int64_t j = 0; j < M; ++j) b.h_members[j] = g->new_id[members[j]];
-    GED_HIP(hipMemcpyAsync(b.members.p, b.h_members.data(), sizeof(int) * (size_t)M,
+  if (Md > 0) {
+    GED_HIP(hipMemcpyAsync(b.members.p, hmem.data(), sizeof(int) * (size_t)Md,
+                           hipMemcpyHostToDevice, st));
+    GED_HIP(hipMemcpyAsync(b.mcol.p, hcol.data(), sizeof(int) * (size_t)Md,
                            hipMemcpyHostToDevice, st));
   }
+  SplitPlan pl;
+  if (split) {
+    pl = split_plan(g, g->prep.ell);
+    size_t wl_need = 1;
+    for (int g0 = 0; g0 < G; g0 += C) {
+      size_t need = 0;
+      for (int j = g0; j < std::min(G, g0 + C); ++j) need += split_wl_need(g, degsum[j]);
+      wl_need = std::max(wl_need, need);
+    }
+    split_tables(g, pl, st);
+    split_fit(g, b.sw, pl, C, wl_need, st);
+    b.sw.zero = false;
+  } else {
+    b.X.ensure(sizeof(double) * (size_t)n * C);
+    b.Y.ensure(sizeof(double) * (size_t)n * C);
+  }
+  auto enqueue = [&]() {
+    if (!split) {
+      enqueue_batch(g, b, G, C, st);
+      return;
+    }
+    for (int g0 = 0; g0 < G; g0 += C) {
+      const int nc = std::min(C, G - g0);
+      // scores of this tile's columns (the buffer has C entries of slack)
+      enqueue_split_tile(g, b.sw, pl, C, b.offsets.as<const int64_t>(), b.members.as<const int>(),
+                         b.mcol.as<const int>(), g0, nc, hoff[g0 + nc] - hoff[g0],
+                         b.tmask.as<uint64_t>(), b.scores.as<double>() + g0, st);
+    }
+  };
   double abits_d = alpha;
   const void *abits;
   std::memcpy(&abits, &abits_d, sizeof(abits));
   std::vector<const void *> sig = {b.tmask.p,      b.X.p,       b.Y.p,
-                                   b.offsets.p,    b.members.p, b.scores.p,
+                                   b.offsets.p,    b.members.p, b.mcol.p,   b.scores.p,
                                    b.ws.blk.p,     b.ws.seg.p,  b.ws.lng.p, b.ws.red2.p,
+                                   b.sw.cnt1.p,    b.sw.cnt2.p, b.sw.lv.p,  b.sw.wl.p,
+                                   b.sw.wl_n.p,    b.sw.ws.blk.p, b.sw.ws.seg.p, b.sw.ws.lng.p,
+                                   b.sw.ws.red2.p, g->omega2.p, g->prep.tr.p,
                                    g->prep.t_levels.p, (const void *)st, abits,
+                                   (const void *)(uintptr_t)b.sw.wl_cap,
+                                   (const void *)(intptr_t)split,
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
                                    (const void *)(intptr_t)C};
   if (g->prof.on) {
     // profiling times every step launch with events: run the batch eagerly
-    enqueue_batch(g, b, G, C, st);
+    enqueue();
   } else {
-  if (b.exec && sig != b.sig) {
-    (void)hipGraphExecDestroy(b.exec);
-    (void)hipGraphDestroy(b.graph);
-    b.exec = nullptr;
-    b.graph = nullptr;
-  }
-  if (!b.exec) {
-    GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    try {
-      enqueue_batch(g, b, G, C, st);
-    } catch (...) {
-      hipGraph_t dummy = nullptr;
-      (void)hipStreamEndCapture(st, &dummy);
-      if (dummy) (void)hipGraphDestroy(dummy);
-      throw;
+    if (b.exec && sig != b.sig) {
+      (void)hipGraphExecDestroy(b.exec);
+      (void)hipGraphDestroy(b.graph);
+      b.exec = nullptr;
+      b.graph = nullptr;
     }
-    GED_HIP(hipStreamEndCapture(st, &b.graph));
-    GED_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
-    b.sig = sig;
-  }
-  GED_HIP(hipGraphLaunch(b.exec, st));
+    if (!b.exec) {
+      GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue();
+      } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(st, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+      }
+      GED_HIP(hipStreamEndCapture(st, &b.graph));
+      GED_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+      b.sig = sig;
+    }
+    GED_HIP(hipGraphLaunch(b.exec, st));
   }
   double *hs = b.h_scores.as<double>();
   GED_HIP(hipMemcpyAsync(hs, b.scores.p, sizeof(double) * (size_t)G, hipMemcpyDeviceToHost, st));
   GED_HIP(hipStreamSynchronize(st));
+  if (split) b.sw.zero = true;
   std::memcpy(out, hs, sizeof(double) * (size_t)G);
   return GED_OK;
 }

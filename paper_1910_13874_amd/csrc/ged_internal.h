@@ -127,7 +127,8 @@ enum InMode : int {
   IN_MASK = 3,     // [u in S]              (hit chain, level 0)
   IN_TILEMASK = 4, // bit c of tmask[u]     (batched hit chains, level 0)
   IN_ONEHOT = 5,   // [cand_col[u] == c]    (gain chains, level 0)
-  IN_FRESH = 6     // fresh[c] ? bit c of tmask[u] : X[u*C+c]   (serving pool)
+  IN_FRESH = 6,    // fresh[c] ? bit c of tmask[u] : X[u*C+c]   (serving pool)
+  IN_CNT = 7       // Xc[u*C + c] (integer walk counts, exact in FP64 below 2^53)
 };
 
 // Row epilogue of a step (what y(v) becomes).
@@ -137,7 +138,9 @@ enum OutMode : int {
   OUT_ZERO = 2,  // v in S ? 0 : alpha * sum                        (miss chain)
   OUT_TILE = 3,  // bit c of tmask[v] ? inj[v] : alpha * sum        (batched hit chains)
   OUT_GAIN = 4,  // v in S ? 0 : (cand_col[v] == c ? inj[v] : alpha * sum)  (gain chains)
-  OUT_POOL = 5   // bit c of tmask[v] ? inj[step[c]*n + v] : alpha * sum   (serving pool)
+  OUT_POOL = 5,  // bit c of tmask[v] ? inj[step[c]*n + v] : alpha * sum   (serving pool)
+  OUT_COMBINE = 6 // y as OUT_TILE, not stored; the column sum takes the split
+                  // combination of y with the stored lower levels (split scoring)
 };
 
 struct StepArgs {
@@ -159,6 +162,18 @@ struct StepArgs {
   double *blk_part = nullptr;    // [n_blocks*C] block column sums
   double *seg_out = nullptr;     // [n_segs*C] raw segment sums
   double *long_part = nullptr;   // [n_long*C] long-row outputs (for column sums)
+  // IN_CNT source
+  const uint64_t *Xc = nullptr;  // [n*C]
+  // OUT_COMBINE: per row v and column c the column sum takes
+  //   q + y + y*tr[v] + [v not in S](inj[v] - y) * (q_even ? q + y : q),
+  // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c]
+  const double *tr = nullptr;       // [n]
+  const uint64_t *q_cnt1 = nullptr; // [n*C] or null
+  const uint64_t *q_cnt2 = nullptr; // [n*C] or null
+  double q_s1 = 0, q_s2 = 0;
+  const double *q_lv = nullptr;     // [q_nlv * n * C]
+  int q_nlv = 0;
+  int q_even = 0;
 };
 
 // Walk-count step: Y = epilogue(alpha * A X) with column sums.  Three
@@ -218,7 +233,30 @@ struct PrepCache {
   DBuf t_tail[2];              // ping-pong vectors to extend W beyond ell*
   int tail_level = -1;         // level held in t_tail[tail_cur]
   int tail_cur = 0;
+  DBuf tr;                     // [n] sum_{c=1..tr_r} t_c (split scoring)
+  int tr_r = -1;               // -1: not built for this (alpha, eps)
 };
+
+// ------------------------------------------------------- split scoring --
+//
+// Undirected graphs only.  ell* levels are obtained from the hit chain up to
+// a = ceil(ell/2): levels 1..s by integer pushes from the group's members,
+// levels s+1..a by dense steps, the last of which combines (OUT_COMBINE).
+struct SplitPlan {
+  int a = 0, r = 0, s = 0, nlv = 0;  // nlv = dense levels stored (s+1 .. a-1)
+  bool even = false;                 // r == a
+};
+
+struct SplitWs {
+  DBuf cnt1, cnt2;       // uint64 [n*C] walk counts of levels 1, 2; zero between tiles
+  DBuf lv;               // double [nlv*n*C] stored dense levels
+  DBuf wl, wl_n;         // uint64 worklist [wl_cap], uint32 length
+  unsigned wl_cap = 0;
+  size_t cnt_elems = 0;  // n*C the count arrays were zeroed for
+  bool zero = false;
+  StepWs ws;
+};
+
 
 struct ScoreGraphExec;  // captured graph for ged_score
 
@@ -275,6 +313,17 @@ struct ged_graph {
   std::vector<const void *> score_sig;  // pointers/values the captured graph depends on
   // batched scoring
   int32_t batch_tile = 0;
+  // split scoring
+  ged::DBuf omega2;             // uint64 [n] walks of length 2 ending at v (unweighted)
+  bool omega2_ready = false;
+  std::vector<uint32_t> stamp;  // host group-dedup stamps
+  uint32_t stamp_gen = 0;
+  ged::SplitWs split_ws;        // single-group scoring workspace
+  ged::DBuf split_tmask;        // uint64 [n], zero between calls
+  bool split_tmask_ready = false;
+  ged::DBuf split_in;           // int64 offsets[2], int members[cap], int mcol[cap]
+  ged::HBuf split_in_host;
+  int split_cap = 0;
   // profiling
   ged::Profiler prof;
   ~ged_graph();
@@ -294,14 +343,36 @@ StepArgs base_args(ged_graph *g, bool reverse = false);
 // Step launch, timed with HIP events around the main kernel when profiling is
 // on for the graph (the only way library code launches walk-count steps).
 void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in_mode, int out_mode,
-              hipStream_t st);
+              hipStream_t st, int extra_rows = 0);
 // Algorithmic bytes of one step launch: row_ptr, col_idx (+ weights), the
-// gathered input, the written output and the epilogue's mask reads.
-double algo_bytes(const ged_graph *g, int C, int in_mode, int out_mode);
+// gathered input, the written output, the epilogue's mask reads and
+// `extra_rows` further C-wide rows per vertex that the epilogue streams.
+double algo_bytes(const ged_graph *g, int C, int in_mode, int out_mode, int extra_rows = 0);
 int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
                 double *out, ged_score_info *info);
 // Drop the batched-scoring workspace of a graph that is being destroyed.
 void batch_forget(const ged_graph *g);
+
+// Split scoring (ged_split.hip).
+bool split_ok(const ged_graph *g);
+SplitPlan split_plan(const ged_graph *g, int ell);
+// Make sure per-graph split tables (omega2, tr) exist for the prepared (alpha, eps).
+void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st);
+// Size a workspace for C columns and a worklist of wl_need entries; zero the
+// count arrays if they are new or dirty.
+void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
+               hipStream_t st);
+// Worklist entries a group needs: min(n, sum of member degrees) + ceil(nnz/chunk).
+size_t split_wl_need(const ged_graph *g, int64_t deg_sum);
+// Enqueue one tile of nc <= C groups (g0 .. g0+nc-1 of the device offsets /
+// members / mcol arrays); scores go to out[0..nc).
+void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
+                        const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
+                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st);
+// Map caller ids to internal ids, dropping duplicates inside the group;
+// returns the sum of the members' degrees.
+int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> &out);
+int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out);
 
 // Run fn, translating HipError into a status code + message.
 template <class F>

@@ -44,8 +44,10 @@ __device__ __forceinline__ double load_in(const StepArgs &a, int u, int c) {
     return ((a.tmask[u] >> c) & 1ull) ? 1.0 : 0.0;
   } else if constexpr (IN == IN_ONEHOT) {
     return (a.cand_col[u] == c) ? 1.0 : 0.0;
-  } else {  // IN_FRESH
+  } else if constexpr (IN == IN_FRESH) {
     return a.fresh[c] ? (((a.tmask[u] >> c) & 1ull) ? 1.0 : 0.0) : a.X[(size_t)u * C + c];
+  } else {  // IN_CNT
+    return (double)a.Xc[(size_t)u * C + c];
   }
 }
 
@@ -61,7 +63,7 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
     return inS ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_ZERO) {
     return inS ? 0.0 : y;
-  } else if constexpr (OUT == OUT_TILE) {
+  } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
@@ -72,10 +74,32 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
   }
 }
 
+// Split scoring, last dense level a (undirected graphs).  Cutting a walk of
+// length a + c after its first a arcs at vertex v: it meets S iff its first
+// part does (h_a(v) of them, each continued by any of the t_c(v) walks of
+// length c leaving v -- by symmetry the walks of length c ending at v), or
+// its first part misses S (t_a(v) - h_a(v), zero for v in S) and its last c
+// vertices meet S (again by reversal, h_c(v) for v outside S).  Summed over
+// c = 1..r and added to levels 1..a, the row's share of the truncated score
+// (Alg. "GED-Walk Computation") is
+//   sum_{i<a} h_i + h_a + h_a * sum_{c<=r} t_c + [v not in S](t_a - h_a) * sum_{c<=r} h_c.
+template <int C>
+__device__ __forceinline__ double combine_contrib(const StepArgs &a, int v, int c, double y,
+                                                  bool inS) {
+  const size_t o = (size_t)v * C + c;
+  double q = 0.0;
+  if (a.q_cnt1) q += a.q_s1 * (double)a.q_cnt1[o];
+  if (a.q_cnt2) q += a.q_s2 * (double)a.q_cnt2[o];
+  for (int l = 0; l < a.q_nlv; ++l) q += a.q_lv[(size_t)l * a.n * C + o];
+  const double rs = a.q_even ? q + y : q;
+  const double miss = inS ? 0.0 : (a.inj[v] - y) * rs;
+  return ((q + y) + y * a.tr[v]) + miss;
+}
+
 template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
                             TM ? a.tmask[v] : 0ull, OUT == OUT_GAIN ? a.cand_col[v] : -1);
 }
@@ -105,7 +129,7 @@ template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE;
   constexpr bool CA = OUT == OUT_GAIN;
   constexpr int LV = lds_values(C);          // values staged per block
   constexpr int PT = LV / kBlock;            // gathered values per thread
@@ -196,8 +220,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         if constexpr (M1) inS = (mw[(r >> 5) - (r0 >> 5)] >> (r & 31)) & 1u;
         const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
                                             CA ? cw[rl] : -1);
-        a.Y[(size_t)r * C + c] = y;
-        colsum += y;
+        if constexpr (OUT == OUT_COMBINE) {
+          colsum += combine_contrib<C>(a, r, c, y, (tmw[rl] >> c) & 1ull);
+        } else {
+          a.Y[(size_t)r * C + c] = y;
+          colsum += y;
+        }
       }
     }
     block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C, a.accum);
@@ -245,8 +273,11 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   }
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-  const double y = epilogue<C, OUT>(a, r, c, acc);
-  a.Y[(size_t)r * C + c] = y;
+  double y = epilogue<C, OUT>(a, r, c, acc);
+  if constexpr (OUT == OUT_COMBINE)
+    y = combine_contrib<C>(a, r, c, y, (a.tmask[r] >> c) & 1ull);
+  else
+    a.Y[(size_t)r * C + c] = y;
   double *lp = a.long_part + (size_t)l * C + c;
   *lp = a.accum ? *lp + y : y;
 }
@@ -327,6 +358,12 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
   GED_CASE(IN_ONEHOT, OUT_GAIN)
   GED_CASE(IN_VEC, OUT_GAIN)
   GED_CASE(IN_FRESH, OUT_POOL)
+  GED_CASE(IN_TILEMASK, OUT_COMBINE)
+  GED_CASE(IN_VEC, OUT_COMBINE)
+  if constexpr (!WGT) {  // integer walk counts exist for unweighted graphs only
+    GED_CASE(IN_CNT, OUT_TILE)
+    GED_CASE(IN_CNT, OUT_COMBINE)
+  }
   if constexpr (C == 1) {
     GED_CASE(IN_ONES, OUT_PLAIN)
     GED_CASE(IN_VEC, OUT_PLAIN)

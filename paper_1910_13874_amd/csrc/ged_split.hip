@@ -1,0 +1,458 @@
+// Split scoring for undirected graphs: the truncated score of a group from
+// the hit chain up to level a = ceil(ell*/2) instead of ell*.
+//
+// A walk of length a + c, cut after its first a arcs at vertex v, meets S iff
+// its first a + 1 vertices do or its last c vertices do.  On an undirected
+// graph the walks of length c leaving v are the reversals of those ending at
+// v, so both halves are counted by chains the scoring path already has: the
+// hit chain h (walks ending at v that meet S, the phi^hit recurrence of
+// Section 3.1.1) and the total chain t (Eq. phisum's omega, decayed):
+//   phi_{a+c}(S) = sum_v h_a(v) t_c(v) + sum_{v not in S} (t_a(v) - h_a(v)) h_c(v).
+// t_a - h_a is the miss count phi^miss of walks ending at v outside S; its
+// rounding error is bounded by the first term.  Every level up to 2a follows
+// from levels <= a, so ell* levels cost ceil(ell*/2) chain levels; the last
+// dense step applies the combination in its epilogue (OUT_COMBINE).
+//
+// On unweighted graphs the first two levels are integer walk counts
+// (h_i = alpha^i * count_i), pushed from the group's members with 64-bit
+// integer atomics (exact and order-free, so the result stays deterministic):
+//   count_1(y) = |N(y) ∩ S| outside S,        deg(y) on S
+//   count_2(x) = sum_{y in N(x)} count_1(y) outside S,   omega_2(x) on S
+// Members push deg(s) to their neighbours (level-2 paths through a member)
+// and every non-member y adjacent to S pushes count_1(y) to N(y) once, from a
+// worklist of (y, column, chunk) entries that splits long rows.  Everything a
+// tile touched is cleared by replaying the same traversal with stores of 0.
+#include <algorithm>
+#include <cstring>
+
+#include "ged_internal.h"
+
+namespace ged {
+
+constexpr int kWlChunk = 512;   // arcs per worklist entry (one wavefront)
+constexpr int kPushGrid = 2048; // blocks of the member kernels (grid-stride)
+constexpr int kWlGrid = 1024;   // blocks of the worklist kernels (4 waves each)
+
+bool split_ok(const ged_graph *g) { return g->flags == GED_UNDIRECTED; }
+
+SplitPlan split_plan(const ged_graph *g, int ell) {
+  SplitPlan p;
+  p.a = (ell + 1) / 2;
+  p.r = ell - p.a;
+  p.even = p.r == p.a;
+  p.s = g->weighted ? 0 : std::min(2, p.a - 1);
+  p.nlv = p.a - 1 - p.s;
+  return p;
+}
+
+size_t split_wl_need(const ged_graph *g, int64_t deg_sum) {
+  // distinct non-members y adjacent to the group (at most min(n, deg_sum)),
+  // each split into ceil(deg(y)/chunk) <= 1 + deg(y)/chunk entries, and the
+  // degrees of distinct vertices add up to at most nnz
+  return (size_t)std::min<int64_t>(g->n, deg_sum) + (size_t)(g->nnz / kWlChunk) + 1;
+}
+
+// --------------------------------------------------------------- kernels --
+
+// Exclusive prefix sum over the 64 lanes of a wavefront (all lanes active).
+__device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) {
+  const int lane = threadIdx.x & 63;
+  unsigned x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// Members of groups g0 .. g0+nc-1, one block per member: level-1 counts, the
+// level-2 contributions of paths through the member, and worklist entries for
+// the non-members they reach first.
+__global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
+                                                 const int *__restrict__ ci,
+                                                 const uint64_t *__restrict__ tmask,
+                                                 const int64_t *offsets, const int *members,
+                                                 const int *mcol, int g0, int nc, int C,
+                                                 unsigned long long *cnt1,
+                                                 unsigned long long *cnt2, uint64_t *wl,
+                                                 unsigned *wl_n, unsigned wl_cap) {
+  const int64_t jb = offsets[g0], je = offsets[g0 + nc];
+  for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
+    const int s = members[j];
+    const int c = mcol[j] - g0;
+    const int k0 = rp[s], k1 = rp[s + 1];
+    const unsigned long long ds = (unsigned long long)(k1 - k0);
+    for (int kb = k0; kb < k1; kb += kBlock) {  // same trip count for the whole block
+      const int k = kb + (int)threadIdx.x;
+      unsigned nch = 0;
+      int y = 0;
+      if (k < k1) {
+        y = ci[k];
+        const size_t o = (size_t)y * C + c;
+        const unsigned long long old = atomicAdd(&cnt1[o], 1ull);
+        if (cnt2) {
+          atomicAdd(&cnt2[o], ds);
+          if (old == 0ull && !((tmask[y] >> c) & 1ull))
+            nch = (unsigned)((rp[y + 1] - rp[y] + kWlChunk - 1) / kWlChunk);
+        }
+      }
+      if (cnt2) {
+        unsigned total;
+        const unsigned ex = wave_excl_scan(nch, &total);
+        unsigned base = 0;
+        if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(wl_n, total);
+        base = __shfl(base, 63, 64);
+        for (unsigned q = 0; q < nch; ++q) {
+          const unsigned at = base + ex + q;
+          if (at < wl_cap) wl[at] = ((uint64_t)(unsigned)y << 32) | ((uint64_t)c << 24) | q;
+        }
+      }
+    }
+  }
+}
+
+// Worklist entries, one wavefront each: count_1(y) goes to every x in one
+// chunk of N(y) (value 0 with clear = 1 stores zeros instead).
+template <bool CLEAR>
+__global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
+                                                    const int *__restrict__ ci, int C,
+                                                    const unsigned long long *cnt1,
+                                                    unsigned long long *cnt2, const uint64_t *wl,
+                                                    const unsigned *wl_n, unsigned wl_cap) {
+  const unsigned count = min(*wl_n, wl_cap);
+  const int lane = threadIdx.x & 63;
+  const unsigned nwaves = (gridDim.x * kBlock) >> 6;
+  for (unsigned i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < count; i += nwaves) {
+    const uint64_t e = wl[i];
+    const int y = (int)(e >> 32);
+    const int c = (int)((e >> 24) & 0xffu);
+    const int q = (int)(e & 0xffffffu);
+    const int j0 = rp[y] + q * kWlChunk, j1 = min(j0 + kWlChunk, rp[y + 1]);
+    if (CLEAR) {
+      for (int j = j0 + lane; j < j1; j += 64) cnt2[(size_t)ci[j] * C + c] = 0ull;
+    } else {
+      const unsigned long long v = cnt1[(size_t)y * C + c];
+      for (int j = j0 + lane; j < j1; j += 64) atomicAdd(&cnt2[(size_t)ci[j] * C + c], v);
+    }
+  }
+}
+
+// Member rows hold the unrestricted counts: deg(s) and omega_2(s).
+__global__ void k_fix_members(const int *__restrict__ rp,
+                              const unsigned long long *__restrict__ omega2,
+                              const int64_t *offsets, const int *members, const int *mcol,
+                              int g0, int nc, int C, unsigned long long *cnt1,
+                              unsigned long long *cnt2) {
+  const int64_t jb = offsets[g0], je = offsets[g0 + nc];
+  for (int64_t j = jb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < je;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int s = members[j];
+    const size_t o = (size_t)s * C + (mcol[j] - g0);
+    cnt1[o] = (unsigned long long)(rp[s + 1] - rp[s]);
+    if (cnt2) cnt2[o] = omega2[s];
+  }
+}
+
+// Zero every count entry k_push / k_fix_members wrote for these members.
+__global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict__ rp,
+                                                          const int *__restrict__ ci,
+                                                          const int64_t *offsets,
+                                                          const int *members, const int *mcol,
+                                                          int g0, int nc, int C,
+                                                          unsigned long long *cnt1,
+                                                          unsigned long long *cnt2) {
+  const int64_t jb = offsets[g0], je = offsets[g0 + nc];
+  for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
+    const int s = members[j];
+    const int c = mcol[j] - g0;
+    if (threadIdx.x == 0) {
+      cnt1[(size_t)s * C + c] = 0ull;
+      if (cnt2) cnt2[(size_t)s * C + c] = 0ull;
+    }
+    for (int k = rp[s] + (int)threadIdx.x; k < rp[s + 1]; k += kBlock) {
+      const size_t o = (size_t)ci[k] * C + c;
+      cnt1[o] = 0ull;
+      if (cnt2) cnt2[o] = 0ull;
+    }
+  }
+}
+
+// omega_2(v) = sum_{u in N(v)} deg(u): walks of length 2 ending at v.
+__global__ void k_omega2(const int *__restrict__ rp, const int *__restrict__ ci, int n,
+                         unsigned long long *out) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    unsigned long long s = 0;
+    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+      const int u = ci[k];
+      s += (unsigned long long)(rp[u + 1] - rp[u]);
+    }
+    out[v] = s;
+  }
+}
+
+// tr(v) = sum_{c=1..r} t_c(v), added in level order.
+__global__ void k_sum_t(const double *__restrict__ T, int64_t n, int r, double *out) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 1; c <= r; ++c) s += T[(size_t)c * n + v];
+    out[v] = s;
+  }
+}
+
+// ------------------------------------------------------------------ host --
+
+static int grid_for(int64_t items, int cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
+}
+
+void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st) {
+  const int64_t n = g->n;
+  const int eg = (int)std::min<int64_t>(8192, (n + kBlock - 1) / kBlock);
+  if (pl.s >= 2 && !g->omega2_ready) {
+    g->omega2.ensure(sizeof(uint64_t) * (size_t)n);
+    hipLaunchKernelGGL(k_omega2, dim3(eg), dim3(kBlock), 0, st, g->rp.as<const int>(),
+                       g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>());
+    GED_HIP(hipGetLastError());
+    g->omega2_ready = true;
+  }
+  PrepCache &pc = g->prep;
+  if (pc.tr_r != pl.r) {
+    pc.tr.ensure(sizeof(double) * (size_t)n);
+    hipLaunchKernelGGL(k_sum_t, dim3(eg), dim3(kBlock), 0, st, pc.t_levels.as<const double>(),
+                       n, pl.r, pc.tr.as<double>());
+    GED_HIP(hipGetLastError());
+    pc.tr_r = pl.r;
+  }
+}
+
+void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
+               hipStream_t st) {
+  const size_t nC = (size_t)g->n * C;
+  Partition &p = partition(g, C);
+  w.ws.fit(p);
+  if (pl.s >= 1) {
+    const size_t cb = sizeof(uint64_t) * nC;
+    if (w.cnt1.bytes < cb || w.cnt2.bytes < cb) {
+      w.cnt1.ensure(cb);
+      w.cnt2.ensure(cb);
+      w.zero = false;
+    }
+    if (!w.zero || w.cnt_elems != nC) {
+      launch_fill_i32(w.cnt1.as<int>(), 0, w.cnt1.bytes / sizeof(int), st);
+      launch_fill_i32(w.cnt2.as<int>(), 0, w.cnt2.bytes / sizeof(int), st);
+      w.wl_n.ensure(sizeof(unsigned));
+      launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
+      w.cnt_elems = nC;
+      w.zero = true;
+    }
+    if (pl.s >= 2 && (wl_need > w.wl_cap || !w.wl.p)) {
+      size_t cap = std::max<size_t>(wl_need, 2 * (size_t)w.wl_cap);
+      cap = std::min<size_t>(cap, 0xffffffffu);
+      w.wl.ensure(sizeof(uint64_t) * cap);
+      w.wl_cap = (unsigned)cap;
+    }
+  }
+  if (pl.nlv > 0) w.lv.ensure(sizeof(double) * nC * (size_t)pl.nlv);
+}
+
+void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
+                        const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
+                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st) {
+  const int64_t n = g->n;
+  const size_t nC = (size_t)n * C;
+  const PrepCache &pc = g->prep;
+  const double alpha = pc.alpha;
+  Partition &p = partition(g, C);
+  const double *T = pc.t_levels.as<const double>();
+  const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
+  unsigned long long *c1 = pl.s >= 1 ? w.cnt1.as<unsigned long long>() : nullptr;
+  unsigned long long *c2 = pl.s >= 2 ? w.cnt2.as<unsigned long long>() : nullptr;
+  const int mgrid = grid_for(tile_members, kPushGrid);
+  launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
+  if (pl.s >= 1) {
+    hipLaunchKernelGGL(k_push, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, tmask, offs, mem, mcol,
+                       g0, nc, C, c1, c2, w.wl.as<uint64_t>(), w.wl_n.as<unsigned>(), w.wl_cap);
+    GED_HIP(hipGetLastError());
+    if (c2) {
+      hipLaunchKernelGGL(k_push_wl<false>, dim3(kWlGrid), dim3(kBlock), 0, st, rp, ci, C, c1, c2,
+                         w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
+      GED_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fix_members, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
+                       dim3(kBlock), 0, st, rp, g->omega2.as<const unsigned long long>(), offs,
+                       mem, mcol,
+                       g0, nc, C, c1, c2);
+    GED_HIP(hipGetLastError());
+  }
+  double lv_scale = alpha;  // alpha^(s+1) for the first dense level after the counts
+  for (int i = 0; i < pl.s; ++i) lv_scale *= alpha;
+  double *lv = w.lv.as<double>();
+  StepArgs a = base_args(g);
+  w.ws.into(a);
+  a.C = C;
+  a.tmask = tmask;
+  a.accum = 0;
+  for (int i = pl.s + 1; i <= pl.a; ++i) {
+    int in;
+    if (i == 1) {
+      in = IN_TILEMASK;
+      a.alpha = alpha;
+    } else if (i == pl.s + 1) {
+      in = IN_CNT;
+      a.Xc = reinterpret_cast<const uint64_t *>(pl.s == 1 ? c1 : c2);
+      a.alpha = lv_scale;
+    } else {
+      in = IN_VEC;
+      a.X = lv + (size_t)(i - 2 - pl.s) * nC;
+      a.alpha = alpha;
+    }
+    a.inj = T + (size_t)i * n;
+    if (i < pl.a) {
+      a.Y = lv + (size_t)(i - 1 - pl.s) * nC;
+      run_step(g, p, a, in, OUT_TILE, st);
+    } else {
+      a.Y = nullptr;
+      a.tr = pc.tr.as<const double>();
+      a.q_cnt1 = reinterpret_cast<const uint64_t *>(c1);
+      a.q_cnt2 = reinterpret_cast<const uint64_t *>(c2);
+      a.q_s1 = alpha;
+      a.q_s2 = alpha * alpha;
+      a.q_lv = lv;
+      a.q_nlv = pl.nlv;
+      a.q_even = pl.even ? 1 : 0;
+      run_step(g, p, a, in, OUT_COMBINE, st, pl.s + pl.nlv);
+    }
+  }
+  launch_reduce(p, a, out, nullptr, nullptr, st, w.ws.scratch());
+  if (pl.s >= 1) {
+    if (c2) {
+      hipLaunchKernelGGL(k_push_wl<true>, dim3(kWlGrid), dim3(kBlock), 0, st, rp, ci, C, c1, c2,
+                         w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
+      GED_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_clear_members, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem, mcol,
+                       g0, nc, C, c1, c2);
+    GED_HIP(hipGetLastError());
+    if (c2) launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
+  }
+  launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
+}
+
+int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> &out) {
+  if (g->stamp.size() != (size_t)g->n) {
+    g->stamp.assign((size_t)g->n, 0u);
+    g->stamp_gen = 0;
+  }
+  if (++g->stamp_gen == 0) {
+    std::fill(g->stamp.begin(), g->stamp.end(), 0u);
+    g->stamp_gen = 1;
+  }
+  const uint32_t gen = g->stamp_gen;
+  int64_t deg_sum = 0;
+  for (int64_t q = 0; q < len; ++q) {
+    const int v = g->new_id[S[q]];
+    if (g->stamp[v] == gen) continue;
+    g->stamp[v] = gen;
+    out.push_back(v);
+    deg_sum += g->h_rp[v + 1] - g->h_rp[v];
+  }
+  return deg_sum;
+}
+
+// ------------------------------------------------------- single group --
+
+static void drop_exec(ged_graph *g) {
+  if (g->score_exec) (void)hipGraphExecDestroy(g->score_exec);
+  if (g->score_graph) (void)hipGraphDestroy(g->score_graph);
+  g->score_exec = nullptr;
+  g->score_graph = nullptr;
+  g->score_sig.clear();
+}
+
+int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
+  hipStream_t st = g->stream;
+  const int64_t n = g->n;
+  const SplitPlan pl = split_plan(g, g->prep.ell);
+  std::vector<int> mem;
+  mem.reserve((size_t)s_len);
+  const int64_t deg_sum = map_group(g, S, s_len, mem);
+  const int len = (int)mem.size();
+  if (len > g->split_cap) {
+    int cap = std::max(256, g->split_cap);
+    while (cap < len) cap *= 2;
+    const size_t bytes = 2 * sizeof(int64_t) + 2 * sizeof(int) * (size_t)cap;
+    g->split_in.ensure(bytes);
+    g->split_in_host.ensure(bytes);
+    // mcol: every member is in column 0
+    launch_fill_i32(reinterpret_cast<int *>(g->split_in.as<char>() + 2 * sizeof(int64_t)) + cap,
+                    0, (size_t)cap, st);
+    g->split_cap = cap;
+  }
+  if (!g->split_tmask.p || g->split_tmask.bytes < sizeof(uint64_t) * (size_t)n) {
+    g->split_tmask.ensure(sizeof(uint64_t) * (size_t)n);
+    g->split_tmask_ready = false;
+  }
+  if (!g->split_tmask_ready) {
+    launch_fill_i32(g->split_tmask.as<int>(), 0, (size_t)n * 2, st);
+    g->split_tmask_ready = true;
+  }
+  split_tables(g, pl, st);
+  split_fit(g, g->split_ws, pl, 1, split_wl_need(g, deg_sum), st);
+  g->acc.ensure(sizeof(double) * 64);
+  g->out_host.ensure(64);
+  const int cap = g->split_cap;
+  char *hb = g->split_in_host.as<char>();
+  int64_t offs[2] = {0, len};
+  std::memcpy(hb, offs, sizeof(offs));
+  std::memcpy(hb + sizeof(offs), mem.data(), sizeof(int) * (size_t)len);
+  GED_HIP(hipMemcpyAsync(g->split_in.p, hb, sizeof(offs) + sizeof(int) * (size_t)len,
+                         hipMemcpyHostToDevice, st));
+  const int64_t *d_offs = g->split_in.as<const int64_t>();
+  const int *d_mem = reinterpret_cast<const int *>(g->split_in.as<char>() + sizeof(offs));
+  const int *d_mcol = d_mem + cap;
+  SplitWs &w = g->split_ws;
+  auto enqueue = [&]() {
+    enqueue_split_tile(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, g->split_tmask.as<uint64_t>(),
+                       g->acc.as<double>(), st);
+  };
+  w.zero = false;
+  if (g->prof.on) {
+    enqueue();
+  } else {
+    double ab = g->prep.alpha;
+    const void *abits;
+    std::memcpy(&abits, &ab, sizeof(ab));
+    std::vector<const void *> sig = {
+        g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.ws.blk.p, w.ws.seg.p,
+        w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
+        g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
+        (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
+        (const void *)(intptr_t)1 /* split */};
+    if (g->score_exec && sig != g->score_sig) drop_exec(g);
+    if (!g->score_exec) {
+      GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue();
+      } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(st, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+      }
+      GED_HIP(hipStreamEndCapture(st, &g->score_graph));
+      GED_HIP(hipGraphInstantiate(&g->score_exec, g->score_graph, nullptr, nullptr, 0));
+      g->score_sig = sig;
+    }
+    GED_HIP(hipGraphLaunch(g->score_exec, st));
+  }
+  double *ho = g->out_host.as<double>();
+  GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  GED_HIP(hipStreamSynchronize(st));
+  w.zero = true;
+  *out = ho[0];
+  return GED_OK;
+}
+
+}  // namespace ged

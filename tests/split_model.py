@@ -1,0 +1,108 @@
+"""CPU model of split scoring (test helper, numpy).
+
+Mirrors the steps the HIP split path takes for an undirected graph, so the
+design can be checked on the host against the oracle and against exact walk
+enumeration: integer pushes for levels 1..s, dense levels s+1..a with member
+injection, and the combination of the last level a = ceil(ell/2) with the
+lower ones,
+
+    phi_{a+c}(S) = sum_v h_a(v) t_c(v) + sum_{v not in S} (t_a(v) - h_a(v)) h_c(v),
+
+which holds because on an undirected graph a walk of length c leaving v is the
+reversal of one ending at v.  Independent of the oracle (shares no code).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _spmv(row_ptr, col_idx, w, x):
+    """y(v) = sum over the in-row of v of w * x(u)."""
+    n = len(row_ptr) - 1
+    y = np.zeros(n)
+    for v in range(n):
+        j0, j1 = int(row_ptr[v]), int(row_ptr[v + 1])
+        if j1 > j0:
+            vals = x[col_idx[j0:j1]]
+            if w is not None:
+                vals = vals * w[j0:j1]
+            y[v] = vals.sum()
+    return y
+
+
+def plan(ell: int, weighted: bool):
+    a = (ell + 1) // 2
+    r = ell - a
+    s = 0 if weighted else min(2, a - 1)
+    return a, r, s
+
+
+def push_counts(row_ptr, col_idx, S, s_levels):
+    """Level-1/2 integer counts by pushes from the members, as the kernels do."""
+    n = len(row_ptr) - 1
+    deg = np.diff(row_ptr).astype(np.int64)
+    inS = np.zeros(n, dtype=bool)
+    inS[S] = True
+    cnt1 = np.zeros(n, dtype=np.int64)
+    cnt2 = np.zeros(n, dtype=np.int64)
+    claimed = []
+    for m in S:
+        for y in col_idx[row_ptr[m]:row_ptr[m + 1]]:
+            old = cnt1[y]
+            cnt1[y] += 1
+            if s_levels >= 2:
+                cnt2[y] += deg[m]
+                if old == 0 and not inS[y]:
+                    claimed.append(int(y))
+    if s_levels >= 2:
+        for y in claimed:
+            for x in col_idx[row_ptr[y]:row_ptr[y + 1]]:
+                cnt2[x] += cnt1[y]
+    # member rows hold the unrestricted walk counts
+    cnt1[inS] = deg[inS]
+    if s_levels >= 2:
+        omega2 = np.array([deg[col_idx[row_ptr[v]:row_ptr[v + 1]]].sum() for v in range(n)],
+                          dtype=np.int64)
+        cnt2[inS] = omega2[inS]
+    return cnt1, cnt2
+
+
+def split_score(row_ptr, col_idx, S, alpha: float, ell: int, w=None) -> float:
+    n = len(row_ptr) - 1
+    S = np.unique(np.asarray(S, dtype=np.int64))
+    if S.size == 0:
+        return 0.0
+    inS = np.zeros(n, dtype=bool)
+    inS[S] = True
+    T = [np.ones(n)]
+    for _ in range(ell):
+        T.append(alpha * _spmv(row_ptr, col_idx, w, T[-1]))
+    a, r, s = plan(ell, w is not None)
+    H = {}
+    cnt1 = cnt2 = None
+    if s >= 1:
+        cnt1, cnt2 = push_counts(row_ptr, col_idx, S, s)
+        H[1] = alpha * cnt1.astype(np.float64)
+        if s >= 2:
+            H[2] = (alpha * alpha) * cnt2.astype(np.float64)
+    for i in range(s + 1, a + 1):
+        if i == 1:
+            x, scale = inS.astype(np.float64), alpha
+        elif i == s + 1:
+            x = (cnt1 if s == 1 else cnt2).astype(np.float64)
+            scale = alpha ** (s + 1)
+        else:
+            x, scale = H[i - 1], alpha
+        y = scale * _spmv(row_ptr, col_idx, w, x)
+        y[inS] = T[i][inS]
+        H[i] = y
+    q = np.zeros(n)
+    for i in range(1, a):
+        q = q + H[i]
+    ha = H[a]
+    tr = np.zeros(n)
+    for c in range(1, r + 1):
+        tr = tr + T[c]
+    rs = q + ha if r == a else q
+    contrib = (q + ha) + ha * tr + np.where(inS, 0.0, (T[a] - ha) * rs)
+    return float(contrib.sum())

@@ -311,3 +311,42 @@ def test_stochastic_greedy_parity(ged):
         ro = oracle.greedy(g, 8, alpha, EPS, stochastic=True, eta=eta, seed=seed)
         compare_greedy(rg, ro, f"stochastic eta={eta}")
     gg.close()
+
+
+@pytest.mark.parametrize("name", ["er", "ba", "weighted"])
+def test_split_ell_sweep(ged, name):
+    """Split scoring for every plan shape: ell* = 1..9 (a = 1, 2, 3+; odd and
+    even ell; integer levels s = 0, 1, 2; weighted has s = 0), single and
+    batched, against the oracle."""
+    if name == "er":
+        g, w = inputs.erdos_renyi(3000, 12000, 51), None
+    else:
+        g, w = inputs.barabasi_albert(4000, 4, 52), None
+        if name == "weighted":
+            deg = g.degrees.astype(np.float64)
+            rows = np.repeat(np.arange(g.n), g.degrees)
+            w = 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+    say(f"[split sweep] {name} n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g, weights=w)
+    alpha = 0.9 * oracle.default_alpha(g, w)
+    sizes = [(1, 1), (2, 7), (3, 60), (4, 700), (5, g.n)]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    groups = [inputs.group(g.n, size, seed) for seed, size in sizes]
+    for j, S in enumerate(groups):
+        off[j + 1] = off[j] + S.size
+    mem = np.concatenate(groups).astype(np.int32)
+    for ell in range(1, 10):
+        B = oracle.comb_bound(g, alpha, ell, w)
+        eps = 4.0 * B if ell == 1 else float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, w)))
+        say(f"  ell={ell} eps={eps:.3e}")
+        ref = []
+        for S in groups:
+            c, ell_o, _, _ = oracle.score(g, S, alpha, eps, w=w)
+            assert ell_o == ell
+            s, ell_g, _ = gg.score(S, alpha, eps, with_info=True)
+            assert ell_g == ell and rel(s, c) <= REL, (name, ell, S.size, s, c)
+            ref.append(c)
+        b = gg.score_batch(off, mem, alpha, eps)
+        for j, c in enumerate(ref):
+            assert rel(b[j], c) <= REL, (name, ell, j, b[j], c)
+    gg.close()

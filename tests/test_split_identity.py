@@ -1,0 +1,109 @@
+"""The split identity behind split scoring, checked without the GPU.
+
+* exactly, by enumerating every walk of tiny undirected graphs;
+* that it fails on a directed graph (why directed graphs keep the
+  level-by-level chain);
+* the push formulation of the level-1/2 counts against enumeration;
+* the whole split scheme (tests/split_model.py) against the oracle for every
+  plan shape (a = 1, 2, 3+, odd and even ell, weighted).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from exact import WalkTable
+from paper_1910_13874_amd import inputs
+from split_model import push_counts, split_score
+
+
+def tiny_graph(n, m, seed):
+    rng = np.random.default_rng(seed)
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    keep = src != dst
+    return inputs.from_edges(n, src[keep], dst[keep], symmetrize=True)
+
+
+def hit_end(tab, i, S, v):
+    """# i-walks ending at v that contain a vertex of S."""
+    m = tab._mask(S)
+    return sum(c for (_, e, mk), c in tab.tab[i].items() if e == v and mk & m)
+
+
+def all_end(tab, i, v):
+    return sum(c for (_, e, _), c in tab.tab[i].items() if e == v)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_split_identity_exact(seed):
+    g = tiny_graph(7, 11, seed)
+    tab = WalkTable(g.n, g.row_ptr, g.col_idx, 6)
+    rng = np.random.default_rng(seed)
+    for S in ([0], [1, 4], list(rng.choice(g.n, 3, replace=False))):
+        S = [int(s) for s in S]
+        for a in range(0, 4):
+            for c in range(0, 7 - a):
+                H_a = [hit_end(tab, a, S, v) for v in range(g.n)]
+                H_c = [hit_end(tab, c, S, v) for v in range(g.n)]
+                T_a = [all_end(tab, a, v) for v in range(g.n)]
+                T_c = [all_end(tab, c, v) for v in range(g.n)]
+                rhs = sum(H_a[v] * T_c[v] for v in range(g.n))
+                rhs += sum((T_a[v] - H_a[v]) * H_c[v] for v in range(g.n) if v not in S)
+                assert tab.phi(a + c, S) == rhs, (seed, S, a, c)
+
+
+def test_split_identity_fails_directed():
+    # arcs 0 -> 1, 2 -> 1, 1 -> 3 and S = {3}: both 2-walks (0-1-3, 2-1-3)
+    # meet S, but the split at a = c = 1 sees one walk of length 1 ending at
+    # 1 that meets S (none) and one ending at 3 (1-3), and the walks of length
+    # 1 ending at v do not stand for those leaving v.
+    g = inputs.from_edges(4, np.array([0, 2, 1], np.int32), np.array([1, 1, 3], np.int32),
+                          symmetrize=False)
+    tab = WalkTable(g.n, g.row_ptr, g.col_idx, 2)
+    S = [3]
+    H1 = [hit_end(tab, 1, S, v) for v in range(g.n)]
+    T1 = [all_end(tab, 1, v) for v in range(g.n)]
+    rhs = sum(H1[v] * T1[v] for v in range(g.n)) + sum(
+        (T1[v] - H1[v]) * H1[v] for v in range(g.n) if v not in S)
+    assert tab.phi(2, S) == 2 and rhs == 1
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_push_counts_match_enumeration(seed):
+    g = tiny_graph(8, 14, seed)
+    tab = WalkTable(g.n, g.row_ptr, g.col_idx, 2)
+    for S in ([0], [2, 5], [1, 3, 6, 7]):
+        cnt1, cnt2 = push_counts(g.row_ptr, g.col_idx, np.array(S), 2)
+        for v in range(g.n):
+            assert cnt1[v] == hit_end(tab, 1, S, v), (S, v)
+            assert cnt2[v] == hit_end(tab, 2, S, v), (S, v)
+
+
+def eps_for(g, alpha, ell, w=None):
+    """An eps whose ell* is exactly `ell` (geometric mean of consecutive bounds)."""
+    B = oracle.comb_bound(g, alpha, ell, w)
+    if ell == 1:
+        return 4.0 * B
+    return float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, w)))
+
+
+@pytest.mark.parametrize("name", ["er", "ba", "weighted"])
+def test_split_model_matches_oracle(name):
+    if name == "er":
+        g, w = inputs.erdos_renyi(300, 900, 41), None
+    else:
+        g = inputs.barabasi_albert(300, 3, 42)
+        w = None
+        if name == "weighted":
+            deg = g.degrees.astype(np.float64)
+            rows = np.repeat(np.arange(g.n), g.degrees)
+            w = 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+    alpha = 0.9 * oracle.default_alpha(g, w)
+    for ell in range(1, 10):
+        eps = eps_for(g, alpha, ell, w)
+        for seed, size in [(1, 1), (2, 7), (3, 60), (4, g.n)]:
+            S = inputs.group(g.n, size, seed)
+            c, ell_o, _, _ = oracle.score(g, S, alpha, eps, w=w)
+            assert ell_o == ell
+            m = split_score(g.row_ptr, g.col_idx, S, alpha, ell, w)
+            assert abs(m - c) <= 1e-12 * abs(c), (name, ell, size, m, c)
