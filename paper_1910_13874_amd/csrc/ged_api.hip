@@ -46,14 +46,15 @@ StepArgs base_args(ged_graph *g, bool reverse) {
   return a;
 }
 
-double algo_bytes(const ged_graph *g, int C, int in, int out, int extra_rows) {
+double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows) {
   const double n = (double)g->n, nnz = (double)g->nnz;
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
-  if (out != OUT_COMBINE) b += 8.0 * n * C;  // Y
+  if (out != OUT_COMBINE && out != OUT_COMBINE32) b += 8.0 * n * C;  // Y
   if (g->weighted) b += 8.0 * nnz;
   switch (in) {
     case IN_VEC:
     case IN_CNT: b += 8.0 * n * C; break;
+    case IN_CNT32: b += 4.0 * n * C; break;
     case IN_MASK:
     case IN_NOTMASK: b += n / 8.0; break;
     case IN_TILEMASK: b += 8.0 * n; break;
@@ -67,7 +68,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, int extra_rows) {
     case OUT_TILE:
     case OUT_POOL: b += 8.0 * n; break;
     case OUT_GAIN: b += n / 8.0 + 4.0 * n; break;
-    case OUT_COMBINE: b += 8.0 * n * 3; break;  // tmask, t_a, tr
+    case OUT_COMBINE:
+    case OUT_COMBINE32: b += 8.0 * n * 3; break;  // tmask, t_a, tr
     default: break;
   }
   return b + 8.0 * n * C * extra_rows;
@@ -105,7 +107,7 @@ static hipEvent_t prof_event(ged_graph *g) {
 }
 
 void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int out,
-              hipStream_t st, int extra_rows) {
+              hipStream_t st, double extra_rows) {
   if (!g->prof.on) {
     launch_step(p, a, in, out, st);
     return;

@@ -113,6 +113,48 @@ static int autotune_tile(ged_graph *g, BatchWs &b) {
   return best_c;
 }
 
+// Split scoring: the same race over the dense levels of a split tile (the
+// level-(s+1) step on count rows and the combining step), at C = 8..64.
+static int autotune_split(ged_graph *g, BatchWs &b, const SplitPlan &pl) {
+  if (g->batch_tile > 0) return g->batch_tile;
+  hipStream_t st = g->stream;
+  const int cands[] = {8, 16, 32, 64};
+  double best = 1e300;
+  int best_c = 16;
+  hipEvent_t e0, e1;
+  GED_HIP(hipEventCreate(&e0));
+  GED_HIP(hipEventCreate(&e1));
+  for (int C : cands) {
+    try {
+      split_fit(g, b.sw, pl, C, 1, st);
+      for (int r = 0; r < 2; ++r) {
+        if (r == 1) GED_HIP(hipEventRecord(e0, st));
+        split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);
+      }
+      GED_HIP(hipEventRecord(e1, st));
+      GED_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      GED_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const double per_col = ms / C;
+      if (per_col < best) {
+        best = per_col;
+        best_c = C;
+      }
+    } catch (const HipError &e) {
+      if (e.code != GED_ERR_NOMEM) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+      }
+      break;  // wider tiles do not fit
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g->batch_tile = best_c;
+  return best_c;
+}
+
 static void enqueue_batch(ged_graph *g, BatchWs &b, int G, int C, hipStream_t st) {
   const int64_t n = g->n;
   const PrepCache &pc = g->prep;
@@ -162,8 +204,13 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
     launch_fill_i32(b.tmask.as<int>(), 0, (size_t)n * 2, st);
     b.tmask_ready = true;
   }
-  const int C = autotune_tile(g, b);
   const bool split = split_ok(g);
+  SplitPlan pl;
+  if (split) {
+    pl = split_plan(g, g->prep.ell);
+    split_tables(g, pl, st);
+  }
+  const int C = split ? autotune_split(g, b, pl) : autotune_tile(g, b);
   Partition &p = partition(g, C);
   b.ws.fit(p);
   // internal ids, duplicates inside a group dropped; column of every member
@@ -202,16 +249,13 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
     GED_HIP(hipMemcpyAsync(b.mcol.p, hcol.data(), sizeof(int) * (size_t)Md,
                            hipMemcpyHostToDevice, st));
   }
-  SplitPlan pl;
   if (split) {
-    pl = split_plan(g, g->prep.ell);
     size_t wl_need = 1;
     for (int g0 = 0; g0 < G; g0 += C) {
       size_t need = 0;
       for (int j = g0; j < std::min(G, g0 + C); ++j) need += split_wl_need(g, degsum[j]);
       wl_need = std::max(wl_need, need);
     }
-    split_tables(g, pl, st);
     split_fit(g, b.sw, pl, C, wl_need, st);
     b.sw.zero = false;
   } else {

@@ -128,7 +128,8 @@ enum InMode : int {
   IN_TILEMASK = 4, // bit c of tmask[u]     (batched hit chains, level 0)
   IN_ONEHOT = 5,   // [cand_col[u] == c]    (gain chains, level 0)
   IN_FRESH = 6,    // fresh[c] ? bit c of tmask[u] : X[u*C+c]   (serving pool)
-  IN_CNT = 7       // Xc[u*C + c] (integer walk counts, exact in FP64 below 2^53)
+  IN_CNT = 7,      // Xc[u*C + c] (integer walk counts, exact in FP64 below 2^53)
+  IN_CNT32 = 8     // Xc32[u*C + c] (the same counts, 32-bit)
 };
 
 // Row epilogue of a step (what y(v) becomes).
@@ -139,8 +140,9 @@ enum OutMode : int {
   OUT_TILE = 3,  // bit c of tmask[v] ? inj[v] : alpha * sum        (batched hit chains)
   OUT_GAIN = 4,  // v in S ? 0 : (cand_col[v] == c ? inj[v] : alpha * sum)  (gain chains)
   OUT_POOL = 5,  // bit c of tmask[v] ? inj[step[c]*n + v] : alpha * sum   (serving pool)
-  OUT_COMBINE = 6 // y as OUT_TILE, not stored; the column sum takes the split
-                  // combination of y with the stored lower levels (split scoring)
+  OUT_COMBINE = 6, // y as OUT_TILE, not stored; the column sum takes the split
+                   // combination of y with the stored lower levels (split scoring)
+  OUT_COMBINE32 = 7 // the same with 32-bit count levels
 };
 
 struct StepArgs {
@@ -162,15 +164,19 @@ struct StepArgs {
   double *blk_part = nullptr;    // [n_blocks*C] block column sums
   double *seg_out = nullptr;     // [n_segs*C] raw segment sums
   double *long_part = nullptr;   // [n_long*C] long-row outputs (for column sums)
-  // IN_CNT source
-  const uint64_t *Xc = nullptr;  // [n*C]
-  // OUT_COMBINE: per row v and column c the column sum takes
+  // IN_CNT / IN_CNT32 source
+  const uint64_t *Xc = nullptr;    // [n*C]
+  const uint32_t *Xc32 = nullptr;  // [n*C]
+  // OUT_COMBINE(32): per row v and column c the column sum takes
   //   q + y + y*tr[v] + [v not in S](inj[v] - y) * (q_even ? q + y : q),
-  // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c]
+  // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c].
+  // Every pointer is valid: an absent input is read at index (o & mask) = 0
+  // of some valid buffer and weighted by 0, so the loads are unconditional.
   const double *tr = nullptr;       // [n]
-  const uint64_t *q_cnt1 = nullptr; // [n*C] or null
-  const uint64_t *q_cnt2 = nullptr; // [n*C] or null
-  double q_s1 = 0, q_s2 = 0;
+  const void *q_cnt1 = nullptr;     // [n*C] uint64 (uint32 for OUT_COMBINE32)
+  const void *q_cnt2 = nullptr;
+  uint64_t q_m1 = 0, q_m2 = 0, q_mlv = 0;  // index masks: ~0 present, 0 absent
+  double q_s1 = 0, q_s2 = 0, q_slv = 0;    // weights (q_slv = 1 if q_nlv > 0)
   const double *q_lv = nullptr;     // [q_nlv * n * C]
   int q_nlv = 0;
   int q_even = 0;
@@ -245,14 +251,16 @@ struct PrepCache {
 struct SplitPlan {
   int a = 0, r = 0, s = 0, nlv = 0;  // nlv = dense levels stored (s+1 .. a-1)
   bool even = false;                 // r == a
+  bool c32 = false;                  // counts fit 32 bits (max degree < 2^16)
 };
 
 struct SplitWs {
-  DBuf cnt1, cnt2;       // uint64 [n*C] walk counts of levels 1, 2; zero between tiles
+  DBuf cnt1, cnt2;       // [n*C] walk counts of levels 1, 2 (uint32 or uint64); zero
+                         // between tiles
   DBuf lv;               // double [nlv*n*C] stored dense levels
   DBuf wl, wl_n;         // uint64 worklist [wl_cap], uint32 length
   unsigned wl_cap = 0;
-  size_t cnt_elems = 0;  // n*C the count arrays were zeroed for
+  size_t cnt_bytes = 0;  // bytes of the count layout the arrays were zeroed for
   bool zero = false;
   StepWs ws;
 };
@@ -343,11 +351,12 @@ StepArgs base_args(ged_graph *g, bool reverse = false);
 // Step launch, timed with HIP events around the main kernel when profiling is
 // on for the graph (the only way library code launches walk-count steps).
 void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in_mode, int out_mode,
-              hipStream_t st, int extra_rows = 0);
+              hipStream_t st, double extra_rows = 0);
 // Algorithmic bytes of one step launch: row_ptr, col_idx (+ weights), the
 // gathered input, the written output, the epilogue's mask reads and
-// `extra_rows` further C-wide rows per vertex that the epilogue streams.
-double algo_bytes(const ged_graph *g, int C, int in_mode, int out_mode, int extra_rows = 0);
+// `extra_rows` further C-wide rows of 8-byte values per vertex that the
+// epilogue streams.
+double algo_bytes(const ged_graph *g, int C, int in_mode, int out_mode, double extra_rows = 0);
 int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
                 double *out, ged_score_info *info);
 // Drop the batched-scoring workspace of a graph that is being destroyed.
@@ -364,6 +373,10 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
                hipStream_t st);
 // Worklist entries a group needs: min(n, sum of member degrees) + ceil(nnz/chunk).
 size_t split_wl_need(const ged_graph *g, int64_t deg_sum);
+// Dense levels s+1..a of a tile (the last one combining into the block
+// partials of w.ws); the counts of levels <= s must be in place.
+void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
+                 hipStream_t st);
 // Enqueue one tile of nc <= C groups (g0 .. g0+nc-1 of the device offsets /
 // members / mcol arrays); scores go to out[0..nc).
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,

@@ -21,6 +21,7 @@
 //     in a fixed order.
 // No floating-point atomics anywhere, so results are bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "ged_internal.h"
 
@@ -46,8 +47,10 @@ __device__ __forceinline__ double load_in(const StepArgs &a, int u, int c) {
     return (a.cand_col[u] == c) ? 1.0 : 0.0;
   } else if constexpr (IN == IN_FRESH) {
     return a.fresh[c] ? (((a.tmask[u] >> c) & 1ull) ? 1.0 : 0.0) : a.X[(size_t)u * C + c];
-  } else {  // IN_CNT
+  } else if constexpr (IN == IN_CNT) {
     return (double)a.Xc[(size_t)u * C + c];
+  } else {  // IN_CNT32
+    return (double)a.Xc32[(size_t)u * C + c];
   }
 }
 
@@ -63,7 +66,7 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
     return inS ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_ZERO) {
     return inS ? 0.0 : y;
-  } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE) {
+  } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
@@ -83,23 +86,45 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
 // c = 1..r and added to levels 1..a, the row's share of the truncated score
 // (Alg. "GED-Walk Computation") is
 //   sum_{i<a} h_i + h_a + h_a * sum_{c<=r} t_c + [v not in S](t_a - h_a) * sum_{c<=r} h_c.
-template <int C>
-__device__ __forceinline__ double combine_contrib(const StepArgs &a, int v, int c, double y,
-                                                  bool inS) {
-  const size_t o = (size_t)v * C + c;
-  double q = 0.0;
-  if (a.q_cnt1) q += a.q_s1 * (double)a.q_cnt1[o];
-  if (a.q_cnt2) q += a.q_s2 * (double)a.q_cnt2[o];
-  for (int l = 0; l < a.q_nlv; ++l) q += a.q_lv[(size_t)l * a.n * C + o];
+// Raw inputs of the combination for row v, column c: the two count levels,
+// the first stored dense level, sum_{c<=r} t_c(v) and t_a(v).  Loads only, so
+// they can be issued early and consumed later.
+template <int C, bool C32>
+struct CombineIn {
+  using CT = typename std::conditional<C32, uint32_t, uint64_t>::type;
+  CT c1 = 0, c2 = 0;
+  double lv0 = 0.0, trv = 0.0, ta = 0.0;
+  __device__ __forceinline__ void load(const StepArgs &a, int v, int c) {
+    const uint64_t o = (uint64_t)v * C + c;
+    c1 = static_cast<const CT *>(a.q_cnt1)[o & a.q_m1];
+    c2 = static_cast<const CT *>(a.q_cnt2)[o & a.q_m2];
+    lv0 = a.q_lv[o & a.q_mlv];
+    trv = a.tr[v];
+    ta = a.inj[v];
+  }
+  // sum_{i<a} h_i(v) for column c (levels beyond the first stored one are
+  // loaded here; there are none unless ell* > 8)
+  __device__ __forceinline__ double q(const StepArgs &a, int v, int c) const {
+    double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * lv0;
+    for (int l = 1; l < a.q_nlv; ++l) s += a.q_lv[(size_t)l * a.n * C + (size_t)v * C + c];
+    return s;
+  }
+};
+
+// y is h_a(v) (t_a(v) for v in S), q = sum_{i<a} h_i(v), trv = sum_{c<=r} t_c(v),
+// ta = t_a(v).
+__device__ __forceinline__ double combine_fin(const StepArgs &a, double q, double y, double trv,
+                                              double ta, bool inS) {
   const double rs = a.q_even ? q + y : q;
-  const double miss = inS ? 0.0 : (a.inj[v] - y) * rs;
-  return ((q + y) + y * a.tr[v]) + miss;
+  const double miss = inS ? 0.0 : (ta - y) * rs;
+  return ((q + y) + y * trv) + miss;
 }
 
 template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE;
+  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || CB;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
                             TM ? a.tmask[v] : 0ull, OUT == OUT_GAIN ? a.cand_col[v] : -1);
 }
@@ -129,7 +154,8 @@ template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE;
+  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || CB;
   constexpr bool CA = OUT == OUT_GAIN;
   constexpr int LV = lds_values(C);          // values staged per block
   constexpr int PT = LV / kBlock;            // gathered values per thread
@@ -178,6 +204,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
       if constexpr (TM) tv[k] = a.tmask[rr];
       if constexpr (CA) cv[k] = a.cand_col[rr];
     }
+    // The combining epilogue's row data for this thread's first (row, column)
+    // pair of phase 2, loaded now so it arrives with the gathers.
+    int tpr = (kBlock / C < 64) ? kBlock / C : 64;
+    while (tpr > 1 && nrows * C * tpr > kBlock) tpr >>= 1;
+    const int rl0 = (t / tpr) / C;
+    CombineIn<C, OUT == OUT_COMBINE32> pf;
+    if constexpr (CB) pf.load(a, r0 + min(rl0, nrows - 1), (t / tpr) & (C - 1));
     double v[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
@@ -202,8 +235,6 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     }
     __syncthreads();
     // Phase 2: tpr lanes per (row, column), as many as the row count allows.
-    int tpr = (kBlock / C < 64) ? kBlock / C : 64;
-    while (tpr > 1 && nrows * C * tpr > kBlock) tpr >>= 1;
     const int s = t & (tpr - 1);
     const int pair = t / tpr;
     const int c = pair & (C - 1);
@@ -218,11 +249,15 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         const int r = r0 + rl;
         bool inS = false;
         if constexpr (M1) inS = (mw[(r >> 5) - (r0 >> 5)] >> (r & 31)) & 1u;
-        const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
-                                            CA ? cw[rl] : -1);
-        if constexpr (OUT == OUT_COMBINE) {
-          colsum += combine_contrib<C>(a, r, c, y, (tmw[rl] >> c) & 1ull);
+        if constexpr (CB) {
+          const bool member = (tmw[rl] >> c) & 1ull;
+          CombineIn<C, OUT == OUT_COMBINE32> in = pf;
+          if (rl != rl0) in.load(a, r, c);
+          colsum += combine_fin(a, in.q(a, r, c), member ? in.ta : a.alpha * acc, in.trv, in.ta,
+                                member);
         } else {
+          const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
+                                              CA ? cw[rl] : -1);
           a.Y[(size_t)r * C + c] = y;
           colsum += y;
         }
@@ -274,10 +309,13 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   double y = epilogue<C, OUT>(a, r, c, acc);
-  if constexpr (OUT == OUT_COMBINE)
-    y = combine_contrib<C>(a, r, c, y, (a.tmask[r] >> c) & 1ull);
-  else
+  if constexpr (OUT == OUT_COMBINE || OUT == OUT_COMBINE32) {
+    CombineIn<C, OUT == OUT_COMBINE32> in;
+    in.load(a, r, c);
+    y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, (a.tmask[r] >> c) & 1ull);
+  } else {
     a.Y[(size_t)r * C + c] = y;
+  }
   double *lp = a.long_part + (size_t)l * C + c;
   *lp = a.accum ? *lp + y : y;
 }
@@ -363,6 +401,9 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
   if constexpr (!WGT) {  // integer walk counts exist for unweighted graphs only
     GED_CASE(IN_CNT, OUT_TILE)
     GED_CASE(IN_CNT, OUT_COMBINE)
+    GED_CASE(IN_CNT32, OUT_TILE)
+    GED_CASE(IN_CNT32, OUT_COMBINE32)
+    GED_CASE(IN_VEC, OUT_COMBINE32)
   }
   if constexpr (C == 1) {
     GED_CASE(IN_ONES, OUT_PLAIN)

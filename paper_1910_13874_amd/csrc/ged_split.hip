@@ -14,8 +14,10 @@
 // dense step applies the combination in its epilogue (OUT_COMBINE).
 //
 // On unweighted graphs the first two levels are integer walk counts
-// (h_i = alpha^i * count_i), pushed from the group's members with 64-bit
-// integer atomics (exact and order-free, so the result stays deterministic):
+// (h_i = alpha^i * count_i), pushed from the group's members with integer
+// atomics (exact and order-free, so the result stays deterministic), 32-bit
+// when the maximum degree is below 2^16 (count_2 <= omega_2 <= max degree^2),
+// else 64-bit:
 //   count_1(y) = |N(y) ∩ S| outside S,        deg(y) on S
 //   count_2(x) = sum_{y in N(x)} count_1(y) outside S,   omega_2(x) on S
 // Members push deg(s) to their neighbours (level-2 paths through a member)
@@ -31,7 +33,12 @@ namespace ged {
 
 constexpr int kWlChunk = 512;   // arcs per worklist entry (one wavefront)
 constexpr int kPushGrid = 2048; // blocks of the member kernels (grid-stride)
-constexpr int kWlGrid = 1024;   // blocks of the worklist kernels (4 waves each)
+// blocks of the worklist kernels (4 waves each): one wave per entry of the
+// capacity, at most kWlGridMax blocks
+constexpr int kWlGridMax = 16384;
+static int wl_grid(unsigned cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kWlGridMax, ((int64_t)cap + 3) / 4));
+}
 
 bool split_ok(const ged_graph *g) { return g->flags == GED_UNDIRECTED; }
 
@@ -42,6 +49,8 @@ SplitPlan split_plan(const ged_graph *g, int ell) {
   p.even = p.r == p.a;
   p.s = g->weighted ? 0 : std::min(2, p.a - 1);
   p.nlv = p.a - 1 - p.s;
+  // count_2 <= omega_2 <= (max degree)^2
+  p.c32 = g->max_deg < 65536;
   return p;
 }
 
@@ -69,20 +78,20 @@ __device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) 
 // Members of groups g0 .. g0+nc-1, one block per member: level-1 counts, the
 // level-2 contributions of paths through the member, and worklist entries for
 // the non-members they reach first.
+template <class CT>
 __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
                                                  const int *__restrict__ ci,
                                                  const uint64_t *__restrict__ tmask,
                                                  const int64_t *offsets, const int *members,
-                                                 const int *mcol, int g0, int nc, int C,
-                                                 unsigned long long *cnt1,
-                                                 unsigned long long *cnt2, uint64_t *wl,
-                                                 unsigned *wl_n, unsigned wl_cap) {
+                                                 const int *mcol, int g0, int nc, int C, CT *cnt1,
+                                                 CT *cnt2, uint64_t *wl, unsigned *wl_n,
+                                                 unsigned wl_cap) {
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
     const int s = members[j];
     const int c = mcol[j] - g0;
     const int k0 = rp[s], k1 = rp[s + 1];
-    const unsigned long long ds = (unsigned long long)(k1 - k0);
+    const CT ds = (CT)(k1 - k0);
     for (int kb = k0; kb < k1; kb += kBlock) {  // same trip count for the whole block
       const int k = kb + (int)threadIdx.x;
       unsigned nch = 0;
@@ -90,10 +99,10 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
       if (k < k1) {
         y = ci[k];
         const size_t o = (size_t)y * C + c;
-        const unsigned long long old = atomicAdd(&cnt1[o], 1ull);
+        const CT old = atomicAdd(&cnt1[o], (CT)1);
         if (cnt2) {
           atomicAdd(&cnt2[o], ds);
-          if (old == 0ull && !((tmask[y] >> c) & 1ull))
+          if (old == 0 && !((tmask[y] >> c) & 1ull))
             nch = (unsigned)((rp[y + 1] - rp[y] + kWlChunk - 1) / kWlChunk);
         }
       }
@@ -114,11 +123,10 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
 
 // Worklist entries, one wavefront each: count_1(y) goes to every x in one
 // chunk of N(y) (value 0 with clear = 1 stores zeros instead).
-template <bool CLEAR>
+template <class CT, bool CLEAR>
 __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
                                                     const int *__restrict__ ci, int C,
-                                                    const unsigned long long *cnt1,
-                                                    unsigned long long *cnt2, const uint64_t *wl,
+                                                    const CT *cnt1, CT *cnt2, const uint64_t *wl,
                                                     const unsigned *wl_n, unsigned wl_cap) {
   const unsigned count = min(*wl_n, wl_cap);
   const int lane = threadIdx.x & 63;
@@ -130,50 +138,50 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
     const int q = (int)(e & 0xffffffu);
     const int j0 = rp[y] + q * kWlChunk, j1 = min(j0 + kWlChunk, rp[y + 1]);
     if (CLEAR) {
-      for (int j = j0 + lane; j < j1; j += 64) cnt2[(size_t)ci[j] * C + c] = 0ull;
+      for (int j = j0 + lane; j < j1; j += 64) cnt2[(size_t)ci[j] * C + c] = 0;
     } else {
-      const unsigned long long v = cnt1[(size_t)y * C + c];
+      const CT v = cnt1[(size_t)y * C + c];
       for (int j = j0 + lane; j < j1; j += 64) atomicAdd(&cnt2[(size_t)ci[j] * C + c], v);
     }
   }
 }
 
 // Member rows hold the unrestricted counts: deg(s) and omega_2(s).
+template <class CT>
 __global__ void k_fix_members(const int *__restrict__ rp,
                               const unsigned long long *__restrict__ omega2,
                               const int64_t *offsets, const int *members, const int *mcol,
-                              int g0, int nc, int C, unsigned long long *cnt1,
-                              unsigned long long *cnt2) {
+                              int g0, int nc, int C, CT *cnt1, CT *cnt2) {
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < je;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int s = members[j];
     const size_t o = (size_t)s * C + (mcol[j] - g0);
-    cnt1[o] = (unsigned long long)(rp[s + 1] - rp[s]);
-    if (cnt2) cnt2[o] = omega2[s];
+    cnt1[o] = (CT)(rp[s + 1] - rp[s]);
+    if (cnt2) cnt2[o] = (CT)omega2[s];
   }
 }
 
 // Zero every count entry k_push / k_fix_members wrote for these members.
+template <class CT>
 __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict__ rp,
                                                           const int *__restrict__ ci,
                                                           const int64_t *offsets,
                                                           const int *members, const int *mcol,
-                                                          int g0, int nc, int C,
-                                                          unsigned long long *cnt1,
-                                                          unsigned long long *cnt2) {
+                                                          int g0, int nc, int C, CT *cnt1,
+                                                          CT *cnt2) {
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
     const int s = members[j];
     const int c = mcol[j] - g0;
     if (threadIdx.x == 0) {
-      cnt1[(size_t)s * C + c] = 0ull;
-      if (cnt2) cnt2[(size_t)s * C + c] = 0ull;
+      cnt1[(size_t)s * C + c] = 0;
+      if (cnt2) cnt2[(size_t)s * C + c] = 0;
     }
     for (int k = rp[s] + (int)threadIdx.x; k < rp[s + 1]; k += kBlock) {
       const size_t o = (size_t)ci[k] * C + c;
-      cnt1[o] = 0ull;
-      if (cnt2) cnt2[o] = 0ull;
+      cnt1[o] = 0;
+      if (cnt2) cnt2[o] = 0;
     }
   }
 }
@@ -233,18 +241,18 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
   Partition &p = partition(g, C);
   w.ws.fit(p);
   if (pl.s >= 1) {
-    const size_t cb = sizeof(uint64_t) * nC;
+    const size_t cb = (pl.c32 ? sizeof(uint32_t) : sizeof(uint64_t)) * nC;
     if (w.cnt1.bytes < cb || w.cnt2.bytes < cb) {
       w.cnt1.ensure(cb);
       w.cnt2.ensure(cb);
       w.zero = false;
     }
-    if (!w.zero || w.cnt_elems != nC) {
+    if (!w.zero || w.cnt_bytes != cb) {
       launch_fill_i32(w.cnt1.as<int>(), 0, w.cnt1.bytes / sizeof(int), st);
       launch_fill_i32(w.cnt2.as<int>(), 0, w.cnt2.bytes / sizeof(int), st);
       w.wl_n.ensure(sizeof(unsigned));
       launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
-      w.cnt_elems = nC;
+      w.cnt_bytes = cb;
       w.zero = true;
     }
     if (pl.s >= 2 && (wl_need > w.wl_cap || !w.wl.p)) {
@@ -257,35 +265,56 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
   if (pl.nlv > 0) w.lv.ensure(sizeof(double) * nC * (size_t)pl.nlv);
 }
 
-void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
+template <class CT>
+static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
+                       const int *mem, const int *mcol, int g0, int nc, int mgrid,
+                       int64_t tile_members, const uint64_t *tmask, hipStream_t st) {
+  const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
+  CT *c1 = w.cnt1.as<CT>();
+  CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
+  hipLaunchKernelGGL(k_push<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, tmask, offs, mem,
+                     mcol, g0, nc, C, c1, c2, w.wl.as<uint64_t>(), w.wl_n.as<unsigned>(),
+                     w.wl_cap);
+  GED_HIP(hipGetLastError());
+  if (c2) {
+    hipLaunchKernelGGL((k_push_wl<CT, false>), dim3(wl_grid(w.wl_cap)), dim3(kBlock), 0, st, rp, ci, C, c1,
+                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
+    GED_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_fix_members<CT>, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
+                     dim3(kBlock), 0, st, rp, g->omega2.as<const unsigned long long>(), offs, mem,
+                     mcol, g0, nc, C, c1, c2);
+  GED_HIP(hipGetLastError());
+}
+
+template <class CT>
+static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
-                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st) {
+                        int mgrid, hipStream_t st) {
+  const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
+  CT *c1 = w.cnt1.as<CT>();
+  CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
+  if (c2) {
+    hipLaunchKernelGGL((k_push_wl<CT, true>), dim3(wl_grid(w.wl_cap)), dim3(kBlock), 0, st, rp, ci, C, c1,
+                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
+    GED_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_clear_members<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem,
+                     mcol, g0, nc, C, c1, c2);
+  GED_HIP(hipGetLastError());
+  if (c2) launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
+}
+
+void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
+                 hipStream_t st) {
   const int64_t n = g->n;
   const size_t nC = (size_t)n * C;
   const PrepCache &pc = g->prep;
   const double alpha = pc.alpha;
   Partition &p = partition(g, C);
   const double *T = pc.t_levels.as<const double>();
-  const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
-  unsigned long long *c1 = pl.s >= 1 ? w.cnt1.as<unsigned long long>() : nullptr;
-  unsigned long long *c2 = pl.s >= 2 ? w.cnt2.as<unsigned long long>() : nullptr;
-  const int mgrid = grid_for(tile_members, kPushGrid);
-  launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
-  if (pl.s >= 1) {
-    hipLaunchKernelGGL(k_push, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, tmask, offs, mem, mcol,
-                       g0, nc, C, c1, c2, w.wl.as<uint64_t>(), w.wl_n.as<unsigned>(), w.wl_cap);
-    GED_HIP(hipGetLastError());
-    if (c2) {
-      hipLaunchKernelGGL(k_push_wl<false>, dim3(kWlGrid), dim3(kBlock), 0, st, rp, ci, C, c1, c2,
-                         w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
-      GED_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_fix_members, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
-                       dim3(kBlock), 0, st, rp, g->omega2.as<const unsigned long long>(), offs,
-                       mem, mcol,
-                       g0, nc, C, c1, c2);
-    GED_HIP(hipGetLastError());
-  }
+  const void *c1 = pl.s >= 1 ? w.cnt1.p : nullptr;
+  const void *c2 = pl.s >= 2 ? w.cnt2.p : nullptr;
   double lv_scale = alpha;  // alpha^(s+1) for the first dense level after the counts
   for (int i = 0; i < pl.s; ++i) lv_scale *= alpha;
   double *lv = w.lv.as<double>();
@@ -300,8 +329,14 @@ void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
       in = IN_TILEMASK;
       a.alpha = alpha;
     } else if (i == pl.s + 1) {
-      in = IN_CNT;
-      a.Xc = reinterpret_cast<const uint64_t *>(pl.s == 1 ? c1 : c2);
+      const void *src = pl.s == 1 ? c1 : c2;
+      if (pl.c32) {
+        in = IN_CNT32;
+        a.Xc32 = static_cast<const uint32_t *>(src);
+      } else {
+        in = IN_CNT;
+        a.Xc = static_cast<const uint64_t *>(src);
+      }
       a.alpha = lv_scale;
     } else {
       in = IN_VEC;
@@ -313,29 +348,49 @@ void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
       a.Y = lv + (size_t)(i - 1 - pl.s) * nC;
       run_step(g, p, a, in, OUT_TILE, st);
     } else {
+      // absent inputs: index mask 0 into a valid buffer, weight 0
+      const double *any = pc.tr.as<const double>();
       a.Y = nullptr;
       a.tr = pc.tr.as<const double>();
-      a.q_cnt1 = reinterpret_cast<const uint64_t *>(c1);
-      a.q_cnt2 = reinterpret_cast<const uint64_t *>(c2);
-      a.q_s1 = alpha;
-      a.q_s2 = alpha * alpha;
-      a.q_lv = lv;
+      a.q_cnt1 = c1 ? c1 : any;
+      a.q_cnt2 = c2 ? c2 : any;
+      a.q_m1 = c1 ? ~0ull : 0ull;
+      a.q_m2 = c2 ? ~0ull : 0ull;
+      a.q_s1 = c1 ? alpha : 0.0;
+      a.q_s2 = c2 ? alpha * alpha : 0.0;
+      a.q_lv = pl.nlv > 0 ? lv : any;
+      a.q_mlv = pl.nlv > 0 ? ~0ull : 0ull;
+      a.q_slv = pl.nlv > 0 ? 1.0 : 0.0;
       a.q_nlv = pl.nlv;
       a.q_even = pl.even ? 1 : 0;
-      run_step(g, p, a, in, OUT_COMBINE, st, pl.s + pl.nlv);
+      const int out = (pl.c32 && pl.s >= 1) ? OUT_COMBINE32 : OUT_COMBINE;
+      run_step(g, p, a, in, out, st, pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
     }
   }
-  launch_reduce(p, a, out, nullptr, nullptr, st, w.ws.scratch());
+}
+
+void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
+                        const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
+                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st) {
+  const int mgrid = grid_for(tile_members, kPushGrid);
+  launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
   if (pl.s >= 1) {
-    if (c2) {
-      hipLaunchKernelGGL(k_push_wl<true>, dim3(kWlGrid), dim3(kBlock), 0, st, rp, ci, C, c1, c2,
-                         w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
-      GED_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_clear_members, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem, mcol,
-                       g0, nc, C, c1, c2);
-    GED_HIP(hipGetLastError());
-    if (c2) launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
+    if (pl.c32)
+      push_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tile_members, tmask, st);
+    else
+      push_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tile_members,
+                                     tmask, st);
+  }
+  split_dense(g, w, pl, C, tmask, st);
+  StepArgs a = base_args(g);
+  w.ws.into(a);
+  a.C = C;
+  launch_reduce(partition(g, C), a, out, nullptr, nullptr, st, w.ws.scratch());
+  if (pl.s >= 1) {
+    if (pl.c32)
+      clear_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, st);
+    else
+      clear_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, st);
   }
   launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
 }

@@ -313,13 +313,22 @@ def test_stochastic_greedy_parity(ged):
     gg.close()
 
 
-@pytest.mark.parametrize("name", ["er", "ba", "weighted"])
+@pytest.mark.parametrize("name", ["er", "ba", "weighted", "hub"])
 def test_split_ell_sweep(ged, name):
     """Split scoring for every plan shape: ell* = 1..9 (a = 1, 2, 3+; odd and
     even ell; integer levels s = 0, 1, 2; weighted has s = 0), single and
-    batched, against the oracle."""
+    batched, against the oracle.  "hub" has a vertex of degree 70,000, which
+    takes the 64-bit count path (32-bit counts need max degree < 2^16)."""
     if name == "er":
         g, w = inputs.erdos_renyi(3000, 12000, 51), None
+    elif name == "hub":
+        rng = np.random.default_rng(53)
+        leaves = np.arange(1, 70001, dtype=np.int32)
+        src = np.concatenate([np.zeros(70000, np.int32), rng.integers(1, 70001, 30000).astype(np.int32)])
+        dst = np.concatenate([leaves, rng.integers(1, 70001, 30000).astype(np.int32)])
+        keep = src != dst
+        g, w = inputs.from_edges(70001, src[keep], dst[keep], symmetrize=True), None
+        assert g.max_degree >= 65536
     else:
         g, w = inputs.barabasi_albert(4000, 4, 52), None
         if name == "weighted":
