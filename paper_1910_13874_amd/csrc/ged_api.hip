@@ -49,7 +49,7 @@ StepArgs base_args(ged_graph *g, bool reverse) {
 double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows) {
   const double n = (double)g->n, nnz = (double)g->nnz;
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
-  if (out != OUT_COMBINE && out != OUT_COMBINE32) b += 8.0 * n * C;  // Y
+  if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_GAINCOMB) b += 8.0 * n * C;  // Y
   if (g->weighted) b += 8.0 * nnz;
   switch (in) {
     case IN_VEC:
@@ -70,6 +70,7 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case OUT_GAIN: b += n / 8.0 + 4.0 * n; break;
     case OUT_COMBINE:
     case OUT_COMBINE32: b += 8.0 * n * 3; break;  // tmask, t_a, tr
+    case OUT_GAINCOMB: b += n / 8.0 + 4.0 * n + 16.0 * n; break;  // S bits, candidates, m_a, M_r
     default: break;
   }
   return b + 8.0 * n * C * extra_rows;
@@ -178,8 +179,31 @@ int prepare(ged_graph *g, double alpha, double eps) {
   pc.alpha = alpha;
   pc.eps = eps;
   pc.tail_level = -1;
+  pc.t_count = pc.ell + 1;
   pc.valid = true;
   return GED_OK;
+}
+
+const double *t_levels_to(ged_graph *g, int L) {
+  PrepCache &pc = g->prep;
+  if (L < pc.t_count) return pc.t_levels.as<const double>();
+  hipStream_t st = g->stream;
+  const int64_t n = g->n;
+  Partition &p = partition(g, 1);
+  g->pws.fit(p);
+  ensure_levels(pc, n, L + 1, st);
+  double *T = pc.t_levels.as<double>();
+  for (int i = pc.t_count; i <= L; ++i) {
+    StepArgs a = base_args(g);
+    g->pws.into(a);
+    a.C = 1;
+    a.alpha = pc.alpha;
+    a.X = T + (size_t)(i - 1) * n;
+    a.Y = T + (size_t)i * n;
+    run_step(g, p, a, IN_VEC, OUT_PLAIN, st);
+  }
+  pc.t_count = L + 1;
+  return T;
 }
 
 double walk_total(ged_graph *g, int ell) {

@@ -18,6 +18,15 @@
 //      algorithm find the same pair).
 //   4. accept u iff L(u) > L(v) + B_ell - eps/k ((eps/k)-separation), else
 //      ell <- 2 ell.  Ties order by larger value, then smaller id.
+//
+// Undirected graphs split the walks as split scoring does: a walk of length
+// a + c that avoids S and contains x, cut after a arcs at v, has either a
+// first part that contains x (d_a(v) of them, each continued by the m_c(v)
+// S-avoiding walks leaving v) or one that does not (m_a(v) - d_a(v)) followed
+// by a last part that contains x (d_c(v), by reversal), so
+//   L_{a+c}(S, x) = sum_v d_a(v) m_c(v) + (m_a(v) - d_a(v)) d_c(v)
+// and both chains are needed only up to a = ceil(ell/2).  The bound of step 2
+// then takes t_j(x) >= m_j(x) for the levels j > a it no longer has.
 #include <math.h>
 
 #include <algorithm>
@@ -48,7 +57,11 @@ __global__ void k_mask_bit(uint32_t *mask, int v, int value) {
 // I(x) = b_0 * sum_{a=1}^{ell} m_a + sum_{c=1}^{ell} b_c * sum_{a=0}^{ell-c} m_a with
 // m_0 = b_0 = 1 for x outside S: every term of Lemma "initialize" once, no
 // subtraction.  ub[x] = -1 marks members of S.
+// Levels j <= ma come from the miss chain M, higher ones from the total-walk
+// levels T (an upper bound: walks that avoid S are walks).  Bl (reverse
+// chain, directed graphs) null means b = m.
 __global__ __launch_bounds__(kBlock) void k_pbound(const double *__restrict__ M,
+                                                   const double *__restrict__ T, int ma,
                                                    const double *__restrict__ Bl, int n, int ell,
                                                    const uint32_t *__restrict__ smask,
                                                    const double *__restrict__ stale,
@@ -59,16 +72,17 @@ __global__ __launch_bounds__(kBlock) void k_pbound(const double *__restrict__ M,
     ub[x] = -1.0;
     return;
   }
+  auto mv = [&](int j) { return (j <= ma ? M : T)[(size_t)j * n + x]; };
   double pre = 1.0, tail = 0.0, acc = 0.0;
   for (int s = 0; s < ell; ++s) {
     if (s > 0) {
-      const double ms = M[(size_t)s * n + x];
+      const double ms = mv(s);
       pre += ms;
       tail += ms;
     }
-    acc += Bl[(size_t)(ell - s) * n + x] * pre;
+    acc += (Bl ? Bl[(size_t)(ell - s) * n + x] : mv(ell - s)) * pre;
   }
-  tail += M[(size_t)ell * n + x];
+  tail += mv(ell);
   acc += tail;
   const double st = stale[x];
   if (st >= 0.0 && st < acc) acc = st;
@@ -201,13 +215,24 @@ __global__ void k_after_batch(const int *cand, const double *gains, int nc, doub
 
 // ------------------------------------------------------------- host side --
 
+// Mr[v] = sum_{c=1..r} M[c][v]
+__global__ void k_sum_range(const double *__restrict__ M, int n, int r, double *__restrict__ Mr) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 1; c <= r; ++c) s += M[(size_t)c * n + v];
+    Mr[v] = s;
+  }
+}
+
 struct GreedyCtx {
   ged_graph *g;
   hipStream_t st;
   int n;
   int C;
   int Lcap = 0;
+  bool split = false;  // undirected: chains to ceil(ell/2) (walk split)
   DBuf smask, m_levels, b_levels, ub, stale, done, cand_col, sampled;
+  DBuf dlv, Mr;        // split: stored gain levels [(a-1)*n*C], sum of miss levels [n]
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
   StepWs ws1, ws1r, wsC;
@@ -248,10 +273,27 @@ static void miss_chains(GreedyCtx &c, int ell) {
 }
 
 static void compute_bounds(GreedyCtx &c, int ell) {
-  const double *B = (c.g->flags == GED_DIRECTED ? c.b_levels : c.m_levels).as<const double>();
-  hipLaunchKernelGGL(k_pbound, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, c.st,
-                     c.m_levels.as<const double>(), B, c.n, ell, c.smask.as<const uint32_t>(),
-                     c.stale.as<const double>(), c.ub.as<double>(), kBoundSlack);
+  const double *M = c.m_levels.as<const double>();
+  const double *B = c.g->flags == GED_DIRECTED ? c.b_levels.as<const double>() : nullptr;
+  const int ma = c.split ? (ell + 1) / 2 : ell;
+  const double *T = c.split ? t_levels_to(c.g, ell) : M;
+  hipLaunchKernelGGL(k_pbound, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, c.st, M, T, ma,
+                     B, c.n, ell, c.smask.as<const uint32_t>(), c.stale.as<const double>(),
+                     c.ub.as<double>(), kBoundSlack);
+  GED_HIP(hipGetLastError());
+}
+
+// Miss levels 1..a of the current S and, for the split gain, their sum to r.
+static void chains_for(GreedyCtx &c, int ell) {
+  if (!c.split) {
+    miss_chains(c, ell);
+    return;
+  }
+  const int a = (ell + 1) / 2, r = ell - a;
+  miss_chains(c, a);
+  c.Mr.ensure(sizeof(double) * c.n);
+  hipLaunchKernelGGL(k_sum_range, dim3(std::min(8192, (c.n + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, c.st, c.m_levels.as<const double>(), c.n, r, c.Mr.as<double>());
   GED_HIP(hipGetLastError());
 }
 
@@ -303,16 +345,47 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
   const double *M = c.m_levels.as<const double>();
   StepArgs a = base_args(g);
   c.wsC.into(a);
-  for (int i = 1; i <= ell; ++i) {
-    a.C = C;
-    a.alpha = g->prep.alpha;
-    a.accum = i > 1;  // L = sum over all levels of the column sums
-    a.smask = c.smask.as<const uint32_t>();
-    a.cand_col = c.cand_col.as<const int>();
-    a.X = ((i & 1) ? c.X : c.Y).as<const double>();
-    a.Y = ((i & 1) ? c.Y : c.X).as<double>();
-    a.inj = M + (size_t)i * n;
-    run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
+  a.C = C;
+  a.alpha = g->prep.alpha;
+  a.smask = c.smask.as<const uint32_t>();
+  a.cand_col = c.cand_col.as<const int>();
+  if (c.split) {
+    // gain levels 1..a-1 stored, level a combined (walk split)
+    const int la = (ell + 1) / 2, r = ell - la;
+    const size_t nC = (size_t)n * C;
+    if (la > 1) c.dlv.ensure(sizeof(double) * nC * (size_t)(la - 1));
+    double *dl = c.dlv.as<double>();
+    const double *any = c.Mr.as<const double>();
+    a.accum = 0;
+    for (int i = 1; i <= la; ++i) {
+      a.X = i == 1 ? nullptr : dl + (size_t)(i - 2) * nC;
+      a.inj = M + (size_t)i * n;
+      if (i < la) {
+        a.Y = dl + (size_t)(i - 1) * nC;
+        run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
+      } else {
+        a.Y = nullptr;
+        a.tr = c.Mr.as<const double>();
+        a.q_cnt1 = any;
+        a.q_cnt2 = any;
+        a.q_m1 = a.q_m2 = 0;
+        a.q_s1 = a.q_s2 = 0.0;
+        a.q_lv = la > 1 ? dl : any;
+        a.q_mlv = la > 1 ? ~0ull : 0ull;
+        a.q_slv = la > 1 ? 1.0 : 0.0;
+        a.q_nlv = la - 1;
+        a.q_even = r == la ? 1 : 0;
+        run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAINCOMB, c.st, la - 1);
+      }
+    }
+  } else {
+    for (int i = 1; i <= ell; ++i) {
+      a.accum = i > 1;  // L = sum over all levels of the column sums
+      a.X = ((i & 1) ? c.X : c.Y).as<const double>();
+      a.Y = ((i & 1) ? c.Y : c.X).as<double>();
+      a.inj = M + (size_t)i * n;
+      run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
+    }
   }
   launch_reduce(p, a, c.gains.as<double>(), nullptr, nullptr, c.st, c.wsC.scratch());
   hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
@@ -367,6 +440,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.st = g->stream;
   c.n = n;
   c.C = 8;
+  c.split = split_ok(g);
   const int K = c.C + 1;
   c.smask.ensure(sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1));
   c.ub.ensure(sizeof(double) * n);
@@ -452,7 +526,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
         sample_pick = s_size;
       }
       if (need_chain) {
-        miss_chains(c, ell);
+        chains_for(c, ell);
         need_chain = false;
       }
       compute_bounds(c, ell);

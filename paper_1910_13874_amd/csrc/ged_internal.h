@@ -142,7 +142,9 @@ enum OutMode : int {
   OUT_POOL = 5,  // bit c of tmask[v] ? inj[step[c]*n + v] : alpha * sum   (serving pool)
   OUT_COMBINE = 6, // y as OUT_TILE, not stored; the column sum takes the split
                    // combination of y with the stored lower levels (split scoring)
-  OUT_COMBINE32 = 7 // the same with 32-bit count levels
+  OUT_COMBINE32 = 7, // the same with 32-bit count levels
+  OUT_GAINCOMB = 8   // y as OUT_GAIN, not stored; the column sum takes the split
+                     // combination of a gain chain (undirected greedy)
 };
 
 struct StepArgs {
@@ -241,6 +243,7 @@ struct PrepCache {
   int tail_cur = 0;
   DBuf tr;                     // [n] sum_{c=1..tr_r} t_c (split scoring)
   int tr_r = -1;               // -1: not built for this (alpha, eps)
+  int t_count = 0;             // levels held in t_levels (ell* + 1 after prepare)
 };
 
 // ------------------------------------------------------- split scoring --
@@ -345,6 +348,9 @@ Partition &partition(ged_graph *g, int C, bool reverse = false);
 int prepare(ged_graph *g, double alpha, double eps);
 // W[ell] for arbitrary ell (extends the total-walk chain on demand).
 double walk_total(ged_graph *g, int ell);
+// The decayed total-walk levels t_0..t_L (extends the stored levels on demand;
+// the buffer may move).
+const double *t_levels_to(ged_graph *g, int L);
 double comb_bound(ged_graph *g, double alpha, double W_ell);
 int check_alpha_eps(ged_graph *g, double alpha, double eps);
 StepArgs base_args(ged_graph *g, bool reverse = false);

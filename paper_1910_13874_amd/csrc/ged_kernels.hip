@@ -68,7 +68,7 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
     return inS ? 0.0 : y;
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
-  } else if constexpr (OUT == OUT_GAIN) {
+  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
   } else {  // OUT_POOL
     const int s = a.col_step[c];
@@ -106,7 +106,17 @@ struct CombineIn {
   // loaded here; there are none unless ell* > 8)
   __device__ __forceinline__ double q(const StepArgs &a, int v, int c) const {
     double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * lv0;
-    for (int l = 1; l < a.q_nlv; ++l) s += a.q_lv[(size_t)l * a.n * C + (size_t)v * C + c];
+    const size_t o = (size_t)v * C + c, ls = (size_t)a.n * C;
+    int l = 1;
+    for (; l + 3 < a.q_nlv; l += 4) {  // four loads in flight, added in level order
+      const double x0 = a.q_lv[l * ls + o], x1 = a.q_lv[(l + 1) * ls + o];
+      const double x2 = a.q_lv[(l + 2) * ls + o], x3 = a.q_lv[(l + 3) * ls + o];
+      s += x0;
+      s += x1;
+      s += x2;
+      s += x3;
+    }
+    for (; l < a.q_nlv; ++l) s += a.q_lv[l * ls + o];
     return s;
   }
 };
@@ -122,11 +132,12 @@ __device__ __forceinline__ double combine_fin(const StepArgs &a, double q, doubl
 
 template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
-  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
-  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || CB;
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
+                      OUT == OUT_COMBINE32;
+  constexpr bool CA = OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
-                            TM ? a.tmask[v] : 0ull, OUT == OUT_GAIN ? a.cand_col[v] : -1);
+                            TM ? a.tmask[v] : 0ull, CA ? a.cand_col[v] : -1);
 }
 
 // Column sums of a block: lanes holding the same column are combined with
@@ -153,10 +164,11 @@ __device__ __forceinline__ void block_colsum(double v, int tpr, double *red, dou
 template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
-  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN;
-  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || CB;
-  constexpr bool CA = OUT == OUT_GAIN;
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
+  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_GAINCOMB;
+  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
+                      OUT == OUT_COMBINE32;
+  constexpr bool CA = OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
   constexpr int LV = lds_values(C);          // values staged per block
   constexpr int PT = LV / kBlock;            // gathered values per thread
   constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
@@ -250,11 +262,18 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         bool inS = false;
         if constexpr (M1) inS = (mw[(r >> 5) - (r0 >> 5)] >> (r & 31)) & 1u;
         if constexpr (CB) {
-          const bool member = (tmw[rl] >> c) & 1ull;
           CombineIn<C, OUT == OUT_COMBINE32> in = pf;
           if (rl != rl0) in.load(a, r, c);
-          colsum += combine_fin(a, in.q(a, r, c), member ? in.ta : a.alpha * acc, in.trv, in.ta,
-                                member);
+          double y;
+          bool member = false;
+          if constexpr (OUT == OUT_GAINCOMB) {
+            // gain chains: 0 on S (where m_a = 0 too), m_a(x) at the candidate
+            y = inS ? 0.0 : (cw[rl] == c ? in.ta : a.alpha * acc);
+          } else {
+            member = (tmw[rl] >> c) & 1ull;
+            y = member ? in.ta : a.alpha * acc;
+          }
+          colsum += combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, member);
         } else {
           const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
                                               CA ? cw[rl] : -1);
@@ -309,10 +328,11 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   double y = epilogue<C, OUT>(a, r, c, acc);
-  if constexpr (OUT == OUT_COMBINE || OUT == OUT_COMBINE32) {
+  if constexpr (OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_GAINCOMB) {
     CombineIn<C, OUT == OUT_COMBINE32> in;
     in.load(a, r, c);
-    y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, (a.tmask[r] >> c) & 1ull);
+    const bool member = OUT == OUT_GAINCOMB ? false : ((a.tmask[r] >> c) & 1ull);
+    y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, member);
   } else {
     a.Y[(size_t)r * C + c] = y;
   }
@@ -404,6 +424,10 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_CNT32, OUT_TILE)
     GED_CASE(IN_CNT32, OUT_COMBINE32)
     GED_CASE(IN_VEC, OUT_COMBINE32)
+  }
+  if constexpr (C == 8) {  // the greedy's candidate batches
+    GED_CASE(IN_ONEHOT, OUT_GAINCOMB)
+    GED_CASE(IN_VEC, OUT_GAINCOMB)
   }
   if constexpr (C == 1) {
     GED_CASE(IN_ONES, OUT_PLAIN)

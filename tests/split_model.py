@@ -106,3 +106,36 @@ def split_score(row_ptr, col_idx, S, alpha: float, ell: int, w=None) -> float:
     rs = q + ha if r == a else q
     contrib = (q + ha) + ha * tr + np.where(inS, 0.0, (T[a] - ha) * rs)
     return float(contrib.sum())
+
+
+def split_gain(row_ptr, col_idx, S, x: int, alpha: float, ell: int, w=None) -> float:
+    """L_ell(S, x) from the miss chain and the gain chain up to a = ceil(ell/2),
+    as the greedy's split evaluation does:
+        L_{a+c} = sum_v d_a(v) m_c(v) + (m_a(v) - d_a(v)) d_c(v)."""
+    n = len(row_ptr) - 1
+    inS = np.zeros(n, dtype=bool)
+    inS[np.asarray(S, dtype=np.int64)] = True
+    a = (ell + 1) // 2
+    r = ell - a
+    m = [(~inS).astype(np.float64)]
+    for _ in range(a):
+        y = alpha * _spmv(row_ptr, col_idx, w, m[-1])
+        y[inS] = 0.0
+        m.append(y)
+    d = [np.zeros(n)]
+    d[0][x] = 1.0
+    for i in range(1, a + 1):
+        y = alpha * _spmv(row_ptr, col_idx, w, d[-1])
+        y[inS] = 0.0
+        y[x] = m[i][x]
+        d.append(y)
+    q = np.zeros(n)
+    for i in range(1, a):
+        q = q + d[i]
+    Mr = np.zeros(n)
+    for c in range(1, r + 1):
+        Mr = Mr + m[c]
+    da = d[a]
+    rs = q + da if r == a else q
+    contrib = (q + da) + da * Mr + (m[a] - da) * rs
+    return float(contrib.sum())

@@ -5,7 +5,8 @@
   level-by-level chain);
 * the push formulation of the level-1/2 counts against enumeration;
 * the whole split scheme (tests/split_model.py) against the oracle for every
-  plan shape (a = 1, 2, 3+, odd and even ell, weighted).
+  plan shape (a = 1, 2, 3+, odd and even ell, weighted);
+* the same split for marginal gains (walks that avoid S and contain x).
 """
 import numpy as np
 import pytest
@@ -13,7 +14,7 @@ import pytest
 import oracle
 from exact import WalkTable
 from paper_1910_13874_amd import inputs
-from split_model import push_counts, split_score
+from split_model import push_counts, split_gain, split_score
 
 
 def tiny_graph(n, m, seed):
@@ -107,3 +108,42 @@ def test_split_model_matches_oracle(name):
             assert ell_o == ell
             m = split_score(g.row_ptr, g.col_idx, S, alpha, ell, w)
             assert abs(m - c) <= 1e-12 * abs(c), (name, ell, size, m, c)
+
+
+def miss_end_x(tab, i, S, x, v, contains):
+    """# i-walks ending at v that avoid S and do (contains=True) or do not contain x."""
+    m = tab._mask(S)
+    bx = 1 << int(x)
+    return sum(c for (_, e, mk), c in tab.tab[i].items()
+               if e == v and not (mk & m) and bool(mk & bx) == contains)
+
+
+@pytest.mark.parametrize("seed", [6, 7])
+def test_gain_split_identity_exact(seed):
+    g = tiny_graph(7, 12, seed)
+    tab = WalkTable(g.n, g.row_ptr, g.col_idx, 6)
+    for S, x in (([0], 3), ([1, 4], 2), ([], 5)):
+        for a in range(0, 4):
+            for c in range(0, 7 - a):
+                D_a = [miss_end_x(tab, a, S, x, v, True) for v in range(g.n)]
+                D_c = [miss_end_x(tab, c, S, x, v, True) for v in range(g.n)]
+                N_a = [miss_end_x(tab, a, S, x, v, False) for v in range(g.n)]
+                M_c = [tab.miss_end(c, S, v) for v in range(g.n)]
+                rhs = sum(D_a[v] * M_c[v] + N_a[v] * D_c[v] for v in range(g.n))
+                assert tab.gain_count(a + c, S, x) == rhs, (seed, S, x, a, c)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_split_gain_model_matches_oracle(weighted):
+    g = inputs.barabasi_albert(300, 3, 43)
+    w = None
+    if weighted:
+        deg = g.degrees.astype(np.float64)
+        rows = np.repeat(np.arange(g.n), g.degrees)
+        w = 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+    alpha = 0.9 * oracle.default_alpha(g, w)
+    for ell in (1, 2, 3, 4, 7, 8, 16):
+        for S, x in (([], 0), ([0, 5], 1), (list(range(10, 40)), 7), ([2], 250)):
+            o = oracle.gain(g, S, x, alpha, ell, w=w)
+            m = split_gain(g.row_ptr, g.col_idx, S, x, alpha, ell, w)
+            assert abs(m - o) <= 1e-12 * abs(o), (weighted, ell, len(S), x, m, o)
