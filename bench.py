@@ -146,7 +146,7 @@ def bench_graph_workload(args, torch, ged, inputs):
     g = inputs.workload_graph(spec["graph"])
     log(f"graph {name}: n={g.n} nnz={g.nnz} dmax={g.max_degree} "
         f"({time.perf_counter() - t_gen:.1f}s)")
-    gg = ged.GedGraph.from_graph(g)
+    gg = ged.GedGraph.from_graph(g, keep_order=args.order == "input")
     stream = torch.cuda.Stream()
     gg.set_stream(stream)
     alpha = gg.default_alpha()
@@ -202,7 +202,7 @@ def bench_batch(args, torch, ged, inputs):
     """Batched scoring of 4,096 groups vs 4,096 sequential single-group calls."""
     g = inputs.workload_graph("ba2m")
     log(f"graph ba2m: n={g.n} nnz={g.nnz}")
-    gg = ged.GedGraph.from_graph(g)
+    gg = ged.GedGraph.from_graph(g, keep_order=args.order == "input")
     stream = torch.cuda.Stream()
     gg.set_stream(stream)
     alpha = gg.default_alpha()
@@ -260,6 +260,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="batch: fix the tile width (0 = autotune)")
     ap.add_argument("--seq-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--order", choices=("degree", "input"), default="degree",
+                    help="internal vertex order: degree-descending relabel (default) or the "
+                         "generator's order")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the stream")
     ap.add_argument("--qps", type=float, default=2000.0, help="serve: arrival rate")
     ap.add_argument("--serve-small", action="store_true", help="serve: only the 3 small graphs")

@@ -87,8 +87,15 @@ def _load():
                               ctypes.c_double, ctypes.c_double, ctypes.c_int32, P_I32,
                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P_I32, P_I32,
                               P_F64, P_F64, P_F64, P_F64, P_I64, P_F64, P_I32]
+    lib.or_set_spectral.argtypes = [ctypes.c_double]
+    lib.or_set_spectral.restype = None
+    lib.or_spectral_bound.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                      ctypes.c_double]
+    lib.or_spectral_bound.restype = ctypes.c_double
+    lib.or_sigma_max.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I64, P_I32, ctypes.c_int32,
+                                 P_F64]
     for f in ("or_walk_totals", "or_score", "or_score_fixed", "or_gain_ext", "or_pinit_ext",
-              "or_greedy"):
+              "or_greedy", "or_sigma_max"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -109,6 +116,20 @@ class _Weights:
 
     def __exit__(self, *a):
         _load().or_set_weights(None, None)
+
+
+class _Spectral:
+    """Select the spectral tail bound with upper estimate `sigma` of sigma_max
+    (None: the combinatorial bound) for the duration of one oracle call."""
+
+    def __init__(self, sigma):
+        self.sigma = 0.0 if sigma is None else float(sigma)
+
+    def __enter__(self):
+        _load().or_set_spectral(self.sigma)
+
+    def __exit__(self, *a):
+        _load().or_set_spectral(0.0)
 
 
 def _ck(rc):
@@ -166,10 +187,35 @@ def comb_bound(g, alpha: float, ell: int, w=None) -> float:
     return float(_load().or_comb_bound(alpha, float(D), W[ell]))
 
 
-def score(g, S, alpha: float, eps: float, max_ell: int = 100000, w=None):
+SIGMA_ITERS = 100
+
+
+def sigma_max(g, rev=None, w=None, w_rev=None, iters: int = SIGMA_ITERS) -> float:
+    """Upper estimate of sigma_max(A) (Collatz-Wielandt on A^T A, power steps
+    on A^T A + I from the all-ones vector); what the spectral bound uses."""
+    rp, ci = _arrs(g)
+    rr, cr = _arrs(rev if rev is not None else g)
+    out = ctypes.c_double()
+    with _Weights(w, w_rev if w_rev is not None else w):
+        rc = _load().or_sigma_max(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
+                                  rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32), iters,
+                                  ctypes.byref(out))
+    _ck(rc)
+    return out.value
+
+
+def spectral_bound(g, alpha: float, ell: int, sigma: float, w=None) -> float:
+    """B_ell(V) by the spectral bound (Lemma "spectral-bound") with sigma."""
+    with _Weights(w, None):
+        W = walk_totals(g, alpha, ell)
+    return float(_load().or_spectral_bound(alpha, float(sigma), g.n, W[ell]))
+
+
+def score(g, S, alpha: float, eps: float, max_ell: int = 100000, w=None, sigma=None):
     """GED_{<=ell*}(S) by the paper's score algorithm.
 
     Returns (c, ell*, B_ell*, phi) with phi[i] = alpha^i phi_i(S), i = 0..ell*.
+    sigma (an upper estimate of sigma_max) selects the spectral tail bound.
     """
     rp, ci = _arrs(g)
     Sb, sl = _grp(S)
@@ -177,7 +223,7 @@ def score(g, S, alpha: float, eps: float, max_ell: int = 100000, w=None):
     ell = ctypes.c_int32()
     B = ctypes.c_double()
     phi = np.zeros(max_ell + 1)
-    with _Weights(w, None):
+    with _Weights(w, None), _Spectral(sigma):
         rc = _load().or_score(g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
                          Sb.ctypes.data_as(P_I32), sl, alpha, eps, max_ell, ctypes.byref(c),
                          ctypes.byref(ell), ctypes.byref(B), phi.ctypes.data_as(P_F64))
@@ -229,7 +275,8 @@ def pinit(g, S, alpha: float, ell: int, rev=None, w=None, w_rev=None) -> np.ndar
 
 def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
            forced_ell: int = 1, max_ell: int = 1 << 16, rev=None, with_score: bool = True,
-           stochastic: bool = False, eta: float = 0.1, seed: int = 1, w=None, w_rev=None):
+           stochastic: bool = False, eta: float = 0.1, seed: int = 1, w=None, w_rev=None,
+           sigma=None):
     """Greedy GED-Walk maximisation (lazy greedy with P-initialisation).
 
     Returns a dict: group (pick order), ell/L1/U2/L2/B/evals per pick, score
@@ -249,7 +296,7 @@ def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
     sc_ell = ctypes.c_int32(0)
     if w is not None and rev is not None and w_rev is None:
         raise ValueError("a weighted directed graph needs the reverse graph's weights")
-    with _Weights(w, w_rev if w_rev is not None else w):
+    with _Weights(w, w_rev if w_rev is not None else w), _Spectral(sigma):
         rc = _load().or_greedy_ex(
                           g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
                           rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32), k, alpha, eps,

@@ -30,7 +30,10 @@
  *   - ties in the priority queues go to the larger value, then the smaller id;
  *   - if only one candidate remains it is accepted without a separation test;
  *   - max degree for the combinatorial bound is the maximum out-degree (equal
- *     to the maximum degree for undirected graphs).
+ *     to the maximum degree for undirected graphs);
+ *   - the spectral bound needs sigma_max itself; an upper estimate replaces it
+ *     (any value >= sigma_max keeps the bound valid), computed by
+ *     or_sigma_max.
  */
 #include <math.h>
 #include <stdint.h>
@@ -177,9 +180,88 @@ double or_comb_bound(double alpha, double deg_max, double W_ell) {
   return alpha * (deg_max / (1.0 - ad)) * W_ell;
 }
 
+/* ------------------------------------------------------- spectral bound --- */
+
+/*
+ * Tail bound selector (Section 3.1.2): g_sigma = 0 selects the combinatorial
+ * bound (Eq. comb-bound, needs alpha < 1/deg_max); g_sigma > 0 selects the
+ * spectral bound (Lemma "spectral-bound", Eq. spectral-bound) with that upper
+ * estimate of sigma_max, which needs only alpha < 1/sigma.  Set for one public
+ * call by or_set_spectral (single-threaded oracle).
+ */
+static double g_sigma = 0.0;
+
+void or_set_spectral(double sigma) { g_sigma = sigma; }
+
+/* sqrt(|V|) * alpha^{ell+1} * sigma / (1 - alpha sigma) * sum_x omega_ell(x), with
+ * the decayed total W_ell = alpha^ell sum_x omega_ell(x) */
+double or_spectral_bound(double alpha, double sigma, int64_t n, double W_ell) {
+  return sqrt((double)n) * alpha * (sigma / (1.0 - alpha * sigma)) * W_ell;
+}
+
+static double tail_bound(double alpha, double deg_max, int64_t n, double W_ell) {
+  if (g_sigma > 0.0) return or_spectral_bound(alpha, g_sigma, n, W_ell);
+  return or_comb_bound(alpha, deg_max, W_ell);
+}
+
 static int check_alpha(double alpha, double deg_max) {
   if (!(alpha > 0.0) || !isfinite(alpha)) return OR_ERR_ALPHA;
+  if (g_sigma > 0.0) return alpha * g_sigma < 1.0 ? OR_OK : OR_ERR_ALPHA;
   if (deg_max > 0 && !(alpha * deg_max < 1.0)) return OR_ERR_ALPHA;
+  return OR_OK;
+}
+
+/*
+ * Upper estimate of sigma_max = ||A||_2, the largest singular value of the
+ * adjacency matrix (Section 2.1; the spectral bound needs a value >= it).
+ * sigma_max^2 is the Perron root of the nonnegative symmetric B = A^T A, and
+ * for every positive vector x the Collatz-Wielandt inequality gives
+ * rho(B) <= max_v (B x)_v / x_v.  So, from x_0 = 1, for k = 1..iters:
+ *     z   = B x_{k-1}
+ *     c_k = max_v z_v / x_{k-1,v}
+ *     x_k = max((z + x_{k-1}) / max_v (z_v + x_{k-1,v}), 2^-990)
+ * (a power step on B + I, which converges also on bipartite graphs, clamped
+ * so every entry stays positive), and
+ *     sigma_hat = sqrt(min_k c_k * (1 + 2^-40)),
+ * the factor covering the rounding of the sums.  (rp_r, ci_r) are the rows of
+ * A^T (out-neighbours); an undirected graph passes (rp, ci) again.  Weights,
+ * when set, are w for A and w_rev for A^T.
+ */
+int or_sigma_max(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
+                 const int32_t *ci_r, int32_t iters, double *out) {
+  if (n < 1 || iters < 1) return OR_ERR_ARG;
+  double *x = (double *)malloc(sizeof(double) * (size_t)n);
+  double *y = (double *)malloc(sizeof(double) * (size_t)n);
+  double *z = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!x || !y || !z) {
+    free(x);
+    free(y);
+    free(z);
+    return OR_ERR_NOMEM;
+  }
+  const double floor_v = ldexp(1.0, -990);
+  for (int64_t v = 0; v < n; ++v) x[v] = 1.0;
+  double best = INFINITY;
+  for (int32_t k = 1; k <= iters; ++k) {
+    for (int64_t v = 0; v < n; ++v) y[v] = row_sum_w(rp, ci, g_w, v, x);       /* A x */
+    for (int64_t v = 0; v < n; ++v) z[v] = row_sum_w(rp_r, ci_r, g_w_rev, v, y); /* A^T A x */
+    double c = 0.0, m = 0.0;
+    for (int64_t v = 0; v < n; ++v) {
+      const double r = z[v] / x[v];
+      if (r > c) c = r;
+      const double s = z[v] + x[v];
+      if (s > m) m = s;
+    }
+    if (c < best) best = c;
+    for (int64_t v = 0; v < n; ++v) {
+      const double t = (z[v] + x[v]) / m;
+      x[v] = t > floor_v ? t : floor_v;
+    }
+  }
+  *out = sqrt(best * (1.0 + ldexp(1.0, -40)));
+  free(x);
+  free(y);
+  free(z);
   return OR_OK;
 }
 
@@ -266,7 +348,7 @@ int or_score(int64_t n, const int64_t *rp, const int32_t *ci, const int32_t *S, 
       nsum_add(&w, hit[v]);
       nsum_add(&w, miss[v]);
     }
-    double B = or_comb_bound(alpha, deg_max, nsum_get(&w));
+    double B = tail_bound(alpha, deg_max, n, nsum_get(&w));
     if (B < eps) {
       *out_c = nsum_get(&c);
       *out_ell = i;
@@ -759,7 +841,7 @@ int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t 
     }
     rc = or_walk_totals(n, rp, ci, alpha, g.ell, W);
     if (rc) goto done;
-    g.B = or_comb_bound(alpha, deg_max, W[g.ell]);
+    g.B = tail_bound(alpha, deg_max, n, W[g.ell]);
     g.stamp++;
     if (lazy) {
       rc = or_pinit(n, rp, ci, rp_r, ci_r, g.inS, alpha, g.ell, g.L);

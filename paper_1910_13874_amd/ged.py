@@ -30,6 +30,7 @@ c_graph_p = ctypes.c_void_p
 
 GED_UNDIRECTED = 1
 GED_DIRECTED = 2
+GED_KEEP_ORDER = 8
 
 STATUS = {0: "ok", -1: "bad argument", -2: "vertex out of range", -3: "alpha out of range",
           -4: "eps out of range", -5: "malformed graph", -6: "out of memory",
@@ -137,13 +138,15 @@ def _i32(a):
 class GedGraph:
     """A graph resident on the GPU (CSR copied at construction)."""
 
-    def __init__(self, n, row_ptr, col_idx, directed=False, weights=None):
+    def __init__(self, n, row_ptr, col_idx, directed=False, weights=None, keep_order=False):
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         if ci.size == 0:
             ci = np.zeros(1, dtype=np.int32)
         h = c_graph_p()
         flags = GED_DIRECTED if directed else GED_UNDIRECTED
+        if keep_order:
+            flags |= GED_KEEP_ORDER
         nnz = int(rp[-1])
         if weights is None:
             rc = _lib.ged_graph_create(n, nnz, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
@@ -161,9 +164,9 @@ class GedGraph:
         self.weighted = weights is not None
 
     @classmethod
-    def from_graph(cls, g, weights=None):
+    def from_graph(cls, g, weights=None, keep_order=False):
         return cls(g.n, g.row_ptr, g.col_idx, directed=getattr(g, "directed", False),
-                   weights=weights)
+                   weights=weights, keep_order=keep_order)
 
     @property
     def handle(self):

@@ -7,7 +7,9 @@ the recurrences do not produce themselves:
   * hand-derived closed forms stored in tests/golden/closed_forms.txt;
   * the paper's structural facts: GED(empty) = 0, GED(V) = sum of Katz scores,
     vertex covers, monotonicity and submodularity (Section 2.2);
-  * validity of the combinatorial tail bound (Eq. comb-bound);
+  * validity of the combinatorial tail bound (Eq. comb-bound) and of the
+    spectral bound (Lemma "spectral-bound") with sigma_max from closed forms
+    and a library SVD;
   * the (1 - 1/e) OPT - eps guarantee of the greedy (Section 3.2.2 and the
     additive-error greedy proposition of the appendix) against brute-force OPT,
     and an exact-rational eager greedy with the same decision rule.
@@ -519,3 +521,108 @@ def test_stochastic_picks_best_of_sample(seed):
                      for x in smp}
             assert gains[int(u)] >= max(gains.values()) - Fraction(EPS) / k
             S.append(int(u))
+
+
+# -------------------------------------------------------- spectral bound --
+# sigma_hat (an upper estimate of sigma_max, Section 2.1) against closed forms
+# and a library SVD; the spectral bound (Lemma "spectral-bound") against the
+# exact tail; scoring and greedy under it against the exact series.
+
+def _undirected(n, edges, name):
+    return inputs.from_edges(n, [a for a, b in edges], [b for a, b in edges], symmetrize=True,
+                             name=name)
+
+
+SIGMA_CASES = [
+    (_undirected(6, [(a, b) for a in range(6) for b in range(a + 1, 6)], "K6"), 5.0),
+    (_undirected(10, [(0, j) for j in range(1, 10)], "star9"), 3.0),
+    (_undirected(8, [(i, (i + 1) % 8) for i in range(8)], "C8"), 2.0),
+    (_undirected(6, [(i, i + 1) for i in range(5)], "P6"), 2.0 * math.cos(math.pi / 7)),
+    (_undirected(7, [(a, b) for a in range(3) for b in range(3, 7)], "K3_4"), math.sqrt(12.0)),
+]
+
+
+@pytest.mark.parametrize("g,sigma", SIGMA_CASES, ids=lambda c: getattr(c, "name", ""))
+def test_sigma_closed_forms(g, sigma):
+    s = oracle.sigma_max(g)
+    assert s >= sigma and s <= sigma * (1 + 1e-9), (g.name, s, sigma)
+
+
+def _dense(g, w=None):
+    A = np.zeros((g.n, g.n))
+    for v in range(g.n):
+        for j in range(g.row_ptr[v], g.row_ptr[v + 1]):
+            A[g.col_idx[j], v] += 1.0 if w is None else w[j]  # arc u -> v
+    return A
+
+
+@pytest.mark.parametrize("kind", ["er", "ba", "directed", "weighted", "edgeless"])
+def test_sigma_matches_svd_from_above(kind):
+    rev = w = w_rev = None
+    if kind == "er":
+        g = inputs.erdos_renyi(120, 400, 61)
+    elif kind == "ba":
+        g = inputs.barabasi_albert(300, 3, 62)
+    elif kind == "directed":
+        r = inputs.uniform_ints(800, 100, 63)
+        g = inputs.from_edges(100, r[0::2], r[1::2], symmetrize=False, name="dir100")
+        rev = inputs.reverse(g)
+    elif kind == "weighted":
+        g = inputs.barabasi_albert(200, 3, 64)
+        deg = g.degrees.astype(np.float64)
+        rows = np.repeat(np.arange(g.n), g.degrees)
+        w = 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+        w_rev = w
+    else:
+        g = inputs.from_edges(5, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    s = oracle.sigma_max(g, rev=rev, w=w, w_rev=w_rev)
+    ref = np.linalg.norm(_dense(g, w), 2)
+    assert s >= ref * (1 - 1e-14), (kind, s, ref)
+    assert s <= ref * (1 + 1e-6) + 1e-300, (kind, s, ref)
+
+
+@pytest.mark.parametrize("g", tiny_graphs()[:7], ids=lambda g: g.name)
+def test_spectral_bound_formula_and_validity(g):
+    sigma = oracle.sigma_max(g)
+    if sigma == 0.0:
+        return
+    alpha = 0.9 / sigma  # beyond 1/deg_max whenever sigma < deg_max
+    arcs = exact.arcs_of(g.n, g.row_ptr, g.col_idx)
+    gedV = exact.ged_exact(g.n, g.row_ptr, g.col_idx, range(g.n), alpha)
+    W = exact.induced_walk_counts(g.n, arcs, range(g.n), 12)
+    a = Fraction(alpha)
+    partial = Fraction(0)
+    for ell in range(1, 13):
+        partial += a ** ell * W[ell]
+        # sqrt(n) alpha^{ell+1} sigma / (1 - alpha sigma) * sum_x omega_ell(x)
+        want = math.sqrt(g.n) * float(a ** (ell + 1)) * sigma / (1 - alpha * sigma) * W[ell]
+        got = oracle.spectral_bound(g, alpha, ell, sigma)
+        assert rel(got, want) <= 1e-12
+        assert gedV - partial <= Fraction(got)
+
+
+@pytest.mark.parametrize("g", tiny_graphs()[:7] + tiny_graphs()[8:10], ids=lambda g: g.name)
+def test_score_and_greedy_under_spectral_bound(g):
+    sigma = oracle.sigma_max(g)
+    if sigma == 0.0:
+        return
+    alpha = 0.8 / sigma
+    delta = oracle.max_out_degree(g)
+    if alpha * delta >= 1:  # outside the combinatorial bound's range
+        with pytest.raises(ValueError):
+            oracle.score(g, [0], alpha, EPS)
+    for S in groups_of(g.n, 3):
+        c, ell, B, _ = oracle.score(g, S, alpha, EPS, sigma=sigma)
+        ex = exact.ged_exact(g.n, g.row_ptr, g.col_idx, S, alpha)
+        assert B < EPS
+        assert Fraction(c) <= ex * (1 + Fraction(1, 10 ** 12)) + Fraction(1, 10 ** 15)
+        assert ex - Fraction(c) <= Fraction(B) * (1 + Fraction(1, 10 ** 9)) + Fraction(1, 10 ** 15)
+        # ell* is the first walk length whose spectral bound is below eps
+        if ell > 1:
+            assert oracle.spectral_bound(g, alpha, ell - 1, sigma) >= EPS
+    k = 2
+    r = oracle.greedy(g, k, alpha, EPS, sigma=sigma)
+    val = exact.ged_exact(g.n, g.row_ptr, g.col_idx, r["group"], alpha)
+    opt, _ = exact.opt_exact(g.n, g.row_ptr, g.col_idx, k, alpha)
+    assert val >= (1 - 1 / Fraction(math.e)) * opt - Fraction(EPS)
+    assert rel(r["score"], oracle.score(g, r["group"], alpha, EPS, sigma=sigma)[0]) == 0.0
