@@ -102,17 +102,42 @@ double ged_default_alpha(const ged_graph *g);
  */
 int ged_set_stream(ged_graph *g, void *hip_stream);
 
+/*
+ * Tail bound used to choose ell* and, in the greedy, U = L + B_ell
+ * (Section 3.1.2).  GED_BOUND_COMBINATORIAL (the default) is Eq. comb-bound
+ * and needs alpha * deg_max < 1.  GED_BOUND_SPECTRAL is Lemma
+ * "spectral-bound", sqrt(n) alpha sigma / (1 - alpha sigma) * sum(t_ell), which
+ * needs only alpha * sigma < 1; sigma is an upper estimate of sigma_max
+ * (ged_sigma_max).  Changing the bound drops the cached precomputation.
+ * Returns GED_ERR_ARG for an unknown kind.
+ */
+#define GED_BOUND_COMBINATORIAL 0
+#define GED_BOUND_SPECTRAL 1
+int ged_set_tail_bound(ged_graph *g, int32_t kind);
+
+/*
+ * Upper estimate of sigma_max, the largest singular value of the (weighted)
+ * adjacency matrix (Section 2.1; the spectral bound is valid with any value
+ * >= sigma_max).  sigma_max^2 is the Perron root of B = A^T A, and for every
+ * positive x the Collatz-Wielandt inequality bounds it by max_v (Bx)_v / x_v;
+ * from x = 1 the library takes 100 power steps on B + I (entries kept
+ * >= 2^-990) and returns sqrt(min over the steps of that maximum * (1 + 2^-40)).
+ * Computed on the device on first use and cached on the handle.
+ */
+int ged_sigma_max(ged_graph *g, double *out_sigma);
+
 typedef struct {
   int32_t ell;       /* ell*: first walk length whose tail bound is < eps */
-  double bound;      /* B_{ell*}, the combinatorial bound (Eq. comb-bound) */
+  double bound;      /* B_{ell*} of the selected tail bound */
   double walk_total; /* alpha^{ell*} * sum_x omega_{ell*}(x) */
 } ged_score_info;
 
 /*
  * Per-(graph, alpha, eps) precomputation: the decayed total-walk levels
  * t_i = alpha * A t_{i-1}, t_0 = 1 (Katz walk counts, Section 2.1), their sums
- * and the bound B_i = alpha*deg_max/(1 - alpha*deg_max) * sum(t_i)
- * (Eq. comb-bound) until B_i < eps.  ell* does not depend on S because the
+ * and the tail bound B_i (combinatorial: alpha*deg_max/(1 - alpha*deg_max) *
+ * sum(t_i), Eq. comb-bound; or spectral, see ged_set_tail_bound) until
+ * B_i < eps.  ell* does not depend on S because the
  * bound is taken on the whole vertex set (Eq. katz-bound).  Called implicitly
  * by the score entry points; cached on the handle.  info may be NULL.
  */

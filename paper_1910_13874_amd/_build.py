@@ -17,6 +17,7 @@ HIP_SOURCES = [
     "ged_api.hip",
     "ged_batch.hip",
     "ged_split.hip",
+    "ged_spectral.hip",
     "ged_greedy.hip",
     "ged_server.hip",
 ]

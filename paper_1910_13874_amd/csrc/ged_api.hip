@@ -77,6 +77,12 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
 }
 
 double comb_bound(ged_graph *g, double alpha, double W_ell) {
+  if (g->bound_kind == GED_BOUND_SPECTRAL) {
+    // Lemma "spectral-bound": sqrt(n) alpha^{ell+1} sigma / (1 - alpha sigma) *
+    // sum_x omega_ell(x)
+    const double sg = sigma_max(g);
+    return sqrt((double)g->n) * alpha * (sg / (1.0 - alpha * sg)) * W_ell;
+  }
   // Eq. comb-bound: alpha^{ell+1} * D/(1 - alpha D) * sum_x omega_ell(x), with the
   // decayed total W_ell = alpha^ell sum_x omega_ell(x).
   const double D = g->weighted ? g->max_wdeg : (double)g->max_deg;
@@ -86,8 +92,12 @@ double comb_bound(ged_graph *g, double alpha, double W_ell) {
 int check_alpha_eps(ged_graph *g, double alpha, double eps) {
   const double D = g->weighted ? g->max_wdeg : (double)g->max_deg;
   if (!(alpha > 0.0) || !isfinite(alpha)) return fail(GED_ERR_ALPHA, "alpha must be > 0");
-  if (D > 0 && !(alpha * D < 1.0))
+  if (g->bound_kind == GED_BOUND_SPECTRAL) {
+    if (!(alpha * sigma_max(g) < 1.0))
+      return fail(GED_ERR_ALPHA, "alpha * sigma_max must be < 1 (spectral bound)");
+  } else if (D > 0 && !(alpha * D < 1.0)) {
     return fail(GED_ERR_ALPHA, "alpha * max out-degree must be < 1 (combinatorial bound)");
+  }
   if (!(eps > 0.0) || !isfinite(eps)) return fail(GED_ERR_EPS, "eps must be finite and > 0");
   return GED_OK;
 }
@@ -597,6 +607,33 @@ extern "C" int ged_prepare(ged_graph *g, double alpha, double eps, ged_score_inf
       info->bound = g->prep.bound;
       info->walk_total = g->prep.W[g->prep.ell];
     }
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_set_tail_bound(ged_graph *g, int32_t kind) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  if (kind != GED_BOUND_COMBINATORIAL && kind != GED_BOUND_SPECTRAL)
+    return fail(GED_ERR_ARG, "unknown tail bound");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    GED_HIP(hipStreamSynchronize(g->stream));
+    if (g->bound_kind != kind) {
+      g->bound_kind = kind;
+      g->prep.valid = false;
+      g->prep.tr_r = -1;
+      g->prep.W.clear();
+      g->prep.tail_level = -1;
+    }
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_sigma_max(ged_graph *g, double *out_sigma) {
+  if (!g || !out_sigma) return fail(GED_ERR_ARG, "null argument");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    *out_sigma = sigma_max(g);
     return GED_OK;
   });
 }

@@ -289,6 +289,8 @@ struct ged_graph {
   int64_t n = 0, nnz = 0;
   uint32_t flags = 0;
   int32_t max_deg = 0;          // maximum out-degree (structural)
+  int32_t bound_kind = 0;       // GED_BOUND_COMBINATORIAL or GED_BOUND_SPECTRAL
+  double sigma = -1.0;          // upper estimate of sigma_max, -1 until computed
   double max_wdeg = 0;          // maximum weighted out-degree (weighted graphs)
   bool weighted = false;
   std::vector<int> h_rp;        // host copy of row_ptr (int32) for partitioning
@@ -351,7 +353,11 @@ double walk_total(ged_graph *g, int ell);
 // The decayed total-walk levels t_0..t_L (extends the stored levels on demand;
 // the buffer may move).
 const double *t_levels_to(ged_graph *g, int L);
+// Tail bound B_ell(V) from W_ell = alpha^ell sum_x omega_ell(x): the
+// combinatorial bound or the spectral one, as selected for the graph.
 double comb_bound(ged_graph *g, double alpha, double W_ell);
+// Upper estimate of sigma_max (ged_spectral.hip); computed once per graph.
+double sigma_max(ged_graph *g);
 int check_alpha_eps(ged_graph *g, double alpha, double eps);
 StepArgs base_args(ged_graph *g, bool reverse = false);
 // Step launch, timed with HIP events around the main kernel when profiling is

@@ -31,6 +31,8 @@ c_graph_p = ctypes.c_void_p
 GED_UNDIRECTED = 1
 GED_DIRECTED = 2
 GED_KEEP_ORDER = 8
+GED_BOUND_COMBINATORIAL = 0
+GED_BOUND_SPECTRAL = 1
 
 STATUS = {0: "ok", -1: "bad argument", -2: "vertex out of range", -3: "alpha out of range",
           -4: "eps out of range", -5: "malformed graph", -6: "out of memory",
@@ -76,6 +78,8 @@ _sig("ged_set_stream", ctypes.c_int, [c_graph_p, ctypes.c_void_p])
 _sig("ged_prepare", ctypes.c_int, [c_graph_p, ctypes.c_double, ctypes.c_double,
                                    ctypes.POINTER(ScoreInfo)])
 _sig("ged_invalidate", ctypes.c_int, [c_graph_p])
+_sig("ged_set_tail_bound", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_sigma_max", ctypes.c_int, [c_graph_p, P_F64])
 _sig("ged_score", ctypes.c_int, [c_graph_p, P_I32, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double, P_F64, ctypes.POINTER(ScoreInfo)])
 _sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, ctypes.c_double,
@@ -223,6 +227,18 @@ class GedGraph:
     def invalidate(self):
         """Drop the cached per-(alpha, eps) precomputation."""
         _ck(_lib.ged_invalidate(self.handle), "ged_invalidate")
+
+    def set_tail_bound(self, kind):
+        """"combinatorial" (Eq. comb-bound, the default) or "spectral"
+        (Lemma spectral-bound, valid for alpha < 1/sigma_max)."""
+        code = {"combinatorial": GED_BOUND_COMBINATORIAL, "spectral": GED_BOUND_SPECTRAL}[kind]
+        _ck(_lib.ged_set_tail_bound(self.handle, code), "ged_set_tail_bound")
+
+    def sigma_max(self):
+        """Upper estimate of the largest singular value of the adjacency matrix."""
+        out = ctypes.c_double()
+        _ck(_lib.ged_sigma_max(self.handle, ctypes.byref(out)), "ged_sigma_max")
+        return out.value
 
     def score(self, S, alpha=None, eps=1e-4, with_info=False):
         arr, ptr = _i32(S)

@@ -359,3 +359,54 @@ def test_split_ell_sweep(ged, name):
         for j, c in enumerate(ref):
             assert rel(b[j], c) <= REL, (name, ell, j, b[j], c)
     gg.close()
+
+
+@pytest.mark.parametrize("name", ["ba", "directed", "weighted"])
+def test_spectral_bound(ged, name):
+    """sigma_max estimate, ell* and scores / greedy under the spectral tail bound
+    with alpha beyond 1/deg_max (where the combinatorial bound does not apply)."""
+    rev = w = None
+    if name == "ba":
+        g = inputs.barabasi_albert(20000, 4, 71)
+    elif name == "directed":
+        r = inputs.uniform_ints(2 * 40000, 5000, 72)
+        g = inputs.from_edges(5000, r[0::2], r[1::2], symmetrize=False, name="dir5k")
+        g.directed = True
+        rev = inputs.reverse(g)
+    else:
+        g = inputs.barabasi_albert(8000, 3, 73)
+        deg = g.degrees.astype(np.float64)
+        rows = np.repeat(np.arange(g.n), g.degrees)
+        w = 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+    say(f"[spectral] {name} n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g, weights=w)
+    s_gpu = gg.sigma_max()
+    s_ora = oracle.sigma_max(g, rev=rev, w=w, w_rev=None if rev is not None else w)
+    assert rel(s_gpu, s_ora) <= 1e-9, (s_gpu, s_ora)
+    alpha = 0.5 / s_gpu
+    D = oracle.max_weighted_out_degree(g, w) if w is not None else oracle.max_out_degree(g)
+    assert alpha * D >= 1.0  # outside the combinatorial bound's range
+    with pytest.raises(ged.GedError) as e:
+        gg.score([0], alpha, EPS)
+    assert e.value.code == -3
+    gg.set_tail_bound("spectral")
+    with pytest.raises(ged.GedError):
+        gg.score([0], 1.0 / s_gpu, EPS)
+    groups = [inputs.group(g.n, size, seed) for seed, size in [(1, 1), (2, 9), (3, 120)]]
+    for S in groups:
+        s, ell, B = gg.score(S, alpha, EPS, with_info=True)
+        c, ell_o, B_o, _ = oracle.score(g, S, alpha, EPS, w=w, sigma=s_gpu)
+        assert ell == ell_o and rel(s, c) <= REL and rel(B, B_o) <= 1e-9, (name, S.size, s, c)
+    if rev is None:
+        off = np.array([0, groups[0].size, groups[0].size + groups[1].size], dtype=np.int64)
+        b = gg.score_batch(off, np.concatenate(groups[:2]).astype(np.int32), alpha, EPS)
+        for j in range(2):
+            assert rel(b[j], oracle.score(g, groups[j], alpha, EPS, w=w, sigma=s_gpu)[0]) <= REL
+    rg = gg.greedy(4, alpha, EPS)
+    ro = oracle.greedy(g, 4, alpha, EPS, rev=rev, w=w, sigma=s_gpu,
+                       w_rev=None if rev is not None else w)
+    compare_greedy(rg, ro, f"spectral {name}")
+    gg.set_tail_bound("combinatorial")
+    with pytest.raises(ged.GedError):
+        gg.score([0], alpha, EPS)
+    gg.close()
