@@ -189,31 +189,47 @@ int prepare(ged_graph *g, double alpha, double eps) {
   pc.alpha = alpha;
   pc.eps = eps;
   pc.tail_level = -1;
-  pc.t_count = pc.ell + 1;
+  pc.t_ext_count = 0;
   pc.valid = true;
   return GED_OK;
 }
 
-const double *t_levels_to(ged_graph *g, int L) {
+void t_levels_to(ged_graph *g, int L) {
   PrepCache &pc = g->prep;
-  if (L < pc.t_count) return pc.t_levels.as<const double>();
+  const int have = pc.ell + pc.t_ext_count;  // highest level stored
+  if (L <= have) return;
   hipStream_t st = g->stream;
   const int64_t n = g->n;
   Partition &p = partition(g, 1);
   g->pws.fit(p);
-  ensure_levels(pc, n, L + 1, st);
-  double *T = pc.t_levels.as<double>();
-  for (int i = pc.t_count; i <= L; ++i) {
+  const size_t need = sizeof(double) * (size_t)n * (size_t)(L - pc.ell);
+  if (pc.t_ext.bytes < need) {
+    DBuf nb;
+    nb.ensure(std::max(need, 2 * pc.t_ext.bytes));
+    if (pc.t_ext_count > 0) {
+      GED_HIP(hipMemcpyAsync(nb.p, pc.t_ext.p, sizeof(double) * (size_t)n * pc.t_ext_count,
+                             hipMemcpyDeviceToDevice, st));
+      GED_HIP(hipStreamSynchronize(st));
+    }
+    std::swap(pc.t_ext.p, nb.p);
+    std::swap(pc.t_ext.bytes, nb.bytes);
+  }
+  for (int i = have + 1; i <= L; ++i) {
     StepArgs a = base_args(g);
     g->pws.into(a);
     a.C = 1;
     a.alpha = pc.alpha;
-    a.X = T + (size_t)(i - 1) * n;
-    a.Y = T + (size_t)i * n;
+    a.X = t_level(g, i - 1);
+    a.Y = pc.t_ext.as<double>() + (size_t)(i - pc.ell - 1) * n;
     run_step(g, p, a, IN_VEC, OUT_PLAIN, st);
+    pc.t_ext_count = i - pc.ell;
   }
-  pc.t_count = L + 1;
-  return T;
+}
+
+const double *t_level(const ged_graph *g, int j) {
+  const PrepCache &pc = g->prep;
+  if (j <= pc.ell) return pc.t_levels.as<const double>() + (size_t)j * g->n;
+  return pc.t_ext.as<const double>() + (size_t)(j - pc.ell - 1) * g->n;
 }
 
 double walk_total(ged_graph *g, int ell) {

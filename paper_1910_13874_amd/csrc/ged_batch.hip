@@ -127,16 +127,21 @@ static int autotune_split(ged_graph *g, BatchWs &b, const SplitPlan &pl) {
   for (int C : cands) {
     try {
       split_fit(g, b.sw, pl, C, 1, st);
-      for (int r = 0; r < 2; ++r) {
-        if (r == 1) GED_HIP(hipEventRecord(e0, st));
+      split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);  // warm-up
+      float ms = 1e30f;
+      for (int r = 0; r < 2; ++r) {  // best of two timed passes
+        GED_HIP(hipEventRecord(e0, st));
         split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);
+        GED_HIP(hipEventRecord(e1, st));
+        GED_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        GED_HIP(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, t);
       }
-      GED_HIP(hipEventRecord(e1, st));
-      GED_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      GED_HIP(hipEventElapsedTime(&ms, e0, e1));
+      // a wider tile must win by 3 % per column (it holds more memory and
+      // leaves more columns idle in the last tile of a batch)
       const double per_col = ms / C;
-      if (per_col < best) {
+      if (per_col < best * 0.97) {
         best = per_col;
         best_c = C;
       }
@@ -251,12 +256,19 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
   }
   if (split) {
     size_t wl_need = 1;
+    int64_t deg_tile = 1;  // largest member-degree sum of a tile: about its worklist size
     for (int g0 = 0; g0 < G; g0 += C) {
       size_t need = 0;
-      for (int j = g0; j < std::min(G, g0 + C); ++j) need += split_wl_need(g, degsum[j]);
+      int64_t ds = 0;
+      for (int j = g0; j < std::min(G, g0 + C); ++j) {
+        need += split_wl_need(g, degsum[j]);
+        ds += degsum[j];
+      }
       wl_need = std::max(wl_need, need);
+      deg_tile = std::max(deg_tile, ds);
     }
     split_fit(g, b.sw, pl, C, wl_need, st);
+    b.sw.wl_blocks = split_wl_blocks(deg_tile);
     b.sw.zero = false;
   } else {
     b.X.ensure(sizeof(double) * (size_t)n * C);
@@ -286,6 +298,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
                                    b.sw.ws.red2.p, g->omega2.p, g->prep.tr.p,
                                    g->prep.t_levels.p, (const void *)st, abits,
                                    (const void *)(uintptr_t)b.sw.wl_cap,
+                                   (const void *)(intptr_t)b.sw.wl_blocks,
                                    (const void *)(intptr_t)split,
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
                                    (const void *)(intptr_t)C};

@@ -58,10 +58,12 @@ __global__ void k_mask_bit(uint32_t *mask, int v, int value) {
 // m_0 = b_0 = 1 for x outside S: every term of Lemma "initialize" once, no
 // subtraction.  ub[x] = -1 marks members of S.
 // Levels j <= ma come from the miss chain M, higher ones from the total-walk
-// levels T (an upper bound: walks that avoid S are walks).  Bl (reverse
-// chain, directed graphs) null means b = m.
+// levels (an upper bound: walks that avoid S are walks), held in T for
+// j <= tb and in Te (level tb + 1 first) above.  Bl (reverse chain, directed
+// graphs) null means b = m.
 __global__ __launch_bounds__(kBlock) void k_pbound(const double *__restrict__ M,
-                                                   const double *__restrict__ T, int ma,
+                                                   const double *__restrict__ T,
+                                                   const double *__restrict__ Te, int tb, int ma,
                                                    const double *__restrict__ Bl, int n, int ell,
                                                    const uint32_t *__restrict__ smask,
                                                    const double *__restrict__ stale,
@@ -72,7 +74,10 @@ __global__ __launch_bounds__(kBlock) void k_pbound(const double *__restrict__ M,
     ub[x] = -1.0;
     return;
   }
-  auto mv = [&](int j) { return (j <= ma ? M : T)[(size_t)j * n + x]; };
+  auto mv = [&](int j) {
+    if (j <= ma) return M[(size_t)j * n + x];
+    return j <= tb ? T[(size_t)j * n + x] : Te[(size_t)(j - tb - 1) * n + x];
+  };
   double pre = 1.0, tail = 0.0, acc = 0.0;
   for (int s = 0; s < ell; ++s) {
     if (s > 0) {
@@ -276,10 +281,13 @@ static void compute_bounds(GreedyCtx &c, int ell) {
   const double *M = c.m_levels.as<const double>();
   const double *B = c.g->flags == GED_DIRECTED ? c.b_levels.as<const double>() : nullptr;
   const int ma = c.split ? (ell + 1) / 2 : ell;
-  const double *T = c.split ? t_levels_to(c.g, ell) : M;
-  hipLaunchKernelGGL(k_pbound, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, c.st, M, T, ma,
-                     B, c.n, ell, c.smask.as<const uint32_t>(), c.stale.as<const double>(),
-                     c.ub.as<double>(), kBoundSlack);
+  if (c.split) t_levels_to(c.g, ell);
+  const PrepCache &pc = c.g->prep;
+  const double *T = pc.t_levels.as<const double>();
+  const double *Te = pc.t_ext_count > 0 ? pc.t_ext.as<const double>() : T;
+  hipLaunchKernelGGL(k_pbound, dim3((c.n + kBlock - 1) / kBlock), dim3(kBlock), 0, c.st, M, T, Te,
+                     pc.ell, ma, B, c.n, ell, c.smask.as<const uint32_t>(),
+                     c.stale.as<const double>(), c.ub.as<double>(), kBoundSlack);
   GED_HIP(hipGetLastError());
 }
 

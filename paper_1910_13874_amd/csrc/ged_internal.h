@@ -243,7 +243,11 @@ struct PrepCache {
   int tail_cur = 0;
   DBuf tr;                     // [n] sum_{c=1..tr_r} t_c (split scoring)
   int tr_r = -1;               // -1: not built for this (alpha, eps)
-  int t_count = 0;             // levels held in t_levels (ell* + 1 after prepare)
+  // Levels beyond ell* (the greedy's walk length may exceed ell*) live in a
+  // buffer of their own, so t_levels never moves after prepare (a server's
+  // score pool may be reading it on another stream).
+  DBuf t_ext;                  // [t_ext_count * n] levels ell*+1 ..
+  int t_ext_count = 0;
 };
 
 // ------------------------------------------------------- split scoring --
@@ -263,6 +267,7 @@ struct SplitWs {
   DBuf lv;               // double [nlv*n*C] stored dense levels
   DBuf wl, wl_n;         // uint64 worklist [wl_cap], uint32 length
   unsigned wl_cap = 0;
+  int wl_blocks = 64;    // grid of the worklist kernels (any value is correct)
   size_t cnt_bytes = 0;  // bytes of the count layout the arrays were zeroed for
   bool zero = false;
   StepWs ws;
@@ -350,9 +355,11 @@ Partition &partition(ged_graph *g, int C, bool reverse = false);
 int prepare(ged_graph *g, double alpha, double eps);
 // W[ell] for arbitrary ell (extends the total-walk chain on demand).
 double walk_total(ged_graph *g, int ell);
-// The decayed total-walk levels t_0..t_L (extends the stored levels on demand;
-// the buffer may move).
-const double *t_levels_to(ged_graph *g, int L);
+// Make the decayed total-walk levels t_0..t_L available (levels beyond ell*
+// are computed on demand into prep.t_ext, which may move; t_levels does not).
+void t_levels_to(ged_graph *g, int L);
+// Pointer to level j (j <= ell* or an extended level).
+const double *t_level(const ged_graph *g, int j);
 // Tail bound B_ell(V) from W_ell = alpha^ell sum_x omega_ell(x): the
 // combinatorial bound or the spectral one, as selected for the graph.
 double comb_bound(ged_graph *g, double alpha, double W_ell);
@@ -385,15 +392,20 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
                hipStream_t st);
 // Worklist entries a group needs: min(n, sum of member degrees) + ceil(nnz/chunk).
 size_t split_wl_need(const ged_graph *g, int64_t deg_sum);
+// Grid of the worklist kernels for about `expected_entries` entries.
+int split_wl_blocks(int64_t expected_entries);
 // Dense levels s+1..a of a tile (the last one combining into the block
 // partials of w.ws); the counts of levels <= s must be in place.
 void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
-                 hipStream_t st);
+                 hipStream_t st, bool profile = true);
 // Enqueue one tile of nc <= C groups (g0 .. g0+nc-1 of the device offsets /
 // members / mcol arrays); scores go to out[0..nc).
+// profile = false launches without profiling events (the server enqueues tiles
+// from its own thread).
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
-                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st);
+                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,
+                        bool profile = true);
 // Map caller ids to internal ids, dropping duplicates inside the group;
 // returns the sum of the members' degrees.
 int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> &out);

@@ -1,14 +1,17 @@
 // Continuous-batching request server.
 //
 // Every score query on a graph runs the same number of walk-count levels
-// (ell*, fixed per graph), and a level is one step over the whole graph.  So
-// the server keeps, per resident graph, a pool of SpMM columns ("slots"): one
-// launch advances every occupied column by one level, each column at its own
-// level (the injection reads t_{level(c)}), and a column whose request has run
-// ell* levels is harvested and refilled with the next waiting request before
-// the following step.  Requests therefore join and leave between steps while
-// others are mid-flight, and the pools of different graphs run on their own
-// streams, so their steps overlap on the device.
+// (ell*, fixed per graph), so queries on one graph batch as SpMM columns.
+// Undirected graphs run them as split tiles (the scoring of ged_split.hip:
+// integer pushes, two or so dense levels, a combining level): each launch
+// takes up to C waiting requests of the graph, and requests that arrive while
+// a tile is on the device join the next one.  Directed graphs keep a pool of
+// SpMM columns ("slots"): one launch advances every occupied column by one
+// level, each column at its own level (the injection reads t_{level(c)}), and
+// a column whose request has run ell* levels is harvested and refilled with
+// the next waiting request before the following step.  Either way requests
+// join and leave while others are mid-flight, and the lanes of different
+// graphs run on their own streams, so their work overlaps on the device.
 //
 // Greedy requests run whole (ged_greedy) on worker threads; each needs
 // working memory proportional to n * (walk length), so they are admitted only
@@ -87,6 +90,13 @@ struct Lane {
   std::deque<Req> pending;
   int cur = 0;
   size_t bytes = 0;
+  // split tiles (undirected graphs)
+  bool split = false;
+  SplitPlan pl;
+  SplitWs sw;
+  DBuf tin;                  // tile input: int64 offsets[C+1], int members[m], int columns[m]
+  HBuf h_tin;
+  std::vector<Req> tile;     // requests of the tile in flight
 };
 
 }  // namespace ged
@@ -119,10 +129,31 @@ static void lane_setup(Lane &L, int C) {
   Partition &p = partition(g, C);
   L.ws.fit(p);
   // everything the greedy path may need, so no partition is built while the
-  // pool runs on another thread
+  // lane runs on another thread
   partition(g, 1);
   partition(g, 8);
   if (g->flags == GED_DIRECTED) partition(g, 1, true);
+  if (split_ok(g)) {
+    L.split = true;
+    L.pl = split_plan(g, g->prep.ell);
+    GED_HIP(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
+    GED_HIP(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
+    split_tables(g, L.pl, L.st);  // per-graph tables now, not while greedy runs
+    // worklist: a tile holds requests while their needs (<= n + nnz/512 + 1
+    // each) fit C * (nnz/512 + 1) + 2n entries; one larger group grows it
+    const size_t cap = (size_t)C * split_wl_need(g, 0) + 2 * (size_t)n;
+    split_fit(g, L.sw, L.pl, C, cap, L.st);
+    L.sw.wl_blocks = split_wl_blocks((int64_t)std::min<size_t>(cap, (size_t)C * 4096));
+    L.tmask.ensure(sizeof(uint64_t) * (size_t)n);
+    L.acc.ensure(sizeof(double) * 64);
+    L.h_acc.ensure(sizeof(double) * 64);
+    launch_fill_i32(L.tmask.as<int>(), 0, (size_t)n * 2, L.st);
+    GED_HIP(hipStreamSynchronize(L.st));
+    L.sw.zero = true;
+    L.bytes = L.tmask.bytes + L.sw.cnt1.bytes + L.sw.cnt2.bytes + L.sw.lv.bytes +
+              L.sw.wl.bytes + L.sw.ws.blk.bytes + L.sw.ws.seg.bytes + L.sw.ws.lng.bytes;
+    return;
+  }
   L.X.ensure(sizeof(double) * (size_t)n * C);
   L.Y.ensure(sizeof(double) * (size_t)n * C);
   L.tmask.ensure(sizeof(uint64_t) * (size_t)n);
@@ -165,10 +196,17 @@ static void emit(ged_server *s, const Req &q, int status, double score, std::vec
   s->cv_done.notify_all();
 }
 
-// Harvest the step that just finished: columns that ran level ell* are done.
+// Harvest the step that just finished: columns that ran level ell* are done
+// (split lanes: every request of the tile).
 static void lane_harvest(ged_server *s, Lane &L) {
   const double t = now_us();
   const double *acc = L.h_acc.as<double>();
+  if (L.split) {
+    for (size_t j = 0; j < L.tile.size(); ++j) emit(s, L.tile[j], GED_OK, acc[j], {}, t);
+    L.tile.clear();
+    L.sw.zero = true;
+    return;
+  }
   for (int c = 0; c < L.C; ++c) {
     if (L.launched[c] == 0) continue;
     if (L.launched[c] == L.ell) {
@@ -182,8 +220,69 @@ static void lane_harvest(ged_server *s, Lane &L) {
   }
 }
 
+// Split lane: the next tile of up to C waiting requests.
+static bool lane_launch_split(ged_server *s, Lane &L) {
+  if (L.pending.empty()) return false;
+  ged_graph *g = L.g;
+  const int C = L.C;
+  if (!L.sw.zero) split_fit(g, L.sw, L.pl, C, L.sw.wl_cap, L.st);  // after a failed tile
+  std::vector<int64_t> offs(1, 0);
+  std::vector<int> mem, col;
+  size_t need = 0;
+  while (!L.pending.empty() && (int)L.tile.size() < C) {
+    const Req &q = L.pending.front();
+    int64_t ds = 0;
+    for (int v : q.S) ds += g->h_rp[v + 1] - g->h_rp[v];
+    const size_t nq = split_wl_need(g, ds);
+    if (!L.tile.empty() && need + nq > L.sw.wl_cap) break;
+    need += nq;
+    const int c = (int)L.tile.size();
+    for (int v : q.S) {
+      mem.push_back(v);
+      col.push_back(c);
+    }
+    offs.push_back((int64_t)mem.size());
+    L.tile.push_back(std::move(L.pending.front()));
+    L.pending.pop_front();
+  }
+  const int nc = (int)L.tile.size();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->waiting -= nc;
+  }
+  if (need > L.sw.wl_cap) split_fit(g, L.sw, L.pl, C, need, L.st);
+  const size_t m = mem.size();
+  const size_t ob = sizeof(int64_t) * (size_t)(nc + 1);
+  const size_t bytes = ob + 2 * sizeof(int) * std::max<size_t>(m, 1);
+  L.tin.ensure(bytes);
+  L.h_tin.ensure(bytes);
+  char *h = L.h_tin.as<char>();
+  std::memcpy(h, offs.data(), ob);
+  if (m) {
+    std::memcpy(h + ob, mem.data(), sizeof(int) * m);
+    std::memcpy(h + ob + sizeof(int) * m, col.data(), sizeof(int) * m);
+  }
+  GED_HIP(hipMemcpyAsync(L.tin.p, h, bytes, hipMemcpyHostToDevice, L.st));
+  const int64_t *d_offs = L.tin.as<const int64_t>();
+  const int *d_mem = reinterpret_cast<const int *>(L.tin.as<char>() + ob);
+  const int *d_col = d_mem + m;
+  L.sw.zero = false;
+  enqueue_split_tile(g, L.sw, L.pl, C, d_offs, d_mem, d_col, 0, nc, (int64_t)m,
+                     L.tmask.as<uint64_t>(), L.acc.as<double>(), L.st, false);
+  GED_HIP(hipMemcpyAsync(L.h_acc.p, L.acc.p, sizeof(double) * nc, hipMemcpyDeviceToHost, L.st));
+  GED_HIP(hipEventRecord(L.ev, L.st));
+  L.inflight = true;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->steps++;
+    s->peak_cols = std::max<int64_t>(s->peak_cols, nc);
+  }
+  return true;
+}
+
 // Admit waiting requests into free columns and launch one step.
 static bool lane_launch(ged_server *s, Lane &L) {
+  if (L.split) return lane_launch_split(s, L);
   ged_graph *g = L.g;
   const int C = L.C;
   // bit updates: clear finished columns' members, set new members
@@ -305,8 +404,14 @@ static void sched_loop(ged_server *s) {
       } catch (const HipError &err) {
         // fail every request of this lane and drop it from service
         const double t = now_us();
-        for (int c = 0; c < L.C; ++c)
-          if (L.step[c] > 0) emit(s, L.slot[c], err.code, 0.0, {}, t);
+        if (L.split) {
+          for (auto &q : L.tile) emit(s, q, err.code, 0.0, {}, t);
+          L.tile.clear();
+          L.sw.zero = false;
+        } else {
+          for (int c = 0; c < L.C; ++c)
+            if (L.step[c] > 0) emit(s, L.slot[c], err.code, 0.0, {}, t);
+        }
         for (auto &q : L.pending) emit(s, q, err.code, 0.0, {}, t);
         {
           std::lock_guard<std::mutex> lk(s->mu);

@@ -33,11 +33,13 @@ namespace ged {
 
 constexpr int kWlChunk = 512;   // arcs per worklist entry (one wavefront)
 constexpr int kPushGrid = 2048; // blocks of the member kernels (grid-stride)
-// blocks of the worklist kernels (4 waves each): one wave per entry of the
-// capacity, at most kWlGridMax blocks
+// Blocks of the worklist kernels (4 waves each, grid-stride over the entries):
+// about one wave per expected entry, between kWlGridMin and kWlGridMax.
+constexpr int kWlGridMin = 64;
 constexpr int kWlGridMax = 16384;
-static int wl_grid(unsigned cap) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kWlGridMax, ((int64_t)cap + 3) / 4));
+int split_wl_blocks(int64_t expected_entries) {
+  return (int)std::max<int64_t>(kWlGridMin,
+                                std::min<int64_t>(kWlGridMax, (expected_entries + 3) / 4));
 }
 
 bool split_ok(const ged_graph *g) { return g->flags == GED_UNDIRECTED; }
@@ -186,16 +188,22 @@ __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict_
   }
 }
 
-// omega_2(v) = sum_{u in N(v)} deg(u): walks of length 2 ending at v.
-__global__ void k_omega2(const int *__restrict__ rp, const int *__restrict__ ci, int n,
-                         unsigned long long *out) {
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+// omega_2(v) = sum_{u in N(v)} deg(u): walks of length 2 ending at v.  One
+// wavefront per row (lanes over its arcs, integer sum), so hub rows do not
+// serialise on one lane.
+__global__ __launch_bounds__(kBlock) void k_omega2(const int *__restrict__ rp,
+                                                   const int *__restrict__ ci, int n,
+                                                   unsigned long long *out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; v < n; v += nw) {
     unsigned long long s = 0;
-    for (int k = rp[v]; k < rp[v + 1]; ++k) {
+    for (int k = rp[v] + lane; k < rp[v + 1]; k += 64) {
       const int u = ci[k];
       s += (unsigned long long)(rp[u + 1] - rp[u]);
     }
-    out[v] = s;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) out[v] = s;
   }
 }
 
@@ -220,7 +228,8 @@ void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st) {
   const int eg = (int)std::min<int64_t>(8192, (n + kBlock - 1) / kBlock);
   if (pl.s >= 2 && !g->omega2_ready) {
     g->omega2.ensure(sizeof(uint64_t) * (size_t)n);
-    hipLaunchKernelGGL(k_omega2, dim3(eg), dim3(kBlock), 0, st, g->rp.as<const int>(),
+    const int og = (int)std::min<int64_t>(16384, (n + kBlock / 64 - 1) / (kBlock / 64));
+    hipLaunchKernelGGL(k_omega2, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
                        g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>());
     GED_HIP(hipGetLastError());
     g->omega2_ready = true;
@@ -277,7 +286,7 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
                      w.wl_cap);
   GED_HIP(hipGetLastError());
   if (c2) {
-    hipLaunchKernelGGL((k_push_wl<CT, false>), dim3(wl_grid(w.wl_cap)), dim3(kBlock), 0, st, rp, ci, C, c1,
+    hipLaunchKernelGGL((k_push_wl<CT, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C, c1,
                        c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
     GED_HIP(hipGetLastError());
   }
@@ -295,7 +304,7 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
   CT *c1 = w.cnt1.as<CT>();
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
   if (c2) {
-    hipLaunchKernelGGL((k_push_wl<CT, true>), dim3(wl_grid(w.wl_cap)), dim3(kBlock), 0, st, rp, ci, C, c1,
+    hipLaunchKernelGGL((k_push_wl<CT, true>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C, c1,
                        c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
     GED_HIP(hipGetLastError());
   }
@@ -306,7 +315,7 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
 }
 
 void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
-                 hipStream_t st) {
+                 hipStream_t st, bool profile) {
   const int64_t n = g->n;
   const size_t nC = (size_t)n * C;
   const PrepCache &pc = g->prep;
@@ -346,7 +355,10 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
     a.inj = T + (size_t)i * n;
     if (i < pl.a) {
       a.Y = lv + (size_t)(i - 1 - pl.s) * nC;
-      run_step(g, p, a, in, OUT_TILE, st);
+      if (profile)
+        run_step(g, p, a, in, OUT_TILE, st);
+      else
+        launch_step(p, a, in, OUT_TILE, st);
     } else {
       // absent inputs: index mask 0 into a valid buffer, weight 0
       const double *any = pc.tr.as<const double>();
@@ -364,14 +376,18 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
       a.q_nlv = pl.nlv;
       a.q_even = pl.even ? 1 : 0;
       const int out = (pl.c32 && pl.s >= 1) ? OUT_COMBINE32 : OUT_COMBINE;
-      run_step(g, p, a, in, out, st, pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
+      if (profile)
+        run_step(g, p, a, in, out, st, pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
+      else
+        launch_step(p, a, in, out, st);
     }
   }
 }
 
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
-                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st) {
+                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,
+                        bool profile) {
   const int mgrid = grid_for(tile_members, kPushGrid);
   launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
   if (pl.s >= 1) {
@@ -381,7 +397,7 @@ void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
       push_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tile_members,
                                      tmask, st);
   }
-  split_dense(g, w, pl, C, tmask, st);
+  split_dense(g, w, pl, C, tmask, st, profile);
   StepArgs a = base_args(g);
   w.ws.into(a);
   a.C = C;
@@ -455,6 +471,8 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   }
   split_tables(g, pl, st);
   split_fit(g, g->split_ws, pl, 1, split_wl_need(g, deg_sum), st);
+  // a fixed worklist grid, so the captured graph serves every group
+  g->split_ws.wl_blocks = 256;
   g->acc.ensure(sizeof(double) * 64);
   g->out_host.ensure(64);
   const int cap = g->split_cap;
