@@ -584,6 +584,7 @@ extern "C" int ged_graph_destroy(ged_graph *g) {
     if (g->stream) (void)hipStreamSynchronize(g->stream);
   }
   batch_forget(g);
+  greedy_forget(g);
   delete g;
   return GED_OK;
 }

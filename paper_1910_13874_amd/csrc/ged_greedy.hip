@@ -245,6 +245,24 @@ struct GreedyCtx {
   int rounds = 0;
 };
 
+// The working buffers stay allocated on the graph between calls (a serving
+// process runs many greedy requests; freeing device memory can stall the
+// device for every stream).
+static std::mutex g_greedy_mu;
+static std::map<const ged_graph *, std::unique_ptr<GreedyCtx>> g_greedy;
+
+static GreedyCtx &greedy_ctx(const ged_graph *g) {
+  std::lock_guard<std::mutex> lk(g_greedy_mu);
+  auto &p = g_greedy[g];
+  if (!p) p = std::make_unique<GreedyCtx>();
+  return *p;
+}
+
+void greedy_forget(const ged_graph *g) {
+  std::lock_guard<std::mutex> lk(g_greedy_mu);
+  g_greedy.erase(g);
+}
+
 static void ensure_levels_cap(GreedyCtx &c, int ell) {
   if (ell <= c.Lcap) return;
   int cap = std::max(16, c.Lcap);
@@ -443,20 +461,24 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   int rc = prepare(g, alpha, eps);
   if (rc) return rc;
   const int n = (int)n64;
-  GreedyCtx c;
+  GreedyCtx &c = greedy_ctx(g);
   c.g = g;
   c.st = g->stream;
   c.n = n;
   c.C = 8;
   c.split = split_ok(g);
+  c.evals = 0;
+  c.rounds = 0;
   const int K = c.C + 1;
   c.smask.ensure(sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1));
   c.ub.ensure(sizeof(double) * n);
   c.stale.ensure(sizeof(double) * n);
   c.done.ensure(sizeof(int) * n);
   c.cand_col.ensure(sizeof(int) * n);
-  c.X.ensure(sizeof(double) * (size_t)n * c.C);
-  c.Y.ensure(sizeof(double) * (size_t)n * c.C);
+  if (!c.split) {  // ping-pong gain levels (split gains store theirs in dlv)
+    c.X.ensure(sizeof(double) * (size_t)n * c.C);
+    c.Y.ensure(sizeof(double) * (size_t)n * c.C);
+  }
   c.cand_dev.ensure(sizeof(int) * 64);
   c.gains.ensure(sizeof(double) * 64);
   const int nb0 = (n + kBlock * kTopE - 1) / (kBlock * kTopE);

@@ -380,6 +380,8 @@ int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, dou
                 double *out, ged_score_info *info);
 // Drop the batched-scoring workspace of a graph that is being destroyed.
 void batch_forget(const ged_graph *g);
+// Drop the greedy workspace of a graph that is being destroyed.
+void greedy_forget(const ged_graph *g);
 
 // Split scoring (ged_split.hip).
 bool split_ok(const ged_graph *g);

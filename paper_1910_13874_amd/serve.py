@@ -107,7 +107,10 @@ def bench(args, torch, ged, inputs, metric):
         alphas.append(gg.default_alpha())
         ns.append(g.n)
     setup_s = time.perf_counter() - t
-    server = ged.Server(hbm_budget_bytes=200 << 30, greedy_workers=2)
+    # three greedy workers: greedy requests on one graph run one at a time (they
+    # share its handle), those on different graphs overlap; more workers crowd
+    # the device and delay the score tiles
+    server = ged.Server(hbm_budget_bytes=200 << 30, greedy_workers=min(3, len(graphs)))
     gids = [server.add_graph(gg, a, eps) for gg, a in zip(graphs, alphas)]
     n_req = getattr(args, "requests", 1000)
     qps = getattr(args, "qps", 2000.0)
