@@ -73,3 +73,36 @@ def test_admission_and_queue_limits(ged):
         got += len(srv2.poll(64, 200000))
     srv2.close()
     gg.close()
+
+
+def test_directed_and_weighted_lanes(ged):
+    """A directed graph (level-by-level column pool) and a weighted undirected one
+    (split tiles without integer levels) served side by side: every result equals
+    the same request alone."""
+    from paper_1910_13874_amd import serve
+    r = inputs.uniform_ints(2 * 60000, 8000, 24)
+    gd = inputs.from_edges(8000, r[0::2], r[1::2], symmetrize=False, name="dir8k")
+    gw = inputs.barabasi_albert(30000, 4, 25)
+    deg = gw.degrees.astype(np.float64)
+    rows = np.repeat(np.arange(gw.n), gw.degrees)
+    w = 1.0 / np.sqrt(deg[rows] * deg[gw.col_idx])
+    ggs = [ged.GedGraph.from_graph(gd), ged.GedGraph.from_graph(gw, weights=w)]
+    alphas = [gg.default_alpha() for gg in ggs]
+    print("[serving directed+weighted]", [gd.n, gw.n], flush=True)
+    srv = ged.Server(hbm_budget_bytes=8 << 30, score_slots=8, greedy_workers=2)
+    gids = [srv.add_graph(gg, a, EPS) for gg, a in zip(ggs, alphas)]
+    reqs = serve.make_requests([gd.n, gw.n], 160, 4e4, seed=11, greedy_frac=0.05)
+    out, wall = serve.run_server(srv, gids, reqs)
+    assert srv.stats()["completed"] == len(reqs)
+    for j, q in enumerate(reqs):
+        kind, status, score, lat, grp = out[j]
+        assert status == 0
+        if q["kind"] == 0:
+            alone = ggs[q["g"]].score(q["S"], alphas[q["g"]], EPS)
+            assert abs(score - alone) <= 1e-12 * max(abs(alone), 1e-300), (j, q["g"], score, alone)
+        else:
+            alone = ggs[q["g"]].greedy(q["k"], alphas[q["g"]], EPS)
+            assert list(grp) == list(alone["group"])
+    srv.close()
+    for gg in ggs:
+        gg.close()
