@@ -270,8 +270,8 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (single-GPU hot path); "
-              "--gpus must be 1", file=sys.stderr)
+        print("bench.py: the walk-count hot path runs on one GPU; multi-GPU runs are not "
+              "supported (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
