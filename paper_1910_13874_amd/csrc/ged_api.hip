@@ -531,6 +531,13 @@ static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int
         if (weights) iw[r] = ow[q];
       }
   }
+  g->simple = true;
+  for (int v = 0; v < N && g->simple; ++v)
+    for (int r = irp[v] + 1; r < irp[v + 1]; ++r)
+      if (ici[r] == ici[r - 1]) {
+        g->simple = false;
+        break;
+      }
   return guarded([&]() -> int {
     GED_HIP(hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking));
     g->stream = g->own_stream;

@@ -298,6 +298,7 @@ struct ged_graph {
   double sigma = -1.0;          // upper estimate of sigma_max, -1 until computed
   double max_wdeg = 0;          // maximum weighted out-degree (weighted graphs)
   bool weighted = false;
+  bool simple = false;          // no arc listed twice (rows are sorted internally)
   std::vector<int> h_rp;        // host copy of row_ptr (int32) for partitioning
   // Vertices are stored in degree-descending order (stable by id) unless
   // GED_KEEP_ORDER is given: internal id = new_id[caller id],

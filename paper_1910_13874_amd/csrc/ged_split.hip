@@ -16,8 +16,8 @@
 // On unweighted graphs the first two levels are integer walk counts
 // (h_i = alpha^i * count_i), pushed from the group's members with integer
 // atomics (exact and order-free, so the result stays deterministic), 32-bit
-// when the maximum degree is below 2^16 (count_2 <= omega_2 <= max degree^2),
-// else 64-bit:
+// when count_2 <= omega_2 is known to fit (maximum degree below 2^16, or no
+// duplicate arcs: then omega_2 <= nnz < 2^31), else 64-bit:
 //   count_1(y) = |N(y) ∩ S| outside S,        deg(y) on S
 //   count_2(x) = sum_{y in N(x)} count_1(y) outside S,   omega_2(x) on S
 // Members push deg(s) to their neighbours (level-2 paths through a member)
@@ -51,8 +51,9 @@ SplitPlan split_plan(const ged_graph *g, int ell) {
   p.even = p.r == p.a;
   p.s = g->weighted ? 0 : std::min(2, p.a - 1);
   p.nlv = p.a - 1 - p.s;
-  // count_2 <= omega_2 <= (max degree)^2
-  p.c32 = g->max_deg < 65536;
+  // count_2(x) <= omega_2(x) = sum_{y in N(x)} deg(y), which is at most
+  // (max degree)^2, and at most nnz < 2^31 when no arc is listed twice
+  p.c32 = g->max_deg < 65536 || g->simple;
   return p;
 }
 

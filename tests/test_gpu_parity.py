@@ -313,21 +313,36 @@ def test_stochastic_greedy_parity(ged):
     gg.close()
 
 
-@pytest.mark.parametrize("name", ["er", "ba", "weighted", "hub"])
+@pytest.mark.parametrize("name", ["er", "ba", "weighted", "hub", "rmat"])
 def test_split_ell_sweep(ged, name):
     """Split scoring for every plan shape: ell* = 1..9 (a = 1, 2, 3+; odd and
     even ell; integer levels s = 0, 1, 2; weighted has s = 0), single and
-    batched, against the oracle.  "hub" has a vertex of degree 70,000, which
-    takes the 64-bit count path (32-bit counts need max degree < 2^16)."""
+    batched, against the oracle.  "hub" has a vertex of degree 70,000 and a few
+    doubled arcs, which takes the 64-bit count path (32-bit counts need max
+    degree < 2^16 or no duplicate arcs); "rmat" takes 32-bit counts through
+    the no-duplicates rule (its max degree is below 2^16 too at this size, so it
+    mainly adds an R-MAT degree profile)."""
     if name == "er":
         g, w = inputs.erdos_renyi(3000, 12000, 51), None
+    elif name == "rmat":
+        g, w = inputs.rmat(17, 16, seed=54), None
     elif name == "hub":
         rng = np.random.default_rng(53)
         leaves = np.arange(1, 70001, dtype=np.int32)
         src = np.concatenate([np.zeros(70000, np.int32), rng.integers(1, 70001, 30000).astype(np.int32)])
         dst = np.concatenate([leaves, rng.integers(1, 70001, 30000).astype(np.int32)])
         keep = src != dst
-        g, w = inputs.from_edges(70001, src[keep], dst[keep], symmetrize=True), None
+        g0 = inputs.from_edges(70001, src[keep], dst[keep], symmetrize=True)
+        # double the arcs between the hub (vertex 0) and leaves 1..5, both ways
+        rows = [list(g0.col_idx[g0.row_ptr[v]:g0.row_ptr[v + 1]]) for v in range(g0.n)]
+        for leaf in range(1, 6):
+            rows[0].append(leaf)
+            rows[leaf].append(0)
+        rows = [sorted(r) for r in rows]
+        rp = np.zeros(g0.n + 1, dtype=np.int64)
+        rp[1:] = np.cumsum([len(r) for r in rows])
+        ci = np.fromiter((u for r in rows for u in r), dtype=np.int32, count=int(rp[-1]))
+        g, w = inputs.Graph(n=g0.n, row_ptr=rp, col_idx=ci, name="hub_multi"), None
         assert g.max_degree >= 65536
     else:
         g, w = inputs.barabasi_albert(4000, 4, 52), None
