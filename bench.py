@@ -93,10 +93,15 @@ def roofline(prof, ged, workload):
     achieved = bytes_per / (ms * 1e-3) / 1e9
     kname = ged.kernel_name(prof["dominant_columns"], prof["dominant_kind"])
     tr = traffic_for(workload, kname)
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
-            "avg_launch_us": ms * 1e3, "algorithmic_bytes_per_launch": bytes_per,
-            "launches": prof["dominant_launches"]}
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
+           "avg_launch_us": ms * 1e3, "algorithmic_bytes_per_launch": bytes_per,
+           "launches": prof["dominant_launches"]}
+    if tr:
+        # measured L2-miss bytes per launch over the same event-timed duration
+        out["traffic_gbs"] = tr / (ms * 1e-3) / 1e9
+        out["traffic_frac"] = out["traffic_gbs"] / HBM_PEAK_GBS
+    return out
 
 
 def run_steps(step, K, W, gg, torch):
