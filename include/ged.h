@@ -148,8 +148,12 @@ int ged_invalidate(ged_graph *g);
 
 /*
  * GED_{<=ell*}(S) for one group (Section 3.1, Algorithm "GED-Walk
- * Computation").  GED(S) - eps < *out_score <= GED(S).  s_len == 0 gives 0.
- * info may be NULL.  Blocks until the result is on the host.
+ * Computation").  GED(S) - eps < *out_score <= GED(S).  s_len == 0 gives 0;
+ * duplicate members count once.  On undirected graphs the sum is formed from
+ * the hit chain up to ceil(ell*/2) by cutting each walk in two (both halves
+ * are counted by the hit and total-walk chains); the result agrees with the
+ * level-by-level sum to rounding.  info may be NULL.  Blocks until the result
+ * is on the host.
  */
 int ged_score(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
               double *out_score, ged_score_info *info);
@@ -256,10 +260,14 @@ typedef struct {
 
 /*
  * Continuous-batching request server.  Resident graphs keep their CSR and
- * walk-count levels in device memory; score requests on one graph share a
- * pool of SpMM columns that advances one walk length per step, admitting new
- * requests into free columns between steps; greedy requests run on their own
- * streams once their working memory fits the HBM budget.
+ * walk-count levels in device memory.  Score requests on one graph run
+ * together as the columns of a tile: on undirected graphs each launch takes
+ * the waiting requests (up to score_slots) through a whole split scoring tile,
+ * and requests arriving meanwhile join the next one; on directed graphs a
+ * pool of columns advances one walk length per step and admits new requests
+ * into free columns between steps.  Greedy requests run on worker threads
+ * (one at a time per graph) once their working memory fits the HBM budget.
+ * Every result equals the same request run alone (scores to ~1e-12).
  */
 int ged_server_create(const ged_server_config *cfg, ged_server **out);
 /* Register a graph (the handle stays owned by the caller and must outlive the

@@ -2,12 +2,14 @@
 //
 // Every score query on a graph stops at the same ell* (the tail bound is taken
 // on the whole vertex set, Eq. katz-bound), so the hit chains of C groups run
-// in lock-step: column c of X holds h_i for group g0 + c, a per-vertex 64-bit
-// word marks which columns have v in their group (injection of t_i(v) there),
-// and one pass over col_idx serves all C columns.  The whole batch -- every
-// tile, every level -- is captured into one hipGraph and replayed, so the host
-// issues one launch per call.  The tile width C is chosen per graph by timing
-// the step kernel for each candidate width (autotuner).
+// in lock-step: column c holds h_i for group g0 + c, a per-vertex 64-bit word
+// marks which columns have v in their group (injection of t_i(v) there), and
+// one pass over col_idx serves all C columns.  Undirected graphs run each tile
+// as a split tile (ged_split.hip: integer levels 1-2, dense levels up to
+// ceil(ell*/2), combining epilogue); directed graphs run all ell* levels.  The
+// whole batch -- every tile, every level -- is captured into one hipGraph and
+// replayed, so the host issues one launch per call.  The tile width C is chosen
+// per graph by timing the dense phase for each candidate width (autotuner).
 #include <algorithm>
 #include <cstring>
 

@@ -19,6 +19,9 @@
 //     fix-up kernel adds the segments of each row in order.
 //   * a reduction kernel sums the block and long-row partials of each column
 //     in a fixed order.
+// Combining epilogues (split scoring and split gains, undirected graphs) do not
+// store y; they add, per (row, column), the combination of y with the lower
+// levels of the chain to the column sums (combine_fin below).
 // No floating-point atomics anywhere, so results are bitwise reproducible.
 #include <algorithm>
 #include <type_traits>
