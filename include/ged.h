@@ -150,7 +150,7 @@ int ged_invalidate(ged_graph *g);
  * GED_{<=ell*}(S) for one group (Section 3.1, Algorithm "GED-Walk
  * Computation").  GED(S) - eps < *out_score <= GED(S).  s_len == 0 gives 0;
  * duplicate members count once.  On undirected graphs the sum is formed from
- * the hit chain up to ceil(ell*/2) by cutting each walk in two (both halves
+ * the hit chain up to ceil(ell* / 2) by cutting each walk in two (both halves
  * are counted by the hit and total-walk chains); the result agrees with the
  * level-by-level sum to rounding.  info may be NULL.  Blocks until the result
  * is on the host.
