@@ -1,0 +1,169 @@
+"""Index arithmetic of the HIP kernels, emulated on the CPU (no GPU).
+
+Mirrors the row partition the library builds (row blocks of at most 2048/C
+arcs and 511 rows, long rows split into segments of 8192/C arcs) and every
+index formula of the step kernel, on CSRs in the library's internal vertex
+order (stable by decreasing out-degree), and asserts that every load and
+store lands inside its buffer -- including the empty trailing row blocks
+that once read one entry past col_idx.  For split scoring it emulates the
+worklist that the member pushes fill and checks the capacity bound the host
+allocates (entries past it would be dropped, not faulted, so a wrong bound
+would give wrong results silently).
+"""
+import numpy as np
+import pytest
+
+from paper_1910_13874_amd import inputs
+
+K_BLOCK, K_ROWS, K_SEG, K_LDS = 256, 511, 8192, 2048
+WL_CHUNK = 512
+
+
+def partition(rp, C):
+    n = len(rp) - 1
+    nnz_blk = K_LDS // C
+    seg_len = max(1, K_SEG // C)
+    deg = np.diff(rp)
+    blocks, segs, lrows = [], [], []
+    r = 0
+    while r < n:
+        if deg[r] > nnz_blk:
+            lrows.append(r)
+            for j in range(int(rp[r]), int(rp[r + 1]), seg_len):
+                segs.append((r, j, min(j + seg_len, int(rp[r + 1]))))
+            r += 1
+            continue
+        r0, acc = r, 0
+        while r < n and r - r0 < K_ROWS:
+            d = deg[r]
+            if d > nnz_blk or acc + d > nnz_blk:
+                break
+            acc += d
+            r += 1
+        blocks.append((r0, r, int(rp[r0]), int(rp[r])))
+    return blocks, segs, lrows
+
+
+def check_step(rp, ci, n, C):
+    nnz = int(rp[-1])
+    ci_alloc = max(1, nnz)
+    blocks, segs, _ = partition(rp, C)
+    PT = K_LDS // K_BLOCK
+    RT = (K_ROWS + K_BLOCK) // K_BLOCK
+    t = np.arange(K_BLOCK)
+    mask_words = (n + 31) // 32 + 1
+    for (r0, r1, p0, p1) in blocks:
+        nrows, tot = r1 - r0, (p1 - p0) * C
+        assert 1 <= nrows <= K_ROWS and 0 <= tot <= K_LDS
+        jlo = p0 if tot > 0 else 0
+        jmax = p1 - 1 if tot > 0 else 0
+        for q in range(PT):  # col_idx loads, gathers, LDS stores
+            j = np.minimum(jlo + (t + q * K_BLOCK) // C, jmax)
+            assert j.min() >= 0 and j.max() < ci_alloc
+            u = ci[j] if tot > 0 else np.zeros_like(j)
+            assert u.min() >= 0 and u.max() < n
+            f = t + q * K_BLOCK
+            assert np.where(f < tot, f, K_LDS + t).max() < K_LDS + K_BLOCK
+        for k in range(RT):  # row_ptr slice
+            assert (r0 + np.minimum(t + k * K_BLOCK, nrows)).max() <= n
+        nw = ((r0 + nrows - 1) >> 5) - (r0 >> 5) + 1
+        assert ((r0 >> 5) + np.minimum(t, nw - 1)).max() < mask_words
+        for k in range(2):  # per-row masks
+            rr = r0 + np.minimum(t + k * K_BLOCK, nrows - 1)
+            assert rr.min() >= 0 and rr.max() < n
+        # combining epilogue's early loads: row r0 + min((t/tpr)/C, nrows-1)
+        tpr = min(K_BLOCK // C, 64)
+        while tpr > 1 and nrows * C * tpr > K_BLOCK:
+            tpr >>= 1
+        rl0 = (t // tpr) // C
+        assert (r0 + np.minimum(rl0, nrows - 1)).max() < n
+        assert (p1 - p0) * C <= K_LDS
+    for (r, y, z) in segs:  # long-row segments, U = 8 clamped loads per lane
+        assert 0 <= y < z <= nnz and z - y <= max(1, K_SEG // C)
+        lpc = K_BLOCK // C
+        j0 = y + t // C
+        while j0.min() < z:
+            for q in range(8):
+                jj = np.minimum(j0 + q * lpc, z - 1)
+                assert jj.min() >= y and jj.max() < nnz
+            j0 = j0 + 8 * lpc
+
+
+def internal_csr(g):
+    """The library's storage: vertices by decreasing out-degree (stable),
+    rows = in-neighbours, sorted."""
+    n = g.n
+    rows = np.repeat(np.arange(n), np.diff(g.row_ptr))
+    outdeg = np.bincount(g.col_idx, minlength=n)
+    order = np.argsort(-outdeg, kind="stable")
+    new = np.empty(n, np.int64)
+    new[order] = np.arange(n)
+    v, u = new[rows], new[g.col_idx]
+    idx = np.lexsort((u, v))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, v + 1, 1)
+    return np.cumsum(rp), u[idx].astype(np.int64)
+
+
+def graphs():
+    r = inputs.uniform_ints(2 * 9000, 2000, 61)
+    return [
+        inputs.from_edges(5, [], [], name="edgeless"),
+        inputs.erdos_renyi(3000, 2000, 7),       # many isolated vertices
+        inputs.erdos_renyi(1000, 5000, 1),
+        inputs.barabasi_albert(20000, 5, 2),
+        inputs.rmat(14, 16, seed=18),
+        inputs.from_edges(2, [0], [1], name="K2"),
+        inputs.from_edges(9000, np.zeros(8999, np.int32), np.arange(1, 9000, dtype=np.int32),
+                          name="star"),           # one row longer than any block
+        inputs.from_edges(2000, r[0::2], r[1::2], symmetrize=False, name="dir"),
+    ]
+
+
+@pytest.mark.parametrize("g", graphs(), ids=lambda g: g.name or str(g.n))
+def test_step_indices_in_bounds(g):
+    for rp, ci in ((np.asarray(g.row_ptr, np.int64), np.asarray(g.col_idx, np.int64)),
+                   internal_csr(g)):
+        for C in (1, 2, 4, 8, 16, 32, 64):
+            check_step(rp, ci, g.n, C)
+
+
+def wl_need(n, nnz, deg_sum):
+    return min(n, deg_sum) + nnz // WL_CHUNK + 1
+
+
+@pytest.mark.parametrize("name", ["ba", "star", "rmat"])
+def test_split_worklist_fits_capacity(name):
+    """Emulate the member pushes of a tile: a non-member neighbour y claimed
+    first adds ceil(deg(y)/512) entries (y, column, chunk); the total must fit
+    the capacity the host computes from the members' degree sums, and every
+    entry's chunk must start inside row y and fit the 24-bit field."""
+    if name == "ba":
+        g = inputs.barabasi_albert(5000, 4, 3)
+    elif name == "star":
+        g = inputs.from_edges(9000, np.zeros(8999, np.int32), np.arange(1, 9000, dtype=np.int32))
+    else:
+        g = inputs.rmat(13, 16, seed=9)
+    rp, ci = internal_csr(g)
+    n, nnz = g.n, int(rp[-1])
+    deg = np.diff(rp)
+    rng = np.random.default_rng(5)
+    for C in (1, 8, 16):
+        groups = [np.unique(rng.integers(0, n, int(rng.integers(1, 300)))) for _ in range(C)]
+        if name == "star":
+            groups[0] = np.array([1])  # a leaf: its neighbour is the hub (8999 arcs)
+        entries, cap = 0, 0
+        for S in groups:
+            member = np.zeros(n, bool)
+            member[S] = True
+            claimed = set()
+            for s in S:
+                for y in ci[rp[s]:rp[s + 1]]:
+                    if not member[y] and y not in claimed:
+                        claimed.add(int(y))
+                        chunks = (int(deg[y]) + WL_CHUNK - 1) // WL_CHUNK
+                        for q in range(chunks):
+                            assert q < (1 << 24) and rp[y] + q * WL_CHUNK < rp[y + 1]
+                        entries += chunks
+            cap += wl_need(n, nnz, int(deg[S].sum()))
+        assert entries <= cap, (name, C, entries, cap)
