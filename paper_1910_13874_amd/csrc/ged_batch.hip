@@ -26,7 +26,14 @@ struct BatchWs {
   DBuf mcol;        // int [cap_m] group of each member
   std::vector<int64_t> h_offsets;
   std::vector<int> h_members, h_mcol;
-  SplitWs sw;       // split scoring (undirected graphs)
+  // split tiles (undirected graphs): tile t uses counts sw / sw2 and member bits
+  // tmask / tmask2 by the parity of t, so the pushes of tile t+1 and the
+  // clearing of tile t-1 (side stream) overlap the dense levels of tile t
+  SplitWs sw, sw2;
+  DBuf tmask2;
+  bool tmask2_ready = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_push[2] = {}, ev_dense[2] = {};
   DBuf scores;      // double [cap_g + 64]
   HBuf h_scores;
   size_t cap_g = 0, cap_m = 0;
@@ -37,6 +44,12 @@ struct BatchWs {
   ~BatchWs() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : {ev_fork, ev_join, ev_push[0], ev_push[1], ev_dense[0], ev_dense[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
   }
 };
 
@@ -270,8 +283,21 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
       deg_tile = std::max(deg_tile, ds);
     }
     split_fit(g, b.sw, pl, C, wl_need, st);
-    b.sw.wl_blocks = split_wl_blocks(deg_tile);
+    split_fit(g, b.sw2, pl, C, wl_need, st, true);
+    b.sw.wl_blocks = b.sw2.wl_blocks = split_wl_blocks(deg_tile);
+    b.tmask2.ensure(sizeof(uint64_t) * (size_t)n);
+    if (!b.tmask2_ready) {
+      launch_fill_i32(b.tmask2.as<int>(), 0, (size_t)n * 2, st);
+      b.tmask2_ready = true;
+    }
+    if (!b.side) {
+      GED_HIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
+      for (hipEvent_t *e : {&b.ev_fork, &b.ev_join, &b.ev_push[0], &b.ev_push[1], &b.ev_dense[0],
+                            &b.ev_dense[1]})
+        GED_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
     b.sw.zero = false;
+    b.sw2.zero = false;
   } else {
     b.X.ensure(sizeof(double) * (size_t)n * C);
     b.Y.ensure(sizeof(double) * (size_t)n * C);
@@ -281,13 +307,36 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
       enqueue_batch(g, b, G, C, st);
       return;
     }
-    for (int g0 = 0; g0 < G; g0 += C) {
-      const int nc = std::min(C, G - g0);
+    const int ntiles = (G + C - 1) / C;
+    SplitWs *cw[2] = {&b.sw, &b.sw2};
+    uint64_t *tm[2] = {b.tmask.as<uint64_t>(), b.tmask2.as<uint64_t>()};
+    const int64_t *offs = b.offsets.as<const int64_t>();
+    const int *mem = b.members.as<const int>(), *mc = b.mcol.as<const int>();
+    auto push = [&](int t) {
+      const int g0 = t * C, nc = std::min(C, G - g0);
+      split_tile_push(g, *cw[t & 1], pl, C, offs, mem, mc, g0, nc, hoff[g0 + nc] - hoff[g0],
+                      tm[t & 1], b.side);
+      GED_HIP(hipEventRecord(b.ev_push[t & 1], b.side));
+    };
+    // side stream: push(0), push(1), clear(0), push(2), clear(1), ...  A tile's
+    // buffers are cleared (side, in order) before the tile two later pushes.
+    GED_HIP(hipEventRecord(b.ev_fork, st));
+    GED_HIP(hipStreamWaitEvent(b.side, b.ev_fork, 0));
+    push(0);
+    for (int t = 0; t < ntiles; ++t) {
+      const int g0 = t * C, nc = std::min(C, G - g0), p = t & 1;
+      if (t + 1 < ntiles) push(t + 1);
+      GED_HIP(hipStreamWaitEvent(st, b.ev_push[p], 0));
+      split_dense(g, b.sw, pl, C, tm[p], st, true, cw[p]);
       // scores of this tile's columns (the buffer has C entries of slack)
-      enqueue_split_tile(g, b.sw, pl, C, b.offsets.as<const int64_t>(), b.members.as<const int>(),
-                         b.mcol.as<const int>(), g0, nc, hoff[g0 + nc] - hoff[g0],
-                         b.tmask.as<uint64_t>(), b.scores.as<double>() + g0, st);
+      split_tile_reduce(g, b.sw, C, b.scores.as<double>() + g0, st);
+      GED_HIP(hipEventRecord(b.ev_dense[p], st));
+      GED_HIP(hipStreamWaitEvent(b.side, b.ev_dense[p], 0));
+      split_tile_clear(g, *cw[p], pl, C, offs, mem, mc, g0, nc, hoff[g0 + nc] - hoff[g0], tm[p],
+                       b.side);
     }
+    GED_HIP(hipEventRecord(b.ev_join, b.side));
+    GED_HIP(hipStreamWaitEvent(st, b.ev_join, 0));
   };
   double abits_d = alpha;
   const void *abits;
@@ -297,9 +346,12 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
                                    b.ws.blk.p,     b.ws.seg.p,  b.ws.lng.p, b.ws.red2.p,
                                    b.sw.cnt1.p,    b.sw.cnt2.p, b.sw.lv.p,  b.sw.wl.p,
                                    b.sw.wl_n.p,    b.sw.ws.blk.p, b.sw.ws.seg.p, b.sw.ws.lng.p,
+                                   b.sw2.cnt1.p,   b.sw2.cnt2.p, b.sw2.wl.p,   b.sw2.wl_n.p,
+                                   b.tmask2.p,     (const void *)b.side,
                                    b.sw.ws.red2.p, g->omega2.p, g->prep.tr.p,
                                    g->prep.t_levels.p, (const void *)st, abits,
                                    (const void *)(uintptr_t)b.sw.wl_cap,
+                                   (const void *)(uintptr_t)b.sw2.wl_cap,
                                    (const void *)(intptr_t)b.sw.wl_blocks,
                                    (const void *)(intptr_t)split,
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
@@ -333,7 +385,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
   double *hs = b.h_scores.as<double>();
   GED_HIP(hipMemcpyAsync(hs, b.scores.p, sizeof(double) * (size_t)G, hipMemcpyDeviceToHost, st));
   GED_HIP(hipStreamSynchronize(st));
-  if (split) b.sw.zero = true;
+  if (split) b.sw.zero = b.sw2.zero = true;
   std::memcpy(out, hs, sizeof(double) * (size_t)G);
   return GED_OK;
 }

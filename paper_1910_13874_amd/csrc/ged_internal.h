@@ -392,19 +392,32 @@ void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st);
 // Size a workspace for C columns and a worklist of wl_need entries; zero the
 // count arrays if they are new or dirty.
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
-               hipStream_t st);
+               hipStream_t st, bool counts_only = false);
 // Worklist entries a group needs: min(n, sum of member degrees) + ceil(nnz/chunk).
 size_t split_wl_need(const ged_graph *g, int64_t deg_sum);
 // Grid of the worklist kernels for about `expected_entries` entries.
 int split_wl_blocks(int64_t expected_entries);
 // Dense levels s+1..a of a tile (the last one combining into the block
 // partials of w.ws); the counts of levels <= s must be in place.
+// counts (nullable) supplies the count levels when they live in another
+// workspace than w's stored levels and partials.
 void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
-                 hipStream_t st, bool profile = true);
+                 hipStream_t st, bool profile = true, const SplitWs *counts = nullptr);
 // Enqueue one tile of nc <= C groups (g0 .. g0+nc-1 of the device offsets /
 // members / mcol arrays); scores go to out[0..nc).
-// profile = false launches without profiling events (the server enqueues tiles
-// from its own thread).
+// The phases of a tile, for callers that overlap them across tiles: member bits
+// and integer levels (push), dense levels (split_dense), column sums of w's
+// partials into out[0..C) (reduce), and clearing of what push wrote (clear).
+// w's counts and tmask must not be shared with a tile in flight.
+void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
+                     const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
+                     uint64_t *tmask, hipStream_t st);
+void split_tile_reduce(ged_graph *g, SplitWs &w, int C, double *out, hipStream_t st);
+void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
+                      const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
+                      uint64_t *tmask, hipStream_t st);
+// All four phases in order on one stream.  profile = false launches without
+// profiling events (the server enqueues tiles from its own thread).
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
                         int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,

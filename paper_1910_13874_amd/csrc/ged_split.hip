@@ -246,10 +246,10 @@ void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st) {
 }
 
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
-               hipStream_t st) {
+               hipStream_t st, bool counts_only) {
   const size_t nC = (size_t)g->n * C;
   Partition &p = partition(g, C);
-  w.ws.fit(p);
+  if (!counts_only) w.ws.fit(p);
   if (pl.s >= 1) {
     const size_t cb = (pl.c32 ? sizeof(uint32_t) : sizeof(uint64_t)) * nC;
     if (w.cnt1.bytes < cb || w.cnt2.bytes < cb) {
@@ -272,7 +272,7 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
       w.wl_cap = (unsigned)cap;
     }
   }
-  if (pl.nlv > 0) w.lv.ensure(sizeof(double) * nC * (size_t)pl.nlv);
+  if (pl.nlv > 0 && !counts_only) w.lv.ensure(sizeof(double) * nC * (size_t)pl.nlv);
 }
 
 template <class CT>
@@ -316,15 +316,16 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
 }
 
 void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
-                 hipStream_t st, bool profile) {
+                 hipStream_t st, bool profile, const SplitWs *counts) {
   const int64_t n = g->n;
   const size_t nC = (size_t)n * C;
   const PrepCache &pc = g->prep;
   const double alpha = pc.alpha;
   Partition &p = partition(g, C);
   const double *T = pc.t_levels.as<const double>();
-  const void *c1 = pl.s >= 1 ? w.cnt1.p : nullptr;
-  const void *c2 = pl.s >= 2 ? w.cnt2.p : nullptr;
+  const SplitWs &cw = counts ? *counts : w;
+  const void *c1 = pl.s >= 1 ? cw.cnt1.p : nullptr;
+  const void *c2 = pl.s >= 2 ? cw.cnt2.p : nullptr;
   double lv_scale = alpha;  // alpha^(s+1) for the first dense level after the counts
   for (int i = 0; i < pl.s; ++i) lv_scale *= alpha;
   double *lv = w.lv.as<double>();
@@ -385,10 +386,9 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
   }
 }
 
-void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
-                        const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
-                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,
-                        bool profile) {
+void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
+                     const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
+                     uint64_t *tmask, hipStream_t st) {
   const int mgrid = grid_for(tile_members, kPushGrid);
   launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
   if (pl.s >= 1) {
@@ -398,11 +398,12 @@ void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
       push_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tile_members,
                                      tmask, st);
   }
-  split_dense(g, w, pl, C, tmask, st, profile);
-  StepArgs a = base_args(g);
-  w.ws.into(a);
-  a.C = C;
-  launch_reduce(partition(g, C), a, out, nullptr, nullptr, st, w.ws.scratch());
+}
+
+void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
+                      const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
+                      uint64_t *tmask, hipStream_t st) {
+  const int mgrid = grid_for(tile_members, kPushGrid);
   if (pl.s >= 1) {
     if (pl.c32)
       clear_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, st);
@@ -410,6 +411,23 @@ void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
       clear_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, st);
   }
   launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
+}
+
+void split_tile_reduce(ged_graph *g, SplitWs &w, int C, double *out, hipStream_t st) {
+  StepArgs a = base_args(g);
+  w.ws.into(a);
+  a.C = C;
+  launch_reduce(partition(g, C), a, out, nullptr, nullptr, st, w.ws.scratch());
+}
+
+void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
+                        const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
+                        int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,
+                        bool profile) {
+  split_tile_push(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st);
+  split_dense(g, w, pl, C, tmask, st, profile);
+  split_tile_reduce(g, w, C, out, st);
+  split_tile_clear(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st);
 }
 
 int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> &out) {
