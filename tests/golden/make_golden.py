@@ -5,6 +5,7 @@ nothing here reads a GPU result.  Output: tests/golden/<name>.json.
 
     python tests/golden/make_golden.py ba1m      # BA n=1e6, m=5: scores + greedy k=10
     python tests/golden/make_golden.py rmat22    # R-MAT scale 22: scores + first greedy picks
+    python tests/golden/make_golden.py ba2m      # BA n=2e6, m=8: sampled groups of the batch
 """
 import json
 import os
@@ -34,6 +35,24 @@ def scores(g, alpha, seeds_sizes):
     return out
 
 
+# the batched workload: 4,096 groups, sizes U[1,200], seed 104; sampled columns
+BATCH_GROUPS, BATCH_SEED = 4096, 104
+BATCH_SAMPLE = [0, 1, 17, 1000, 2047, 2048, 3333, 4095]
+
+
+def batch_sample(g, alpha):
+    off, mem = inputs.groups(g.n, BATCH_GROUPS, 1, 200, BATCH_SEED)
+    out = []
+    for j in BATCH_SAMPLE:
+        S = mem[off[j]:off[j + 1]]
+        t = time.time()
+        c, ell, B, _ = oracle.score(g, S, alpha, EPS)
+        out.append({"index": j, "size": int(S.size), "score": c, "ell": ell,
+                    "oracle_s": time.time() - t})
+        print(f"  group {j} |S|={S.size}: {c!r} ell*={ell} ({time.time() - t:.1f}s)", flush=True)
+    return out
+
+
 def main(name):
     g = inputs.workload_graph(name)
     alpha = g.default_alpha()
@@ -46,6 +65,12 @@ def main(name):
     elif name == "rmat22":
         rec["scores"] = scores(g, alpha, [(102, 5), (103, 100)])
         k = 3
+    elif name == "ba2m":
+        rec["batch"] = {"groups": BATCH_GROUPS, "seed": BATCH_SEED,
+                        "sample": batch_sample(g, alpha)}
+        with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+            json.dump(rec, f, indent=1)
+        return
     else:
         raise SystemExit(f"unknown {name}")
     t = time.time()

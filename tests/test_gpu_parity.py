@@ -249,6 +249,31 @@ def test_full_size_ba1m(ged):
     gg.close()
 
 
+def test_full_size_batch_ba2m(ged):
+    """The batched workload at full size (BA n=2e6, m=8, 4,096 groups |S|~U[1,200])
+    with the autotuned tile: sampled columns against the oracle, every column
+    against its solo score, and a repeated call bit for bit."""
+    gold = load_golden("ba2m")
+    g = inputs.workload_graph("ba2m")
+    assert g.fingerprint() == gold["fingerprint"]
+    say(f"[full ba2m batch] n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = gold["alpha"]
+    bt = gold["batch"]
+    off, mem = inputs.groups(g.n, bt["groups"], 1, 200, bt["seed"])
+    b = gg.score_batch(off, mem, alpha, EPS)
+    say(f"  tile {gg.batch_tile()}")
+    for rec in bt["sample"]:
+        j = rec["index"]
+        assert off[j + 1] - off[j] == rec["size"]
+        assert rel(b[j], rec["score"]) <= REL, (j, b[j], rec["score"])
+    for j in range(len(off) - 1):
+        solo = gg.score(mem[off[j]:off[j + 1]], alpha, EPS)
+        assert rel(b[j], solo) <= 1e-12, (j, b[j], solo)
+    np.testing.assert_array_equal(gg.score_batch(off, mem, alpha, EPS), b)
+    gg.close()
+
+
 @pytest.mark.timeout(900)
 def test_full_size_rmat22(ged):
     """R-MAT scale 22 at full size: oracle scores, the oracle's first picks, and
