@@ -227,7 +227,7 @@ typedef struct {
   double dominant_ms;        /* their summed duration */
   double dominant_bytes;     /* their summed algorithmic bytes */
   int32_t dominant_columns;  /* its column count C */
-  int32_t dominant_kind;     /* its gather/epilogue variant (input mode * 8 + output mode) */
+  int32_t dominant_kind;     /* its gather/epilogue variant (input mode * 16 + output mode) */
 } ged_profile;
 
 /* Start (on != 0) or stop timing every walk-count step launch of this handle

@@ -31,9 +31,21 @@ Partition &partition(ged_graph *g, int C, bool reverse) {
   auto it = m.find(C);
   if (it != m.end()) return *it->second;
   auto p = std::make_unique<Partition>();
-  build_partition(*p, reverse ? g->h_rp_r : g->h_rp, C);
+  build_partition(*p, reverse ? g->h_rp_r : g->h_rp, C, C);
   Partition &ref = *p;
   m[C] = std::move(p);
+  return ref;
+}
+
+Partition &partition_narrow(ged_graph *g, int C) {
+  if (C < 2) return partition(g, C);
+  auto &m = g->parts;
+  auto it = m.find(-C);  // narrow partitions under negative keys
+  if (it != m.end()) return *it->second;
+  auto p = std::make_unique<Partition>();
+  build_partition(*p, g->h_rp, C, C / 2);
+  Partition &ref = *p;
+  m[-C] = std::move(p);
   return ref;
 }
 
@@ -49,7 +61,11 @@ StepArgs base_args(ged_graph *g, bool reverse) {
 double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows) {
   const double n = (double)g->n, nnz = (double)g->nnz;
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
-  if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_GAINCOMB) b += 8.0 * n * C;  // Y
+  if (out == OUT_TILE32)
+    b += 4.0 * n * C;  // Y32
+  else if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_COMBINE32L &&
+           out != OUT_GAINCOMB)
+    b += 8.0 * n * C;  // Y
   if (g->weighted) b += 8.0 * nnz;
   switch (in) {
     case IN_VEC:
@@ -66,10 +82,12 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case OUT_INJ:
     case OUT_ZERO: b += n / 8.0; break;
     case OUT_TILE:
+    case OUT_TILE32:
     case OUT_POOL: b += 8.0 * n; break;
     case OUT_GAIN: b += n / 8.0 + 4.0 * n; break;
     case OUT_COMBINE:
-    case OUT_COMBINE32: b += 8.0 * n * 3; break;  // tmask, t_a, tr
+    case OUT_COMBINE32:
+    case OUT_COMBINE32L: b += 8.0 * n * 3; break;  // tmask, t_a, tr
     case OUT_GAINCOMB: b += n / 8.0 + 4.0 * n + 16.0 * n; break;  // S bits, candidates, m_a, M_r
     default: break;
   }
@@ -127,7 +145,7 @@ void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int o
   GED_HIP(hipEventRecord(e0, st));
   launch_step(p, a, in, out, st, e1);
   g->prof.recs.push_back({e0, e1, a.C, algo_bytes(g, a.C, in, out, extra_rows),
-                          (double)g->nnz * a.C, in * 8 + out});
+                          (double)g->nnz * a.C, in * kKindBase + out});
 }
 
 // -------------------------------------------------------- precomputation --

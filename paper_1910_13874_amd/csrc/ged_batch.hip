@@ -329,7 +329,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
       GED_HIP(hipStreamWaitEvent(st, b.ev_push[p], 0));
       split_dense(g, b.sw, pl, C, tm[p], st, true, cw[p]);
       // scores of this tile's columns (the buffer has C entries of slack)
-      split_tile_reduce(g, b.sw, C, b.scores.as<double>() + g0, st);
+      split_tile_reduce(g, b.sw, pl, C, b.scores.as<double>() + g0, st);
       GED_HIP(hipEventRecord(b.ev_dense[p], st));
       GED_HIP(hipStreamWaitEvent(b.side, b.ev_dense[p], 0));
       split_tile_clear(g, *cw[p], pl, C, offs, mem, mc, g0, nc, hoff[g0 + nc] - hoff[g0], tm[p],
@@ -348,7 +348,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
                                    b.sw.wl_n.p,    b.sw.ws.blk.p, b.sw.ws.seg.p, b.sw.ws.lng.p,
                                    b.sw2.cnt1.p,   b.sw2.cnt2.p, b.sw2.wl.p,   b.sw2.wl_n.p,
                                    b.tmask2.p,     (const void *)b.side,
-                                   b.sw.ws.red2.p, g->omega2.p, g->prep.tr.p,
+                                   b.sw.ws.red2.p, g->omega2.p, g->omega_lv.p, g->prep.tr.p,
                                    g->prep.t_levels.p, (const void *)st, abits,
                                    (const void *)(uintptr_t)b.sw.wl_cap,
                                    (const void *)(uintptr_t)b.sw2.wl_cap,

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -106,10 +107,13 @@ constexpr int kRowsPerBlock = 511;     // max rows of one row block (row_ptr sli
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 
 // Row partition for a step with C columns: row blocks of consecutive short
-// rows (nnz*C <= lds_values(C)) staged through LDS, and rows longer than that
-// split into fixed segments whose partial sums a fix-up pass combines.
+// rows (nnz*units <= lds_values(C)) staged through LDS, and rows longer than
+// that split into fixed segments whose partial sums a fix-up pass combines.
+// units = 8-byte gather units per arc: C, or C/2 for 32-bit inputs gathered
+// as column pairs (narrow_gather).
 struct Partition {
   int C = 0;
+  int units = 0;
   int n_blocks = 0;  // row blocks
   int n_segs = 0;    // long-row segments
   int n_long = 0;    // long rows
@@ -143,9 +147,15 @@ enum OutMode : int {
   OUT_COMBINE = 6, // y as OUT_TILE, not stored; the column sum takes the split
                    // combination of y with the stored lower levels (split scoring)
   OUT_COMBINE32 = 7, // the same with 32-bit count levels
-  OUT_GAINCOMB = 8   // y as OUT_GAIN, not stored; the column sum takes the split
+  OUT_GAINCOMB = 8,  // y as OUT_GAIN, not stored; the column sum takes the split
                      // combination of a gain chain (undirected greedy)
+  OUT_TILE32 = 9,    // y as OUT_TILE, stored to Y32 as an exact 32-bit integer
+                     // (unscaled walk counts: alpha = 1, inj = integer omega level)
+  OUT_COMBINE32L = 10  // OUT_COMBINE32 whose stored levels are 32-bit counts too
 };
+// Profile records and kernel names encode a (gather, epilogue) pair as
+// in * kKindBase + out.
+constexpr int kKindBase = 16;
 
 struct StepArgs {
   const int *rp = nullptr;       // row_ptr int32 [n+1]
@@ -155,6 +165,7 @@ struct StepArgs {
   int C = 1;
   const double *X = nullptr;     // [n*C]
   double *Y = nullptr;           // [n*C]
+  uint32_t *Y32 = nullptr;       // [n*C] (OUT_TILE32)
   const uint32_t *smask = nullptr;  // S bitmap [ceil(n/32)]
   const uint64_t *tmask = nullptr;  // per-vertex column bits [n]
   const int *cand_col = nullptr;    // [n], -1 = not a candidate
@@ -171,7 +182,8 @@ struct StepArgs {
   const uint32_t *Xc32 = nullptr;  // [n*C]
   // OUT_COMBINE(32): per row v and column c the column sum takes
   //   q + y + y*tr[v] + [v not in S](inj[v] - y) * (q_even ? q + y : q),
-  // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c].
+  // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c]
+  // (OUT_COMBINE32L: sum_l q_slv * q_alpha^l * q_lv[l][v,c], 32-bit counts).
   // Every pointer is valid: an absent input is read at index (o & mask) = 0
   // of some valid buffer and weighted by 0, so the loads are unconditional.
   const double *tr = nullptr;       // [n]
@@ -179,7 +191,8 @@ struct StepArgs {
   const void *q_cnt2 = nullptr;
   uint64_t q_m1 = 0, q_m2 = 0, q_mlv = 0;  // index masks: ~0 present, 0 absent
   double q_s1 = 0, q_s2 = 0, q_slv = 0;    // weights (q_slv = 1 if q_nlv > 0)
-  const double *q_lv = nullptr;     // [q_nlv * n * C]
+  const void *q_lv = nullptr;       // [q_nlv * n * C] double (uint32 for OUT_COMBINE32L)
+  double q_alpha = 0;               // weight ratio of consecutive stored levels (OUT_COMBINE32L)
   int q_nlv = 0;
   int q_even = 0;
 };
@@ -199,7 +212,15 @@ constexpr int kReduceBlocks = 256;
 void launch_reduce(const Partition &p, const StepArgs &a, double *level, double *acc,
                    const int *active, hipStream_t st, double *ws2);
 
-void build_partition(Partition &p, const std::vector<int> &row_ptr, int C);
+void build_partition(Partition &p, const std::vector<int> &row_ptr, int C, int units);
+
+// 32-bit inputs at C >= 2 are gathered as pairs of adjacent columns (8 bytes
+// per lane), so a wavefront's load covers as many cache lines as an FP64
+// gather and keeps as many in flight; such steps take the partition of
+// partition_narrow (blocks of kLdsDoubles / (C/2) arcs).
+__host__ __device__ constexpr bool narrow_gather(int C, int in_mode, bool weighted) {
+  return in_mode == IN_CNT32 && C >= 2 && !weighted;
+}
 
 // Partial-sum buffers of one step stream (each path owns its own, so captured
 // graphs never see a buffer another path reallocated).
@@ -259,12 +280,16 @@ struct SplitPlan {
   int a = 0, r = 0, s = 0, nlv = 0;  // nlv = dense levels stored (s+1 .. a-1)
   bool even = false;                 // r == a
   bool c32 = false;                  // counts fit 32 bits (max degree < 2^16)
+  // stored levels are unscaled 32-bit counts: count_i(v) <= omega_i(v), the
+  // number of all walks of length i ending at v, and max omega_i < 2^32 for
+  // every stored level (set by split_tables)
+  bool lv32 = false;
 };
 
 struct SplitWs {
   DBuf cnt1, cnt2;       // [n*C] walk counts of levels 1, 2 (uint32 or uint64); zero
                          // between tiles
-  DBuf lv;               // double [nlv*n*C] stored dense levels
+  DBuf lv;               // [nlv*n*C] stored dense levels (double, or uint32 counts)
   DBuf wl, wl_n;         // uint64 worklist [wl_cap], uint32 length
   unsigned wl_cap = 0;
   int wl_blocks = 64;    // grid of the worklist kernels (any value is correct)
@@ -335,6 +360,11 @@ struct ged_graph {
   // split scoring
   ged::DBuf omega2;             // uint64 [n] walks of length 2 ending at v (unweighted)
   bool omega2_ready = false;
+  // omega_i(v) for i = 3 .. omega_top, exact integers as doubles [(omega_top-2)*n];
+  // omega_fit = largest i <= omega_top with max_v omega_j(v) < 2^32 for 3 <= j <= i
+  ged::DBuf omega_lv;
+  int omega_top = 2, omega_fit = 2;
+  std::list<ged::DBuf> omega_old;  // replaced omega_lv buffers, freed with the graph
   std::vector<uint32_t> stamp;  // host group-dedup stamps
   uint32_t stamp_gen = 0;
   ged::SplitWs split_ws;        // single-group scoring workspace
@@ -352,6 +382,8 @@ namespace ged {
 
 // Partition for C columns (built on first use).
 Partition &partition(ged_graph *g, int C, bool reverse = false);
+// The partition of a narrow_gather step with C columns (forward rows).
+Partition &partition_narrow(ged_graph *g, int C);
 // Precompute for (alpha, eps); throws HipError, returns status for arg errors.
 int prepare(ged_graph *g, double alpha, double eps);
 // W[ell] for arbitrary ell (extends the total-walk chain on demand).
@@ -387,8 +419,11 @@ void greedy_forget(const ged_graph *g);
 // Split scoring (ged_split.hip).
 bool split_ok(const ged_graph *g);
 SplitPlan split_plan(const ged_graph *g, int ell);
-// Make sure per-graph split tables (omega2, tr) exist for the prepared (alpha, eps).
-void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st);
+// Make sure per-graph split tables (omega2, tr, and the integer omega levels
+// of the stored levels) exist for the prepared (alpha, eps), and set pl.lv32.
+// The first call that needs new omega levels synchronizes the stream once to
+// read their maxima.
+void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st);
 // Size a workspace for C columns and a worklist of wl_need entries; zero the
 // count arrays if they are new or dirty.
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
@@ -412,7 +447,8 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
 void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                      const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
                      uint64_t *tmask, hipStream_t st);
-void split_tile_reduce(ged_graph *g, SplitWs &w, int C, double *out, hipStream_t st);
+void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, double *out,
+                       hipStream_t st);
 void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                       const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
                       uint64_t *tmask, hipStream_t st);

@@ -14,6 +14,9 @@
 //     from the block's row count, reduces lanes with DPP/bpermute shuffles and
 //     writes the masked output coalesced.  Column partial sums of the block go
 //     to blk_part in a fixed tree order.
+//     32-bit inputs at C >= 2 (integer walk counts) are gathered as pairs of
+//     adjacent columns, 8 bytes per lane like an FP64 value, into blocks of
+//     twice the arcs, so each wavefront keeps as many cache lines in flight.
 //   * long rows (more arcs than a row block holds, the power-law hubs): split
 //     into fixed segments, one block each, whose raw sums go to seg_out; a
 //     fix-up kernel adds the segments of each row in order.
@@ -69,7 +72,8 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
     return inS ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_ZERO) {
     return inS ? 0.0 : y;
-  } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32) {
+  } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
+                       OUT == OUT_TILE32 || OUT == OUT_COMBINE32L) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
@@ -91,38 +95,66 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
 //   sum_{i<a} h_i + h_a + h_a * sum_{c<=r} t_c + [v not in S](t_a - h_a) * sum_{c<=r} h_c.
 // Raw inputs of the combination for row v, column c: the two count levels,
 // the first stored dense level, sum_{c<=r} t_c(v) and t_a(v).  Loads only, so
-// they can be issued early and consumed later.
-template <int C, bool C32>
+// they can be issued early and consumed later.  C32: the count levels are
+// 32-bit.  LV32: the stored levels are unscaled 32-bit counts too, level l
+// weighted by q_slv * q_alpha^l; otherwise they hold h_i itself (weight 1).
+template <int C, bool C32, bool LV32>
 struct CombineIn {
   using CT = typename std::conditional<C32, uint32_t, uint64_t>::type;
+  using LT = typename std::conditional<LV32, uint32_t, double>::type;
   CT c1 = 0, c2 = 0;
-  double lv0 = 0.0, trv = 0.0, ta = 0.0;
+  LT lv0 = 0;
+  double trv = 0.0, ta = 0.0;
   __device__ __forceinline__ void load(const StepArgs &a, int v, int c) {
     const uint64_t o = (uint64_t)v * C + c;
     c1 = static_cast<const CT *>(a.q_cnt1)[o & a.q_m1];
     c2 = static_cast<const CT *>(a.q_cnt2)[o & a.q_m2];
-    lv0 = a.q_lv[o & a.q_mlv];
+    lv0 = static_cast<const LT *>(a.q_lv)[o & a.q_mlv];
     trv = a.tr[v];
     ta = a.inj[v];
   }
   // sum_{i<a} h_i(v) for column c (levels beyond the first stored one are
   // loaded here; there are none unless ell* > 8)
   __device__ __forceinline__ double q(const StepArgs &a, int v, int c) const {
-    double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * lv0;
+    double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * (double)lv0;
+    const LT *lv = static_cast<const LT *>(a.q_lv);
     const size_t o = (size_t)v * C + c, ls = (size_t)a.n * C;
+    double w = a.q_slv;
     int l = 1;
     for (; l + 3 < a.q_nlv; l += 4) {  // four loads in flight, added in level order
-      const double x0 = a.q_lv[l * ls + o], x1 = a.q_lv[(l + 1) * ls + o];
-      const double x2 = a.q_lv[(l + 2) * ls + o], x3 = a.q_lv[(l + 3) * ls + o];
-      s += x0;
-      s += x1;
-      s += x2;
-      s += x3;
+      const LT x0 = lv[l * ls + o], x1 = lv[(l + 1) * ls + o];
+      const LT x2 = lv[(l + 2) * ls + o], x3 = lv[(l + 3) * ls + o];
+      if constexpr (LV32) {
+        w *= a.q_alpha;
+        s += w * (double)x0;
+        w *= a.q_alpha;
+        s += w * (double)x1;
+        w *= a.q_alpha;
+        s += w * (double)x2;
+        w *= a.q_alpha;
+        s += w * (double)x3;
+      } else {
+        s += x0;
+        s += x1;
+        s += x2;
+        s += x3;
+      }
     }
-    for (; l < a.q_nlv; ++l) s += a.q_lv[l * ls + o];
+    for (; l < a.q_nlv; ++l) {
+      if constexpr (LV32) {
+        w *= a.q_alpha;
+        s += w * (double)lv[l * ls + o];
+      } else {
+        s += lv[l * ls + o];
+      }
+    }
     return s;
   }
 };
+
+template <int C, int OUT>
+using CombineFor = CombineIn<C, OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L,
+                             OUT == OUT_COMBINE32L>;
 
 // y is h_a(v) (t_a(v) for v in S), q = sum_{i<a} h_i(v), trv = sum_{c<=r} t_c(v),
 // ta = t_a(v).
@@ -137,7 +169,7 @@ template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
   constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
-                      OUT == OUT_COMBINE32;
+                      OUT == OUT_COMBINE32 || OUT == OUT_TILE32 || OUT == OUT_COMBINE32L;
   constexpr bool CA = OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
                             TM ? a.tmask[v] : 0ull, CA ? a.cand_col[v] : -1);
@@ -164,19 +196,44 @@ __device__ __forceinline__ void block_colsum(double v, int tpr, double *red, dou
   }
 }
 
+// The same for lanes holding a pair of columns (2k, 2k+1), k = t % (C/2), one
+// value each; every lane carries values (tpr = 1).
+template <int C>
+__device__ __forceinline__ void block_colsum_pairs(double v0, double v1, double *red,
+                                                   double *out) {
+  constexpr int CU = C / 2;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int o = CU; o < 64; o <<= 1) {
+    v0 += __shfl_xor(v0, o, 64);
+    v1 += __shfl_xor(v1, o, 64);
+  }
+  if (lane < CU) {
+    red[w * C + 2 * lane] = v0;
+    red[w * C + 2 * lane + 1] = v1;
+  }
+  __syncthreads();
+  if (t < C) out[t] = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
+}
+
 template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
-  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_GAINCOMB;
+  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L ||
+                       OUT == OUT_GAINCOMB;
   constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
-                      OUT == OUT_COMBINE32;
+                      OUT == OUT_COMBINE32 || OUT == OUT_TILE32 || OUT == OUT_COMBINE32L;
   constexpr bool CA = OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
-  constexpr int LV = lds_values(C);          // values staged per block
-  constexpr int PT = LV / kBlock;            // gathered values per thread
+  // NP: 32-bit input gathered as column pairs; a gather unit is 8 bytes
+  // either way (one FP64 value or two 32-bit values), CU units per arc
+  constexpr bool NP = narrow_gather(C, IN, WGT);
+  constexpr int CU = NP ? C / 2 : C;
+  constexpr int LV = lds_values(C);          // gather units staged per block
+  constexpr int PT = LV / kBlock;            // gather units per thread
   constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
-  // vals has one spare slot per thread so every phase-1 store is unconditional
-  __shared__ double vals[LV + kBlock];
+  using SV = typename std::conditional<NP, uint32_t, double>::type;
+  // vals has one spare unit per thread so every phase-1 store is unconditional
+  __shared__ SV vals[(NP ? 2 : 1) * (LV + kBlock)];
   __shared__ int rps[kRowsPerBlock + 1];
   __shared__ double red[(kBlock / 64) * C];
   __shared__ uint32_t mw[M1 ? kRowsPerBlock / 32 + 2 : 1];
@@ -189,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     // descriptor: rows [r0, r0 + nrows), arcs [p0, p1)
     const int4 d = blocks[b];
     const int r0 = d.x, nrows = d.y - d.x, p0 = d.z;
-    const int tot = (d.w - d.z) * C;
+    const int tot = (d.w - d.z) * CU;  // gather units of the block
     if (t < (kBlock / 64) * C) red[t] = 0.0;
     // Phase 1.  Load order matters: the col_idx stream first, then the row
     // pointers and epilogue masks of the block, then the gathers (which wait
@@ -202,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     int u[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-      u[q] = __builtin_nontemporal_load(a.ci + min(jlo + (t + q * kBlock) / C, jmax));
+      u[q] = __builtin_nontemporal_load(a.ci + min(jlo + (t + q * kBlock) / CU, jmax));
       if (tot == 0) u[q] = 0;
     }
     int rv[RT];
@@ -224,13 +281,19 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     int tpr = (kBlock / C < 64) ? kBlock / C : 64;
     while (tpr > 1 && nrows * C * tpr > kBlock) tpr >>= 1;
     const int rl0 = (t / tpr) / C;
-    CombineIn<C, OUT == OUT_COMBINE32> pf;
+    CombineFor<C, OUT> pf;
     if constexpr (CB) pf.load(a, r0 + min(rl0, nrows - 1), (t / tpr) & (C - 1));
-    double v[PT];
+    double v[NP ? 1 : PT];
+    uint2 v2[NP ? PT : 1];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-      v[q] = load_in<C, IN>(a, u[q], (t + q * kBlock) & (C - 1));
-      if constexpr (WGT) v[q] *= a.w[min(jlo + (t + q * kBlock) / C, jmax)];
+      if constexpr (NP) {
+        v2[q] = *reinterpret_cast<const uint2 *>(a.Xc32 + (size_t)u[q] * C +
+                                                 2 * ((t + q * kBlock) & (CU - 1)));
+      } else {
+        v[q] = load_in<C, IN>(a, u[q], (t + q * kBlock) & (C - 1));
+        if constexpr (WGT) v[q] *= a.w[min(jlo + (t + q * kBlock) / C, jmax)];
+      }
     }
 #pragma unroll
     for (int k = 0; k < RT; ++k)
@@ -246,7 +309,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int f = t + q * kBlock;
-      vals[f < tot ? f : LV + t] = v[q];
+      if constexpr (NP)
+        reinterpret_cast<uint2 *>(vals)[f < tot ? f : LV + t] = v2[q];
+      else
+        vals[f < tot ? f : LV + t] = v[q];
     }
     __syncthreads();
     // Phase 2: tpr lanes per (row, column), as many as the row count allows.
@@ -258,14 +324,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     for (int rl = pair / C; rl < nrows; rl += rstep) {
       const int j0 = rps[rl], j1 = rps[rl + 1];
       double acc = 0.0;
-      for (int j = j0 + s; j < j1; j += tpr) acc += vals[j * C + c];
+      for (int j = j0 + s; j < j1; j += tpr) acc += (double)vals[j * C + c];
       for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
       if (s == 0) {
         const int r = r0 + rl;
         bool inS = false;
         if constexpr (M1) inS = (mw[(r >> 5) - (r0 >> 5)] >> (r & 31)) & 1u;
         if constexpr (CB) {
-          CombineIn<C, OUT == OUT_COMBINE32> in = pf;
+          CombineFor<C, OUT> in = pf;
           if (rl != rl0) in.load(a, r, c);
           double y;
           bool member = false;
@@ -280,12 +346,39 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         } else {
           const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
                                               CA ? cw[rl] : -1);
-          a.Y[(size_t)r * C + c] = y;
+          if constexpr (OUT == OUT_TILE32)
+            a.Y32[(size_t)r * C + c] = (uint32_t)y;
+          else
+            a.Y[(size_t)r * C + c] = y;
           colsum += y;
         }
       }
     }
     block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C, a.accum);
+  } else if constexpr (NP) {
+    // One segment of a long row, column pairs: kBlock / CU lanes per pair.
+    const int4 sd = segs[b - n_blocks];
+    const int k = t & (CU - 1);
+    const int s = t / CU;
+    constexpr int LPU = kBlock / CU;
+    constexpr int U = 8;  // arcs in flight per lane
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int j0 = sd.y + s; j0 < sd.z; j0 += U * LPU) {
+      int u[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) u[q] = __builtin_nontemporal_load(a.ci + min(j0 + q * LPU, sd.z - 1));
+      uint2 v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        v[q] = *reinterpret_cast<const uint2 *>(a.Xc32 + (size_t)u[q] * C + 2 * k);
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const bool ok = j0 + q * LPU < sd.z;
+        acc0 += ok ? (double)v[q].x : 0.0;
+        acc1 += ok ? (double)v[q].y : 0.0;
+      }
+    }
+    block_colsum_pairs<C>(acc0, acc1, red, a.seg_out + (size_t)(b - n_blocks) * C);
   } else {
     // One segment of a long row: LPC lanes per column stride over its arcs.
     const int4 sd = segs[b - n_blocks];
@@ -331,11 +424,14 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   double y = epilogue<C, OUT>(a, r, c, acc);
-  if constexpr (OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_GAINCOMB) {
-    CombineIn<C, OUT == OUT_COMBINE32> in;
+  if constexpr (OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L ||
+                OUT == OUT_GAINCOMB) {
+    CombineFor<C, OUT> in;
     in.load(a, r, c);
     const bool member = OUT == OUT_GAINCOMB ? false : ((a.tmask[r] >> c) & 1ull);
     y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, member);
+  } else if constexpr (OUT == OUT_TILE32) {
+    a.Y32[(size_t)r * C + c] = (uint32_t)y;
   } else {
     a.Y[(size_t)r * C + c] = y;
   }
@@ -427,6 +523,8 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_CNT32, OUT_TILE)
     GED_CASE(IN_CNT32, OUT_COMBINE32)
     GED_CASE(IN_VEC, OUT_COMBINE32)
+    GED_CASE(IN_CNT32, OUT_TILE32)
+    GED_CASE(IN_CNT32, OUT_COMBINE32L)
   }
   if constexpr (C == 8) {  // the greedy's candidate batches
     GED_CASE(IN_ONEHOT, OUT_GAINCOMB)
@@ -462,6 +560,9 @@ static bool dispatch_c(int C, int in, int out, const Partition &p, const StepArg
 void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
                  hipStream_t st, hipEvent_t after_main) {
   if (a.C != p.C) throw HipError{GED_ERR_ARG, "step column count does not match partition"};
+  const int units = narrow_gather(a.C, in_mode, a.w != nullptr) ? a.C / 2 : a.C;
+  if (p.units != units)
+    throw HipError{GED_ERR_ARG, "step gather width does not match partition"};
   const bool ok = a.w ? dispatch_c<true>(a.C, in_mode, out_mode, p, a, st, after_main)
                       : dispatch_c<false>(a.C, in_mode, out_mode, p, a, st, after_main);
   if (!ok)
@@ -497,10 +598,10 @@ void launch_reduce(const Partition &p, const StepArgs &a, double *level, double 
 
 // ----------------------------------------------------------- partition --
 
-void build_partition(Partition &p, const std::vector<int> &rp, int C) {
+void build_partition(Partition &p, const std::vector<int> &rp, int C, int units) {
   const int n = (int)rp.size() - 1;
-  const int nnz_blk = lds_values(C) / C;
-  const int seg_len = std::max(1, kSegDoubles / C);
+  const int nnz_blk = lds_values(C) / units;
+  const int seg_len = std::max(1, kSegDoubles / units);
   std::vector<int4> blocks;
   std::vector<int4> segs;
   std::vector<int> lrows, lfirst;
@@ -528,6 +629,7 @@ void build_partition(Partition &p, const std::vector<int> &rp, int C) {
   }
   lfirst.push_back((int)segs.size());
   p.C = C;
+  p.units = units;
   p.n_blocks = (int)blocks.size();
   p.n_segs = (int)segs.size();
   p.n_long = (int)lrows.size();

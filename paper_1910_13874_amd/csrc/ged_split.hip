@@ -24,6 +24,14 @@
 // and every non-member y adjacent to S pushes count_1(y) to N(y) once, from a
 // worklist of (y, column, chunk) entries that splits long rows.  Everything a
 // tile touched is cleared by replaying the same traversal with stores of 0.
+//
+// The dense levels i = 3 .. a-1 that the combining step reads back are the
+// same integer counts scaled by alpha^i, and count_i(v) <= omega_i(v), the
+// number of all walks of length i ending at v.  When max_v omega_i(v) < 2^32
+// for each of them they are stored unscaled as 32-bit integers (half the
+// bytes of FP64, so a 32-column tile gathers one 128-byte line per vertex):
+// members take the exact omega_i(v), computed once per graph by an integer
+// chain, and alpha^a is applied once in the combining step.
 #include <algorithm>
 #include <cstring>
 
@@ -208,6 +216,35 @@ __global__ __launch_bounds__(kBlock) void k_omega2(const int *__restrict__ rp,
   }
 }
 
+// omega_i(v) = sum_{u in N(v)} omega_{i-1}(u), saturating at 2^64 - 1, also
+// written as a double (exact below 2^53, the only range it is used in); the
+// wave's largest value goes to *maxv.  One wavefront per row, as k_omega2.
+__device__ __forceinline__ unsigned long long sat_add(unsigned long long x, unsigned long long y) {
+  const unsigned long long z = x + y;
+  return z < x ? ~0ull : z;
+}
+
+__global__ __launch_bounds__(kBlock) void k_omega_next(const int *__restrict__ rp,
+                                                       const int *__restrict__ ci, int n,
+                                                       const unsigned long long *__restrict__ prev,
+                                                       unsigned long long *out, double *out_d,
+                                                       unsigned long long *maxv) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  unsigned long long m = 0;
+  for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; v < n; v += nw) {
+    unsigned long long s = 0;
+    for (int k = rp[v] + lane; k < rp[v + 1]; k += 64) s = sat_add(s, prev[ci[k]]);
+    for (int o = 32; o > 0; o >>= 1) s = sat_add(s, __shfl_xor(s, o, 64));
+    if (lane == 0) {
+      out[v] = s;
+      out_d[v] = (double)s;
+      m = s > m ? s : m;
+    }
+  }
+  if (lane == 0 && m > 0) atomicMax(maxv, m);
+}
+
 // tr(v) = sum_{c=1..r} t_c(v), added in level order.
 __global__ void k_sum_t(const double *__restrict__ T, int64_t n, int r, double *out) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
@@ -224,7 +261,47 @@ static int grid_for(int64_t items, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
 }
 
-void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st) {
+// omega_3 .. omega_top as doubles (levels past the first one whose maximum
+// reaches 2^32 are not computed).  Built in fresh buffers and published after
+// the stream has finished them; a replaced buffer is kept until the graph is
+// destroyed, since captured work may still name it.
+static void omega_levels(ged_graph *g, int top, hipStream_t st) {
+  const int64_t n = g->n;
+  const int L = top - 2;
+  DBuf lv, tmp, mx;
+  lv.ensure(sizeof(double) * (size_t)n * L);
+  tmp.ensure(2 * sizeof(unsigned long long) * (size_t)n);
+  mx.ensure(sizeof(unsigned long long) * L);
+  launch_fill_i32(mx.as<int>(), 0, (size_t)L * 2, st);
+  const int og = (int)std::max<int64_t>(
+      1, std::min<int64_t>(16384, (n + kBlock / 64 - 1) / (kBlock / 64)));
+  unsigned long long *t2 = tmp.as<unsigned long long>();
+  for (int i = 3; i <= top; ++i) {
+    const unsigned long long *prev = i == 3 ? g->omega2.as<const unsigned long long>()
+                                            : t2 + (size_t)((i - 1) & 1) * n;
+    hipLaunchKernelGGL(k_omega_next, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
+                       g->ci.as<const int>(), (int)n, prev, t2 + (size_t)(i & 1) * n,
+                       lv.as<double>() + (size_t)(i - 3) * n, mx.as<unsigned long long>() + (i - 3));
+    GED_HIP(hipGetLastError());
+  }
+  std::vector<unsigned long long> hm((size_t)L);
+  GED_HIP(hipMemcpyAsync(hm.data(), mx.p, sizeof(unsigned long long) * L, hipMemcpyDeviceToHost,
+                         st));
+  GED_HIP(hipStreamSynchronize(st));
+  int fit = 2;
+  while (fit < top && hm[(size_t)(fit - 2)] < (1ull << 32)) ++fit;
+  if (g->omega_lv.p) {
+    g->omega_old.emplace_back();
+    std::swap(g->omega_old.back().p, g->omega_lv.p);
+    std::swap(g->omega_old.back().bytes, g->omega_lv.bytes);
+  }
+  std::swap(g->omega_lv.p, lv.p);
+  std::swap(g->omega_lv.bytes, lv.bytes);
+  g->omega_top = top;
+  g->omega_fit = fit;
+}
+
+void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st) {
   const int64_t n = g->n;
   const int eg = (int)std::min<int64_t>(8192, (n + kBlock - 1) / kBlock);
   if (pl.s >= 2 && !g->omega2_ready) {
@@ -234,6 +311,15 @@ void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st) {
                        g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>());
     GED_HIP(hipGetLastError());
     g->omega2_ready = true;
+  }
+  // 32-bit stored levels: 3 .. a-1 must all fit (levels only grow past a
+  // level that does not, so none is computed beyond the first that fails)
+  pl.lv32 = false;
+  if (pl.nlv > 0 && pl.c32 && pl.s == 2) {
+    const int need = pl.a - 1;
+    if (need > g->omega_top && g->omega_fit == g->omega_top)
+      omega_levels(g, std::max(need, 4), st);
+    pl.lv32 = g->omega_fit >= need;
   }
   PrepCache &pc = g->prep;
   if (pc.tr_r != pl.r) {
@@ -245,11 +331,26 @@ void split_tables(ged_graph *g, const SplitPlan &pl, hipStream_t st) {
   }
 }
 
+// Gather of the last (combining) dense level of a tile.
+static int final_in(const SplitPlan &pl) {
+  if (pl.lv32) return IN_CNT32;
+  if (pl.a == 1) return IN_TILEMASK;
+  if (pl.a == pl.s + 1) return pl.c32 ? IN_CNT32 : IN_CNT;
+  return IN_VEC;
+}
+
+// Partition of a step gathering `in` at C columns.
+static Partition &step_partition(ged_graph *g, int C, int in) {
+  return narrow_gather(C, in, g->weighted) ? partition_narrow(g, C) : partition(g, C);
+}
+
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
                hipStream_t st, bool counts_only) {
   const size_t nC = (size_t)g->n * C;
-  Partition &p = partition(g, C);
-  if (!counts_only) w.ws.fit(p);
+  if (!counts_only) {
+    w.ws.fit(partition(g, C));
+    if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, C, IN_CNT32));
+  }
   if (pl.s >= 1) {
     const size_t cb = (pl.c32 ? sizeof(uint32_t) : sizeof(uint64_t)) * nC;
     if (w.cnt1.bytes < cb || w.cnt2.bytes < cb) {
@@ -272,7 +373,8 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
       w.wl_cap = (unsigned)cap;
     }
   }
-  if (pl.nlv > 0 && !counts_only) w.lv.ensure(sizeof(double) * nC * (size_t)pl.nlv);
+  if (pl.nlv > 0 && !counts_only)
+    w.lv.ensure((pl.lv32 ? sizeof(uint32_t) : sizeof(double)) * nC * (size_t)pl.nlv);
 }
 
 template <class CT>
@@ -322,6 +424,7 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
   const PrepCache &pc = g->prep;
   const double alpha = pc.alpha;
   Partition &p = partition(g, C);
+  Partition &pn = step_partition(g, C, IN_CNT32);  // 32-bit gathers (count levels)
   const double *T = pc.t_levels.as<const double>();
   const SplitWs &cw = counts ? *counts : w;
   const void *c1 = pl.s >= 1 ? cw.cnt1.p : nullptr;
@@ -329,11 +432,54 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
   double lv_scale = alpha;  // alpha^(s+1) for the first dense level after the counts
   for (int i = 0; i < pl.s; ++i) lv_scale *= alpha;
   double *lv = w.lv.as<double>();
+  uint32_t *lv32 = w.lv.as<uint32_t>();
   StepArgs a = base_args(g);
   w.ws.into(a);
   a.C = C;
   a.tmask = tmask;
   a.accum = 0;
+  if (pl.lv32) {
+    // unscaled 32-bit counts for levels s+1 .. a-1 (members: omega_i), then
+    // h_a = alpha^a * (sum of level a-1 counts) in the combining step
+    const double *om = g->omega_lv.as<const double>();
+    double alpha_a = lv_scale;  // alpha^(s+1)
+    for (int i = pl.s + 1; i < pl.a; ++i) alpha_a *= alpha;
+    for (int i = pl.s + 1; i <= pl.a; ++i) {
+      a.Xc32 = i == pl.s + 1 ? static_cast<const uint32_t *>(c2) : lv32 + (size_t)(i - 2 - pl.s) * nC;
+      if (i < pl.a) {
+        a.alpha = 1.0;
+        a.inj = om + (size_t)(i - 3) * n;
+        a.Y32 = lv32 + (size_t)(i - 1 - pl.s) * nC;
+        if (profile)
+          run_step(g, pn, a, IN_CNT32, OUT_TILE32, st);
+        else
+          launch_step(pn, a, IN_CNT32, OUT_TILE32, st);
+      } else {
+        a.alpha = alpha_a;
+        a.inj = T + (size_t)i * n;
+        a.Y = nullptr;
+        a.Y32 = nullptr;
+        a.tr = pc.tr.as<const double>();
+        a.q_cnt1 = c1;
+        a.q_cnt2 = c2;
+        a.q_m1 = ~0ull;
+        a.q_m2 = ~0ull;
+        a.q_s1 = alpha;
+        a.q_s2 = alpha * alpha;
+        a.q_lv = lv32;
+        a.q_mlv = ~0ull;
+        a.q_slv = lv_scale;
+        a.q_alpha = alpha;
+        a.q_nlv = pl.nlv;
+        a.q_even = pl.even ? 1 : 0;
+        if (profile)
+          run_step(g, pn, a, IN_CNT32, OUT_COMBINE32L, st, 0.5 * (pl.s + pl.nlv));
+        else
+          launch_step(pn, a, IN_CNT32, OUT_COMBINE32L, st);
+      }
+    }
+    return;
+  }
   for (int i = pl.s + 1; i <= pl.a; ++i) {
     int in;
     if (i == 1) {
@@ -355,12 +501,13 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
       a.alpha = alpha;
     }
     a.inj = T + (size_t)i * n;
+    Partition &ps = in == IN_CNT32 ? pn : p;
     if (i < pl.a) {
       a.Y = lv + (size_t)(i - 1 - pl.s) * nC;
       if (profile)
-        run_step(g, p, a, in, OUT_TILE, st);
+        run_step(g, ps, a, in, OUT_TILE, st);
       else
-        launch_step(p, a, in, OUT_TILE, st);
+        launch_step(ps, a, in, OUT_TILE, st);
     } else {
       // absent inputs: index mask 0 into a valid buffer, weight 0
       const double *any = pc.tr.as<const double>();
@@ -379,9 +526,9 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
       a.q_even = pl.even ? 1 : 0;
       const int out = (pl.c32 && pl.s >= 1) ? OUT_COMBINE32 : OUT_COMBINE;
       if (profile)
-        run_step(g, p, a, in, out, st, pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
+        run_step(g, ps, a, in, out, st, pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
       else
-        launch_step(p, a, in, out, st);
+        launch_step(ps, a, in, out, st);
     }
   }
 }
@@ -413,11 +560,14 @@ void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, cons
   launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
 }
 
-void split_tile_reduce(ged_graph *g, SplitWs &w, int C, double *out, hipStream_t st) {
+void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, double *out,
+                       hipStream_t st) {
   StepArgs a = base_args(g);
   w.ws.into(a);
   a.C = C;
-  launch_reduce(partition(g, C), a, out, nullptr, nullptr, st, w.ws.scratch());
+  // the partials are laid out by the partition of the combining step
+  launch_reduce(step_partition(g, C, final_in(pl)), a, out, nullptr, nullptr, st,
+                w.ws.scratch());
 }
 
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
@@ -426,7 +576,7 @@ void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         bool profile) {
   split_tile_push(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st);
   split_dense(g, w, pl, C, tmask, st, profile);
-  split_tile_reduce(g, w, C, out, st);
+  split_tile_reduce(g, w, pl, C, out, st);
   split_tile_clear(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st);
 }
 
@@ -464,7 +614,7 @@ static void drop_exec(ged_graph *g) {
 int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   hipStream_t st = g->stream;
   const int64_t n = g->n;
-  const SplitPlan pl = split_plan(g, g->prep.ell);
+  SplitPlan pl = split_plan(g, g->prep.ell);
   std::vector<int> mem;
   mem.reserve((size_t)s_len);
   const int64_t deg_sum = map_group(g, S, s_len, mem);
@@ -519,7 +669,7 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
     std::vector<const void *> sig = {
         g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.ws.blk.p, w.ws.seg.p,
         w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
-        g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
+        g->omega_lv.p, g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
         (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
         (const void *)(intptr_t)1 /* split */};
     if (g->score_exec && sig != g->score_sig) drop_exec(g);

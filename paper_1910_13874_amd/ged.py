@@ -378,13 +378,15 @@ class Server:
             pass
 
 
-IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh"]
-OUT_MODES = ["plain", "inj", "zero", "tile", "gain", "pool"]
+IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh", "cnt", "cnt32"]
+OUT_MODES = ["plain", "inj", "zero", "tile", "gain", "pool", "combine", "combine32", "gaincomb",
+             "tile32", "combine32l"]
+KIND_BASE = 16  # a profile record's kind is input mode * KIND_BASE + output mode
 
 
 def kernel_name(columns, kind, weighted=False):
     """Symbol of the step-kernel instantiation a profile record refers to."""
-    return (f"ged::k_step<{columns}, {kind // 8}, {kind % 8}, "
+    return (f"ged::k_step<{columns}, {kind // KIND_BASE}, {kind % KIND_BASE}, "
             f"{'true' if weighted else 'false'}>")
 
 

@@ -108,6 +108,66 @@ def split_score(row_ptr, col_idx, S, alpha: float, ell: int, w=None) -> float:
     return float(contrib.sum())
 
 
+def omega_levels(row_ptr, col_idx, top: int):
+    """omega_i(v) = # walks of length i ending at v, i = 0..top, as exact Python ints."""
+    n = len(row_ptr) - 1
+    om = [[1] * n]
+    for _ in range(top):
+        prev = om[-1]
+        om.append([sum(prev[int(u)] for u in col_idx[row_ptr[v]:row_ptr[v + 1]])
+                   for v in range(n)])
+    return om
+
+
+def count_levels(row_ptr, col_idx, S, top: int):
+    """count_i(v) = h_i(v) / alpha^i for i = 1..top as exact Python ints: the
+    hit chain's integer walk counts (members hold omega_i)."""
+    n = len(row_ptr) - 1
+    inS = set(int(v) for v in S)
+    om = omega_levels(row_ptr, col_idx, top)
+    cnt = [[1 if v in inS else 0 for v in range(n)]]
+    for i in range(1, top + 1):
+        prev = cnt[-1]
+        cnt.append([om[i][v] if v in inS else
+                    sum(prev[int(u)] for u in col_idx[row_ptr[v]:row_ptr[v + 1]])
+                    for v in range(n)])
+    return cnt, om
+
+
+def split_score_counts(row_ptr, col_idx, S, alpha: float, ell: int) -> float:
+    """Split scoring with the dense levels s+1..a-1 kept as unscaled integer
+    counts (the 32-bit layout of the kernels): level i weighted by alpha^i in
+    the combination, and h_a = alpha^a * (sum of level a-1 counts) outside S."""
+    n = len(row_ptr) - 1
+    S = np.unique(np.asarray(S, dtype=np.int64))
+    if S.size == 0:
+        return 0.0
+    inS = np.zeros(n, dtype=bool)
+    inS[S] = True
+    T = [np.ones(n)]
+    for _ in range(ell):
+        T.append(alpha * _spmv(row_ptr, col_idx, None, T[-1]))
+    a, r, s = plan(ell, False)
+    assert s == 2 and a - 1 > s, "the count layout has stored levels"
+    cnt, _ = count_levels(row_ptr, col_idx, S, a - 1)
+    q = np.zeros(n)
+    wgt = alpha
+    for i in range(1, a):
+        q = q + wgt * np.array(cnt[i], dtype=np.float64)
+        wgt *= alpha
+    alpha_a = alpha ** (s + 1)
+    for _ in range(s + 1, a):
+        alpha_a *= alpha
+    ha = alpha_a * _spmv(row_ptr, col_idx, None, np.array(cnt[a - 1], dtype=np.float64))
+    ha[inS] = T[a][inS]
+    tr = np.zeros(n)
+    for c in range(1, r + 1):
+        tr = tr + T[c]
+    rs = q + ha if r == a else q
+    contrib = (q + ha) + ha * tr + np.where(inS, 0.0, (T[a] - ha) * rs)
+    return float(contrib.sum())
+
+
 def split_gain(row_ptr, col_idx, S, x: int, alpha: float, ell: int, w=None) -> float:
     """L_ell(S, x) from the miss chain and the gain chain up to a = ceil(ell/2),
     as the greedy's split evaluation does:

@@ -401,6 +401,76 @@ def test_split_ell_sweep(ged, name):
     gg.close()
 
 
+def omega_max(g, top):
+    """max_v omega_i(v) (walks of length i ending at v) for i = 0..top, in float64
+    (exact while below 2^53, which covers every comparison with 2^32 here)."""
+    om = np.ones(g.n)
+    out = [1.0]
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    for _ in range(top):
+        om = np.bincount(rows, weights=om[g.col_idx], minlength=g.n)
+        out.append(float(om.max()))
+    return out
+
+
+@pytest.mark.parametrize("name", ["sparse_er", "star"])
+def test_split_count_layout(ged, name):
+    """Dense split levels stored as unscaled 32-bit counts when every stored
+    level's omega maximum is below 2^32, FP64 otherwise.  "sparse_er" (average
+    degree 3) keeps omega small for many levels, so ell* = 7..17 stores 1..6
+    levels as 32-bit counts (the combining step's four-level loop and its
+    remainder), while ell* = 29 needs omega_14 > 2^32 and stores FP64; "star" (70,000 leaves, no duplicate arcs, so 32-bit counts)
+    has omega_3 = 70,000^2 > 2^32 and must keep FP64 levels.  The profiled
+    dominant step kernel shows which layout ran; scores single and batched
+    against the oracle."""
+    if name == "sparse_er":
+        g = inputs.erdos_renyi(3000, 4500, 57)
+        ells = list(range(7, 18, 2)) + [29]  # 29: omega_14 > 2^32, back to FP64
+    else:
+        g = inputs.from_edges(70001, np.zeros(70000, np.int32),
+                              np.arange(1, 70001, dtype=np.int32), name="star70k")
+        ells = [7, 8]
+    say(f"[count layout] {name} n={g.n} nnz={g.nnz}")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = 0.9 * oracle.default_alpha(g, None)
+    om = omega_max(g, 20)
+    sizes = [(1, 1), (2, 9), (3, 120)]
+    groups = [inputs.group(g.n, size, seed) for seed, size in sizes]
+    off = np.zeros(len(groups) + 1, dtype=np.int64)
+    for j, S in enumerate(groups):
+        off[j + 1] = off[j] + S.size
+    mem = np.concatenate(groups).astype(np.int32)
+    for ell in ells:
+        B = oracle.comb_bound(g, alpha, ell, None)
+        eps = float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, None)))
+        a = (ell + 1) // 2
+        u32 = all(om[i] < 2.0 ** 32 for i in range(3, a))
+        say(f"  ell={ell} stored levels={a - 3} 32-bit={u32}")
+        ref = []
+        for j, S in enumerate(groups):
+            c, ell_o, _, _ = oracle.score(g, S, alpha, eps)
+            assert ell_o == ell
+            if j == 0:
+                gg.prepare(alpha, eps)  # t-levels outside the profiled call
+                gg.profile_enable(True)
+            s = gg.score(S, alpha, eps)
+            if j == 0:
+                kind = gg.profile_read()["dominant_kind"]
+                gg.profile_enable(False)
+                out = kind % ged.KIND_BASE
+                assert (out in (9, 10)) == u32, (name, ell, kind)
+            assert rel(s, c) <= REL, (name, ell, S.size, s, c)
+            ref.append(c)
+        b = gg.score_batch(off, mem, alpha, eps)
+        for j, c in enumerate(ref):
+            assert rel(b[j], c) <= REL, (name, ell, j, b[j], c)
+    if name == "sparse_er":
+        assert om[(17 + 1) // 2 - 1] < 2.0 ** 32  # the last ell still stores 32-bit levels
+    else:
+        assert om[3] > 2.0 ** 32
+    gg.close()
+
+
 @pytest.mark.parametrize("name", ["ba", "directed", "weighted"])
 def test_spectral_bound(ged, name):
     """sigma_max estimate, ell* and scores / greedy under the spectral tail bound

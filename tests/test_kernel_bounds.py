@@ -5,7 +5,9 @@ arcs and 511 rows, long rows split into segments of 8192/C arcs) and every
 index formula of the step kernel, on CSRs in the library's internal vertex
 order (stable by decreasing out-degree), and asserts that every load and
 store lands inside its buffer -- including the empty trailing row blocks
-that once read one entry past col_idx.  For split scoring it emulates the
+that once read one entry past col_idx -- in both gather layouts: one 8-byte
+value per (arc, column), and 32-bit inputs gathered as 8-byte column pairs
+into blocks of twice the arcs.  For split scoring it emulates the
 worklist that the member pushes fill and checks the capacity bound the host
 allocates (entries past it would be dropped, not faulted, so a wrong bound
 would give wrong results silently).
@@ -19,10 +21,13 @@ K_BLOCK, K_ROWS, K_SEG, K_LDS = 256, 511, 8192, 2048
 WL_CHUNK = 512
 
 
-def partition(rp, C):
+def partition(rp, C, units=None):
+    """Row blocks and long-row segments for C columns gathered in `units`
+    8-byte units per arc (C, or C/2 for column pairs)."""
+    units = units or C
     n = len(rp) - 1
-    nnz_blk = K_LDS // C
-    seg_len = max(1, K_SEG // C)
+    nnz_blk = K_LDS // units
+    seg_len = max(1, K_SEG // units)
     deg = np.diff(rp)
     blocks, segs, lrows = [], [], []
     r = 0
@@ -44,26 +49,36 @@ def partition(rp, C):
     return blocks, segs, lrows
 
 
-def check_step(rp, ci, n, C):
+def check_step(rp, ci, n, C, pairs=False):
+    """pairs: 32-bit input gathered as column pairs (C >= 2): unit q of thread
+    t loads elements u*C + 2k, +1 with k = unit mod C/2, staged as two 32-bit
+    LDS slots; phase 2 reads slot j*C + c."""
     nnz = int(rp[-1])
     ci_alloc = max(1, nnz)
-    blocks, segs, _ = partition(rp, C)
+    U = C // 2 if pairs else C
+    blocks, segs, _ = partition(rp, C, U)
     PT = K_LDS // K_BLOCK
     RT = (K_ROWS + K_BLOCK) // K_BLOCK
     t = np.arange(K_BLOCK)
     mask_words = (n + 31) // 32 + 1
     for (r0, r1, p0, p1) in blocks:
-        nrows, tot = r1 - r0, (p1 - p0) * C
+        nrows, tot = r1 - r0, (p1 - p0) * U
         assert 1 <= nrows <= K_ROWS and 0 <= tot <= K_LDS
         jlo = p0 if tot > 0 else 0
         jmax = p1 - 1 if tot > 0 else 0
         for q in range(PT):  # col_idx loads, gathers, LDS stores
-            j = np.minimum(jlo + (t + q * K_BLOCK) // C, jmax)
+            j = np.minimum(jlo + (t + q * K_BLOCK) // U, jmax)
             assert j.min() >= 0 and j.max() < ci_alloc
             u = ci[j] if tot > 0 else np.zeros_like(j)
             assert u.min() >= 0 and u.max() < n
+            if pairs:
+                e = u * C + 2 * ((t + q * K_BLOCK) & (U - 1))
+                assert e.min() >= 0 and (e + 1).max() < n * C and (e % 2 == 0).all()
             f = t + q * K_BLOCK
-            assert np.where(f < tot, f, K_LDS + t).max() < K_LDS + K_BLOCK
+            slot = np.where(f < tot, f, K_LDS + t)
+            assert slot.max() < K_LDS + K_BLOCK
+        if pairs and tot > 0:  # phase 2 reads 32-bit slot j*C + c of the staged arcs
+            assert (p1 - p0 - 1) * C + C - 1 < 2 * tot
         for k in range(RT):  # row_ptr slice
             assert (r0 + np.minimum(t + k * K_BLOCK, nrows)).max() <= n
         nw = ((r0 + nrows - 1) >> 5) - (r0 >> 5) + 1
@@ -77,15 +92,18 @@ def check_step(rp, ci, n, C):
             tpr >>= 1
         rl0 = (t // tpr) // C
         assert (r0 + np.minimum(rl0, nrows - 1)).max() < n
-        assert (p1 - p0) * C <= K_LDS
-    for (r, y, z) in segs:  # long-row segments, U = 8 clamped loads per lane
-        assert 0 <= y < z <= nnz and z - y <= max(1, K_SEG // C)
-        lpc = K_BLOCK // C
-        j0 = y + t // C
+        assert (p1 - p0) * U <= K_LDS
+    for (r, y, z) in segs:  # long-row segments, 8 clamped loads per lane
+        assert 0 <= y < z <= nnz and z - y <= max(1, K_SEG // U)
+        lpc = K_BLOCK // U
+        j0 = y + t // U
         while j0.min() < z:
             for q in range(8):
                 jj = np.minimum(j0 + q * lpc, z - 1)
                 assert jj.min() >= y and jj.max() < nnz
+                if pairs:
+                    e = ci[jj].astype(np.int64) * C + 2 * (t & (U - 1))
+                    assert (e + 1).max() < n * C
             j0 = j0 + 8 * lpc
 
 
@@ -126,6 +144,8 @@ def test_step_indices_in_bounds(g):
                    internal_csr(g)):
         for C in (1, 2, 4, 8, 16, 32, 64):
             check_step(rp, ci, g.n, C)
+            if C >= 2:
+                check_step(rp, ci, g.n, C, pairs=True)
 
 
 def wl_need(n, nnz, deg_sum):

@@ -6,7 +6,9 @@
 * the push formulation of the level-1/2 counts against enumeration;
 * the whole split scheme (tests/split_model.py) against the oracle for every
   plan shape (a = 1, 2, 3+, odd and even ell, weighted);
-* the same split for marginal gains (walks that avoid S and contain x).
+* the same split for marginal gains (walks that avoid S and contain x);
+* the bound count_i <= omega_i that lets the dense levels be stored as 32-bit
+  integers, and split scoring with integer levels against the oracle.
 """
 import numpy as np
 import pytest
@@ -14,7 +16,8 @@ import pytest
 import oracle
 from exact import WalkTable
 from paper_1910_13874_amd import inputs
-from split_model import push_counts, split_gain, split_score
+from split_model import (count_levels, push_counts, split_gain, split_score,
+                         split_score_counts)
 
 
 def tiny_graph(n, m, seed):
@@ -147,3 +150,42 @@ def test_split_gain_model_matches_oracle(weighted):
             o = oracle.gain(g, S, x, alpha, ell, w=w)
             m = split_gain(g.row_ptr, g.col_idx, S, x, alpha, ell, w)
             assert abs(m - o) <= 1e-12 * abs(o), (weighted, ell, len(S), x, m, o)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_count_levels_bounded_by_omega(seed):
+    """count_i(v) <= omega_i(v) for every level, vertex and group: a level
+    whose omega maximum is below 2^32 fits 32 bits for any group.  Also checks
+    count_i against exact enumeration of the walks that meet S."""
+    g = tiny_graph(9, 16, seed)
+    tab = WalkTable(g.n, g.row_ptr, g.col_idx, 5)
+    rng = np.random.default_rng(seed)
+    for size in (1, 2, 4, g.n):
+        S = np.sort(rng.choice(g.n, size, replace=False))
+        cnt, om = count_levels(g.row_ptr, g.col_idx, S, 5)
+        for i in range(1, 6):
+            for v in range(g.n):
+                assert cnt[i][v] <= om[i][v]
+                assert cnt[i][v] == hit_end(tab, i, S, v), (i, v)
+                assert om[i][v] == all_end(tab, i, v)
+
+
+@pytest.mark.parametrize("name", ["er", "ba", "star"])
+def test_split_count_model_matches_oracle(name):
+    """Split scoring with unscaled integer dense levels (alpha^i applied in the
+    combination) equals the oracle's score, for ell with 1..5 stored levels."""
+    if name == "er":
+        g = inputs.erdos_renyi(200, 600, 43)
+    elif name == "ba":
+        g = inputs.barabasi_albert(200, 3, 44)
+    else:
+        g = inputs.from_edges(60, np.zeros(59, np.int32), np.arange(1, 60, dtype=np.int32))
+    alpha = 0.9 * oracle.default_alpha(g, None)
+    for ell in range(7, 15):
+        eps = eps_for(g, alpha, ell, None)
+        for seed, size in [(1, 1), (2, 5), (3, 40)]:
+            S = inputs.group(g.n, size, seed)
+            c, ell_o, _, _ = oracle.score(g, S, alpha, eps)
+            assert ell_o == ell
+            m = split_score_counts(g.row_ptr, g.col_idx, S, alpha, ell)
+            assert abs(m - c) <= 1e-12 * abs(c), (name, ell, size, m, c)
