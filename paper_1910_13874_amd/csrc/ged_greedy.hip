@@ -54,6 +54,26 @@ __global__ void k_mask_bit(uint32_t *mask, int v, int value) {
   }
 }
 
+// A vertex u joined S: one more arc from S into each v in N(u) (undirected,
+// so the row of u lists them; repeated arcs count each time).
+__global__ void k_sdeg_add(const int *__restrict__ rp, const int *__restrict__ ci, int u,
+                           int *sdeg) {
+  for (int k = rp[u] + blockIdx.x * blockDim.x + threadIdx.x; k < rp[u + 1];
+       k += gridDim.x * blockDim.x)
+    atomicAdd(&sdeg[ci[k]], 1);
+}
+
+// Miss level 1 (unweighted, undirected): m_1(v) = alpha * (deg(v) - arcs from
+// S into v) outside S, 0 on S -- the same integer times alpha as the dense
+// step from the complement mask computes, at O(n).
+__global__ void k_miss1(const int *__restrict__ rp, const int *__restrict__ sdeg,
+                        const uint32_t *__restrict__ smask, double alpha, int n, double *m1) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const bool inS = (smask[v >> 5] >> (v & 31)) & 1u;
+    m1[v] = inS ? 0.0 : alpha * (double)(rp[v + 1] - rp[v] - sdeg[v]);
+  }
+}
+
 // I(x) = b_0 * sum_{a=1}^{ell} m_a + sum_{c=1}^{ell} b_c * sum_{a=0}^{ell-c} m_a with
 // m_0 = b_0 = 1 for x outside S: every term of Lemma "initialize" once, no
 // subtraction.  ub[x] = -1 marks members of S.
@@ -229,6 +249,27 @@ __global__ void k_sum_range(const double *__restrict__ M, int n, int r, double *
   }
 }
 
+// Level 1 of the gain chains of a candidate batch (undirected graph, no arc
+// listed twice, unweighted): d_1(v, c) = alpha for each v in N(x_c) outside S
+// and v != x_c (one walk x_c -> v), m_1(x_c) at the candidate, 0 elsewhere --
+// what a dense step from the one-hot columns would write, at O(deg(x_c)).
+// The buffer is zero between batches; clear = 1 stores the zeros back.
+__global__ __launch_bounds__(kBlock) void k_gain_level1(const int *__restrict__ rp,
+                                                        const int *__restrict__ ci,
+                                                        const uint32_t *__restrict__ smask,
+                                                        const int *cand, int C, double alpha,
+                                                        const double *__restrict__ m1, double *d1,
+                                                        int clear) {
+  const int c = blockIdx.y;
+  const int x = cand[c];
+  const int k1 = rp[x + 1];
+  for (int k = rp[x] + blockIdx.x * kBlock + (int)threadIdx.x; k < k1; k += gridDim.x * kBlock) {
+    const int v = ci[k];
+    if (v != x && !((smask[v >> 5] >> (v & 31)) & 1u)) d1[(size_t)v * C + c] = clear ? 0.0 : alpha;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) d1[(size_t)x * C + c] = clear ? 0.0 : m1[x];
+}
+
 struct GreedyCtx {
   ged_graph *g;
   hipStream_t st;
@@ -237,7 +278,9 @@ struct GreedyCtx {
   int Lcap = 0;
   bool split = false;  // undirected: chains to ceil(ell/2) (walk split)
   DBuf smask, m_levels, b_levels, ub, stale, done, cand_col, sampled;
+  DBuf sdeg;            // split, unweighted: int32 [n] arcs from S into each vertex
   DBuf dlv, Mr;        // split: stored gain levels [(a-1)*n*C], sum of miss levels [n]
+  void *d1_zeroed = nullptr;  // dlv allocation whose level 1 is known to be all zero
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
   StepWs ws1, ws1r, wsC;
@@ -282,7 +325,15 @@ static void miss_chains(GreedyCtx &c, int ell) {
     StepWs &ws = rev ? c.ws1r : c.ws1;
     ws.fit(p);
     double *L = (rev ? c.b_levels : c.m_levels).as<double>();
-    for (int i = 1; i <= ell; ++i) {
+    int i0 = 1;
+    if (c.split && !g->weighted) {  // level 1 from the S-arc counts
+      hipLaunchKernelGGL(k_miss1, dim3(std::min(8192, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                         c.st, g->rp.as<const int>(), c.sdeg.as<const int>(),
+                         c.smask.as<const uint32_t>(), g->prep.alpha, n, L + (size_t)n);
+      GED_HIP(hipGetLastError());
+      i0 = 2;
+    }
+    for (int i = i0; i <= ell; ++i) {
       StepArgs a = base_args(g, rev);
       ws.into(a);
       a.C = 1;
@@ -382,8 +433,21 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
     if (la > 1) c.dlv.ensure(sizeof(double) * nC * (size_t)(la - 1));
     double *dl = c.dlv.as<double>();
     const double *any = c.Mr.as<const double>();
+    // level 1 by a push from the candidates when each neighbour is one walk
+    const bool push1 = la > 1 && g->simple && !g->weighted;
+    int gx = 1;
+    if (push1) {
+      if (c.d1_zeroed != c.dlv.p) launch_fill_f64(dl, 0.0, nC, c.st);
+      c.d1_zeroed = nullptr;  // dirty until the clear below has been enqueued
+      int dmax = 0;
+      for (int q = 0; q < nc; ++q) dmax = std::max(dmax, g->h_rp[cand[q] + 1] - g->h_rp[cand[q]]);
+      gx = std::max(1, std::min(64, (dmax + kBlock - 1) / kBlock));
+      hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci, a.smask,
+                         c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 0);
+      GED_HIP(hipGetLastError());
+    }
     a.accum = 0;
-    for (int i = 1; i <= la; ++i) {
+    for (int i = push1 ? 2 : 1; i <= la; ++i) {
       a.X = i == 1 ? nullptr : dl + (size_t)(i - 2) * nC;
       a.inj = M + (size_t)i * n;
       if (i < la) {
@@ -403,6 +467,12 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
         a.q_even = r == la ? 1 : 0;
         run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAINCOMB, c.st, la - 1);
       }
+    }
+    if (push1) {
+      hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci, a.smask,
+                         c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 1);
+      GED_HIP(hipGetLastError());
+      c.d1_zeroed = c.dlv.p;
     }
   } else {
     for (int i = 1; i <= ell; ++i) {
@@ -488,6 +558,21 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.topk_i[1].ensure(sizeof(int) * (size_t)nb0 * K);
   c.h_small.ensure(4096);
   launch_fill_i32(c.smask.as<int>(), 0, c.smask.bytes / sizeof(int), c.st);
+  const bool track_sdeg = c.split && !g->weighted;
+  if (track_sdeg) {
+    c.sdeg.ensure(sizeof(int) * (size_t)n);
+    launch_fill_i32(c.sdeg.as<int>(), 0, (size_t)n, c.st);
+  }
+  auto join = [&](int u) {
+    hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
+    if (track_sdeg) {
+      const int d = g->h_rp[u + 1] - g->h_rp[u];
+      hipLaunchKernelGGL(k_sdeg_add, dim3(std::max(1, std::min(256, (d + kBlock - 1) / kBlock))),
+                         dim3(kBlock), 0, c.st, g->rp.as<const int>(), g->ci.as<const int>(), u,
+                         c.sdeg.as<int>());
+    }
+    GED_HIP(hipGetLastError());
+  };
   launch_fill_i32(c.done.as<int>(), -1, (size_t)n, c.st);
   launch_fill_i32(c.cand_col.as<int>(), -1, (size_t)n, c.st);
   std::vector<int> sample_host;
@@ -515,7 +600,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
       if (tr->B) tr->B[s_size] = NAN;
       if (tr->evals) tr->evals[s_size] = 0;
       s_size++;
-      hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
+      join(u);
     }
     ell = tr->forced_ell >= 1 ? tr->forced_ell : 1;
   }
@@ -588,7 +673,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
         if (tr->evals) tr->evals[s_size] = c.evals;
       }
       s_size++;
-      hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
+      join(u);
       need_chain = true;
     }
     if (s_size < k) ell *= 2;

@@ -105,13 +105,22 @@ struct CombineIn {
   CT c1 = 0, c2 = 0;
   LT lv0 = 0;
   double trv = 0.0, ta = 0.0;
+  // Wide tiles stream these rows once: nontemporal loads keep them from
+  // displacing the gathered vector in the caches.
   __device__ __forceinline__ void load(const StepArgs &a, int v, int c) {
     const uint64_t o = (uint64_t)v * C + c;
-    c1 = static_cast<const CT *>(a.q_cnt1)[o & a.q_m1];
-    c2 = static_cast<const CT *>(a.q_cnt2)[o & a.q_m2];
-    lv0 = static_cast<const LT *>(a.q_lv)[o & a.q_mlv];
+    c1 = ld(static_cast<const CT *>(a.q_cnt1) + (o & a.q_m1));
+    c2 = ld(static_cast<const CT *>(a.q_cnt2) + (o & a.q_m2));
+    lv0 = ld(static_cast<const LT *>(a.q_lv) + (o & a.q_mlv));
     trv = a.tr[v];
     ta = a.inj[v];
+  }
+  template <class T>
+  static __device__ __forceinline__ T ld(const T *p) {
+    if constexpr (C >= 8)
+      return __builtin_nontemporal_load(p);
+    else
+      return *p;
   }
   // sum_{i<a} h_i(v) for column c (levels beyond the first stored one are
   // loaded here; there are none unless ell* > 8)
@@ -346,10 +355,19 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         } else {
           const double y = epilogue_v<C, OUT>(a, r, c, acc, inS, TM ? tmw[rl] : 0ull,
                                               CA ? cw[rl] : -1);
-          if constexpr (OUT == OUT_TILE32)
-            a.Y32[(size_t)r * C + c] = (uint32_t)y;
-          else
-            a.Y[(size_t)r * C + c] = y;
+          // wide tiles: the output is not read again before the next
+          // launch, which gathers it from beyond the L2 anyway
+          if constexpr (OUT == OUT_TILE32) {
+            if constexpr (C >= 8)
+              __builtin_nontemporal_store((uint32_t)y, a.Y32 + (size_t)r * C + c);
+            else
+              a.Y32[(size_t)r * C + c] = (uint32_t)y;
+          } else {
+            if constexpr (C >= 8)
+              __builtin_nontemporal_store(y, a.Y + (size_t)r * C + c);
+            else
+              a.Y[(size_t)r * C + c] = y;
+          }
           colsum += y;
         }
       }

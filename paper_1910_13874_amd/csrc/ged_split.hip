@@ -173,14 +173,18 @@ __global__ void k_fix_members(const int *__restrict__ rp,
   }
 }
 
-// Zero every count entry k_push / k_fix_members wrote for these members.
+// Zero every count entry k_push / k_fix_members wrote for these members, and
+// the members' column bits in tmask; reset the worklist length (the worklist
+// replay that reads it has finished).
 template <class CT>
 __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict__ rp,
                                                           const int *__restrict__ ci,
                                                           const int64_t *offsets,
                                                           const int *members, const int *mcol,
                                                           int g0, int nc, int C, CT *cnt1,
-                                                          CT *cnt2) {
+                                                          CT *cnt2, unsigned long long *tmask,
+                                                          unsigned *wl_n) {
+  if (wl_n && blockIdx.x == 0 && threadIdx.x == 0) *wl_n = 0;
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
     const int s = members[j];
@@ -188,6 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict_
     if (threadIdx.x == 0) {
       cnt1[(size_t)s * C + c] = 0;
       if (cnt2) cnt2[(size_t)s * C + c] = 0;
+      atomicAnd(&tmask[s], ~(1ull << c));
     }
     for (int k = rp[s] + (int)threadIdx.x; k < rp[s + 1]; k += kBlock) {
       const size_t o = (size_t)ci[k] * C + c;
@@ -402,7 +407,7 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
 template <class CT>
 static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
-                        int mgrid, hipStream_t st) {
+                        int mgrid, uint64_t *tmask, hipStream_t st) {
   const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
   CT *c1 = w.cnt1.as<CT>();
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
@@ -412,9 +417,9 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_clear_members<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem,
-                     mcol, g0, nc, C, c1, c2);
+                     mcol, g0, nc, C, c1, c2, reinterpret_cast<unsigned long long *>(tmask),
+                     c2 ? w.wl_n.as<unsigned>() : nullptr);
   GED_HIP(hipGetLastError());
-  if (c2) launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
 }
 
 void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uint64_t *tmask,
@@ -551,13 +556,14 @@ void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, cons
                       const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
                       uint64_t *tmask, hipStream_t st) {
   const int mgrid = grid_for(tile_members, kPushGrid);
-  if (pl.s >= 1) {
+  if (pl.s >= 1) {  // clears the members' tmask bits too
     if (pl.c32)
-      clear_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, st);
+      clear_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tmask, st);
     else
-      clear_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, st);
+      clear_phase<unsigned long long>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tmask, st);
+  } else {
+    launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
   }
-  launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
 }
 
 void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, double *out,
