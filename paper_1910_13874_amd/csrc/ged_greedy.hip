@@ -658,6 +658,10 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
         eval_batch(c, internal.data(), nc, ell, round, gains.data());
         for (int q = 0; q < nc; ++q) top.add(gains[q], hi[q]);
         if (m <= c.C) break;  // nothing else eligible
+        // the (C+1)-th bound is the best among the candidates not evaluated
+        // (their bounds do not change within a round): the next selection
+        // would stop on it
+        if (top.v >= 0 && hk[c.C] < top.L2) break;
       }
       if (top.u < 0) return fail(GED_ERR_ARG, "no candidate left");
       if (top.v >= 0 && top.L1 <= (top.L2 + B) - eps / (double)k) break;  // not separated
