@@ -270,6 +270,42 @@ __global__ __launch_bounds__(kBlock) void k_gain_level1(const int *__restrict__ 
   if (blockIdx.x == 0 && threadIdx.x == 0) d1[(size_t)x * C + c] = clear ? 0.0 : m1[x];
 }
 
+// The same level as unscaled 32-bit counts: 1 on N(x_c) outside S, and at the
+// candidate the number of its arcs from outside S, deg(x_c) - sdeg(x_c).
+__global__ __launch_bounds__(kBlock) void k_gain_level1_32(const int *__restrict__ rp,
+                                                           const int *__restrict__ ci,
+                                                           const uint32_t *__restrict__ smask,
+                                                           const int *cand, int C,
+                                                           const int *__restrict__ sdeg,
+                                                           uint32_t *d1, int clear) {
+  const int c = blockIdx.y;
+  const int x = cand[c];
+  const int k0 = rp[x], k1 = rp[x + 1];
+  for (int k = k0 + blockIdx.x * kBlock + (int)threadIdx.x; k < k1; k += gridDim.x * kBlock) {
+    const int v = ci[k];
+    if (v != x && !((smask[v >> 5] >> (v & 31)) & 1u)) d1[(size_t)v * C + c] = clear ? 0u : 1u;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    d1[(size_t)x * C + c] = clear ? 0u : (uint32_t)(k1 - k0 - sdeg[x]);
+}
+
+// Unscaled miss counts of the candidates, injc[i*C + c] = m_i(x_c) / alpha^i
+// rounded to the nearest integer, for 2 <= i <= top.  Exact when the count is
+// below 2^32 and i*(deg_max + 3) < 2^19: every miss level is a sum of
+// nonnegative terms, so its relative error is at most about
+// i*(deg_max + 2)*2^-53, under 1/4 of a unit at 2^32.
+__global__ void k_gain_inj(const double *__restrict__ M, int n, const int *cand, int nc, int C,
+                           double alpha, int top, double *injc) {
+  const int c = threadIdx.x;
+  if (c >= nc) return;
+  const int x = cand[c];
+  double ap = alpha;
+  for (int i = 2; i <= top; ++i) {
+    ap *= alpha;
+    injc[i * C + c] = rint(M[(size_t)i * n + x] / ap);
+  }
+}
+
 struct GreedyCtx {
   ged_graph *g;
   hipStream_t st;
@@ -281,6 +317,10 @@ struct GreedyCtx {
   DBuf sdeg;            // split, unweighted: int32 [n] arcs from S into each vertex
   DBuf dlv, Mr;        // split: stored gain levels [(a-1)*n*C], sum of miss levels [n]
   void *d1_zeroed = nullptr;  // dlv allocation whose level 1 is known to be all zero
+  int d1_bytes = 0;           // ... in this element size (8 = FP64 levels, 4 = 32-bit)
+  DBuf injc;                  // [(a)*C] candidate injections of the 32-bit gain levels
+  int g32_ell = -1;           // walk length g32_ok was decided for
+  bool g32_ok = false;        // gain levels as 32-bit counts at g32_ell
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
   StepWs ws1, ws1r, wsC;
@@ -408,6 +448,23 @@ static int select_topk(GreedyCtx &c, int K, int round, const int *sampled, int p
   return m;
 }
 
+// Gain levels as unscaled 32-bit counts at walk length ell (undirected,
+// unweighted, no repeated arcs): d_i(v) / alpha^i counts walks that avoid S
+// and contain x, at most omega_i(v), so levels 1 .. ceil(ell/2)-1 fit when
+// max omega_i < 2^32; the candidates' injected miss counts are recovered
+// exactly by rounding when i*(deg_max + 3) < 2^19 (k_gain_inj).
+static bool gains32(GreedyCtx &c, int ell) {
+  if (c.g32_ell == ell) return c.g32_ok;
+  ged_graph *g = c.g;
+  const int top = (ell + 1) / 2 - 1;
+  bool ok = c.split && g->simple && !g->weighted && top >= 1 &&
+            (int64_t)top * ((int64_t)g->max_deg + 3) + 2 < (int64_t(1) << 19);
+  if (ok) ok = omega_fit_level(g, top, c.st) >= top;
+  c.g32_ell = ell;
+  c.g32_ok = ok;
+  return ok;
+}
+
 // Exact L_ell(S, x) for up to C candidates (one SpMM column each).
 static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round, double *out) {
   ged_graph *g = c.g;
@@ -426,53 +483,109 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
   a.alpha = g->prep.alpha;
   a.smask = c.smask.as<const uint32_t>();
   a.cand_col = c.cand_col.as<const int>();
+  Partition *pr = &p;  // partition of the last step (its partials are reduced)
   if (c.split) {
     // gain levels 1..a-1 stored, level a combined (walk split)
     const int la = (ell + 1) / 2, r = ell - la;
     const size_t nC = (size_t)n * C;
-    if (la > 1) c.dlv.ensure(sizeof(double) * nC * (size_t)(la - 1));
+    const bool g32 = la > 1 && gains32(c, ell);
+    const int eb = g32 ? 4 : 8;  // bytes per stored value
+    if (la > 1) c.dlv.ensure((size_t)eb * nC * (size_t)(la - 1));
     double *dl = c.dlv.as<double>();
+    uint32_t *dl32 = c.dlv.as<uint32_t>();
     const double *any = c.Mr.as<const double>();
     // level 1 by a push from the candidates when each neighbour is one walk
     const bool push1 = la > 1 && g->simple && !g->weighted;
     int gx = 1;
     if (push1) {
-      if (c.d1_zeroed != c.dlv.p) launch_fill_f64(dl, 0.0, nC, c.st);
+      if (c.d1_zeroed != c.dlv.p || c.d1_bytes != eb)
+        launch_fill_i32(c.dlv.as<int>(), 0, nC * eb / sizeof(int), c.st);
       c.d1_zeroed = nullptr;  // dirty until the clear below has been enqueued
       int dmax = 0;
       for (int q = 0; q < nc; ++q) dmax = std::max(dmax, g->h_rp[cand[q] + 1] - g->h_rp[cand[q]]);
       gx = std::max(1, std::min(64, (dmax + kBlock - 1) / kBlock));
-      hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci, a.smask,
-                         c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 0);
+      if (g32)
+        hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dl32,
+                           0);
+      else
+        hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 0);
       GED_HIP(hipGetLastError());
     }
     a.accum = 0;
-    for (int i = push1 ? 2 : 1; i <= la; ++i) {
-      a.X = i == 1 ? nullptr : dl + (size_t)(i - 2) * nC;
-      a.inj = M + (size_t)i * n;
-      if (i < la) {
-        a.Y = dl + (size_t)(i - 1) * nC;
-        run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
-      } else {
-        a.Y = nullptr;
-        a.tr = c.Mr.as<const double>();
-        a.q_cnt1 = any;
-        a.q_cnt2 = any;
-        a.q_m1 = a.q_m2 = 0;
-        a.q_s1 = a.q_s2 = 0.0;
-        a.q_lv = la > 1 ? dl : any;
-        a.q_mlv = la > 1 ? ~0ull : 0ull;
-        a.q_slv = la > 1 ? 1.0 : 0.0;
-        a.q_nlv = la - 1;
-        a.q_even = r == la ? 1 : 0;
-        run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAINCOMB, c.st, la - 1);
+    if (g32) {
+      Partition &pn = partition_narrow(g, C);
+      c.wsC.fit(pn);
+      c.wsC.into(a);
+      pr = &pn;
+      c.injc.ensure(sizeof(double) * (size_t)(la + 1) * C);
+      if (la > 2)
+        hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
+                           c.cand_dev.as<const int>(), nc, C, g->prep.alpha, la - 1,
+                           c.injc.as<double>());
+      double alpha_a = g->prep.alpha;
+      for (int i = 1; i < la; ++i) alpha_a *= g->prep.alpha;
+      for (int i = 2; i <= la; ++i) {
+        a.Xc32 = dl32 + (size_t)(i - 2) * nC;
+        if (i < la) {
+          a.alpha = 1.0;
+          a.injc = c.injc.as<const double>() + (size_t)i * C;
+          a.Y32 = dl32 + (size_t)(i - 1) * nC;
+          run_step(g, pn, a, IN_CNT32, OUT_GAIN32, c.st);
+        } else {
+          a.alpha = alpha_a;
+          a.inj = M + (size_t)i * n;
+          a.Y = nullptr;
+          a.Y32 = nullptr;
+          a.tr = c.Mr.as<const double>();
+          a.q_cnt1 = any;
+          a.q_cnt2 = any;
+          a.q_m1 = a.q_m2 = 0;
+          a.q_s1 = a.q_s2 = 0.0;
+          a.q_lv = dl32;
+          a.q_mlv = ~0ull;
+          a.q_slv = g->prep.alpha;
+          a.q_alpha = g->prep.alpha;
+          a.q_nlv = la - 1;
+          a.q_even = r == la ? 1 : 0;
+          run_step(g, pn, a, IN_CNT32, OUT_GAINCOMB32L, c.st, 0.5 * (la - 1));
+        }
+      }
+    } else {
+      for (int i = push1 ? 2 : 1; i <= la; ++i) {
+        a.X = i == 1 ? nullptr : dl + (size_t)(i - 2) * nC;
+        a.inj = M + (size_t)i * n;
+        if (i < la) {
+          a.Y = dl + (size_t)(i - 1) * nC;
+          run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
+        } else {
+          a.Y = nullptr;
+          a.tr = c.Mr.as<const double>();
+          a.q_cnt1 = any;
+          a.q_cnt2 = any;
+          a.q_m1 = a.q_m2 = 0;
+          a.q_s1 = a.q_s2 = 0.0;
+          a.q_lv = la > 1 ? dl : any;
+          a.q_mlv = la > 1 ? ~0ull : 0ull;
+          a.q_slv = la > 1 ? 1.0 : 0.0;
+          a.q_nlv = la - 1;
+          a.q_even = r == la ? 1 : 0;
+          run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAINCOMB, c.st, la - 1);
+        }
       }
     }
     if (push1) {
-      hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci, a.smask,
-                         c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 1);
+      if (g32)
+        hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dl32,
+                           1);
+      else
+        hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 1);
       GED_HIP(hipGetLastError());
       c.d1_zeroed = c.dlv.p;
+      c.d1_bytes = eb;
     }
   } else {
     for (int i = 1; i <= ell; ++i) {
@@ -483,7 +596,7 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
     }
   }
-  launch_reduce(p, a, c.gains.as<double>(), nullptr, nullptr, c.st, c.wsC.scratch());
+  launch_reduce(*pr, a, c.gains.as<double>(), nullptr, nullptr, c.st, c.wsC.scratch());
   hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
                      c.cand_dev.as<const int>(), nc, 0);
   hipLaunchKernelGGL(k_after_batch, dim3(1), dim3(64), 0, c.st, c.cand_dev.as<const int>(),

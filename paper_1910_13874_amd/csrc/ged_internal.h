@@ -151,7 +151,10 @@ enum OutMode : int {
                      // combination of a gain chain (undirected greedy)
   OUT_TILE32 = 9,    // y as OUT_TILE, stored to Y32 as an exact 32-bit integer
                      // (unscaled walk counts: alpha = 1, inj = integer omega level)
-  OUT_COMBINE32L = 10  // OUT_COMBINE32 whose stored levels are 32-bit counts too
+  OUT_COMBINE32L = 10, // OUT_COMBINE32 whose stored levels are 32-bit counts too
+  OUT_GAIN32 = 11,     // y as OUT_GAIN (inj at the candidate from injc[c]), stored to Y32
+                       // as an exact 32-bit integer (unscaled gain-chain counts)
+  OUT_GAINCOMB32L = 12 // OUT_GAINCOMB whose stored levels are 32-bit counts
 };
 // Profile records and kernel names encode a (gather, epilogue) pair as
 // in * kKindBase + out.
@@ -172,6 +175,7 @@ struct StepArgs {
   const double *inj = nullptr;      // injection vector [n] (or level array for OUT_POOL)
   const int *col_step = nullptr;    // [C] per-column level (OUT_POOL), 0 = idle
   const int *fresh = nullptr;       // [C] first-step flags (IN_FRESH)
+  const double *injc = nullptr;     // [C] value at column c's candidate (OUT_GAIN32)
   double alpha = 0;
   int accum = 0;                 // 1: add this step's column sums to blk_part/long_part
   double *blk_part = nullptr;    // [n_blocks*C] block column sums
@@ -365,6 +369,8 @@ struct ged_graph {
   ged::DBuf omega_lv;
   int omega_top = 2, omega_fit = 2;
   std::list<ged::DBuf> omega_old;  // replaced omega_lv buffers, freed with the graph
+  // maxima known for levels 3 .. omax_top; omax_fit as omega_fit for them
+  int omax_top = 2, omax_fit = 2;
   std::vector<uint32_t> stamp;  // host group-dedup stamps
   uint32_t stamp_gen = 0;
   ged::SplitWs split_ws;        // single-group scoring workspace
@@ -424,6 +430,10 @@ SplitPlan split_plan(const ged_graph *g, int ell);
 // The first call that needs new omega levels synchronizes the stream once to
 // read their maxima.
 void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st);
+// Largest i <= L such that max_v omega_j(v) < 2^32 for 3 <= j <= i (L itself
+// for L <= 2).  Computes the maxima by the integer chain the first time a
+// level is asked for (synchronizes the stream once); stores no levels.
+int omega_fit_level(ged_graph *g, int L, hipStream_t st);
 // Size a workspace for C columns and a worklist of wl_need entries; zero the
 // count arrays if they are new or dirty.
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,

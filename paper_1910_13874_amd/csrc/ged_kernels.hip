@@ -75,8 +75,10 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                        OUT == OUT_TILE32 || OUT == OUT_COMBINE32L) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
-  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB) {
+  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
+  } else if constexpr (OUT == OUT_GAIN32) {
+    return inS ? 0.0 : (cand == c ? a.injc[c] : y);
   } else {  // OUT_POOL
     const int s = a.col_step[c];
     if (s <= 0) return 0.0;
@@ -163,7 +165,18 @@ struct CombineIn {
 
 template <int C, int OUT>
 using CombineFor = CombineIn<C, OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L,
-                             OUT == OUT_COMBINE32L>;
+                             OUT == OUT_COMBINE32L || OUT == OUT_GAINCOMB32L>;
+
+// Output modes by property.
+template <int OUT>
+struct OutTraits {
+  static constexpr bool gain = OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAIN32 ||
+                               OUT == OUT_GAINCOMB32L;  // S bits and candidate columns
+  static constexpr bool gaincomb = OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L;
+  static constexpr bool combine = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
+                                  OUT == OUT_COMBINE32L || gaincomb;  // y not stored
+  static constexpr bool store32 = OUT == OUT_TILE32 || OUT == OUT_GAIN32;
+};
 
 // y is h_a(v) (t_a(v) for v in S), q = sum_{i<a} h_i(v), trv = sum_{c<=r} t_c(v),
 // ta = t_a(v).
@@ -176,10 +189,10 @@ __device__ __forceinline__ double combine_fin(const StepArgs &a, double q, doubl
 
 template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
-  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OutTraits<OUT>::gain;
   constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
                       OUT == OUT_COMBINE32 || OUT == OUT_TILE32 || OUT == OUT_COMBINE32L;
-  constexpr bool CA = OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
+  constexpr bool CA = OutTraits<OUT>::gain;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
                             TM ? a.tmask[v] : 0ull, CA ? a.cand_col[v] : -1);
 }
@@ -227,12 +240,11 @@ __device__ __forceinline__ void block_colsum_pairs(double v0, double v1, double 
 template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
-  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
-  constexpr bool CB = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L ||
-                       OUT == OUT_GAINCOMB;
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OutTraits<OUT>::gain;
+  constexpr bool CB = OutTraits<OUT>::combine;
   constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
                       OUT == OUT_COMBINE32 || OUT == OUT_TILE32 || OUT == OUT_COMBINE32L;
-  constexpr bool CA = OUT == OUT_GAIN || OUT == OUT_GAINCOMB;
+  constexpr bool CA = OutTraits<OUT>::gain;
   // NP: 32-bit input gathered as column pairs; a gather unit is 8 bytes
   // either way (one FP64 value or two 32-bit values), CU units per arc
   constexpr bool NP = narrow_gather(C, IN, WGT);
@@ -344,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
           if (rl != rl0) in.load(a, r, c);
           double y;
           bool member = false;
-          if constexpr (OUT == OUT_GAINCOMB) {
+          if constexpr (OutTraits<OUT>::gaincomb) {
             // gain chains: 0 on S (where m_a = 0 too), m_a(x) at the candidate
             y = inS ? 0.0 : (cw[rl] == c ? in.ta : a.alpha * acc);
           } else {
@@ -357,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
                                               CA ? cw[rl] : -1);
           // wide tiles: the output is not read again before the next
           // launch, which gathers it from beyond the L2 anyway
-          if constexpr (OUT == OUT_TILE32) {
+          if constexpr (OutTraits<OUT>::store32) {
             if constexpr (C >= 8)
               __builtin_nontemporal_store((uint32_t)y, a.Y32 + (size_t)r * C + c);
             else
@@ -442,13 +454,12 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   double y = epilogue<C, OUT>(a, r, c, acc);
-  if constexpr (OUT == OUT_COMBINE || OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L ||
-                OUT == OUT_GAINCOMB) {
+  if constexpr (OutTraits<OUT>::combine) {
     CombineFor<C, OUT> in;
     in.load(a, r, c);
-    const bool member = OUT == OUT_GAINCOMB ? false : ((a.tmask[r] >> c) & 1ull);
+    const bool member = OutTraits<OUT>::gaincomb ? false : ((a.tmask[r] >> c) & 1ull);
     y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, member);
-  } else if constexpr (OUT == OUT_TILE32) {
+  } else if constexpr (OutTraits<OUT>::store32) {
     a.Y32[(size_t)r * C + c] = (uint32_t)y;
   } else {
     a.Y[(size_t)r * C + c] = y;
@@ -547,6 +558,10 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
   if constexpr (C == 8) {  // the greedy's candidate batches
     GED_CASE(IN_ONEHOT, OUT_GAINCOMB)
     GED_CASE(IN_VEC, OUT_GAINCOMB)
+    if constexpr (!WGT) {
+      GED_CASE(IN_CNT32, OUT_GAIN32)
+      GED_CASE(IN_CNT32, OUT_GAINCOMB32L)
+    }
   }
   if constexpr (C == 1) {
     GED_CASE(IN_ONES, OUT_PLAIN)

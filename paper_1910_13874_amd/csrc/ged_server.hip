@@ -133,6 +133,7 @@ static void lane_setup(Lane &L, int C) {
   partition(g, 1);
   partition(g, 8);
   if (g->flags == GED_DIRECTED) partition(g, 1, true);
+  if (split_ok(g)) partition_narrow(g, 8);  // 32-bit gain levels
   if (split_ok(g)) {
     L.split = true;
     L.pl = split_plan(g, g->prep.ell);

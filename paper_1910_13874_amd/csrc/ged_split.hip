@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_omega_next(const int *__restrict__ r
     for (int o = 32; o > 0; o >>= 1) s = sat_add(s, __shfl_xor(s, o, 64));
     if (lane == 0) {
       out[v] = s;
-      out_d[v] = (double)s;
+      if (out_d) out_d[v] = (double)s;
       m = s > m ? s : m;
     }
   }
@@ -266,15 +266,30 @@ static int grid_for(int64_t items, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
 }
 
-// omega_3 .. omega_top as doubles (levels past the first one whose maximum
-// reaches 2^32 are not computed).  Built in fresh buffers and published after
-// the stream has finished them; a replaced buffer is kept until the graph is
-// destroyed, since captured work may still name it.
-static void omega_levels(ged_graph *g, int top, hipStream_t st) {
+// Per-graph omega tables are built under this lock (greedy workers and lanes
+// of a server may ask for them from several threads).
+static std::mutex g_omega_mu;
+
+static void ensure_omega2(ged_graph *g, hipStream_t st) {
+  if (g->omega2_ready) return;
+  const int64_t n = g->n;
+  g->omega2.ensure(sizeof(uint64_t) * (size_t)n);
+  const int og = (int)std::max<int64_t>(
+      1, std::min<int64_t>(16384, (n + kBlock / 64 - 1) / (kBlock / 64)));
+  hipLaunchKernelGGL(k_omega2, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
+                     g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>());
+  GED_HIP(hipGetLastError());
+  g->omega2_ready = true;
+}
+
+// The integer chain omega_3 .. omega_top from omega_2, written as doubles to
+// out[(i-3)*n ..] if out is non-null.  Returns the largest i <= top such that
+// max_v omega_j(v) < 2^32 for 3 <= j <= i (2 if omega_3 does not fit).
+// Synchronizes the stream.
+static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st) {
   const int64_t n = g->n;
   const int L = top - 2;
-  DBuf lv, tmp, mx;
-  lv.ensure(sizeof(double) * (size_t)n * L);
+  DBuf tmp, mx;
   tmp.ensure(2 * sizeof(unsigned long long) * (size_t)n);
   mx.ensure(sizeof(unsigned long long) * L);
   launch_fill_i32(mx.as<int>(), 0, (size_t)L * 2, st);
@@ -286,7 +301,8 @@ static void omega_levels(ged_graph *g, int top, hipStream_t st) {
                                             : t2 + (size_t)((i - 1) & 1) * n;
     hipLaunchKernelGGL(k_omega_next, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
                        g->ci.as<const int>(), (int)n, prev, t2 + (size_t)(i & 1) * n,
-                       lv.as<double>() + (size_t)(i - 3) * n, mx.as<unsigned long long>() + (i - 3));
+                       out ? out + (size_t)(i - 3) * n : nullptr,
+                       mx.as<unsigned long long>() + (i - 3));
     GED_HIP(hipGetLastError());
   }
   std::vector<unsigned long long> hm((size_t)L);
@@ -295,6 +311,21 @@ static void omega_levels(ged_graph *g, int top, hipStream_t st) {
   GED_HIP(hipStreamSynchronize(st));
   int fit = 2;
   while (fit < top && hm[(size_t)(fit - 2)] < (1ull << 32)) ++fit;
+  if (top > g->omax_top) {
+    g->omax_top = top;
+    g->omax_fit = fit;
+  }
+  return fit;
+}
+
+// omega_3 .. omega_top as doubles (levels past the first one whose maximum
+// reaches 2^32 are not used).  Built in fresh buffers and published after
+// the stream has finished them; a replaced buffer is kept until the graph is
+// destroyed, since captured work may still name it.
+static void omega_levels(ged_graph *g, int top, hipStream_t st) {
+  DBuf lv;
+  lv.ensure(sizeof(double) * (size_t)g->n * (top - 2));
+  const int fit = omega_chain(g, top, lv.as<double>(), st);
   if (g->omega_lv.p) {
     g->omega_old.emplace_back();
     std::swap(g->omega_old.back().p, g->omega_lv.p);
@@ -306,17 +337,21 @@ static void omega_levels(ged_graph *g, int top, hipStream_t st) {
   g->omega_fit = fit;
 }
 
+int omega_fit_level(ged_graph *g, int L, hipStream_t st) {
+  if (L <= 2) return L;
+  std::lock_guard<std::mutex> lk(g_omega_mu);
+  if (L > g->omax_top && g->omax_fit == g->omax_top) {
+    ensure_omega2(g, st);
+    omega_chain(g, std::max(L, 4), nullptr, st);
+  }
+  return std::min(L, g->omax_fit);
+}
+
 void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st) {
   const int64_t n = g->n;
   const int eg = (int)std::min<int64_t>(8192, (n + kBlock - 1) / kBlock);
-  if (pl.s >= 2 && !g->omega2_ready) {
-    g->omega2.ensure(sizeof(uint64_t) * (size_t)n);
-    const int og = (int)std::min<int64_t>(16384, (n + kBlock / 64 - 1) / (kBlock / 64));
-    hipLaunchKernelGGL(k_omega2, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
-                       g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>());
-    GED_HIP(hipGetLastError());
-    g->omega2_ready = true;
-  }
+  std::unique_lock<std::mutex> lk(g_omega_mu);
+  if (pl.s >= 2) ensure_omega2(g, st);
   // 32-bit stored levels: 3 .. a-1 must all fit (levels only grow past a
   // level that does not, so none is computed beyond the first that fails)
   pl.lv32 = false;
@@ -326,6 +361,7 @@ void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st) {
       omega_levels(g, std::max(need, 4), st);
     pl.lv32 = g->omega_fit >= need;
   }
+  lk.unlock();
   PrepCache &pc = g->prep;
   if (pc.tr_r != pl.r) {
     pc.tr.ensure(sizeof(double) * (size_t)n);

@@ -199,3 +199,55 @@ def split_gain(row_ptr, col_idx, S, x: int, alpha: float, ell: int, w=None) -> f
     rs = q + da if r == a else q
     contrib = (q + da) + da * Mr + (m[a] - da) * rs
     return float(contrib.sum())
+
+
+def split_gain_counts(row_ptr, col_idx, S, x: int, alpha: float, ell: int):
+    """split_gain with the gain levels 1..a-1 as unscaled integer counts (the
+    32-bit layout of the greedy, unweighted graphs without repeated arcs):
+    level 1 is 1 on N(x) outside S and the number of x's arcs from outside S
+    at x; deeper levels inject the candidate's miss count recovered from the
+    FP64 miss chain by rounding m_i(x) / alpha^i; level a is
+    alpha^a * (sum of level a-1 counts).  Returns (L, injected counts)."""
+    n = len(row_ptr) - 1
+    inS = np.zeros(n, dtype=bool)
+    inS[np.asarray(S, dtype=np.int64)] = True
+    a = (ell + 1) // 2
+    r = ell - a
+    assert a >= 2
+    m = [(~inS).astype(np.float64)]
+    for _ in range(a):
+        y = alpha * _spmv(row_ptr, col_idx, None, m[-1])
+        y[inS] = 0.0
+        m.append(y)
+    deg = np.diff(row_ptr)
+    nbrs = col_idx[row_ptr[x]:row_ptr[x + 1]]
+    d1 = np.zeros(n, dtype=np.int64)
+    d1[nbrs[~inS[nbrs] & (nbrs != x)]] = 1
+    d1[x] = int(deg[x]) - int(inS[nbrs].sum())
+    d = [None, d1]
+    inj = {}
+    ap = alpha
+    for i in range(2, a):
+        ap *= alpha
+        inj[i] = int(np.rint(m[i][x] / ap))
+        y = _spmv(row_ptr, col_idx, None, d[-1].astype(np.float64)).astype(np.int64)
+        y[inS] = 0
+        y[x] = inj[i]
+        d.append(y)
+    alpha_a = alpha
+    for _ in range(1, a):
+        alpha_a *= alpha
+    da = alpha_a * _spmv(row_ptr, col_idx, None, d[a - 1].astype(np.float64))
+    da[inS] = 0.0
+    da[x] = m[a][x]
+    q = np.zeros(n)
+    wgt = alpha
+    for i in range(1, a):
+        q = q + wgt * d[i].astype(np.float64)
+        wgt *= alpha
+    Mr = np.zeros(n)
+    for c in range(1, r + 1):
+        Mr = Mr + m[c]
+    rs = q + da if r == a else q
+    contrib = (q + da) + da * Mr + (m[a] - da) * rs
+    return float(contrib.sum()), inj

@@ -197,6 +197,32 @@ def test_greedy_multigraph(ged):
     gg.close()
 
 
+def test_greedy_gain_layout(ged):
+    """The greedy's gain levels as 32-bit counts: on a sparse Erdos-Renyi graph
+    (max degree 11, omega_13 < 2^32) every walk length the greedy reaches keeps
+    its stored gain levels below 2^32, so the profiled dominant step kernel is
+    a 32-bit gain kernel; picks, lengths and gains match the oracle."""
+    g = inputs.erdos_renyi(3000, 4500, 57)
+    om = omega_max(g, 20)
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    gg.prepare(alpha, EPS)
+    gg.profile_enable(True)
+    rg = gg.greedy(6, alpha, EPS, with_score=False)
+    kind = gg.profile_read()["dominant_kind"]
+    gg.profile_enable(False)
+    ro = oracle.greedy(g, 6, alpha, EPS)
+    rg_full = gg.greedy(6, alpha, EPS)
+    compare_greedy(rg_full, ro, "gain layout")
+    assert list(rg["group"]) == list(ro["group"])
+    top = (max(int(e) for e in rg["ell"]) + 1) // 2 - 1
+    say(f"[gain layout] ells={list(rg['ell'])} kind={kind} top={top}")
+    assert all(om[i] < 2.0 ** 32 for i in range(3, top + 1))
+    assert top * (g.max_degree + 3) + 2 < 2 ** 19
+    assert kind % ged.KIND_BASE in (11, 12), kind
+    gg.close()
+
+
 def test_greedy_forced_prefix(ged):
     g = GRAPHS["ba20k"]()
     gg = ged.GedGraph.from_graph(g)

@@ -8,7 +8,9 @@
   plan shape (a = 1, 2, 3+, odd and even ell, weighted);
 * the same split for marginal gains (walks that avoid S and contain x);
 * the bound count_i <= omega_i that lets the dense levels be stored as 32-bit
-  integers, and split scoring with integer levels against the oracle.
+  integers, and split scoring with integer levels against the oracle;
+* split gains with integer gain levels (the candidate's miss counts recovered
+  by rounding the FP64 miss chain) against the oracle and exact counts.
 """
 import numpy as np
 import pytest
@@ -16,8 +18,8 @@ import pytest
 import oracle
 from exact import WalkTable
 from paper_1910_13874_amd import inputs
-from split_model import (count_levels, push_counts, split_gain, split_score,
-                         split_score_counts)
+from split_model import (count_levels, push_counts, split_gain, split_gain_counts,
+                         split_score, split_score_counts)
 
 
 def tiny_graph(n, m, seed):
@@ -189,3 +191,27 @@ def test_split_count_model_matches_oracle(name):
             assert ell_o == ell
             m = split_score_counts(g.row_ptr, g.col_idx, S, alpha, ell)
             assert abs(m - c) <= 1e-12 * abs(c), (name, ell, size, m, c)
+
+
+@pytest.mark.parametrize("name", ["ba", "er"])
+def test_split_gain_count_model_matches_oracle(name):
+    """Gain chains as unscaled integer counts equal the oracle's L_ell(S, x);
+    the miss counts injected at the candidate, recovered by rounding
+    m_i(x) / alpha^i, equal the exact number of walks avoiding S that end at x
+    (enumerated with Python integers)."""
+    g = inputs.barabasi_albert(300, 3, 45) if name == "ba" else inputs.erdos_renyi(300, 900, 46)
+    alpha = 0.9 * oracle.default_alpha(g, None)
+    rp, ci = g.row_ptr, g.col_idx
+    for ell in (3, 4, 7, 8, 12, 16):
+        for S, x in (([], 0), ([0, 5], 1), (list(range(10, 40)), 7), ([2], 250)):
+            o = oracle.gain(g, S, x, alpha, ell)
+            m, inj = split_gain_counts(rp, ci, S, x, alpha, ell)
+            assert abs(m - o) <= 1e-12 * abs(o), (name, ell, len(S), x, m, o)
+            # exact miss counts at x: walks avoiding S, by end vertex
+            inS = set(S)
+            mc = [0 if v in inS else 1 for v in range(g.n)]
+            for i in range(1, max(inj) + 1 if inj else 1):
+                mc = [0 if v in inS else sum(mc[int(u)] for u in ci[rp[v]:rp[v + 1]])
+                      for v in range(g.n)]
+                if i in inj:
+                    assert inj[i] == mc[x], (name, ell, i, inj[i], mc[x])
