@@ -133,12 +133,15 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
 }
 
 // Worklist entries, one wavefront each: count_1(y) goes to every x in one
-// chunk of N(y) (value 0 with clear = 1 stores zeros instead).
+// chunk of N(y) outside the group (member rows are overwritten with omega_2
+// afterwards, and a member hub would take one contended atomic per
+// neighbour); value 0 with clear = 1 stores zeros instead.
 template <class CT, bool CLEAR>
 __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
                                                     const int *__restrict__ ci, int C,
                                                     const CT *cnt1, CT *cnt2, const uint64_t *wl,
-                                                    const unsigned *wl_n, unsigned wl_cap) {
+                                                    const unsigned *wl_n, unsigned wl_cap,
+                                                    const uint64_t *__restrict__ tmask) {
   const unsigned count = min(*wl_n, wl_cap);
   const int lane = threadIdx.x & 63;
   const unsigned nwaves = (gridDim.x * kBlock) >> 6;
@@ -152,7 +155,10 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
       for (int j = j0 + lane; j < j1; j += 64) cnt2[(size_t)ci[j] * C + c] = 0;
     } else {
       const CT v = cnt1[(size_t)y * C + c];
-      for (int j = j0 + lane; j < j1; j += 64) atomicAdd(&cnt2[(size_t)ci[j] * C + c], v);
+      for (int j = j0 + lane; j < j1; j += 64) {
+        const int x = ci[j];
+        if (!((tmask[x] >> c) & 1ull)) atomicAdd(&cnt2[(size_t)x * C + c], v);
+      }
     }
   }
 }
@@ -431,7 +437,7 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
   GED_HIP(hipGetLastError());
   if (c2) {
     hipLaunchKernelGGL((k_push_wl<CT, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C, c1,
-                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
+                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap, tmask);
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_fix_members<CT>, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
@@ -449,7 +455,7 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
   if (c2) {
     hipLaunchKernelGGL((k_push_wl<CT, true>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C, c1,
-                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap);
+                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap, tmask);
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_clear_members<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem,

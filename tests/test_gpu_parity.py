@@ -522,6 +522,36 @@ def test_split_count_layout(ged, name):
     gg.close()
 
 
+@pytest.mark.parametrize("name", ["ba", "star"])
+def test_batch_every_tile_width(ged, name):
+    """Batched split scoring forced to each tile width 1..64: the step kernels'
+    column-pair gathers (32-bit inputs at C >= 2, blocks of twice the arcs),
+    32-bit stored levels ("ba": omega fits) and FP64 stored levels ("star":
+    omega_3 > 2^32), partials reduced over the matching partition.  Every column
+    equals the solo score; a sample against the oracle."""
+    if name == "ba":
+        g = inputs.barabasi_albert(20000, 5, 59)
+    else:
+        g = inputs.from_edges(70001, np.zeros(70000, np.int32),
+                              np.arange(1, 70001, dtype=np.int32), name="star70k")
+    gg = ged.GedGraph.from_graph(g)
+    alpha = 0.9 * oracle.default_alpha(g, None)
+    B = oracle.comb_bound(g, alpha, 7, None)
+    eps = float(np.sqrt(B * oracle.comb_bound(g, alpha, 6, None)))  # ell* = 7: one stored level
+    off, mem = inputs.groups(g.n, 70, 1, 60, 160)
+    solo = [gg.score(mem[off[j]:off[j + 1]], alpha, eps) for j in range(70)]
+    for j in (0, 33, 69):
+        c, ell_o, _, _ = oracle.score(g, mem[off[j]:off[j + 1]], alpha, eps)
+        assert ell_o == 7 and rel(solo[j], c) <= REL, (name, j, solo[j], c)
+    for tile in (1, 2, 4, 8, 16, 32, 64):
+        say(f"[tile widths] {name} tile={tile}")
+        gg.set_batch_tile(tile)
+        b = gg.score_batch(off, mem, alpha, eps)
+        worst = max(rel(b[j], solo[j]) for j in range(70))
+        assert worst <= 1e-12, (name, tile, worst)
+    gg.close()
+
+
 @pytest.mark.parametrize("name", ["ba", "directed", "weighted"])
 def test_spectral_bound(ged, name):
     """sigma_max estimate, ell* and scores / greedy under the spectral tail bound
