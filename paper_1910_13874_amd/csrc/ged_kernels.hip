@@ -125,7 +125,7 @@ struct CombineIn {
       return *p;
   }
   // sum_{i<a} h_i(v) for column c (levels beyond the first stored one are
-  // loaded here; there are none unless ell* > 8)
+  // loaded here; there are none unless ell > 8)
   __device__ __forceinline__ double q(const StepArgs &a, int v, int c) const {
     double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * (double)lv0;
     const LT *lv = static_cast<const LT *>(a.q_lv);
@@ -176,6 +176,9 @@ struct OutTraits {
   static constexpr bool combine = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                                   OUT == OUT_COMBINE32L || gaincomb;  // y not stored
   static constexpr bool store32 = OUT == OUT_TILE32 || OUT == OUT_GAIN32;
+  static constexpr bool tile = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
+                               OUT == OUT_COMBINE32 || OUT == OUT_TILE32 ||
+                               OUT == OUT_COMBINE32L;  // per-vertex column bits (tmask)
 };
 
 // y is h_a(v) (t_a(v) for v in S), q = sum_{i<a} h_i(v), trv = sum_{c<=r} t_c(v),
@@ -190,8 +193,7 @@ __device__ __forceinline__ double combine_fin(const StepArgs &a, double q, doubl
 template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OutTraits<OUT>::gain;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
-                      OUT == OUT_COMBINE32 || OUT == OUT_TILE32 || OUT == OUT_COMBINE32L;
+  constexpr bool TM = OutTraits<OUT>::tile;
   constexpr bool CA = OutTraits<OUT>::gain;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
                             TM ? a.tmask[v] : 0ull, CA ? a.cand_col[v] : -1);
@@ -242,8 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
                                                  const int4 *__restrict__ segs, int n_blocks) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OutTraits<OUT>::gain;
   constexpr bool CB = OutTraits<OUT>::combine;
-  constexpr bool TM = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
-                      OUT == OUT_COMBINE32 || OUT == OUT_TILE32 || OUT == OUT_COMBINE32L;
+  constexpr bool TM = OutTraits<OUT>::tile;
   constexpr bool CA = OutTraits<OUT>::gain;
   // NP: 32-bit input gathered as column pairs; a gather unit is 8 bytes
   // either way (one FP64 value or two 32-bit values), CU units per arc
