@@ -63,6 +63,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
   if (out == OUT_TILE32 || out == OUT_GAIN32)
     b += 4.0 * n * C;  // Y32
+  else if (out == OUT_ZERO32)
+    b += 12.0 * n * C;  // Y32 and Y
   else if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_COMBINE32L &&
            out != OUT_GAINCOMB && out != OUT_GAINCOMB32L)
     b += 8.0 * n * C;  // Y
@@ -80,7 +82,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
   }
   switch (out) {
     case OUT_INJ:
-    case OUT_ZERO: b += n / 8.0; break;
+    case OUT_ZERO:
+    case OUT_ZERO32: b += n / 8.0; break;
     case OUT_TILE:
     case OUT_TILE32:
     case OUT_POOL: b += 8.0 * n; break;

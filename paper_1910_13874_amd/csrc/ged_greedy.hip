@@ -66,11 +66,15 @@ __global__ void k_sdeg_add(const int *__restrict__ rp, const int *__restrict__ c
 // Miss level 1 (unweighted, undirected): m_1(v) = alpha * (deg(v) - arcs from
 // S into v) outside S, 0 on S -- the same integer times alpha as the dense
 // step from the complement mask computes, at O(n).
+// m1c (nullable) receives the count itself.
 __global__ void k_miss1(const int *__restrict__ rp, const int *__restrict__ sdeg,
-                        const uint32_t *__restrict__ smask, double alpha, int n, double *m1) {
+                        const uint32_t *__restrict__ smask, double alpha, int n, double *m1,
+                        uint32_t *m1c) {
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const bool inS = (smask[v >> 5] >> (v & 31)) & 1u;
-    m1[v] = inS ? 0.0 : alpha * (double)(rp[v + 1] - rp[v] - sdeg[v]);
+    const int cnt = inS ? 0 : rp[v + 1] - rp[v] - sdeg[v];
+    m1[v] = alpha * (double)cnt;
+    if (m1c) m1c[v] = (uint32_t)cnt;
   }
 }
 
@@ -315,6 +319,7 @@ struct GreedyCtx {
   bool split = false;  // undirected: chains to ceil(ell/2) (walk split)
   DBuf smask, m_levels, b_levels, ub, stale, done, cand_col, sampled;
   DBuf sdeg;            // split, unweighted: int32 [n] arcs from S into each vertex
+  DBuf mc32;            // 2 x uint32 [n]: miss counts of the last two levels (32-bit chain)
   DBuf dlv, Mr;        // split: stored gain levels [(a-1)*n*C], sum of miss levels [n]
   void *d1_zeroed = nullptr;  // dlv allocation whose level 1 is known to be all zero
   int d1_bytes = 0;           // ... in this element size (8 = FP64 levels, 4 = 32-bit)
@@ -356,9 +361,23 @@ static void ensure_levels_cap(GreedyCtx &c, int ell) {
 }
 
 // Miss chain(s) for the current S at walk length ell.
+// Miss levels as exact 32-bit counts up to level L: the counts are at most
+// omega_i, so on undirected unweighted graphs with 32-bit level-2 counts
+// (no repeated arcs, or max degree below 2^16) they fit when max omega_i < 2^32.
+static bool miss32(GreedyCtx &c, int L) {
+  ged_graph *g = c.g;
+  return c.split && !g->weighted && (g->simple || g->max_deg < 65536) &&
+         omega_fit_level(g, L, c.st) >= L;
+}
+
 static void miss_chains(GreedyCtx &c, int ell) {
   ged_graph *g = c.g;
   const int n = c.n;
+  // levels 2.. gather the previous level's counts (half the bytes of FP64) and
+  // store the count and alpha^i times it
+  const bool m32 = ell >= 2 && miss32(c, ell);
+  if (m32) c.mc32.ensure(2 * sizeof(uint32_t) * (size_t)n);
+  uint32_t *mc = c.mc32.as<uint32_t>();
   for (int dir = 0; dir < (g->flags == GED_DIRECTED ? 2 : 1); ++dir) {
     const bool rev = dir == 1;
     Partition &p = partition(g, 1, rev);
@@ -369,10 +388,13 @@ static void miss_chains(GreedyCtx &c, int ell) {
     if (c.split && !g->weighted) {  // level 1 from the S-arc counts
       hipLaunchKernelGGL(k_miss1, dim3(std::min(8192, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                          c.st, g->rp.as<const int>(), c.sdeg.as<const int>(),
-                         c.smask.as<const uint32_t>(), g->prep.alpha, n, L + (size_t)n);
+                         c.smask.as<const uint32_t>(), g->prep.alpha, n, L + (size_t)n,
+                         m32 ? mc + (size_t)n : nullptr);
       GED_HIP(hipGetLastError());
       i0 = 2;
     }
+    double ai = g->prep.alpha;  // alpha^i
+    for (int i = 2; i < i0; ++i) ai *= g->prep.alpha;
     for (int i = i0; i <= ell; ++i) {
       StepArgs a = base_args(g, rev);
       ws.into(a);
@@ -381,7 +403,15 @@ static void miss_chains(GreedyCtx &c, int ell) {
       a.smask = c.smask.as<const uint32_t>();
       a.X = L + (size_t)(i - 1) * n;
       a.Y = L + (size_t)i * n;
-      run_step(g, p, a, i == 1 ? IN_NOTMASK : IN_VEC, OUT_ZERO, c.st);
+      if (m32 && !rev) {
+        ai *= g->prep.alpha;
+        a.alpha = ai;
+        a.Xc32 = mc + (size_t)((i - 1) & 1) * n;
+        a.Y32 = mc + (size_t)(i & 1) * n;
+        run_step(g, p, a, IN_CNT32, OUT_ZERO32, c.st);
+      } else {
+        run_step(g, p, a, i == 1 ? IN_NOTMASK : IN_VEC, OUT_ZERO, c.st);
+      }
     }
   }
 }

@@ -154,7 +154,9 @@ enum OutMode : int {
   OUT_COMBINE32L = 10, // OUT_COMBINE32 whose stored levels are 32-bit counts too
   OUT_GAIN32 = 11,     // y as OUT_GAIN (inj at the candidate from injc[c]), stored to Y32
                        // as an exact 32-bit integer (unscaled gain-chain counts)
-  OUT_GAINCOMB32L = 12 // OUT_GAINCOMB whose stored levels are 32-bit counts
+  OUT_GAINCOMB32L = 12, // OUT_GAINCOMB whose stored levels are 32-bit counts
+  OUT_ZERO32 = 13       // miss-chain count: y = v in S ? 0 : sum (exact integer), stored
+                        // to Y32, and alpha * y to Y (alpha = alpha^i: the FP64 level)
 };
 // Profile records and kernel names encode a (gather, epilogue) pair as
 // in * kKindBase + out.

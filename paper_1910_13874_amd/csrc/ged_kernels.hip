@@ -72,6 +72,8 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
     return inS ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_ZERO) {
     return inS ? 0.0 : y;
+  } else if constexpr (OUT == OUT_ZERO32) {
+    return inS ? 0.0 : sum;  // the count; the caller also stores alpha * it
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                        OUT == OUT_TILE32 || OUT == OUT_COMBINE32L) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
@@ -192,7 +194,8 @@ __device__ __forceinline__ double combine_fin(const StepArgs &a, double q, doubl
 
 template <int C, int OUT>
 __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, double sum) {
-  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OutTraits<OUT>::gain;
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_ZERO32 ||
+                      OutTraits<OUT>::gain;
   constexpr bool TM = OutTraits<OUT>::tile;
   constexpr bool CA = OutTraits<OUT>::gain;
   return epilogue_v<C, OUT>(a, v, c, sum, M1 ? bit_of(a.smask, v) : false,
@@ -242,7 +245,8 @@ __device__ __forceinline__ void block_colsum_pairs(double v0, double v1, double 
 template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
-  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OutTraits<OUT>::gain;
+  constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_ZERO32 ||
+                      OutTraits<OUT>::gain;
   constexpr bool CB = OutTraits<OUT>::combine;
   constexpr bool TM = OutTraits<OUT>::tile;
   constexpr bool CA = OutTraits<OUT>::gain;
@@ -370,7 +374,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
                                               CA ? cw[rl] : -1);
           // wide tiles: the output is not read again before the next
           // launch, which gathers it from beyond the L2 anyway
-          if constexpr (OutTraits<OUT>::store32) {
+          if constexpr (OUT == OUT_ZERO32) {
+            a.Y32[(size_t)r * C + c] = (uint32_t)y;
+            a.Y[(size_t)r * C + c] = a.alpha * y;
+          } else if constexpr (OutTraits<OUT>::store32) {
             if constexpr (C >= 8)
               __builtin_nontemporal_store((uint32_t)y, a.Y32 + (size_t)r * C + c);
             else
@@ -460,6 +467,9 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
     in.load(a, r, c);
     const bool member = OutTraits<OUT>::gaincomb ? false : ((a.tmask[r] >> c) & 1ull);
     y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, member);
+  } else if constexpr (OUT == OUT_ZERO32) {
+    a.Y32[(size_t)r * C + c] = (uint32_t)y;
+    a.Y[(size_t)r * C + c] = a.alpha * y;
   } else if constexpr (OutTraits<OUT>::store32) {
     a.Y32[(size_t)r * C + c] = (uint32_t)y;
   } else {
@@ -571,6 +581,7 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_VEC, OUT_INJ)
     GED_CASE(IN_NOTMASK, OUT_ZERO)
     GED_CASE(IN_VEC, OUT_ZERO)
+    if constexpr (!WGT) GED_CASE(IN_CNT32, OUT_ZERO32)
   }
 #undef GED_CASE
   return false;
