@@ -425,6 +425,9 @@ using namespace ged;
 ged_graph::~ged_graph() {
   if (score_exec) (void)hipGraphExecDestroy(score_exec);
   if (score_graph) (void)hipGraphDestroy(score_graph);
+  if (score_clear_exec) (void)hipGraphExecDestroy(score_clear_exec);
+  if (score_clear_graph) (void)hipGraphDestroy(score_clear_graph);
+  if (score_done) (void)hipEventDestroy(score_done);
   for (auto e : prof.pool) (void)hipEventDestroy(e);
   for (auto &r : prof.recs) {
     (void)hipEventDestroy(r.a);

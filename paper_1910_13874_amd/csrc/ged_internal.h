@@ -361,6 +361,11 @@ struct ged_graph {
   hipGraphExec_t score_exec = nullptr;
   hipGraph_t score_graph = nullptr;
   std::vector<const void *> score_sig;  // pointers/values the captured graph depends on
+  // split scoring: the clean-up of a call, captured separately and left
+  // running after the result is on the host (same stream as the next call)
+  hipGraphExec_t score_clear_exec = nullptr;
+  hipGraph_t score_clear_graph = nullptr;
+  hipEvent_t score_done = nullptr;  // recorded after the result copy
   // batched scoring
   int32_t batch_tile = 0;
   // split scoring

@@ -654,9 +654,28 @@ int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> 
 static void drop_exec(ged_graph *g) {
   if (g->score_exec) (void)hipGraphExecDestroy(g->score_exec);
   if (g->score_graph) (void)hipGraphDestroy(g->score_graph);
+  if (g->score_clear_exec) (void)hipGraphExecDestroy(g->score_clear_exec);
+  if (g->score_clear_graph) (void)hipGraphDestroy(g->score_clear_graph);
   g->score_exec = nullptr;
   g->score_graph = nullptr;
+  g->score_clear_exec = nullptr;
+  g->score_clear_graph = nullptr;
   g->score_sig.clear();
+}
+
+template <class F>
+static void capture(hipStream_t st, F &&enqueue, hipGraph_t *graph, hipGraphExec_t *exec) {
+  GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue();
+  } catch (...) {
+    hipGraph_t dummy = nullptr;
+    (void)hipStreamEndCapture(st, &dummy);
+    if (dummy) (void)hipGraphDestroy(dummy);
+    throw;
+  }
+  GED_HIP(hipStreamEndCapture(st, graph));
+  GED_HIP(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
 }
 
 int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
@@ -703,44 +722,54 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   const int *d_mem = reinterpret_cast<const int *>(g->split_in.as<char>() + sizeof(offs));
   const int *d_mcol = d_mem + cap;
   SplitWs &w = g->split_ws;
-  auto enqueue = [&]() {
-    enqueue_split_tile(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, g->split_tmask.as<uint64_t>(),
-                       g->acc.as<double>(), st);
+  uint64_t *tm = g->split_tmask.as<uint64_t>();
+  // The tile's clean-up (zeroing the counts and member bits) is enqueued after
+  // the result copy and not waited for: any later work on this stream runs
+  // after it, and ged_set_stream / ged_graph_destroy synchronize the stream.
+  auto enqueue_main = [&]() {
+    split_tile_push(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, tm, st);
+    split_dense(g, w, pl, 1, tm, st);
+    split_tile_reduce(g, w, pl, 1, g->acc.as<double>(), st);
   };
-  w.zero = false;
-  if (g->prof.on) {
-    enqueue();
-  } else {
-    double ab = g->prep.alpha;
-    const void *abits;
-    std::memcpy(&abits, &ab, sizeof(ab));
-    std::vector<const void *> sig = {
-        g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.ws.blk.p, w.ws.seg.p,
-        w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
-        g->omega_lv.p, g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
-        (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
-        (const void *)(intptr_t)1 /* split */};
-    if (g->score_exec && sig != g->score_sig) drop_exec(g);
-    if (!g->score_exec) {
-      GED_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      try {
-        enqueue();
-      } catch (...) {
-        hipGraph_t dummy = nullptr;
-        (void)hipStreamEndCapture(st, &dummy);
-        if (dummy) (void)hipGraphDestroy(dummy);
-        throw;
-      }
-      GED_HIP(hipStreamEndCapture(st, &g->score_graph));
-      GED_HIP(hipGraphInstantiate(&g->score_exec, g->score_graph, nullptr, nullptr, 0));
-      g->score_sig = sig;
-    }
-    GED_HIP(hipGraphLaunch(g->score_exec, st));
-  }
+  auto enqueue_clear = [&]() {
+    split_tile_clear(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, tm, st);
+  };
+  if (!g->score_done) GED_HIP(hipEventCreateWithFlags(&g->score_done, hipEventDisableTiming));
   double *ho = g->out_host.as<double>();
-  GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
-  GED_HIP(hipStreamSynchronize(st));
-  w.zero = true;
+  w.zero = false;
+  try {
+    if (g->prof.on) {
+      enqueue_main();
+      GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      GED_HIP(hipEventRecord(g->score_done, st));
+      enqueue_clear();
+    } else {
+      double ab = g->prep.alpha;
+      const void *abits;
+      std::memcpy(&abits, &ab, sizeof(ab));
+      std::vector<const void *> sig = {
+          g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.ws.blk.p, w.ws.seg.p,
+          w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
+          g->omega_lv.p, g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
+          (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
+          (const void *)(intptr_t)1 /* split */};
+      if (g->score_exec && sig != g->score_sig) drop_exec(g);
+      if (!g->score_exec) {
+        capture(st, enqueue_main, &g->score_graph, &g->score_exec);
+        capture(st, enqueue_clear, &g->score_clear_graph, &g->score_clear_exec);
+        g->score_sig = sig;
+      }
+      GED_HIP(hipGraphLaunch(g->score_exec, st));
+      GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      GED_HIP(hipEventRecord(g->score_done, st));
+      GED_HIP(hipGraphLaunch(g->score_clear_exec, st));
+    }
+  } catch (...) {
+    g->split_tmask_ready = false;  // member bits may be left set
+    throw;
+  }
+  w.zero = true;  // the clean-up is queued ahead of any later work on the stream
+  GED_HIP(hipEventSynchronize(g->score_done));
   *out = ho[0];
   return GED_OK;
 }

@@ -198,10 +198,12 @@ def test_greedy_multigraph(ged):
 
 
 def test_greedy_gain_layout(ged):
-    """The greedy's gain levels as 32-bit counts: on a sparse Erdos-Renyi graph
-    (max degree 11, omega_13 < 2^32) every walk length the greedy reaches keeps
-    its stored gain levels below 2^32, so the profiled dominant step kernel is
-    a 32-bit gain kernel; picks, lengths and gains match the oracle."""
+    """The greedy's gain and miss levels as 32-bit counts: on a sparse
+    Erdos-Renyi graph (max degree 11, omega_13 < 2^32) every walk length the
+    greedy reaches keeps its gain levels (up to ceil(ell/2) - 1) and miss
+    levels (up to ceil(ell/2)) below 2^32, so the profiled dominant step
+    kernel is one of the 32-bit gain or miss kernels (their times are close on
+    a graph this small); picks, lengths and gains match the oracle."""
     g = inputs.erdos_renyi(3000, 4500, 57)
     om = omega_max(g, 20)
     gg = ged.GedGraph.from_graph(g)
@@ -217,9 +219,9 @@ def test_greedy_gain_layout(ged):
     assert list(rg["group"]) == list(ro["group"])
     top = (max(int(e) for e in rg["ell"]) + 1) // 2 - 1
     say(f"[gain layout] ells={list(rg['ell'])} kind={kind} top={top}")
-    assert all(om[i] < 2.0 ** 32 for i in range(3, top + 1))
+    assert all(om[i] < 2.0 ** 32 for i in range(3, top + 2))
     assert top * (g.max_degree + 3) + 2 < 2 ** 19
-    assert kind % ged.KIND_BASE in (11, 12), kind
+    assert kind % ged.KIND_BASE in (11, 12, 13), kind
     gg.close()
 
 
