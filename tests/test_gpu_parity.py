@@ -78,6 +78,27 @@ def test_score_parity(ged, name):
     gg.close()
 
 
+def test_scores_across_streams(ged):
+    """Scores issued back to back on one stream, then on another stream after
+    ged_set_stream, then on the handle's own stream again: each call leaves its
+    clean-up running on the stream it used, and every score still equals the
+    oracle's (the switch waits for the old stream)."""
+    import torch
+    g = GRAPHS["ba20k"]()
+    gg = ged.GedGraph.from_graph(g)
+    alpha = g.default_alpha()
+    groups = [inputs.group(g.n, size, 300 + size) for size in (1, 5, 40, 400)]
+    ref = [oracle.score(g, S, alpha, EPS)[0] for S in groups]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for st in (None, s1, s2, None, s1):
+        gg.set_stream(st)
+        for S, c in zip(groups, ref):
+            assert rel(gg.score(S, alpha, EPS), c) <= REL
+        for S, c in zip(reversed(groups), reversed(ref)):
+            assert rel(gg.score(S, alpha, EPS), c) <= REL
+    gg.close()
+
+
 def test_score_deterministic_and_alpha_change(ged):
     g = GRAPHS["rmat16"]()
     gg = ged.GedGraph.from_graph(g)
