@@ -361,21 +361,24 @@ static void ensure_levels_cap(GreedyCtx &c, int ell) {
 }
 
 // Miss chain(s) for the current S at walk length ell.
-// Miss levels as exact 32-bit counts up to level L: the counts are at most
-// omega_i, so on undirected unweighted graphs with 32-bit level-2 counts
-// (no repeated arcs, or max degree below 2^16) they fit when max omega_i < 2^32.
-static bool miss32(GreedyCtx &c, int L) {
+// Last miss level (<= L) kept as exact 32-bit counts: the counts are at most
+// omega_i, so on undirected unweighted graphs with 32-bit level-2 counts (no
+// repeated arcs, or max degree below 2^16) levels 1, 2 always fit and level i
+// fits when max omega_j < 2^32 for j <= i.  1 = no 32-bit chain.
+static int miss32_top(GreedyCtx &c, int L) {
   ged_graph *g = c.g;
-  return c.split && !g->weighted && (g->simple || g->max_deg < 65536) &&
-         omega_fit_level(g, L, c.st) >= L;
+  if (L < 2 || !c.split || g->weighted || !(g->simple || g->max_deg < 65536)) return 1;
+  return omega_fit_level(g, L, c.st);
 }
 
 static void miss_chains(GreedyCtx &c, int ell) {
   ged_graph *g = c.g;
   const int n = c.n;
-  // levels 2.. gather the previous level's counts (half the bytes of FP64) and
-  // store the count and alpha^i times it
-  const bool m32 = ell >= 2 && miss32(c, ell);
+  // levels 2 .. top32 gather the previous level's counts (half the bytes of
+  // FP64) and store the count and alpha^i times it; level top32 + 1 gathers
+  // counts and stores FP64; later levels continue the FP64 chain
+  const int top32 = miss32_top(c, ell);
+  const bool m32 = top32 >= 2;
   if (m32) c.mc32.ensure(2 * sizeof(uint32_t) * (size_t)n);
   uint32_t *mc = c.mc32.as<uint32_t>();
   for (int dir = 0; dir < (g->flags == GED_DIRECTED ? 2 : 1); ++dir) {
@@ -403,12 +406,16 @@ static void miss_chains(GreedyCtx &c, int ell) {
       a.smask = c.smask.as<const uint32_t>();
       a.X = L + (size_t)(i - 1) * n;
       a.Y = L + (size_t)i * n;
-      if (m32 && !rev) {
-        ai *= g->prep.alpha;
+      ai *= g->prep.alpha;
+      if (m32 && !rev && i <= top32 + 1) {
         a.alpha = ai;
         a.Xc32 = mc + (size_t)((i - 1) & 1) * n;
-        a.Y32 = mc + (size_t)(i & 1) * n;
-        run_step(g, p, a, IN_CNT32, OUT_ZERO32, c.st);
+        if (i <= top32) {
+          a.Y32 = mc + (size_t)(i & 1) * n;
+          run_step(g, p, a, IN_CNT32, OUT_ZERO32, c.st);
+        } else {
+          run_step(g, p, a, IN_CNT32, OUT_ZERO, c.st);
+        }
       } else {
         run_step(g, p, a, i == 1 ? IN_NOTMASK : IN_VEC, OUT_ZERO, c.st);
       }

@@ -581,7 +581,10 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_VEC, OUT_INJ)
     GED_CASE(IN_NOTMASK, OUT_ZERO)
     GED_CASE(IN_VEC, OUT_ZERO)
-    if constexpr (!WGT) GED_CASE(IN_CNT32, OUT_ZERO32)
+    if constexpr (!WGT) {
+      GED_CASE(IN_CNT32, OUT_ZERO32)
+      GED_CASE(IN_CNT32, OUT_ZERO)
+    }
   }
 #undef GED_CASE
   return false;
