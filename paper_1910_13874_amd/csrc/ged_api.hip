@@ -63,7 +63,7 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
   if (out == OUT_TILE32 || out == OUT_GAIN32)
     b += 4.0 * n * C;  // Y32
-  else if (out == OUT_ZERO32)
+  else if (out == OUT_ZERO32 || out == OUT_GAIN32D)
     b += 12.0 * n * C;  // Y32 and Y
   else if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_COMBINE32L &&
            out != OUT_GAINCOMB && out != OUT_GAINCOMB32L)
@@ -88,7 +88,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case OUT_TILE32:
     case OUT_POOL: b += 8.0 * n; break;
     case OUT_GAIN:
-    case OUT_GAIN32: b += n / 8.0 + 4.0 * n; break;
+    case OUT_GAIN32:
+    case OUT_GAIN32D: b += n / 8.0 + 4.0 * n; break;
     case OUT_COMBINE:
     case OUT_COMBINE32:
     case OUT_COMBINE32L: b += 8.0 * n * 3; break;  // tmask, t_a, tr

@@ -324,6 +324,8 @@ struct GreedyCtx {
   void *d1_zeroed = nullptr;  // dlv allocation whose level 1 is known to be all zero
   int d1_bytes = 0;           // ... in this element size (8 = FP64 levels, 4 = 32-bit)
   DBuf injc;                  // [(a)*C] candidate injections of the 32-bit gain levels
+  DBuf dc32;                  // 2 x uint32 [n*C]: gain levels 1, 2 as counts (FP64 chains)
+  void *dc1_zeroed = nullptr; // dc32 allocation whose level 1 is known to be all zero
   int g32_ell = -1;           // walk length g32_ok was decided for
   bool g32_ok = false;        // gain levels as 32-bit counts at g32_ell
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
@@ -590,12 +592,49 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
         }
       }
     } else {
+      // FP64 levels.  With the first level pushed and a >= 3, levels 1 and 2
+      // are also kept as 32-bit counts (they fit: level 2 <= omega_2 <= nnz on
+      // a graph without repeated arcs), so levels 2 and 3 gather counts; the
+      // candidate's level-2 miss count is exact (the miss chain stores level
+      // 2 as fl(alpha^2) times its count).
+      const bool p32 = push1 && la >= 3;
+      Partition &pn = partition_narrow(g, C);
+      uint32_t *dc = nullptr;
+      const double al = g->prep.alpha;
+      if (p32) {
+        c.wsC.fit(pn);
+        c.wsC.into(a);
+        c.dc32.ensure(2 * sizeof(uint32_t) * nC);
+        dc = c.dc32.as<uint32_t>();
+        if (c.dc1_zeroed != c.dc32.p) launch_fill_i32(c.dc32.as<int>(), 0, nC, c.st);
+        c.dc1_zeroed = nullptr;
+        hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 0);
+        GED_HIP(hipGetLastError());
+        c.injc.ensure(sizeof(double) * (size_t)(la + 1) * C);
+        hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
+                           c.cand_dev.as<const int>(), nc, C, al, 2, c.injc.as<double>());
+        GED_HIP(hipGetLastError());
+      }
+      double ai = al;  // alpha^i
       for (int i = push1 ? 2 : 1; i <= la; ++i) {
+        ai *= al;
+        const bool from32 = p32 && i <= 3;  // gathers the counts of level i - 1
+        Partition &ps = from32 ? pn : p;
+        const int in = from32 ? IN_CNT32 : (i == 1 ? IN_ONEHOT : IN_VEC);
         a.X = i == 1 ? nullptr : dl + (size_t)(i - 2) * nC;
+        a.Xc32 = from32 ? dc + (size_t)(i - 2) * nC : nullptr;
+        a.alpha = from32 ? ai : al;
         a.inj = M + (size_t)i * n;
         if (i < la) {
           a.Y = dl + (size_t)(i - 1) * nC;
-          run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAIN, c.st);
+          if (p32 && i == 2) {  // counts for level 3's gather, FP64 for the combination
+            a.Y32 = dc + nC;
+            a.injc = c.injc.as<const double>() + (size_t)2 * C;
+            run_step(g, ps, a, IN_CNT32, OUT_GAIN32D, c.st);
+          } else {
+            run_step(g, ps, a, in, OUT_GAIN, c.st);
+          }
         } else {
           a.Y = nullptr;
           a.tr = c.Mr.as<const double>();
@@ -608,8 +647,15 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
           a.q_slv = la > 1 ? 1.0 : 0.0;
           a.q_nlv = la - 1;
           a.q_even = r == la ? 1 : 0;
-          run_step(g, p, a, i == 1 ? IN_ONEHOT : IN_VEC, OUT_GAINCOMB, c.st, la - 1);
+          run_step(g, ps, a, in, OUT_GAINCOMB, c.st, la - 1);
+          pr = &ps;
         }
+      }
+      if (p32) {
+        hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 1);
+        GED_HIP(hipGetLastError());
+        c.dc1_zeroed = c.dc32.p;
       }
     }
     if (push1) {

@@ -155,8 +155,9 @@ enum OutMode : int {
   OUT_GAIN32 = 11,     // y as OUT_GAIN (inj at the candidate from injc[c]), stored to Y32
                        // as an exact 32-bit integer (unscaled gain-chain counts)
   OUT_GAINCOMB32L = 12, // OUT_GAINCOMB whose stored levels are 32-bit counts
-  OUT_ZERO32 = 13       // miss-chain count: y = v in S ? 0 : sum (exact integer), stored
+  OUT_ZERO32 = 13,      // miss-chain count: y = v in S ? 0 : sum (exact integer), stored
                         // to Y32, and alpha * y to Y (alpha = alpha^i: the FP64 level)
+  OUT_GAIN32D = 14      // OUT_GAIN32 that also stores alpha * y to Y (the FP64 level)
 };
 // Profile records and kernel names encode a (gather, epilogue) pair as
 // in * kKindBase + out.

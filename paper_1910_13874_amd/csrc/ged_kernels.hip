@@ -79,8 +79,8 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
-  } else if constexpr (OUT == OUT_GAIN32) {
-    return inS ? 0.0 : (cand == c ? a.injc[c] : y);
+  } else if constexpr (OUT == OUT_GAIN32 || OUT == OUT_GAIN32D) {
+    return inS ? 0.0 : (cand == c ? a.injc[c] : sum);  // the count
   } else {  // OUT_POOL
     const int s = a.col_step[c];
     if (s <= 0) return 0.0;
@@ -173,7 +173,7 @@ using CombineFor = CombineIn<C, OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L,
 template <int OUT>
 struct OutTraits {
   static constexpr bool gain = OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAIN32 ||
-                               OUT == OUT_GAINCOMB32L;  // S bits and candidate columns
+                               OUT == OUT_GAINCOMB32L || OUT == OUT_GAIN32D;  // S bits, candidates
   static constexpr bool gaincomb = OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L;
   static constexpr bool combine = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                                   OUT == OUT_COMBINE32L || gaincomb;  // y not stored
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
                                               CA ? cw[rl] : -1);
           // wide tiles: the output is not read again before the next
           // launch, which gathers it from beyond the L2 anyway
-          if constexpr (OUT == OUT_ZERO32) {
+          if constexpr (OUT == OUT_ZERO32 || OUT == OUT_GAIN32D) {
             a.Y32[(size_t)r * C + c] = (uint32_t)y;
             a.Y[(size_t)r * C + c] = a.alpha * y;
           } else if constexpr (OutTraits<OUT>::store32) {
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
     in.load(a, r, c);
     const bool member = OutTraits<OUT>::gaincomb ? false : ((a.tmask[r] >> c) & 1ull);
     y = combine_fin(a, in.q(a, r, c), y, in.trv, in.ta, member);
-  } else if constexpr (OUT == OUT_ZERO32) {
+  } else if constexpr (OUT == OUT_ZERO32 || OUT == OUT_GAIN32D) {
     a.Y32[(size_t)r * C + c] = (uint32_t)y;
     a.Y[(size_t)r * C + c] = a.alpha * y;
   } else if constexpr (OutTraits<OUT>::store32) {
@@ -572,6 +572,9 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     if constexpr (!WGT) {
       GED_CASE(IN_CNT32, OUT_GAIN32)
       GED_CASE(IN_CNT32, OUT_GAINCOMB32L)
+      GED_CASE(IN_CNT32, OUT_GAIN32D)
+      GED_CASE(IN_CNT32, OUT_GAIN)
+      GED_CASE(IN_CNT32, OUT_GAINCOMB)
     }
   }
   if constexpr (C == 1) {
