@@ -170,6 +170,9 @@ static void ensure_levels(PrepCache &pc, int64_t n, int levels_needed, hipStream
 }
 
 // t_i = alpha * A t_{i-1} with t_0 = 1; W[i] = sum_v t_i(v) = alpha^i sum_x omega_i(x).
+// Levels whose exact walk counts omega_i the graph already holds are written
+// as alpha^i omega_i with W_i from the integer sums (no step, no reduction, no
+// host round trip); the rest follow by steps.
 int prepare(ged_graph *g, double alpha, double eps) {
   int rc = check_alpha_eps(g, alpha, eps);
   if (rc) return rc;
@@ -184,11 +187,22 @@ int prepare(ged_graph *g, double alpha, double eps) {
   pc.tr_r = -1;
   pc.W.clear();
   pc.W.push_back((double)n);
-  ensure_levels(pc, n, 16, st);
+  const int held = omega_prefix_levels(g);
+  ensure_levels(pc, n, std::max(16, held + 1), st);
   double *T = pc.t_levels.as<double>();
   launch_fill_f64(T, 1.0, (size_t)n, st);
+  const int i0 = t_levels_from_omega(g, alpha, eps, held, T, pc.W, st);
+  bool done = false;
+  if (i0 > 0) {
+    const double B = comb_bound(g, alpha, pc.W.back());
+    if (B < eps) {
+      pc.ell = i0;
+      pc.bound = B;
+      done = true;
+    }
+  }
   double W_host = 0.0;
-  for (int i = 1;; ++i) {
+  for (int i = i0 + 1; !done; ++i) {
     if (i > 65536) return fail(GED_ERR_ELL, "walk length limit reached in precomputation");
     ensure_levels(pc, n, i + 1, st);
     T = pc.t_levels.as<double>();
@@ -207,7 +221,7 @@ int prepare(ged_graph *g, double alpha, double eps) {
     if (B < eps) {
       pc.ell = i;
       pc.bound = B;
-      break;
+      done = true;
     }
   }
   pc.alpha = alpha;

@@ -379,6 +379,9 @@ struct ged_graph {
   std::list<ged::DBuf> omega_old;  // replaced omega_lv buffers, freed with the graph
   // maxima known for levels 3 .. omax_top; omax_fit as omega_fit for them
   int omax_top = 2, omax_fit = 2;
+  // omega_sum[i] = sum_v omega_i(v) for i = 1 .. (2 once omega2 is ready, then
+  // omega_top once omega_lv holds levels 3..); exact for levels that fit 2^32
+  std::vector<double> omega_sum;
   std::vector<uint32_t> stamp;  // host group-dedup stamps
   uint32_t stamp_gen = 0;
   ged::SplitWs split_ws;        // single-group scoring workspace
@@ -442,6 +445,16 @@ void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st);
 // for L <= 2).  Computes the maxima by the integer chain the first time a
 // level is asked for (synchronizes the stream once); stores no levels.
 int omega_fit_level(ged_graph *g, int L, hipStream_t st);
+// Walk-count levels of the precomputation from the graph's exact integer
+// counts omega_i (unweighted graphs): omega_prefix_levels gives how many
+// levels those counts are held for (0 for weighted graphs);
+// t_levels_from_omega writes t_1 .. t_L (level i at T + i*n) for L up to
+// levels_cap, stopping at the first level whose tail bound is below eps,
+// appends W_1 .. W_L to W and returns L.
+constexpr int kTPrefixMax = 32;
+int omega_prefix_levels(ged_graph *g);
+int t_levels_from_omega(ged_graph *g, double alpha, double eps, int levels_cap, double *T,
+                        std::vector<double> &W, hipStream_t st);
 // Size a workspace for C columns and a worklist of wl_need entries; zero the
 // count arrays if they are new or dirty.
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,

@@ -211,11 +211,33 @@ __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict_
 // omega_2(v) = sum_{u in N(v)} deg(u): walks of length 2 ending at v.  One
 // wavefront per row (lanes over its arcs, integer sum), so hub rows do not
 // serialise on one lane.
+// Block-wide max and saturating sum of the wave leaders' values (lane 0 of
+// each wave holds one); thread 0 returns them.  Keeps the same-address
+// atomics that follow at one per block.
+__device__ __forceinline__ void block_max_sum(unsigned long long &m, unsigned long long &acc) {
+  __shared__ unsigned long long sm[kBlock / 64], sa[kBlock / 64];
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[wid] = m;
+    sa[wid] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      m = sm[w] > m ? sm[w] : m;
+      acc += sa[w];
+    }
+  }
+}
+
+// *sum (zeroed by the caller) receives sum_v omega_2(v).
 __global__ __launch_bounds__(kBlock) void k_omega2(const int *__restrict__ rp,
                                                    const int *__restrict__ ci, int n,
-                                                   unsigned long long *out) {
+                                                   unsigned long long *out,
+                                                   unsigned long long *sum) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  unsigned long long acc = 0, m = 0;
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; v < n; v += nw) {
     unsigned long long s = 0;
     for (int k = rp[v] + lane; k < rp[v + 1]; k += 64) {
@@ -224,12 +246,16 @@ __global__ __launch_bounds__(kBlock) void k_omega2(const int *__restrict__ rp,
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (lane == 0) out[v] = s;
+    acc += s;
   }
+  block_max_sum(m, acc);
+  if (threadIdx.x == 0 && acc > 0) atomicAdd(sum, acc);
 }
 
 // omega_i(v) = sum_{u in N(v)} omega_{i-1}(u), saturating at 2^64 - 1, also
 // written as a double (exact below 2^53, the only range it is used in); the
-// wave's largest value goes to *maxv.  One wavefront per row, as k_omega2.
+// wave's largest value goes to *maxv and its sum to *sumv (exact while the
+// level fits 2^32).  One wavefront per row, as k_omega2.
 __device__ __forceinline__ unsigned long long sat_add(unsigned long long x, unsigned long long y) {
   const unsigned long long z = x + y;
   return z < x ? ~0ull : z;
@@ -239,10 +265,11 @@ __global__ __launch_bounds__(kBlock) void k_omega_next(const int *__restrict__ r
                                                        const int *__restrict__ ci, int n,
                                                        const unsigned long long *__restrict__ prev,
                                                        unsigned long long *out, double *out_d,
-                                                       unsigned long long *maxv) {
+                                                       unsigned long long *maxv,
+                                                       unsigned long long *sumv) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-  unsigned long long m = 0;
+  unsigned long long m = 0, acc = 0;
   for (int64_t v = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; v < n; v += nw) {
     unsigned long long s = 0;
     for (int k = rp[v] + lane; k < rp[v + 1]; k += 64) s = sat_add(s, prev[ci[k]]);
@@ -251,9 +278,14 @@ __global__ __launch_bounds__(kBlock) void k_omega_next(const int *__restrict__ r
       out[v] = s;
       if (out_d) out_d[v] = (double)s;
       m = s > m ? s : m;
+      acc = sat_add(acc, s);
     }
   }
-  if (lane == 0 && m > 0) atomicMax(maxv, m);
+  block_max_sum(m, acc);
+  if (threadIdx.x == 0 && m > 0) {
+    atomicMax(maxv, m);
+    atomicAdd(sumv, acc);
+  }
 }
 
 // tr(v) = sum_{c=1..r} t_c(v), added in level order.
@@ -263,6 +295,25 @@ __global__ void k_sum_t(const double *__restrict__ T, int64_t n, int r, double *
     double s = 0.0;
     for (int c = 1; c <= r; ++c) s += T[(size_t)c * n + v];
     out[v] = s;
+  }
+}
+
+// t_i(v) = apow.a[i] * omega_i(v) for i = 1 .. P (omega_1 = degree): the
+// walk-count levels of the precomputation from the integer counts.
+struct TPow {
+  double a[kTPrefixMax + 1];
+};
+
+__global__ void k_t_from_omega(const int *__restrict__ rp,
+                               const unsigned long long *__restrict__ om2,
+                               const double *__restrict__ omlv, int64_t n, int P, TPow apow,
+                               double *__restrict__ T) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    T[(size_t)n + v] = apow.a[1] * (double)(rp[v + 1] - rp[v]);
+    if (P >= 2) T[2 * (size_t)n + v] = apow.a[2] * (double)om2[v];
+    for (int i = 3; i <= P; ++i)
+      T[(size_t)i * n + v] = apow.a[i] * omlv[(size_t)(i - 3) * n + v];
   }
 }
 
@@ -280,27 +331,37 @@ static void ensure_omega2(ged_graph *g, hipStream_t st) {
   if (g->omega2_ready) return;
   const int64_t n = g->n;
   g->omega2.ensure(sizeof(uint64_t) * (size_t)n);
+  DBuf sum;
+  sum.ensure(sizeof(unsigned long long));
+  launch_fill_i32(sum.as<int>(), 0, 2, st);
   const int og = (int)std::max<int64_t>(
-      1, std::min<int64_t>(16384, (n + kBlock / 64 - 1) / (kBlock / 64)));
+      1, std::min<int64_t>(2048, (n + kBlock / 64 - 1) / (kBlock / 64)));
   hipLaunchKernelGGL(k_omega2, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
-                     g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>());
+                     g->ci.as<const int>(), (int)n, g->omega2.as<unsigned long long>(),
+                     sum.as<unsigned long long>());
   GED_HIP(hipGetLastError());
+  unsigned long long hs = 0;
+  GED_HIP(hipMemcpyAsync(&hs, sum.p, sizeof(hs), hipMemcpyDeviceToHost, st));
+  GED_HIP(hipStreamSynchronize(st));
+  g->omega_sum.assign(3, 0.0);
+  g->omega_sum[1] = (double)g->nnz;
+  g->omega_sum[2] = (double)hs;
   g->omega2_ready = true;
 }
 
 // The integer chain omega_3 .. omega_top from omega_2, written as doubles to
-// out[(i-3)*n ..] if out is non-null.  Returns the largest i <= top such that
-// max_v omega_j(v) < 2^32 for 3 <= j <= i (2 if omega_3 does not fit).
-// Synchronizes the stream.
+// out[(i-3)*n ..] if out is non-null (then their sums go to omega_sum).
+// Returns the largest i <= top such that max_v omega_j(v) < 2^32 for
+// 3 <= j <= i (2 if omega_3 does not fit).  Synchronizes the stream.
 static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st) {
   const int64_t n = g->n;
   const int L = top - 2;
   DBuf tmp, mx;
   tmp.ensure(2 * sizeof(unsigned long long) * (size_t)n);
-  mx.ensure(sizeof(unsigned long long) * L);
-  launch_fill_i32(mx.as<int>(), 0, (size_t)L * 2, st);
+  mx.ensure(2 * sizeof(unsigned long long) * L);  // maxima, then sums
+  launch_fill_i32(mx.as<int>(), 0, (size_t)L * 4, st);
   const int og = (int)std::max<int64_t>(
-      1, std::min<int64_t>(16384, (n + kBlock / 64 - 1) / (kBlock / 64)));
+      1, std::min<int64_t>(2048, (n + kBlock / 64 - 1) / (kBlock / 64)));
   unsigned long long *t2 = tmp.as<unsigned long long>();
   for (int i = 3; i <= top; ++i) {
     const unsigned long long *prev = i == 3 ? g->omega2.as<const unsigned long long>()
@@ -308,15 +369,20 @@ static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_omega_next, dim3(og), dim3(kBlock), 0, st, g->rp.as<const int>(),
                        g->ci.as<const int>(), (int)n, prev, t2 + (size_t)(i & 1) * n,
                        out ? out + (size_t)(i - 3) * n : nullptr,
-                       mx.as<unsigned long long>() + (i - 3));
+                       mx.as<unsigned long long>() + (i - 3),
+                       mx.as<unsigned long long>() + L + (i - 3));
     GED_HIP(hipGetLastError());
   }
-  std::vector<unsigned long long> hm((size_t)L);
-  GED_HIP(hipMemcpyAsync(hm.data(), mx.p, sizeof(unsigned long long) * L, hipMemcpyDeviceToHost,
-                         st));
+  std::vector<unsigned long long> hm(2 * (size_t)L);
+  GED_HIP(hipMemcpyAsync(hm.data(), mx.p, 2 * sizeof(unsigned long long) * L,
+                         hipMemcpyDeviceToHost, st));
   GED_HIP(hipStreamSynchronize(st));
   int fit = 2;
   while (fit < top && hm[(size_t)(fit - 2)] < (1ull << 32)) ++fit;
+  if (out) {  // sums of levels past fit may have wrapped: not kept
+    g->omega_sum.resize((size_t)fit + 1);
+    for (int i = 3; i <= fit; ++i) g->omega_sum[(size_t)i] = (double)hm[(size_t)L + (i - 3)];
+  }
   if (top > g->omax_top) {
     g->omax_top = top;
     g->omax_fit = fit;
@@ -351,6 +417,36 @@ int omega_fit_level(ged_graph *g, int L, hipStream_t st) {
     omega_chain(g, std::max(L, 4), nullptr, st);
   }
   return std::min(L, g->omax_fit);
+}
+
+int omega_prefix_levels(ged_graph *g) {
+  if (g->weighted) return 0;
+  std::lock_guard<std::mutex> lk(g_omega_mu);
+  const int P = !g->omega2_ready ? 1 : g->omega_lv.p ? g->omega_fit : 2;
+  return std::min(P, kTPrefixMax);
+}
+
+int t_levels_from_omega(ged_graph *g, double alpha, double eps, int levels_cap, double *T,
+                        std::vector<double> &W, hipStream_t st) {
+  if (g->weighted || levels_cap < 1) return 0;
+  // the tables only grow, so they still hold the levels_cap levels counted
+  std::lock_guard<std::mutex> lk(g_omega_mu);
+  TPow apow;
+  apow.a[0] = 1.0;
+  int L = 0;
+  while (L < levels_cap) {
+    ++L;
+    apow.a[L] = apow.a[L - 1] * alpha;
+    W.push_back(apow.a[L] * (L == 1 ? (double)g->nnz : g->omega_sum[(size_t)L]));
+    if (comb_bound(g, alpha, W.back()) < eps) break;
+  }
+  const int64_t n = g->n;
+  hipLaunchKernelGGL(k_t_from_omega, dim3(grid_for((n + kBlock - 1) / kBlock, 8192)),
+                     dim3(kBlock), 0, st, g->rp.as<const int>(),
+                     L >= 2 ? g->omega2.as<const unsigned long long>() : nullptr,
+                     L >= 3 ? g->omega_lv.as<const double>() : nullptr, n, L, apow, T);
+  GED_HIP(hipGetLastError());
+  return L;
 }
 
 void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st) {

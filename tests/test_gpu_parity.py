@@ -193,10 +193,8 @@ def test_greedy_parity(ged, name, k):
     gg.close()
 
 
-def test_greedy_multigraph(ged):
-    """A graph with doubled arcs: the first gain level cannot be a push of
-    single walks, so the greedy keeps the dense one-hot step; picks, walk
-    lengths and gains still match the oracle (which counts every listed arc)."""
+def ba_multigraph():
+    """BA(3000, 3) with 200 of its edges listed twice (both directions)."""
     g0 = inputs.barabasi_albert(3000, 3, 58)
     rows = [list(g0.col_idx[g0.row_ptr[v]:g0.row_ptr[v + 1]]) for v in range(g0.n)]
     rng = np.random.default_rng(58)
@@ -208,7 +206,14 @@ def test_greedy_multigraph(ged):
     rp = np.zeros(g0.n + 1, dtype=np.int64)
     rp[1:] = np.cumsum([len(r) for r in rows])
     ci = np.fromiter((u for r in rows for u in r), dtype=np.int32, count=int(rp[-1]))
-    g = inputs.Graph(n=g0.n, row_ptr=rp, col_idx=ci, name="ba_multi")
+    return inputs.Graph(n=g0.n, row_ptr=rp, col_idx=ci, name="ba_multi")
+
+
+def test_greedy_multigraph(ged):
+    """A graph with doubled arcs: the first gain level cannot be a push of
+    single walks, so the greedy keeps the dense one-hot step; picks, walk
+    lengths and gains still match the oracle (which counts every listed arc)."""
+    g = ba_multigraph()
     say(f"[greedy multigraph] n={g.n} nnz={g.nnz}")
     gg = ged.GedGraph.from_graph(g)
     alpha = oracle.default_alpha(g, None)
@@ -485,6 +490,89 @@ def omega_max(g, top):
         om = np.bincount(rows, weights=om[g.col_idx], minlength=g.n)
         out.append(float(om.max()))
     return out
+
+
+def _prepare_graph(name):
+    if name == "sparse_er":
+        return inputs.erdos_renyi(3000, 4500, 57), None
+    if name == "ba20k":
+        return GRAPHS["ba20k"](), None
+    if name == "multigraph":
+        return ba_multigraph(), None
+    if name == "directed":
+        r = inputs.uniform_ints(2 * 9000, 2000, 61)
+        return inputs.from_edges(2000, r[0::2], r[1::2], symmetrize=False, name="dir2k"), None
+    if name == "edgeless":
+        return inputs.from_edges(50, [], [], symmetrize=True), None
+    g = inputs.barabasi_albert(5000, 4, 33)  # weighted
+    deg = g.degrees.astype(np.float64)
+    rows = np.repeat(np.arange(g.n), g.degrees)
+    return g, 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+
+
+@pytest.mark.parametrize("name", ["sparse_er", "ba20k", "multigraph", "directed", "edgeless",
+                                  "weighted"])
+def test_prepare_from_counts(ged, name):
+    """Precomputation levels written from the graph's integer walk counts:
+    level 1 from the degrees on a fresh handle, and after scores have built
+    the omega tables (undirected graphs) every level they hold, so the
+    precomputation runs fewer steps.  ell*, B and the walk total equal those of
+    the first precomputation (1e-12) and the oracle's, and scores after it
+    match the oracle, over eps values whose ell* ends inside and past the
+    levels held.  Weighted graphs take every level by steps."""
+    g, w = _prepare_graph(name)
+    gg = ged.GedGraph.from_graph(g, weights=w)
+    alpha = (0.5 / oracle.max_weighted_out_degree(g, w) if w is not None
+             else oracle.default_alpha(g))
+    eps_list = [1e-1, 1e-3, 1e-4, 1e-7, 1e-10, 1e-13]
+    first = {}
+    for eps in eps_list:
+        gg.invalidate()
+        gg.profile_enable(True)
+        first[eps] = gg.prepare(alpha, eps)
+        steps = gg.profile_read()["launches"]
+        gg.profile_enable(False)
+        ell = first[eps][0]
+        say(f"[prepare counts] {name} eps={eps:g} ell={ell} fresh steps={steps}")
+        assert steps == (ell if w is not None else max(ell - 1, 0)), (eps, ell, steps)
+    groups = [inputs.group(g.n, 5, 11), inputs.group(g.n, 40, 12)]
+    for S in groups:  # builds the omega tables on undirected graphs
+        gg.score(S, alpha, eps_list[-1])
+    for eps in eps_list:
+        gg.invalidate()
+        gg.profile_enable(True)
+        again = gg.prepare(alpha, eps)
+        steps = gg.profile_read()["launches"]
+        gg.profile_enable(False)
+        ell = again[0]
+        say(f"[prepare counts] {name} eps={eps:g} ell={ell} steps after scores={steps}")
+        assert ell == first[eps][0]
+        assert rel(again[1], first[eps][1]) <= 1e-12 and rel(again[2], first[eps][2]) <= 1e-12
+        if w is not None:
+            assert steps == ell
+            B_o = oracle.comb_bound(g, alpha, ell, w=w)
+        else:
+            assert steps <= max(ell - 1, 0)
+            if not g.directed and g.nnz > 0:
+                assert steps <= max(ell - 2, 0)
+            B_o = oracle.comb_bound(g, alpha, ell)
+        assert rel(again[1], B_o) <= REL, (again[1], B_o)
+        if w is None:
+            for S in groups:
+                check_score(gg, g, S, alpha, eps, tag=(name, eps))
+        else:
+            for S in groups:
+                s, ell_s, _ = gg.score(S, alpha, eps, with_info=True)
+                c, ell_o, _, _ = oracle.score(g, S, alpha, eps, w=w)
+                assert ell_s == ell_o and rel(s, c) <= REL, (eps, s, c)
+    if name == "sparse_er":  # the 32-bit omega levels are held and used
+        gg.invalidate()
+        gg.profile_enable(True)
+        ell = gg.prepare(alpha, eps_list[-1])[0]
+        steps = gg.profile_read()["launches"]
+        gg.profile_enable(False)
+        assert steps < ell - 2, (ell, steps)
+    gg.close()
 
 
 @pytest.mark.parametrize("name", ["sparse_er", "star"])
