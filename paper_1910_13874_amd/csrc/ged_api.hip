@@ -440,8 +440,7 @@ using namespace ged;
 ged_graph::~ged_graph() {
   if (score_exec) (void)hipGraphExecDestroy(score_exec);
   if (score_graph) (void)hipGraphDestroy(score_graph);
-  if (score_clear_exec) (void)hipGraphExecDestroy(score_clear_exec);
-  if (score_clear_graph) (void)hipGraphDestroy(score_clear_graph);
+  for (auto &x : split_exec) x.drop();
   if (score_done) (void)hipEventDestroy(score_done);
   for (auto e : prof.pool) (void)hipEventDestroy(e);
   for (auto &r : prof.recs) {

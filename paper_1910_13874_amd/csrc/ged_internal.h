@@ -291,6 +291,10 @@ struct SplitPlan {
   // number of all walks of length i ending at v, and max omega_i < 2^32 for
   // every stored level (set by split_tables)
   bool lv32 = false;
+  // single group with 32-bit stored levels whose level-3 push is small: the
+  // first stored level (3) is pushed from the vertices holding level-2
+  // counts instead of gathered
+  bool push3 = false;
 };
 
 struct SplitWs {
@@ -299,6 +303,9 @@ struct SplitWs {
   DBuf lv;               // [nlv*n*C] stored dense levels (double, or uint32 counts)
   DBuf wl, wl_n;         // uint64 worklist [wl_cap], uint32 length
   unsigned wl_cap = 0;
+  DBuf wl3, wl3_n;       // sources of the pushed level 3 (push3)
+  unsigned wl3_cap = 0;
+  bool lv_zero = false;  // first stored level all zero, as the push needs
   int wl_blocks = 64;    // grid of the worklist kernels (any value is correct)
   size_t cnt_bytes = 0;  // bytes of the count layout the arrays were zeroed for
   bool zero = false;
@@ -306,7 +313,15 @@ struct SplitWs {
 };
 
 
-struct ScoreGraphExec;  // captured graph for ged_score
+// A single-group split score captured as two graphs: the main work up to the
+// result, and its clean-up (left running after the result is on the host;
+// the next call is on the same stream).
+struct SplitExec {
+  hipGraph_t graph = nullptr, clear_graph = nullptr;
+  hipGraphExec_t exec = nullptr, clear_exec = nullptr;
+  std::vector<const void *> sig;  // pointers/values the captured graphs depend on
+  void drop();
+};
 
 struct Profiler {
   bool on = false;
@@ -314,7 +329,7 @@ struct Profiler {
     hipEvent_t a, b;
     int C;
     double bytes, edges;
-    int kind;  // in_mode * 8 + out_mode: one kernel instantiation per (C, kind)
+    int kind;  // in_mode * kKindBase + out_mode: one kernel instantiation per (C, kind)
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -362,10 +377,9 @@ struct ged_graph {
   hipGraphExec_t score_exec = nullptr;
   hipGraph_t score_graph = nullptr;
   std::vector<const void *> score_sig;  // pointers/values the captured graph depends on
-  // split scoring: the clean-up of a call, captured separately and left
-  // running after the result is on the host (same stream as the next call)
-  hipGraphExec_t score_clear_exec = nullptr;
-  hipGraph_t score_clear_graph = nullptr;
+  // split scoring: one captured pair per third-level variant (gathered,
+  // pushed), so groups that alternate between them keep both
+  ged::SplitExec split_exec[2];
   hipEvent_t score_done = nullptr;  // recorded after the result copy
   // batched scoring
   int32_t batch_tile = 0;
@@ -379,6 +393,8 @@ struct ged_graph {
   std::list<ged::DBuf> omega_old;  // replaced omega_lv buffers, freed with the graph
   // maxima known for levels 3 .. omax_top; omax_fit as omega_fit for them
   int omax_top = 2, omax_fit = 2;
+  // deg(v) + omega_2(v) + omega_3(v) on the host (single-group level-3 push)
+  std::vector<double> push_bound;
   // omega_sum[i] = sum_v omega_i(v) for i = 1 .. (2 once omega2 is ready, then
   // omega_top once omega_lv holds levels 3..); exact for levels that fit 2^32
   std::vector<double> omega_sum;

@@ -45,6 +45,9 @@ constexpr int kPushGrid = 2048; // blocks of the member kernels (grid-stride)
 // about one wave per expected entry, between kWlGridMin and kWlGridMax.
 constexpr int kWlGridMin = 64;
 constexpr int kWlGridMax = 16384;
+// Grid of the pushed level 3 and its clearing: one wave per entry up to
+// 4096 entries (waves without an entry end at once).
+constexpr int kWl3Grid = 1024;
 int split_wl_blocks(int64_t expected_entries) {
   return (int)std::max<int64_t>(kWlGridMin,
                                 std::min<int64_t>(kWlGridMax, (expected_entries + 3) / 4));
@@ -86,9 +89,37 @@ __device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) 
   return x - v;
 }
 
+// Worklist entry: chunk q of vertex y's arcs, column c.
+__device__ __forceinline__ uint64_t wl_entry(int y, int c, unsigned q) {
+  return ((uint64_t)(unsigned)y << 32) | ((uint64_t)c << 24) | q;
+}
+
+__device__ __forceinline__ unsigned wl_chunks(const int *rp, int y) {
+  return (unsigned)((rp[y + 1] - rp[y] + kWlChunk - 1) / kWlChunk);
+}
+
+// Each lane appends its nch entries for vertex y (all lanes of the wave
+// call this together): one atomic per wave; entries past cap are dropped
+// while the length keeps counting, so the reader sees the overflow.
+__device__ __forceinline__ void wl_append(uint64_t *wl, unsigned *wl_n, unsigned cap, int y, int c,
+                                          unsigned nch) {
+  unsigned total;
+  const unsigned ex = wave_excl_scan(nch, &total);
+  unsigned base = 0;
+  if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(wl_n, total);
+  base = __shfl(base, 63, 64);
+  for (unsigned q = 0; q < nch; ++q) {
+    const unsigned at = base + ex + q;
+    if (at < cap) wl[at] = wl_entry(y, c, q);
+  }
+}
+
 // Members of groups g0 .. g0+nc-1, one block per member: level-1 counts, the
 // level-2 contributions of paths through the member, and worklist entries for
-// the non-members they reach first.
+// the non-members they reach first.  With wl3 (single group, pushed level 3)
+// also the entries of every vertex holding a level-2 count so far: the
+// member itself (its count is omega_2) and each non-member neighbour the
+// first time its level-2 count is touched.
 template <class CT>
 __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
                                                  const int *__restrict__ ci,
@@ -96,53 +127,63 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
                                                  const int64_t *offsets, const int *members,
                                                  const int *mcol, int g0, int nc, int C, CT *cnt1,
                                                  CT *cnt2, uint64_t *wl, unsigned *wl_n,
-                                                 unsigned wl_cap) {
+                                                 unsigned wl_cap, uint64_t *wl3, unsigned *wl3_n,
+                                                 unsigned wl3_cap) {
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
     const int s = members[j];
     const int c = mcol[j] - g0;
     const int k0 = rp[s], k1 = rp[s + 1];
     const CT ds = (CT)(k1 - k0);
+    if (wl3 && threadIdx.x == 0 && k1 > k0) {
+      const unsigned nch = wl_chunks(rp, s);
+      const unsigned base = atomicAdd(wl3_n, nch);
+      for (unsigned q = 0; q < nch; ++q)
+        if (base + q < wl3_cap) wl3[base + q] = wl_entry(s, c, q);
+    }
     for (int kb = k0; kb < k1; kb += kBlock) {  // same trip count for the whole block
       const int k = kb + (int)threadIdx.x;
-      unsigned nch = 0;
+      unsigned nch = 0, nch3 = 0;
       int y = 0;
       if (k < k1) {
         y = ci[k];
         const size_t o = (size_t)y * C + c;
         const CT old = atomicAdd(&cnt1[o], (CT)1);
         if (cnt2) {
-          atomicAdd(&cnt2[o], ds);
-          if (old == 0 && !((tmask[y] >> c) & 1ull))
-            nch = (unsigned)((rp[y + 1] - rp[y] + kWlChunk - 1) / kWlChunk);
+          const CT old2 = atomicAdd(&cnt2[o], ds);
+          if (!((tmask[y] >> c) & 1ull)) {
+            const unsigned ch = wl_chunks(rp, y);
+            if (old == 0) nch = ch;
+            if (old2 == 0) nch3 = ch;
+          }
         }
       }
-      if (cnt2) {
-        unsigned total;
-        const unsigned ex = wave_excl_scan(nch, &total);
-        unsigned base = 0;
-        if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(wl_n, total);
-        base = __shfl(base, 63, 64);
-        for (unsigned q = 0; q < nch; ++q) {
-          const unsigned at = base + ex + q;
-          if (at < wl_cap) wl[at] = ((uint64_t)(unsigned)y << 32) | ((uint64_t)c << 24) | q;
-        }
-      }
+      if (cnt2) wl_append(wl, wl_n, wl_cap, y, c, nch);
+      if (wl3) wl_append(wl3, wl3_n, wl3_cap, y, c, nch3);
     }
   }
 }
 
-// Worklist entries, one wavefront each: count_1(y) goes to every x in one
-// chunk of N(y) outside the group (member rows are overwritten with omega_2
-// afterwards, and a member hub would take one contended atomic per
-// neighbour); value 0 with clear = 1 stores zeros instead.
-template <class CT, bool CLEAR>
+// Worklist entries, one wavefront each: src(y) (the next lower level's
+// count) goes to dst at every x in one chunk of N(y) outside the group
+// (member rows are overwritten with the unrestricted counts afterwards, and a
+// member hub would take one contended atomic per neighbour); with wl_next,
+// each x whose dst count is first touched appends its entries there.  CLEAR
+// stores zeros instead.  NEXT: wl_next is used (the adds return the old
+// count); otherwise the adds return nothing and the wave does not wait.
+template <class CT, bool CLEAR, bool NEXT>
 __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
                                                     const int *__restrict__ ci, int C,
-                                                    const CT *cnt1, CT *cnt2, const uint64_t *wl,
+                                                    const CT *src, CT *dst, const uint64_t *wl,
                                                     const unsigned *wl_n, unsigned wl_cap,
-                                                    const uint64_t *__restrict__ tmask) {
-  const unsigned count = min(*wl_n, wl_cap);
+                                                    const uint64_t *__restrict__ tmask,
+                                                    uint64_t *wl_next, unsigned *wl_next_n,
+                                                    unsigned wl_next_cap) {
+  const unsigned count = min(*wl_n, wl_cap);  // capacities are sized to never overflow
+  // A chunk is at most U arcs per lane: every col_idx load of the chunk is
+  // issued before the first use, then every tmask load, then every add, so a
+  // wave waits for one round trip of each instead of U.
+  constexpr int U = kWlChunk / 64;
   const int lane = threadIdx.x & 63;
   const unsigned nwaves = (gridDim.x * kBlock) >> 6;
   for (unsigned i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < count; i += nwaves) {
@@ -150,25 +191,57 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
     const int y = (int)(e >> 32);
     const int c = (int)((e >> 24) & 0xffu);
     const int q = (int)(e & 0xffffffu);
-    const int j0 = rp[y] + q * kWlChunk, j1 = min(j0 + kWlChunk, rp[y + 1]);
+    const int j0 = rp[y] + q * kWlChunk + lane, j1 = min(rp[y] + (q + 1) * kWlChunk, rp[y + 1]);
+    int x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) x[k] = j0 + 64 * k < j1 ? ci[j0 + 64 * k] : -1;
     if (CLEAR) {
-      for (int j = j0 + lane; j < j1; j += 64) cnt2[(size_t)ci[j] * C + c] = 0;
-    } else {
-      const CT v = cnt1[(size_t)y * C + c];
-      for (int j = j0 + lane; j < j1; j += 64) {
-        const int x = ci[j];
-        if (!((tmask[x] >> c) & 1ull)) atomicAdd(&cnt2[(size_t)x * C + c], v);
-      }
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (x[k] >= 0) dst[(size_t)x[k] * C + c] = 0;
+      continue;
     }
+    bool out[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) out[k] = x[k] >= 0 && !((tmask[x[k]] >> c) & 1ull);
+    const CT v = src[(size_t)y * C + c];
+    if (!NEXT) {
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (out[k]) atomicAdd(&dst[(size_t)x[k] * C + c], v);
+      continue;
+    }
+    bool first[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      first[k] = out[k] && atomicAdd(&dst[(size_t)x[k] * C + c], v) == 0;
+    unsigned nch[U], tot = 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      nch[k] = first[k] ? wl_chunks(rp, x[k]) : 0u;
+      tot += nch[k];
+    }
+    // one append for the lane's vertices (in k order)
+    unsigned total;
+    const unsigned ex = wave_excl_scan(tot, &total);
+    unsigned base = 0;
+    if (lane == 63 && total) base = atomicAdd(wl_next_n, total);
+    base = __shfl(base, 63, 64) + ex;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      for (unsigned r = 0; r < nch[k]; ++r, ++base)
+        if (base < wl_next_cap) wl_next[base] = wl_entry(x[k], c, r);
   }
 }
 
-// Member rows hold the unrestricted counts: deg(s) and omega_2(s).
+// Member rows hold the unrestricted counts: deg(s), omega_2(s) and, for a
+// pushed level 3, omega_3(s) (om3, exact integers as doubles).
 template <class CT>
 __global__ void k_fix_members(const int *__restrict__ rp,
                               const unsigned long long *__restrict__ omega2,
                               const int64_t *offsets, const int *members, const int *mcol,
-                              int g0, int nc, int C, CT *cnt1, CT *cnt2) {
+                              int g0, int nc, int C, CT *cnt1, CT *cnt2, CT *lv3,
+                              const double *__restrict__ om3) {
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < je;
        j += (int64_t)gridDim.x * blockDim.x) {
@@ -176,21 +249,26 @@ __global__ void k_fix_members(const int *__restrict__ rp,
     const size_t o = (size_t)s * C + (mcol[j] - g0);
     cnt1[o] = (CT)(rp[s + 1] - rp[s]);
     if (cnt2) cnt2[o] = (CT)omega2[s];
+    if (lv3) lv3[o] = (CT)om3[s];
   }
 }
 
 // Zero every count entry k_push / k_fix_members wrote for these members, and
-// the members' column bits in tmask; reset the worklist length (the worklist
-// replay that reads it has finished).
+// the members' column bits in tmask; reset the worklist lengths (the worklist
+// replays that read them have finished).
 template <class CT>
 __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict__ rp,
                                                           const int *__restrict__ ci,
                                                           const int64_t *offsets,
                                                           const int *members, const int *mcol,
                                                           int g0, int nc, int C, CT *cnt1,
-                                                          CT *cnt2, unsigned long long *tmask,
-                                                          unsigned *wl_n) {
-  if (wl_n && blockIdx.x == 0 && threadIdx.x == 0) *wl_n = 0;
+                                                          CT *cnt2, CT *lv3,
+                                                          unsigned long long *tmask,
+                                                          unsigned *wl_n, unsigned *wl3_n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (wl_n) *wl_n = 0;
+    if (wl3_n) *wl3_n = 0;
+  }
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
     const int s = members[j];
@@ -198,6 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict_
     if (threadIdx.x == 0) {
       cnt1[(size_t)s * C + c] = 0;
       if (cnt2) cnt2[(size_t)s * C + c] = 0;
+      if (lv3) lv3[(size_t)s * C + c] = 0;
       atomicAnd(&tmask[s], ~(1ull << c));
     }
     for (int k = rp[s] + (int)threadIdx.x; k < rp[s + 1]; k += kBlock) {
@@ -487,9 +566,47 @@ static Partition &step_partition(ged_graph *g, int C, int in) {
   return narrow_gather(C, in, g->weighted) ? partition_narrow(g, C) : partition(g, C);
 }
 
+// The level-3 push adds each level-2 source's count to all its neighbours:
+// as many adds as the sources' degrees sum to, scattered and contended at
+// hubs, so it is taken only for groups whose bound on that sum (below) is at
+// most nnz/32; the dense step gathers every arc.
+static int64_t push3_max_arcs(const ged_graph *g) { return g->nnz / 32; }
+
+// Worklist entries the push can need: each source has an arc, so at most one
+// per arc plus one per further 512 arcs.
+static size_t push3_cap(const ged_graph *g) {
+  const int64_t v = push3_max_arcs(g);
+  return (size_t)std::min<int64_t>(v + v / kWlChunk + 2, 0xffffffffll);
+}
+
+// Host table of deg(v) + omega_2(v) + omega_3(v), which bounds the degrees
+// added by the sources v contributes: its neighbours (2-walks from v) and the
+// ends of its 2-walks (3-walks); members count themselves (deg).
+static void ensure_push_bound(ged_graph *g, hipStream_t st) {
+  if (g->push_bound.size() == (size_t)g->n) return;
+  const size_t n = (size_t)g->n;
+  std::vector<unsigned long long> om2(n);
+  std::vector<double> om3(n);
+  const void *lv;
+  {
+    std::lock_guard<std::mutex> lk(g_omega_mu);
+    lv = g->omega_lv.p;  // a replaced table stays allocated with the graph
+  }
+  GED_HIP(hipMemcpyAsync(om2.data(), g->omega2.p, sizeof(unsigned long long) * n,
+                         hipMemcpyDeviceToHost, st));
+  GED_HIP(hipMemcpyAsync(om3.data(), lv, sizeof(double) * n, hipMemcpyDeviceToHost,
+                         st));  // omega_3 is level 0 of the table
+  GED_HIP(hipStreamSynchronize(st));
+  std::vector<double> b(n);
+  for (size_t v = 0; v < n; ++v)
+    b[v] = (double)(g->h_rp[v + 1] - g->h_rp[v]) + (double)om2[v] + om3[v];
+  g->push_bound.swap(b);
+}
+
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
                hipStream_t st, bool counts_only) {
   const size_t nC = (size_t)g->n * C;
+  const bool dirty = !w.zero;
   if (!counts_only) {
     w.ws.fit(partition(g, C));
     if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, C, IN_CNT32));
@@ -516,8 +633,27 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
       w.wl_cap = (unsigned)cap;
     }
   }
-  if (pl.nlv > 0 && !counts_only)
+  if (pl.nlv > 0 && !counts_only) {
+    const void *old = w.lv.p;
     w.lv.ensure((pl.lv32 ? sizeof(uint32_t) : sizeof(double)) * nC * (size_t)pl.nlv);
+    if (w.lv.p != old) w.lv_zero = false;
+  }
+  if (pl.push3) {
+    const size_t cap = push3_cap(g);
+    if (w.wl3_cap < cap || !w.wl3.p) {
+      w.wl3.ensure(sizeof(uint64_t) * cap);
+      w.wl3_cap = (unsigned)cap;
+    }
+    if (!w.wl3_n.p) {
+      w.wl3_n.ensure(sizeof(unsigned));
+      w.lv_zero = false;
+    }
+    if (dirty || !w.lv_zero) {
+      launch_fill_i32(w.lv.as<int>(), 0, nC, st);  // the first stored level (uint32)
+      launch_fill_i32(w.wl3_n.as<int>(), 0, 1, st);
+      w.lv_zero = true;
+    }
+  }
 }
 
 template <class CT>
@@ -527,19 +663,38 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
   const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
   CT *c1 = w.cnt1.as<CT>();
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
+  // pushed level 3: 32-bit counts only (push3 implies lv32, hence CT = uint32)
+  CT *l3 = pl.push3 ? w.lv.as<CT>() : nullptr;
+  uint64_t *wl3 = l3 ? w.wl3.as<uint64_t>() : nullptr;
+  unsigned *wl3_n = l3 ? w.wl3_n.as<unsigned>() : nullptr;
   hipLaunchKernelGGL(k_push<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, tmask, offs, mem,
                      mcol, g0, nc, C, c1, c2, w.wl.as<uint64_t>(), w.wl_n.as<unsigned>(),
-                     w.wl_cap);
+                     w.wl_cap, wl3, wl3_n, w.wl3_cap);
   GED_HIP(hipGetLastError());
   if (c2) {
-    hipLaunchKernelGGL((k_push_wl<CT, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C, c1,
-                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap, tmask);
+    if (wl3)
+      hipLaunchKernelGGL((k_push_wl<CT, false, true>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp,
+                         ci, C, c1, c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(),
+                         w.wl_cap, tmask, wl3, wl3_n, w.wl3_cap);
+    else
+      hipLaunchKernelGGL((k_push_wl<CT, false, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st,
+                         rp, ci, C, c1, c2, w.wl.as<const uint64_t>(),
+                         w.wl_n.as<const unsigned>(), w.wl_cap, tmask, (uint64_t *)nullptr,
+                         (unsigned *)nullptr, 0u);
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_fix_members<CT>, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
                      dim3(kBlock), 0, st, rp, g->omega2.as<const unsigned long long>(), offs, mem,
-                     mcol, g0, nc, C, c1, c2);
+                     mcol, g0, nc, C, c1, c2, l3,
+                     l3 ? g->omega_lv.as<const double>() : nullptr);  // omega_3 is level 0
   GED_HIP(hipGetLastError());
+  if (l3) {  // level 3 from every vertex holding a level-2 count
+    hipLaunchKernelGGL((k_push_wl<CT, false, false>), dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C,
+                       static_cast<const CT *>(c2), l3, w.wl3.as<const uint64_t>(),
+                       w.wl3_n.as<const unsigned>(), w.wl3_cap, tmask, (uint64_t *)nullptr,
+                       (unsigned *)nullptr, 0u);
+    GED_HIP(hipGetLastError());
+  }
 }
 
 template <class CT>
@@ -549,14 +704,23 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
   const int *rp = g->rp.as<const int>(), *ci = g->ci.as<const int>();
   CT *c1 = w.cnt1.as<CT>();
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
+  CT *l3 = pl.push3 ? w.lv.as<CT>() : nullptr;
   if (c2) {
-    hipLaunchKernelGGL((k_push_wl<CT, true>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C, c1,
-                       c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap, tmask);
+    hipLaunchKernelGGL((k_push_wl<CT, true, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C,
+                       c1, c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap,
+                       tmask, (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
+    GED_HIP(hipGetLastError());
+  }
+  if (l3) {  // the pushed level's targets
+    hipLaunchKernelGGL((k_push_wl<CT, true, false>), dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C,
+                       static_cast<const CT *>(c2), l3, w.wl3.as<const uint64_t>(),
+                       w.wl3_n.as<const unsigned>(), w.wl3_cap, tmask, (uint64_t *)nullptr,
+                       (unsigned *)nullptr, 0u);
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_clear_members<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem,
-                     mcol, g0, nc, C, c1, c2, reinterpret_cast<unsigned long long *>(tmask),
-                     c2 ? w.wl_n.as<unsigned>() : nullptr);
+                     mcol, g0, nc, C, c1, c2, l3, reinterpret_cast<unsigned long long *>(tmask),
+                     c2 ? w.wl_n.as<unsigned>() : nullptr, l3 ? w.wl3_n.as<unsigned>() : nullptr);
   GED_HIP(hipGetLastError());
 }
 
@@ -593,6 +757,7 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
         a.alpha = 1.0;
         a.inj = om + (size_t)(i - 3) * n;
         a.Y32 = lv32 + (size_t)(i - 1 - pl.s) * nC;
+        if (pl.push3 && i == pl.s + 1) continue;  // pushed with the first levels
         if (profile)
           run_step(g, pn, a, IN_CNT32, OUT_TILE32, st);
         else
@@ -747,16 +912,14 @@ int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> 
 
 // ------------------------------------------------------- single group --
 
-static void drop_exec(ged_graph *g) {
-  if (g->score_exec) (void)hipGraphExecDestroy(g->score_exec);
-  if (g->score_graph) (void)hipGraphDestroy(g->score_graph);
-  if (g->score_clear_exec) (void)hipGraphExecDestroy(g->score_clear_exec);
-  if (g->score_clear_graph) (void)hipGraphDestroy(g->score_clear_graph);
-  g->score_exec = nullptr;
-  g->score_graph = nullptr;
-  g->score_clear_exec = nullptr;
-  g->score_clear_graph = nullptr;
-  g->score_sig.clear();
+void SplitExec::drop() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (clear_exec) (void)hipGraphExecDestroy(clear_exec);
+  if (clear_graph) (void)hipGraphDestroy(clear_graph);
+  exec = clear_exec = nullptr;
+  graph = clear_graph = nullptr;
+  sig.clear();
 }
 
 template <class F>
@@ -802,6 +965,12 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
     g->split_tmask_ready = true;
   }
   split_tables(g, pl, st);
+  if (pl.lv32 && pl.s == 2 && pl.nlv >= 1) {
+    ensure_push_bound(g, st);
+    double b = 0.0;
+    for (int v : mem) b += g->push_bound[(size_t)v];
+    pl.push3 = b <= (double)push3_max_arcs(g);
+  }
   split_fit(g, g->split_ws, pl, 1, split_wl_need(g, deg_sum), st);
   // a fixed worklist grid, so the captured graph serves every group
   g->split_ws.wl_blocks = 256;
@@ -844,27 +1013,31 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
       const void *abits;
       std::memcpy(&abits, &ab, sizeof(ab));
       std::vector<const void *> sig = {
-          g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.ws.blk.p, w.ws.seg.p,
+          g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.wl3.p, w.wl3_n.p,
+          (const void *)(uintptr_t)w.wl3_cap, (const void *)(intptr_t)pl.push3, w.ws.blk.p, w.ws.seg.p,
           w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
           g->omega_lv.p, g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
           (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
           (const void *)(intptr_t)1 /* split */};
-      if (g->score_exec && sig != g->score_sig) drop_exec(g);
-      if (!g->score_exec) {
-        capture(st, enqueue_main, &g->score_graph, &g->score_exec);
-        capture(st, enqueue_clear, &g->score_clear_graph, &g->score_clear_exec);
-        g->score_sig = sig;
+      SplitExec &x = g->split_exec[pl.push3 ? 1 : 0];
+      if (x.exec && sig != x.sig) x.drop();
+      if (!x.exec) {
+        capture(st, enqueue_main, &x.graph, &x.exec);
+        capture(st, enqueue_clear, &x.clear_graph, &x.clear_exec);
+        x.sig = sig;
       }
-      GED_HIP(hipGraphLaunch(g->score_exec, st));
+      GED_HIP(hipGraphLaunch(x.exec, st));
       GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
       GED_HIP(hipEventRecord(g->score_done, st));
-      GED_HIP(hipGraphLaunch(g->score_clear_exec, st));
+      GED_HIP(hipGraphLaunch(x.clear_exec, st));
     }
   } catch (...) {
     g->split_tmask_ready = false;  // member bits may be left set
     throw;
   }
   w.zero = true;  // the clean-up is queued ahead of any later work on the stream
+  // a dense first stored level leaves its values; the pushed one is cleared
+  if (pl.nlv > 0) w.lv_zero = pl.push3;
   GED_HIP(hipEventSynchronize(g->score_done));
   *out = ho[0];
   return GED_OK;

@@ -575,6 +575,87 @@ def test_prepare_from_counts(ged, name):
     gg.close()
 
 
+def push3_arcs(g, S):
+    """Arcs the level-3 push of one group would touch: the degrees of every
+    vertex holding a level-2 count (members with arcs, and non-members
+    adjacent to S or to a neighbour of S)."""
+    deg = np.diff(g.row_ptr)
+    rows = np.repeat(np.arange(g.n), deg)
+    m = np.zeros(g.n, bool)
+    m[np.asarray(S)] = True
+    n1 = np.zeros(g.n, bool)
+    n1[g.col_idx[m[rows]]] = True  # neighbours of S
+    n2 = np.zeros(g.n, bool)
+    n2[g.col_idx[(m | n1)[rows]]] = True  # neighbours of S and of N(S)
+    src = (m & (deg > 0)) | (n2 & ~m)
+    return int(deg[src].sum())
+
+
+def push3_vertex_bounds(g):
+    """deg + omega_2 + omega_3 per vertex."""
+    deg = np.diff(g.row_ptr).astype(np.float64)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    om2 = np.bincount(rows, weights=deg[g.col_idx], minlength=g.n)
+    om3 = np.bincount(rows, weights=om2[g.col_idx], minlength=g.n)
+    return deg + om2 + om3
+
+
+def push3_bound(g, S, vb=None):
+    """The library's host bound on push3_arcs: the vertex bounds summed over
+    S; the push is taken when it is at most nnz/32."""
+    vb = push3_vertex_bounds(g) if vb is None else vb
+    return float(vb[np.unique(np.asarray(S))].sum())
+
+
+@pytest.mark.parametrize("name", ["sparse_er", "ba20k", "multigraph"])
+def test_score_pushed_level3(ged, name):
+    """Single scores whose first stored level (walk length 3, 32-bit counts)
+    is pushed from the vertices holding level-2 counts when a host bound on
+    the arcs that push touches (deg + omega_2 + omega_3 summed over S, which
+    is at least the true count) is at most nnz/32, and gathered otherwise:
+    groups on both sides of that threshold, in an order that moves between
+    the two and through walk lengths with no stored level or FP64 stored
+    levels, so the zeroed-level invariant is exercised.  Every score matches
+    the oracle and the batched score of the same groups."""
+    g, _ = _prepare_graph(name)
+    gg = ged.GedGraph.from_graph(g)
+    alpha = oracle.default_alpha(g)
+    lim = g.nnz // 32
+    sizes = [1, 5, 40, 400, 5, 2000, 3]
+    groups = [inputs.group(g.n, min(k, g.n), 900 + i) for i, k in enumerate(sizes)]
+    vb = push3_vertex_bounds(g)
+    low = np.argsort(vb, kind="stable")
+    groups[1:1] = [low[:1].astype(np.int32), low[:3].astype(np.int32)]  # smallest bounds
+    bound = [push3_bound(g, S, vb) for S in groups]
+    pushed = [b <= lim for b in bound]
+    for S, b in zip(groups, bound):
+        assert push3_arcs(g, S) <= b
+    say(f"[pushed level 3] {name} nnz={g.nnz} limit={lim} bounds={bound}")
+    assert any(pushed) and not all(pushed), "both regimes must be covered"
+    eps_seq = [1e-7, 100.0, 1e-7, 1e-13, 1e-2] if name == "sparse_er" else [1e-7, 1.0, 1e-2]
+    for eps in eps_seq:
+        ell = gg.prepare(alpha, eps)[0]
+        for S in groups:
+            s = check_score(gg, g, S, alpha, eps, tag=(name, eps, len(S)))
+        off = np.concatenate([[0], np.cumsum([len(S) for S in groups])]).astype(np.int64)
+        mem = np.concatenate(groups).astype(np.int32)
+        batch = gg.score_batch(off, mem, alpha, eps)
+        for j, S in enumerate(groups):
+            assert rel(batch[j], gg.score(S, alpha, eps)) <= 1e-12, (eps, j)
+        say(f"[pushed level 3] {name} eps={eps:g} ell={ell} ok")
+    if name == "ba20k":
+        # ell* = 7: levels 1-2 pushed, level 3 pushed or dense, level 4 combining
+        assert gg.prepare(alpha, 1e-2)[0] == 7
+        for S, p in zip(groups, pushed):
+            gg.profile_enable(True)
+            s = gg.score(S, alpha, 1e-2)
+            launches = gg.profile_read()["launches"]
+            gg.profile_enable(False)
+            assert launches == (1 if p else 2), (len(S), p, launches)
+            assert s == gg.score(S, alpha, 1e-2)  # profiled and captured runs agree
+    gg.close()
+
+
 @pytest.mark.parametrize("name", ["sparse_er", "star"])
 def test_split_count_layout(ged, name):
     """Dense split levels stored as unscaled 32-bit counts when every stored
