@@ -67,6 +67,52 @@ def push_counts(row_ptr, col_idx, S, s_levels):
     return cnt1, cnt2
 
 
+def push3_counts(row_ptr, col_idx, S):
+    """Level-3 counts of a single group by the third push, as the kernels do:
+    the level-2 pushes list every vertex whose level-2 count they touch first
+    (members list themselves), and each listed vertex adds its final level-2
+    count to its non-member neighbours; member rows hold omega_3.  Returns
+    (count_3, sources)."""
+    n = len(row_ptr) - 1
+    deg = np.diff(row_ptr).astype(np.int64)
+    inS = np.zeros(n, dtype=bool)
+    inS[S] = True
+    cnt1 = np.zeros(n, dtype=np.int64)
+    cnt2 = np.zeros(n, dtype=np.int64)
+    level1, sources = [], [int(m) for m in S if deg[m] > 0]
+    for m in S:
+        for y in col_idx[row_ptr[m]:row_ptr[m + 1]]:
+            if cnt1[y] == 0 and not inS[y]:
+                level1.append(int(y))
+            cnt1[y] += 1
+            if cnt2[y] == 0 and not inS[y]:
+                sources.append(int(y))
+            cnt2[y] += deg[m]
+    for y in level1:
+        for x in col_idx[row_ptr[y]:row_ptr[y + 1]]:
+            if inS[x]:
+                continue
+            if cnt2[x] == 0:
+                sources.append(int(x))
+            cnt2[x] += cnt1[y]
+    om = omega_levels(row_ptr, col_idx, 3)
+    cnt2[inS] = np.array(om[2], dtype=np.int64)[inS]
+    cnt3 = np.zeros(n, dtype=np.int64)
+    for u in sources:
+        for x in col_idx[row_ptr[u]:row_ptr[u + 1]]:
+            if not inS[x]:
+                cnt3[x] += cnt2[u]
+    cnt3[inS] = np.array(om[3], dtype=np.int64)[inS]
+    return cnt3, sources
+
+
+def push3_bound(row_ptr, col_idx, S) -> int:
+    """sum over S of deg + omega_2 + omega_3: what the host compares with
+    nnz/32 before taking the third push; it bounds the sources' degrees."""
+    om = omega_levels(row_ptr, col_idx, 3)
+    return int(sum(om[1][v] + om[2][v] + om[3][v] for v in set(int(v) for v in S)))
+
+
 def split_score(row_ptr, col_idx, S, alpha: float, ell: int, w=None) -> float:
     n = len(row_ptr) - 1
     S = np.unique(np.asarray(S, dtype=np.int64))

@@ -18,8 +18,8 @@ import pytest
 import oracle
 from exact import WalkTable
 from paper_1910_13874_amd import inputs
-from split_model import (count_levels, push_counts, split_gain, split_gain_counts,
-                         split_score, split_score_counts)
+from split_model import (count_levels, push3_bound, push3_counts, push_counts, split_gain,
+                         split_gain_counts, split_score, split_score_counts)
 
 
 def tiny_graph(n, m, seed):
@@ -215,3 +215,44 @@ def test_split_gain_count_model_matches_oracle(name):
                       for v in range(g.n)]
                 if i in inj:
                     assert inj[i] == mc[x], (name, ell, i, inj[i], mc[x])
+
+
+def multigraph(seed):
+    """tiny_graph with some edges listed twice."""
+    g = tiny_graph(12, 20, seed)
+    rows = [list(g.col_idx[g.row_ptr[v]:g.row_ptr[v + 1]]) for v in range(g.n)]
+    for v in range(0, g.n, 3):
+        if rows[v]:
+            u = rows[v][0]
+            rows[v].append(u)
+            rows[u].append(v)
+    rows = [sorted(r) for r in rows]
+    rp = np.zeros(g.n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.fromiter((u for r in rows for u in r), dtype=np.int32, count=int(rp[-1]))
+    return inputs.Graph(n=g.n, row_ptr=rp, col_idx=ci, name="multi")
+
+
+@pytest.mark.parametrize("kind", ["simple", "multi", "ba"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_push3_level_and_bound(kind, seed):
+    """The single-group third push: its sources (members with arcs, and every
+    vertex whose level-2 count the level-2 pushes touch first) give level-3
+    counts equal to the gathered chain's, and the host bound sum_S (deg +
+    omega_2 + omega_3) is at least the sources' degree sum, so a worklist of
+    bound + bound/512 + 1 entries (one per source and per further 512 arcs)
+    never overflows."""
+    g = (tiny_graph(12, 20, seed) if kind == "simple" else multigraph(seed) if kind == "multi"
+         else inputs.barabasi_albert(200, 3, seed))
+    deg = np.diff(g.row_ptr)
+    rng = np.random.default_rng(seed)
+    for size in (1, 2, 3, 6, g.n // 2):
+        S = np.sort(rng.choice(g.n, size, replace=False))
+        cnt, _ = count_levels(g.row_ptr, g.col_idx, S, 3)
+        cnt3, src = push3_counts(g.row_ptr, g.col_idx, S)
+        assert list(cnt3) == cnt[3]
+        assert len(src) == len(set(src))  # each source listed once
+        b = push3_bound(g.row_ptr, g.col_idx, S)
+        arcs = int(deg[src].sum())
+        entries = int(sum((deg[u] + 511) // 512 for u in src))
+        assert arcs <= b and entries <= b + b // 512 + 1, (arcs, entries, b)
