@@ -103,33 +103,41 @@ def _load():
 
 class _Weights:
     """Install arc weights (aligned with col_idx; rev aligned with the reverse
-    graph's col_idx) for the duration of one oracle call."""
+    graph's col_idx) for the duration of one oracle call.  Unweighted calls
+    leave the library's (unweighted) default untouched, so they may run
+    concurrently from several threads."""
 
     def __init__(self, w, w_rev):
         self.w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
         self.w_rev = None if w_rev is None else np.ascontiguousarray(w_rev, dtype=np.float64)
 
     def __enter__(self):
+        if self.w is None and self.w_rev is None:
+            return
         lib = _load()
         lib.or_set_weights(self.w.ctypes.data_as(P_F64) if self.w is not None else None,
                            self.w_rev.ctypes.data_as(P_F64) if self.w_rev is not None else None)
 
     def __exit__(self, *a):
-        _load().or_set_weights(None, None)
+        if self.w is not None or self.w_rev is not None:
+            _load().or_set_weights(None, None)
 
 
 class _Spectral:
     """Select the spectral tail bound with upper estimate `sigma` of sigma_max
-    (None: the combinatorial bound) for the duration of one oracle call."""
+    (None: the combinatorial bound, the library's default, left untouched)
+    for the duration of one oracle call."""
 
     def __init__(self, sigma):
         self.sigma = 0.0 if sigma is None else float(sigma)
 
     def __enter__(self):
-        _load().or_set_spectral(self.sigma)
+        if self.sigma != 0.0:
+            _load().or_set_spectral(self.sigma)
 
     def __exit__(self, *a):
-        _load().or_set_spectral(0.0)
+        if self.sigma != 0.0:
+            _load().or_set_spectral(0.0)
 
 
 def _ck(rc):

@@ -626,3 +626,20 @@ def test_score_and_greedy_under_spectral_bound(g):
     opt, _ = exact.opt_exact(g.n, g.row_ptr, g.col_idx, k, alpha)
     assert val >= (1 - 1 / Fraction(math.e)) * opt - Fraction(EPS)
     assert rel(r["score"], oracle.score(g, r["group"], alpha, EPS, sigma=sigma)[0]) == 0.0
+
+
+def test_oracle_default_calls_run_concurrently():
+    """Unweighted, combinatorial-bound oracle calls touch no shared state, so
+    scores computed on several threads at once equal the sequential ones
+    bit for bit (the host baseline runs them that way); a weighted call in
+    between leaves the defaults restored."""
+    from concurrent.futures import ThreadPoolExecutor
+    g = inputs.erdos_renyi(2000, 8000, 5)
+    alpha = oracle.default_alpha(g)
+    groups = [inputs.group(g.n, 5 + j, 300 + j) for j in range(12)]
+    seq = [oracle.score(g, S, alpha, 1e-6)[0] for S in groups]
+    w = np.full(g.nnz, 0.5)
+    oracle.score(g, groups[0], 0.5 / oracle.max_weighted_out_degree(g, w), 1e-6, w=w)
+    with ThreadPoolExecutor(4) as ex:
+        par = list(ex.map(lambda S: oracle.score(g, S, alpha, 1e-6)[0], groups))
+    assert par == seq
