@@ -78,6 +78,29 @@ __global__ void k_miss1(const int *__restrict__ rp, const int *__restrict__ sdeg
   }
 }
 
+// Miss levels 2 .. top of S + {x} from those of S (undirected, 32-bit
+// counts): the walks that avoid S + {x} are the walks that avoid S minus
+// those that also contain x, whose counts x's gain chain has just stored
+// (column col of the 32-bit gain levels dl32, level i at (i-1)*n*C; at x
+// itself they equal x's miss counts, so x's rows become 0).  M_i = fl(alpha^i)
+// * count on both sides, the counts are exact integers (M_i / alpha^i rounds
+// back to the count), so the result equals the recomputed chain bit for bit.
+// mc_top receives the level-top counts for the next dense level.
+__global__ void k_miss_sub(double *__restrict__ M, int n, const uint32_t *__restrict__ dl32, int C,
+                           int col, int top, double alpha, uint32_t *__restrict__ mc_top) {
+  const size_t nC = (size_t)n * C;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    double ai = alpha;
+    for (int i = 2; i <= top; ++i) {
+      ai *= alpha;
+      const double m = M[(size_t)i * n + v];
+      const double cnt = rint(m / ai) - (double)dl32[(size_t)(i - 1) * nC + (size_t)v * C + col];
+      M[(size_t)i * n + v] = ai * cnt;
+      if (i == top) mc_top[v] = (uint32_t)cnt;
+    }
+  }
+}
+
 // I(x) = b_0 * sum_{a=1}^{ell} m_a + sum_{c=1}^{ell} b_c * sum_{a=0}^{ell-c} m_a with
 // m_0 = b_0 = 1 for x outside S: every term of Lemma "initialize" once, no
 // subtraction.  ub[x] = -1 marks members of S.
@@ -328,6 +351,12 @@ struct GreedyCtx {
   void *dc1_zeroed = nullptr; // dc32 allocation whose level 1 is known to be all zero
   int g32_ell = -1;           // walk length g32_ok was decided for
   bool g32_ok = false;        // gain levels as 32-bit counts at g32_ell
+  // the last gain batch's candidates when its levels 2 .. a-1 are stored as
+  // 32-bit counts for walk length last_ell (-1: none), and the column of the
+  // vertex just added to S if it is one of them (-1: recompute the chain)
+  std::vector<int> last_cand;
+  int last_ell = -1;
+  int sub_col = -1;
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
   StepWs ws1, ws1r, wsC;
@@ -381,6 +410,12 @@ static void miss_chains(GreedyCtx &c, int ell) {
   // counts and stores FP64; later levels continue the FP64 chain
   const int top32 = miss32_top(c, ell);
   const bool m32 = top32 >= 2;
+  // right after a pick from the last gain batch: levels 2 .. ell-1 by
+  // subtracting the new member's stored gain levels (all counts)
+  const int sub = c.sub_col;
+  c.sub_col = -1;
+  const bool by_sub = sub >= 0 && m32 && top32 >= ell - 1 && ell >= 3 &&
+                      g->flags != GED_DIRECTED && c.split && !g->weighted;
   if (m32) c.mc32.ensure(2 * sizeof(uint32_t) * (size_t)n);
   uint32_t *mc = c.mc32.as<uint32_t>();
   for (int dir = 0; dir < (g->flags == GED_DIRECTED ? 2 : 1); ++dir) {
@@ -397,6 +432,13 @@ static void miss_chains(GreedyCtx &c, int ell) {
                          m32 ? mc + (size_t)n : nullptr);
       GED_HIP(hipGetLastError());
       i0 = 2;
+      if (by_sub) {
+        hipLaunchKernelGGL(k_miss_sub, dim3(std::min(8192, (n + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, c.st, L, n, c.dlv.as<const uint32_t>(), c.C, sub,
+                           ell - 1, g->prep.alpha, mc + (size_t)((ell - 1) & 1) * n);
+        GED_HIP(hipGetLastError());
+        i0 = ell;
+      }
     }
     double ai = g->prep.alpha;  // alpha^i
     for (int i = 2; i < i0; ++i) ai *= g->prep.alpha;
@@ -508,6 +550,7 @@ static bool gains32(GreedyCtx &c, int ell) {
 static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round, double *out) {
   ged_graph *g = c.g;
   const int n = c.n, C = c.C;
+  c.last_ell = -1;  // set below when the batch stores its levels as counts
   Partition &p = partition(g, C);
   c.wsC.fit(p);
   int *hc = reinterpret_cast<int *>(c.h_small.as<char>() + 1024);
@@ -563,6 +606,10 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
         hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
                            c.cand_dev.as<const int>(), nc, C, g->prep.alpha, la - 1,
                            c.injc.as<double>());
+      if (la > 2) {
+        c.last_cand.assign(cand, cand + nc);
+        c.last_ell = ell;
+      }
       double alpha_a = g->prep.alpha;
       for (int i = 1; i < la; ++i) alpha_a *= g->prep.alpha;
       for (int i = 2; i <= la; ++i) {
@@ -735,6 +782,8 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.split = split_ok(g);
   c.evals = 0;
   c.rounds = 0;
+  c.last_ell = -1;  // nothing of an earlier call is reused
+  c.sub_col = -1;
   const int K = c.C + 1;
   c.smask.ensure(sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1));
   c.ub.ensure(sizeof(double) * n);
@@ -875,6 +924,10 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
       s_size++;
       join(u);
       need_chain = true;
+      c.sub_col = -1;
+      if (c.last_ell == ell)
+        for (size_t q = 0; q < c.last_cand.size(); ++q)
+          if (c.last_cand[q] == u) c.sub_col = (int)q;
     }
     if (s_size < k) ell *= 2;
   }

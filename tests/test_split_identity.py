@@ -256,3 +256,60 @@ def test_push3_level_and_bound(kind, seed):
         arcs = int(deg[src].sum())
         entries = int(sum((deg[u] + 511) // 512 for u in src))
         assert arcs <= b and entries <= b + b // 512 + 1, (arcs, entries, b)
+
+
+def _miss_counts(g, S, top):
+    """Integer miss counts: walks ending at v that avoid S, levels 0..top."""
+    inS = np.zeros(g.n, dtype=bool)
+    inS[np.asarray(S, dtype=np.int64)] = True
+    m = [(~inS).astype(np.int64)]
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    for _ in range(top):
+        y = np.bincount(rows, weights=m[-1][g.col_idx], minlength=g.n).astype(np.int64)
+        y[inS] = 0
+        m.append(y)
+    return m
+
+
+def _gain_counts(g, S, x, top, m):
+    """The greedy's stored gain levels of candidate x as counts: level 1 is 1
+    on N(x) outside S and x's miss count at x; each deeper level sums its
+    in-neighbours' counts outside S and takes x's miss count at x."""
+    inS = np.zeros(g.n, dtype=bool)
+    inS[np.asarray(S, dtype=np.int64)] = True
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    nb = g.col_idx[g.row_ptr[x]:g.row_ptr[x + 1]]
+    d1 = np.zeros(g.n, dtype=np.int64)
+    d1[nb[~inS[nb] & (nb != x)]] = 1
+    d1[x] = m[1][x]
+    d = [None, d1]
+    for i in range(2, top + 1):
+        y = np.bincount(rows, weights=d[-1][g.col_idx], minlength=g.n).astype(np.int64)
+        y[inS] = 0
+        y[x] = m[i][x]
+        d.append(y)
+    return d
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_miss_counts_by_subtraction(seed):
+    """After x joins S the greedy takes the new miss counts (walks ending at v
+    that avoid S + {x}) as the old ones minus x's stored gain-level counts:
+    exact integers, so equal to the recomputed chain, which is itself checked
+    against explicit walk enumeration here; x's rows become 0."""
+    g = tiny_graph(10, 18, seed)
+    tab = WalkTable(g.n, g.row_ptr, g.col_idx, 5)
+    rng = np.random.default_rng(seed)
+    for size in (1, 2, 3):
+        S = list(rng.choice(g.n, size, replace=False))
+        for x in range(g.n):
+            if x in S:
+                continue
+            m = _miss_counts(g, S, 5)
+            d = _gain_counts(g, S, x, 5, m)
+            m2 = _miss_counts(g, S + [x], 5)
+            for i in range(1, 6):
+                assert list(m[i] - d[i]) == list(m2[i]), (S, x, i)
+                for v in range(g.n):
+                    assert m2[i][v] == tab.miss_end(i, S + [x], v)
+                    assert d[i][v] == (tab.miss_end(i, S, v) - tab.miss_end(i, S + [x], v))
