@@ -61,12 +61,12 @@ StepArgs base_args(ged_graph *g, bool reverse) {
 double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows) {
   const double n = (double)g->n, nnz = (double)g->nnz;
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
-  if (out == OUT_TILE32 || out == OUT_GAIN32)
+  if (out == OUT_TILE32 || out == OUT_GAIN32 || out == OUT_GAINCOMB32S)
     b += 4.0 * n * C;  // Y32
   else if (out == OUT_ZERO32 || out == OUT_GAIN32D)
     b += 12.0 * n * C;  // Y32 and Y
   else if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_COMBINE32L &&
-           out != OUT_GAINCOMB && out != OUT_GAINCOMB32L)
+           out != OUT_GAINCOMB && out != OUT_GAINCOMB32L && out != OUT_GAINCOMB32S)
     b += 8.0 * n * C;  // Y
   if (g->weighted) b += 8.0 * nnz;
   switch (in) {
@@ -94,7 +94,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case OUT_COMBINE32:
     case OUT_COMBINE32L: b += 8.0 * n * 3; break;  // tmask, t_a, tr
     case OUT_GAINCOMB:
-    case OUT_GAINCOMB32L: b += n / 8.0 + 4.0 * n + 16.0 * n; break;  // S bits, candidates, m_a, M_r
+    case OUT_GAINCOMB32L:
+    case OUT_GAINCOMB32S: b += n / 8.0 + 4.0 * n + 16.0 * n; break;  // S bits, candidates, m_a, M_r
     default: break;
   }
   return b + 8.0 * n * C * extra_rows;

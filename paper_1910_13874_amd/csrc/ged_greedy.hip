@@ -81,8 +81,9 @@ __global__ void k_miss1(const int *__restrict__ rp, const int *__restrict__ sdeg
 // Miss levels 2 .. top of S + {x} from those of S (undirected, 32-bit
 // counts): the walks that avoid S + {x} are the walks that avoid S minus
 // those that also contain x, whose counts x's gain chain has just stored
-// (column col of the 32-bit gain levels dl32, level i at (i-1)*n*C; at x
-// itself they equal x's miss counts, so x's rows become 0).  M_i = fl(alpha^i)
+// (column col of the 32-bit gain levels dl32, level i at (i-1)*n*C, the top
+// one by the combining step; at x itself they equal x's miss counts, so x's
+// rows become 0).  M_i = fl(alpha^i)
 // * count on both sides, the counts are exact integers (M_i / alpha^i rounds
 // back to the count), so the result equals the recomputed chain bit for bit.
 // mc_top receives the level-top counts for the next dense level.
@@ -356,6 +357,7 @@ struct GreedyCtx {
   // vertex just added to S if it is one of them (-1: recompute the chain)
   std::vector<int> last_cand;
   int last_ell = -1;
+  bool last_top = false;  // ... and level a of the gain chains too (OUT_GAINCOMB32S)
   int sub_col = -1;
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
@@ -410,12 +412,14 @@ static void miss_chains(GreedyCtx &c, int ell) {
   // counts and stores FP64; later levels continue the FP64 chain
   const int top32 = miss32_top(c, ell);
   const bool m32 = top32 >= 2;
-  // right after a pick from the last gain batch: levels 2 .. ell-1 by
-  // subtracting the new member's stored gain levels (all counts)
+  // right after a pick from the last gain batch: levels 2 .. ell-1 (and ell
+  // when the batch stored its top level) by subtracting the new member's
+  // stored gain levels (all counts)
   const int sub = c.sub_col;
   c.sub_col = -1;
   const bool by_sub = sub >= 0 && m32 && top32 >= ell - 1 && ell >= 3 &&
                       g->flags != GED_DIRECTED && c.split && !g->weighted;
+  const int sub_top = by_sub && c.last_top && top32 >= ell ? ell : ell - 1;
   if (m32) c.mc32.ensure(2 * sizeof(uint32_t) * (size_t)n);
   uint32_t *mc = c.mc32.as<uint32_t>();
   for (int dir = 0; dir < (g->flags == GED_DIRECTED ? 2 : 1); ++dir) {
@@ -435,9 +439,9 @@ static void miss_chains(GreedyCtx &c, int ell) {
       if (by_sub) {
         hipLaunchKernelGGL(k_miss_sub, dim3(std::min(8192, (n + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, c.st, L, n, c.dlv.as<const uint32_t>(), c.C, sub,
-                           ell - 1, g->prep.alpha, mc + (size_t)((ell - 1) & 1) * n);
+                           sub_top, g->prep.alpha, mc + (size_t)(sub_top & 1) * n);
         GED_HIP(hipGetLastError());
-        i0 = ell;
+        i0 = sub_top + 1;
       }
     }
     double ai = g->prep.alpha;  // alpha^i
@@ -572,7 +576,10 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
     const size_t nC = (size_t)n * C;
     const bool g32 = la > 1 && gains32(c, ell);
     const int eb = g32 ? 4 : 8;  // bytes per stored value
-    if (la > 1) c.dlv.ensure((size_t)eb * nC * (size_t)(la - 1));
+    // the combining level's counts too, when they fit 32 bits: after a pick
+    // from this batch the whole miss chain follows by subtraction
+    const bool top_a = g32 && la > 2 && omega_fit_level(g, la, c.st) >= la;
+    if (la > 1) c.dlv.ensure((size_t)eb * nC * (size_t)(la - 1 + (top_a ? 1 : 0)));
     double *dl = c.dlv.as<double>();
     uint32_t *dl32 = c.dlv.as<uint32_t>();
     const double *any = c.Mr.as<const double>();
@@ -609,6 +616,7 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       if (la > 2) {
         c.last_cand.assign(cand, cand + nc);
         c.last_ell = ell;
+        c.last_top = top_a;
       }
       double alpha_a = g->prep.alpha;
       for (int i = 1; i < la; ++i) alpha_a *= g->prep.alpha;
@@ -635,7 +643,9 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
           a.q_alpha = g->prep.alpha;
           a.q_nlv = la - 1;
           a.q_even = r == la ? 1 : 0;
-          run_step(g, pn, a, IN_CNT32, OUT_GAINCOMB32L, c.st, 0.5 * (la - 1));
+          a.Y32 = top_a ? dl32 + (size_t)(la - 1) * nC : nullptr;
+          run_step(g, pn, a, IN_CNT32, top_a ? OUT_GAINCOMB32S : OUT_GAINCOMB32L, c.st,
+                   0.5 * (la - 1));
         }
       }
     } else {

@@ -157,7 +157,9 @@ enum OutMode : int {
   OUT_GAINCOMB32L = 12, // OUT_GAINCOMB whose stored levels are 32-bit counts
   OUT_ZERO32 = 13,      // miss-chain count: y = v in S ? 0 : sum (exact integer), stored
                         // to Y32, and alpha * y to Y (alpha = alpha^i: the FP64 level)
-  OUT_GAIN32D = 14      // OUT_GAIN32 that also stores alpha * y to Y (the FP64 level)
+  OUT_GAIN32D = 14,     // OUT_GAIN32 that also stores alpha * y to Y (the FP64 level)
+  OUT_GAINCOMB32S = 15  // OUT_GAINCOMB32L that also stores y's count to Y32: 0 on S, the
+                        // candidate's miss count (inj / alpha) at it, else the sum
 };
 // Profile records and kernel names encode a (gather, epilogue) pair as
 // in * kKindBase + out.

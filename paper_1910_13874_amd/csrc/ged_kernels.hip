@@ -77,7 +77,8 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                        OUT == OUT_TILE32 || OUT == OUT_COMBINE32L) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
-  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L) {
+  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L ||
+                       OUT == OUT_GAINCOMB32S) {
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
   } else if constexpr (OUT == OUT_GAIN32 || OUT == OUT_GAIN32D) {
     return inS ? 0.0 : (cand == c ? a.injc[c] : sum);  // the count
@@ -167,14 +168,19 @@ struct CombineIn {
 
 template <int C, int OUT>
 using CombineFor = CombineIn<C, OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L,
-                             OUT == OUT_COMBINE32L || OUT == OUT_GAINCOMB32L>;
+                             OUT == OUT_COMBINE32L || OUT == OUT_GAINCOMB32L ||
+                                 OUT == OUT_GAINCOMB32S>;
 
 // Output modes by property.
 template <int OUT>
 struct OutTraits {
   static constexpr bool gain = OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAIN32 ||
-                               OUT == OUT_GAINCOMB32L || OUT == OUT_GAIN32D;  // S bits, candidates
-  static constexpr bool gaincomb = OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L;
+                               OUT == OUT_GAINCOMB32L || OUT == OUT_GAIN32D ||
+                               OUT == OUT_GAINCOMB32S;  // S bits, candidates
+  static constexpr bool gaincomb =
+      OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L || OUT == OUT_GAINCOMB32S;
+  // the combination's level count is stored as well (gain levels by counts)
+  static constexpr bool cstore = OUT == OUT_GAINCOMB32S;
   static constexpr bool combine = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                                   OUT == OUT_COMBINE32L || gaincomb;  // y not stored
   static constexpr bool store32 = OUT == OUT_TILE32 || OUT == OUT_GAIN32;
@@ -182,6 +188,14 @@ struct OutTraits {
                                OUT == OUT_COMBINE32 || OUT == OUT_TILE32 ||
                                OUT == OUT_COMBINE32L;  // per-vertex column bits (tmask)
 };
+
+// The count behind a gain combination's level value y (OUT_GAINCOMB32S): 0 on
+// S (y = 0), the candidate's miss count at it (y = m_a = alpha^a times that
+// count, exactly: it rounds back), else the gathered sum itself.
+__device__ __forceinline__ uint32_t gain_count(const StepArgs &a, double y, double sum,
+                                               bool cand) {
+  return (uint32_t)(y == 0.0 ? 0.0 : (cand ? rint(y / a.alpha) : sum));
+}
 
 // y is h_a(v) (t_a(v) for v in S), q = sum_{i<a} h_i(v), trv = sum_{c<=r} t_c(v),
 // ta = t_a(v).
@@ -364,6 +378,9 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
           if constexpr (OutTraits<OUT>::gaincomb) {
             // gain chains: 0 on S (where m_a = 0 too), m_a(x) at the candidate
             y = inS ? 0.0 : (cw[rl] == c ? in.ta : a.alpha * acc);
+            if constexpr (OutTraits<OUT>::cstore)
+              __builtin_nontemporal_store(gain_count(a, y, acc, cw[rl] == c),
+                                          a.Y32 + (size_t)r * C + c);
           } else {
             member = (tmw[rl] >> c) & 1ull;
             y = member ? in.ta : a.alpha * acc;
@@ -462,6 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   double y = epilogue<C, OUT>(a, r, c, acc);
+  if constexpr (OutTraits<OUT>::cstore)
+    a.Y32[(size_t)r * C + c] = gain_count(a, y, acc, a.cand_col[r] == c);
   if constexpr (OutTraits<OUT>::combine) {
     CombineFor<C, OUT> in;
     in.load(a, r, c);
@@ -572,6 +591,7 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     if constexpr (!WGT) {
       GED_CASE(IN_CNT32, OUT_GAIN32)
       GED_CASE(IN_CNT32, OUT_GAINCOMB32L)
+      GED_CASE(IN_CNT32, OUT_GAINCOMB32S)
       GED_CASE(IN_CNT32, OUT_GAIN32D)
       GED_CASE(IN_CNT32, OUT_GAIN)
       GED_CASE(IN_CNT32, OUT_GAINCOMB)

@@ -380,7 +380,7 @@ class Server:
 
 IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh", "cnt", "cnt32"]
 OUT_MODES = ["plain", "inj", "zero", "tile", "gain", "pool", "combine", "combine32", "gaincomb",
-             "tile32", "combine32l"]
+             "tile32", "combine32l", "gain32", "gaincomb32l", "zero32", "gain32d", "gaincomb32s"]
 KIND_BASE = 16  # a profile record's kind is input mode * KIND_BASE + output mode
 
 
