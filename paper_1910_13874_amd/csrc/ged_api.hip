@@ -170,6 +170,18 @@ static void ensure_levels(PrepCache &pc, int64_t n, int levels_needed, hipStream
   std::swap(pc.t_levels.bytes, nb.bytes);
 }
 
+// Sum of one step's single column, reduced straight into coherent host
+// memory (slot 1 of out_host; a single score's result takes slot 0), after
+// waiting for the stream.
+static double level_sum_to_host(ged_graph *g, const Partition &p, const StepArgs &a,
+                                hipStream_t st) {
+  g->out_host.ensure(64, hipHostMallocCoherent);
+  double *hw = g->out_host.as<double>() + 1;
+  launch_reduce(p, a, hw, nullptr, nullptr, st, g->pws.scratch());
+  GED_HIP(hipStreamSynchronize(st));
+  return *hw;
+}
+
 // t_i = alpha * A t_{i-1} with t_0 = 1; W[i] = sum_v t_i(v) = alpha^i sum_x omega_i(x).
 // Levels whose exact walk counts omega_i the graph already holds are written
 // as alpha^i omega_i with W_i from the integer sums (no step, no reduction, no
@@ -183,7 +195,6 @@ int prepare(ged_graph *g, double alpha, double eps) {
   const int64_t n = g->n;
   Partition &p = partition(g, 1);
   g->pws.fit(p);
-  g->levels.ensure(sizeof(double) * 64);
   pc.valid = false;
   pc.tr_r = -1;
   pc.W.clear();
@@ -214,9 +225,7 @@ int prepare(ged_graph *g, double alpha, double eps) {
     a.X = T + (size_t)(i - 1) * n;
     a.Y = T + (size_t)i * n;
     run_step(g, p, a, i == 1 ? IN_ONES : IN_VEC, OUT_PLAIN, st);
-    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st, g->pws.scratch());
-    GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    GED_HIP(hipStreamSynchronize(st));
+    W_host = level_sum_to_host(g, p, a, st);
     pc.W.push_back(W_host);
     const double B = comb_bound(g, alpha, W_host);
     if (B < eps) {
@@ -295,9 +304,7 @@ double walk_total(ged_graph *g, int ell) {
     a.X = pc.t_tail[pc.tail_cur].as<double>();
     a.Y = pc.t_tail[pc.tail_cur ^ 1].as<double>();
     run_step(g, p, a, IN_VEC, OUT_PLAIN, st);
-    launch_reduce(p, a, g->levels.as<double>(), nullptr, nullptr, st, g->pws.scratch());
-    GED_HIP(hipMemcpyAsync(&W_host, g->levels.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    GED_HIP(hipStreamSynchronize(st));
+    W_host = level_sum_to_host(g, p, a, st);
     pc.tail_cur ^= 1;
     pc.tail_level++;
     pc.W.push_back(W_host);
@@ -359,7 +366,7 @@ static void ensure_score_buffers(ged_graph *g, int s_len, hipStream_t st) {
   g->vec[1].ensure(sizeof(double) * (size_t)n);
   g->acc.ensure(sizeof(double) * 64);
   g->s_levels.ensure(sizeof(double) * (size_t)(g->prep.ell + 2));
-  g->out_host.ensure(64);
+  g->out_host.ensure(64, hipHostMallocCoherent);
   g->sws.fit(partition(g, 1));
   if (s_len > g->s_cap) {
     int cap = std::max(256, g->s_cap);

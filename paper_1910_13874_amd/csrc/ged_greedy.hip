@@ -253,13 +253,30 @@ __global__ void k_cand_set(int *cand_col, const int *cand, int nc, int value) {
   if (c < nc) cand_col[cand[c]] = value ? c : -1;
 }
 
+// A batch's candidates, passed by value (no host-to-device copy).
+struct CandList {
+  int v[64];
+};
+
+// cand[c] = the batch's c-th candidate, cand_col[candidate] = c.
+__global__ void k_cand_put(int *cand_col, int *cand, CandList cl, int nc) {
+  const int c = threadIdx.x;
+  if (c < nc) {
+    cand[c] = cl.v[c];
+    cand_col[cl.v[c]] = c;
+  }
+}
+
 // After a batch: remember the exact gains (valid upper bounds for any larger
 // S at this ell) and mark the candidates as evaluated in this round.
+// The gains also go to host_gains (coherent host memory, read by the host
+// after it waits for the stream).
 __global__ void k_after_batch(const int *cand, const double *gains, int nc, double *stale,
-                              double *ub, int *done, int round) {
+                              double *ub, int *done, int round, double *host_gains) {
   const int c = threadIdx.x;
   if (c < nc) {
     const int x = cand[c];
+    host_gains[c] = gains[c];
     stale[x] = gains[c];
     ub[x] = gains[c];
     done[x] = round;
@@ -503,25 +520,27 @@ static void chains_for(GreedyCtx &c, int ell) {
 static int select_topk(GreedyCtx &c, int K, int round, const int *sampled, int pick, double *hk,
                        int *hi) {
   const int chunk = kBlock * kTopE;
+  // the launch that leaves one block writes its K pairs straight into the
+  // coherent host buffer
+  double *sk = c.h_small.as<double>();
+  int *si = reinterpret_cast<int *>(sk + 64);
   int nb = (c.n + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_topk_ub, dim3(nb), dim3(kBlock), 0, c.st, c.ub.as<const double>(),
                      c.done.as<const int>(), round, sampled, pick, c.g->d_old_id.as<const int>(),
-                     c.n, K, c.topk_k[0].as<double>(), c.topk_i[0].as<int>());
+                     c.n, K, nb == 1 ? sk : c.topk_k[0].as<double>(),
+                     nb == 1 ? si : c.topk_i[0].as<int>());
   GED_HIP(hipGetLastError());
   int cur = 0, count = nb * K;
   while (nb > 1) {
     nb = (count + chunk - 1) / chunk;
     hipLaunchKernelGGL(k_topk_pairs, dim3(nb), dim3(kBlock), 0, c.st,
                        c.topk_k[cur].as<const double>(), c.topk_i[cur].as<const int>(), count, K,
-                       c.topk_k[cur ^ 1].as<double>(), c.topk_i[cur ^ 1].as<int>());
+                       nb == 1 ? sk : c.topk_k[cur ^ 1].as<double>(),
+                       nb == 1 ? si : c.topk_i[cur ^ 1].as<int>());
     GED_HIP(hipGetLastError());
     cur ^= 1;
     count = nb * K;
   }
-  double *sk = c.h_small.as<double>();
-  int *si = reinterpret_cast<int *>(sk + 64);
-  GED_HIP(hipMemcpyAsync(sk, c.topk_k[cur].p, sizeof(double) * K, hipMemcpyDeviceToHost, c.st));
-  GED_HIP(hipMemcpyAsync(si, c.topk_i[cur].p, sizeof(int) * K, hipMemcpyDeviceToHost, c.st));
   GED_HIP(hipStreamSynchronize(c.st));
   int m = 0;
   for (int q = 0; q < K; ++q) {
@@ -557,11 +576,11 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
   c.last_ell = -1;  // set below when the batch stores its levels as counts
   Partition &p = partition(g, C);
   c.wsC.fit(p);
-  int *hc = reinterpret_cast<int *>(c.h_small.as<char>() + 1024);
-  for (int q = 0; q < nc; ++q) hc[q] = cand[q];
-  GED_HIP(hipMemcpyAsync(c.cand_dev.p, hc, sizeof(int) * nc, hipMemcpyHostToDevice, c.st));
-  hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
-                     c.cand_dev.as<const int>(), nc, 1);
+  if (nc > 64) throw HipError{GED_ERR_ARG, "candidate batch larger than 64"};
+  CandList cl;
+  for (int q = 0; q < nc; ++q) cl.v[q] = cand[q];
+  hipLaunchKernelGGL(k_cand_put, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
+                     c.cand_dev.as<int>(), cl, nc);
   const double *M = c.m_levels.as<const double>();
   StepArgs a = base_args(g);
   c.wsC.into(a);
@@ -739,12 +758,11 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
   launch_reduce(*pr, a, c.gains.as<double>(), nullptr, nullptr, c.st, c.wsC.scratch());
   hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
                      c.cand_dev.as<const int>(), nc, 0);
+  double *hg = c.h_small.as<double>() + 256;
   hipLaunchKernelGGL(k_after_batch, dim3(1), dim3(64), 0, c.st, c.cand_dev.as<const int>(),
                      c.gains.as<const double>(), nc, c.stale.as<double>(), c.ub.as<double>(),
-                     c.done.as<int>(), round);
+                     c.done.as<int>(), round, hg);
   GED_HIP(hipGetLastError());
-  double *hg = c.h_small.as<double>() + 256;
-  GED_HIP(hipMemcpyAsync(hg, c.gains.p, sizeof(double) * nc, hipMemcpyDeviceToHost, c.st));
   GED_HIP(hipStreamSynchronize(c.st));
   for (int q = 0; q < nc; ++q) out[q] = hg[q];
   c.evals += nc;
@@ -811,7 +829,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.topk_i[0].ensure(sizeof(int) * (size_t)nb0 * K);
   c.topk_k[1].ensure(sizeof(double) * (size_t)nb0 * K);
   c.topk_i[1].ensure(sizeof(int) * (size_t)nb0 * K);
-  c.h_small.ensure(4096);
+  c.h_small.ensure(4096, hipHostMallocCoherent);
   launch_fill_i32(c.smask.as<int>(), 0, c.smask.bytes / sizeof(int), c.st);
   const bool track_sdeg = c.split && !g->weighted;
   if (track_sdeg) {

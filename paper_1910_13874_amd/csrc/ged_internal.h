@@ -67,27 +67,31 @@ struct DBuf {
   }
 };
 
-// Pinned host buffer (hipHostMalloc).
+// Pinned host buffer (hipHostMalloc).  With hipHostMallocCoherent kernels
+// may store results into it directly (uncached on the device side), so the
+// host reads them after waiting for the stream, without a copy.
 struct HBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  unsigned flags = hipHostMallocDefault;
   HBuf() = default;
   HBuf(const HBuf &) = delete;
   HBuf &operator=(const HBuf &) = delete;
   ~HBuf() {
     if (p) (void)hipHostFree(p);
   }
-  void ensure(size_t nbytes) {
-    if (nbytes <= bytes && p) return;
+  void ensure(size_t nbytes, unsigned fl = hipHostMallocDefault) {
+    if (nbytes <= bytes && p && fl == flags) return;
     if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
-    if (hipHostMalloc(&p, nbytes ? nbytes : 256, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&p, nbytes ? nbytes : 256, fl) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
       throw HipError{GED_ERR_NOMEM, "hipHostMalloc failed"};
     }
     bytes = nbytes ? nbytes : 256;
+    flags = fl;
   }
   template <class T>
   T *as() const {
@@ -364,7 +368,6 @@ struct ged_graph {
   ged::PrepCache prep;
   // precomputation workspace (C = 1 steps)
   ged::StepWs pws;
-  ged::DBuf levels;             // double [64] level sums
   // plain-score workspace
   ged::StepWs sws;
   ged::DBuf mask;               // uint32 [ceil(n/32)+1], all zero between calls

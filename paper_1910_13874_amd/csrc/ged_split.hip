@@ -974,8 +974,9 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   split_fit(g, g->split_ws, pl, 1, split_wl_need(g, deg_sum), st);
   // a fixed worklist grid, so the captured graph serves every group
   g->split_ws.wl_blocks = 256;
-  g->acc.ensure(sizeof(double) * 64);
-  g->out_host.ensure(64);
+  // the score is reduced straight into coherent host memory (no copy)
+  g->out_host.ensure(64, hipHostMallocCoherent);
+  double *ho = g->out_host.as<double>();
   const int cap = g->split_cap;
   char *hb = g->split_in_host.as<char>();
   int64_t offs[2] = {0, len};
@@ -994,18 +995,16 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   auto enqueue_main = [&]() {
     split_tile_push(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, tm, st);
     split_dense(g, w, pl, 1, tm, st);
-    split_tile_reduce(g, w, pl, 1, g->acc.as<double>(), st);
+    split_tile_reduce(g, w, pl, 1, ho, st);
   };
   auto enqueue_clear = [&]() {
     split_tile_clear(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, tm, st);
   };
   if (!g->score_done) GED_HIP(hipEventCreateWithFlags(&g->score_done, hipEventDisableTiming));
-  double *ho = g->out_host.as<double>();
   w.zero = false;
   try {
     if (g->prof.on) {
       enqueue_main();
-      GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
       GED_HIP(hipEventRecord(g->score_done, st));
       enqueue_clear();
     } else {
@@ -1016,7 +1015,7 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
           g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.wl3.p, w.wl3_n.p,
           (const void *)(uintptr_t)w.wl3_cap, (const void *)(intptr_t)pl.push3, w.ws.blk.p, w.ws.seg.p,
           w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
-          g->omega_lv.p, g->acc.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
+          g->omega_lv.p, g->out_host.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
           (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
           (const void *)(intptr_t)1 /* split */};
       SplitExec &x = g->split_exec[pl.push3 ? 1 : 0];
@@ -1027,7 +1026,6 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
         x.sig = sig;
       }
       GED_HIP(hipGraphLaunch(x.exec, st));
-      GED_HIP(hipMemcpyAsync(ho, g->acc.p, sizeof(double), hipMemcpyDeviceToHost, st));
       GED_HIP(hipEventRecord(g->score_done, st));
       GED_HIP(hipGraphLaunch(x.clear_exec, st));
     }
