@@ -258,13 +258,15 @@ struct CandList {
   int v[64];
 };
 
-// cand[c] = the batch's c-th candidate, cand_col[candidate] = c.
-__global__ void k_cand_put(int *cand_col, int *cand, CandList cl, int nc) {
+// cand[c] = the batch's c-th candidate, cand_col[candidate] = c; a non-null
+// wl_n (the batch's level-2 worklist) starts empty.
+__global__ void k_cand_put(int *cand_col, int *cand, CandList cl, int nc, unsigned *wl_n) {
   const int c = threadIdx.x;
   if (c < nc) {
     cand[c] = cl.v[c];
     cand_col[cl.v[c]] = c;
   }
+  if (wl_n && c == 0) *wl_n = 0;
 }
 
 // After a batch: remember the exact gains (valid upper bounds for any larger
@@ -317,21 +319,109 @@ __global__ __launch_bounds__(kBlock) void k_gain_level1(const int *__restrict__ 
 
 // The same level as unscaled 32-bit counts: 1 on N(x_c) outside S, and at the
 // candidate the number of its arcs from outside S, deg(x_c) - sdeg(x_c).
+// With wl (level 2 pushed), every vertex written here, the candidate
+// included, appends its chunks: they are the sources of level 2.
 __global__ __launch_bounds__(kBlock) void k_gain_level1_32(const int *__restrict__ rp,
                                                            const int *__restrict__ ci,
                                                            const uint32_t *__restrict__ smask,
                                                            const int *cand, int C,
                                                            const int *__restrict__ sdeg,
-                                                           uint32_t *d1, int clear) {
+                                                           uint32_t *d1, int clear, uint64_t *wl,
+                                                           unsigned *wl_n, unsigned wl_cap) {
   const int c = blockIdx.y;
   const int x = cand[c];
   const int k0 = rp[x], k1 = rp[x + 1];
-  for (int k = k0 + blockIdx.x * kBlock + (int)threadIdx.x; k < k1; k += gridDim.x * kBlock) {
-    const int v = ci[k];
-    if (v != x && !((smask[v >> 5] >> (v & 31)) & 1u)) d1[(size_t)v * C + c] = clear ? 0u : 1u;
+  for (int kb = k0 + blockIdx.x * kBlock; kb < k1; kb += gridDim.x * kBlock) {  // uniform trips
+    const int k = kb + (int)threadIdx.x;
+    unsigned nch = 0;
+    int v = 0;
+    if (k < k1) {
+      v = ci[k];
+      if (v != x && !((smask[v >> 5] >> (v & 31)) & 1u)) {
+        d1[(size_t)v * C + c] = clear ? 0u : 1u;
+        if (wl) nch = wl_chunks(rp, v);
+      }
+    }
+    if (wl) wl_append(wl, wl_n, wl_cap, v, c, nch);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     d1[(size_t)x * C + c] = clear ? 0u : (uint32_t)(k1 - k0 - sdeg[x]);
+    if (wl && k1 > k0) {
+      const unsigned nch = wl_chunks(rp, x);
+      const unsigned base = atomicAdd(wl_n, nch);
+      for (unsigned q = 0; q < nch; ++q)
+        if (base + q < wl_cap) wl[base + q] = wl_entry(x, c, q);
+    }
+  }
+}
+
+// Level 2 of a batch's gain chains as 32-bit counts by a push: each listed
+// source u (a level-1 vertex of column c) adds its level-1 count to its
+// neighbours outside S other than the candidate x_c, whose own entry is its
+// miss count (injc2[c]); the level is zero before.  The same integers the
+// dense step gathers.  A wave issues all loads of a chunk before their uses;
+// the adds return nothing.
+__global__ __launch_bounds__(kBlock) void k_gain_push2(const int *__restrict__ rp,
+                                                       const int *__restrict__ ci,
+                                                       const uint32_t *__restrict__ smask,
+                                                       const int *cand, int nc, int C,
+                                                       const uint32_t *d1, uint32_t *d2,
+                                                       const uint64_t *wl, const unsigned *wl_n,
+                                                       unsigned wl_cap,
+                                                       const double *__restrict__ injc2) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < nc)
+    d2[(size_t)cand[threadIdx.x] * C + threadIdx.x] = (uint32_t)injc2[threadIdx.x];
+  constexpr int U = kWlChunk / 64;
+  const unsigned count = min(*wl_n, wl_cap);
+  const int lane = threadIdx.x & 63;
+  const unsigned nwaves = (gridDim.x * kBlock) >> 6;
+  for (unsigned i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < count; i += nwaves) {
+    const uint64_t e = wl[i];
+    const int u = (int)(e >> 32);
+    const int c = (int)((e >> 24) & 0xffu);
+    const int q = (int)(e & 0xffffffu);
+    const int x = cand[c];
+    const int j0 = rp[u] + q * kWlChunk + lane, j1 = min(rp[u] + (q + 1) * kWlChunk, rp[u + 1]);
+    int w[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) w[k] = j0 + 64 * k < j1 ? ci[j0 + 64 * k] : -1;
+    bool ok[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      ok[k] = w[k] >= 0 && w[k] != x && !((smask[w[k] >> 5] >> (w[k] & 31)) & 1u);
+    const uint32_t val = d1[(size_t)u * C + c];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (ok[k]) atomicAdd(&d2[(size_t)w[k] * C + c], val);
+  }
+}
+
+// Zero what k_gain_push2 wrote for a batch (cand, nc, its worklist): the
+// candidates' entries and every neighbour of every listed source.
+__global__ __launch_bounds__(kBlock) void k_gain_clear2(const int *__restrict__ rp,
+                                                        const int *__restrict__ ci,
+                                                        const int *cand, int nc, int C,
+                                                        uint32_t *d2, const uint64_t *wl,
+                                                        const unsigned *wl_n, unsigned wl_cap) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < nc)
+    d2[(size_t)cand[threadIdx.x] * C + threadIdx.x] = 0u;
+  constexpr int U = kWlChunk / 64;
+  const unsigned count = min(*wl_n, wl_cap);
+  const int lane = threadIdx.x & 63;
+  const unsigned nwaves = (gridDim.x * kBlock) >> 6;
+  for (unsigned i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < count; i += nwaves) {
+    const uint64_t e = wl[i];
+    const int u = (int)(e >> 32);
+    const int c = (int)((e >> 24) & 0xffu);
+    const int q = (int)(e & 0xffffffu);
+    const int j0 = rp[u] + q * kWlChunk + lane, j1 = min(rp[u] + (q + 1) * kWlChunk, rp[u + 1]);
+    int w[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) w[k] = j0 + 64 * k < j1 ? ci[j0 + 64 * k] : -1;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (w[k] >= 0) d2[(size_t)w[k] * C + c] = 0u;
+  }
 }
 
 // Unscaled miss counts of the candidates, injc[i*C + c] = m_i(x_c) / alpha^i
@@ -372,6 +462,15 @@ struct GreedyCtx {
   // the last gain batch's candidates when its levels 2 .. a-1 are stored as
   // 32-bit counts for walk length last_ell (-1: none), and the column of the
   // vertex just added to S if it is one of them (-1: recompute the chain)
+  // gain level 2 by a push: worklist of its sources, and the state of the
+  // level-2 region of dlv (d2_buf): all zero, or holding the last batch's
+  // pushed level (kept until the next batch: a pick reads it) with that
+  // batch's size last_nc2
+  DBuf wl2, wl2_n;
+  unsigned wl2_cap = 0;
+  void *d2_buf = nullptr;
+  bool d2_zero = false, d2_pending = false;
+  int last_nc2 = 0;
   std::vector<int> last_cand;
   int last_ell = -1;
   bool last_top = false;  // ... and level a of the gain chains too (OUT_GAINCOMB32S)
@@ -577,10 +676,49 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
   Partition &p = partition(g, C);
   c.wsC.fit(p);
   if (nc > 64) throw HipError{GED_ERR_ARG, "candidate batch larger than 64"};
+  // Level 2 of 32-bit gain chains by a push from the level-1 vertices when
+  // the arcs it adds along are few: at most sum_x (omega_2(x) + deg(x)) <=
+  // nnz/8 (the dense step gathers every arc; the push's adds are scattered
+  // and contend at hubs: on BA-1M a push at that size takes a third of the
+  // gather).  Its sources are N(x) outside S and x, so the
+  // worklist needs at most sum (deg(x) + 1) + that sum / 512 + 1 entries.
+  bool push2 = false;
+  size_t wl2_need = 0;
+  if (c.split && (ell + 1) / 2 >= 3 && g->simple && !g->weighted && gains32(c, ell)) {
+    const std::vector<double> &om2 = omega2_host(g, c.st);
+    double vol = 0.0;
+    size_t src = 0;
+    for (int q = 0; q < nc; ++q) {
+      const int d = g->h_rp[cand[q] + 1] - g->h_rp[cand[q]];
+      vol += om2[(size_t)cand[q]] + d;
+      src += (size_t)d + 1;
+    }
+    push2 = vol <= (double)(g->nnz / 8);
+    wl2_need = src + (size_t)(vol / kWlChunk) + 1;
+  }
+  if (c.d2_buf != c.dlv.p) c.d2_zero = c.d2_pending = false;
+  if (c.d2_pending && push2) {  // zero what the last batch pushed (its candidates are in cand_dev)
+    hipLaunchKernelGGL(k_gain_clear2, dim3(std::min(4096, std::max(64, (int)(c.wl2_cap / 4)))),
+                       dim3(kBlock), 0, c.st, g->rp.as<const int>(), g->ci.as<const int>(),
+                       c.cand_dev.as<const int>(), c.last_nc2, C, c.dlv.as<uint32_t>() + (size_t)n * C,
+                       c.wl2.as<const uint64_t>(), c.wl2_n.as<const unsigned>(), c.wl2_cap);
+    GED_HIP(hipGetLastError());
+    c.d2_zero = true;
+  }
+  c.d2_pending = false;
+  if (push2) {
+    if (wl2_need > c.wl2_cap || !c.wl2.p) {
+      const size_t cap = std::min<size_t>(std::max<size_t>(wl2_need, 2 * (size_t)c.wl2_cap),
+                                          0xffffffffu);
+      c.wl2.ensure(sizeof(uint64_t) * cap);
+      c.wl2_cap = (unsigned)cap;
+    }
+    c.wl2_n.ensure(sizeof(unsigned));
+  }
   CandList cl;
   for (int q = 0; q < nc; ++q) cl.v[q] = cand[q];
   hipLaunchKernelGGL(k_cand_put, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
-                     c.cand_dev.as<int>(), cl, nc);
+                     c.cand_dev.as<int>(), cl, nc, push2 ? c.wl2_n.as<unsigned>() : nullptr);
   const double *M = c.m_levels.as<const double>();
   StepArgs a = base_args(g);
   c.wsC.into(a);
@@ -601,6 +739,11 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
     if (la > 1) c.dlv.ensure((size_t)eb * nC * (size_t)(la - 1 + (top_a ? 1 : 0)));
     double *dl = c.dlv.as<double>();
     uint32_t *dl32 = c.dlv.as<uint32_t>();
+    if (c.dlv.p != c.d2_buf) {
+      c.d2_buf = c.dlv.p;
+      c.d2_zero = false;
+    }
+    if (push2 && !c.d2_zero) launch_fill_i32(c.dlv.as<int>() + nC, 0, nC, c.st);
     const double *any = c.Mr.as<const double>();
     // level 1 by a push from the candidates when each neighbour is one walk
     const bool push1 = la > 1 && g->simple && !g->weighted;
@@ -615,7 +758,8 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       if (g32)
         hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
                            a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dl32,
-                           0);
+                           0, push2 ? c.wl2.as<uint64_t>() : nullptr,
+                           push2 ? c.wl2_n.as<unsigned>() : nullptr, c.wl2_cap);
       else
         hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
                            a.smask, c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 0);
@@ -632,6 +776,17 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
         hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
                            c.cand_dev.as<const int>(), nc, C, g->prep.alpha, la - 1,
                            c.injc.as<double>());
+      if (push2) {  // injc (level 2) is ready
+        hipLaunchKernelGGL(k_gain_push2, dim3(std::min(4096, std::max(64, (int)(wl2_need / 4)))),
+                           dim3(kBlock), 0, c.st, a.rp, a.ci, a.smask, c.cand_dev.as<const int>(),
+                           nc, C, dl32, dl32 + nC, c.wl2.as<const uint64_t>(),
+                           c.wl2_n.as<const unsigned>(), c.wl2_cap,
+                           c.injc.as<const double>() + (size_t)2 * C);
+        GED_HIP(hipGetLastError());
+        c.d2_pending = true;
+        c.last_nc2 = nc;
+      }
+      c.d2_zero = false;  // pushed (cleared by the next batch) or gathered
       if (la > 2) {
         c.last_cand.assign(cand, cand + nc);
         c.last_ell = ell;
@@ -641,6 +796,7 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       for (int i = 1; i < la; ++i) alpha_a *= g->prep.alpha;
       for (int i = 2; i <= la; ++i) {
         a.Xc32 = dl32 + (size_t)(i - 2) * nC;
+        if (i == 2 && push2) continue;
         if (i < la) {
           a.alpha = 1.0;
           a.injc = c.injc.as<const double>() + (size_t)i * C;
@@ -685,7 +841,8 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
         if (c.dc1_zeroed != c.dc32.p) launch_fill_i32(c.dc32.as<int>(), 0, nC, c.st);
         c.dc1_zeroed = nullptr;
         hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
-                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 0);
+                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 0,
+                           (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
         GED_HIP(hipGetLastError());
         c.injc.ensure(sizeof(double) * (size_t)(la + 1) * C);
         hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
@@ -729,7 +886,8 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       }
       if (p32) {
         hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
-                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 1);
+                           a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 1,
+                           (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
         GED_HIP(hipGetLastError());
         c.dc1_zeroed = c.dc32.p;
       }
@@ -738,7 +896,7 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       if (g32)
         hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
                            a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dl32,
-                           1);
+                           1, (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
       else
         hipLaunchKernelGGL(k_gain_level1, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
                            a.smask, c.cand_dev.as<const int>(), C, a.alpha, M + (size_t)n, dl, 1);
@@ -812,6 +970,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.rounds = 0;
   c.last_ell = -1;  // nothing of an earlier call is reused
   c.sub_col = -1;
+  c.d2_zero = c.d2_pending = false;
   const int K = c.C + 1;
   c.smask.ensure(sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1));
   c.ub.ensure(sizeof(double) * n);

@@ -99,6 +99,49 @@ struct HBuf {
   }
 };
 
+// ------------------------------------------------------------ worklists --
+// Push kernels walk lists of (vertex, column, chunk) entries, one wavefront
+// per chunk of at most kWlChunk arcs.
+
+constexpr int kWlChunk = 512;  // arcs per worklist entry (one wavefront)
+
+// Exclusive prefix sum over the 64 lanes of a wavefront (all lanes active).
+__device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) {
+  const int lane = threadIdx.x & 63;
+  unsigned x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// Worklist entry: chunk q of vertex y's arcs, column c.
+__device__ __forceinline__ uint64_t wl_entry(int y, int c, unsigned q) {
+  return ((uint64_t)(unsigned)y << 32) | ((uint64_t)c << 24) | q;
+}
+
+__device__ __forceinline__ unsigned wl_chunks(const int *rp, int y) {
+  return (unsigned)((rp[y + 1] - rp[y] + kWlChunk - 1) / kWlChunk);
+}
+
+// Each lane appends its nch entries for vertex y (all lanes of the wave
+// call this together): one atomic per wave.  Entries past cap are dropped;
+// every caller sizes cap so that none is.
+__device__ __forceinline__ void wl_append(uint64_t *wl, unsigned *wl_n, unsigned cap, int y, int c,
+                                          unsigned nch) {
+  unsigned total;
+  const unsigned ex = wave_excl_scan(nch, &total);
+  unsigned base = 0;
+  if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(wl_n, total);
+  base = __shfl(base, 63, 64);
+  for (unsigned q = 0; q < nch; ++q) {
+    const unsigned at = base + ex + q;
+    if (at < cap) wl[at] = wl_entry(y, c, q);
+  }
+}
+
 // ------------------------------------------------------ work partitioning --
 
 // Launch geometry shared by every walk-count step kernel.
@@ -400,6 +443,8 @@ struct ged_graph {
   int omax_top = 2, omax_fit = 2;
   // deg(v) + omega_2(v) + omega_3(v) on the host (single-group level-3 push)
   std::vector<double> push_bound;
+  // omega_2(v) on the host (push volumes decided before launch)
+  std::vector<double> h_omega2;
   // omega_sum[i] = sum_v omega_i(v) for i = 1 .. (2 once omega2 is ready, then
   // omega_top once omega_lv holds levels 3..); exact for levels that fit 2^32
   std::vector<double> omega_sum;
@@ -466,6 +511,8 @@ void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st);
 // for L <= 2).  Computes the maxima by the integer chain the first time a
 // level is asked for (synchronizes the stream once); stores no levels.
 int omega_fit_level(ged_graph *g, int L, hipStream_t st);
+// omega_2 as a host array (built on first use; synchronizes the stream then).
+const std::vector<double> &omega2_host(ged_graph *g, hipStream_t st);
 // Walk-count levels of the precomputation from the graph's exact integer
 // counts omega_i (unweighted graphs): omega_prefix_levels gives how many
 // levels those counts are held for (0 for weighted graphs);

@@ -39,7 +39,6 @@
 
 namespace ged {
 
-constexpr int kWlChunk = 512;   // arcs per worklist entry (one wavefront)
 constexpr int kPushGrid = 2048; // blocks of the member kernels (grid-stride)
 // Blocks of the worklist kernels (4 waves each, grid-stride over the entries):
 // about one wave per expected entry, between kWlGridMin and kWlGridMax.
@@ -76,43 +75,6 @@ size_t split_wl_need(const ged_graph *g, int64_t deg_sum) {
 }
 
 // --------------------------------------------------------------- kernels --
-
-// Exclusive prefix sum over the 64 lanes of a wavefront (all lanes active).
-__device__ __forceinline__ unsigned wave_excl_scan(unsigned v, unsigned *total) {
-  const int lane = threadIdx.x & 63;
-  unsigned x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  *total = __shfl(x, 63, 64);
-  return x - v;
-}
-
-// Worklist entry: chunk q of vertex y's arcs, column c.
-__device__ __forceinline__ uint64_t wl_entry(int y, int c, unsigned q) {
-  return ((uint64_t)(unsigned)y << 32) | ((uint64_t)c << 24) | q;
-}
-
-__device__ __forceinline__ unsigned wl_chunks(const int *rp, int y) {
-  return (unsigned)((rp[y + 1] - rp[y] + kWlChunk - 1) / kWlChunk);
-}
-
-// Each lane appends its nch entries for vertex y (all lanes of the wave
-// call this together): one atomic per wave; entries past cap are dropped
-// while the length keeps counting, so the reader sees the overflow.
-__device__ __forceinline__ void wl_append(uint64_t *wl, unsigned *wl_n, unsigned cap, int y, int c,
-                                          unsigned nch) {
-  unsigned total;
-  const unsigned ex = wave_excl_scan(nch, &total);
-  unsigned base = 0;
-  if ((threadIdx.x & 63) == 63 && total) base = atomicAdd(wl_n, total);
-  base = __shfl(base, 63, 64);
-  for (unsigned q = 0; q < nch; ++q) {
-    const unsigned at = base + ex + q;
-    if (at < cap) wl[at] = wl_entry(y, c, q);
-  }
-}
 
 // Members of groups g0 .. g0+nc-1, one block per member: level-1 counts, the
 // level-2 contributions of paths through the member, and worklist entries for
@@ -579,27 +541,42 @@ static size_t push3_cap(const ged_graph *g) {
   return (size_t)std::min<int64_t>(v + v / kWlChunk + 2, 0xffffffffll);
 }
 
+const std::vector<double> &omega2_host(ged_graph *g, hipStream_t st) {
+  if (g->h_omega2.size() == (size_t)g->n) return g->h_omega2;
+  const size_t n = (size_t)g->n;
+  {
+    std::lock_guard<std::mutex> lk(g_omega_mu);
+    ensure_omega2(g, st);
+  }
+  std::vector<unsigned long long> om2(n);
+  GED_HIP(hipMemcpyAsync(om2.data(), g->omega2.p, sizeof(unsigned long long) * n,
+                         hipMemcpyDeviceToHost, st));
+  GED_HIP(hipStreamSynchronize(st));
+  std::vector<double> h(n);
+  for (size_t v = 0; v < n; ++v) h[v] = (double)om2[v];
+  g->h_omega2.swap(h);
+  return g->h_omega2;
+}
+
 // Host table of deg(v) + omega_2(v) + omega_3(v), which bounds the degrees
 // added by the sources v contributes: its neighbours (2-walks from v) and the
 // ends of its 2-walks (3-walks); members count themselves (deg).
 static void ensure_push_bound(ged_graph *g, hipStream_t st) {
   if (g->push_bound.size() == (size_t)g->n) return;
   const size_t n = (size_t)g->n;
-  std::vector<unsigned long long> om2(n);
+  const std::vector<double> &om2 = omega2_host(g, st);
   std::vector<double> om3(n);
   const void *lv;
   {
     std::lock_guard<std::mutex> lk(g_omega_mu);
     lv = g->omega_lv.p;  // a replaced table stays allocated with the graph
   }
-  GED_HIP(hipMemcpyAsync(om2.data(), g->omega2.p, sizeof(unsigned long long) * n,
-                         hipMemcpyDeviceToHost, st));
   GED_HIP(hipMemcpyAsync(om3.data(), lv, sizeof(double) * n, hipMemcpyDeviceToHost,
                          st));  // omega_3 is level 0 of the table
   GED_HIP(hipStreamSynchronize(st));
   std::vector<double> b(n);
   for (size_t v = 0; v < n; ++v)
-    b[v] = (double)(g->h_rp[v + 1] - g->h_rp[v]) + (double)om2[v] + om3[v];
+    b[v] = (double)(g->h_rp[v + 1] - g->h_rp[v]) + om2[v] + om3[v];
   g->push_bound.swap(b);
 }
 
