@@ -459,9 +459,6 @@ struct GreedyCtx {
   void *dc1_zeroed = nullptr; // dc32 allocation whose level 1 is known to be all zero
   int g32_ell = -1;           // walk length g32_ok was decided for
   bool g32_ok = false;        // gain levels as 32-bit counts at g32_ell
-  // the last gain batch's candidates when its levels 2 .. a-1 are stored as
-  // 32-bit counts for walk length last_ell (-1: none), and the column of the
-  // vertex just added to S if it is one of them (-1: recompute the chain)
   // gain level 2 by a push: worklist of its sources, and the state of the
   // level-2 region of dlv (d2_buf): all zero, or holding the last batch's
   // pushed level (kept until the next batch: a pick reads it) with that
@@ -471,9 +468,14 @@ struct GreedyCtx {
   void *d2_buf = nullptr;
   bool d2_zero = false, d2_pending = false;
   int last_nc2 = 0;
+  // the last gain batch's candidates when it left gain levels 2 ..
+  // last_levels as 32-bit counts at last_src (level i at (i-1)*n*C) for walk
+  // length last_ell (-1: none), and the column of the vertex just added to S
+  // if it is one of them (-1: recompute the chain)
   std::vector<int> last_cand;
   int last_ell = -1;
-  bool last_top = false;  // ... and level a of the gain chains too (OUT_GAINCOMB32S)
+  int last_levels = 0;
+  const uint32_t *last_src = nullptr;
   int sub_col = -1;
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
@@ -528,14 +530,14 @@ static void miss_chains(GreedyCtx &c, int ell) {
   // counts and stores FP64; later levels continue the FP64 chain
   const int top32 = miss32_top(c, ell);
   const bool m32 = top32 >= 2;
-  // right after a pick from the last gain batch: levels 2 .. ell-1 (and ell
-  // when the batch stored its top level) by subtracting the new member's
-  // stored gain levels (all counts)
+  // right after a pick from the last gain batch: levels 2 .. sub_top by
+  // subtracting the new member's stored gain counts (levels whose miss
+  // values are counts too); the rest gather from the level-sub_top counts
   const int sub = c.sub_col;
   c.sub_col = -1;
-  const bool by_sub = sub >= 0 && m32 && top32 >= ell - 1 && ell >= 3 &&
-                      g->flags != GED_DIRECTED && c.split && !g->weighted;
-  const int sub_top = by_sub && c.last_top && top32 >= ell ? ell : ell - 1;
+  const int sub_top = std::min({ell, c.last_levels, top32});
+  const bool by_sub = sub >= 0 && m32 && sub_top >= 2 && g->flags != GED_DIRECTED && c.split &&
+                      !g->weighted;
   if (m32) c.mc32.ensure(2 * sizeof(uint32_t) * (size_t)n);
   uint32_t *mc = c.mc32.as<uint32_t>();
   for (int dir = 0; dir < (g->flags == GED_DIRECTED ? 2 : 1); ++dir) {
@@ -554,7 +556,7 @@ static void miss_chains(GreedyCtx &c, int ell) {
       i0 = 2;
       if (by_sub) {
         hipLaunchKernelGGL(k_miss_sub, dim3(std::min(8192, (n + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, c.st, L, n, c.dlv.as<const uint32_t>(), c.C, sub,
+                           dim3(kBlock), 0, c.st, L, n, c.last_src, c.C, sub,
                            sub_top, g->prep.alpha, mc + (size_t)(sub_top & 1) * n);
         GED_HIP(hipGetLastError());
         i0 = sub_top + 1;
@@ -790,7 +792,8 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       if (la > 2) {
         c.last_cand.assign(cand, cand + nc);
         c.last_ell = ell;
-        c.last_top = top_a;
+        c.last_src = dl32;
+        c.last_levels = top_a ? la : la - 1;
       }
       double alpha_a = g->prep.alpha;
       for (int i = 1; i < la; ++i) alpha_a *= g->prep.alpha;
@@ -890,6 +893,12 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
                            (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
         GED_HIP(hipGetLastError());
         c.dc1_zeroed = c.dc32.p;
+        // level 2 stays as counts until the next batch: a pick from this
+        // batch subtracts it from the miss chain
+        c.last_cand.assign(cand, cand + nc);
+        c.last_ell = ell;
+        c.last_src = dc;
+        c.last_levels = 2;
       }
     }
     if (push1) {
