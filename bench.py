@@ -21,6 +21,8 @@ Workloads (a "step" is one pass of the hot path over one batch of input):
   batch   Barabasi-Albert n=2,000,000, m=8: 4,096 groups (|S| ~ U[1,200])
           scored batched vs 4,096 sequential single-group calls.
   serve   request stream over 8 resident graphs (see paper_1910_13874_amd/serve.py).
+  variants  directed graphs, arc weights, the spectral bound and the stochastic
+          greedy on ~10^5-vertex graphs, each beside the oracle.
 """
 import argparse
 import hashlib
@@ -284,13 +286,109 @@ def bench_batch(args, torch, ged, inputs):
     return out
 
 
+def bench_variants(args, torch, ged, inputs, k=10, n_scores=16):
+    """The paper's variants beside the undirected unweighted path -- directed
+    graphs, arc weights, the spectral tail bound, the stochastic greedy --
+    each on a graph of about 10^5 vertices: 16 scores (|S| = 5) and a greedy
+    (k = 10) timed on the GPU with the dominant step kernel's roofline, and
+    the oracle on the same calls (two of the scores, the whole greedy) on this
+    host's cores, one call per core."""
+    import oracle
+
+    def directed_rmat():
+        u = inputs.rmat(17, 8, seed=21)
+        src = np.repeat(np.arange(u.n, dtype=np.int64), np.diff(u.row_ptr))
+        dst = u.col_idx.astype(np.int64)
+        # one orientation per undirected edge, chosen by a hash of the pair
+        lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+        flip = ((lo * 2654435761 + hi * 40503) >> 7) & 1
+        keep = src == np.where(flip == 1, lo, hi)
+        return inputs.from_edges(u.n, src[keep], dst[keep], symmetrize=False, name="rmat17_dir")
+
+    ba = inputs.barabasi_albert(100000, 5, 33)
+    deg = np.diff(ba.row_ptr).astype(np.float64)
+    rows = np.repeat(np.arange(ba.n), np.diff(ba.row_ptr))
+    w = 1.0 / np.sqrt(deg[rows] * deg[ba.col_idx])
+    gd = directed_rmat()
+    rev = inputs.reverse(gd)
+    cases = {"directed": (gd, None, "combinatorial"), "weighted": (ba, w, "combinatorial"),
+             "spectral": (ba, None, "spectral"), "stochastic": (ba, None, "combinatorial")}
+    res, edges, wall = {}, 0.0, 0.0
+    for name, (g, wt, bound) in cases.items():
+        log(f"variant {name}: n={g.n} nnz={g.nnz}")
+        gg = ged.GedGraph.from_graph(g, weights=wt)
+        stream = torch.cuda.Stream()
+        gg.set_stream(stream)
+        sigma = None
+        if bound == "spectral":
+            gg.set_tail_bound("spectral")
+            sigma = gg.sigma_max()
+            alpha = 0.5 / sigma
+        elif wt is not None:
+            alpha = 0.5 / oracle.max_weighted_out_degree(g, wt)
+        else:
+            alpha = gg.default_alpha()
+        groups = [inputs.group(g.n, 5, 2000 + j) for j in range(n_scores)]
+        if name == "stochastic":
+            run_greedy = lambda: gg.greedy_stochastic(k, alpha, EPS, eta=0.1, seed=1)
+            run_oracle = lambda: oracle.greedy(g, k, alpha, EPS, stochastic=True, eta=0.1, seed=1)
+        else:
+            run_greedy = lambda: gg.greedy(k, alpha, EPS)
+            run_oracle = lambda: oracle.greedy(g, k, alpha, EPS, rev=rev if g.directed else None,
+                                               w=wt, w_rev=wt, sigma=sigma)
+        gg.score(groups[0], alpha, EPS)  # warm-up: precompute, tables, kernels
+        run_greedy()
+        torch.cuda.synchronize()
+        gg.profile_enable(True)
+        t0 = time.perf_counter()
+        scores = [gg.score(S, alpha, EPS) for S in groups]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rg = run_greedy()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prof = gg.profile_read()
+        gg.profile_enable(False)
+        edges += prof["edges"]
+        wall += t2 - t0
+        t = time.perf_counter()
+        oscores = [oracle.score(g, S, alpha, EPS, w=wt, sigma=sigma)[0] for S in groups[:2]]
+        o_score = (time.perf_counter() - t) / 2
+        t = time.perf_counter()
+        ro = run_oracle()
+        o_greedy = time.perf_counter() - t
+        rel = max(abs(a - b) / max(abs(a), abs(b), 1e-300) for a, b in zip(scores, oscores))
+        res[name] = {
+            "graph": g.name, "n": g.n, "nnz": g.nnz, "alpha": alpha,
+            "score_ms": (t1 - t0) / n_scores * 1e3, "greedy_ms": (t2 - t1) * 1e3,
+            "greedy_ells": [int(x) for x in rg["ell"]],
+            "roofline": roofline(prof, ged, "variants"),
+            "oracle_score_s": o_score, "oracle_greedy_s": o_greedy,
+            "scores_max_rel_vs_oracle": rel,
+            "greedy_same_as_oracle": list(rg["group"]) == list(ro["group"]),
+        }
+        log(f"variant {name}: score {res[name]['score_ms']:.3f} ms, greedy "
+            f"{res[name]['greedy_ms']:.1f} ms; oracle {o_score:.2f} s / {o_greedy:.1f} s")
+        gg.close()
+    return {
+        "metric": METRIC, "value": edges / wall / 1e9, "unit": "GTEPS", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "paper variants: directed R-MAT s17 ef8, weighted BA n=1e5 "
+                               "m=5 (D^-1/2 A D^-1/2), spectral bound and stochastic greedy "
+                               "(eta=0.1) on BA n=1e5 m=5; 16 scores |S|=5 + greedy k=10 each",
+                   "parallelism": "single GPU"},
+        "variants": res, "host": host_cpu(),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ba1m",
-                    choices=["ba1m", "rmat22", "er1k", "batch", "serve"])
+                    choices=["ba1m", "rmat22", "er1k", "batch", "serve", "variants"])
     ap.add_argument("--groups", type=int, default=4096)
     ap.add_argument("--tile", type=int, default=0, help="batch: fix the tile width (0 = autotune)")
     ap.add_argument("--seq-sample", type=int, default=4096)
@@ -323,6 +421,8 @@ def main():
         del a, b
     if args.workload == "batch":
         out = bench_batch(args, torch, ged, inputs)
+    elif args.workload == "variants":
+        out = bench_variants(args, torch, ged, inputs)
     elif args.workload == "serve":
         from paper_1910_13874_amd import serve
         out = serve.bench(args, torch, ged, inputs, METRIC)
