@@ -797,3 +797,28 @@ def test_spectral_bound(ged, name):
     with pytest.raises(ged.GedError):
         gg.score([0], alpha, EPS)
     gg.close()
+
+
+def test_keep_order_parity(ged):
+    """A handle that keeps the caller's vertex order (no degree relabelling):
+    single scores (pushed and gathered third levels), a batch and the greedy
+    against the oracle, and against a relabelled handle."""
+    g = GRAPHS["ba20k"]()
+    alpha = g.default_alpha()
+    kept = ged.GedGraph.from_graph(g, keep_order=True)
+    relab = ged.GedGraph.from_graph(g)
+    vb = push3_vertex_bounds(g)
+    low = np.argsort(vb, kind="stable")
+    groups = [low[:1].astype(np.int32), low[:4].astype(np.int32), inputs.group(g.n, 5, 31),
+              inputs.group(g.n, 60, 32), inputs.group(g.n, 700, 33)]
+    for eps in (1e-2, 1e-7):
+        for S in groups:
+            s = check_score(kept, g, S, alpha, eps, tag=("kept", eps, len(S)))
+            assert rel(s, relab.score(S, alpha, eps)) <= 1e-12
+        off = np.concatenate([[0], np.cumsum([len(S) for S in groups])]).astype(np.int64)
+        b = kept.score_batch(off, np.concatenate(groups).astype(np.int32), alpha, eps)
+        for j, S in enumerate(groups):
+            assert rel(b[j], kept.score(S, alpha, eps)) <= 1e-12
+    compare_greedy(kept.greedy(8, alpha, EPS), oracle.greedy(g, 8, alpha, EPS), "kept order")
+    kept.close()
+    relab.close()
