@@ -126,13 +126,64 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
   }
 }
 
+// Member rows hold the unrestricted counts: deg(s), omega_2(s) and, for a
+// pushed level 3, omega_3(s) (om3, exact integers as doubles).  members ==
+// nullptr: nothing to do.
+template <class CT>
+struct MemberFix {
+  const int *rp = nullptr;
+  const unsigned long long *omega2 = nullptr;
+  const int64_t *offsets = nullptr;
+  const int *members = nullptr, *mcol = nullptr;
+  int g0 = 0, nc = 0, C = 1;
+  CT *cnt1 = nullptr, *cnt2 = nullptr, *lv3 = nullptr;
+  const double *om3 = nullptr;
+};
+
+// All threads of the launch, grid-stride over the members.
+template <class CT>
+__device__ __forceinline__ void fix_members(const MemberFix<CT> &f) {
+  if (!f.members) return;
+  const int64_t jb = f.offsets[f.g0], je = f.offsets[f.g0 + f.nc];
+  for (int64_t j = jb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < je;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int s = f.members[j];
+    const size_t o = (size_t)s * f.C + (f.mcol[j] - f.g0);
+    f.cnt1[o] = (CT)(f.rp[s + 1] - f.rp[s]);
+    if (f.cnt2) f.cnt2[o] = (CT)f.omega2[s];
+    if (f.lv3) f.lv3[o] = (CT)f.om3[s];
+  }
+}
+
+// Zero dst at the targets of one worklist entry (one wavefront, all loads
+// of the chunk issued first).
+template <class CT>
+__device__ __forceinline__ void clear_entry(const int *__restrict__ rp,
+                                            const int *__restrict__ ci, int C, CT *dst,
+                                            uint64_t e) {
+  constexpr int U = kWlChunk / 64;
+  const int lane = threadIdx.x & 63;
+  const int y = (int)(e >> 32);
+  const int c = (int)((e >> 24) & 0xffu);
+  const int q = (int)(e & 0xffffffu);
+  const int j0 = rp[y] + q * kWlChunk + lane, j1 = min(rp[y] + (q + 1) * kWlChunk, rp[y + 1]);
+  int x[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) x[k] = j0 + 64 * k < j1 ? ci[j0 + 64 * k] : -1;
+#pragma unroll
+  for (int k = 0; k < U; ++k)
+    if (x[k] >= 0) dst[(size_t)x[k] * C + c] = 0;
+}
+
 // Worklist entries, one wavefront each: src(y) (the next lower level's
 // count) goes to dst at every x in one chunk of N(y) outside the group
 // (member rows are overwritten with the unrestricted counts afterwards, and a
 // member hub would take one contended atomic per neighbour); with wl_next,
 // each x whose dst count is first touched appends its entries there.  CLEAR
 // stores zeros instead.  NEXT: wl_next is used (the adds return the old
-// count); otherwise the adds return nothing and the wave does not wait.
+// count); otherwise the adds return nothing and the wave does not wait.  The
+// level-2 push also fixes the member rows (fx): it neither reads nor writes
+// them, and the member pushes before it have finished.
 template <class CT, bool CLEAR, bool NEXT>
 __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
                                                     const int *__restrict__ ci, int C,
@@ -140,7 +191,8 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
                                                     const unsigned *wl_n, unsigned wl_cap,
                                                     const uint64_t *__restrict__ tmask,
                                                     uint64_t *wl_next, unsigned *wl_next_n,
-                                                    unsigned wl_next_cap) {
+                                                    unsigned wl_next_cap, MemberFix<CT> fx) {
+  fix_members(fx);
   const unsigned count = min(*wl_n, wl_cap);  // capacities are sized to never overflow
   // A chunk is at most U arcs per lane: every col_idx load of the chunk is
   // issued before the first use, then every tmask load, then every add, so a
@@ -153,16 +205,14 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
     const int y = (int)(e >> 32);
     const int c = (int)((e >> 24) & 0xffu);
     const int q = (int)(e & 0xffffffu);
+    if (CLEAR) {
+      clear_entry(rp, ci, C, dst, e);
+      continue;
+    }
     const int j0 = rp[y] + q * kWlChunk + lane, j1 = min(rp[y] + (q + 1) * kWlChunk, rp[y + 1]);
     int x[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) x[k] = j0 + 64 * k < j1 ? ci[j0 + 64 * k] : -1;
-    if (CLEAR) {
-#pragma unroll
-      for (int k = 0; k < U; ++k)
-        if (x[k] >= 0) dst[(size_t)x[k] * C + c] = 0;
-      continue;
-    }
     bool out[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) out[k] = x[k] >= 0 && !((tmask[x[k]] >> c) & 1ull);
@@ -196,22 +246,28 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
   }
 }
 
-// Member rows hold the unrestricted counts: deg(s), omega_2(s) and, for a
-// pushed level 3, omega_3(s) (om3, exact integers as doubles).
+// The member rows alone (tiles without a level-2 push).
 template <class CT>
-__global__ void k_fix_members(const int *__restrict__ rp,
-                              const unsigned long long *__restrict__ omega2,
-                              const int64_t *offsets, const int *members, const int *mcol,
-                              int g0, int nc, int C, CT *cnt1, CT *cnt2, CT *lv3,
-                              const double *__restrict__ om3) {
-  const int64_t jb = offsets[g0], je = offsets[g0 + nc];
-  for (int64_t j = jb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < je;
-       j += (int64_t)gridDim.x * blockDim.x) {
-    const int s = members[j];
-    const size_t o = (size_t)s * C + (mcol[j] - g0);
-    cnt1[o] = (CT)(rp[s + 1] - rp[s]);
-    if (cnt2) cnt2[o] = (CT)omega2[s];
-    if (lv3) lv3[o] = (CT)om3[s];
+__global__ void k_fix_members(MemberFix<CT> fx) {
+  fix_members(fx);
+}
+
+// Zero dst_a at every target of list a's entries and dst_b at every target
+// of list b's (a single score's pushed levels 2 and 3): one launch.
+template <class CT>
+__global__ __launch_bounds__(kBlock) void k_clear_two(const int *__restrict__ rp,
+                                                      const int *__restrict__ ci, int C,
+                                                      CT *dst_a, const uint64_t *wl_a,
+                                                      const unsigned *n_a, unsigned cap_a,
+                                                      CT *dst_b, const uint64_t *wl_b,
+                                                      const unsigned *n_b, unsigned cap_b) {
+  const unsigned ca = min(*n_a, cap_a), cb = min(*n_b, cap_b);
+  const unsigned nwaves = (gridDim.x * kBlock) >> 6;
+  for (unsigned i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < ca + cb; i += nwaves) {
+    if (i < ca)
+      clear_entry(rp, ci, C, dst_a, wl_a[i]);
+    else
+      clear_entry(rp, ci, C, dst_b, wl_b[i - ca]);
   }
 }
 
@@ -648,28 +704,39 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
                      mcol, g0, nc, C, c1, c2, w.wl.as<uint64_t>(), w.wl_n.as<unsigned>(),
                      w.wl_cap, wl3, wl3_n, w.wl3_cap);
   GED_HIP(hipGetLastError());
-  if (c2) {
+  MemberFix<CT> fx;
+  fx.rp = rp;
+  fx.omega2 = g->omega2.as<const unsigned long long>();
+  fx.offsets = offs;
+  fx.members = mem;
+  fx.mcol = mcol;
+  fx.g0 = g0;
+  fx.nc = nc;
+  fx.C = C;
+  fx.cnt1 = c1;
+  fx.cnt2 = c2;
+  fx.lv3 = l3;
+  fx.om3 = l3 ? g->omega_lv.as<const double>() : nullptr;  // omega_3 is level 0
+  if (c2) {  // level 2, with the member rows
     if (wl3)
       hipLaunchKernelGGL((k_push_wl<CT, false, true>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp,
                          ci, C, c1, c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(),
-                         w.wl_cap, tmask, wl3, wl3_n, w.wl3_cap);
+                         w.wl_cap, tmask, wl3, wl3_n, w.wl3_cap, fx);
     else
       hipLaunchKernelGGL((k_push_wl<CT, false, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st,
                          rp, ci, C, c1, c2, w.wl.as<const uint64_t>(),
                          w.wl_n.as<const unsigned>(), w.wl_cap, tmask, (uint64_t *)nullptr,
-                         (unsigned *)nullptr, 0u);
-    GED_HIP(hipGetLastError());
+                         (unsigned *)nullptr, 0u, fx);
+  } else {
+    hipLaunchKernelGGL(k_fix_members<CT>, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
+                       dim3(kBlock), 0, st, fx);
   }
-  hipLaunchKernelGGL(k_fix_members<CT>, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
-                     dim3(kBlock), 0, st, rp, g->omega2.as<const unsigned long long>(), offs, mem,
-                     mcol, g0, nc, C, c1, c2, l3,
-                     l3 ? g->omega_lv.as<const double>() : nullptr);  // omega_3 is level 0
   GED_HIP(hipGetLastError());
   if (l3) {  // level 3 from every vertex holding a level-2 count
     hipLaunchKernelGGL((k_push_wl<CT, false, false>), dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C,
                        static_cast<const CT *>(c2), l3, w.wl3.as<const uint64_t>(),
                        w.wl3_n.as<const unsigned>(), w.wl3_cap, tmask, (uint64_t *)nullptr,
-                       (unsigned *)nullptr, 0u);
+                       (unsigned *)nullptr, 0u, MemberFix<CT>());
     GED_HIP(hipGetLastError());
   }
 }
@@ -682,17 +749,15 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
   CT *c1 = w.cnt1.as<CT>();
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
   CT *l3 = pl.push3 ? w.lv.as<CT>() : nullptr;
-  if (c2) {
+  if (l3) {  // level-2 and pushed level-3 targets in one launch
+    hipLaunchKernelGGL(k_clear_two<CT>, dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C, c2,
+                       w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap, l3,
+                       w.wl3.as<const uint64_t>(), w.wl3_n.as<const unsigned>(), w.wl3_cap);
+    GED_HIP(hipGetLastError());
+  } else if (c2) {
     hipLaunchKernelGGL((k_push_wl<CT, true, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C,
                        c1, c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap,
-                       tmask, (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
-    GED_HIP(hipGetLastError());
-  }
-  if (l3) {  // the pushed level's targets
-    hipLaunchKernelGGL((k_push_wl<CT, true, false>), dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C,
-                       static_cast<const CT *>(c2), l3, w.wl3.as<const uint64_t>(),
-                       w.wl3_n.as<const unsigned>(), w.wl3_cap, tmask, (uint64_t *)nullptr,
-                       (unsigned *)nullptr, 0u);
+                       tmask, (uint64_t *)nullptr, (unsigned *)nullptr, 0u, MemberFix<CT>());
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_clear_members<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem,
