@@ -55,9 +55,11 @@ __global__ void k_mask_bit(uint32_t *mask, int v, int value) {
 }
 
 // A vertex u joined S: one more arc from S into each v in N(u) (undirected,
-// so the row of u lists them; repeated arcs count each time).
+// so the row of u lists them; repeated arcs count each time), and u's bit in
+// the S bitmap.
 __global__ void k_sdeg_add(const int *__restrict__ rp, const int *__restrict__ ci, int u,
-                           int *sdeg) {
+                           int *sdeg, uint32_t *smask) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) smask[u >> 5] |= 1u << (u & 31);
   for (int k = rp[u] + blockIdx.x * blockDim.x + threadIdx.x; k < rp[u + 1];
        k += gridDim.x * blockDim.x)
     atomicAdd(&sdeg[ci[k]], 1);
@@ -86,11 +88,16 @@ __global__ void k_miss1(const int *__restrict__ rp, const int *__restrict__ sdeg
 // rows become 0).  M_i = fl(alpha^i)
 // * count on both sides, the counts are exact integers (M_i / alpha^i rounds
 // back to the count), so the result equals the recomputed chain bit for bit.
-// mc_top receives the level-top counts for the next dense level.
-__global__ void k_miss_sub(double *__restrict__ M, int n, const uint32_t *__restrict__ dl32, int C,
-                           int col, int top, double alpha, uint32_t *__restrict__ mc_top) {
+// mc_top receives the level-top counts for the next dense level.  Level 1
+// is written as k_miss1 writes it (from the arcs-from-S counts).
+__global__ void k_miss_sub(const int *__restrict__ rp, const int *__restrict__ sdeg,
+                           const uint32_t *__restrict__ smask, double *__restrict__ M, int n,
+                           const uint32_t *__restrict__ dl32, int C, int col, int top,
+                           double alpha, uint32_t *__restrict__ mc_top) {
   const size_t nC = (size_t)n * C;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const bool inS = (smask[v >> 5] >> (v & 31)) & 1u;
+    M[(size_t)n + v] = alpha * (double)(inS ? 0 : rp[v + 1] - rp[v] - sdeg[v]);
     double ai = alpha;
     for (int i = 2; i <= top; ++i) {
       ai *= alpha;
@@ -548,19 +555,20 @@ static void miss_chains(GreedyCtx &c, int ell) {
     double *L = (rev ? c.b_levels : c.m_levels).as<double>();
     int i0 = 1;
     if (c.split && !g->weighted) {  // level 1 from the S-arc counts
-      hipLaunchKernelGGL(k_miss1, dim3(std::min(8192, (n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                         c.st, g->rp.as<const int>(), c.sdeg.as<const int>(),
-                         c.smask.as<const uint32_t>(), g->prep.alpha, n, L + (size_t)n,
-                         m32 ? mc + (size_t)n : nullptr);
-      GED_HIP(hipGetLastError());
-      i0 = 2;
-      if (by_sub) {
+      if (by_sub) {  // ... with levels 2 .. sub_top by subtraction, one pass
         hipLaunchKernelGGL(k_miss_sub, dim3(std::min(8192, (n + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, c.st, L, n, c.last_src, c.C, sub,
-                           sub_top, g->prep.alpha, mc + (size_t)(sub_top & 1) * n);
-        GED_HIP(hipGetLastError());
+                           dim3(kBlock), 0, c.st, g->rp.as<const int>(), c.sdeg.as<const int>(),
+                           c.smask.as<const uint32_t>(), L, n, c.last_src, c.C, sub, sub_top,
+                           g->prep.alpha, mc + (size_t)(sub_top & 1) * n);
         i0 = sub_top + 1;
+      } else {
+        hipLaunchKernelGGL(k_miss1, dim3(std::min(8192, (n + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, c.st, g->rp.as<const int>(), c.sdeg.as<const int>(),
+                           c.smask.as<const uint32_t>(), g->prep.alpha, n, L + (size_t)n,
+                           m32 ? mc + (size_t)n : nullptr);
+        i0 = 2;
       }
+      GED_HIP(hipGetLastError());
     }
     double ai = g->prep.alpha;  // alpha^i
     for (int i = 2; i < i0; ++i) ai *= g->prep.alpha;
@@ -1005,12 +1013,13 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
     launch_fill_i32(c.sdeg.as<int>(), 0, (size_t)n, c.st);
   }
   auto join = [&](int u) {
-    hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
-    if (track_sdeg) {
+    if (track_sdeg) {  // S-arc counts and u's S bit in one launch
       const int d = g->h_rp[u + 1] - g->h_rp[u];
       hipLaunchKernelGGL(k_sdeg_add, dim3(std::max(1, std::min(256, (d + kBlock - 1) / kBlock))),
                          dim3(kBlock), 0, c.st, g->rp.as<const int>(), g->ci.as<const int>(), u,
-                         c.sdeg.as<int>());
+                         c.sdeg.as<int>(), c.smask.as<uint32_t>());
+    } else {
+      hipLaunchKernelGGL(k_mask_bit, dim3(1), dim3(64), 0, c.st, c.smask.as<uint32_t>(), u, 1);
     }
     GED_HIP(hipGetLastError());
   };
