@@ -425,9 +425,10 @@ struct ged_graph {
   hipGraphExec_t score_exec = nullptr;
   hipGraph_t score_graph = nullptr;
   std::vector<const void *> score_sig;  // pointers/values the captured graph depends on
-  // split scoring: one captured pair per third-level variant (gathered,
-  // pushed), so groups that alternate between them keep both
-  ged::SplitExec split_exec[2];
+  // split scoring: one captured pair per variant (third level gathered or
+  // pushed; group copied to the device or staged by the first kernel), so
+  // groups that alternate between them keep each
+  ged::SplitExec split_exec[4];
   hipEvent_t score_done = nullptr;  // recorded after the result copy
   // batched scoring
   int32_t batch_tile = 0;
@@ -545,7 +546,7 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
 // w's counts and tmask must not be shared with a tile in flight.
 void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                      const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
-                     uint64_t *tmask, hipStream_t st);
+                     uint64_t *tmask, hipStream_t st, bool set_tmask = true);
 void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, double *out,
                        hipStream_t st);
 void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,

@@ -47,6 +47,9 @@ constexpr int kWlGridMax = 16384;
 // Grid of the pushed level 3 and its clearing: one wave per entry up to
 // 4096 entries (waves without an entry end at once).
 constexpr int kWl3Grid = 1024;
+// Largest single group whose members the score's first kernel reads from
+// host memory instead of a copy.
+constexpr int kStageMembers = 1024;
 int split_wl_blocks(int64_t expected_entries) {
   return (int)std::max<int64_t>(kWlGridMin,
                                 std::min<int64_t>(kWlGridMax, (expected_entries + 3) / 4));
@@ -392,6 +395,22 @@ __global__ void k_sum_t(const double *__restrict__ T, int64_t n, int r, double *
     double s = 0.0;
     for (int c = 1; c <= r; ++c) s += T[(size_t)c * n + v];
     out[v] = s;
+  }
+}
+
+// A single group staged from coherent host memory by the first kernel of a
+// score: offsets {0, len} and members copied to the device buffer every later
+// kernel reads (the deferred clean-up included, so the host may reuse its
+// buffer once the score is done), and the members' column bit set in tmask.
+__global__ void k_stage_group(const int64_t *h_offs, const int *h_mem, int64_t *d_offs,
+                              int *d_mem, unsigned long long *tmask) {
+  const int64_t len = h_offs[1];
+  if (blockIdx.x == 0 && threadIdx.x < 2) d_offs[threadIdx.x] = h_offs[threadIdx.x];
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < len;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int v = h_mem[j];
+    d_mem[j] = v;
+    atomicOr(&tmask[v], 1ull);
   }
 }
 
@@ -885,9 +904,9 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
 
 void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                      const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
-                     uint64_t *tmask, hipStream_t st) {
+                     uint64_t *tmask, hipStream_t st, bool set_tmask) {
   const int mgrid = grid_for(tile_members, kPushGrid);
-  launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
+  if (set_tmask) launch_tmask_set(tmask, offs, mem, g0, nc, 1, st);
   if (pl.s >= 1) {
     if (pl.c32)
       push_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tile_members, tmask, st);
@@ -992,7 +1011,7 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
     while (cap < len) cap *= 2;
     const size_t bytes = 2 * sizeof(int64_t) + 2 * sizeof(int) * (size_t)cap;
     g->split_in.ensure(bytes);
-    g->split_in_host.ensure(bytes);
+    g->split_in_host.ensure(bytes, hipHostMallocCoherent);
     // mcol: every member is in column 0
     launch_fill_i32(reinterpret_cast<int *>(g->split_in.as<char>() + 2 * sizeof(int64_t)) + cap,
                     0, (size_t)cap, st);
@@ -1024,8 +1043,13 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   int64_t offs[2] = {0, len};
   std::memcpy(hb, offs, sizeof(offs));
   std::memcpy(hb + sizeof(offs), mem.data(), sizeof(int) * (size_t)len);
-  GED_HIP(hipMemcpyAsync(g->split_in.p, hb, sizeof(offs) + sizeof(int) * (size_t)len,
-                         hipMemcpyHostToDevice, st));
+  // small groups are staged by the graph's first kernel (no copy launch);
+  // larger ones are copied (a kernel reading thousands of members over the
+  // host link would take longer)
+  const bool staged = len <= kStageMembers;
+  if (!staged)
+    GED_HIP(hipMemcpyAsync(g->split_in.p, hb, sizeof(offs) + sizeof(int) * (size_t)len,
+                           hipMemcpyHostToDevice, st));
   const int64_t *d_offs = g->split_in.as<const int64_t>();
   const int *d_mem = reinterpret_cast<const int *>(g->split_in.as<char>() + sizeof(offs));
   const int *d_mcol = d_mem + cap;
@@ -1035,7 +1059,15 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
   // the result copy and not waited for: any later work on this stream runs
   // after it, and ged_set_stream / ged_graph_destroy synchronize the stream.
   auto enqueue_main = [&]() {
-    split_tile_push(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, tm, st);
+    if (staged) {
+      hipLaunchKernelGGL(k_stage_group, dim3(grid_for((len + kBlock - 1) / kBlock, 16)),
+                         dim3(kBlock), 0, st, reinterpret_cast<const int64_t *>(hb),
+                         reinterpret_cast<const int *>(hb + sizeof(offs)),
+                         g->split_in.as<int64_t>(), const_cast<int *>(d_mem),
+                         reinterpret_cast<unsigned long long *>(tm));
+      GED_HIP(hipGetLastError());
+    }
+    split_tile_push(g, w, pl, 1, d_offs, d_mem, d_mcol, 0, 1, cap, tm, st, !staged);
     split_dense(g, w, pl, 1, tm, st);
     split_tile_reduce(g, w, pl, 1, ho, st);
   };
@@ -1056,11 +1088,12 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
       std::vector<const void *> sig = {
           g->split_tmask.p, w.cnt1.p, w.cnt2.p, w.lv.p, w.wl.p, w.wl_n.p, w.wl3.p, w.wl3_n.p,
           (const void *)(uintptr_t)w.wl3_cap, (const void *)(intptr_t)pl.push3, w.ws.blk.p, w.ws.seg.p,
-          w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
+          w.ws.lng.p, w.ws.red2.p, g->split_in.p, g->split_in_host.p, (const void *)(intptr_t)staged,
+          g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
           g->omega_lv.p, g->out_host.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
           (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
           (const void *)(intptr_t)1 /* split */};
-      SplitExec &x = g->split_exec[pl.push3 ? 1 : 0];
+      SplitExec &x = g->split_exec[(pl.push3 ? 1 : 0) + (staged ? 2 : 0)];
       if (x.exec && sig != x.sig) x.drop();
       if (!x.exec) {
         capture(st, enqueue_main, &x.graph, &x.exec);
