@@ -255,10 +255,6 @@ __global__ __launch_bounds__(kBlock) void k_topk_pairs(const double *__restrict_
 }
 
 // Candidates of a batch: cand_col[x_c] = c (value=1) or -1 (value=0).
-__global__ void k_cand_set(int *cand_col, const int *cand, int nc, int value) {
-  const int c = threadIdx.x;
-  if (c < nc) cand_col[cand[c]] = value ? c : -1;
-}
 
 // A batch's candidates, passed by value (no host-to-device copy).
 struct CandList {
@@ -266,12 +262,27 @@ struct CandList {
 };
 
 // cand[c] = the batch's c-th candidate, cand_col[candidate] = c; a non-null
-// wl_n (the batch's level-2 worklist) starts empty.
-__global__ void k_cand_put(int *cand_col, int *cand, CandList cl, int nc, unsigned *wl_n) {
+// wl_n (the batch's level-2 worklist) starts empty.  With injc, the
+// candidates' unscaled miss counts injc[i*C + c] = m_i(x_c) / alpha^i rounded
+// to the nearest integer, 2 <= i <= inj_top: exact when the count is below
+// 2^32 and i*(deg_max + 3) < 2^19, since every miss level is a sum of
+// nonnegative terms with relative error at most about i*(deg_max + 2)*2^-53,
+// under 1/4 of a unit at 2^32.
+__global__ void k_cand_put(int *cand_col, int *cand, CandList cl, int nc, unsigned *wl_n,
+                           const double *__restrict__ M, int n, int C, double alpha, int inj_top,
+                           double *injc) {
   const int c = threadIdx.x;
   if (c < nc) {
-    cand[c] = cl.v[c];
-    cand_col[cl.v[c]] = c;
+    const int x = cl.v[c];
+    cand[c] = x;
+    cand_col[x] = c;
+    if (injc) {
+      double ap = alpha;
+      for (int i = 2; i <= inj_top; ++i) {
+        ap *= alpha;
+        injc[i * C + c] = rint(M[(size_t)i * n + x] / ap);
+      }
+    }
   }
   if (wl_n && c == 0) *wl_n = 0;
 }
@@ -281,10 +292,12 @@ __global__ void k_cand_put(int *cand_col, int *cand, CandList cl, int nc, unsign
 // The gains also go to host_gains (coherent host memory, read by the host
 // after it waits for the stream).
 __global__ void k_after_batch(const int *cand, const double *gains, int nc, double *stale,
-                              double *ub, int *done, int round, double *host_gains) {
+                              double *ub, int *done, int round, double *host_gains,
+                              int *cand_col) {
   const int c = threadIdx.x;
   if (c < nc) {
     const int x = cand[c];
+    cand_col[x] = -1;  // no longer a candidate column
     host_gains[c] = gains[c];
     stale[x] = gains[c];
     ub[x] = gains[c];
@@ -428,23 +441,6 @@ __global__ __launch_bounds__(kBlock) void k_gain_clear2(const int *__restrict__ 
 #pragma unroll
     for (int k = 0; k < U; ++k)
       if (w[k] >= 0) d2[(size_t)w[k] * C + c] = 0u;
-  }
-}
-
-// Unscaled miss counts of the candidates, injc[i*C + c] = m_i(x_c) / alpha^i
-// rounded to the nearest integer, for 2 <= i <= top.  Exact when the count is
-// below 2^32 and i*(deg_max + 3) < 2^19: every miss level is a sum of
-// nonnegative terms, so its relative error is at most about
-// i*(deg_max + 2)*2^-53, under 1/4 of a unit at 2^32.
-__global__ void k_gain_inj(const double *__restrict__ M, int n, const int *cand, int nc, int C,
-                           double alpha, int top, double *injc) {
-  const int c = threadIdx.x;
-  if (c >= nc) return;
-  const int x = cand[c];
-  double ap = alpha;
-  for (int i = 2; i <= top; ++i) {
-    ap *= alpha;
-    injc[i * C + c] = rint(M[(size_t)i * n + x] / ap);
   }
 }
 
@@ -665,7 +661,7 @@ static int select_topk(GreedyCtx &c, int K, int round, const int *sampled, int p
 // unweighted, no repeated arcs): d_i(v) / alpha^i counts walks that avoid S
 // and contain x, at most omega_i(v), so levels 1 .. ceil(ell/2)-1 fit when
 // max omega_i < 2^32; the candidates' injected miss counts are recovered
-// exactly by rounding when i*(deg_max + 3) < 2^19 (k_gain_inj).
+// exactly by rounding when i*(deg_max + 3) < 2^19 (k_cand_put).
 static bool gains32(GreedyCtx &c, int ell) {
   if (c.g32_ell == ell) return c.g32_ok;
   ged_graph *g = c.g;
@@ -725,11 +721,24 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
     }
     c.wl2_n.ensure(sizeof(unsigned));
   }
+  const double *M = c.m_levels.as<const double>();
+  // the candidates' miss counts the 32-bit gain levels inject (levels 2 ..
+  // a-1, or 2 on FP64 chains that keep levels 1-2 as counts)
+  int inj_top = 0;
+  if (c.split) {
+    const int la = (ell + 1) / 2;
+    const bool push1 = la > 1 && g->simple && !g->weighted;
+    if (la > 2 && gains32(c, ell))
+      inj_top = la - 1;
+    else if (push1 && la >= 3)
+      inj_top = 2;
+    if (inj_top > 0) c.injc.ensure(sizeof(double) * (size_t)(la + 1) * C);
+  }
   CandList cl;
   for (int q = 0; q < nc; ++q) cl.v[q] = cand[q];
   hipLaunchKernelGGL(k_cand_put, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
-                     c.cand_dev.as<int>(), cl, nc, push2 ? c.wl2_n.as<unsigned>() : nullptr);
-  const double *M = c.m_levels.as<const double>();
+                     c.cand_dev.as<int>(), cl, nc, push2 ? c.wl2_n.as<unsigned>() : nullptr, M,
+                     n, C, g->prep.alpha, inj_top, inj_top > 0 ? c.injc.as<double>() : nullptr);
   StepArgs a = base_args(g);
   c.wsC.into(a);
   a.C = C;
@@ -781,11 +790,7 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
       c.wsC.fit(pn);
       c.wsC.into(a);
       pr = &pn;
-      c.injc.ensure(sizeof(double) * (size_t)(la + 1) * C);
-      if (la > 2)
-        hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
-                           c.cand_dev.as<const int>(), nc, C, g->prep.alpha, la - 1,
-                           c.injc.as<double>());
+      // the candidates' injected miss counts were written by k_cand_put
       if (push2) {  // injc (level 2) is ready
         hipLaunchKernelGGL(k_gain_push2, dim3(std::min(4096, std::max(64, (int)(wl2_need / 4)))),
                            dim3(kBlock), 0, c.st, a.rp, a.ci, a.smask, c.cand_dev.as<const int>(),
@@ -854,10 +859,6 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
         hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
                            a.smask, c.cand_dev.as<const int>(), C, c.sdeg.as<const int>(), dc, 0,
                            (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
-        GED_HIP(hipGetLastError());
-        c.injc.ensure(sizeof(double) * (size_t)(la + 1) * C);
-        hipLaunchKernelGGL(k_gain_inj, dim3(1), dim3(64), 0, c.st, M, n,
-                           c.cand_dev.as<const int>(), nc, C, al, 2, c.injc.as<double>());
         GED_HIP(hipGetLastError());
       }
       double ai = al;  // alpha^i
@@ -931,12 +932,10 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int ell, int round
     }
   }
   launch_reduce(*pr, a, c.gains.as<double>(), nullptr, nullptr, c.st, c.wsC.scratch());
-  hipLaunchKernelGGL(k_cand_set, dim3(1), dim3(64), 0, c.st, c.cand_col.as<int>(),
-                     c.cand_dev.as<const int>(), nc, 0);
   double *hg = c.h_small.as<double>() + 256;
   hipLaunchKernelGGL(k_after_batch, dim3(1), dim3(64), 0, c.st, c.cand_dev.as<const int>(),
                      c.gains.as<const double>(), nc, c.stale.as<double>(), c.ub.as<double>(),
-                     c.done.as<int>(), round, hg);
+                     c.done.as<int>(), round, hg, c.cand_col.as<int>());
   GED_HIP(hipGetLastError());
   GED_HIP(hipStreamSynchronize(c.st));
   for (int q = 0; q < nc; ++q) out[q] = hg[q];
