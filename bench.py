@@ -398,6 +398,8 @@ def main():
                          "generator's order")
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the stream")
     ap.add_argument("--qps", type=float, default=2000.0, help="serve: arrival rate")
+    ap.add_argument("--greedy-frac", type=float, default=0.1,
+                    help="serve: fraction of greedy requests in the stream")
     ap.add_argument("--serve-small", action="store_true", help="serve: only the 3 small graphs")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")

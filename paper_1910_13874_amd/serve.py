@@ -17,7 +17,8 @@ GREEDY_KS = (5, 20, 100)
 
 def make_requests(ns, n_req, qps, seed, greedy_frac=0.1, smax=100):
     """Seeded stream: exponential inter-arrival gaps at rate qps, graph uniform,
-    90 % scores with |S| ~ U[1, smax], 10 % greedy with k uniform over GREEDY_KS."""
+    a fraction greedy_frac of greedy requests with k uniform over GREEDY_KS, the
+    rest scores with |S| ~ U[1, smax]."""
     from . import inputs
     rng = np.random.Generator(np.random.PCG64(seed))
     gaps = rng.exponential(1.0 / qps, size=n_req)
@@ -114,7 +115,8 @@ def bench(args, torch, ged, inputs, metric):
     gids = [server.add_graph(gg, a, eps) for gg, a in zip(graphs, alphas)]
     n_req = getattr(args, "requests", 1000)
     qps = getattr(args, "qps", 2000.0)
-    reqs = make_requests(ns, n_req, qps, seed=105)
+    gfrac = getattr(args, "greedy_frac", 0.1)
+    reqs = make_requests(ns, n_req, qps, seed=105, greedy_frac=gfrac)
     # warm the pools and the greedy path once
     warm = make_requests(ns, 16, 1e6, seed=7, greedy_frac=0.0)
     run_server(server, gids, warm)
@@ -145,9 +147,10 @@ def bench(args, torch, ged, inputs, metric):
         "steps": 1, "warmup": 1, "ms_per_step": wall * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"serving: Poisson stream of {n_req} requests at {qps:g} req/s "
-                               f"over {len(names)} resident graphs ({', '.join(names)}); 90% "
-                               "score |S|~U[1,100], 10% greedy k in {5,20,100}, eps=1e-4, FP64",
-                   "requests": n_req, "qps": qps, "graphs": names, "parallelism": "single GPU"},
+                               f"over {len(names)} resident graphs ({', '.join(names)}); "
+                               f"{100 * (1 - gfrac):g}% score |S|~U[1,100], {100 * gfrac:g}% "
+                               "greedy k in {5,20,100}, eps=1e-4, FP64",
+                   "requests": n_req, "qps": qps, "greedy_frac": gfrac, "graphs": names, "parallelism": "single GPU"},
         "served_queries_per_s": n_req / wall,
         "plain_queries_per_s": n_req / plain_clock,
         "served_vs_plain": (n_req / wall) / (n_req / plain_clock),
