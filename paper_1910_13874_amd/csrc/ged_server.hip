@@ -4,8 +4,9 @@
 // (ell*, fixed per graph), so queries on one graph batch as SpMM columns.
 // Undirected graphs run them as split tiles (the scoring of ged_split.hip:
 // integer pushes, two or so dense levels, a combining level): each launch
-// takes up to C waiting requests of the graph, and requests that arrive while
-// a tile is on the device join the next one.  Directed graphs keep a pool of
+// takes up to C waiting requests of the graph, at the narrowest power-of-two
+// width that holds them, and requests that arrive while a tile is on the
+// device join the next one.  Directed graphs keep a pool of
 // SpMM columns ("slots"): one launch advances every occupied column by one
 // level, each column at its own level (the injection reads t_{level(c)}), and
 // a column whose request has run ell* levels is harvested and refilled with
@@ -31,6 +32,7 @@ namespace ged {
 
 int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, uint64_t seed,
                bool stochastic, int32_t *out_group, double *out_score, ged_greedy_trace *tr);
+void split_fit_width(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C);
 
 static double now_us() {
   using namespace std::chrono;
@@ -144,6 +146,8 @@ static void lane_setup(Lane &L, int C) {
     // each) fit C * (nnz/512 + 1) + 2n entries; one larger group grows it
     const size_t cap = (size_t)C * split_wl_need(g, 0) + 2 * (size_t)n;
     split_fit(g, L.sw, L.pl, C, cap, L.st);
+    // a tile runs at the narrowest power-of-two width that holds its requests
+    for (int w = 1; w < C; w *= 2) split_fit_width(g, L.sw, L.pl, w);
     L.sw.wl_blocks = split_wl_blocks((int64_t)std::min<size_t>(cap, (size_t)C * 4096));
     L.tmask.ensure(sizeof(uint64_t) * (size_t)n);
     L.acc.ensure(sizeof(double) * 64);
@@ -268,7 +272,11 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
   const int *d_mem = reinterpret_cast<const int *>(L.tin.as<char>() + ob);
   const int *d_col = d_mem + m;
   L.sw.zero = false;
-  enqueue_split_tile(g, L.sw, L.pl, C, d_offs, d_mem, d_col, 0, nc, (int64_t)m,
+  // the narrowest width that holds the tile: a step's cost grows with its
+  // width, so a tile of one request on a large graph runs as one column
+  int W = 1;
+  while (W < nc) W *= 2;
+  enqueue_split_tile(g, L.sw, L.pl, W, d_offs, d_mem, d_col, 0, nc, (int64_t)m,
                      L.tmask.as<uint64_t>(), L.acc.as<double>(), L.st, false);
   GED_HIP(hipMemcpyAsync(L.h_acc.p, L.acc.p, sizeof(double) * nc, hipMemcpyDeviceToHost, L.st));
   GED_HIP(hipEventRecord(L.ev, L.st));
@@ -503,8 +511,13 @@ extern "C" int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, d
     L->ell = g->prep.ell;
     int C = s->cfg.score_slots;
     if (C == 0) {
+      // split tiles run no wider than their requests need, so a wide limit
+      // costs memory only; a column pool steps all its columns every time
       const int64_t n = g->n;
-      C = n <= 200000 ? 64 : n <= 1000000 ? 32 : n <= 2000000 ? 16 : 8;
+      if (split_ok(g))
+        C = n <= 1000000 ? 64 : 32;
+      else
+        C = n <= 200000 ? 64 : n <= 1000000 ? 32 : n <= 2000000 ? 16 : 8;
     }
     lane_setup(*L, C);
     if (s->bytes_lanes + L->bytes > (size_t)s->cfg.hbm_budget_bytes)

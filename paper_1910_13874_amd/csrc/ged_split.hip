@@ -708,6 +708,15 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
   }
 }
 
+// Partitions and partial buffers for tiles of width C in a workspace whose
+// counts were fitted for a wider tile: the counts, levels and worklists of a
+// narrower tile use the first n * C entries of the same buffers.
+void split_fit_width(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C) {
+  w.ws.fit(partition(g, C));
+  if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, C, IN_CNT32));
+  w.ws.fit(step_partition(g, C, final_in(pl)));
+}
+
 template <class CT>
 static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                        const int *mem, const int *mcol, int g0, int nc, int mgrid,

@@ -44,6 +44,29 @@ def test_mix_equals_alone(ged):
         gg.close()
 
 
+def test_burst_fills_wide_tiles(ged):
+    """Default lane width (64 columns for this size): a burst of scores runs
+    as tiles of many widths, each result equal to the request alone."""
+    from paper_1910_13874_amd import serve
+    g = inputs.barabasi_albert(30000, 4, 23)
+    gg = ged.GedGraph.from_graph(g)
+    alpha = gg.default_alpha()
+    print("[serving burst] n", g.n, flush=True)
+    srv = ged.Server(hbm_budget_bytes=8 << 30, greedy_workers=1)
+    gid = srv.add_graph(gg, alpha, EPS)
+    reqs = serve.make_requests([g.n], 200, 1e7, seed=31, greedy_frac=0.0)
+    out, wall = serve.run_server(srv, [gid], reqs)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["peak_columns"] > 32, st
+    for j, q in enumerate(reqs):
+        kind, status, score, lat, grp = out[j]
+        assert status == 0
+        alone = gg.score(q["S"], alpha, EPS)
+        assert abs(score - alone) <= 1e-12 * max(abs(alone), 1e-300), (j, score, alone)
+    srv.close()
+    gg.close()
+
+
 def test_admission_and_queue_limits(ged):
     g = inputs.barabasi_albert(200000, 4, 23)
     gg = ged.GedGraph.from_graph(g)
