@@ -148,7 +148,6 @@ static void lane_setup(Lane &L, int C) {
     split_fit(g, L.sw, L.pl, C, cap, L.st);
     // a tile runs at the narrowest power-of-two width that holds its requests
     for (int w = 1; w < C; w *= 2) split_fit_width(g, L.sw, L.pl, w);
-    L.sw.wl_blocks = split_wl_blocks((int64_t)std::min<size_t>(cap, (size_t)C * 4096));
     L.tmask.ensure(sizeof(uint64_t) * (size_t)n);
     L.acc.ensure(sizeof(double) * 64);
     L.h_acc.ensure(sizeof(double) * 64);
@@ -234,6 +233,7 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
   std::vector<int64_t> offs(1, 0);
   std::vector<int> mem, col;
   size_t need = 0;
+  int64_t ds_tile = 0;  // members' degree sum: about the tile's worklist entries
   while (!L.pending.empty() && (int)L.tile.size() < C) {
     const Req &q = L.pending.front();
     int64_t ds = 0;
@@ -241,6 +241,7 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
     const size_t nq = split_wl_need(g, ds);
     if (!L.tile.empty() && need + nq > L.sw.wl_cap) break;
     need += nq;
+    ds_tile += ds;
     const int c = (int)L.tile.size();
     for (int v : q.S) {
       mem.push_back(v);
@@ -256,6 +257,8 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
     s->waiting -= nc;
   }
   if (need > L.sw.wl_cap) split_fit(g, L.sw, L.pl, C, need, L.st);
+  // worklist kernels loop over their grid: size it for this tile
+  L.sw.wl_blocks = split_wl_blocks(ds_tile);
   const size_t m = mem.size();
   const size_t ob = sizeof(int64_t) * (size_t)(nc + 1);
   const size_t bytes = ob + 2 * sizeof(int) * std::max<size_t>(m, 1);
