@@ -242,7 +242,10 @@ typedef struct ged_server ged_server;
 
 typedef struct {
   int64_t hbm_budget_bytes; /* admission limit for request working memory */
-  int32_t score_slots;      /* columns per resident graph for score requests */
+  int32_t score_slots;      /* columns per resident graph for score requests: 0 or a
+                               power of two <= 64; 0 picks 64 (undirected, n <= 1e6),
+                               32 (undirected, larger), or 64/32/16/8 for directed
+                               column pools by n (<= 2e5, 1e6, 2e6, beyond) */
   int32_t max_queue;        /* requests waiting for a column or a worker before GED_ERR_BUSY */
   int32_t greedy_workers;   /* concurrent greedy requests */
 } ged_server_config;
@@ -263,7 +266,8 @@ typedef struct {
  * walk-count levels in device memory.  Score requests on one graph run
  * together as the columns of a tile: on undirected graphs each launch takes
  * the waiting requests (up to score_slots) through a whole split scoring tile,
- * and requests arriving meanwhile join the next one; on directed graphs a
+ * run at the narrowest power-of-two width that holds them, and requests
+ * arriving meanwhile join the next one; on directed graphs a
  * pool of columns advances one walk length per step and admits new requests
  * into free columns between steps.  Greedy requests run on worker threads
  * (one at a time per graph) once their working memory fits the HBM budget.
