@@ -1,0 +1,16 @@
+"""Closed forms that pin scores without sharing code with the oracle or the
+HIP path (scipy sparse products only)."""
+import numpy as np
+
+
+def whole_set_score(g, alpha, ell):
+    """GED(V): every walk meets V, so the score truncated at ell is the
+    weighted count of all walks, sum_{i<=ell} alpha^i 1^T A^i 1."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    x = np.ones(g.n)
+    total = 0.0
+    for i in range(1, ell + 1):
+        x = A @ x
+        total += alpha ** i * float(x.sum())
+    return total

@@ -315,6 +315,16 @@ def load_golden(name):
 
 
 @pytest.mark.timeout(600)
+def check_whole_set(gg, g, alpha):
+    """Full size, pinned without the oracle: the score of the whole vertex set
+    is the alpha-weighted count of all walks up to ell*."""
+    from closed_forms import whole_set_score
+    s, ell, B = gg.score(np.arange(g.n, dtype=np.int32), alpha, EPS, with_info=True)
+    c = whole_set_score(g, alpha, ell)
+    say(f"  whole set: ell={ell} score={s!r} closed form={c!r}")
+    assert rel(s, c) <= REL, (s, c)
+
+
 def test_full_size_ba1m(ged):
     """BA n=1e6, m=5 at full size: oracle scores and the oracle's greedy k=10 trace."""
     gold = load_golden("ba1m")
@@ -327,6 +337,7 @@ def test_full_size_ba1m(ged):
         S = inputs.group(g.n, rec["size"], rec["seed"])
         s, ell, B = gg.score(S, alpha, EPS, with_info=True)
         assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
+    check_whole_set(gg, g, alpha)
     gr = gold["greedy"]
     rg = gg.greedy(gr["k"], alpha, EPS)
     compare_greedy(rg, gr, "ba1m")
@@ -372,6 +383,7 @@ def test_full_size_rmat22(ged):
         S = inputs.group(g.n, rec["size"], rec["seed"])
         s, ell, B = gg.score(S, alpha, EPS, with_info=True)
         assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
+    check_whole_set(gg, g, alpha)
     gr = gold["greedy"]
     k = 100
     rg = gg.greedy(k, alpha, EPS)

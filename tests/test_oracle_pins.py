@@ -643,3 +643,16 @@ def test_oracle_default_calls_run_concurrently():
     with ThreadPoolExecutor(4) as ex:
         par = list(ex.map(lambda S: oracle.score(g, S, alpha, 1e-6)[0], groups))
     assert par == seq
+
+
+def test_whole_vertex_set_counts_every_walk():
+    """Sect. 3 (walk-based group score): with S = V every walk of every length
+    counts, so the oracle's score equals the total walk count weighted by
+    alpha^i, whatever the graph family or the walk length."""
+    for g in (inputs.barabasi_albert(3000, 4, 3), inputs.erdos_renyi(2000, 6000, 5),
+              inputs.rmat(11, 8, seed=2)):
+        alpha = g.default_alpha()
+        s, ell, _, _ = oracle.score(g, np.arange(g.n), alpha, 1e-4)
+        from closed_forms import whole_set_score
+        assert abs(s - whole_set_score(g, alpha, ell)) <= 1e-12 * s, (g.name, s)
+
