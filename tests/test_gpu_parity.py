@@ -366,6 +366,15 @@ def test_full_size_batch_ba2m(ged):
         solo = gg.score(mem[off[j]:off[j + 1]], alpha, EPS)
         assert rel(b[j], solo) <= 1e-12, (j, b[j], solo)
     np.testing.assert_array_equal(gg.score_batch(off, mem, alpha, EPS), b)
+    # the whole vertex set as a batch of one, and as a single score: the
+    # closed form (all walks), pinned without the oracle
+    from closed_forms import whole_set_score
+    whole = np.arange(g.n, dtype=np.int32)
+    bw = gg.score_batch(np.array([0, g.n], dtype=np.int64), whole, alpha, EPS)
+    s, ell, B = gg.score(whole, alpha, EPS, with_info=True)
+    c = whole_set_score(g, alpha, ell)
+    say(f"  whole set: ell={ell} batch={bw[0]!r} single={s!r} closed form={c!r}")
+    assert rel(bw[0], c) <= REL and rel(s, c) <= REL, (bw[0], s, c)
     gg.close()
 
 
