@@ -14,3 +14,22 @@ def whole_set_score(g, alpha, ell):
         x = A @ x
         total += alpha ** i * float(x.sum())
     return total
+
+
+def group_score(g, S, alpha, ell):
+    """GED(S) from its definition by complement: the walks that meet S are all
+    walks minus those whose every vertex lies outside S, i.e. the walks of the
+    subgraph induced by V \\ S.  y_i(v) counts walks of length i ending at v
+    that avoid S: y_0 = 1_{V\\S}, y_i = 1_{V\\S} * (A y_{i-1})."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    keep = np.ones(g.n)
+    keep[np.asarray(S, dtype=np.int64)] = 0.0
+    x = np.ones(g.n)
+    y = keep.copy()
+    total = 0.0
+    for i in range(1, ell + 1):
+        x = A @ x
+        y = keep * (A @ y)
+        total += alpha ** i * (float(x.sum()) - float(y.sum()))
+    return total

@@ -315,6 +315,15 @@ def load_golden(name):
 
 
 @pytest.mark.timeout(600)
+def check_by_complement(g, S, alpha, ell, score, tag):
+    """Full size, pinned without the oracle: all walks minus the walks of the
+    subgraph induced by V \\ S."""
+    from closed_forms import group_score
+    c = group_score(g, S, alpha, ell)
+    say(f"  complement {tag}: |S|={len(S)} score={score!r} closed form={c!r}")
+    assert rel(score, c) <= REL, (tag, score, c)
+
+
 def check_whole_set(gg, g, alpha):
     """Full size, pinned without the oracle: the score of the whole vertex set
     is the alpha-weighted count of all walks up to ell*."""
@@ -337,6 +346,7 @@ def test_full_size_ba1m(ged):
         S = inputs.group(g.n, rec["size"], rec["seed"])
         s, ell, B = gg.score(S, alpha, EPS, with_info=True)
         assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
+        check_by_complement(g, S, alpha, ell, s, rec["seed"])
     check_whole_set(gg, g, alpha)
     gr = gold["greedy"]
     rg = gg.greedy(gr["k"], alpha, EPS)
@@ -358,10 +368,13 @@ def test_full_size_batch_ba2m(ged):
     off, mem = inputs.groups(g.n, bt["groups"], 1, 200, bt["seed"])
     b = gg.score_batch(off, mem, alpha, EPS)
     say(f"  tile {gg.batch_tile()}")
-    for rec in bt["sample"]:
+    for q, rec in enumerate(bt["sample"]):
         j = rec["index"]
         assert off[j + 1] - off[j] == rec["size"]
         assert rel(b[j], rec["score"]) <= REL, (j, b[j], rec["score"])
+        if q < 3:
+            check_by_complement(g, mem[off[j]:off[j + 1]], alpha, gg.prepare(alpha, EPS)[0],
+                                b[j], j)
     for j in range(len(off) - 1):
         solo = gg.score(mem[off[j]:off[j + 1]], alpha, EPS)
         assert rel(b[j], solo) <= 1e-12, (j, b[j], solo)
@@ -392,6 +405,7 @@ def test_full_size_rmat22(ged):
         S = inputs.group(g.n, rec["size"], rec["seed"])
         s, ell, B = gg.score(S, alpha, EPS, with_info=True)
         assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
+        check_by_complement(g, S, alpha, ell, s, rec["seed"])
     check_whole_set(gg, g, alpha)
     gr = gold["greedy"]
     k = 100

@@ -656,3 +656,18 @@ def test_whole_vertex_set_counts_every_walk():
         from closed_forms import whole_set_score
         assert abs(s - whole_set_score(g, alpha, ell)) <= 1e-12 * s, (g.name, s)
 
+
+def test_group_score_by_complement():
+    """Sect. 3 (walk-based group score): a walk meets S unless all its vertices
+    lie outside S, so GED(S) = all walks - walks of the subgraph induced by
+    V \\ S, each weighted by alpha^length; groups from one vertex to 300."""
+    from closed_forms import group_score
+    for g in (inputs.barabasi_albert(3000, 4, 3), inputs.erdos_renyi(2000, 6000, 5),
+              inputs.rmat(11, 8, seed=2)):
+        alpha = g.default_alpha()
+        for seed, size in ((1, 1), (2, 5), (3, 40), (4, 300)):
+            S = inputs.group(g.n, size, seed)
+            s, ell, _, _ = oracle.score(g, S, alpha, 1e-4)
+            c = group_score(g, S, alpha, ell)
+            assert abs(s - c) <= 1e-12 * abs(c), (g.name, size, s, c)
+
