@@ -33,3 +33,21 @@ def group_score(g, S, alpha, ell):
         y = keep * (A @ y)
         total += alpha ** i * (float(x.sum()) - float(y.sum()))
     return total
+
+
+def gain(g, S, u, alpha, ell):
+    """Marginal gain GED_{<=ell}(S + u) - GED_{<=ell}(S): the walks that avoid S
+    but not u, i.e. the avoiding-walk counts of V \\ S minus those of V \\ (S + u)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    k1 = np.ones(g.n)
+    k1[np.asarray(S, dtype=np.int64)] = 0.0
+    k2 = k1.copy()
+    k2[u] = 0.0
+    y1, y2 = k1.copy(), k2.copy()
+    total = 0.0
+    for i in range(1, ell + 1):
+        y1 = k1 * (A @ y1)
+        y2 = k2 * (A @ y2)
+        total += alpha ** i * (float(y1.sum()) - float(y2.sum()))
+    return total

@@ -324,6 +324,17 @@ def check_by_complement(g, S, alpha, ell, score, tag):
     assert rel(score, c) <= REL, (tag, score, c)
 
 
+def check_gains_by_complement(g, rg, alpha, picks, tag):
+    """Full size, pinned without the oracle: each pick's recorded gain is the
+    count of walks that avoid the previous picks and meet this one."""
+    from closed_forms import gain
+    for j in range(picks):
+        grp = rg["group"]
+        c = gain(g, grp[:j], int(grp[j]), alpha, int(rg["ell"][j]))
+        say(f"  gain {tag} pick {j}: ell={rg['ell'][j]} L={rg['L1'][j]!r} closed form={c!r}")
+        assert rel(rg["L1"][j], c) <= REL, (tag, j, rg["L1"][j], c)
+
+
 def check_whole_set(gg, g, alpha):
     """Full size, pinned without the oracle: the score of the whole vertex set
     is the alpha-weighted count of all walks up to ell*."""
@@ -351,6 +362,7 @@ def test_full_size_ba1m(ged):
     gr = gold["greedy"]
     rg = gg.greedy(gr["k"], alpha, EPS)
     compare_greedy(rg, gr, "ba1m")
+    check_gains_by_complement(g, rg, alpha, gr["k"], "ba1m")
     gg.close()
 
 
@@ -413,6 +425,7 @@ def test_full_size_rmat22(ged):
     kk = gr["k"]
     assert list(rg["group"][:kk]) == gr["group"]
     assert list(rg["ell"][:kk]) == gr["ell"]
+    check_gains_by_complement(g, rg, alpha, min(kk, 2), "rmat22")
     for j in range(kk):
         assert rel(rg["L1"][j], gr["L1"][j]) <= REL
     # any-size properties of the rest of the run

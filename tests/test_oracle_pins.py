@@ -671,3 +671,19 @@ def test_group_score_by_complement():
             c = group_score(g, S, alpha, ell)
             assert abs(s - c) <= 1e-12 * abs(c), (g.name, size, s, c)
 
+
+def test_greedy_gains_by_complement():
+    """Alg. "lazy greedy": the gain recorded for each pick is the truncated
+    marginal L_ell(S, u) = GED_{<=ell}(S + u) - GED_{<=ell}(S), which counts
+    the walks avoiding S that meet u (avoiding-walk counts of two induced
+    subgraphs), at the pick's own ell."""
+    from closed_forms import gain
+    for g in (inputs.barabasi_albert(3000, 4, 3), inputs.erdos_renyi(2000, 6000, 5),
+              inputs.rmat(11, 8, seed=2)):
+        alpha = g.default_alpha()
+        r = oracle.greedy(g, 6, alpha, 1e-4)
+        for j in range(6):
+            grp = r["group"]
+            c = gain(g, grp[:j], grp[j], alpha, int(r["ell"][j]))
+            assert abs(r["L1"][j] - c) <= 1e-12 * abs(c), (g.name, j, r["L1"][j], c)
+
