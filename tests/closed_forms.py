@@ -16,13 +16,16 @@ def whole_set_score(g, alpha, ell):
     return total
 
 
-def group_score(g, S, alpha, ell):
+def group_score(g, S, alpha, ell, w=None):
     """GED(S) from its definition by complement: the walks that meet S are all
     walks minus those whose every vertex lies outside S, i.e. the walks of the
     subgraph induced by V \\ S.  y_i(v) counts walks of length i ending at v
-    that avoid S: y_0 = 1_{V\\S}, y_i = 1_{V\\S} * (A y_{i-1})."""
+    that avoid S: y_0 = 1_{V\\S}, y_i = 1_{V\\S} * (A y_{i-1}).  Row v of A
+    holds the in-arcs u -> v, so directed graphs count walks along the arcs;
+    per-arc weights w (aligned with col_idx) weight a walk by their product."""
     import scipy.sparse as sp
-    A = sp.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    data = np.ones(g.nnz) if w is None else np.asarray(w, dtype=np.float64)
+    A = sp.csr_matrix((data, g.col_idx, g.row_ptr), shape=(g.n, g.n))
     keep = np.ones(g.n)
     keep[np.asarray(S, dtype=np.int64)] = 0.0
     x = np.ones(g.n)

@@ -687,3 +687,24 @@ def test_greedy_gains_by_complement():
             c = gain(g, grp[:j], grp[j], alpha, int(r["ell"][j]))
             assert abs(r["L1"][j] - c) <= 1e-12 * abs(c), (g.name, j, r["L1"][j], c)
 
+
+def test_group_score_by_complement_directed_and_weighted():
+    """The complement identity for directed graphs (walks follow the arcs) and
+    for per-arc weights (Sect. 4.4: a walk counts the product of its weights)."""
+    from closed_forms import group_score
+    cases = [(g, None) for g in directed_graphs()]
+    gd = inputs.rmat(10, 8, seed=6)
+    gd = inputs.from_edges(gd.n, np.repeat(np.arange(gd.n), np.diff(gd.row_ptr))[::2],
+                           gd.col_idx[::2], symmetrize=False, name="dir_rmat10")
+    cases.append((gd, None))
+    gw = inputs.barabasi_albert(2000, 3, 8)
+    cases.append((gw, sym_weights(gw, 3)))
+    for g, w in cases:
+        dmax = max(int(np.diff(g.row_ptr).max()), int(np.bincount(g.col_idx).max()), 1)
+        alpha = 0.5 / dmax  # below 1 / (max in- and out-degree)
+        for seed, size in ((1, 1), (2, 3), (3, max(1, g.n // 5))):
+            S = inputs.group(g.n, min(size, g.n), seed)
+            s, ell, _, _ = oracle.score(g, S, alpha, 1e-6, w=w)
+            c = group_score(g, S, alpha, ell, w=w)
+            assert abs(s - c) <= 1e-12 * max(abs(c), 1e-300), (g.name, size, s, c)
+
