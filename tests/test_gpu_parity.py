@@ -121,7 +121,10 @@ def test_directed_score_and_greedy(ged):
     alpha = oracle.default_alpha(g)
     assert abs(gg.default_alpha() - alpha) == 0.0
     for seed, size in [(1, 3), (2, 40)]:
-        check_score(gg, g, inputs.group(n, size, seed), alpha, tag=("dir", seed))
+        S = inputs.group(n, size, seed)
+        check_score(gg, g, S, alpha, tag=("dir", seed))
+        s, ell, B = gg.score(S, alpha, EPS, with_info=True)
+        check_by_complement(g, S, alpha, ell, s, ("dir", seed))
     rg = gg.greedy(5, alpha, EPS)
     ro = oracle.greedy(g, 5, alpha, EPS, rev=rev)
     assert list(rg["group"]) == list(ro["group"])
@@ -315,11 +318,11 @@ def load_golden(name):
 
 
 @pytest.mark.timeout(600)
-def check_by_complement(g, S, alpha, ell, score, tag):
-    """Full size, pinned without the oracle: all walks minus the walks of the
-    subgraph induced by V \\ S."""
+def check_by_complement(g, S, alpha, ell, score, tag, w=None):
+    """Pinned without the oracle: all walks minus the walks of the subgraph
+    induced by V \\ S (weighted by the product of arc weights when given)."""
     from closed_forms import group_score
-    c = group_score(g, S, alpha, ell)
+    c = group_score(g, S, alpha, ell, w=w)
     say(f"  complement {tag}: |S|={len(S)} score={score!r} closed form={c!r}")
     assert rel(score, c) <= REL, (tag, score, c)
 
@@ -453,6 +456,7 @@ def test_weighted_parity(ged):
         s, ell, B = gg.score(S, alpha, EPS, with_info=True)
         c, ell_o, B_o, _ = oracle.score(g, S, alpha, EPS, w=w)
         assert ell == ell_o and rel(s, c) <= REL, (seed, s, c)
+        check_by_complement(g, S, alpha, ell, s, ("weighted", seed), w=w)
     rg = gg.greedy(5, alpha, EPS)
     ro = oracle.greedy(g, 5, alpha, EPS, w=w)
     compare_greedy(rg, ro, "weighted")
