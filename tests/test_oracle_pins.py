@@ -14,6 +14,7 @@ the recurrences do not produce themselves:
     additive-error greedy proposition of the appendix) against brute-force OPT,
     and an exact-rational eager greedy with the same decision rule.
 """
+import itertools
 import math
 import os
 from fractions import Fraction
@@ -495,6 +496,81 @@ def test_stochastic_sample_properties():
     # different additions draw different samples; a tiny eta takes all of V \ S
     assert not np.array_equal(smp, oracle.stochastic_sample(g, S, k, eta, 5, 4))
     assert len(oracle.stochastic_sample(g, S, k, 1e-300, 5, 3)) == g.n - len(S)
+
+
+def _sample_counts(g, S, k, eta, draws, p_mod):
+    from collections import Counter
+    subsets = Counter()
+    for s in range(draws):
+        smp = oracle.stochastic_sample(g, S, k, eta, 1000 + s, s % p_mod)
+        subsets[tuple(int(x) for x in smp)] += 1
+    return subsets
+
+
+def test_stochastic_sample_uniform_subsets():
+    """The appendix on large k draws each addition's candidates uniformly at
+    random without replacement from V minus S, so every m-subset of the r
+    vertices outside S is equally likely.  n = 8, S = {0, 5}, k = 4,
+    eta = 0.3: m = ceil((8/4) ln(1/0.3)) = 3 of r = 6.  Over 100,000 seeds
+    (addition index 0, 1 or 2) the 20 subsets are compared with 1/20 each by
+    a chi-square statistic (19 degrees of freedom; its 1 - 1e-6 quantile is
+    63.7), and every vertex with m/r = 1/2 and every pair with
+    m(m-1)/(r(r-1)) = 1/5, each within 5 standard deviations.  A shuffle that
+    swaps entry j with one drawn from the whole pool instead of its unsorted
+    rest gives subset probabilities from 1/36 to 1/8 (statistic about 2e4)."""
+    g = inputs.erdos_renyi(8, 10, 5)
+    S = [0, 5]
+    k, eta, draws = 4, 0.3, 100_000
+    m, rest = 3, [1, 2, 3, 4, 6, 7]
+    r = len(rest)
+    assert math.ceil(g.n / k * math.log(1 / eta)) == m
+    subsets = _sample_counts(g, S, k, eta, draws, 3)
+    allsub = list(itertools.combinations(rest, m))
+    assert set(subsets) <= set(allsub)
+    exp = draws / len(allsub)
+    stat = sum((subsets.get(t, 0) - exp) ** 2 / exp for t in allsub)
+    assert stat < 63.7, stat
+
+    def within(count, p):
+        return abs(count - draws * p) <= 5 * math.sqrt(draws * p * (1 - p))
+
+    for v in rest:
+        assert within(sum(c for t, c in subsets.items() if v in t), m / r), v
+    for a, b in itertools.combinations(rest, 2):
+        cnt = sum(c for t, c in subsets.items() if a in t and b in t)
+        assert within(cnt, m * (m - 1) / (r * (r - 1))), (a, b)
+
+
+def test_stochastic_sample_uniform_larger_pool():
+    """The same marginals on a larger pool: n = 40, S = 4 vertices, k = 10,
+    eta = 0.1, m = ceil(4 ln 10) = 10 of r = 36.  Over 30,000 seeds each of
+    the 36 vertices appears with frequency m/r and each of the 630 pairs with
+    m(m-1)/(r(r-1)), within 5.5 standard deviations."""
+    g = inputs.erdos_renyi(40, 80, 6)
+    S = [2, 11, 23, 39]
+    k, eta, draws = 10, 0.1, 30_000
+    m = math.ceil(g.n / k * math.log(1 / eta))
+    assert m == 10
+    rest = [v for v in range(g.n) if v not in S]
+    r = len(rest)
+    subsets = _sample_counts(g, S, k, eta, draws, 5)
+    single = {v: 0 for v in rest}
+    pair = {}
+    for t, c in subsets.items():
+        assert len(t) == m
+        for v in t:
+            single[v] += c
+        for ab in itertools.combinations(t, 2):
+            pair[ab] = pair.get(ab, 0) + c
+
+    def within(count, p):
+        return abs(count - draws * p) <= 5.5 * math.sqrt(draws * p * (1 - p))
+
+    for v in rest:
+        assert within(single[v], m / r), (v, single[v])
+    p2 = m * (m - 1) / (r * (r - 1))
+    for ab in itertools.combinations(rest, 2):
+        assert within(pair.get(ab, 0), p2), (ab, pair.get(ab, 0))
 
 
 def test_stochastic_tiny_eta_is_lazy_greedy():
