@@ -68,8 +68,8 @@ def _load():
     lib.or_greedy_ex.argtypes = [ctypes.c_int64, P_I64, P_I32, P_I64, P_I32, ctypes.c_int32,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_double, ctypes.c_uint64, P_I32, ctypes.c_int32,
-                                 ctypes.c_int32, ctypes.c_int32, P_I32, P_I32, P_F64, P_F64,
-                                 P_F64, P_F64, P_I64, P_F64, P_I32]
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P_I32, P_I32,
+                                 P_F64, P_F64, P_F64, P_F64, P_I64, P_F64, P_I32]
     lib.or_greedy_ex.restype = ctypes.c_int
     lib.or_sample.argtypes = [ctypes.c_int64, P_I32, ctypes.c_int32, ctypes.c_int32,
                               ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, P_I32]
@@ -284,11 +284,13 @@ def pinit(g, S, alpha: float, ell: int, rev=None, w=None, w_rev=None) -> np.ndar
 def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
            forced_ell: int = 1, max_ell: int = 1 << 16, rev=None, with_score: bool = True,
            stochastic: bool = False, eta: float = 0.1, seed: int = 1, w=None, w_rev=None,
-           sigma=None):
+           sigma=None, stop_after: int = 0):
     """Greedy GED-Walk maximisation (lazy greedy with P-initialisation).
 
     Returns a dict: group (pick order), ell/L1/U2/L2/B/evals per pick, score
-    (GED_{<=ell*} of the final group) and score_ell.
+    (GED_{<=ell*} of the final group) and score_ell.  stop_after = m > 0
+    returns after the first m picks of the k-pick run (the separation
+    threshold stays eps/k); the arrays then hold m valid entries.
     """
     rp, ci = _arrs(g)
     rr, cr = _arrs(rev if rev is not None else g)
@@ -309,7 +311,7 @@ def greedy(g, k: int, alpha: float, eps: float, lazy: bool = True, forced=None,
                           g.n, rp.ctypes.data_as(P_I64), ci.ctypes.data_as(P_I32),
                           rr.ctypes.data_as(P_I64), cr.ctypes.data_as(P_I32), k, alpha, eps,
                           1 if lazy else 0, 1 if stochastic else 0, eta, seed,
-                          fb.ctypes.data_as(P_I32), nf, forced_ell, max_ell,
+                          fb.ctypes.data_as(P_I32), nf, forced_ell, max_ell, stop_after,
                           grp.ctypes.data_as(P_I32), t_ell.ctypes.data_as(P_I32),
                           t_L1.ctypes.data_as(P_F64), t_U2.ctypes.data_as(P_F64),
                           t_L2.ctypes.data_as(P_F64), t_B.ctypes.data_as(P_F64),

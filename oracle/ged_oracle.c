@@ -729,9 +729,10 @@ static void draw_sample(int64_t n, const uint8_t *inS, int32_t k, double eta, ui
 int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
                  const int32_t *ci_r, int32_t k, double alpha, double eps, int32_t lazy,
                  int32_t stochastic, double eta, uint64_t seed, const int32_t *forced,
-                 int32_t n_forced, int32_t forced_ell, int32_t max_ell, int32_t *out_group,
-                 int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2, double *tr_B,
-                 int64_t *tr_evals, double *out_score, int32_t *out_score_ell);
+                 int32_t n_forced, int32_t forced_ell, int32_t max_ell, int32_t stop_after,
+                 int32_t *out_group, int32_t *tr_ell, double *tr_L1, double *tr_U2,
+                 double *tr_L2, double *tr_B, int64_t *tr_evals, double *out_score,
+                 int32_t *out_score_ell);
 
 /* The sample of addition p for group S (test helper): writes the sampled ids
  * (increasing) to out and returns their number. */
@@ -764,17 +765,22 @@ int or_greedy(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp
               int32_t *out_group, int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2,
               double *tr_B, int64_t *tr_evals, double *out_score, int32_t *out_score_ell) {
   return or_greedy_ex(n, rp, ci, rp_r, ci_r, k, alpha, eps, lazy, 0, 0.0, 0, forced, n_forced,
-                      forced_ell, max_ell, out_group, tr_ell, tr_L1, tr_U2, tr_L2, tr_B, tr_evals,
-                      out_score, out_score_ell);
+                      forced_ell, max_ell, 0, out_group, tr_ell, tr_L1, tr_U2, tr_L2, tr_B,
+                      tr_evals, out_score, out_score_ell);
 }
 
 int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t *rp_r,
                  const int32_t *ci_r, int32_t k, double alpha, double eps, int32_t lazy,
                  int32_t stochastic, double eta, uint64_t seed, const int32_t *forced,
-                 int32_t n_forced, int32_t forced_ell, int32_t max_ell, int32_t *out_group,
-                 int32_t *tr_ell, double *tr_L1, double *tr_U2, double *tr_L2, double *tr_B,
-                 int64_t *tr_evals, double *out_score, int32_t *out_score_ell) {
+                 int32_t n_forced, int32_t forced_ell, int32_t max_ell, int32_t stop_after,
+                 int32_t *out_group, int32_t *tr_ell, double *tr_L1, double *tr_U2,
+                 double *tr_L2, double *tr_B, int64_t *tr_evals, double *out_score,
+                 int32_t *out_score_ell) {
   if (n < 1 || k < 1 || k > n || n_forced < 0 || n_forced > k || max_ell < 1) return OR_ERR_ARG;
+  if (stop_after < 0 || stop_after > k) return OR_ERR_ARG;
+  /* stop_after = m in [1, k) returns after the first m picks of the k-pick
+   * run (the separation threshold stays eps/k); 0 runs all k picks */
+  const int32_t stop = stop_after > 0 ? stop_after : k;
   if (stochastic && !(eta > 0.0 && eta < 1.0)) return OR_ERR_ARG;
   if (!(eps > 0.0) || !isfinite(eps)) return OR_ERR_EPS;
   double deg_max = bound_degree(n, rp, ci);
@@ -833,7 +839,7 @@ int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t 
   }
   g.ell = n_forced > 0 ? (forced_ell >= 1 ? forced_ell : 1) : 1;
 
-  while (s_size < k) {
+  while (s_size < stop) {
     /* reset: new walk length, fresh priorities */
     if (g.ell > max_ell) {
       rc = OR_ERR_ELL;
@@ -850,7 +856,7 @@ int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t 
     }
     int32_t heaps_for = -1; /* addition whose candidate set the heaps hold */
     for (;;) {
-      if (s_size == k) break;
+      if (s_size >= stop) break;
       if (stochastic && sampled_for != s_size) {
         draw_sample(n, g.inS, k, eta, seed, s_size, pool, mark);
         sampled_for = s_size;
@@ -900,13 +906,14 @@ int or_greedy_ex(int64_t n, const int64_t *rp, const int32_t *ci, const int64_t 
       s_size++;
       g.stamp++; /* S changed: every value is stale (still an upper bound) */
     }
-    if (s_size == k) break;
+    if (s_size >= stop) break;
     g.ell *= 2;
   }
   if (out_score) {
     int32_t ell_s = 0;
     double Bs = 0.0;
-    rc = or_score(n, rp, ci, out_group, k, alpha, eps, 1 << 20, out_score, &ell_s, &Bs, NULL);
+    rc = or_score(n, rp, ci, out_group, s_size, alpha, eps, 1 << 20, out_score, &ell_s, &Bs,
+                  NULL);
     if (out_score_ell) *out_score_ell = ell_s;
     if (rc) goto done;
   }

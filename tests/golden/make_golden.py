@@ -6,6 +6,19 @@ nothing here reads a GPU result.  Output: tests/golden/<name>.json.
     python tests/golden/make_golden.py ba1m      # BA n=1e6, m=5: scores + greedy k=10
     python tests/golden/make_golden.py rmat22    # R-MAT scale 22: scores + first greedy picks
     python tests/golden/make_golden.py ba2m      # BA n=2e6, m=8: sampled groups of the batch
+    python tests/golden/make_golden.py rmat22_k100   # R-MAT scale 22: greedy k=100, all picks
+
+The k=100 trace runs for hours on one core, so it is computed in segments of
+SEGMENT picks and written after each one (tests/golden/rmat22_k100.json holds
+the picks done so far; running the command again resumes).  A segment restarts
+the oracle's k-pick greedy (separation threshold eps/k) with the picks so far
+as its forced prefix and the last pick's walk length as its starting length,
+and stops it after SEGMENT more picks.  The greedy's decision at a pick is
+the exact top two of L_ell over V minus S and the separation test, whatever
+priorities the heaps held (the lazy and eager oracle greedies give identical
+traces, pinned on the CPU), so the segmented trace is the one an unbroken run
+gives; only the running evaluation counts differ (each segment counts its
+own).
 """
 import json
 import os
@@ -53,7 +66,59 @@ def batch_sample(g, alpha):
     return out
 
 
+SEGMENT = 10
+
+
+def greedy_segmented(name, k):
+    path = os.path.join(HERE, f"{name}_k{k}.json")
+    g = inputs.workload_graph(name)
+    alpha = g.default_alpha()
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+        assert rec["fingerprint"] == g.fingerprint() and rec["alpha"] == alpha
+    else:
+        rec = {"graph": name, "n": g.n, "nnz": g.nnz, "max_degree": g.max_degree,
+               "alpha": alpha, "eps": EPS, "fingerprint": g.fingerprint(), "k": k,
+               "segment": SEGMENT, "group": [], "ell": [], "L1": [], "U2": [], "L2": [],
+               "B": [], "segment_evals": [], "segment_s": []}
+    print(f"{name}: n={g.n} nnz={g.nnz}; {len(rec['group'])} of {k} picks stored", flush=True)
+    while len(rec["group"]) < k:
+        done = len(rec["group"])
+        kk = min(k, done + SEGMENT)
+        t = time.time()
+        r = oracle.greedy(g, k, alpha, EPS, forced=rec["group"],
+                          forced_ell=rec["ell"][-1] if done else 1, with_score=False,
+                          stop_after=kk)
+        dt = time.time() - t
+        assert [int(x) for x in r["group"][:done]] == rec["group"]
+        for key in ("ell", "L1", "U2", "L2", "B"):
+            conv = int if key == "ell" else float
+            rec[key] += [conv(x) for x in r[key][done:kk]]
+        rec["group"] += [int(x) for x in r["group"][done:kk]]
+        rec["segment_evals"].append(int(r["evals"][kk - 1]))
+        rec["segment_s"].append(dt)
+        rec["oracle_s"] = sum(rec["segment_s"])
+        with open(path + ".tmp", "w") as f:
+            json.dump(rec, f, indent=1)
+        os.replace(path + ".tmp", path)
+        print(f"  picks {done}..{kk - 1}: {rec['group'][done:kk]} ells={rec['ell'][done:kk]} "
+              f"evals={rec['segment_evals'][-1]} ({dt:.0f}s, total {rec['oracle_s']:.0f}s)",
+              flush=True)
+    if "score" not in rec:
+        t = time.time()
+        c, ell, B, _ = oracle.score(g, rec["group"], alpha, EPS)
+        rec.update(score=c, score_ell=ell, score_s=time.time() - t)
+        with open(path + ".tmp", "w") as f:
+            json.dump(rec, f, indent=1)
+        os.replace(path + ".tmp", path)
+        print(f"  score of the group: {c!r} ell*={ell}", flush=True)
+
+
 def main(name):
+    if name == "rmat22_k100":
+        greedy_segmented("rmat22", 100)
+        return
     g = inputs.workload_graph(name)
     alpha = g.default_alpha()
     rec = {"graph": name, "n": g.n, "nnz": g.nnz, "max_degree": g.max_degree, "alpha": alpha,

@@ -484,6 +484,38 @@ def test_weighted_greedy_is_greedy():
         S.append(int(u))
 
 
+@pytest.mark.parametrize("name", ["ba", "er"])
+def test_greedy_segments_reproduce_the_run(name):
+    """The long full-size greedy trace is computed in segments: the k-pick run
+    stopped after m picks (stop_after), restarted with those picks as its
+    forced prefix at the last pick's walk length.  The decision at each pick
+    is the exact top two of L_ell and the eps/k separation test whatever the
+    heaps held, so the segmented trace must equal the unbroken one exactly:
+    picks, walk lengths (the BA case doubles ell mid-run), L1, U2 and L2."""
+    g = (inputs.barabasi_albert(400, 3, 12) if name == "ba"
+         else inputs.erdos_renyi(300, 900, 4))
+    k = 14 if name == "ba" else 10
+    alpha = g.default_alpha()
+    full = oracle.greedy(g, k, alpha, EPS, with_score=False)
+    part = oracle.greedy(g, k, alpha, EPS, with_score=False, stop_after=4)
+    assert list(part["group"][:4]) == list(full["group"][:4])
+    grp, tr = [], {key: [] for key in ("ell", "L1", "U2", "L2")}
+    while len(grp) < k:
+        d = len(grp)
+        m = min(k, d + 3)
+        r = oracle.greedy(g, k, alpha, EPS, forced=grp, forced_ell=tr["ell"][-1] if d else 1,
+                          with_score=False, stop_after=m)
+        grp += [int(x) for x in r["group"][d:m]]
+        for key in tr:
+            tr[key] += list(r[key][d:m])
+    assert grp == [int(x) for x in full["group"]]
+    assert tr["ell"] == list(full["ell"])
+    if name == "ba":
+        assert len(set(tr["ell"])) > 1
+    for key in ("L1", "U2", "L2"):
+        np.testing.assert_array_equal(np.array(tr[key]), full[key])
+
+
 # ----------------------------------------------------------- stochastic --
 
 def test_stochastic_sample_properties():
