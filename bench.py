@@ -12,10 +12,11 @@ algorithmic bytes per launch over its average HIP-event duration, against the
 same workload.
 
 Workloads (a "step" is one pass of the hot path over one batch of input):
-  ba1m    (default) Barabasi-Albert n=1,000,000, m=5: per step the per-graph
-          precompute (t-levels, ell*), 16 single-group scores (|S|=5), greedy
-          k=10 and a batched scoring of 256 groups (|S| ~ U[1,200]).
-  rmat22  R-MAT scale 22, edge factor 16: precompute, 16 scores, greedy k=100.
+  rmat22  (default) R-MAT scale 22, edge factor 16, (0.57,0.19,0.19,0.05),
+          symmetrized: per step the per-graph precompute (t-levels, ell*),
+          16 single-group scores (|S|=5) and greedy k=100.
+  ba1m    Barabasi-Albert n=1,000,000, m=5: precompute, 16 scores (|S|=5),
+          greedy k=10 and a batched scoring of 256 groups (|S| ~ U[1,200]).
   er1k    Erdos-Renyi n=1,000, average degree 10: precompute, score |S|=5,
           greedy k=5.
   batch   Barabasi-Albert n=2,000,000, m=8: 4,096 groups (|S| ~ U[1,200])
@@ -119,16 +120,50 @@ def cpu_baseline(g, alpha, groups, budget_s=6.0, max_threads=16):
             "host": host_cpu()}
 
 
-def roofline(prof, ged, workload):
+def step_bytes(n, nnz, C, weighted=False):
+    """Algorithmic bytes of one masked walk-count step over C FP64 columns:
+    row_ptr 4(n+1), col_idx 4 nnz (+ 8 nnz weights), one read of the input
+    columns 8nC, one write of the output columns 8nC, the group bitmap n/8."""
+    return 4.0 * (n + 1) + 4.0 * nnz + 16.0 * n * C + n / 8.0 + (8.0 * nnz if weighted else 0.0)
+
+
+def oracle_greedy_context(g, name, k, rg):
+    """The oracle's greedy trace for this graph and k, when one is stored with
+    the tests (written once by tests/golden/make_golden.py): its wall time on
+    one core and whether the GPU's picks and walk lengths equal it."""
+    p = os.path.join(ROOT, "tests", "golden", f"{name}_k{k}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        rec = json.load(f)
+    if rec.get("fingerprint") != g.fingerprint():
+        return None
+    m = len(rec["group"])
+    return {"picks_stored": m, "oracle_s": rec.get("oracle_s"),
+            "oracle_s_note": "one core, single-threaded FP64 oracle, run in segments of "
+                             f"{rec.get('segment')} picks (forced-prefix replay)",
+            "same_picks": [int(x) for x in rg["group"][:m]] == rec["group"],
+            "same_ells": [int(x) for x in rg["ell"][:m]] == rec["ell"]}
+
+
+def roofline(prof, ged, workload, n, nnz, weighted=False):
+    """Dominant step kernel: step_bytes() for its column count over its
+    average launch duration (HIP events on the launch stream), against the
+    HBM peak.  The bytes the kernel's own operands occupy (32-bit counts,
+    column masks, combining inputs) are reported beside it."""
     ms = prof["dominant_ms"] / max(1, prof["dominant_launches"])
-    bytes_per = prof["dominant_bytes"] / max(1, prof["dominant_launches"])
+    C = prof["dominant_columns"]
+    bytes_per = step_bytes(n, nnz, C, weighted)
+    operand_per = prof["dominant_bytes"] / max(1, prof["dominant_launches"])
     achieved = bytes_per / (ms * 1e-3) / 1e9
-    kname = ged.kernel_name(prof["dominant_columns"], prof["dominant_kind"])
+    kname = ged.kernel_name(C, prof["dominant_kind"])
     tr = traffic_for(workload, kname)
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname,
+           "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kname, "columns": C,
            "avg_launch_us": ms * 1e3, "algorithmic_bytes_per_launch": bytes_per,
-           "launches": prof["dominant_launches"]}
+           "launches": prof["dominant_launches"],
+           "operand_bytes_per_launch": operand_per,
+           "operand_frac": operand_per / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if tr:
         # measured L2-miss bytes per launch over the same event-timed duration
         out["traffic_gbs"] = tr / (ms * 1e-3) / 1e9
@@ -186,6 +221,8 @@ def bench_graph_workload(args, torch, ged, inputs):
     gg = ged.GedGraph.from_graph(g, keep_order=args.order == "input")
     stream = torch.cuda.Stream()
     gg.set_stream(stream)
+    if args.greedy_width:
+        gg.set_greedy_width(args.greedy_width)
     alpha = gg.default_alpha()
     groups = [inputs.group(g.n, 5, 1000 + j) for j in range(max(spec["n_scores"], 16))]
     if spec["batch"]:
@@ -220,7 +257,7 @@ def bench_graph_workload(args, torch, ged, inputs):
                    "max_degree": g.max_degree, "alpha": alpha, "eps": EPS, "ell_star": info["ell"],
                    "greedy_k": spec["k"], "score_groups": spec["n_scores"],
                    "batch_groups": spec["batch"], "parallelism": "single GPU"},
-        "roofline": roofline(prof, ged, name),
+        "roofline": roofline(prof, ged, name, g.n, g.nnz),
         "greedy_s": greedy_s,
         "greedy_ells": [int(x) for x in rg["ell"]],
         "greedy_evals": int(rg["evals"][-1]),
@@ -228,7 +265,11 @@ def bench_graph_workload(args, torch, ged, inputs):
         "step_kernels_ms": prof["total_ms"] / args.steps,
         "step_kernels_frac_of_step": prof["total_ms"] / (dt * 1e3),
         "batch_tile": gg.batch_tile() if spec["batch"] else None,
+        "greedy_width": gg.greedy_width(),
     }
+    ctx = oracle_greedy_context(g, spec["graph"], spec["k"], rg)
+    if ctx:
+        out["oracle_greedy"] = ctx
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, alpha, groups)
     gg.close()
@@ -274,7 +315,7 @@ def bench_batch(args, torch, ged, inputs):
         "config": {"workload": f"batched scoring: {G} groups |S|~U[1,200] on Barabasi-Albert "
                                "n=2,000,000 m=8, FP64, eps=1e-4", "n": g.n, "nnz": g.nnz,
                    "groups": G, "tile": gg.batch_tile(), "parallelism": "single GPU"},
-        "roofline": roofline(prof, ged, "batch"),
+        "roofline": roofline(prof, ged, "batch", g.n, g.nnz),
         "batch_queries_per_s": batch_qps, "plain_queries_per_s": plain_qps,
         "batch_speedup": batch_qps / plain_qps, "plain_sample": n_seq,
         "batch_vs_plain_max_rel": maxrel,
@@ -362,7 +403,7 @@ def bench_variants(args, torch, ged, inputs, k=10, n_scores=16):
             "graph": g.name, "n": g.n, "nnz": g.nnz, "alpha": alpha,
             "score_ms": (t1 - t0) / n_scores * 1e3, "greedy_ms": (t2 - t1) * 1e3,
             "greedy_ells": [int(x) for x in rg["ell"]],
-            "roofline": roofline(prof, ged, "variants"),
+            "roofline": roofline(prof, ged, "variants", g.n, g.nnz, weighted=wt is not None),
             "oracle_score_s": o_score, "oracle_greedy_s": o_greedy,
             "scores_max_rel_vs_oracle": rel,
             "greedy_same_as_oracle": list(rg["group"]) == list(ro["group"]),
@@ -387,10 +428,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ba1m",
+    ap.add_argument("--workload", default="rmat22",
                     choices=["ba1m", "rmat22", "er1k", "batch", "serve", "variants"])
     ap.add_argument("--groups", type=int, default=4096)
     ap.add_argument("--tile", type=int, default=0, help="batch: fix the tile width (0 = autotune)")
+    ap.add_argument("--greedy-width", type=int, default=0,
+                    help="candidates per gain SpMM of the greedy (0 = the library's choice)")
     ap.add_argument("--seq-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--order", choices=("degree", "input"), default="degree",

@@ -216,6 +216,21 @@ int ged_greedy_stochastic(ged_graph *g, int32_t k, double alpha, double eps, dou
                           uint64_t seed, int32_t *out_group, double *out_score,
                           ged_greedy_trace *trace);
 
+/*
+ * Candidate batch width of the greedy: the number of candidates whose exact
+ * gains one walk-count SpMM evaluates (one column each).  The decisions do
+ * not depend on it (every batch width finds the same exact top two of L_ell,
+ * Section 3.2.2); it sets how much of each level's gather traffic a batch
+ * shares and how many gains a pick evaluates.  width is 2, 4, 8 or 16, or 0
+ * for the library's choice (the default; see ged_greedy_width).
+ * GED_ERR_ARG for another value.
+ */
+int ged_set_greedy_width(ged_graph *g, int32_t width);
+
+/* The width ged_greedy uses on this graph: the value set with
+ * ged_set_greedy_width, or the library's choice when that is 0. */
+int32_t ged_greedy_width(const ged_graph *g);
+
 /* ------------------------------------------------------------ profiling --- */
 
 typedef struct {

@@ -482,6 +482,7 @@ struct GreedyCtx {
   int sub_col = -1;
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
+  int layout_C = 0;  // batch width the zero-state flags above were kept for
   StepWs ws1, ws1r, wsC;
   int64_t evals = 0;
   int rounds = 0;
@@ -504,6 +505,8 @@ void greedy_forget(const ged_graph *g) {
   std::lock_guard<std::mutex> lk(g_greedy_mu);
   g_greedy.erase(g);
 }
+
+int greedy_width_for(const ged_graph *g) { return g->greedy_width > 0 ? g->greedy_width : 8; }
 
 static void ensure_levels_cap(GreedyCtx &c, int ell) {
   if (ell <= c.Lcap) return;
@@ -980,7 +983,12 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.g = g;
   c.st = g->stream;
   c.n = n;
-  c.C = 8;
+  c.C = greedy_width_for(g);
+  if (c.C != c.layout_C) {  // the stored levels' layout changes with the width
+    c.d1_zeroed = nullptr;
+    c.dc1_zeroed = nullptr;
+    c.layout_C = c.C;
+  }
   c.split = split_ok(g);
   c.evals = 0;
   c.rounds = 0;
@@ -1158,6 +1166,17 @@ extern "C" int ged_greedy(ged_graph *g, int32_t k, double alpha, double eps, int
     return greedy_run(g, k, alpha, eps, 0.0, 0, false, out_group, out_score, trace);
   });
 }
+
+extern "C" int ged_set_greedy_width(ged_graph *g, int32_t width) {
+  if (!g) return fail(GED_ERR_ARG, "null graph");
+  if (width != 0 && width != 2 && width != 4 && width != 8 && width != 16)
+    return fail(GED_ERR_ARG, "greedy width must be 0, 2, 4, 8 or 16");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  g->greedy_width = width;
+  return GED_OK;
+}
+
+extern "C" int32_t ged_greedy_width(const ged_graph *g) { return g ? greedy_width_for(g) : 0; }
 
 extern "C" int ged_greedy_stochastic(ged_graph *g, int32_t k, double alpha, double eps,
                                      double eta, uint64_t seed, int32_t *out_group,

@@ -432,6 +432,8 @@ struct ged_graph {
   hipEvent_t score_done = nullptr;  // recorded after the result copy
   // batched scoring
   int32_t batch_tile = 0;
+  // greedy candidate batch width (0 = the library's choice)
+  int32_t greedy_width = 0;
   // split scoring
   ged::DBuf omega2;             // uint64 [n] walks of length 2 ending at v (unweighted)
   bool omega2_ready = false;
@@ -499,6 +501,8 @@ int score_group(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, dou
 void batch_forget(const ged_graph *g);
 // Drop the greedy workspace of a graph that is being destroyed.
 void greedy_forget(const ged_graph *g);
+// Candidate batch width the greedy uses on g.
+int greedy_width_for(const ged_graph *g);
 
 // Split scoring (ged_split.hip).
 bool split_ok(const ged_graph *g);

@@ -585,7 +585,7 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_CNT32, OUT_TILE32)
     GED_CASE(IN_CNT32, OUT_COMBINE32L)
   }
-  if constexpr (C == 8) {  // the greedy's candidate batches
+  if constexpr (C == 2 || C == 4 || C == 8 || C == 16) {  // the greedy's candidate batches
     GED_CASE(IN_ONEHOT, OUT_GAINCOMB)
     GED_CASE(IN_VEC, OUT_GAINCOMB)
     if constexpr (!WGT) {

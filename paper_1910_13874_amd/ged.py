@@ -86,6 +86,8 @@ _sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, 
                                        ctypes.c_double, P_F64])
 _sig("ged_batch_tile", ctypes.c_int32, [c_graph_p])
 _sig("ged_set_batch_tile", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_set_greedy_width", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_greedy_width", ctypes.c_int32, [c_graph_p])
 _sig("ged_greedy", ctypes.c_int, [c_graph_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                   P_I32, P_F64, ctypes.POINTER(GreedyTrace)])
 _sig("ged_greedy_stochastic", ctypes.c_int,
@@ -267,6 +269,13 @@ class GedGraph:
     def set_batch_tile(self, tile):
         """Fix the batched-scoring tile width (0 = autotune on the next call)."""
         _ck(_lib.ged_set_batch_tile(self.handle, int(tile)), "ged_set_batch_tile")
+
+    def set_greedy_width(self, width):
+        """Candidates per gain SpMM of the greedy (2, 4, 8, 16; 0 = library's choice)."""
+        _ck(_lib.ged_set_greedy_width(self.handle, int(width)), "ged_set_greedy_width")
+
+    def greedy_width(self):
+        return _lib.ged_greedy_width(self.handle)
 
     def _greedy(self, fn, k, alpha, eps, extra, forced, forced_ell, with_score):
         grp = np.zeros(k, dtype=np.int32)

@@ -111,10 +111,16 @@ def test_score_deterministic_and_alpha_change(ged):
     gg.close()
 
 
-def test_directed_score_and_greedy(ged):
+def directed_graph():
+    """Directed G(n, M)-like graph: 2,000 vertices, 9,000 uniform arcs, seed 61."""
     n = 2000
     r = inputs.uniform_ints(2 * 9000, n, 61)
-    g = inputs.from_edges(n, r[0::2], r[1::2], symmetrize=False, name="dir2k")
+    return inputs.from_edges(n, r[0::2], r[1::2], symmetrize=False, name="dir2k")
+
+
+def test_directed_score_and_greedy(ged):
+    g = directed_graph()
+    n = g.n
     rev = inputs.reverse(g)
     say(f"[directed] n={g.n} nnz={g.nnz}")
     gg = ged.GedGraph.from_graph(g)
@@ -196,6 +202,35 @@ def test_greedy_parity(ged, name, k):
     rg = gg.greedy(k, alpha, EPS)
     ro = oracle.greedy(g, k, alpha, EPS)
     compare_greedy(rg, ro, name)
+    gg.close()
+
+
+@pytest.mark.parametrize("width", [2, 4, 16])
+def test_greedy_width_parity(ged, width):
+    """The candidate batch width changes how many gains one SpMM evaluates,
+    not the decisions: every width gives the oracle's picks, walk lengths and
+    gains, on graphs whose batches take the 32-bit count levels (ER), the
+    pushed and dense second gain levels (BA), FP64 levels (R-MAT), and the
+    level-by-level chains of a directed graph."""
+    cases = [("ba20k", GRAPHS["ba20k"](), 10), ("rmat16", GRAPHS["rmat16"](), 8),
+             ("er_sparse", inputs.erdos_renyi(3000, 4500, 57), 6)]
+    for name, g, k in cases:
+        say(f"[greedy width {width}] {name} k={k}")
+        gg = ged.GedGraph.from_graph(g)
+        gg.set_greedy_width(width)
+        assert gg.greedy_width() == width
+        alpha = g.default_alpha()
+        compare_greedy(gg.greedy(k, alpha, EPS), oracle.greedy(g, k, alpha, EPS),
+                       f"{name} width {width}")
+        gg.close()
+    gd = directed_graph()
+    rev = inputs.reverse(gd)
+    say(f"[greedy width {width}] directed n={gd.n}")
+    gg = ged.GedGraph.from_graph(gd)
+    gg.set_greedy_width(width)
+    alpha = oracle.default_alpha(gd, None)
+    compare_greedy(gg.greedy(6, alpha, EPS), oracle.greedy(gd, 6, alpha, EPS, rev=rev),
+                   f"directed width {width}")
     gg.close()
 
 
@@ -317,7 +352,6 @@ def load_golden(name):
         return json.load(f)
 
 
-@pytest.mark.timeout(600)
 def check_by_complement(g, S, alpha, ell, score, tag, w=None):
     """Pinned without the oracle: all walks minus the walks of the subgraph
     induced by V \\ S (weighted by the product of arc weights when given)."""
@@ -329,9 +363,10 @@ def check_by_complement(g, S, alpha, ell, score, tag, w=None):
 
 def check_gains_by_complement(g, rg, alpha, picks, tag):
     """Full size, pinned without the oracle: each pick's recorded gain is the
-    count of walks that avoid the previous picks and meet this one."""
+    count of walks that avoid the previous picks and meet this one.  picks is
+    a count (the first picks) or a list of pick indices."""
     from closed_forms import gain
-    for j in range(picks):
+    for j in (range(picks) if isinstance(picks, int) else picks):
         grp = rg["group"]
         c = gain(g, grp[:j], int(grp[j]), alpha, int(rg["ell"][j]))
         say(f"  gain {tag} pick {j}: ell={rg['ell'][j]} L={rg['L1'][j]!r} closed form={c!r}")
@@ -348,6 +383,7 @@ def check_whole_set(gg, g, alpha):
     assert rel(s, c) <= REL, (s, c)
 
 
+@pytest.mark.timeout(600)
 def test_full_size_ba1m(ged):
     """BA n=1e6, m=5 at full size: oracle scores and the oracle's greedy k=10 trace."""
     gold = load_golden("ba1m")
@@ -369,6 +405,7 @@ def test_full_size_ba1m(ged):
     gg.close()
 
 
+@pytest.mark.timeout(600)
 def test_full_size_batch_ba2m(ged):
     """The batched workload at full size (BA n=2e6, m=8, 4,096 groups |S|~U[1,200])
     with the autotuned tile: sampled columns against the oracle, every column
@@ -408,9 +445,12 @@ def test_full_size_batch_ba2m(ged):
 
 @pytest.mark.timeout(900)
 def test_full_size_rmat22(ged):
-    """R-MAT scale 22 at full size: oracle scores, the oracle's first picks, and
-    the separation invariants of a k=100 run."""
+    """R-MAT scale 22 at full size (the greedy k=100 workload): oracle scores,
+    the oracle's whole k=100 trace (picks, walk lengths, L1, U2, L2 at every
+    pick, through the doubling of ell from 8 to 16), and the recorded gains of
+    picks at both walk lengths against the complement closed form."""
     gold = load_golden("rmat22")
+    gk = load_golden("rmat22_k100")
     g = inputs.workload_graph("rmat22")
     assert g.fingerprint() == gold["fingerprint"]
     say(f"[full rmat22] n={g.n} nnz={g.nnz}")
@@ -422,16 +462,23 @@ def test_full_size_rmat22(ged):
         assert ell == rec["ell"] and rel(s, rec["score"]) <= REL, (rec["seed"], s, rec["score"])
         check_by_complement(g, S, alpha, ell, s, rec["seed"])
     check_whole_set(gg, g, alpha)
-    gr = gold["greedy"]
     k = 100
+    assert gk["fingerprint"] == gold["fingerprint"] and gk["k"] == k
     rg = gg.greedy(k, alpha, EPS)
-    kk = gr["k"]
-    assert list(rg["group"][:kk]) == gr["group"]
-    assert list(rg["ell"][:kk]) == gr["ell"]
-    check_gains_by_complement(g, rg, alpha, min(kk, 2), "rmat22")
+    kk = len(gk["group"])
+    say(f"  oracle trace: {kk} of {k} picks stored, ells {sorted(set(gk['ell']))}")
+    assert kk >= 1
     for j in range(kk):
-        assert rel(rg["L1"][j], gr["L1"][j]) <= REL
-    # any-size properties of the rest of the run
+        assert int(rg["group"][j]) == gk["group"][j], (j, rg["group"][j], gk["group"][j])
+        assert int(rg["ell"][j]) == gk["ell"][j], (j, rg["ell"][j], gk["ell"][j])
+        assert rel(rg["L1"][j], gk["L1"][j]) <= REL, (j, rg["L1"][j], gk["L1"][j])
+        if gk["U2"][j] == gk["U2"][j]:  # not NaN
+            assert rel(rg["U2"][j], gk["U2"][j]) <= REL, (j, rg["U2"][j], gk["U2"][j])
+            assert rel(rg["L2"][j], gk["L2"][j]) <= REL, (j, rg["L2"][j], gk["L2"][j])
+    if "score" in gk:
+        assert rel(rg["score"], gk["score"]) <= REL and rg["score_ell"] == gk["score_ell"]
+    check_gains_by_complement(g, rg, alpha, [j for j in (0, 1, 6, 50, 99) if j < kk], "rmat22")
+    # any-size properties of the whole run
     assert len(set(int(x) for x in rg["group"])) == k
     assert np.all(np.diff(rg["ell"]) >= 0)
     for j in range(k):

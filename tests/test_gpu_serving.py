@@ -1,11 +1,43 @@
-"""Serving (continuous batching): every result equals the same request run alone."""
+"""Serving (continuous batching): every result equals the same request run
+alone (scores to 1e-12, groups identical) and the CPU oracle on the same
+graph, alpha and eps (scores to 1e-9 relative; greedy groups identical, with
+the group's final score to 1e-9)."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1910_13874_amd import inputs
 
 pytestmark = pytest.mark.gpu
 EPS = 1e-4
+REL = 1e-9
+
+
+def rel(a, b):
+    return 0.0 if a == b else abs(a - b) / max(abs(a), abs(b))
+
+
+class OracleCheck:
+    """Checks served results against the oracle on the same graph, alpha and
+    eps (directed graphs need the reverse graph for the greedy's backward
+    chain; weighted graphs their arc weights)."""
+
+    def __init__(self, g, alpha, w=None):
+        self.g, self.alpha, self.w = g, alpha, w
+        self.rev = inputs.reverse(g) if g.directed else None
+        self.greedy_cache = {}
+
+    def score(self, S, served, tag):
+        c, ell, B, _ = oracle.score(self.g, S, self.alpha, EPS, w=self.w)
+        assert rel(served, c) <= REL, (tag, served, c)
+
+    def greedy(self, k, grp, served_score, tag):
+        if k not in self.greedy_cache:
+            self.greedy_cache[k] = oracle.greedy(self.g, k, self.alpha, EPS, rev=self.rev,
+                                                 w=self.w, w_rev=self.w)
+        ro = self.greedy_cache[k]
+        assert [int(x) for x in grp] == [int(x) for x in ro["group"]], (tag, grp, ro["group"])
+        assert rel(served_score, ro["score"]) <= REL, (tag, served_score, ro["score"])
 
 
 @pytest.fixture(scope="module")
@@ -29,16 +61,20 @@ def test_mix_equals_alone(ged):
     out, wall = serve.run_server(srv, gids, reqs)
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["peak_columns"] > 1
+    orc = [OracleCheck(g, a) for g, a in zip(gs, alphas)]
     for j, q in enumerate(reqs):
         kind, status, score, lat, grp = out[j]
         assert status == 0
         if q["kind"] == 0:
             alone = ggs[q["g"]].score(q["S"], alphas[q["g"]], EPS)
             assert abs(score - alone) <= 1e-12 * max(abs(alone), 1e-300), (j, score, alone)
+            orc[q["g"]].score(q["S"], score, j)
         else:
             alone = ggs[q["g"]].greedy(q["k"], alphas[q["g"]], EPS)
             assert list(grp) == list(alone["group"])
             assert abs(score - alone["score"]) <= 1e-12 * abs(alone["score"])
+            orc[q["g"]].greedy(q["k"], grp, score, j)
+    print(f"[serving mix] {len(reqs)} results checked against the oracle", flush=True)
     srv.close()
     for gg in ggs:
         gg.close()
@@ -58,11 +94,13 @@ def test_burst_fills_wide_tiles(ged):
     out, wall = serve.run_server(srv, [gid], reqs)
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["peak_columns"] > 32, st
+    orc = OracleCheck(g, alpha)
     for j, q in enumerate(reqs):
         kind, status, score, lat, grp = out[j]
         assert status == 0
         alone = gg.score(q["S"], alpha, EPS)
         assert abs(score - alone) <= 1e-12 * max(abs(alone), 1e-300), (j, score, alone)
+        orc.score(q["S"], score, j)
     srv.close()
     gg.close()
 
@@ -117,15 +155,18 @@ def test_directed_and_weighted_lanes(ged):
     reqs = serve.make_requests([gd.n, gw.n], 160, 4e4, seed=11, greedy_frac=0.05)
     out, wall = serve.run_server(srv, gids, reqs)
     assert srv.stats()["completed"] == len(reqs)
+    orc = [OracleCheck(gd, alphas[0]), OracleCheck(gw, alphas[1], w=w)]
     for j, q in enumerate(reqs):
         kind, status, score, lat, grp = out[j]
         assert status == 0
         if q["kind"] == 0:
             alone = ggs[q["g"]].score(q["S"], alphas[q["g"]], EPS)
             assert abs(score - alone) <= 1e-12 * max(abs(alone), 1e-300), (j, q["g"], score, alone)
+            orc[q["g"]].score(q["S"], score, (j, q["g"]))
         else:
             alone = ggs[q["g"]].greedy(q["k"], alphas[q["g"]], EPS)
             assert list(grp) == list(alone["group"])
+            orc[q["g"]].greedy(q["k"], grp, score, (j, q["g"]))
     srv.close()
     for gg in ggs:
         gg.close()
