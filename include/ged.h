@@ -48,8 +48,10 @@ enum ged_status {
   GED_ERR_GRAPH = -5,  /* malformed CSR */
   GED_ERR_NOMEM = -6,  /* device allocation failed, or over the serving budget */
   GED_ERR_DEVICE = -7, /* a HIP call failed (message in ged_last_error) */
-  GED_ERR_BUSY = -8,   /* serving queue full */
-  GED_ERR_ELL = -9     /* walk length limit (65536) reached */
+  GED_ERR_BUSY = -8,   /* serving queue full; or the graph is registered with a server */
+  GED_ERR_ELL = -9,    /* walk length limit (65536) reached */
+  GED_ERR_CANCELLED = -10, /* serving: the request was cancelled */
+  GED_ERR_DEADLINE = -11   /* serving: the request passed its deadline */
 };
 
 #define GED_UNDIRECTED 1u /* col_idx is symmetric: rows are neighbour lists */
@@ -173,8 +175,22 @@ int ged_score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members
 int32_t ged_batch_tile(const ged_graph *g);
 
 /* Fix the tile width of ged_score_batch (a power of two <= 64), or 0 to let
- * the autotuner choose on the next call. */
+ * the autotuner choose it (and the row-split threshold) on the next call. */
 int ged_set_batch_tile(ged_graph *g, int32_t tile);
+
+/*
+ * Row-split threshold of ged_score_batch's tiles, as a divisor cut_div of a
+ * step block's staging capacity (2048 FP64 values, i.e. 2048 / C arcs at C
+ * columns, twice that for 32-bit counts gathered as column pairs): rows with
+ * more arcs than capacity / cut_div are cut into fixed segments summed by a
+ * fix-up pass, and no block takes more arcs than that.  cut_div 1, 2 or 4,
+ * or 0 to let the autotuner choose it after the tile width (it races 2 and 4
+ * against 1 at the chosen width).  Results are the same to rounding for any
+ * threshold; a graph's batch scores are reproducible bit for bit while it is
+ * fixed.  ged_batch_row_cut returns the divisor in use (0 before tuning).
+ */
+int ged_set_batch_row_cut(ged_graph *g, int32_t cut_div);
+int32_t ged_batch_row_cut(const ged_graph *g);
 
 typedef struct {
   /* per-pick outputs, arrays of length k (any may be NULL) */
@@ -221,14 +237,30 @@ int ged_greedy_stochastic(ged_graph *g, int32_t k, double alpha, double eps, dou
  * gains one walk-count SpMM evaluates (one column each).  The decisions do
  * not depend on it (every batch width finds the same exact top two of L_ell,
  * Section 3.2.2); it sets how much of each level's gather traffic a batch
- * shares and how many gains a pick evaluates.  width is 2, 4, 8 or 16, or 0
- * for the library's choice (the default; see ged_greedy_width).
+ * shares and how many gains a pick evaluates.  width 2, 4, 8 or 16 makes
+ * every batch that wide; 0 (the default) starts each separation round with a
+ * batch of 2 (of 8 on graphs of at most 2^20 arcs, whose steps cost the same
+ * at any width) and doubles the width of the round's later batches up to 16.
  * GED_ERR_ARG for another value.
  */
 int ged_set_greedy_width(ged_graph *g, int32_t width);
 
-/* The width ged_greedy uses on this graph: the value set with
- * ged_set_greedy_width, or the library's choice when that is 0. */
+/*
+ * Device memory of the greedy, for callers that plan it: *estimate receives
+ * an upper bound of the bytes a ged_greedy call of k picks at (alpha, eps)
+ * can leave allocated on the handle (its workspace, grown to the largest walk
+ * length k can reach -- the first power of two whose tail bound is below
+ * eps/k, where every round separates -- and the widest candidate batch, and
+ * the total-walk levels beyond ell*), counted from nothing; *held (nullable)
+ * the bytes that workspace holds now.  The handle keeps the workspace for
+ * later calls.  The single-group score of the final group uses the handle's
+ * score workspace, which is not included.  May run the precomputation.
+ */
+int ged_greedy_footprint(ged_graph *g, int32_t k, double alpha, double eps, int64_t *estimate,
+                         int64_t *held);
+
+/* The width of a round's first candidate batch on this graph: the value set
+ * with ged_set_greedy_width, or the default's first width when that is 0. */
 int32_t ged_greedy_width(const ged_graph *g);
 
 /* ------------------------------------------------------------ profiling --- */
@@ -289,8 +321,12 @@ typedef struct {
  * Every result equals the same request run alone (scores to ~1e-12).
  */
 int ged_server_create(const ged_server_config *cfg, ged_server **out);
-/* Register a graph (the handle stays owned by the caller and must outlive the
- * server); *graph_id receives its index. */
+/* Register a graph at (alpha, eps); *graph_id receives its index.  The handle
+ * stays owned by the caller and must outlive the server; until
+ * ged_server_destroy the server's threads read its precomputation, so calls
+ * on the handle through other entry points must use the same alpha and eps
+ * (others, and ged_invalidate / ged_set_tail_bound, give GED_ERR_BUSY).  A
+ * handle serves one server at a time. */
 int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, double eps, int32_t *graph_id);
 int ged_server_submit_score(ged_server *s, int32_t graph_id, const int32_t *S, int32_t s_len,
                             uint64_t *req_id);
@@ -301,8 +337,29 @@ int ged_server_poll(ged_server *s, ged_result *out, int32_t max, int32_t *n_out,
                     int64_t timeout_us);
 /* Picks of a finished greedy request (out int32[k]); valid until destroy. */
 int ged_server_group(ged_server *s, uint64_t req_id, int32_t *out, int32_t k);
+/*
+ * Ask a request to stop.  GED_OK: it will complete with status
+ * GED_ERR_CANCELLED -- a waiting request is dropped by the scheduler's next
+ * pass, a running greedy stops before its next separation round (its device
+ * memory stays with the graph for later requests).  GED_ERR_BUSY: a score
+ * already on the device, which completes normally.  GED_ERR_ARG: unknown or
+ * finished id.
+ */
+int ged_server_cancel(ged_server *s, uint64_t req_id);
+/*
+ * Absolute deadline of a request, in the clock of ged_result.t_submit_us
+ * (steady clock, microseconds); 0 removes it.  A request not finished by its
+ * deadline stops as ged_server_cancel would stop it and completes with
+ * GED_ERR_DEADLINE (scores already on the device complete normally).
+ * Deadlines are checked about every half millisecond.  GED_ERR_ARG for an
+ * unknown or finished id.
+ */
+int ged_server_set_deadline(ged_server *s, uint64_t req_id, double deadline_us);
 /* Counters: [0] admitted, [1] completed, [2] steps launched, [3] peak bytes
- * in use, [4] peak active score columns, [5] rejected (budget). */
+ * counted against the budget (lane pools, the graphs' single-score
+ * workspaces, greedy working memory held with each graph, reservations of
+ * running greedy requests), [4] peak active score columns, [5] rejected
+ * (budget). */
 int ged_server_stats(ged_server *s, int64_t *out6);
 int ged_server_destroy(ged_server *s);
 

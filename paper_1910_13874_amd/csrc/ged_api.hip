@@ -26,27 +26,47 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
-Partition &partition(ged_graph *g, int C, bool reverse) {
+// Partitions are kept under key C * 8 + cut_div (narrow ones negated).
+static int part_key(int C, int cut_div) { return C * 8 + cut_div; }
+
+static void check_cut(int cut_div) {
+  if (cut_div != 1 && cut_div != 2 && cut_div != 4)
+    throw HipError{GED_ERR_ARG, "row-split threshold divisor must be 1, 2 or 4"};
+}
+
+Partition &partition(ged_graph *g, int C, bool reverse, int cut_div) {
+  check_cut(cut_div);
+  std::lock_guard<std::mutex> lk(g->parts_mu);
   auto &m = reverse ? g->parts_r : g->parts;
-  auto it = m.find(C);
+  const int key = part_key(C, cut_div);
+  auto it = m.find(key);
   if (it != m.end()) return *it->second;
   auto p = std::make_unique<Partition>();
-  build_partition(*p, reverse ? g->h_rp_r : g->h_rp, C, C);
+  build_partition(*p, reverse ? g->h_rp_r : g->h_rp, C, C, cut_div);
   Partition &ref = *p;
-  m[C] = std::move(p);
+  m[key] = std::move(p);
   return ref;
 }
 
-Partition &partition_narrow(ged_graph *g, int C) {
-  if (C < 2) return partition(g, C);
+Partition &partition_narrow(ged_graph *g, int C, int cut_div) {
+  if (C < 2) return partition(g, C, false, cut_div);
+  check_cut(cut_div);
+  std::lock_guard<std::mutex> lk(g->parts_mu);
   auto &m = g->parts;
-  auto it = m.find(-C);  // narrow partitions under negative keys
+  const int key = -part_key(C, cut_div);
+  auto it = m.find(key);
   if (it != m.end()) return *it->second;
   auto p = std::make_unique<Partition>();
-  build_partition(*p, g->h_rp, C, C / 2);
+  build_partition(*p, g->h_rp, C, C / 2, cut_div);
   Partition &ref = *p;
-  m[-C] = std::move(p);
+  m[key] = std::move(p);
   return ref;
+}
+
+const Partition *partition_if_built(ged_graph *g, int C) {
+  std::lock_guard<std::mutex> lk(g->parts_mu);
+  auto it = g->parts.find(part_key(C, 1));
+  return it == g->parts.end() ? nullptr : it->second.get();
 }
 
 StepArgs base_args(ged_graph *g, bool reverse) {
@@ -112,6 +132,18 @@ double comb_bound(ged_graph *g, double alpha, double W_ell) {
   // decayed total W_ell = alpha^ell sum_x omega_ell(x).
   const double D = g->weighted ? g->max_wdeg : (double)g->max_deg;
   return alpha * (D / (1.0 - alpha * D)) * W_ell;
+}
+
+size_t score_bytes_held(const ged_graph *g) {
+  size_t b = 0;
+  for (const DBuf *d : {&g->mask, &g->vec[0], &g->vec[1], &g->s_levels, &g->acc, &g->s_dev,
+                        &g->sws.blk, &g->sws.seg, &g->sws.lng, &g->sws.red2,
+                        &g->split_ws.cnt1, &g->split_ws.cnt2, &g->split_ws.lv, &g->split_ws.wl,
+                        &g->split_ws.wl_n, &g->split_ws.wl3, &g->split_ws.wl3_n,
+                        &g->split_ws.ws.blk, &g->split_ws.ws.seg, &g->split_ws.ws.lng,
+                        &g->split_ws.ws.red2, &g->split_tmask, &g->split_in})
+    b += d->bytes;
+  return b;
 }
 
 int check_alpha_eps(ged_graph *g, double alpha, double eps) {
@@ -189,6 +221,8 @@ static double level_sum_to_host(ged_graph *g, const Partition &p, const StepArgs
 int prepare(ged_graph *g, double alpha, double eps) {
   int rc = check_alpha_eps(g, alpha, eps);
   if (rc) return rc;
+  if (g->served && (alpha != g->served_alpha || eps != g->served_eps))
+    return fail(GED_ERR_BUSY, "the graph is registered with a server at another alpha and eps");
   PrepCache &pc = g->prep;
   if (pc.valid && pc.alpha == alpha && pc.eps == eps) return GED_OK;
   hipStream_t st = g->stream;
@@ -688,6 +722,7 @@ extern "C" int ged_set_tail_bound(ged_graph *g, int32_t kind) {
   if (kind != GED_BOUND_COMBINATORIAL && kind != GED_BOUND_SPECTRAL)
     return fail(GED_ERR_ARG, "unknown tail bound");
   std::lock_guard<std::recursive_mutex> lk(g->mu);
+  if (g->served) return fail(GED_ERR_BUSY, "the graph is registered with a server");
   return guarded([&]() -> int {
     GED_HIP(hipStreamSynchronize(g->stream));
     if (g->bound_kind != kind) {
@@ -713,6 +748,7 @@ extern "C" int ged_sigma_max(ged_graph *g, double *out_sigma) {
 extern "C" int ged_invalidate(ged_graph *g) {
   if (!g) return fail(GED_ERR_ARG, "graph is null");
   std::lock_guard<std::recursive_mutex> lk(g->mu);
+  if (g->served) return fail(GED_ERR_BUSY, "the graph is registered with a server");
   return guarded([&]() -> int {
     GED_HIP(hipStreamSynchronize(g->stream));
     g->prep.valid = false;

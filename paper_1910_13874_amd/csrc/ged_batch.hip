@@ -68,117 +68,143 @@ void batch_forget(const ged_graph *g) {
   g_batch.erase(g);
 }
 
+// The race both autotuners run: every candidate width at the threshold the
+// caller fixed (or the full LDS capacity), then -- when the threshold is left
+// to the tuner -- thresholds of 1/2 and 1/4 of the capacity at the chosen
+// width.  time_per_col(C, cut_div) returns milliseconds per column, or throws
+// HipError{GED_ERR_NOMEM} when the width does not fit (wider ones are then
+// skipped).  A candidate replaces the best so far only if it is faster per
+// column by the factor `margin` (wider tiles hold more memory and leave more
+// columns idle in a batch's last tile; lower thresholds add segments).
+template <class F>
+static int race_tile(ged_graph *g, std::initializer_list<int> widths, double margin,
+                     F &&time_per_col) {
+  const int cut0 = g->batch_cut_div > 0 ? g->batch_cut_div : 1;
+  double best = 1e300;
+  int best_c = g->batch_tile > 0 ? g->batch_tile : 16, best_cut = cut0;
+  std::vector<int> ws;
+  if (g->batch_tile > 0)
+    ws.push_back(g->batch_tile);
+  else
+    ws.assign(widths.begin(), widths.end());
+  for (int C : ws) {
+    double t;
+    try {
+      t = time_per_col(C, cut0);
+    } catch (const HipError &e) {
+      if (e.code != GED_ERR_NOMEM) throw;
+      break;  // wider tiles do not fit either
+    }
+    if (t < best * margin) {
+      best = t;
+      best_c = C;
+    }
+  }
+  if (g->batch_cut_div == 0)
+    for (int d : {2, 4}) {
+      const double t = time_per_col(best_c, d);
+      if (t < best * 0.97) {
+        best = t;
+        best_cut = d;
+      }
+    }
+  g->batch_tile = best_c;
+  g->batch_cut_div = best_cut;
+  return best_c;
+}
+
 // Step time per column for each candidate tile width; the fastest wins.  Each
 // candidate runs three ping-pong steps (X -> Y -> X -> Y) and the last two
 // are timed, so the cache state (the dense tiles of a step stay in the
 // Infinity Cache only when they fit) is that of a running batch.
 static int autotune_tile(ged_graph *g, BatchWs &b) {
-  if (g->batch_tile > 0) return g->batch_tile;
+  if (g->batch_tile > 0 && g->batch_cut_div > 0) return g->batch_tile;
   const int n = (int)g->n;
   hipStream_t st = g->stream;
-  const int cands[] = {4, 8, 16, 32, 64};
-  double best = 1e300;
-  int best_c = 16;
   hipEvent_t e0, e1;
   GED_HIP(hipEventCreate(&e0));
   GED_HIP(hipEventCreate(&e1));
-  for (int C : cands) {
-    try {
-      Partition &p = partition(g, C);
-      StepWs ws;
-      ws.fit(p);
-      b.X.ensure(sizeof(double) * (size_t)n * C);
-      b.Y.ensure(sizeof(double) * (size_t)n * C);
-      launch_fill_f64(b.X.as<double>(), 0.0, (size_t)n * C, st);
-      StepArgs a = base_args(g);
-      ws.into(a);
-      a.C = C;
-      a.alpha = g->prep.alpha;
-      a.tmask = b.tmask.as<const uint64_t>();
-      a.inj = g->prep.t_levels.as<const double>();
-      for (int r = 0; r < 3; ++r) {
-        if (r == 1) GED_HIP(hipEventRecord(e0, st));
-        a.X = ((r & 1) ? b.Y : b.X).as<const double>();
-        a.Y = ((r & 1) ? b.X : b.Y).as<double>();
-        a.accum = r > 0;
-        launch_step(p, a, IN_VEC, OUT_TILE, st);
-      }
-      launch_reduce(p, a, nullptr, nullptr, nullptr, st, ws.scratch());
-      GED_HIP(hipEventRecord(e1, st));
-      GED_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      GED_HIP(hipEventElapsedTime(&ms, e0, e1));
-      const double per_col = ms / C;
-      if (per_col < best) {
-        best = per_col;
-        best_c = C;
-      }
-    } catch (const HipError &e) {
-      if (e.code != GED_ERR_NOMEM) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        throw;
-      }
-      break;  // wider tiles do not fit
+  auto timed = [&](int C, int cut) -> double {
+    Partition &p = partition(g, C, false, cut);
+    StepWs ws;
+    ws.fit(p);
+    b.X.ensure(sizeof(double) * (size_t)n * C);
+    b.Y.ensure(sizeof(double) * (size_t)n * C);
+    launch_fill_f64(b.X.as<double>(), 0.0, (size_t)n * C, st);
+    StepArgs a = base_args(g);
+    ws.into(a);
+    a.C = C;
+    a.alpha = g->prep.alpha;
+    a.tmask = b.tmask.as<const uint64_t>();
+    a.inj = g->prep.t_levels.as<const double>();
+    for (int r = 0; r < 3; ++r) {
+      if (r == 1) GED_HIP(hipEventRecord(e0, st));
+      a.X = ((r & 1) ? b.Y : b.X).as<const double>();
+      a.Y = ((r & 1) ? b.X : b.Y).as<double>();
+      a.accum = r > 0;
+      launch_step(p, a, IN_VEC, OUT_TILE, st);
     }
+    launch_reduce(p, a, nullptr, nullptr, nullptr, st, ws.scratch());
+    GED_HIP(hipEventRecord(e1, st));
+    GED_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GED_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms / C;
+  };
+  try {
+    const int C = race_tile(g, {4, 8, 16, 32, 64}, 1.0, timed);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return C;
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  g->batch_tile = best_c;
-  return best_c;
 }
 
 // Split scoring: the same race over the dense levels of a split tile (the
-// level-(s+1) step on count rows and the combining step), at C = 8..64.
-static int autotune_split(ged_graph *g, BatchWs &b, const SplitPlan &pl) {
-  if (g->batch_tile > 0) return g->batch_tile;
+// level-(s+1) step on count rows and the combining step), at C = 8..64; best
+// of two timed passes after a warm-up.
+static int autotune_split(ged_graph *g, BatchWs &b, const SplitPlan &pl0) {
+  if (g->batch_tile > 0 && g->batch_cut_div > 0) return g->batch_tile;
   hipStream_t st = g->stream;
-  const int cands[] = {8, 16, 32, 64};
-  double best = 1e300;
-  int best_c = 16;
   hipEvent_t e0, e1;
   GED_HIP(hipEventCreate(&e0));
   GED_HIP(hipEventCreate(&e1));
-  for (int C : cands) {
-    try {
-      split_fit(g, b.sw, pl, C, 1, st);
-      split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);  // warm-up
-      float ms = 1e30f;
-      for (int r = 0; r < 2; ++r) {  // best of two timed passes
-        GED_HIP(hipEventRecord(e0, st));
-        split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);
-        GED_HIP(hipEventRecord(e1, st));
-        GED_HIP(hipEventSynchronize(e1));
-        float t = 0.f;
-        GED_HIP(hipEventElapsedTime(&t, e0, e1));
-        ms = std::min(ms, t);
-      }
-      // a wider tile must win by 3 % per column (it holds more memory and
-      // leaves more columns idle in the last tile of a batch)
-      const double per_col = ms / C;
-      if (per_col < best * 0.97) {
-        best = per_col;
-        best_c = C;
-      }
-    } catch (const HipError &e) {
-      if (e.code != GED_ERR_NOMEM) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        throw;
-      }
-      break;  // wider tiles do not fit
+  auto timed = [&](int C, int cut) -> double {
+    SplitPlan pl = pl0;
+    pl.cut_div = cut;
+    split_fit(g, b.sw, pl, C, 1, st);
+    split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);  // warm-up
+    float ms = 1e30f;
+    for (int r = 0; r < 2; ++r) {
+      GED_HIP(hipEventRecord(e0, st));
+      split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);
+      GED_HIP(hipEventRecord(e1, st));
+      GED_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      GED_HIP(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, t);
     }
+    return ms / C;
+  };
+  try {
+    const int C = race_tile(g, {8, 16, 32, 64}, 0.97, timed);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return C;
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  g->batch_tile = best_c;
-  return best_c;
 }
 
 static void enqueue_batch(ged_graph *g, BatchWs &b, int G, int C, hipStream_t st) {
   const int64_t n = g->n;
   const PrepCache &pc = g->prep;
-  Partition &p = partition(g, C);
+  Partition &p = partition(g, C, false, g->batch_cut_div);
   const double *T = pc.t_levels.as<const double>();
   for (int g0 = 0; g0 < G; g0 += C) {
     const int nc = std::min(C, G - g0);
@@ -231,7 +257,8 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
     split_tables(g, pl, st);
   }
   const int C = split ? autotune_split(g, b, pl) : autotune_tile(g, b);
-  Partition &p = partition(g, C);
+  pl.cut_div = g->batch_cut_div;
+  Partition &p = partition(g, C, false, g->batch_cut_div);
   b.ws.fit(p);
   // internal ids, duplicates inside a group dropped; column of every member
   std::vector<int64_t> &hoff = b.h_offsets;
@@ -355,7 +382,8 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
                                    (const void *)(intptr_t)b.sw.wl_blocks,
                                    (const void *)(intptr_t)split,
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
-                                   (const void *)(intptr_t)C};
+                                   (const void *)(intptr_t)C,
+                                   (const void *)(intptr_t)g->batch_cut_div};
   if (g->prof.on) {
     // profiling times every step launch with events: run the batch eagerly
     enqueue();
@@ -409,5 +437,17 @@ extern "C" int ged_set_batch_tile(ged_graph *g, int32_t tile) {
     return fail(GED_ERR_ARG, "tile must be 0 (autotune) or a power of two <= 64");
   std::lock_guard<std::recursive_mutex> lk(g->mu);
   g->batch_tile = tile;
+  if (tile == 0) g->batch_cut_div = 0;
+  return GED_OK;
+}
+
+extern "C" int32_t ged_batch_row_cut(const ged_graph *g) { return g ? g->batch_cut_div : 0; }
+
+extern "C" int ged_set_batch_row_cut(ged_graph *g, int32_t cut_div) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  if (cut_div != 0 && cut_div != 1 && cut_div != 2 && cut_div != 4)
+    return fail(GED_ERR_ARG, "cut_div must be 0 (autotune), 1, 2 or 4");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  g->batch_cut_div = cut_div;
   return GED_OK;
 }

@@ -147,20 +147,25 @@ __device__ __forceinline__ void wl_append(uint64_t *wl, unsigned *wl_n, unsigned
 // Launch geometry shared by every walk-count step kernel.
 constexpr int kBlock = 256;            // threads per block (4 wavefronts of 64)
 constexpr int kLdsDoubles = 2048;      // LDS staging per block (16 KiB)
-// Values a block stages in LDS for a C-column step.  (64 KiB blocks for wide
-// steps were measured slower on BA n=2e6: 816 vs 764 us at C = 16.)
-__host__ __device__ constexpr int lds_values(int C) { return C > 0 ? kLdsDoubles : kLdsDoubles; }
+// Values a block stages in LDS for a C-column step, whatever C is.  (64 KiB
+// blocks for wide steps were measured slower on BA n=2e6: 816 vs 764 us at
+// C = 16.)
+__host__ __device__ constexpr int lds_values(int) { return kLdsDoubles; }
 constexpr int kRowsPerBlock = 511;     // max rows of one row block (row_ptr slice: 2 loads per thread)
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 
 // Row partition for a step with C columns: row blocks of consecutive short
-// rows (nnz*units <= lds_values(C)) staged through LDS, and rows longer than
-// that split into fixed segments whose partial sums a fix-up pass combines.
+// rows staged through LDS, and rows longer than the row-split threshold
+// split into fixed segments whose partial sums a fix-up pass combines.
 // units = 8-byte gather units per arc: C, or C/2 for 32-bit inputs gathered
-// as column pairs (narrow_gather).
+// as column pairs (narrow_gather).  The threshold -- also the most arcs a
+// block takes -- is the LDS capacity lds_values(C) / units divided by
+// cut_div (1, 2 or 4; the batch autotuner chooses it per graph).
+constexpr int kMaxCutDiv = 4;
 struct Partition {
   int C = 0;
   int units = 0;
+  int cut = 0;       // row-split threshold in arcs
   int n_blocks = 0;  // row blocks
   int n_segs = 0;    // long-row segments
   int n_long = 0;    // long rows
@@ -268,7 +273,8 @@ constexpr int kReduceBlocks = 256;
 void launch_reduce(const Partition &p, const StepArgs &a, double *level, double *acc,
                    const int *active, hipStream_t st, double *ws2);
 
-void build_partition(Partition &p, const std::vector<int> &row_ptr, int C, int units);
+void build_partition(Partition &p, const std::vector<int> &row_ptr, int C, int units,
+                     int cut_div = 1);
 
 // 32-bit inputs at C >= 2 are gathered as pairs of adjacent columns (8 bytes
 // per lane), so a wavefront's load covers as many cache lines as an FP64
@@ -344,6 +350,7 @@ struct SplitPlan {
   // first stored level (3) is pushed from the vertices holding level-2
   // counts instead of gathered
   bool push3 = false;
+  int cut_div = 1;  // row-split threshold divisor of the dense steps' partitions
 };
 
 struct SplitWs {
@@ -407,6 +414,10 @@ struct ged_graph {
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   std::recursive_mutex mu;
+  // partitions are looked up by server lanes on their own thread while calls
+  // holding mu may add new ones: the maps have a lock of their own (entries
+  // are never removed, so a returned reference stays valid)
+  std::mutex parts_mu;
   std::map<int, std::unique_ptr<ged::Partition>> parts, parts_r;
   ged::PrepCache prep;
   // precomputation workspace (C = 1 steps)
@@ -430,10 +441,15 @@ struct ged_graph {
   // groups that alternate between them keep each
   ged::SplitExec split_exec[4];
   hipEvent_t score_done = nullptr;  // recorded after the result copy
-  // batched scoring
+  // batched scoring: tile width and row-split threshold divisor (0 = autotune)
   int32_t batch_tile = 0;
+  int32_t batch_cut_div = 0;
   // greedy candidate batch width (0 = the library's choice)
   int32_t greedy_width = 0;
+  // registered with a server at (served_alpha, served_eps): other values,
+  // invalidation and a change of tail bound are refused until it is destroyed
+  bool served = false;
+  double served_alpha = 0, served_eps = 0;
   // split scoring
   ged::DBuf omega2;             // uint64 [n] walks of length 2 ending at v (unweighted)
   bool omega2_ready = false;
@@ -466,10 +482,14 @@ struct ged_graph {
 
 namespace ged {
 
-// Partition for C columns (built on first use).
-Partition &partition(ged_graph *g, int C, bool reverse = false);
+// Partition for C columns (built on first use), at a row-split threshold of
+// the LDS capacity / cut_div.
+Partition &partition(ged_graph *g, int C, bool reverse = false, int cut_div = 1);
 // The partition of a narrow_gather step with C columns (forward rows).
-Partition &partition_narrow(ged_graph *g, int C);
+Partition &partition_narrow(ged_graph *g, int C, int cut_div = 1);
+// The forward C-column partition at cut_div 1 if it was built, else null
+// (builds nothing).
+const Partition *partition_if_built(ged_graph *g, int C);
 // Precompute for (alpha, eps); throws HipError, returns status for arg errors.
 int prepare(ged_graph *g, double alpha, double eps);
 // W[ell] for arbitrary ell (extends the total-walk chain on demand).
@@ -485,6 +505,8 @@ double comb_bound(ged_graph *g, double alpha, double W_ell);
 // Upper estimate of sigma_max (ged_spectral.hip); computed once per graph.
 double sigma_max(ged_graph *g);
 int check_alpha_eps(ged_graph *g, double alpha, double eps);
+// Device bytes of the handle's single-group score workspace.
+size_t score_bytes_held(const ged_graph *g);
 StepArgs base_args(ged_graph *g, bool reverse = false);
 // Step launch, timed with HIP events around the main kernel when profiling is
 // on for the graph (the only way library code launches walk-count steps).
@@ -503,6 +525,10 @@ void batch_forget(const ged_graph *g);
 void greedy_forget(const ged_graph *g);
 // Candidate batch width the greedy uses on g.
 int greedy_width_for(const ged_graph *g);
+// Upper bound of the device bytes a greedy run (walk length up to ell_max, k
+// picks) can leave allocated on g, and the bytes its workspace holds now.
+size_t greedy_footprint(ged_graph *g, int ell_max, int k);
+size_t greedy_bytes_held(const ged_graph *g);
 
 // Split scoring (ged_split.hip).
 bool split_ok(const ged_graph *g);

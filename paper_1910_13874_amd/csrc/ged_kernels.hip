@@ -669,9 +669,9 @@ void launch_reduce(const Partition &p, const StepArgs &a, double *level, double 
 
 // ----------------------------------------------------------- partition --
 
-void build_partition(Partition &p, const std::vector<int> &rp, int C, int units) {
+void build_partition(Partition &p, const std::vector<int> &rp, int C, int units, int cut_div) {
   const int n = (int)rp.size() - 1;
-  const int nnz_blk = lds_values(C) / units;
+  const int nnz_blk = std::max(1, lds_values(C) / units / std::max(1, cut_div));
   const int seg_len = std::max(1, kSegDoubles / units);
   std::vector<int4> blocks;
   std::vector<int4> segs;
@@ -701,6 +701,7 @@ void build_partition(Partition &p, const std::vector<int> &rp, int C, int units)
   lfirst.push_back((int)segs.size());
   p.C = C;
   p.units = units;
+  p.cut = nnz_blk;
   p.n_blocks = (int)blocks.size();
   p.n_segs = (int)segs.size();
   p.n_long = (int)lrows.size();

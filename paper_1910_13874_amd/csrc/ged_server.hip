@@ -14,10 +14,14 @@
 // join and leave while others are mid-flight, and the lanes of different
 // graphs run on their own streams, so their work overlaps on the device.
 //
-// Greedy requests run whole (ged_greedy) on worker threads; each needs
-// working memory proportional to n * (walk length), so they are admitted only
-// while the sum of their estimated footprints stays within the configured HBM
-// budget, and wait otherwise.
+// Greedy requests run whole (ged_greedy) on worker threads.  Admission,
+// queue limits, deadlines and cancellation follow server_policy.h: a greedy
+// request's working memory is estimated from the allocations the greedy makes
+// at the largest walk length its k can reach (the first power of two whose
+// tail bound is below eps/k, from a table built when the graph is added), it
+// starts when that fits the HBM budget beside the lanes, the memory the
+// graphs already hold and the running requests, and the memory its graph
+// holds afterwards stays counted.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -27,11 +31,13 @@
 #include <unordered_map>
 
 #include "ged_internal.h"
+#include "server_policy.h"
 
 namespace ged {
 
 int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, uint64_t seed,
-               bool stochastic, int32_t *out_group, double *out_score, ged_greedy_trace *tr);
+               bool stochastic, int32_t *out_group, double *out_score, ged_greedy_trace *tr,
+               const std::atomic<int> *stop);
 void split_fit_width(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C);
 
 static double now_us() {
@@ -90,6 +96,10 @@ struct Lane {
   std::vector<Req> slot;     // request in each column
   std::vector<int> done_cols;  // columns finished by the previous step (bits to clear)
   std::deque<Req> pending;
+  // greedy admission: walk lengths 1, 2, 4, ... with their tail bounds B_ell,
+  // up to the first one below eps / n, and the greedy footprint at each
+  std::vector<std::pair<int, double>> sep;
+  std::vector<size_t> fp;
   int cur = 0;
   size_t bytes = 0;
   // split tiles (undirected graphs)
@@ -106,16 +116,18 @@ struct Lane {
 struct ged_server {
   ged_server_config cfg{};
   std::vector<std::unique_ptr<ged::Lane>> lanes;
-  std::mutex mu;  // guards inbox, results, counters, greedy queue
+  std::mutex mu;  // guards inbox, results, the policy, the greedy queue, stop flags
   std::condition_variable cv_work, cv_done, cv_greedy;
   std::deque<ged::Req> inbox;
   std::deque<ged::Req> greedy_q;
   std::deque<ged::Done> results;
   std::unordered_map<uint64_t, std::vector<int>> groups;
+  // stop flags of the running greedy requests (polled between their rounds)
+  std::unordered_map<uint64_t, std::shared_ptr<std::atomic<int>>> running_stop;
+  std::unique_ptr<ged::ServePolicy> pol;
   uint64_t next_id = 1;
-  int64_t admitted = 0, completed = 0, steps = 0, rejected = 0, peak_cols = 0;
-  int64_t waiting = 0;  // submitted, not yet in a column or on a worker
-  size_t bytes_lanes = 0, bytes_greedy = 0, peak_bytes = 0;
+  int64_t steps = 0, peak_cols = 0;
+  double last_expire_us = 0;
   bool stop = false;
   std::thread sched;
   std::vector<std::thread> workers;
@@ -179,8 +191,10 @@ static void lane_setup(Lane &L, int C) {
             L.ws.lng.bytes;
 }
 
+// Complete request q (held_after: for a greedy request that ran, the bytes
+// its graph's greedy workspace holds now).
 static void emit(ged_server *s, const Req &q, int status, double score, std::vector<int> group,
-                 double t_done) {
+                 double t_done, size_t held_after = 0) {
   Done d;
   d.r.id = q.id;
   d.r.kind = q.kind;
@@ -192,12 +206,45 @@ static void emit(ged_server *s, const Req &q, int status, double score, std::vec
   d.r.t_done_us = t_done;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (q.kind == 1) s->groups[q.id] = group;
+    s->pol->finish(q.id, held_after);
+    if (q.kind == 1 && status == GED_OK) s->groups[q.id] = group;
     d.group = std::move(group);
     s->results.push_back(std::move(d));
-    s->completed++;
   }
   s->cv_done.notify_all();
+  s->cv_greedy.notify_all();  // a greedy reservation may have been released
+}
+
+// Move requests from the front of a lane's queue onto the device (up to
+// `max`, and while take(q) accepts them); requests asked to stop meanwhile
+// are completed with their stop status instead.
+template <class Take>
+static std::vector<Req> take_pending(ged_server *s, Lane &L, size_t max, Take &&take) {
+  std::vector<Req> got, stopped;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    while (!L.pending.empty() && got.size() < max) {
+      Req &q = L.pending.front();
+      if (s->pol->stop_status(q.id)) {
+        stopped.push_back(std::move(q));
+        L.pending.pop_front();
+        continue;
+      }
+      if (!take(q, got.size())) break;
+      s->pol->start(q.id);
+      got.push_back(std::move(q));
+      L.pending.pop_front();
+    }
+  }
+  for (auto &q : stopped) {
+    int st;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      st = s->pol->stop_status(q.id);
+    }
+    emit(s, q, st, 0.0, {}, now_us());
+  }
+  return got;
 }
 
 // Harvest the step that just finished: columns that ran level ell* are done
@@ -234,28 +281,23 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
   std::vector<int> mem, col;
   size_t need = 0;
   int64_t ds_tile = 0;  // members' degree sum: about the tile's worklist entries
-  while (!L.pending.empty() && (int)L.tile.size() < C) {
-    const Req &q = L.pending.front();
+  L.tile = take_pending(s, L, (size_t)C, [&](const Req &q, size_t have) {
     int64_t ds = 0;
     for (int v : q.S) ds += g->h_rp[v + 1] - g->h_rp[v];
     const size_t nq = split_wl_need(g, ds);
-    if (!L.tile.empty() && need + nq > L.sw.wl_cap) break;
+    if (have > 0 && need + nq > L.sw.wl_cap) return false;
     need += nq;
     ds_tile += ds;
-    const int c = (int)L.tile.size();
+    const int c = (int)have;
     for (int v : q.S) {
       mem.push_back(v);
       col.push_back(c);
     }
     offs.push_back((int64_t)mem.size());
-    L.tile.push_back(std::move(L.pending.front()));
-    L.pending.pop_front();
-  }
+    return true;
+  });
   const int nc = (int)L.tile.size();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->waiting -= nc;
-  }
+  if (nc == 0) return false;
   if (need > L.sw.wl_cap) split_fit(g, L.sw, L.pl, C, need, L.st);
   // worklist kernels loop over their grid: size it for this tile
   L.sw.wl_blocks = split_wl_blocks(ds_tile);
@@ -302,19 +344,17 @@ static bool lane_launch(ged_server *s, Lane &L) {
   for (int c : L.done_cols)
     for (int v : L.slot[c].S) clr.push_back(make_int2(v, c));
   L.done_cols.clear();
-  int took = 0;
-  for (int c = 0; c < C && !L.pending.empty(); ++c) {
+  size_t free_cols = 0;
+  for (int c = 0; c < C; ++c) free_cols += L.step[c] == 0;
+  std::vector<Req> fresh_reqs =
+      take_pending(s, L, free_cols, [](const Req &, size_t) { return true; });
+  size_t next = 0;
+  for (int c = 0; c < C && next < fresh_reqs.size(); ++c) {
     if (L.step[c] != 0) continue;
-    L.slot[c] = std::move(L.pending.front());
-    L.pending.pop_front();
+    L.slot[c] = std::move(fresh_reqs[next++]);
     L.step[c] = 1;
     L.fresh[c] = 1;
-    ++took;
     for (int v : L.slot[c].S) set.push_back(make_int2(v, c));
-  }
-  if (took) {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->waiting -= took;
   }
   int active = 0;
   for (int c = 0; c < C; ++c) active += L.step[c] > 0;
@@ -386,7 +426,8 @@ static bool lane_launch(ged_server *s, Lane &L) {
 
 static void sched_loop(ged_server *s) {
   for (;;) {
-    std::vector<Req> incoming;
+    std::vector<Req> incoming, dropped;
+    std::vector<uint64_t> drop_ids;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       bool busy = false;
@@ -394,12 +435,52 @@ static void sched_loop(ged_server *s) {
       if (!busy && s->inbox.empty() && !s->stop)
         s->cv_work.wait_for(lk, std::chrono::microseconds(200));
       if (s->stop) break;
+      const double now = now_us();
+      if (now - s->last_expire_us >= 500.0) {
+        s->pol->expire(now);
+        s->last_expire_us = now;
+      }
+      for (auto &kv : s->running_stop) {
+        const int st = s->pol->stop_status(kv.first);
+        if (st) kv.second->store(st, std::memory_order_relaxed);
+      }
+      drop_ids = s->pol->take_dropped();
+      auto is_dropped = [&](const Req &q) {
+        return std::find(drop_ids.begin(), drop_ids.end(), q.id) != drop_ids.end();
+      };
+      for (auto *dq : {&s->inbox, &s->greedy_q})
+        for (auto it = dq->begin(); it != dq->end();) {
+          if (!drop_ids.empty() && is_dropped(*it)) {
+            dropped.push_back(std::move(*it));
+            it = dq->erase(it);
+          } else {
+            ++it;
+          }
+        }
       while (!s->inbox.empty()) {
         incoming.push_back(std::move(s->inbox.front()));
         s->inbox.pop_front();
       }
     }
     for (auto &q : incoming) s->lanes[q.graph]->pending.push_back(std::move(q));
+    if (!drop_ids.empty())
+      for (auto &Lp : s->lanes)
+        for (auto it = Lp->pending.begin(); it != Lp->pending.end();) {
+          if (std::find(drop_ids.begin(), drop_ids.end(), it->id) != drop_ids.end()) {
+            dropped.push_back(std::move(*it));
+            it = Lp->pending.erase(it);
+          } else {
+            ++it;
+          }
+        }
+    for (auto &q : dropped) {
+      int st;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        st = s->pol->stop_status(q.id);
+      }
+      emit(s, q, st ? st : GED_ERR_CANCELLED, 0.0, {}, now_us());
+    }
     bool progressed = false;
     for (auto &Lp : s->lanes) {
       Lane &L = *Lp;
@@ -425,10 +506,6 @@ static void sched_loop(ged_server *s) {
             if (L.step[c] > 0) emit(s, L.slot[c], err.code, 0.0, {}, t);
         }
         for (auto &q : L.pending) emit(s, q, err.code, 0.0, {}, t);
-        {
-          std::lock_guard<std::mutex> lk(s->mu);
-          s->waiting -= (int64_t)L.pending.size();
-        }
         L.pending.clear();
         std::fill(L.step.begin(), L.step.end(), 0);
         L.inflight = false;
@@ -441,37 +518,50 @@ static void sched_loop(ged_server *s) {
 static void greedy_worker(ged_server *s) {
   for (;;) {
     Req q;
+    std::shared_ptr<std::atomic<int>> flag;
+    int stopped = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      // admission: the head of the queue starts once its footprint fits
+      // admission: the head of the queue starts once its working memory
+      // fits (or leaves at once if it was asked to stop)
       s->cv_greedy.wait(lk, [&] {
-        return s->stop || (!s->greedy_q.empty() &&
-                           s->bytes_lanes + s->bytes_greedy + s->greedy_q.front().footprint <=
-                               (size_t)s->cfg.hbm_budget_bytes);
+        if (s->stop) return true;
+        if (s->greedy_q.empty()) return false;
+        const uint64_t id = s->greedy_q.front().id;
+        return s->pol->stop_status(id) != 0 || s->pol->greedy_fits(id);
       });
       if (s->stop) return;
       q = std::move(s->greedy_q.front());
       s->greedy_q.pop_front();
-      s->waiting--;
-      s->bytes_greedy += q.footprint;
-      s->peak_bytes = std::max(s->peak_bytes, s->bytes_lanes + s->bytes_greedy);
+      stopped = s->pol->stop_status(q.id);
+      if (!stopped) {
+        s->pol->start(q.id);
+        flag = std::make_shared<std::atomic<int>>(0);
+        s->running_stop[q.id] = flag;
+      }
+    }
+    if (stopped) {
+      emit(s, q, stopped, 0.0, {}, now_us());
+      continue;
     }
     Lane &L = *s->lanes[q.graph];
     std::vector<int> grp(q.k);
     double score = 0.0;
     int rc;
+    size_t held = 0;
     {
       std::lock_guard<std::recursive_mutex> lk(L.g->mu);
       rc = guarded([&]() {
-        return greedy_run(L.g, q.k, L.alpha, L.eps, 0.0, 0, false, grp.data(), &score, nullptr);
+        return greedy_run(L.g, q.k, L.alpha, L.eps, 0.0, 0, false, grp.data(), &score, nullptr,
+                          flag.get());
       });
+      held = greedy_bytes_held(L.g);
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      s->bytes_greedy -= q.footprint;
+      s->running_stop.erase(q.id);
     }
-    s->cv_greedy.notify_all();
-    emit(s, q, rc, score, rc == GED_OK ? grp : std::vector<int>(), now_us());
+    emit(s, q, rc, score, rc == GED_OK ? grp : std::vector<int>(), now_us(), held);
   }
 }
 
@@ -494,6 +584,7 @@ extern "C" int ged_server_create(const ged_server_config *cfg, ged_server **out)
     return fail(GED_ERR_ARG, "bad server config (score_slots must be 0 or a power of two <= 64)");
   auto s = std::make_unique<ged_server>();
   s->cfg = *cfg;
+  s->pol = std::make_unique<ServePolicy>(cfg->hbm_budget_bytes, cfg->max_queue);
   *out = s.release();
   return GED_OK;
 }
@@ -503,6 +594,7 @@ extern "C" int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, d
   if (!s || !g || !graph_id) return fail(GED_ERR_ARG, "null argument");
   if (s->started) return fail(GED_ERR_ARG, "graphs must be added before the first request");
   std::lock_guard<std::recursive_mutex> lk(g->mu);
+  if (g->served) return fail(GED_ERR_BUSY, "the graph is registered with a server already");
   return guarded([&]() -> int {
     int rc = prepare(g, alpha, eps);
     if (rc) return rc;
@@ -523,10 +615,30 @@ extern "C" int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, d
         C = n <= 200000 ? 64 : n <= 1000000 ? 32 : n <= 2000000 ? 16 : 8;
     }
     lane_setup(*L, C);
-    if (s->bytes_lanes + L->bytes > (size_t)s->cfg.hbm_budget_bytes)
-      return fail(GED_ERR_NOMEM, "graph pool exceeds the HBM budget");
-    s->bytes_lanes += L->bytes;
-    s->peak_bytes = std::max(s->peak_bytes, s->bytes_lanes);
+    // the handle's single-group score workspace (a greedy's final score uses
+    // it): materialised now and counted with the lane
+    double tmp = 0.0;
+    const int32_t v0 = 0;
+    rc = score_group(g, &v0, 1, alpha, eps, &tmp, nullptr);
+    if (rc) return rc;
+    // walk lengths a greedy can reach: ell doubles until the tail bound drops
+    // below eps / k, after which every round separates
+    for (int ell = 1;; ell *= 2) {
+      const double B = comb_bound(g, alpha, walk_total(g, ell));
+      L->sep.push_back({ell, B});
+      L->fp.push_back(greedy_footprint(g, ell, 0));
+      if (B < eps / (double)g->n || ell >= 65536) break;
+    }
+    GED_HIP(hipStreamSynchronize(g->stream));
+    {
+      std::lock_guard<std::mutex> lk2(s->mu);
+      if (s->pol->add_lane(L->bytes + score_bytes_held(g)) != GED_OK)
+        return fail(GED_ERR_NOMEM, "graph pool exceeds the HBM budget");
+      s->pol->set_held(L->gid, greedy_bytes_held(g));
+    }
+    g->served = true;
+    g->served_alpha = alpha;
+    g->served_eps = eps;
     *graph_id = L->gid;
     s->lanes.push_back(std::move(L));
     return GED_OK;
@@ -535,12 +647,14 @@ extern "C" int ged_server_add_graph(ged_server *s, ged_graph *g, double alpha, d
 
 static int submit(ged_server *s, Req &&q, uint64_t *req_id) {
   std::lock_guard<std::mutex> lk(s->mu);
-  if (s->waiting >= s->cfg.max_queue) return fail(GED_ERR_BUSY, "request queue full");
-  s->waiting++;
-  q.id = s->next_id++;
+  const uint64_t id = s->next_id;
+  const int rc = s->pol->submit(id, q.kind, q.graph, q.footprint, 0.0);
+  if (rc == GED_ERR_BUSY) return fail(rc, "request queue full");
+  if (rc == GED_ERR_NOMEM) return fail(rc, "greedy request exceeds the HBM budget");
+  s->next_id++;
+  q.id = id;
   q.t_submit = now_us();
   if (req_id) *req_id = q.id;
-  s->admitted++;
   if (q.kind == 0) {
     s->inbox.push_back(std::move(q));
     s->cv_work.notify_one();
@@ -580,15 +694,17 @@ extern "C" int ged_server_submit_greedy(ged_server *s, int32_t graph_id, int32_t
   q.kind = 1;
   q.graph = graph_id;
   q.k = k;
-  // miss levels (walk length up to 4 ell*), 8 gain columns twice, bounds and
-  // bookkeeping vectors
-  const size_t n = (size_t)g->n;
-  q.footprint = 8 * n * (size_t)(4 * s->lanes[graph_id]->ell + 1) + 2 * 8 * n * 8 + 40 * n;
-  if (s->bytes_lanes + q.footprint > (size_t)s->cfg.hbm_budget_bytes) {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->rejected++;
-    return fail(GED_ERR_NOMEM, "greedy request exceeds the HBM budget");
-  }
+  // working memory at the largest walk length this k can reach: the first
+  // tabulated length whose tail bound is below eps / k (the last one, where
+  // the table ends, bounds every k)
+  const Lane &L = *s->lanes[graph_id];
+  size_t fp = L.fp.back();
+  for (size_t j = 0; j < L.sep.size(); ++j)
+    if (L.sep[j].second < L.eps / (double)k) {
+      fp = L.fp[j];
+      break;
+    }
+  q.footprint = fp + 16 * (size_t)k + 4096;
   start(s);
   return submit(s, std::move(q), req_id);
 }
@@ -622,12 +738,37 @@ extern "C" int ged_server_group(ged_server *s, uint64_t req_id, int32_t *out, in
 extern "C" int ged_server_stats(ged_server *s, int64_t *out6) {
   if (!s || !out6) return fail(GED_ERR_ARG, "null argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  out6[0] = s->admitted;
-  out6[1] = s->completed;
+  out6[0] = s->pol->admitted();
+  out6[1] = s->pol->completed();
   out6[2] = s->steps;
-  out6[3] = (int64_t)s->peak_bytes;
+  out6[3] = (int64_t)s->pol->peak_bytes();
   out6[4] = s->peak_cols;
-  out6[5] = s->rejected;
+  out6[5] = s->pol->rejected();
+  return GED_OK;
+}
+
+extern "C" int ged_server_cancel(ged_server *s, uint64_t req_id) {
+  if (!s) return fail(GED_ERR_ARG, "null argument");
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    rc = s->pol->request_stop(req_id, GED_ERR_CANCELLED);
+    auto it = s->running_stop.find(req_id);
+    if (rc == GED_OK && it != s->running_stop.end())
+      it->second->store(s->pol->stop_status(req_id), std::memory_order_relaxed);
+  }
+  s->cv_work.notify_all();
+  s->cv_greedy.notify_all();
+  if (rc == GED_ERR_ARG) return fail(rc, "no waiting or running request with this id");
+  if (rc == GED_ERR_BUSY) return fail(rc, "the score is already on the device");
+  return rc;
+}
+
+extern "C" int ged_server_set_deadline(ged_server *s, uint64_t req_id, double deadline_us) {
+  if (!s || !(deadline_us >= 0.0)) return fail(GED_ERR_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  const int rc = s->pol->set_deadline(req_id, deadline_us);
+  if (rc) return fail(rc, "no waiting or running request with this id");
   return GED_OK;
 }
 
@@ -648,6 +789,8 @@ extern "C" int ged_server_destroy(ged_server *s) {
       (void)hipStreamDestroy(L->st);
     }
     if (L->ev) (void)hipEventDestroy(L->ev);
+    std::lock_guard<std::recursive_mutex> lk(L->g->mu);
+    L->g->served = false;
   }
   delete s;
   return GED_OK;

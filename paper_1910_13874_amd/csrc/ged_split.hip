@@ -598,9 +598,10 @@ static int final_in(const SplitPlan &pl) {
   return IN_VEC;
 }
 
-// Partition of a step gathering `in` at C columns.
-static Partition &step_partition(ged_graph *g, int C, int in) {
-  return narrow_gather(C, in, g->weighted) ? partition_narrow(g, C) : partition(g, C);
+// Partition of a step gathering `in` at C columns (row-split threshold of pl).
+static Partition &step_partition(ged_graph *g, const SplitPlan &pl, int C, int in) {
+  return narrow_gather(C, in, g->weighted) ? partition_narrow(g, C, pl.cut_div)
+                                           : partition(g, C, false, pl.cut_div);
 }
 
 // The level-3 push adds each level-2 source's count to all its neighbours:
@@ -660,8 +661,8 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
   const size_t nC = (size_t)g->n * C;
   const bool dirty = !w.zero;
   if (!counts_only) {
-    w.ws.fit(partition(g, C));
-    if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, C, IN_CNT32));
+    w.ws.fit(partition(g, C, false, pl.cut_div));
+    if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, pl, C, IN_CNT32));
   }
   if (pl.s >= 1) {
     const size_t cb = (pl.c32 ? sizeof(uint32_t) : sizeof(uint64_t)) * nC;
@@ -712,9 +713,9 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
 // counts were fitted for a wider tile: the counts, levels and worklists of a
 // narrower tile use the first n * C entries of the same buffers.
 void split_fit_width(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C) {
-  w.ws.fit(partition(g, C));
-  if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, C, IN_CNT32));
-  w.ws.fit(step_partition(g, C, final_in(pl)));
+  w.ws.fit(partition(g, C, false, pl.cut_div));
+  if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, pl, C, IN_CNT32));
+  w.ws.fit(step_partition(g, pl, C, final_in(pl)));
 }
 
 template <class CT>
@@ -800,8 +801,8 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
   const size_t nC = (size_t)n * C;
   const PrepCache &pc = g->prep;
   const double alpha = pc.alpha;
-  Partition &p = partition(g, C);
-  Partition &pn = step_partition(g, C, IN_CNT32);  // 32-bit gathers (count levels)
+  Partition &p = partition(g, C, false, pl.cut_div);
+  Partition &pn = step_partition(g, pl, C, IN_CNT32);  // 32-bit gathers (count levels)
   const double *T = pc.t_levels.as<const double>();
   const SplitWs &cw = counts ? *counts : w;
   const void *c1 = pl.s >= 1 ? cw.cnt1.p : nullptr;
@@ -945,7 +946,7 @@ void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, dou
   w.ws.into(a);
   a.C = C;
   // the partials are laid out by the partition of the combining step
-  launch_reduce(step_partition(g, C, final_in(pl)), a, out, nullptr, nullptr, st,
+  launch_reduce(step_partition(g, pl, C, final_in(pl)), a, out, nullptr, nullptr, st,
                 w.ws.scratch());
 }
 

@@ -36,7 +36,8 @@ GED_BOUND_SPECTRAL = 1
 
 STATUS = {0: "ok", -1: "bad argument", -2: "vertex out of range", -3: "alpha out of range",
           -4: "eps out of range", -5: "malformed graph", -6: "out of memory",
-          -7: "device error", -8: "busy", -9: "walk length limit"}
+          -7: "device error", -8: "busy", -9: "walk length limit", -10: "cancelled",
+          -11: "deadline passed"}
 
 
 class ScoreInfo(ctypes.Structure):
@@ -86,8 +87,12 @@ _sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, 
                                        ctypes.c_double, P_F64])
 _sig("ged_batch_tile", ctypes.c_int32, [c_graph_p])
 _sig("ged_set_batch_tile", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_set_batch_row_cut", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_batch_row_cut", ctypes.c_int32, [c_graph_p])
 _sig("ged_set_greedy_width", ctypes.c_int, [c_graph_p, ctypes.c_int32])
 _sig("ged_greedy_width", ctypes.c_int32, [c_graph_p])
+_sig("ged_greedy_footprint", ctypes.c_int, [c_graph_p, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_double, P_I64, P_I64])
 _sig("ged_greedy", ctypes.c_int, [c_graph_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                   P_I32, P_F64, ctypes.POINTER(GreedyTrace)])
 _sig("ged_greedy_stochastic", ctypes.c_int,
@@ -121,6 +126,8 @@ _sig("ged_server_poll", ctypes.c_int, [c_server_p, ctypes.POINTER(Result), ctype
                                        ctypes.c_int64])
 _sig("ged_server_group", ctypes.c_int, [c_server_p, ctypes.c_uint64, P_I32, ctypes.c_int32])
 _sig("ged_server_stats", ctypes.c_int, [c_server_p, P_I64])
+_sig("ged_server_cancel", ctypes.c_int, [c_server_p, ctypes.c_uint64])
+_sig("ged_server_set_deadline", ctypes.c_int, [c_server_p, ctypes.c_uint64, ctypes.c_double])
 _sig("ged_server_destroy", ctypes.c_int, [c_server_p])
 
 
@@ -270,12 +277,28 @@ class GedGraph:
         """Fix the batched-scoring tile width (0 = autotune on the next call)."""
         _ck(_lib.ged_set_batch_tile(self.handle, int(tile)), "ged_set_batch_tile")
 
+    def batch_row_cut(self):
+        return _lib.ged_batch_row_cut(self.handle)
+
+    def set_batch_row_cut(self, cut_div):
+        """Row-split threshold divisor of batched tiles (1, 2, 4; 0 = autotune)."""
+        _ck(_lib.ged_set_batch_row_cut(self.handle, int(cut_div)), "ged_set_batch_row_cut")
+
     def set_greedy_width(self, width):
         """Candidates per gain SpMM of the greedy (2, 4, 8, 16; 0 = library's choice)."""
         _ck(_lib.ged_set_greedy_width(self.handle, int(width)), "ged_set_greedy_width")
 
     def greedy_width(self):
         return _lib.ged_greedy_width(self.handle)
+
+    def greedy_footprint(self, k, alpha=None, eps=1e-4):
+        """(upper bound of the greedy's device bytes for k picks, bytes its
+        workspace holds now)."""
+        est, held = ctypes.c_int64(), ctypes.c_int64()
+        _ck(_lib.ged_greedy_footprint(self.handle, int(k), self._alpha(alpha), eps,
+                                      ctypes.byref(est), ctypes.byref(held)),
+            "ged_greedy_footprint")
+        return est.value, held.value
 
     def _greedy(self, fn, k, alpha, eps, extra, forced, forced_ell, with_score):
         grp = np.zeros(k, dtype=np.int32)
@@ -363,6 +386,15 @@ class Server:
         _ck(_lib.ged_server_poll(self._h, buf, max_results, ctypes.byref(n), int(timeout_us)),
             "ged_server_poll")
         return [buf[i] for i in range(n.value)]
+
+    def cancel(self, rid):
+        """Ask request rid to stop; returns the status code (0: it will complete
+        cancelled; -8: a score already on the device; -1: unknown or done)."""
+        return _lib.ged_server_cancel(self._h, int(rid))
+
+    def set_deadline(self, rid, deadline_us):
+        """Absolute deadline in the clock of Result.t_submit_us (0 removes it)."""
+        return _lib.ged_server_set_deadline(self._h, int(rid), float(deadline_us))
 
     def group(self, rid, k):
         out = np.zeros(k, dtype=np.int32)

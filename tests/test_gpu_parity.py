@@ -205,10 +205,12 @@ def test_greedy_parity(ged, name, k):
     gg.close()
 
 
-@pytest.mark.parametrize("width", [2, 4, 16])
+@pytest.mark.parametrize("width", [0, 2, 4, 8, 16])
 def test_greedy_width_parity(ged, width):
     """The candidate batch width changes how many gains one SpMM evaluates,
-    not the decisions: every width gives the oracle's picks, walk lengths and
+    not the decisions: every fixed width, and the default that widens a
+    round's batches 2, 4, 8, 16 (width 0; the double star's exact ties need
+    several batches in one round), gives the oracle's picks, walk lengths and
     gains, on graphs whose batches take the 32-bit count levels (ER), the
     pushed and dense second gain levels (BA), FP64 levels (R-MAT), and the
     level-by-level chains of a directed graph."""
@@ -218,10 +220,33 @@ def test_greedy_width_parity(ged, width):
         say(f"[greedy width {width}] {name} k={k}")
         gg = ged.GedGraph.from_graph(g)
         gg.set_greedy_width(width)
-        assert gg.greedy_width() == width
+        assert gg.greedy_width() == (width or (8 if g.nnz <= 1 << 20 else 2))
         alpha = g.default_alpha()
         compare_greedy(gg.greedy(k, alpha, EPS), oracle.greedy(g, k, alpha, EPS),
                        f"{name} width {width}")
+        gg.close()
+    if width == 0:
+        # above 2^20 arcs (a cycle of 600,000 vertices) three identical stars
+        # K_{1,50}: their centres tie exactly, so a round's first batch of 2
+        # cannot settle the runner-up and the round widens
+        nc_ = 600_000
+        src = list(range(nc_))
+        dst = [(v + 1) % nc_ for v in range(nc_)]
+        for c in range(3):
+            ctr = nc_ + 51 * c
+            src += [ctr] * 50
+            dst += list(range(ctr + 1, ctr + 51))
+        tied = inputs.from_edges(nc_ + 153, np.array(src, np.int32), np.array(dst, np.int32),
+                                 name="cycle+3stars")
+        assert tied.nnz > 1 << 20
+        gg = ged.GedGraph.from_graph(tied)
+        assert gg.greedy_width() == 2
+        alpha = tied.default_alpha()
+        r = gg.greedy(2, alpha, EPS)
+        say(f"[greedy widening] picks {list(r['group'])} evals {list(r['evals'])} "
+            f"rounds {r['rounds']}")
+        compare_greedy(r, oracle.greedy(tied, 2, alpha, EPS), "tied stars, widening")
+        assert r["evals"][-1] > 2 * r["rounds"], (r["evals"], r["rounds"])
         gg.close()
     gd = directed_graph()
     rev = inputs.reverse(gd)
@@ -845,6 +870,47 @@ def test_batch_every_tile_width(ged, name):
         b = gg.score_batch(off, mem, alpha, eps)
         worst = max(rel(b[j], solo[j]) for j in range(70))
         assert worst <= 1e-12, (name, tile, worst)
+    gg.close()
+
+
+@pytest.mark.parametrize("name", ["ba", "star", "directed"])
+def test_batch_row_cuts(ged, name):
+    """Batched scoring at each row-split threshold (cut_div 1, 2, 4: rows above
+    2048/C/cut_div arcs become segments) and several tile widths, on the split
+    path ("ba", "star": one row of 70,000 arcs) and the level-by-level column
+    path ("directed"): every column equals its solo score to 1e-12, a sample
+    the oracle to 1e-9; with both knobs left to the autotuner it records a
+    width and a threshold, and a repeated batch is bit for bit the same."""
+    if name == "ba":
+        g = inputs.barabasi_albert(20000, 5, 59)
+    elif name == "star":
+        g = inputs.from_edges(70001, np.zeros(70000, np.int32),
+                              np.arange(1, 70001, dtype=np.int32), name="star70k")
+    else:
+        g = directed_graph()
+    gg = ged.GedGraph.from_graph(g)
+    alpha = oracle.default_alpha(g, None)
+    off, mem = inputs.groups(g.n, 40, 1, 60, 161)
+    solo = [gg.score(mem[off[j]:off[j + 1]], alpha, EPS) for j in range(40)]
+    for j in (0, 39):
+        c, _, _, _ = oracle.score(g, mem[off[j]:off[j + 1]], alpha, EPS)
+        assert rel(solo[j], c) <= REL, (name, j, solo[j], c)
+    for tile in (4, 16, 64):
+        for cut in (1, 2, 4):
+            say(f"[row cuts] {name} tile={tile} cut_div={cut}")
+            gg.set_batch_tile(tile)
+            gg.set_batch_row_cut(cut)
+            assert gg.batch_row_cut() == cut
+            b = gg.score_batch(off, mem, alpha, EPS)
+            worst = max(rel(b[j], solo[j]) for j in range(40))
+            assert worst <= 1e-12, (name, tile, cut, worst)
+    gg.set_batch_tile(0)  # both knobs back to the autotuner
+    assert gg.batch_row_cut() == 0
+    b = gg.score_batch(off, mem, alpha, EPS)
+    say(f"  autotuned: tile {gg.batch_tile()} cut_div {gg.batch_row_cut()}")
+    assert gg.batch_tile() in (4, 8, 16, 32, 64) and gg.batch_row_cut() in (1, 2, 4)
+    assert max(rel(b[j], solo[j]) for j in range(40)) <= 1e-12
+    np.testing.assert_array_equal(gg.score_batch(off, mem, alpha, EPS), b)
     gg.close()
 
 

@@ -136,6 +136,101 @@ def test_admission_and_queue_limits(ged):
     gg.close()
 
 
+@pytest.mark.parametrize("name", ["ba", "rmat", "directed", "weighted"])
+def test_greedy_footprint_bounds_allocations(ged, name):
+    """The greedy's memory estimate (what serving admission charges) bounds
+    what a run leaves allocated, from a fresh handle, for several k; the
+    workspace is kept for the next call, so a repeated run adds nothing."""
+    if name == "ba":
+        g, w = inputs.barabasi_albert(30000, 4, 41), None
+    elif name == "rmat":
+        g, w = inputs.rmat(15, 16, seed=42), None
+    elif name == "directed":
+        r = inputs.uniform_ints(2 * 60000, 8000, 43)
+        g, w = inputs.from_edges(8000, r[0::2], r[1::2], symmetrize=False, name="dir8k"), None
+    else:
+        g = inputs.barabasi_albert(20000, 4, 44)
+        deg = g.degrees.astype(np.float64)
+        rows = np.repeat(np.arange(g.n), g.degrees)
+        w = 1.0 / np.sqrt(deg[rows] * deg[g.col_idx])
+    gg = ged.GedGraph.from_graph(g, weights=w)
+    alpha = gg.default_alpha()
+    for k in (5, 40):
+        est, held0 = gg.greedy_footprint(k, alpha, EPS)
+        gg.greedy(k, alpha, EPS)
+        _, held1 = gg.greedy_footprint(k, alpha, EPS)
+        print(f"[footprint] {name} k={k}: estimate {est} held {held0} -> {held1}", flush=True)
+        assert held1 <= est, (name, k, held1, est)
+        gg.greedy(k, alpha, EPS)
+        assert gg.greedy_footprint(k, alpha, EPS)[1] == held1
+    gg.close()
+
+
+def test_cancel_and_deadline(ged):
+    """A greedy cancelled right after submission and one given a deadline 1 ms
+    away both complete with their stop status (whether they were still
+    waiting or already running: a running greedy stops before its next
+    round), a later request on the same graph is still correct, and the
+    server's counters add up."""
+    import time
+    g = inputs.barabasi_albert(200000, 4, 45)
+    gg = ged.GedGraph.from_graph(g)
+    alpha = gg.default_alpha()
+    srv = ged.Server(hbm_budget_bytes=16 << 30, score_slots=8, greedy_workers=1)
+    gid = srv.add_graph(gg, alpha, EPS)
+    r1 = srv.submit_greedy(gid, 100)
+    assert srv.cancel(r1) == 0
+    r2 = srv.submit_greedy(gid, 100)
+    # the server's clock is the steady clock (CLOCK_MONOTONIC), in microseconds
+    assert srv.set_deadline(r2, time.monotonic() * 1e6 + 1000.0) == 0
+    S = inputs.group(g.n, 20, 7)
+    r3 = srv.submit_score(gid, S)
+    r4 = srv.submit_greedy(gid, 5)
+    got = {}
+    t0 = time.time()
+    while len(got) < 4 and time.time() - t0 < 60:
+        for r in srv.poll(16, 100000):
+            got[r.id] = (r.status, r.score)
+    assert got[r1][0] == -10, got[r1]
+    assert got[r2][0] == -11, got[r2]
+    assert got[r3][0] == 0 and got[r4][0] == 0
+    assert srv.cancel(r1) == -1  # finished
+    c, _, _, _ = oracle.score(g, S, alpha, EPS)
+    assert rel(got[r3][1], c) <= REL
+    ro = oracle.greedy(g, 5, alpha, EPS)
+    assert list(srv.group(r4, 5)) == [int(x) for x in ro["group"]]
+    st = srv.stats()
+    assert st["admitted"] == 4 and st["completed"] == 4
+    srv.close()
+    gg.prepare(alpha * 0.5, EPS)  # the handle is free again after destroy
+    srv2, srv3 = ged.Server(), ged.Server()
+    srv2.add_graph(gg, alpha, EPS)
+    with pytest.raises(ged.GedError) as e:
+        srv3.add_graph(gg, alpha, EPS)  # a handle serves one server at a time
+    assert e.value.code == -8
+    srv3.close()
+    srv2.close()
+    gg.close()
+
+
+def test_served_handle_refuses_other_alpha(ged):
+    """A registered handle keeps its (alpha, eps) until the server is gone."""
+    g = inputs.barabasi_albert(20000, 4, 46)
+    gg = ged.GedGraph.from_graph(g)
+    alpha = gg.default_alpha()
+    srv = ged.Server(hbm_budget_bytes=8 << 30)
+    srv.add_graph(gg, alpha, EPS)
+    assert gg.score([1, 2], alpha, EPS) > 0  # same alpha, eps: fine
+    for call in (lambda: gg.score([1, 2], alpha * 0.5, EPS), gg.invalidate,
+                 lambda: gg.set_tail_bound("spectral")):
+        with pytest.raises(ged.GedError) as e:
+            call()
+        assert e.value.code == -8
+    srv.close()
+    assert gg.score([1, 2], alpha * 0.5, EPS) > 0
+    gg.close()
+
+
 def test_directed_and_weighted_lanes(ged):
     """A directed graph (level-by-level column pool) and a weighted undirected one
     (split tiles without integer levels) served side by side: every result equals

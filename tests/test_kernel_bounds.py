@@ -1,7 +1,9 @@
 """Index arithmetic of the HIP kernels, emulated on the CPU (no GPU).
 
-Mirrors the row partition the library builds (row blocks of at most 2048/C
-arcs and 511 rows, long rows split into segments of 8192/C arcs) and every
+Mirrors the row partition the library builds (row blocks of at most
+2048/C/cut_div arcs and 511 rows, rows above that row-split threshold split
+into segments of 8192/C arcs, for the divisors 1, 2 and 4 the batch
+autotuner races) and every
 index formula of the step kernel, on CSRs in the library's internal vertex
 order (stable by decreasing out-degree), and asserts that every load and
 store lands inside its buffer -- including the empty trailing row blocks
@@ -21,12 +23,12 @@ K_BLOCK, K_ROWS, K_SEG, K_LDS = 256, 511, 8192, 2048
 WL_CHUNK = 512
 
 
-def partition(rp, C, units=None):
+def partition(rp, C, units=None, cut_div=1):
     """Row blocks and long-row segments for C columns gathered in `units`
     8-byte units per arc (C, or C/2 for column pairs)."""
     units = units or C
     n = len(rp) - 1
-    nnz_blk = K_LDS // units
+    nnz_blk = max(1, K_LDS // units // cut_div)
     seg_len = max(1, K_SEG // units)
     deg = np.diff(rp)
     blocks, segs, lrows = [], [], []
@@ -49,14 +51,21 @@ def partition(rp, C, units=None):
     return blocks, segs, lrows
 
 
-def check_step(rp, ci, n, C, pairs=False):
+def check_step(rp, ci, n, C, pairs=False, cut_div=1):
     """pairs: 32-bit input gathered as column pairs (C >= 2): unit q of thread
     t loads elements u*C + 2k, +1 with k = unit mod C/2, staged as two 32-bit
     LDS slots; phase 2 reads slot j*C + c."""
     nnz = int(rp[-1])
     ci_alloc = max(1, nnz)
     U = C // 2 if pairs else C
-    blocks, segs, _ = partition(rp, C, U)
+    blocks, segs, lrows = partition(rp, C, U, cut_div)
+    cut = max(1, K_LDS // U // cut_div)
+    deg = np.diff(rp)
+    # every arc is in exactly one block or segment; long rows are those above the cut
+    covered = sum(p1 - p0 for (_, _, p0, p1) in blocks) + sum(z - y for (_, y, z) in segs)
+    assert covered == nnz
+    assert all(deg[r] > cut for r in lrows)
+    assert all(deg[r0:r1].max(initial=0) <= cut and p1 - p0 <= cut for (r0, r1, p0, p1) in blocks)
     PT = K_LDS // K_BLOCK
     RT = (K_ROWS + K_BLOCK) // K_BLOCK
     t = np.arange(K_BLOCK)
@@ -143,9 +152,10 @@ def test_step_indices_in_bounds(g):
     for rp, ci in ((np.asarray(g.row_ptr, np.int64), np.asarray(g.col_idx, np.int64)),
                    internal_csr(g)):
         for C in (1, 2, 4, 8, 16, 32, 64):
-            check_step(rp, ci, g.n, C)
-            if C >= 2:
-                check_step(rp, ci, g.n, C, pairs=True)
+            for cut_div in ((1, 2, 4) if C in (1, 2, 16, 64) else (1,)):
+                check_step(rp, ci, g.n, C, cut_div=cut_div)
+                if C >= 2:
+                    check_step(rp, ci, g.n, C, pairs=True, cut_div=cut_div)
 
 
 def wl_need(n, nnz, deg_sum):
