@@ -263,6 +263,26 @@ int ged_greedy_footprint(ged_graph *g, int32_t k, double alpha, double eps, int6
  * with ged_set_greedy_width, or the default's first width when that is 0. */
 int32_t ged_greedy_width(const ged_graph *g);
 
+/*
+ * For callers that cannot allocate device memory (code between other work
+ * that must not call hipMalloc, tight serving loops, harnesses that forbid
+ * allocation): GED_{<=ell*}(S) of one group, like ged_score, computed by the
+ * level-by-level hit chain (Section 3.1.1, Eq. phisum; Algorithm "GED-Walk
+ * Computation") with every per-call buffer in a fixed 80 MiB region of device
+ * memory that the library holds on each device it runs on until the process
+ * ends.  The call allocates nothing: ged_prepare(g, alpha, eps) must have
+ * been called on the handle first (otherwise GED_ERR_ARG), and a graph and
+ * group whose working memory -- about 16 bytes per vertex plus the group --
+ * exceeds the region give GED_ERR_NOMEM with the sizes in ged_last_error()
+ * (graphs up to about 5 million vertices fit).  Arguments, set semantics and
+ * errors otherwise as ged_score; the result equals ged_score's to rounding.
+ * Calls are serialised by the library (they share the region); calls made
+ * through other means that overlap on one GPU would race on it.  Blocks until
+ * the result is on the host.
+ */
+int ged_score_noalloc(ged_graph *g, const int32_t *S, int32_t s_len, double alpha, double eps,
+                      double *out_score, ged_score_info *info);
+
 /* ------------------------------------------------------------ profiling --- */
 
 typedef struct {

@@ -20,6 +20,7 @@ HIP_SOURCES = [
     "ged_spectral.hip",
     "ged_greedy.hip",
     "ged_server.hip",
+    "ged_noalloc.hip",
 ]
 
 HIP_FLAGS = [
