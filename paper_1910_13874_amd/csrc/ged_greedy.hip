@@ -109,6 +109,60 @@ __global__ void k_miss_sub(const int *__restrict__ rp, const int *__restrict__ s
   }
 }
 
+// Speculative miss columns (gain batches on FP64 levels, undirected graphs
+// without repeated arcs, unweighted): column W + j of a batch of width C
+// carries the miss chain of S + {x_j} beside x_j's gain chain, so that after
+// x_j wins the next pick's miss levels are already computed.  Their first
+// level is the count of arcs into v from outside S + {x_j}: deg(v) - sdeg(v)
+// - [v in N(x_j)] outside S + {x_j}, 0 on it -- the integer k_miss1 writes
+// for that group, with alpha times it as FP64.  k_spec_miss1 writes deg -
+// sdeg (0 on S and at x_j) for every vertex; k_spec_miss1_fix takes one off
+// at x_j's neighbours outside S (each once: no repeated arcs).
+__global__ void k_spec_miss1(const int *__restrict__ rp, const int *__restrict__ sdeg,
+                             const uint32_t *__restrict__ smask, const int *__restrict__ cand,
+                             int nc, int W, int C, int n, double alpha, uint32_t *__restrict__ c1,
+                             double *__restrict__ d1) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const bool inS = (smask[v >> 5] >> (v & 31)) & 1u;
+    const int base = inS ? 0 : rp[v + 1] - rp[v] - sdeg[v];
+    for (int j = 0; j < nc; ++j) {
+      const int cnt = v == cand[j] ? 0 : base;
+      c1[(size_t)v * C + W + j] = (uint32_t)cnt;
+      d1[(size_t)v * C + W + j] = alpha * (double)cnt;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_spec_miss1_fix(const int *__restrict__ rp,
+                                                           const int *__restrict__ ci,
+                                                           const uint32_t *__restrict__ smask,
+                                                           const int *__restrict__ cand, int W,
+                                                           int C, double alpha,
+                                                           uint32_t *__restrict__ c1,
+                                                           double *__restrict__ d1) {
+  const int j = blockIdx.y;
+  const int x = cand[j];
+  for (int k = rp[x] + blockIdx.x * kBlock + (int)threadIdx.x; k < rp[x + 1];
+       k += gridDim.x * kBlock) {
+    const int v = ci[k];
+    if (v != x && !((smask[v >> 5] >> (v & 31)) & 1u)) {
+      const size_t o = (size_t)v * C + W + j;
+      const uint32_t cnt = c1[o] - 1u;
+      c1[o] = cnt;
+      d1[o] = alpha * (double)cnt;
+    }
+  }
+}
+
+// The miss levels 1 .. la of S + {x_j}, taken from column col of a
+// speculative batch's stored levels (level i at src + (i-1) * n * C).
+__global__ void k_spec_take(const double *__restrict__ src, int la, int n, int C, int col,
+                            double *__restrict__ M) {
+  const size_t nC = (size_t)n * C;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    for (int i = 1; i <= la; ++i) M[(size_t)i * n + v] = src[(size_t)(i - 1) * nC + (size_t)v * C + col];
+}
+
 // I(x) = b_0 * sum_{a=1}^{ell} m_a + sum_{c=1}^{ell} b_c * sum_{a=0}^{ell-c} m_a with
 // m_0 = b_0 = 1 for x outside S: every term of Lemma "initialize" once, no
 // subtraction.  ub[x] = -1 marks members of S.
@@ -482,6 +536,14 @@ struct GreedyCtx {
   const uint32_t *last_src = nullptr;
   int last_C = 0;  // width of the batch that left them (their layout [n][last_C])
   int sub_col = -1;
+  // the last batch, if it carried speculative miss columns and was the last
+  // batch of its round: its candidates, walk length, layout and stored levels
+  // (level i at spec_src + (i-1)*n*spec_C, miss column of candidate j at
+  // spec_W + j); spec_col: the column to take after a pick (-1: none)
+  std::vector<int> spec_cand;
+  int spec_ell = -1, spec_C = 0, spec_W = 0, spec_la = 0, spec_col = -1;
+  const double *spec_src = nullptr;
+  bool spec_dirty = false;  // miss columns left dense data in the level-1 regions
   DBuf X, Y, cand_dev, gains, topk_k[2], topk_i[2];
   HBuf h_small;
   int layout_C = 0;  // batch width the zero-state flags above were established for
@@ -707,13 +769,24 @@ static void compute_bounds(GreedyCtx &c, int ell) {
 }
 
 // Miss levels 1..a of the current S and, for the split gain, their sum to r.
+// After a pick whose candidate carried a speculative miss column, the levels
+// are copied from it instead of recomputed.
 static void chains_for(GreedyCtx &c, int ell) {
   if (!c.split) {
     miss_chains(c, ell);
     return;
   }
   const int a = (ell + 1) / 2, r = ell - a;
-  miss_chains(c, a);
+  if (c.spec_col >= 0 && c.spec_ell == ell && c.spec_la == a) {
+    hipLaunchKernelGGL(k_spec_take, dim3(std::min(8192, (c.n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, c.st, c.spec_src, a, c.n, c.spec_C,
+                       c.spec_W + c.spec_col, c.m_levels.as<double>());
+    GED_HIP(hipGetLastError());
+    c.sub_col = -1;
+  } else {
+    miss_chains(c, a);
+  }
+  c.spec_col = -1;
   c.Mr.ensure(sizeof(double) * c.n);
   hipLaunchKernelGGL(k_sum_range, dim3(std::min(8192, (c.n + kBlock - 1) / kBlock)), dim3(kBlock),
                      0, c.st, c.m_levels.as<const double>(), c.n, r, c.Mr.as<double>());
@@ -773,13 +846,25 @@ static bool gains32(GreedyCtx &c, int ell) {
   return ok;
 }
 
-// Exact L_ell(S, x) for up to C candidates (one SpMM column each; C a
-// power of two, at most c.C).
-static void eval_batch(GreedyCtx &c, const int *cand, int nc, int C, int ell, int round,
-                       double *out) {
+// Exact L_ell(S, x) for up to Cb candidates (one SpMM column each; Cb a
+// power of two, at most c.C).  want_spec: the first batch of a round, which
+// on FP64 gain levels also carries a speculative miss column per candidate
+// (the step then runs 2 Cb columns).
+static void eval_batch(GreedyCtx &c, const int *cand, int nc, int Cb, int ell, int round,
+                       double *out, bool want_spec) {
   ged_graph *g = c.g;
   const int n = c.n;
   c.last_ell = -1;  // set below when the batch stores its levels as counts
+  c.spec_ell = -1;  // set below when this batch carries miss columns
+  const int la0 = (ell + 1) / 2;
+  const bool spec = want_spec && c.split && la0 >= 3 && g->simple && !g->weighted &&
+                    2 * Cb <= c.C && !gains32(c, ell);
+  const int C = spec ? 2 * Cb : Cb;
+  if (c.spec_dirty) {  // dense miss columns sit in the level-1 regions
+    c.d1_zeroed = nullptr;
+    c.dc1_zeroed = nullptr;
+    c.spec_dirty = false;
+  }
   if (C != c.layout_C) {
     // the stored levels' layout [n][C] changes with the width: regions that
     // must be zero (the pushed first and second gain levels) are zeroed
@@ -865,7 +950,8 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int C, int ell, in
     // the combining level's counts too, when they fit 32 bits: after a pick
     // from this batch the whole miss chain follows by subtraction
     const bool top_a = g32 && la > 2 && omega_fit_level(g, la, c.st) >= la;
-    if (la > 1) c.dlv.ensure((size_t)eb * nC * (size_t)(la - 1 + (top_a ? 1 : 0)));
+    // miss columns keep their level la too
+    if (la > 1) c.dlv.ensure((size_t)eb * nC * (size_t)(la - 1 + (top_a || spec ? 1 : 0)));
     double *dl = c.dlv.as<double>();
     uint32_t *dl32 = c.dlv.as<uint32_t>();
     if (c.dlv.p != c.d2_buf) {
@@ -972,6 +1058,15 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int C, int ell, in
                            (uint64_t *)nullptr, (unsigned *)nullptr, 0u);
         GED_HIP(hipGetLastError());
       }
+      if (spec) {  // level 1 of the miss columns (counts and FP64), dense
+        hipLaunchKernelGGL(k_spec_miss1, dim3(std::min(8192, (n + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, c.st, a.rp, c.sdeg.as<const int>(), a.smask,
+                           c.cand_dev.as<const int>(), nc, Cb, C, n, al, dc, dl);
+        hipLaunchKernelGGL(k_spec_miss1_fix, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
+                           a.smask, c.cand_dev.as<const int>(), Cb, C, al, dc, dl);
+        GED_HIP(hipGetLastError());
+        a.spec_from = Cb;
+      }
       double ai = al;  // alpha^i
       for (int i = push1 ? 2 : 1; i <= la; ++i) {
         ai *= al;
@@ -992,7 +1087,8 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int C, int ell, in
             run_step(g, ps, a, in, OUT_GAIN, c.st);
           }
         } else {
-          a.Y = nullptr;
+          // miss columns store their level la after the stored levels
+          a.Y = spec ? dl + (size_t)(la - 1) * nC : nullptr;
           a.tr = c.Mr.as<const double>();
           a.q_cnt1 = any;
           a.q_cnt2 = any;
@@ -1006,6 +1102,15 @@ static void eval_batch(GreedyCtx &c, const int *cand, int nc, int C, int ell, in
           run_step(g, ps, a, in, OUT_GAINCOMB, c.st, la - 1);
           pr = &ps;
         }
+      }
+      if (spec) {
+        c.spec_cand.assign(cand, cand + nc);
+        c.spec_ell = ell;
+        c.spec_C = C;
+        c.spec_W = Cb;
+        c.spec_la = la;
+        c.spec_src = dl;
+        c.spec_dirty = true;
       }
       if (p32) {
         hipLaunchKernelGGL(k_gain_level1_32, dim3(gx, nc), dim3(kBlock), 0, c.st, a.rp, a.ci,
@@ -1100,6 +1205,8 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
   c.rounds = 0;
   c.last_ell = -1;  // nothing of an earlier call is reused
   c.sub_col = -1;
+  c.spec_ell = -1;
+  c.spec_col = -1;
   c.d2_zero = c.d2_pending = false;
   const int K = c.C + 1;  // the most pairs one selection returns
   c.smask.ensure(sizeof(uint32_t) * (size_t)((n + 31) / 32 + 1));
@@ -1227,7 +1334,7 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
         if (top.v >= 0 && hk[0] < top.L2) break;  // no bound reaches the runner-up
         const int nc = std::min(m, Cb);
         for (int q = 0; q < nc; ++q) internal[q] = g->new_id[hi[q]];
-        eval_batch(c, internal.data(), nc, Cb, ell, round, gains.data());
+        eval_batch(c, internal.data(), nc, Cb, ell, round, gains.data(), batch_in_round == 1);
         for (int q = 0; q < nc; ++q) top.add(gains[q], hi[q]);
         if (m <= Cb) break;  // nothing else eligible
         // the (Cb+1)-th bound is the best among the candidates not evaluated
@@ -1252,9 +1359,13 @@ int greedy_run(ged_graph *g, int32_t k, double alpha, double eps, double eta, ui
       join(u);
       need_chain = true;
       c.sub_col = -1;
+      c.spec_col = -1;
       if (c.last_ell == ell)
         for (size_t q = 0; q < c.last_cand.size(); ++q)
           if (c.last_cand[q] == u) c.sub_col = (int)q;
+      if (c.spec_ell == ell)
+        for (size_t q = 0; q < c.spec_cand.size(); ++q)
+          if (c.spec_cand[q] == u) c.spec_col = (int)q;
     }
     if (s_size < k) ell *= 2;
   }

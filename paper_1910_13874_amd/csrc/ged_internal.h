@@ -256,6 +256,12 @@ struct StepArgs {
   double q_alpha = 0;               // weight ratio of consecutive stored levels (OUT_COMBINE32L)
   int q_nlv = 0;
   int q_even = 0;
+  // Gain batches with speculative miss columns (OUT_GAIN, OUT_GAIN32D,
+  // OUT_GAINCOMB): column c >= spec_from carries the miss chain of S plus the
+  // candidate of column c - spec_from -- 0 on S and at that candidate, the
+  // plain level elsewhere (alpha * sum; the count for OUT_GAIN32D) -- and a
+  // combining step stores it to Y instead of combining it.
+  int spec_from = 1 << 30;
 };
 
 // Walk-count step: Y = epilogue(alpha * A X) with column sums.  Three

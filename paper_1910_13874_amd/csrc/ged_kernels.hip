@@ -77,10 +77,15 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                        OUT == OUT_TILE32 || OUT == OUT_COMBINE32L) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
-  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB || OUT == OUT_GAINCOMB32L ||
-                       OUT == OUT_GAINCOMB32S) {
+  } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB) {
+    if (c >= a.spec_from) return (inS || cand == c - a.spec_from) ? 0.0 : y;  // miss column
     return inS ? 0.0 : (cand == c ? a.inj[v] : y);
-  } else if constexpr (OUT == OUT_GAIN32 || OUT == OUT_GAIN32D) {
+  } else if constexpr (OUT == OUT_GAINCOMB32L || OUT == OUT_GAINCOMB32S) {
+    return inS ? 0.0 : (cand == c ? a.inj[v] : y);
+  } else if constexpr (OUT == OUT_GAIN32D) {
+    if (c >= a.spec_from) return (inS || cand == c - a.spec_from) ? 0.0 : sum;  // miss column
+    return inS ? 0.0 : (cand == c ? a.injc[c] : sum);  // the count
+  } else if constexpr (OUT == OUT_GAIN32) {
     return inS ? 0.0 : (cand == c ? a.injc[c] : sum);  // the count
   } else {  // OUT_POOL
     const int s = a.col_step[c];
@@ -376,6 +381,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
           double y;
           bool member = false;
           if constexpr (OutTraits<OUT>::gaincomb) {
+            if constexpr (OUT == OUT_GAINCOMB) {
+              if (c >= a.spec_from) {  // miss column: its level is stored, not combined
+                a.Y[(size_t)r * C + c] =
+                    (inS || cw[rl] == c - a.spec_from) ? 0.0 : a.alpha * acc;
+                continue;
+              }
+            }
             // gain chains: 0 on S (where m_a = 0 too), m_a(x) at the candidate
             y = inS ? 0.0 : (cw[rl] == c ? in.ta : a.alpha * acc);
             if constexpr (OutTraits<OUT>::cstore)
@@ -479,6 +491,13 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
   const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   double y = epilogue<C, OUT>(a, r, c, acc);
+  if constexpr (OUT == OUT_GAINCOMB) {
+    if (c >= a.spec_from) {  // miss column: its level is stored, not combined
+      a.Y[(size_t)r * C + c] = y;
+      a.long_part[(size_t)l * C + c] = 0.0;
+      return;
+    }
+  }
   if constexpr (OutTraits<OUT>::cstore)
     a.Y32[(size_t)r * C + c] = gain_count(a, y, acc, a.cand_col[r] == c);
   if constexpr (OutTraits<OUT>::combine) {
