@@ -329,6 +329,20 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
     b.X.ensure(sizeof(double) * (size_t)n * C);
     b.Y.ensure(sizeof(double) * (size_t)n * C);
   }
+  // per tile: clear its count levels by a fill where replaying its pushes
+  // would cost more (members' omega_2 sum against the levels' size); decided
+  // before any capture (the host table may need a synchronisation once).  A
+  // captured batch keeps the choices of the call that captured it: both
+  // clear everything the pushes wrote, so later groups only differ in speed.
+  std::vector<char> fill((size_t)(G + C - 1) / C, 0);
+  if (split && pl.s >= 2 && !pl.push3) {
+    const std::vector<double> &om2 = omega2_host(g, st);
+    for (size_t t = 0; t < fill.size(); ++t) {
+      double v = 0.0;
+      for (int64_t q = hoff[t * C]; q < hoff[std::min(G, (int)(t + 1) * C)]; ++q) v += om2[hmem[q]];
+      fill[t] = split_clear_by_fill(g, pl, C, v) ? 1 : 0;
+    }
+  }
   auto enqueue = [&]() {
     if (!split) {
       enqueue_batch(g, b, G, C, st);
@@ -360,7 +374,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
       GED_HIP(hipEventRecord(b.ev_dense[p], st));
       GED_HIP(hipStreamWaitEvent(b.side, b.ev_dense[p], 0));
       split_tile_clear(g, *cw[p], pl, C, offs, mem, mc, g0, nc, hoff[g0 + nc] - hoff[g0], tm[p],
-                       b.side);
+                       b.side, fill[t] != 0);
     }
     GED_HIP(hipEventRecord(b.ev_join, b.side));
     GED_HIP(hipStreamWaitEvent(st, b.ev_join, 0));
@@ -384,6 +398,7 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
                                    (const void *)(intptr_t)C,
                                    (const void *)(intptr_t)g->batch_cut_div};
+
   if (g->prof.on) {
     // profiling times every step launch with events: run the batch eagerly
     enqueue();

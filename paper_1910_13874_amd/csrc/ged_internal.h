@@ -585,15 +585,21 @@ void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const
                      uint64_t *tmask, hipStream_t st, bool set_tmask = true);
 void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, double *out,
                        hipStream_t st);
+// fill: zero the count levels with a dense fill instead of replaying the
+// pushes (split_clear_by_fill decides from the tile's estimated push volume).
 void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                       const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
-                      uint64_t *tmask, hipStream_t st);
+                      uint64_t *tmask, hipStream_t st, bool fill = false);
+// Is a dense fill cheaper than replaying a tile's pushes?  push2_arcs: the
+// sum of omega_2 over the tile's members, a bound on the arcs its level-2
+// push wrote along.
+bool split_clear_by_fill(const ged_graph *g, const SplitPlan &pl, int C, double push2_arcs);
 // All four phases in order on one stream.  profile = false launches without
 // profiling events (the server enqueues tiles from its own thread).
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
                         int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,
-                        bool profile = true);
+                        bool profile = true, bool fill_clear = false);
 // Map caller ids to internal ids, dropping duplicates inside the group;
 // returns the sum of the members' degrees.
 int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> &out);

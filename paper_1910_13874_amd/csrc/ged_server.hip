@@ -109,6 +109,7 @@ struct Lane {
   DBuf tin;                  // tile input: int64 offsets[C+1], int members[m], int columns[m]
   HBuf h_tin;
   std::vector<Req> tile;     // requests of the tile in flight
+  std::vector<double> om2;   // omega_2 per vertex (undirected unweighted lanes; push volumes)
 };
 
 }  // namespace ged
@@ -154,6 +155,7 @@ static void lane_setup(Lane &L, int C) {
     GED_HIP(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
     GED_HIP(hipEventCreateWithFlags(&L.ev, hipEventDisableTiming));
     split_tables(g, L.pl, L.st);  // per-graph tables now, not while greedy runs
+    if (L.pl.s >= 2) L.om2 = omega2_host(g, L.st);
     // worklist: a tile holds requests while their needs (<= n + nnz/512 + 1
     // each) fit C * (nnz/512 + 1) + 2n entries; one larger group grows it
     const size_t cap = (size_t)C * split_wl_need(g, 0) + 2 * (size_t)n;
@@ -281,9 +283,13 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
   std::vector<int> mem, col;
   size_t need = 0;
   int64_t ds_tile = 0;  // members' degree sum: about the tile's worklist entries
+  double om2 = 0.0;     // members' omega_2 sum: the level-2 push volume
+  const std::vector<double> &h_om2 = L.om2;
   L.tile = take_pending(s, L, (size_t)C, [&](const Req &q, size_t have) {
     int64_t ds = 0;
     for (int v : q.S) ds += g->h_rp[v + 1] - g->h_rp[v];
+    if (!h_om2.empty())
+      for (int v : q.S) om2 += h_om2[v];
     const size_t nq = split_wl_need(g, ds);
     if (have > 0 && need + nq > L.sw.wl_cap) return false;
     need += nq;
@@ -322,7 +328,8 @@ static bool lane_launch_split(ged_server *s, Lane &L) {
   int W = 1;
   while (W < nc) W *= 2;
   enqueue_split_tile(g, L.sw, L.pl, W, d_offs, d_mem, d_col, 0, nc, (int64_t)m,
-                     L.tmask.as<uint64_t>(), L.acc.as<double>(), L.st, false);
+                     L.tmask.as<uint64_t>(), L.acc.as<double>(), L.st, false,
+                     split_clear_by_fill(g, L.pl, W, om2));
   GED_HIP(hipMemcpyAsync(L.h_acc.p, L.acc.p, sizeof(double) * nc, hipMemcpyDeviceToHost, L.st));
   GED_HIP(hipEventRecord(L.ev, L.st));
   L.inflight = true;

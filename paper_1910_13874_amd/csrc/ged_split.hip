@@ -926,11 +926,28 @@ void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const
   }
 }
 
+// Replaying a push stores one zero per arc it wrote along, each to its own
+// cache line (about 64 bytes of traffic); a fill writes the count levels of
+// the tile's width once.  Replay while that is cheaper.
+bool split_clear_by_fill(const ged_graph *g, const SplitPlan &pl, int C, double push2_arcs) {
+  if (pl.s < 2 || pl.push3) return false;
+  const double cb = pl.c32 ? 4.0 : 8.0;
+  return push2_arcs * 64.0 > 2.0 * (double)g->n * C * cb;
+}
+
 void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
                       const int *mem, const int *mcol, int g0, int nc, int64_t tile_members,
-                      uint64_t *tmask, hipStream_t st) {
+                      uint64_t *tmask, hipStream_t st, bool fill) {
   const int mgrid = grid_for(tile_members, kPushGrid);
-  if (pl.s >= 1) {  // clears the members' tmask bits too
+  if (fill && pl.s >= 2 && !pl.push3) {
+    // the two count levels of this width, the members' column bits and the
+    // worklist length: everything the pushes wrote
+    const size_t words = (size_t)g->n * C * (pl.c32 ? 1 : 2);
+    launch_fill_i32(w.cnt1.as<int>(), 0, words, st);
+    launch_fill_i32(w.cnt2.as<int>(), 0, words, st);
+    launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
+    launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
+  } else if (pl.s >= 1) {  // clears the members' tmask bits too
     if (pl.c32)
       clear_phase<unsigned>(g, w, pl, C, offs, mem, mcol, g0, nc, mgrid, tmask, st);
     else
@@ -953,11 +970,11 @@ void split_tile_reduce(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, dou
 void enqueue_split_tile(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
                         const int64_t *offs, const int *mem, const int *mcol, int g0, int nc,
                         int64_t tile_members, uint64_t *tmask, double *out, hipStream_t st,
-                        bool profile) {
+                        bool profile, bool fill_clear) {
   split_tile_push(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st);
   split_dense(g, w, pl, C, tmask, st, profile);
   split_tile_reduce(g, w, pl, C, out, st);
-  split_tile_clear(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st);
+  split_tile_clear(g, w, pl, C, offs, mem, mcol, g0, nc, tile_members, tmask, st, fill_clear);
 }
 
 int64_t map_group(ged_graph *g, const int32_t *S, int64_t len, std::vector<int> &out) {
