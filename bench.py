@@ -223,6 +223,8 @@ def bench_graph_workload(args, torch, ged, inputs):
     gg.set_stream(stream)
     if args.greedy_width:
         gg.set_greedy_width(args.greedy_width)
+    if args.tile:
+        gg.set_batch_tile(args.tile)
     alpha = gg.default_alpha()
     groups = [inputs.group(g.n, 5, 1000 + j) for j in range(max(spec["n_scores"], 16))]
     if spec["batch"]:
@@ -272,6 +274,41 @@ def bench_graph_workload(args, torch, ged, inputs):
         out["oracle_greedy"] = ctx
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, alpha, groups)
+    gg.close()
+    if name == "rmat22" and not args.no_batch:
+        log("batched-scoring context: BA n=2e6, 4096 groups")
+        out["batched"] = batch_ratio(torch, ged, inputs)
+    return out
+
+
+def batch_ratio(torch, ged, inputs, groups=4096, steps=2):
+    """Batched scoring of `groups` groups (|S| ~ U[1,200], seed 104) on BA
+    n=2,000,000, m=8 against the same groups scored one call at a time on the
+    same GPU: queries/s of each and their ratio (context keys of the default
+    line; --workload batch is the full measurement)."""
+    g = inputs.workload_graph("ba2m")
+    gg = ged.GedGraph.from_graph(g)
+    gg.set_stream(torch.cuda.Stream())
+    alpha = gg.default_alpha()
+    off, mem = inputs.groups(g.n, groups, 1, 200, 104)
+    gg.prepare(alpha, EPS)
+    gg.score_batch(off, mem, alpha, EPS)  # autotune, capture
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        b = gg.score_batch(off, mem, alpha, EPS)
+    torch.cuda.synchronize()
+    bq = groups * steps / (time.perf_counter() - t)
+    seq = np.zeros(groups)
+    t = time.perf_counter()
+    for j in range(groups):
+        seq[j] = gg.score(mem[off[j]:off[j + 1]], alpha, EPS)
+    torch.cuda.synchronize()
+    pq = groups / (time.perf_counter() - t)
+    out = {"workload": f"BA n=2,000,000 m=8, {groups} groups |S|~U[1,200]",
+           "batch_queries_per_s": bq, "plain_queries_per_s": pq, "batch_speedup": bq / pq,
+           "tile": gg.batch_tile(), "row_cut_div": gg.batch_row_cut(),
+           "max_rel_batch_vs_plain": float(np.max(np.abs(b - seq) / np.maximum(np.abs(seq), 1e-300)))}
     gg.close()
     return out
 
@@ -431,11 +468,14 @@ def main():
     ap.add_argument("--workload", default="rmat22",
                     choices=["ba1m", "rmat22", "er1k", "batch", "serve", "variants"])
     ap.add_argument("--groups", type=int, default=4096)
-    ap.add_argument("--tile", type=int, default=0, help="batch: fix the tile width (0 = autotune)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="batch, ba1m: fix the batched tile width (0 = autotune)")
     ap.add_argument("--greedy-width", type=int, default=0,
                     help="candidates per gain SpMM of the greedy (0 = the library's choice)")
     ap.add_argument("--seq-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="rmat22: skip the batched-scoring context keys")
     ap.add_argument("--order", choices=("degree", "input"), default="degree",
                     help="internal vertex order: degree-descending relabel (default) or the "
                          "generator's order")
