@@ -445,7 +445,7 @@ struct ged_graph {
   // split scoring: one captured pair per variant (third level gathered or
   // pushed; group copied to the device or staged by the first kernel), so
   // groups that alternate between them keep each
-  ged::SplitExec split_exec[4];
+  ged::SplitExec split_exec[8];
   hipEvent_t score_done = nullptr;  // recorded after the result copy
   // batched scoring: tile width and row-split threshold divisor (0 = autotune)
   int32_t batch_tile = 0;
@@ -463,6 +463,9 @@ struct ged_graph {
   // omega_fit = largest i <= omega_top with max_v omega_j(v) < 2^32 for 3 <= j <= i
   ged::DBuf omega_lv;
   int omega_top = 2, omega_fit = 2;
+  // largest level of omega_lv shown free of 64-bit wrap-around everywhere
+  // (each value exact), by max_v omega_i <= max_deg * max_v omega_{i-1}
+  int omega_exact = 2;
   std::list<ged::DBuf> omega_old;  // replaced omega_lv buffers, freed with the graph
   // maxima known for levels 3 .. omax_top; omax_fit as omega_fit for them
   int omax_top = 2, omax_fit = 2;
@@ -470,6 +473,9 @@ struct ged_graph {
   std::vector<double> push_bound;
   // omega_2(v) on the host (push volumes decided before launch)
   std::vector<double> h_omega2;
+  // omega_i(v) on the host for levels i >= 3 the graph holds (per-group
+  // bounds of the stored levels of a single score)
+  std::map<int, std::vector<double>> h_omega_lv;
   // omega_sum[i] = sum_v omega_i(v) for i = 1 .. (2 once omega2 is ready, then
   // omega_top once omega_lv holds levels 3..); exact for levels that fit 2^32
   std::vector<double> omega_sum;

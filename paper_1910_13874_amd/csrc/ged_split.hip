@@ -468,8 +468,12 @@ static void ensure_omega2(ged_graph *g, hipStream_t st) {
 // The integer chain omega_3 .. omega_top from omega_2, written as doubles to
 // out[(i-3)*n ..] if out is non-null (then their sums go to omega_sum).
 // Returns the largest i <= top such that max_v omega_j(v) < 2^32 for
-// 3 <= j <= i (2 if omega_3 does not fit).  Synchronizes the stream.
-static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st) {
+// 3 <= j <= i (2 if omega_3 does not fit); *exact (if non-null) gets the
+// largest level no value of which can have wrapped around 2^64: level i is
+// safe when the one below is and max_deg times its maximum stays below 2^64
+// (omega_2 <= max_deg^2, and <= nnz without repeated arcs).  Synchronizes
+// the stream.
+static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st, int *exact = nullptr) {
   const int64_t n = g->n;
   const int L = top - 2;
   DBuf tmp, mx;
@@ -495,6 +499,17 @@ static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st) {
   GED_HIP(hipStreamSynchronize(st));
   int fit = 2;
   while (fit < top && hm[(size_t)(fit - 2)] < (1ull << 32)) ++fit;
+  if (exact) {
+    const double md = (double)g->max_deg;
+    double m = md * md;  // bound on max omega_2
+    if (g->simple) m = std::min(m, (double)g->nnz);
+    int e = 2;
+    while (e < top && md * m < 0.99 * 18446744073709551616.0) {
+      ++e;
+      m = (double)hm[(size_t)(e - 3)];  // exact: no value of level e wrapped
+    }
+    *exact = e;
+  }
   if (out) {  // sums of levels past fit may have wrapped: not kept
     g->omega_sum.resize((size_t)fit + 1);
     for (int i = 3; i <= fit; ++i) g->omega_sum[(size_t)i] = (double)hm[(size_t)L + (i - 3)];
@@ -513,7 +528,8 @@ static int omega_chain(ged_graph *g, int top, double *out, hipStream_t st) {
 static void omega_levels(ged_graph *g, int top, hipStream_t st) {
   DBuf lv;
   lv.ensure(sizeof(double) * (size_t)g->n * (top - 2));
-  const int fit = omega_chain(g, top, lv.as<double>(), st);
+  int exact = 2;
+  const int fit = omega_chain(g, top, lv.as<double>(), st, &exact);
   if (g->omega_lv.p) {
     g->omega_old.emplace_back();
     std::swap(g->omega_old.back().p, g->omega_lv.p);
@@ -523,6 +539,7 @@ static void omega_levels(ged_graph *g, int top, hipStream_t st) {
   std::swap(g->omega_lv.bytes, lv.bytes);
   g->omega_top = top;
   g->omega_fit = fit;
+  g->omega_exact = exact;
 }
 
 int omega_fit_level(ged_graph *g, int L, hipStream_t st) {
@@ -654,6 +671,60 @@ static void ensure_push_bound(ged_graph *g, hipStream_t st) {
   for (size_t v = 0; v < n; ++v)
     b[v] = (double)(g->h_rp[v + 1] - g->h_rp[v]) + om2[v] + om3[v];
   g->push_bound.swap(b);
+}
+
+// omega_i(v) on the host, for a level i >= 3 that the graph's integer chain
+// holds (level i - 3 of omega_lv); copied once.
+static const std::vector<double> &omega_level_host(ged_graph *g, int i, hipStream_t st) {
+  auto it = g->h_omega_lv.find(i);
+  if (it != g->h_omega_lv.end()) return it->second;
+  const size_t n = (size_t)g->n;
+  std::vector<double> h(n);
+  const void *lv;
+  {
+    std::lock_guard<std::mutex> lk(g_omega_mu);
+    lv = g->omega_lv.p;  // a replaced table stays allocated with the graph
+  }
+  GED_HIP(hipMemcpyAsync(h.data(), static_cast<const double *>(lv) + (size_t)(i - 3) * n,
+                         sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  GED_HIP(hipStreamSynchronize(st));
+  return g->h_omega_lv[i] = std::move(h);
+}
+
+// Per-group 32-bit stored levels (single scores on graphs whose omega maxima
+// do not fit 32 bits).  A walk of length i that ends at v and meets S can be
+// cut after its last member s, at position j < i (v itself is a member only
+// on the member rows, which hold omega_i(v), the j = 0 term): a walk of
+// length j ending at s followed by one of length i - j leaving s, so the
+// level-i count at any row is at most
+//   sum_{s in S} sum_{j=0}^{i-1} omega_j(s) omega_{i-j}(s)
+// (omega_0 = 1; walks leaving s are walks ending at s reversed).  When that
+// is below 2^32 for every stored level (and the graph holds omega up to the
+// top stored level, for the member rows), the levels are stored as exact
+// 32-bit counts as for graphs whose maxima fit.
+static bool group_levels_fit32(ged_graph *g, const SplitPlan &pl, const std::vector<int> &mem,
+                               hipStream_t st) {
+  const int top = pl.a - 1;
+  if (pl.nlv <= 0 || pl.s != 2 || !pl.c32 || g->weighted || top < 3) return false;
+  {
+    std::lock_guard<std::mutex> lk(g_omega_mu);
+    if (g->omega_top < top || g->omega_exact < top) return false;
+  }
+  const std::vector<double> &om2 = omega2_host(g, st);
+  std::vector<const std::vector<double> *> om((size_t)top + 1, nullptr);
+  for (int i = 3; i <= top; ++i) om[i] = &omega_level_host(g, i, st);
+  auto w = [&](int j, int v) -> double {
+    if (j == 0) return 1.0;
+    if (j == 1) return (double)(g->h_rp[v + 1] - g->h_rp[v]);
+    return j == 2 ? om2[(size_t)v] : (*om[j])[(size_t)v];
+  };
+  for (int i = pl.s + 1; i <= top; ++i) {
+    double b = 0.0;
+    for (int v : mem)
+      for (int j = 0; j < i; ++j) b += w(j, v) * w(i - j, v);
+    if (!(b < 0.999 * 4294967296.0)) return false;
+  }
+  return true;
 }
 
 void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_need,
@@ -1053,6 +1124,7 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
     g->split_tmask_ready = true;
   }
   split_tables(g, pl, st);
+  if (!pl.lv32 && group_levels_fit32(g, pl, mem, st)) pl.lv32 = true;
   if (pl.lv32 && pl.s == 2 && pl.nlv >= 1) {
     ensure_push_bound(g, st);
     double b = 0.0;
@@ -1119,8 +1191,8 @@ int split_score(ged_graph *g, const int32_t *S, int32_t s_len, double *out) {
           g->prep.t_levels.p, g->prep.tr.p, g->omega2.p,
           g->omega_lv.p, g->out_host.p, (const void *)st, abits, (const void *)(intptr_t)g->prep.ell,
           (const void *)(intptr_t)cap, (const void *)(uintptr_t)w.wl_cap,
-          (const void *)(intptr_t)1 /* split */};
-      SplitExec &x = g->split_exec[(pl.push3 ? 1 : 0) + (staged ? 2 : 0)];
+          (const void *)(intptr_t)1 /* split */, (const void *)(intptr_t)pl.lv32};
+      SplitExec &x = g->split_exec[(pl.push3 ? 1 : 0) + (staged ? 2 : 0) + (pl.lv32 ? 4 : 0)];
       if (x.exec && sig != x.sig) x.drop();
       if (!x.exec) {
         capture(st, enqueue_main, &x.graph, &x.exec);

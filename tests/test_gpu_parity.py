@@ -788,19 +788,48 @@ def test_score_pushed_level3(ged, name):
     gg.close()
 
 
+def omega_rows(g, top):
+    """omega_i(v) for i = 0..top as float64 rows (exact while below 2^53)."""
+    om = [np.ones(g.n)]
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    for _ in range(top):
+        om.append(np.bincount(rows, weights=om[-1][g.col_idx], minlength=g.n))
+    return om
+
+
+def group_levels_fit(om, S, a):
+    """A single score's own bound on its stored level-i hit counts, i = 3 ..
+    a-1: a walk of length i meeting S splits at its last member s into a walk
+    ending at s and one leaving it, so count_i(v) <= sum_s sum_{j<i}
+    omega_j(s) omega_{i-j}(s).  True when every such bound is below 2^32 (with
+    the library's 0.1 % margin)."""
+    if a - 1 < 3:
+        return False
+    S = np.unique(np.asarray(S))
+    for i in range(3, a):
+        b = sum(float(np.dot(om[j][S], om[i - j][S])) for j in range(i))
+        if not b < 0.999 * 2.0 ** 32:
+            return False
+    return True
+
+
 @pytest.mark.parametrize("name", ["sparse_er", "star"])
 def test_split_count_layout(ged, name):
     """Dense split levels stored as unscaled 32-bit counts when every stored
-    level's omega maximum is below 2^32, FP64 otherwise.  "sparse_er" (average
-    degree 3) keeps omega small for many levels, so ell* = 7..17 stores 1..6
-    levels as 32-bit counts (the combining step's four-level loop and its
-    remainder), while ell* = 29 needs omega_14 > 2^32 and stores FP64; "star" (70,000 leaves, no duplicate arcs, so 32-bit counts)
-    has omega_3 = 70,000^2 > 2^32 and must keep FP64 levels.  The profiled
-    dominant step kernel shows which layout ran; scores single and batched
-    against the oracle."""
+    level's omega maximum is below 2^32, or, for a single score, when the
+    group's own bound on its hit counts is (member-wise sums of omega_j omega_
+    {i-j}); FP64 otherwise.  "sparse_er" (average degree 3) keeps omega small
+    for many levels, so ell* = 7..17 stores 1..6 levels as 32-bit counts (the
+    combining step's four-level loop and its remainder), while ell* = 29 needs
+    omega_14 > 2^32 and only groups of small bound stay 32-bit; "star" (70,000
+    leaves, no duplicate arcs) has omega_3 = 70,000^2 > 2^32, so a group
+    holding the centre keeps FP64 levels while groups of leaves fit on their
+    own bound.  The profiled dominant step kernel shows which layout ran;
+    scores single and batched against the oracle (batches use the graph-wide
+    layout)."""
     if name == "sparse_er":
         g = inputs.erdos_renyi(3000, 4500, 57)
-        ells = list(range(7, 18, 2)) + [29]  # 29: omega_14 > 2^32, back to FP64
+        ells = list(range(7, 18, 2)) + [29]  # 29: omega_14 > 2^32
     else:
         g = inputs.from_edges(70001, np.zeros(70000, np.int32),
                               np.arange(1, 70001, dtype=np.int32), name="star70k")
@@ -809,12 +838,16 @@ def test_split_count_layout(ged, name):
     gg = ged.GedGraph.from_graph(g)
     alpha = 0.9 * oracle.default_alpha(g, None)
     om = omega_max(g, 20)
+    orow = omega_rows(g, 15)
     sizes = [(1, 1), (2, 9), (3, 120)]
     groups = [inputs.group(g.n, size, seed) for seed, size in sizes]
+    if name == "star":
+        groups.append(np.array([0, 5], np.int32))  # the centre: omega_3 = 4.9e9
     off = np.zeros(len(groups) + 1, dtype=np.int64)
     for j, S in enumerate(groups):
         off[j + 1] = off[j] + S.size
     mem = np.concatenate(groups).astype(np.int32)
+    seen = {False: 0, True: 0}
     for ell in ells:
         B = oracle.comb_bound(g, alpha, ell, None)
         eps = float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, None)))
@@ -822,18 +855,19 @@ def test_split_count_layout(ged, name):
         u32 = all(om[i] < 2.0 ** 32 for i in range(3, a))
         say(f"  ell={ell} stored levels={a - 3} 32-bit={u32}")
         ref = []
+        gg.prepare(alpha, eps)  # t-levels outside the profiled calls
         for j, S in enumerate(groups):
             c, ell_o, _, _ = oracle.score(g, S, alpha, eps)
             assert ell_o == ell
-            if j == 0:
-                gg.prepare(alpha, eps)  # t-levels outside the profiled call
-                gg.profile_enable(True)
+            gg.profile_enable(True)
             s = gg.score(S, alpha, eps)
-            if j == 0:
-                kind = gg.profile_read()["dominant_kind"]
-                gg.profile_enable(False)
-                out = kind % ged.KIND_BASE
-                assert (out in (9, 10)) == u32, (name, ell, kind)
+            kind = gg.profile_read()["dominant_kind"]
+            gg.profile_enable(False)
+            out = kind % ged.KIND_BASE
+            want = u32 or group_levels_fit(orow, S, a)
+            if a - 1 >= 3:
+                seen[want] += 1
+            assert (out in (9, 10)) == want, (name, ell, S.size, kind)
             assert rel(s, c) <= REL, (name, ell, S.size, s, c)
             ref.append(c)
         b = gg.score_batch(off, mem, alpha, eps)
@@ -843,6 +877,9 @@ def test_split_count_layout(ged, name):
         assert om[(17 + 1) // 2 - 1] < 2.0 ** 32  # the last ell still stores 32-bit levels
     else:
         assert om[3] > 2.0 ** 32
+        # leaves fit on their own bound, the centre's group does not
+        assert group_levels_fit(orow, groups[0], 4) and not group_levels_fit(orow, groups[-1], 4)
+    assert seen[True] > 0 and seen[False] > 0, seen
     gg.close()
 
 
