@@ -219,6 +219,8 @@ def bench_graph_workload(args, torch, ged, inputs):
     log(f"graph {name}: n={g.n} nnz={g.nnz} dmax={g.max_degree} "
         f"({time.perf_counter() - t_gen:.1f}s)")
     gg = ged.GedGraph.from_graph(g, keep_order=args.order == "input")
+    if args.buckets is not None:
+        gg.set_source_buckets(args.buckets)
     stream = torch.cuda.Stream()
     gg.set_stream(stream)
     if args.greedy_width:
@@ -318,6 +320,8 @@ def bench_batch(args, torch, ged, inputs):
     g = inputs.workload_graph("ba2m")
     log(f"graph ba2m: n={g.n} nnz={g.nnz}")
     gg = ged.GedGraph.from_graph(g, keep_order=args.order == "input")
+    if args.buckets is not None:
+        gg.set_source_buckets(args.buckets)
     stream = torch.cuda.Stream()
     gg.set_stream(stream)
     alpha = gg.default_alpha()
@@ -470,6 +474,9 @@ def main():
     ap.add_argument("--groups", type=int, default=4096)
     ap.add_argument("--tile", type=int, default=0,
                     help="batch, ba1m: fix the batched tile width (0 = autotune)")
+    ap.add_argument("--buckets", type=int, default=None,
+                    help="source-bucket bytes of the long rows (0 = library's choice, "
+                         "-1 = off)")
     ap.add_argument("--greedy-width", type=int, default=0,
                     help="candidates per gain SpMM of the greedy (0 = the library's choice)")
     ap.add_argument("--seq-sample", type=int, default=4096)

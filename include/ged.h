@@ -192,6 +192,48 @@ int ged_set_batch_tile(ged_graph *g, int32_t tile);
 int ged_set_batch_row_cut(ged_graph *g, int32_t cut_div);
 int32_t ged_batch_row_cut(const ged_graph *g);
 
+/*
+ * Layout of the rows above the row-split threshold in every step (the
+ * per-level pull of Section 3.1.1).  Their arcs can be grouped by source:
+ * the vertex range is cut into buckets of `bytes` of gathered vector, each
+ * row's arcs in one bucket form pieces, and the blocks summing the pieces
+ * are dealt bucket range by bucket range to the device's XCDs, so that the
+ * slice each XCD gathers from stays in its L2 (the long rows' col_idx
+ * entries are copied once per partition for this).  bytes 0 (the default)
+ * does so with 3 MiB buckets on unweighted graphs whose gathered vector
+ * exceeds 24 MiB, for gathers of 16 to 32 bytes per arc; bytes < 0 never
+ * does; bytes > 0 always does (gathers of at most 32 bytes per arc), with
+ * that bucket size (any graph, any size: for tests and tuning).  Results are the same to rounding for any layout
+ * and reproducible bit for bit under one.  Set it before the first call
+ * that computes anything: GED_ERR_BUSY once a step partition exists.
+ * ged_source_buckets returns the setting.
+ */
+int ged_set_source_buckets(ged_graph *g, int64_t bytes);
+int64_t ged_source_buckets(const ged_graph *g);
+
+/*
+ * Host-only diagnostic (touches no device): the step partition the library
+ * builds for a CSR whose rows it would store as given (row_ptr [n+1],
+ * col_idx [nnz], rows sorted), gathering `units` 8-byte units per arc, with
+ * row-split divisor cut_div (1, 2, 4) and source buckets of bucket_rows
+ * vertices (0: segments).  counts is always filled; each non-NULL array
+ * receives its part of the plan, sized from the counts of a first call:
+ *   blocks [4*n_blocks]  row blocks (row0, row1, arc0, arc1)
+ *   grid2 [4*n_grid2]    segments (row, arc0, arc1, long index), or bucket
+ *                        blocks (piece0, piece1, arc0, arc1) in launch order
+ *   long_rows [n_long], long_first [n_long+1]
+ *   bk_ptr [n_segs+1], bk_lsub [n_segs], bk_ci [bk_arcs]  (buckets only)
+ * The CPU tests check every index of the step kernels against it.
+ */
+typedef struct {
+  int32_t n_blocks, n_grid2, n_segs, n_long, cut, bucketed;
+  int64_t bucket_rows, bk_arcs;
+} ged_partition_counts;
+int ged_partition_plan(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t units,
+                       int32_t cut_div, int64_t bucket_rows, ged_partition_counts *counts,
+                       int32_t *blocks, int32_t *grid2, int32_t *long_rows,
+                       int32_t *long_first, int32_t *bk_ptr, int32_t *bk_lsub, int32_t *bk_ci);
+
 typedef struct {
   /* per-pick outputs, arrays of length k (any may be NULL) */
   int32_t *ell;  /* walk length at which the pick was separated */

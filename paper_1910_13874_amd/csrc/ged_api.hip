@@ -34,6 +34,31 @@ static void check_cut(int cut_div) {
     throw HipError{GED_ERR_ARG, "row-split threshold divisor must be 1, 2 or 4"};
 }
 
+// Source-bucket size (in vertices) of a partition gathering `units` 8-byte
+// units per arc, 0 for segments; copies col_idx to the host the first time.
+// Called with parts_mu held.
+static int64_t bucket_rows_for(ged_graph *g, int units, bool reverse) {
+  if (g->weighted || units > kBucketMaxUnits || g->bucket_bytes < 0 || g->nnz == 0) return 0;
+  if (g->bucket_bytes == 0 &&
+      ((int64_t)g->n * 8 * units <= kBucketAutoBytes || units < kBucketMinUnits))
+    return 0;
+  const int64_t bytes = g->bucket_bytes > 0 ? g->bucket_bytes : kBucketBytes;
+  std::vector<int> &h = reverse ? g->h_ci_r : g->h_ci;
+  if (h.size() != (size_t)g->nnz) {
+    std::vector<int> t((size_t)g->nnz);
+    GED_HIP(hipMemcpy(t.data(), (reverse ? g->ci_r : g->ci).p, sizeof(int) * t.size(),
+                      hipMemcpyDeviceToHost));
+    h.swap(t);
+  }
+  return std::max<int64_t>(1, bytes / (8 * units));
+}
+
+static void build_for(ged_graph *g, Partition &p, int C, int units, bool reverse, int cut_div) {
+  const int64_t br = bucket_rows_for(g, units, reverse);
+  build_partition(p, reverse ? g->h_rp_r : g->h_rp, C, units, cut_div,
+                  br > 0 ? (reverse ? g->h_ci_r : g->h_ci).data() : nullptr, br);
+}
+
 Partition &partition(ged_graph *g, int C, bool reverse, int cut_div) {
   check_cut(cut_div);
   std::lock_guard<std::mutex> lk(g->parts_mu);
@@ -42,7 +67,7 @@ Partition &partition(ged_graph *g, int C, bool reverse, int cut_div) {
   auto it = m.find(key);
   if (it != m.end()) return *it->second;
   auto p = std::make_unique<Partition>();
-  build_partition(*p, reverse ? g->h_rp_r : g->h_rp, C, C, cut_div);
+  build_for(g, *p, C, C, reverse, cut_div);
   Partition &ref = *p;
   m[key] = std::move(p);
   return ref;
@@ -57,7 +82,7 @@ Partition &partition_narrow(ged_graph *g, int C, int cut_div) {
   auto it = m.find(key);
   if (it != m.end()) return *it->second;
   auto p = std::make_unique<Partition>();
-  build_partition(*p, g->h_rp, C, C / 2, cut_div);
+  build_for(g, *p, C, C / 2, false, cut_div);
   Partition &ref = *p;
   m[key] = std::move(p);
   return ref;
@@ -741,6 +766,61 @@ extern "C" int ged_sigma_max(ged_graph *g, double *out_sigma) {
   std::lock_guard<std::recursive_mutex> lk(g->mu);
   return guarded([&]() -> int {
     *out_sigma = sigma_max(g);
+    return GED_OK;
+  });
+}
+
+extern "C" int ged_set_source_buckets(ged_graph *g, int64_t bytes) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  std::lock_guard<std::mutex> pk(g->parts_mu);
+  if (!g->parts.empty() || !g->parts_r.empty())
+    return fail(GED_ERR_BUSY, "the graph's step partitions are already built");
+  g->bucket_bytes = bytes;
+  return GED_OK;
+}
+
+extern "C" int64_t ged_source_buckets(const ged_graph *g) { return g ? g->bucket_bytes : 0; }
+
+extern "C" int ged_partition_plan(const int32_t *row_ptr, const int32_t *col_idx, int32_t n,
+                                  int32_t units, int32_t cut_div, int64_t bucket_rows,
+                                  ged_partition_counts *counts, int32_t *blocks, int32_t *grid2,
+                                  int32_t *long_rows, int32_t *long_first, int32_t *bk_ptr,
+                                  int32_t *bk_lsub, int32_t *bk_ci) {
+  if (!row_ptr || !counts || n < 0 || units < 1 || bucket_rows < 0 ||
+      (bucket_rows > 0 && !col_idx))
+    return fail(GED_ERR_ARG, "bad argument to ged_partition_plan");
+  if (cut_div != 1 && cut_div != 2 && cut_div != 4)
+    return fail(GED_ERR_ARG, "cut_div must be 1, 2 or 4");
+  if (row_ptr[0] != 0) return fail(GED_ERR_GRAPH, "row_ptr[0] must be 0");
+  for (int32_t v = 0; v < n; ++v)
+    if (row_ptr[v + 1] < row_ptr[v]) return fail(GED_ERR_GRAPH, "row_ptr must not decrease");
+  if (col_idx)
+    for (int32_t j = 0; j < row_ptr[n]; ++j)
+      if (col_idx[j] < 0 || col_idx[j] >= n) return fail(GED_ERR_GRAPH, "col_idx out of range");
+  return guarded([&]() -> int {
+    PartitionPlan pl;
+    plan_partition(pl, row_ptr, col_idx, n, units, cut_div, bucket_rows);
+    counts->n_blocks = pl.n_blocks;
+    counts->n_grid2 = pl.n_grid2;
+    counts->n_segs = pl.n_segs;
+    counts->n_long = pl.n_long;
+    counts->cut = pl.cut;
+    counts->bucketed = pl.bucket_rows > 0 ? 1 : 0;
+    counts->bucket_rows = pl.bucket_rows;
+    counts->bk_arcs = pl.bucket_rows > 0 ? (int64_t)pl.bk_ptr[(size_t)pl.n_segs] : 0;
+    auto out = [](int32_t *dst, const std::vector<int> &v, size_t count) {
+      if (dst && count) std::copy(v.begin(), v.begin() + count, dst);
+    };
+    out(blocks, pl.blocks, 4 * (size_t)pl.n_blocks);
+    out(grid2, pl.grid2, 4 * (size_t)pl.n_grid2);
+    out(long_rows, pl.long_rows, (size_t)pl.n_long);
+    out(long_first, pl.long_first, (size_t)pl.n_long + 1);
+    if (pl.bucket_rows > 0) {
+      out(bk_ptr, pl.bk_ptr, (size_t)pl.n_segs + 1);
+      out(bk_lsub, pl.bk_lsub, (size_t)pl.n_segs);
+      out(bk_ci, pl.bk_ci, (size_t)counts->bk_arcs);
+    }
     return GED_OK;
   });
 }

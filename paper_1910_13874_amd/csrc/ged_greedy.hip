@@ -635,8 +635,12 @@ size_t greedy_footprint(ged_graph *g, int ell_max, int k) {
     b += 2 * 8 * n * Cm;                 // X, Y
   }
   // step partials: C = 1 in each direction, and the widest need of each
-  // partial buffer over the batch partitions (StepWs grows field by field)
-  auto fields = [](const Partition &p, size_t *f) {
+  // partial buffer over the batch partitions (StepWs grows field by field);
+  // the partitions themselves (descriptors, and the copied col_idx of
+  // source-bucketed ones)
+  size_t parts = 0;
+  auto fields = [&parts](const Partition &p, size_t *f) {
+    parts += p.device_bytes();
     f[0] = std::max(f[0], 8 * (size_t)std::max(1, p.n_blocks) * p.C);
     f[1] = std::max(f[1], 8 * (size_t)std::max(1, p.n_segs) * p.C);
     f[2] = std::max(f[2], 8 * (size_t)std::max(1, p.n_long) * p.C);
@@ -650,6 +654,7 @@ size_t greedy_footprint(ged_graph *g, int ell_max, int k) {
     if (split && !g->weighted) fields(partition_narrow(g, C), fc);
   }
   for (int i = 0; i < 4; ++i) b += f1[i] + fr[i] + fc[i];
+  b += parts;
   // total-walk levels beyond ell* (the bounds read them up to ell on
   // undirected graphs): the buffer doubles, and the old one is copied
   // before it is freed; the two chain vectors of the level sums

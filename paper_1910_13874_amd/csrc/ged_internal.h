@@ -161,19 +161,60 @@ constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 // as column pairs (narrow_gather).  The threshold -- also the most arcs a
 // block takes -- is the LDS capacity lds_values(C) / units divided by
 // cut_div (1, 2 or 4; the batch autotuner chooses it per graph).
+//
+// Source buckets.  On graphs whose gathered vector is many times the L2 of
+// an XCD, the arcs of the long rows are instead grouped by source: the
+// vertex range is cut into buckets of bucket_rows vertices (about 3 MiB of
+// gathered vector each), every long row's arcs in one bucket form pieces of
+// at most the threshold's arcs, and the pieces -- bucket by bucket -- are
+// packed into bucket blocks that write each piece's raw sum; the fix-up
+// adds a row's pieces in (bucket, offset) order.  Workgroup i of a launch
+// runs on XCD i mod 8, so the bucket blocks are cut into eight contiguous
+// runs, one per XCD, interleaved in the grid: each XCD walks its own range
+// of buckets, and the slice of the vector it gathers from stays in its L2
+// (the short rows gather mostly the low-id, high-degree vertices, which
+// stay cached anyway).  The pieces copy the long rows' col_idx entries; a
+// fix-up wavefront per long row adds its pieces.  Measured on R-MAT scale 22
+// (4 FP64 columns): the step takes 924 instead of 1009 us; single-column
+// steps were slower, so by default only gathers of 2 to 4 units are bucketed.
 constexpr int kMaxCutDiv = 4;
+constexpr int kXcds = 8;                       // XCDs of the device (dispatch round-robin)
+constexpr int64_t kBucketBytes = 3 << 20;      // gathered bytes per source bucket
+constexpr int64_t kBucketAutoBytes = 24 << 20; // bucket long rows above this gathered size
+constexpr int kBucketMinUnits = 2;             // narrowest gather (8-byte units per arc) and
+constexpr int kBucketMaxUnits = 4;             // widest, bucketed by default
 struct Partition {
   int C = 0;
   int units = 0;
   int cut = 0;       // row-split threshold in arcs
   int n_blocks = 0;  // row blocks
-  int n_segs = 0;    // long-row segments
+  int n_segs = 0;    // long-row segments, or pieces (the slots of seg_out)
+  int n_grid2 = 0;   // blocks after the row blocks: segments, or bucket blocks
   int n_long = 0;    // long rows
+  int64_t bucket_rows = 0;  // 0: long rows cut into segments, else source buckets
   DBuf blocks;       // int4 [n_blocks]: (row0, row1, nnz0, nnz1)
-  DBuf segs;         // int4 [n_segs]:   (row, nnz0, nnz1, long index)
+  DBuf segs;         // int4 [n_grid2]: segments (row, nnz0, nnz1, long index), or
+                     // bucket blocks (piece0, piece1, arc0, arc1) in launch order
   DBuf long_rows;    // int  [n_long]:   row id
-  DBuf long_first;   // int  [n_long+1]: first segment of each long row
+  DBuf long_first;   // int  [n_long+1]: first segment (or entry of bk_lsub) of each long row
+  DBuf bk_ci;        // int [arcs of long rows]: sources, piece by piece
+  DBuf bk_ptr;       // int [n_segs+1]: first arc of each piece in bk_ci
+  DBuf bk_lsub;      // int [n_segs]: the pieces of each long row in (bucket, offset) order
+  size_t device_bytes() const {
+    return blocks.bytes + segs.bytes + long_rows.bytes + long_first.bytes + bk_ci.bytes +
+           bk_ptr.bytes + bk_lsub.bytes;
+  }
 };
+
+// Host plan of a partition (what build_partition uploads).
+struct PartitionPlan {
+  int n_blocks = 0, n_segs = 0, n_grid2 = 0, n_long = 0, cut = 0;
+  int64_t bucket_rows = 0;
+  std::vector<int> blocks, grid2, long_rows, long_first, bk_ci, bk_ptr, bk_lsub;  // int4 as 4 ints
+};
+// ci: the CSR's col_idx on the host (read only when bucket_rows > 0).
+void plan_partition(PartitionPlan &pl, const int *rp, const int *ci, int n, int units,
+                    int cut_div, int64_t bucket_rows);
 
 // Gather source of a step (what x(u) means).
 enum InMode : int {
@@ -236,7 +277,7 @@ struct StepArgs {
   double alpha = 0;
   int accum = 0;                 // 1: add this step's column sums to blk_part/long_part
   double *blk_part = nullptr;    // [n_blocks*C] block column sums
-  double *seg_out = nullptr;     // [n_segs*C] raw segment sums
+  double *seg_out = nullptr;     // [n_segs*C] raw segment (or piece) sums
   double *long_part = nullptr;   // [n_long*C] long-row outputs (for column sums)
   // IN_CNT / IN_CNT32 source
   const uint64_t *Xc = nullptr;    // [n*C]
@@ -262,6 +303,9 @@ struct StepArgs {
   // plain level elsewhere (alpha * sum; the count for OUT_GAIN32D) -- and a
   // combining step stores it to Y instead of combining it.
   int spec_from = 1 << 30;
+  // source-bucketed partitions (set by the launch from the partition)
+  const int *bk_ci = nullptr;   // sources of the pieces
+  const int *bk_ptr = nullptr;  // [pieces+1] first arc of each piece
 };
 
 // Walk-count step: Y = epilogue(alpha * A X) with column sums.  Three
@@ -279,8 +323,9 @@ constexpr int kReduceBlocks = 256;
 void launch_reduce(const Partition &p, const StepArgs &a, double *level, double *acc,
                    const int *active, hipStream_t st, double *ws2);
 
+// bucket_rows > 0 groups the long rows by source (ci: host col_idx).
 void build_partition(Partition &p, const std::vector<int> &row_ptr, int C, int units,
-                     int cut_div = 1);
+                     int cut_div = 1, const int *ci = nullptr, int64_t bucket_rows = 0);
 
 // 32-bit inputs at C >= 2 are gathered as pairs of adjacent columns (8 bytes
 // per lane), so a wavefront's load covers as many cache lines as an FP64
@@ -417,6 +462,13 @@ struct ged_graph {
   ged::DBuf rp, ci, w;          // device CSR (in-neighbour rows)
   ged::DBuf rp_r, ci_r, w_r;    // reverse graph (directed only)
   std::vector<int> h_rp_r;
+  // host col_idx (and of the reverse graph), copied when a source-bucketed
+  // partition is first built
+  std::vector<int> h_ci, h_ci_r;
+  // gathered bytes per source bucket of new partitions: 0 = kBucketBytes
+  // where the gathered vector exceeds kBucketAutoBytes, < 0 = never, > 0 =
+  // always, with this size
+  int64_t bucket_bytes = 0;
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   std::recursive_mutex mu;

@@ -422,6 +422,59 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
       }
     }
     block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C, a.accum);
+  } else if (a.bk_ci != nullptr) {
+    // Bucket block: pieces [s0, s0 + np) of long rows, all of whose sources
+    // lie in one or two adjacent buckets; the same two phases as a row block
+    // over the pieces' copied col_idx, writing each piece's raw sum (the
+    // fix-up applies the epilogue).  Weighted graphs are never bucketed.
+    if constexpr (!WGT) {
+      const int4 d = segs[b - n_blocks];
+      const int s0 = d.x, np = d.y - d.x, p0 = d.z;
+      const int tot = (d.w - d.z) * CU;  // >= CU: every piece has an arc
+      const int jmax = d.w - 1;
+      int u[PT];
+#pragma unroll
+      for (int q = 0; q < PT; ++q)
+        u[q] = __builtin_nontemporal_load(a.bk_ci + min(p0 + (t + q * kBlock) / CU, jmax));
+      int rv[RT];
+#pragma unroll
+      for (int k = 0; k < RT; ++k) rv[k] = a.bk_ptr[s0 + min(t + k * kBlock, np)];
+      double v[NP ? 1 : PT];
+      uint2 v2[NP ? PT : 1];
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        if constexpr (NP)
+          v2[q] = *reinterpret_cast<const uint2 *>(a.Xc32 + (size_t)u[q] * C +
+                                                   2 * ((t + q * kBlock) & (CU - 1)));
+        else
+          v[q] = load_in<C, IN>(a, u[q], (t + q * kBlock) & (C - 1));
+      }
+#pragma unroll
+      for (int k = 0; k < RT; ++k)
+        if (t + k * kBlock <= np) rps[t + k * kBlock] = rv[k] - p0;
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const int f = t + q * kBlock;
+        if constexpr (NP)
+          reinterpret_cast<uint2 *>(vals)[f < tot ? f : LV + t] = v2[q];
+        else
+          vals[f < tot ? f : LV + t] = v[q];
+      }
+      __syncthreads();
+      int tpr = (kBlock / C < 64) ? kBlock / C : 64;
+      while (tpr > 1 && np * C * tpr > kBlock) tpr >>= 1;
+      const int s = t & (tpr - 1);
+      const int pair = t / tpr;
+      const int c = pair & (C - 1);
+      const int rstep = (kBlock / tpr) / C;
+      for (int rl = pair / C; rl < np; rl += rstep) {
+        const int j0 = rps[rl], j1 = rps[rl + 1];
+        double acc = 0.0;
+        for (int j = j0 + s; j < j1; j += tpr) acc += (double)vals[j * C + c];
+        for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (s == 0) a.seg_out[(size_t)(s0 + rl) * C + c] = acc;
+      }
+    }
   } else if constexpr (NP) {
     // One segment of a long row, column pairs: kBlock / CU lanes per pair.
     const int4 sd = segs[b - n_blocks];
@@ -470,26 +523,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
   }
 }
 
-// Long rows: add the segment sums of each row in segment order, apply the
-// epilogue, and keep the output for the column sums.
+// Long row l (row r), column c, given the sum of its segments or pieces:
+// apply the epilogue and keep the output for the column sums.
 template <int C, int OUT>
-__global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restrict__ long_rows,
-                                                  const int *__restrict__ long_first, int n_long) {
-  const int gid = blockIdx.x * kBlock + threadIdx.x;
-  const int l = gid / C, c = gid & (C - 1);
-  if (l >= n_long) return;
-  const int r = long_rows[l];
-  const int q0 = long_first[l], q1 = long_first[l + 1];
-  // four independent partial sums keep four loads in flight; combined in a
-  // fixed order
-  double s4[4] = {0.0, 0.0, 0.0, 0.0};
-  int q = q0;
-  for (; q + 3 < q1; q += 4) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s4[k] += a.seg_out[(size_t)(q + k) * C + c];
-  }
-  for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
-  const double acc = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+__device__ __forceinline__ void fixup_tail(const StepArgs &a, int l, int r, int c, double acc) {
   double y = epilogue<C, OUT>(a, r, c, acc);
   if constexpr (OUT == OUT_GAINCOMB) {
     if (c >= a.spec_from) {  // miss column: its level is stored, not combined
@@ -515,6 +552,62 @@ __global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restr
   }
   double *lp = a.long_part + (size_t)l * C + c;
   *lp = a.accum ? *lp + y : y;
+}
+
+// Long rows cut into segments: one thread per (row, column) adds the row's
+// segment sums in segment order.
+template <int C, int OUT>
+__global__ __launch_bounds__(kBlock) void k_fixup(StepArgs a, const int *__restrict__ long_rows,
+                                                  const int *__restrict__ long_first, int n_long) {
+  const int gid = blockIdx.x * kBlock + threadIdx.x;
+  const int l = gid / C, c = gid & (C - 1);
+  if (l >= n_long) return;
+  const int q0 = long_first[l], q1 = long_first[l + 1];
+  // four independent partial sums keep four loads in flight; combined in a
+  // fixed order
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  int q = q0;
+  for (; q + 3 < q1; q += 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s4[k] += a.seg_out[(size_t)(q + k) * C + c];
+  }
+  for (; q < q1; ++q) s4[0] += a.seg_out[(size_t)q * C + c];
+  fixup_tail<C, OUT>(a, l, long_rows[l], c, (s4[0] + s4[1]) + (s4[2] + s4[3]));
+}
+
+// Long rows in source-bucket pieces (scattered over seg_out, listed per row
+// by lsub; a hub row has hundreds): one wavefront per row, lanes striding
+// over its pieces with all columns, then a butterfly sum (fixed order, so
+// deterministic); lane c finishes column c.  Bucketed partitions gather at
+// most 4 units per arc, so C <= 8 here.
+template <int C, int OUT>
+__global__ __launch_bounds__(kBlock) void k_fixup_pieces(StepArgs a,
+                                                         const int *__restrict__ long_rows,
+                                                         const int *__restrict__ long_first,
+                                                         const int *__restrict__ lsub,
+                                                         int n_long) {
+  if constexpr (C <= 8) {
+    const int l = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (l >= n_long) return;  // the whole wavefront
+    const int q0 = long_first[l], q1 = long_first[l + 1];
+    double s[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = 0.0;
+    for (int q = q0 + lane; q < q1; q += 64) {
+      const double *p = a.seg_out + (size_t)lsub[q] * C;
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c] += p[c];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      for (int off = 32; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off, 64);
+    double acc = s[0];
+#pragma unroll
+    for (int c = 1; c < C; ++c)
+      if (lane == c) acc = s[c];
+    if (lane < C) fixup_tail<C, OUT>(a, l, long_rows[l], lane, acc);
+  }
 }
 
 // Pass 1: block g sums rows [g*R, (g+1)*R) of the concatenation of blk_part
@@ -568,15 +661,26 @@ __global__ __launch_bounds__(kBlock) void k_reduce2(const double *__restrict__ i
 
 template <int C, int IN, int OUT, bool WGT>
 static void launch_t(const Partition &p, const StepArgs &a, hipStream_t st, hipEvent_t ev) {
-  const int grid = p.n_blocks + p.n_segs;
+  const int grid = p.n_blocks + p.n_grid2;
+  StepArgs b = a;
+  const bool bk = p.bucket_rows > 0 && p.n_grid2 > 0;
+  if (bk && C > 8) throw HipError{GED_ERR_ARG, "source buckets at more than 8 columns"};
+  b.bk_ci = bk ? p.bk_ci.as<const int>() : nullptr;
+  b.bk_ptr = bk ? p.bk_ptr.as<const int>() : nullptr;
   if (grid > 0)
-    hipLaunchKernelGGL((k_step<C, IN, OUT, WGT>), dim3(grid), dim3(kBlock), 0, st, a,
+    hipLaunchKernelGGL((k_step<C, IN, OUT, WGT>), dim3(grid), dim3(kBlock), 0, st, b,
                        p.blocks.as<const int4>(), p.segs.as<const int4>(), p.n_blocks);
   if (ev) GED_HIP(hipEventRecord(ev, st));
-  if (p.n_long > 0) {
+  if (p.n_long > 0 && bk) {
+    const int rows_per_block = kBlock / 64;
+    hipLaunchKernelGGL((k_fixup_pieces<C, OUT>),
+                       dim3((p.n_long + rows_per_block - 1) / rows_per_block), dim3(kBlock), 0, st,
+                       b, p.long_rows.as<const int>(), p.long_first.as<const int>(),
+                       p.bk_lsub.as<const int>(), p.n_long);
+  } else if (p.n_long > 0) {
     const int thr = p.n_long * C;
     hipLaunchKernelGGL((k_fixup<C, OUT>), dim3((thr + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                       a, p.long_rows.as<const int>(), p.long_first.as<const int>(), p.n_long);
+                       b, p.long_rows.as<const int>(), p.long_first.as<const int>(), p.n_long);
   }
 }
 
@@ -688,22 +792,106 @@ void launch_reduce(const Partition &p, const StepArgs &a, double *level, double 
 
 // ----------------------------------------------------------- partition --
 
-void build_partition(Partition &p, const std::vector<int> &rp, int C, int units, int cut_div) {
-  const int n = (int)rp.size() - 1;
-  const int nnz_blk = std::max(1, lds_values(C) / units / std::max(1, cut_div));
+// Source buckets of the long rows (see Partition): pieces of at most cut
+// arcs, each inside one bucket, numbered bucket by bucket (rows in order,
+// arcs in order); bk_lsub lists each row's pieces in its arc order; bucket
+// blocks pack consecutive pieces (at most cut arcs, kRowsPerBlock pieces)
+// and are dealt to the XCDs in eight contiguous runs.
+static void plan_buckets(PartitionPlan &pl, const int *rp, const int *ci, int nnz_blk,
+                         int64_t n) {
+  const int64_t BR = pl.bucket_rows;
+  const int64_t nbk = (n + BR - 1) / BR;
+  const int nl = (int)pl.long_rows.size();
+  std::vector<int64_t> pcnt((size_t)nbk + 1, 0), acnt((size_t)nbk + 1, 0);
+  auto runs = [&](int r, auto &&f) {  // f(bucket, j0, j1) for each piece of row r
+    int j = rp[r];
+    const int e = rp[r + 1];
+    while (j < e) {
+      const int64_t b = ci[j] / BR;
+      int k = j + 1;
+      while (k < e && k - j < nnz_blk && ci[k] / BR == b) ++k;
+      f(b, j, k);
+      j = k;
+    }
+  };
+  for (int l = 0; l < nl; ++l)
+    runs(pl.long_rows[l], [&](int64_t b, int j0, int j1) {
+      pcnt[(size_t)b + 1] += 1;
+      acnt[(size_t)b + 1] += j1 - j0;
+    });
+  for (int64_t b = 0; b < nbk; ++b) {
+    pcnt[(size_t)b + 1] += pcnt[(size_t)b];
+    acnt[(size_t)b + 1] += acnt[(size_t)b];
+  }
+  const int npieces = (int)pcnt[(size_t)nbk];
+  const int64_t narcs = acnt[(size_t)nbk];
+  pl.bk_ptr.assign((size_t)npieces + 1, 0);
+  pl.bk_ci.assign((size_t)std::max<int64_t>(1, narcs), 0);
+  pl.bk_lsub.assign((size_t)std::max(1, npieces), 0);
+  pl.long_first.assign((size_t)nl + 1, 0);
+  std::vector<int64_t> pc(pcnt.begin(), pcnt.end() - 1), ac(acnt.begin(), acnt.end() - 1);
+  int q = 0;
+  for (int l = 0; l < nl; ++l) {
+    pl.long_first[(size_t)l] = q;
+    runs(pl.long_rows[l], [&](int64_t b, int j0, int j1) {
+      const int id = (int)pc[(size_t)b]++;
+      const int64_t at = ac[(size_t)b];
+      ac[(size_t)b] += j1 - j0;
+      pl.bk_ptr[(size_t)id] = (int)at;
+      std::copy(ci + j0, ci + j1, pl.bk_ci.begin() + at);
+      pl.bk_lsub[(size_t)q++] = id;
+    });
+  }
+  pl.long_first[(size_t)nl] = q;
+  pl.bk_ptr[(size_t)npieces] = (int)narcs;
+  // bucket blocks in piece order
+  std::vector<int> bb;
+  for (int s0 = 0; s0 < npieces;) {
+    int s1 = s0, arcs = 0;
+    while (s1 < npieces && s1 - s0 < kRowsPerBlock) {
+      const int len = pl.bk_ptr[(size_t)s1 + 1] - pl.bk_ptr[(size_t)s1];
+      if (arcs + len > nnz_blk) break;
+      arcs += len;
+      ++s1;
+    }
+    bb.insert(bb.end(), {s0, s1, pl.bk_ptr[(size_t)s0], pl.bk_ptr[(size_t)s1]});
+    s0 = s1;
+  }
+  const int nb = (int)bb.size() / 4;
+  // grid position n_blocks + i runs on XCD (n_blocks + i) mod kXcds: XCD x
+  // takes the x-th contiguous run of the blocks, as long as its positions
+  int start[kXcds + 1] = {0}, take[kXcds] = {0};
+  for (int i = 0; i < nb; ++i) ++start[(pl.n_blocks + i) % kXcds + 1];
+  for (int x = 0; x < kXcds; ++x) start[x + 1] += start[x];
+  pl.grid2.resize((size_t)nb * 4);
+  for (int i = 0; i < nb; ++i) {
+    const int x = (pl.n_blocks + i) % kXcds;
+    const int src = start[x] + take[x]++;
+    std::copy(bb.begin() + (size_t)src * 4, bb.begin() + (size_t)src * 4 + 4,
+              pl.grid2.begin() + (size_t)i * 4);
+  }
+  pl.n_segs = npieces;
+  pl.n_grid2 = nb;
+}
+
+void plan_partition(PartitionPlan &pl, const int *rp, const int *ci, int n, int units,
+                    int cut_div, int64_t bucket_rows) {
+  pl = PartitionPlan();
+  const int nnz_blk = std::max(1, lds_values(0) / units / std::max(1, cut_div));
   const int seg_len = std::max(1, kSegDoubles / units);
-  std::vector<int4> blocks;
-  std::vector<int4> segs;
-  std::vector<int> lrows, lfirst;
+  pl.cut = nnz_blk;
+  std::vector<int> &segs = pl.grid2;
   int r = 0;
   while (r < n) {
     const int deg = rp[r + 1] - rp[r];
     if (deg > nnz_blk) {
-      const int l = (int)lrows.size();
-      lrows.push_back(r);
-      lfirst.push_back((int)segs.size());
-      for (int j = rp[r]; j < rp[r + 1]; j += seg_len)
-        segs.push_back(make_int4(r, j, std::min(j + seg_len, rp[r + 1]), l));
+      const int l = (int)pl.long_rows.size();
+      pl.long_rows.push_back(r);
+      if (bucket_rows <= 0) {
+        pl.long_first.push_back((int)segs.size() / 4);
+        for (int j = rp[r]; j < rp[r + 1]; j += seg_len)
+          segs.insert(segs.end(), {r, j, std::min(j + seg_len, rp[r + 1]), l});
+      }
       ++r;
       continue;
     }
@@ -715,29 +903,46 @@ void build_partition(Partition &p, const std::vector<int> &rp, int C, int units,
       acc += d;
       ++r;
     }
-    blocks.push_back(make_int4(r0, r, rp[r0], rp[r]));
+    pl.blocks.insert(pl.blocks.end(), {r0, r, rp[r0], rp[r]});
   }
-  lfirst.push_back((int)segs.size());
+  pl.n_blocks = (int)pl.blocks.size() / 4;
+  pl.n_long = (int)pl.long_rows.size();
+  if (bucket_rows > 0 && pl.n_long > 0) {
+    pl.bucket_rows = bucket_rows;
+    plan_buckets(pl, rp, ci, nnz_blk, n);
+  } else {
+    pl.long_first.push_back((int)segs.size() / 4);
+    pl.n_segs = (int)segs.size() / 4;
+    pl.n_grid2 = pl.n_segs;
+  }
+}
+
+void build_partition(Partition &p, const std::vector<int> &rp, int C, int units, int cut_div,
+                     const int *ci, int64_t bucket_rows) {
+  PartitionPlan pl;
+  plan_partition(pl, rp.data(), ci, (int)rp.size() - 1, units, cut_div, ci ? bucket_rows : 0);
   p.C = C;
   p.units = units;
-  p.cut = nnz_blk;
-  p.n_blocks = (int)blocks.size();
-  p.n_segs = (int)segs.size();
-  p.n_long = (int)lrows.size();
-  p.blocks.ensure(sizeof(int4) * std::max<size_t>(1, blocks.size()));
-  p.segs.ensure(sizeof(int4) * std::max<size_t>(1, segs.size()));
-  p.long_rows.ensure(sizeof(int) * std::max<size_t>(1, lrows.size()));
-  p.long_first.ensure(sizeof(int) * lfirst.size());
-  if (!blocks.empty())
-    GED_HIP(hipMemcpy(p.blocks.p, blocks.data(), sizeof(int4) * blocks.size(),
-                      hipMemcpyHostToDevice));
-  if (!segs.empty())
-    GED_HIP(hipMemcpy(p.segs.p, segs.data(), sizeof(int4) * segs.size(), hipMemcpyHostToDevice));
-  if (!lrows.empty())
-    GED_HIP(hipMemcpy(p.long_rows.p, lrows.data(), sizeof(int) * lrows.size(),
-                      hipMemcpyHostToDevice));
-  GED_HIP(hipMemcpy(p.long_first.p, lfirst.data(), sizeof(int) * lfirst.size(),
-                    hipMemcpyHostToDevice));
+  p.cut = pl.cut;
+  p.n_blocks = pl.n_blocks;
+  p.n_segs = pl.n_segs;
+  p.n_grid2 = pl.n_grid2;
+  p.n_long = pl.n_long;
+  p.bucket_rows = pl.bucket_rows;
+  auto up = [](DBuf &d, const std::vector<int> &v) {
+    d.ensure(sizeof(int) * std::max<size_t>(4, v.size()));
+    if (!v.empty())
+      GED_HIP(hipMemcpy(d.p, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice));
+  };
+  up(p.blocks, pl.blocks);
+  up(p.segs, pl.grid2);
+  up(p.long_rows, pl.long_rows);
+  up(p.long_first, pl.long_first);
+  if (p.bucket_rows > 0) {
+    up(p.bk_ci, pl.bk_ci);
+    up(p.bk_ptr, pl.bk_ptr);
+    up(p.bk_lsub, pl.bk_lsub);
+  }
 }
 
 // -------------------------------------------------------- small kernels --

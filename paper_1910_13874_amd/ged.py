@@ -52,6 +52,13 @@ class GreedyTrace(ctypes.Structure):
                 ("n_rounds", ctypes.c_int32)]
 
 
+class PartitionCounts(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("n_grid2", ctypes.c_int32),
+                ("n_segs", ctypes.c_int32), ("n_long", ctypes.c_int32),
+                ("cut", ctypes.c_int32), ("bucketed", ctypes.c_int32),
+                ("bucket_rows", ctypes.c_int64), ("bk_arcs", ctypes.c_int64)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("edges", ctypes.c_double),
@@ -87,6 +94,11 @@ _sig("ged_score_batch", ctypes.c_int, [c_graph_p, P_I64, P_I32, ctypes.c_int32, 
                                        ctypes.c_double, P_F64])
 _sig("ged_batch_tile", ctypes.c_int32, [c_graph_p])
 _sig("ged_set_batch_tile", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_set_source_buckets", ctypes.c_int, [c_graph_p, ctypes.c_int64])
+_sig("ged_source_buckets", ctypes.c_int64, [c_graph_p])
+_sig("ged_partition_plan", ctypes.c_int,
+     [P_I32, P_I32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+      ctypes.POINTER(PartitionCounts), P_I32, P_I32, P_I32, P_I32, P_I32, P_I32, P_I32])
 _sig("ged_set_batch_row_cut", ctypes.c_int, [c_graph_p, ctypes.c_int32])
 _sig("ged_batch_row_cut", ctypes.c_int32, [c_graph_p])
 _sig("ged_set_greedy_width", ctypes.c_int, [c_graph_p, ctypes.c_int32])
@@ -284,6 +296,14 @@ class GedGraph:
         """Row-split threshold divisor of batched tiles (1, 2, 4; 0 = autotune)."""
         _ck(_lib.ged_set_batch_row_cut(self.handle, int(cut_div)), "ged_set_batch_row_cut")
 
+    def set_source_buckets(self, nbytes):
+        """Source-bucket size of the long rows' pieces in bytes of gathered
+        vector (0 = library's choice, < 0 = off); before the first step."""
+        _ck(_lib.ged_set_source_buckets(self.handle, int(nbytes)), "ged_set_source_buckets")
+
+    def source_buckets(self):
+        return _lib.ged_source_buckets(self.handle)
+
     def set_greedy_width(self, width):
         """Candidates per gain SpMM of the greedy (2, 4, 8, 16; 0 = library's choice)."""
         _ck(_lib.ged_set_greedy_width(self.handle, int(width)), "ged_set_greedy_width")
@@ -423,6 +443,41 @@ IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh", "cn
 OUT_MODES = ["plain", "inj", "zero", "tile", "gain", "pool", "combine", "combine32", "gaincomb",
              "tile32", "combine32l", "gain32", "gaincomb32l", "zero32", "gain32d", "gaincomb32s"]
 KIND_BASE = 16  # a profile record's kind is input mode * KIND_BASE + output mode
+
+
+def partition_plan(row_ptr, col_idx, n, units, cut_div=1, bucket_rows=0):
+    """The step partition the library builds for a CSR (host-only call):
+    dict of counts and int32 arrays (blocks and grid2 as (m, 4))."""
+    rp = _i32(row_ptr)[0]
+    ci = _i32(col_idx)[0] if col_idx is not None and len(col_idx) else np.zeros(1, np.int32)
+    cnt = PartitionCounts()
+    p = lambda a: a.ctypes.data_as(P_I32)
+    null = ctypes.cast(None, P_I32)
+    _ck(_lib.ged_partition_plan(p(rp), p(ci), int(n), int(units), int(cut_div), int(bucket_rows),
+                                ctypes.byref(cnt), null, null, null, null, null, null, null),
+        "ged_partition_plan")
+    out = {f: getattr(cnt, f) for f, _ in PartitionCounts._fields_}
+    arr = {"blocks": np.zeros(4 * max(1, cnt.n_blocks), np.int32),
+           "grid2": np.zeros(4 * max(1, cnt.n_grid2), np.int32),
+           "long_rows": np.zeros(max(1, cnt.n_long), np.int32),
+           "long_first": np.zeros(cnt.n_long + 1, np.int32),
+           "bk_ptr": np.zeros(cnt.n_segs + 1, np.int32),
+           "bk_lsub": np.zeros(max(1, cnt.n_segs), np.int32),
+           "bk_ci": np.zeros(max(1, cnt.bk_arcs), np.int32)}
+    _ck(_lib.ged_partition_plan(p(rp), p(ci), int(n), int(units), int(cut_div), int(bucket_rows),
+                                ctypes.byref(cnt), *[p(arr[k]) for k in
+                                                     ("blocks", "grid2", "long_rows", "long_first",
+                                                      "bk_ptr", "bk_lsub", "bk_ci")]),
+        "ged_partition_plan")
+    out["blocks"] = arr["blocks"][:4 * cnt.n_blocks].reshape(-1, 4)
+    out["grid2"] = arr["grid2"][:4 * cnt.n_grid2].reshape(-1, 4)
+    out["long_rows"] = arr["long_rows"][:cnt.n_long]
+    out["long_first"] = arr["long_first"]
+    if cnt.bucketed:
+        out["bk_ptr"] = arr["bk_ptr"]
+        out["bk_lsub"] = arr["bk_lsub"][:cnt.n_segs]
+        out["bk_ci"] = arr["bk_ci"][:cnt.bk_arcs]
+    return out
 
 
 def kernel_name(columns, kind, weighted=False):

@@ -370,6 +370,54 @@ def test_batch_matches_solo_and_oracle(ged):
     gg.close()
 
 
+@pytest.mark.parametrize("name,nbytes", [("rmat16", 4096), ("ba20k", 65536), ("star", 512),
+                                         ("directed", 2048)])
+def test_source_buckets_parity(ged, name, nbytes):
+    """Every path with the long rows' arcs grouped by source (forced, with
+    small buckets so that rows split into many pieces): single scores, a
+    batch, the greedy (gain batches, miss chains; the reverse graph when
+    directed) against the oracle, and against the same graph without
+    buckets (rounding only).  Setting the layout once a partition exists is
+    refused."""
+    if name == "star":
+        g = inputs.from_edges(9000, np.zeros(8999, np.int32), np.arange(1, 9000, dtype=np.int32),
+                              name="star9k")
+    elif name == "directed":
+        g = directed_graph()
+    else:
+        g = GRAPHS[name]()
+    say(f"[source buckets] {name} n={g.n} nnz={g.nnz} bucket bytes={nbytes}")
+    gb = ged.GedGraph.from_graph(g)
+    gb.set_source_buckets(nbytes)
+    assert gb.source_buckets() == nbytes
+    gp = ged.GedGraph.from_graph(g)
+    gp.set_source_buckets(-1)
+    alpha = oracle.default_alpha(g)
+    rev = inputs.reverse(g) if g.directed else None
+    for seed, size in [(11, 1), (12, 5), (13, 40), (14, 300)]:
+        S = inputs.group(g.n, size, seed)
+        s = check_score(gb, g, S, alpha, tag=(name, seed))
+        assert rel(s, gp.score(S, alpha, EPS)) <= 1e-12
+    with pytest.raises(ged.GedError) as e:
+        gb.set_source_buckets(0)
+    assert e.value.code == -8
+    off, mem = inputs.groups(g.n, 40, 1, 120, 170)
+    b = gb.score_batch(off, mem, alpha, EPS)
+    bp = gp.score_batch(off, mem, alpha, EPS)
+    for j in range(len(off) - 1):
+        assert rel(b[j], bp[j]) <= 1e-12, (j, b[j], bp[j])
+        if j % 8 == 0:
+            assert rel(b[j], oracle.score(g, mem[off[j]:off[j + 1]], alpha, EPS)[0]) <= REL
+    np.testing.assert_array_equal(gb.score_batch(off, mem, alpha, EPS), b)
+    k = 8
+    rg = gb.greedy(k, alpha, EPS)
+    ro = oracle.greedy(g, k, alpha, EPS, rev=rev)
+    compare_greedy(rg, ro, name)
+    assert list(gp.greedy(k, alpha, EPS)["group"]) == list(rg["group"])
+    gb.close()
+    gp.close()
+
+
 # ------------------------------------------------------------ full sizes --
 
 def load_golden(name):

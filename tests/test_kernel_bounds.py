@@ -197,3 +197,102 @@ def test_split_worklist_fits_capacity(name):
                         entries += chunks
             cap += wl_need(n, nnz, int(deg[S].sum()))
         assert entries <= cap, (name, C, entries, cap)
+
+
+def check_plan_matches_emulation(ged, rp, ci, n, U, cut_div):
+    """Without buckets the library's own planner gives exactly the partition
+    emulated above."""
+    pl = ged.partition_plan(rp, ci, n, U, cut_div, 0)
+    blocks, segs, lrows = partition(rp, U, U, cut_div)
+    assert pl["bucketed"] == 0 and pl["cut"] == max(1, K_LDS // U // cut_div)
+    assert [tuple(b) for b in pl["blocks"]] == [tuple(map(int, b)) for b in blocks]
+    assert [tuple(s[:3]) for s in pl["grid2"]] == [tuple(map(int, s)) for s in segs]
+    assert list(pl["long_rows"]) == list(lrows)
+    assert pl["n_segs"] == pl["n_grid2"] == len(segs)
+
+
+def check_buckets(ged, rp, ci, n, C, pairs, cut_div, bucket_rows, rng):
+    """Source-bucketed plan from the library's planner: every long row's arcs
+    are split into pieces inside one bucket, copied, and summed back exactly
+    by the fix-up's piece lists; bucket blocks respect the block limits and
+    are dealt to the XCDs (grid position n_blocks + i runs on XCD
+    (n_blocks + i) mod 8) in eight contiguous runs; and every index the step
+    kernel's bucket blocks and the fix-up form stays inside its buffer."""
+    U = C // 2 if pairs else C
+    pl = ged.partition_plan(rp, ci, n, U, cut_div, bucket_rows)
+    cut = pl["cut"]
+    deg = np.diff(rp)
+    lrows = pl["long_rows"]
+    if len(lrows) == 0:
+        assert pl["bucketed"] == 0
+        return
+    assert pl["bucketed"] == 1 and pl["bucket_rows"] == bucket_rows
+    nseg, bk_ptr, bk_ci, lsub = pl["n_segs"], pl["bk_ptr"], pl["bk_ci"], pl["bk_lsub"]
+    lf = pl["long_first"]
+    assert bk_ptr[0] == 0 and np.all(np.diff(bk_ptr) >= 1) and bk_ptr[-1] == pl["bk_arcs"]
+    assert np.all(np.diff(bk_ptr) <= cut)
+    assert pl["bk_arcs"] == int(deg[lrows].sum())
+    # pieces of each row: its arcs in order, each piece inside one bucket
+    assert lf[0] == 0 and np.all(np.diff(lf) >= 1) and lf[-1] == nseg
+    assert sorted(lsub.tolist()) == list(range(nseg))
+    bucket_of_piece = np.empty(nseg, np.int64)
+    for l, r in enumerate(lrows):
+        pieces = [bk_ci[bk_ptr[s]:bk_ptr[s + 1]] for s in lsub[lf[l]:lf[l + 1]]]
+        assert np.array_equal(np.concatenate(pieces), ci[rp[r]:rp[r + 1]])
+        for s, p in zip(lsub[lf[l]:lf[l + 1]], pieces):
+            b = p // bucket_rows
+            assert (b == b[0]).all()
+            bucket_of_piece[s] = b[0]
+    assert np.all(np.diff(bucket_of_piece) >= 0)  # pieces numbered bucket by bucket
+    # exact sums through the pieces and the fix-up lists
+    x = rng.integers(0, 1000, n).astype(np.int64)
+    piece_sum = np.array([x[bk_ci[bk_ptr[s]:bk_ptr[s + 1]]].sum() for s in range(nseg)])
+    for l, r in enumerate(lrows):
+        assert piece_sum[lsub[lf[l]:lf[l + 1]]].sum() == x[ci[rp[r]:rp[r + 1]]].sum()
+    # bucket blocks: limits, cover, XCD runs
+    g2 = pl["grid2"]
+    nb, n_blocks = len(g2), pl["n_blocks"]
+    assert pl["n_grid2"] == nb
+    order = sorted(range(nb), key=lambda i: g2[i][0])
+    assert [int(g2[i][0]) for i in order] == [0] + [int(g2[i][1]) for i in order[:-1]]
+    assert int(g2[order[-1]][1]) == nseg
+    runs = [[i for i in range(nb) if (n_blocks + i) % 8 == xcd] for xcd in range(8)]
+    seq = [int(g2[i][0]) for xcd in range(8) for i in runs[xcd]]
+    assert seq == sorted(seq)  # XCD 0's run first, each run in piece order
+    PT = K_LDS // K_BLOCK
+    RT = (K_ROWS + K_BLOCK) // K_BLOCK
+    t = np.arange(K_BLOCK)
+    for (s0, s1, a0, a1) in g2:
+        npc, tot = s1 - s0, (a1 - a0) * U
+        assert 1 <= npc <= K_ROWS and U <= tot <= K_LDS
+        assert bk_ptr[s0] == a0 and bk_ptr[s1] == a1
+        for q in range(PT):
+            j = np.minimum(a0 + (t + q * K_BLOCK) // U, a1 - 1)
+            assert j.min() >= 0 and j.max() < len(bk_ci)
+            u = bk_ci[j]
+            assert u.min() >= 0 and u.max() < n
+            if pairs:
+                e = u.astype(np.int64) * C + 2 * ((t + q * K_BLOCK) & (U - 1))
+                assert (e + 1).max() < n * C
+            f = t + q * K_BLOCK
+            assert np.where(f < tot, f, K_LDS + t).max() < K_LDS + K_BLOCK
+        for k in range(RT):
+            assert (s0 + np.minimum(t + k * K_BLOCK, npc)).max() <= nseg
+        # phase 2: arc slots j*C + c of the staged values, piece sums to seg_out
+        assert (a1 - a0) * C <= (2 if pairs else 1) * K_LDS
+        assert s1 <= nseg
+    # fix-up: entries of the piece lists name seg_out slots
+    assert lsub.max() < nseg and lf.max() <= len(lsub)
+
+
+@pytest.mark.parametrize("g", graphs(), ids=lambda g: g.name or str(g.n))
+def test_bucket_plan_in_bounds(g):
+    from paper_1910_13874_amd import ged
+    rng = np.random.default_rng(5)
+    rp, ci = internal_csr(g)
+    for U, cut_div in ((1, 1), (2, 1), (4, 1), (4, 2), (8, 4), (32, 1)):
+        check_plan_matches_emulation(ged, rp, ci, g.n, U, cut_div)
+    for C, pairs in ((1, False), (2, False), (4, False), (2, True), (4, True), (8, True)):
+        for cut_div in (1, 2, 4):
+            for br in (1, 7, 64, 4096, 1 << 20):
+                check_buckets(ged, rp, ci, g.n, C, pairs, cut_div, br, rng)
