@@ -193,6 +193,31 @@ int ged_set_batch_row_cut(ged_graph *g, int32_t cut_div);
 int32_t ged_batch_row_cut(const ged_graph *g);
 
 /*
+ * Width of the level-2 walk counts in ged_score_batch's tiles (undirected
+ * unweighted graphs; the second level of the hit chain of Section 3.1.1,
+ * pushed as exact integers).  On such a graph the level-2 count at v is at
+ * most omega_2(v), the number of length-2 walks ending at v, so it fits 16
+ * bits wherever omega_2(v) <= 2^16 - 2 (2^16 - 1 marks the rows below the
+ * cut in the gather's staging).  The library keeps vertices in
+ * decreasing-degree order; the rows below a cut `hub` (which must include
+ * every vertex with omega_2 > 2^16 - 2) keep 32-bit counts and all others
+ * are stored in 16 bits, halving the bytes the next level gathers per arc.
+ * hub = 0 (default): the least such cut, when it is at most n/8, for tiles
+ * of at least 4 columns whose plan stores its deeper levels as 32-bit counts
+ * (or has none); -1: never; hub > 0: that cut (GED_ERR_ARG if it is below
+ * the least cut or not below n).  The counts are exact integers either
+ * way.  When the plan stores a level above 2 (the 16-bit level feeds that
+ * exact level), scores are bit-identical for every setting; when the
+ * combining step gathers level 2 itself, its 16-bit form sums the rows in
+ * blocks of twice the arcs, so scores with and without it differ by the
+ * rounding of the column sums (~1e-16 relative), and are bit-identical among
+ * the 16-bit settings.  ged_count16_hub returns the cut the last
+ * ged_score_batch used, -1 for 32-bit counts.
+ */
+int ged_set_count16(ged_graph *g, int32_t hub);
+int32_t ged_count16_hub(const ged_graph *g);
+
+/*
  * Layout of the rows above the row-split threshold in every step (the
  * per-level pull of Section 3.1.1).  Their arcs can be grouped by source:
  * the vertex range is cut into buckets of `bytes` of gathered vector, each

@@ -53,8 +53,9 @@ static int64_t bucket_rows_for(ged_graph *g, int units, bool reverse) {
   return std::max<int64_t>(1, bytes / (8 * units));
 }
 
-static void build_for(ged_graph *g, Partition &p, int C, int units, bool reverse, int cut_div) {
-  const int64_t br = bucket_rows_for(g, units, reverse);
+static void build_for(ged_graph *g, Partition &p, int C, int units, bool reverse, int cut_div,
+                      bool buckets = true) {
+  const int64_t br = buckets ? bucket_rows_for(g, units, reverse) : 0;
   build_partition(p, reverse ? g->h_rp_r : g->h_rp, C, units, cut_div,
                   br > 0 ? (reverse ? g->h_ci_r : g->h_ci).data() : nullptr, br);
 }
@@ -88,6 +89,22 @@ Partition &partition_narrow(ged_graph *g, int C, int cut_div) {
   return ref;
 }
 
+Partition &partition_quad(ged_graph *g, int C, int cut_div) {
+  if (C < 4) throw HipError{GED_ERR_ARG, "16-bit gathers need at least 4 columns"};
+  check_cut(cut_div);
+  std::lock_guard<std::mutex> lk(g->parts_mu);
+  auto &m = g->parts;
+  const int key = -(1 << 16) - part_key(C, cut_div);
+  auto it = m.find(key);
+  if (it != m.end()) return *it->second;
+  auto p = std::make_unique<Partition>();
+  // the bucket fix-up sums at most 8 columns per row
+  build_for(g, *p, C, C / 4, false, cut_div, C <= 8);
+  Partition &ref = *p;
+  m[key] = std::move(p);
+  return ref;
+}
+
 const Partition *partition_if_built(ged_graph *g, int C) {
   std::lock_guard<std::mutex> lk(g->parts_mu);
   auto it = g->parts.find(part_key(C, 1));
@@ -111,6 +128,7 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
   else if (out == OUT_ZERO32 || out == OUT_GAIN32D)
     b += 12.0 * n * C;  // Y32 and Y
   else if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_COMBINE32L &&
+           out != OUT_COMBINE16 &&
            out != OUT_GAINCOMB && out != OUT_GAINCOMB32L && out != OUT_GAINCOMB32S)
     b += 8.0 * n * C;  // Y
   if (g->weighted) b += 8.0 * nnz;
@@ -118,6 +136,7 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case IN_VEC:
     case IN_CNT: b += 8.0 * n * C; break;
     case IN_CNT32: b += 4.0 * n * C; break;
+    case IN_CNT16: b += 2.0 * n * C; break;
     case IN_MASK:
     case IN_NOTMASK: b += n / 8.0; break;
     case IN_TILEMASK: b += 8.0 * n; break;
@@ -137,7 +156,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case OUT_GAIN32D: b += n / 8.0 + 4.0 * n; break;
     case OUT_COMBINE:
     case OUT_COMBINE32:
-    case OUT_COMBINE32L: b += 8.0 * n * 3; break;  // tmask, t_a, tr
+    case OUT_COMBINE32L:
+    case OUT_COMBINE16: b += 8.0 * n * 3; break;  // tmask, t_a, tr
     case OUT_GAINCOMB:
     case OUT_GAINCOMB32L:
     case OUT_GAINCOMB32S: b += n / 8.0 + 4.0 * n + 16.0 * n; break;  // S bits, candidates, m_a, M_r

@@ -175,6 +175,7 @@ static int autotune_split(ged_graph *g, BatchWs &b, const SplitPlan &pl0) {
   auto timed = [&](int C, int cut) -> double {
     SplitPlan pl = pl0;
     pl.cut_div = cut;
+    pl.c16_hub = split_c16_hub(g, pl, C, st);
     split_fit(g, b.sw, pl, C, 1, st);
     split_dense(g, b.sw, pl, C, b.tmask.as<const uint64_t>(), st);  // warm-up
     float ms = 1e30f;
@@ -258,6 +259,8 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
   }
   const int C = split ? autotune_split(g, b, pl) : autotune_tile(g, b);
   pl.cut_div = g->batch_cut_div;
+  if (split) pl.c16_hub = split_c16_hub(g, pl, C, st);
+  g->c16_used = pl.c16_hub;
   Partition &p = partition(g, C, false, g->batch_cut_div);
   b.ws.fit(p);
   // internal ids, duplicates inside a group dropped; column of every member
@@ -397,7 +400,8 @@ int score_batch(ged_graph *g, const int64_t *offsets, const int32_t *members, in
                                    (const void *)(intptr_t)split,
                                    (const void *)(intptr_t)g->prep.ell, (const void *)(intptr_t)G,
                                    (const void *)(intptr_t)C,
-                                   (const void *)(intptr_t)g->batch_cut_div};
+                                   (const void *)(intptr_t)g->batch_cut_div,
+                                   (const void *)(intptr_t)pl.c16_hub};
 
   if (g->prof.on) {
     // profiling times every step launch with events: run the batch eagerly
@@ -457,6 +461,20 @@ extern "C" int ged_set_batch_tile(ged_graph *g, int32_t tile) {
 }
 
 extern "C" int32_t ged_batch_row_cut(const ged_graph *g) { return g ? g->batch_cut_div : 0; }
+
+extern "C" int ged_set_count16(ged_graph *g, int32_t hub) {
+  if (!g) return fail(GED_ERR_ARG, "graph is null");
+  if (hub < -1 || hub >= g->n) return fail(GED_ERR_ARG, "hub must be -1, 0 or a cut below n");
+  std::lock_guard<std::recursive_mutex> lk(g->mu);
+  return guarded([&]() -> int {
+    if (hub > 0 && !g->weighted && split_ok(g) && hub < least_c16_hub(g, g->stream))
+      return fail(GED_ERR_ARG, "hub cut below the last vertex whose omega_2 exceeds 2^16 - 2");
+    g->count16 = hub;
+    return GED_OK;
+  });
+}
+
+extern "C" int32_t ged_count16_hub(const ged_graph *g) { return g ? g->c16_used : -1; }
 
 extern "C" int ged_set_batch_row_cut(ged_graph *g, int32_t cut_div) {
   if (!g) return fail(GED_ERR_ARG, "graph is null");

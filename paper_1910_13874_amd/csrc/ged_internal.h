@@ -226,7 +226,9 @@ enum InMode : int {
   IN_ONEHOT = 5,   // [cand_col[u] == c]    (gain chains, level 0)
   IN_FRESH = 6,    // fresh[c] ? bit c of tmask[u] : X[u*C+c]   (serving pool)
   IN_CNT = 7,      // Xc[u*C + c] (integer walk counts, exact in FP64 below 2^53)
-  IN_CNT32 = 8     // Xc32[u*C + c] (the same counts, 32-bit)
+  IN_CNT32 = 8,    // Xc32[u*C + c] (the same counts, 32-bit)
+  IN_CNT16 = 9     // level-2 counts in the 16-bit layout (below): u < hub ? Xc32[u*C + c]
+                   // : Xc16[u*C + c]; C >= 4, gathered as 4-column units
 };
 
 // Row epilogue of a step (what y(v) becomes).
@@ -251,12 +253,14 @@ enum OutMode : int {
   OUT_ZERO32 = 13,      // miss-chain count: y = v in S ? 0 : sum (exact integer), stored
                         // to Y32, and alpha * y to Y (alpha = alpha^i: the FP64 level)
   OUT_GAIN32D = 14,     // OUT_GAIN32 that also stores alpha * y to Y (the FP64 level)
-  OUT_GAINCOMB32S = 15  // OUT_GAINCOMB32L that also stores y's count to Y32: 0 on S, the
+  OUT_GAINCOMB32S = 15, // OUT_GAINCOMB32L that also stores y's count to Y32: 0 on S, the
                         // candidate's miss count (inj / alpha) at it, else the sum
+  OUT_COMBINE16 = 16    // OUT_COMBINE32L (32-bit stored levels, or none) whose level-2
+                        // counts q_cnt2 are in the 16-bit layout (hub table q_cnt2, Xc16)
 };
 // Profile records and kernel names encode a (gather, epilogue) pair as
 // in * kKindBase + out.
-constexpr int kKindBase = 16;
+constexpr int kKindBase = 32;
 
 struct StepArgs {
   const int *rp = nullptr;       // row_ptr int32 [n+1]
@@ -282,6 +286,9 @@ struct StepArgs {
   // IN_CNT / IN_CNT32 source
   const uint64_t *Xc = nullptr;    // [n*C]
   const uint32_t *Xc32 = nullptr;  // [n*C]
+  // IN_CNT16 / OUT_COMBINE16: rows v >= hub of the level-2 counts, 16-bit
+  const uint16_t *Xc16 = nullptr;  // [n*C]
+  int hub = 0;
   // OUT_COMBINE(32): per row v and column c the column sum takes
   //   q + y + y*tr[v] + [v not in S](inj[v] - y) * (q_even ? q + y : q),
   // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c]
@@ -333,6 +340,36 @@ void build_partition(Partition &p, const std::vector<int> &row_ptr, int C, int u
 // partition_narrow (blocks of kLdsDoubles / (C/2) arcs).
 __host__ __device__ constexpr bool narrow_gather(int C, int in_mode, bool weighted) {
   return in_mode == IN_CNT32 && C >= 2 && !weighted;
+}
+
+// 16-bit layout of the level-2 counts (split tiles of C >= 4 columns).  On an
+// unweighted graph count_2(v) <= omega_2(v), the number of length-2 walks
+// ending at v, and the partial sums the pushes build never exceed it.  With
+// the vertices in decreasing-degree order, those of omega_2 >= 2^16 - 1 sit
+// at the front; `hub` is a cut below which all of them lie.  Rows v < hub
+// keep 32-bit counts at v*C + c of the buffer; rows v >= hub hold 16-bit
+// counts, at most 2^16 - 2, at v*C + c of the packed array that starts at
+// c16_pk_offset bytes (its rows below the cut stay zero).  Two adjacent
+// columns share a 32-bit word, so the pushes add (value << 16*(c & 1)) to
+// that word: no carry crosses between the halves.  A 32-column row is 64
+// bytes instead of 128.  The gather (IN_CNT16) stages the packed values in
+// LDS, with the value 2^16 - 1 -- which no packed count takes -- standing for
+// rows below the cut, whose 32-bit counts the per-row sums fetch instead.
+constexpr uint32_t kC16Max = 0xfffe;    // largest count the packed rows hold
+constexpr uint32_t kC16Hub = 0xffff;    // staged in place of a hub row's value
+__host__ __device__ constexpr size_t c16_pk_offset(int hub, int C) {
+  return ((size_t)hub * C * 4 + 255) & ~(size_t)255;
+}
+inline size_t c16_bytes(int64_t n, int hub, int C) {
+  return c16_pk_offset(hub, C) + 2 * (size_t)n * C;
+}
+
+// 8-byte gather units per arc of a step: C values, C/2 column pairs of 32-bit
+// inputs, C/4 four-column units of 16-bit inputs.
+__host__ __device__ constexpr int gather_units(int C, int in_mode, bool weighted) {
+  return in_mode == IN_CNT16 && C >= 4 && !weighted ? C / 4
+                                                    : narrow_gather(C, in_mode, weighted) ? C / 2
+                                                                                           : C;
 }
 
 // Partial-sum buffers of one step stream (each path owns its own, so captured
@@ -402,6 +439,10 @@ struct SplitPlan {
   // counts instead of gathered
   bool push3 = false;
   int cut_div = 1;  // row-split threshold divisor of the dense steps' partitions
+  // level-2 counts in the 16-bit layout with this hub cut (c16_pk_offset),
+  // -1: plain 32-bit counts.  Batch tiles of C >= 4 columns only (c32, s = 2,
+  // no pushed level 3, stored levels 32-bit or none).
+  int c16_hub = -1;
 };
 
 struct SplitWs {
@@ -504,6 +545,11 @@ struct ged_graph {
   int32_t batch_cut_div = 0;
   // greedy candidate batch width (0 = the library's choice)
   int32_t greedy_width = 0;
+  // 16-bit level-2 counts in batch tiles: 0 the library's choice, -1 off,
+  // > 0 this hub cut (at least c16_least_hub)
+  int32_t count16 = 0;
+  int c16_least_hub = -1;       // 1 + the last vertex with omega_2 > kC16Max (-1: not known)
+  int c16_used = -1;            // hub cut of the last batch's tiles (-1: 32-bit counts)
   // registered with a server at (served_alpha, served_eps): other values,
   // invalidation and a change of tail bound are refused until it is destroyed
   bool served = false;
@@ -551,6 +597,9 @@ namespace ged {
 Partition &partition(ged_graph *g, int C, bool reverse = false, int cut_div = 1);
 // The partition of a narrow_gather step with C columns (forward rows).
 Partition &partition_narrow(ged_graph *g, int C, int cut_div = 1);
+// The partition of a 16-bit (IN_CNT16) step with C >= 4 columns: blocks of
+// kLdsDoubles / (C/4) arcs; source buckets only at C <= 8.
+Partition &partition_quad(ged_graph *g, int C, int cut_div = 1);
 // The forward C-column partition at cut_div 1 if it was built, else null
 // (builds nothing).
 const Partition *partition_if_built(ged_graph *g, int C);
@@ -608,6 +657,12 @@ void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st);
 int omega_fit_level(ged_graph *g, int L, hipStream_t st);
 // omega_2 as a host array (built on first use; synchronizes the stream then).
 const std::vector<double> &omega2_host(ged_graph *g, hipStream_t st);
+// Hub cut of the 16-bit level-2 layout for tiles of C columns under plan pl,
+// or -1 when the layout does not apply (the plan's shape, C < 4, the graph's
+// setting, or -- left to the library -- more than n/8 rows below the cut).
+int split_c16_hub(ged_graph *g, const SplitPlan &pl, int C, hipStream_t st);
+// 1 + the last vertex (internal order) with omega_2 > kC16Max: the least cut.
+int least_c16_hub(ged_graph *g, hipStream_t st);
 // Walk-count levels of the precomputation from the graph's exact integer
 // counts omega_i (unweighted graphs): omega_prefix_levels gives how many
 // levels those counts are held for (0 for weighted graphs);

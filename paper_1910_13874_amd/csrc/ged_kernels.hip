@@ -55,9 +55,30 @@ __device__ __forceinline__ double load_in(const StepArgs &a, int u, int c) {
     return a.fresh[c] ? (((a.tmask[u] >> c) & 1ull) ? 1.0 : 0.0) : a.X[(size_t)u * C + c];
   } else if constexpr (IN == IN_CNT) {
     return (double)a.Xc[(size_t)u * C + c];
+  } else if constexpr (IN == IN_CNT16) {
+    return u < a.hub ? (double)a.Xc32[(size_t)u * C + c] : (double)a.Xc16[(size_t)u * C + c];
   } else {  // IN_CNT32
     return (double)a.Xc32[(size_t)u * C + c];
   }
+}
+
+// Columns 4k .. 4k+3 of row u of 16-bit level-2 counts (IN_CNT16), as 32-bit
+// values: the packed row's 8 bytes, or -- rows below the hub cut -- 16 bytes
+// of the 32-bit table (long-row segments, which sum in registers).
+template <int C>
+__device__ __forceinline__ uint4 load_quad16(const StepArgs &a, int u, int k) {
+  const uint2 p = *reinterpret_cast<const uint2 *>(a.Xc16 + (size_t)u * C + 4 * k);
+  uint4 r = make_uint4(p.x & 0xffffu, p.x >> 16, p.y & 0xffffu, p.y >> 16);
+  if (u < a.hub) r = *reinterpret_cast<const uint4 *>(a.Xc32 + (size_t)u * C + 4 * k);
+  return r;
+}
+
+// The packed 8 bytes of columns 4k .. 4k+3 of row u as staged in LDS: the
+// row's four 16-bit counts, or kC16Hub in each for a row below the hub cut.
+template <int C>
+__device__ __forceinline__ uint2 load_pk16(const StepArgs &a, int u, int k) {
+  const uint2 p = *reinterpret_cast<const uint2 *>(a.Xc16 + (size_t)u * C + 4 * k);
+  return u < a.hub ? make_uint2(0xffffffffu, 0xffffffffu) : p;
 }
 
 // Row epilogue given the row's membership bit (S), column bits (tile/pool
@@ -75,7 +96,7 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
   } else if constexpr (OUT == OUT_ZERO32) {
     return inS ? 0.0 : sum;  // the count; the caller also stores alpha * it
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
-                       OUT == OUT_TILE32 || OUT == OUT_COMBINE32L) {
+                       OUT == OUT_TILE32 || OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB) {
     if (c >= a.spec_from) return (inS || cand == c - a.spec_from) ? 0.0 : y;  // miss column
@@ -108,7 +129,9 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
 // they can be issued early and consumed later.  C32: the count levels are
 // 32-bit.  LV32: the stored levels are unscaled 32-bit counts too, level l
 // weighted by q_slv * q_alpha^l; otherwise they hold h_i itself (weight 1).
-template <int C, bool C32, bool LV32>
+// C16: the level-2 counts are in the 16-bit layout (q_cnt2 is the hub table,
+// Xc16 the packed rows); both loads are issued, the one not needed at index 0.
+template <int C, bool C32, bool LV32, bool C16 = false>
 struct CombineIn {
   using CT = typename std::conditional<C32, uint32_t, uint64_t>::type;
   using LT = typename std::conditional<LV32, uint32_t, double>::type;
@@ -120,7 +143,14 @@ struct CombineIn {
   __device__ __forceinline__ void load(const StepArgs &a, int v, int c) {
     const uint64_t o = (uint64_t)v * C + c;
     c1 = ld(static_cast<const CT *>(a.q_cnt1) + (o & a.q_m1));
-    c2 = ld(static_cast<const CT *>(a.q_cnt2) + (o & a.q_m2));
+    if constexpr (C16) {
+      const bool hb = v < a.hub;
+      const CT h = ld(static_cast<const CT *>(a.q_cnt2) + (hb ? o : 0));
+      const uint16_t pk = ld(a.Xc16 + (hb ? 0 : o));
+      c2 = hb ? h : (CT)pk;
+    } else {
+      c2 = ld(static_cast<const CT *>(a.q_cnt2) + (o & a.q_m2));
+    }
     lv0 = ld(static_cast<const LT *>(a.q_lv) + (o & a.q_mlv));
     trv = a.tr[v];
     ta = a.inj[v];
@@ -172,9 +202,10 @@ struct CombineIn {
 };
 
 template <int C, int OUT>
-using CombineFor = CombineIn<C, OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L,
+using CombineFor = CombineIn<C, OUT == OUT_COMBINE32 || OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16,
                              OUT == OUT_COMBINE32L || OUT == OUT_GAINCOMB32L ||
-                                 OUT == OUT_GAINCOMB32S>;
+                                 OUT == OUT_GAINCOMB32S || OUT == OUT_COMBINE16,
+                             OUT == OUT_COMBINE16>;
 
 // Output modes by property.
 template <int OUT>
@@ -187,11 +218,13 @@ struct OutTraits {
   // the combination's level count is stored as well (gain levels by counts)
   static constexpr bool cstore = OUT == OUT_GAINCOMB32S;
   static constexpr bool combine = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
-                                  OUT == OUT_COMBINE32L || gaincomb;  // y not stored
+                                  OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16 ||
+                                  gaincomb;  // y not stored
   static constexpr bool store32 = OUT == OUT_TILE32 || OUT == OUT_GAIN32;
   static constexpr bool tile = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
                                OUT == OUT_COMBINE32 || OUT == OUT_TILE32 ||
-                               OUT == OUT_COMBINE32L;  // per-vertex column bits (tmask)
+                               OUT == OUT_COMBINE32L ||
+                               OUT == OUT_COMBINE16;  // per-vertex column bits (tmask)
 };
 
 // The count behind a gain combination's level value y (OUT_GAINCOMB32S): 0 on
@@ -261,6 +294,53 @@ __device__ __forceinline__ void block_colsum_pairs(double v0, double v1, double 
   if (t < C) out[t] = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
 }
 
+// Per-row sum of staged integer counts (32-bit pairs or 16-bit units) over
+// arcs j0 + s, j0 + s + tpr, .. < j1 of column c: four independent 64-bit
+// partials keep four LDS reads in flight, and integer sums are exact in any
+// order, so the result is the exact count (converted once; exact below 2^53).
+// Q4: a staged kC16Hub stands for a row below the hub cut, fetched from the
+// 32-bit table at the arc's source src[j].
+template <int C, bool Q4, class SV>
+__device__ __forceinline__ double sum_staged_counts(const StepArgs &a, const SV *vals, int j0,
+                                                   int j1, int s, int tpr, int c,
+                                                   const int *src) {
+  uint64_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+  auto val = [&](int j) -> uint32_t {
+    uint32_t x = vals[j * C + c];
+    if constexpr (Q4)
+      if (x == kC16Hub) x = a.Xc32[(size_t)src[j] * C + c];
+    return x;
+  };
+  int j = j0 + s;
+  for (; j + 3 * tpr < j1; j += 4 * tpr) {
+    const uint32_t x0 = val(j), x1 = val(j + tpr), x2 = val(j + 2 * tpr), x3 = val(j + 3 * tpr);
+    q0 += x0;
+    q1 += x1;
+    q2 += x2;
+    q3 += x3;
+  }
+  for (; j < j1; j += tpr) q0 += val(j);
+  return (double)((q0 + q1) + (q2 + q3));
+}
+
+// The same for lanes holding four columns (4k .. 4k+3), k = t % (C/4).
+template <int C>
+__device__ __forceinline__ void block_colsum_quads(const double (&v)[4], double *red, double *out) {
+  constexpr int CQ = C / 4;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double x[4] = {v[0], v[1], v[2], v[3]};
+  for (int o = CQ; o < 64; o <<= 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] += __shfl_xor(x[j], o, 64);
+  }
+  if (lane < CQ) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[w * C + 4 * lane + j] = x[j];
+  }
+  __syncthreads();
+  if (t < C) out[t] = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
+}
+
 template <int C, int IN, int OUT, bool WGT>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
@@ -272,13 +352,18 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
   // NP: 32-bit input gathered as column pairs; a gather unit is 8 bytes
   // either way (one FP64 value or two 32-bit values), CU units per arc
   constexpr bool NP = narrow_gather(C, IN, WGT);
+  // Q4: 16-bit inputs (IN_CNT16) gathered as 8-byte units of four columns
+  // and staged as 16-bit values (partition_quad: kLdsDoubles / (C/4) arcs)
+  constexpr bool Q4 = IN == IN_CNT16 && C >= 4 && !WGT;
   constexpr int CU = NP ? C / 2 : C;
   constexpr int LV = lds_values(C);          // gather units staged per block
   constexpr int PT = LV / kBlock;            // gather units per thread
+  constexpr int GU = Q4 ? C / 4 : CU;        // gather units per arc
   constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
-  using SV = typename std::conditional<NP, uint32_t, double>::type;
+  using SV = typename std::conditional<Q4, uint16_t,
+                                       typename std::conditional<NP, uint32_t, double>::type>::type;
   // vals has one spare unit per thread so every phase-1 store is unconditional
-  __shared__ SV vals[(NP ? 2 : 1) * (LV + kBlock)];
+  __shared__ alignas(16) SV vals[(Q4 ? 4 : NP ? 2 : 1) * (LV + kBlock)];
   __shared__ int rps[kRowsPerBlock + 1];
   __shared__ double red[(kBlock / 64) * C];
   __shared__ uint32_t mw[M1 ? kRowsPerBlock / 32 + 2 : 1];
@@ -291,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     // descriptor: rows [r0, r0 + nrows), arcs [p0, p1)
     const int4 d = blocks[b];
     const int r0 = d.x, nrows = d.y - d.x, p0 = d.z;
-    const int tot = (d.w - d.z) * CU;  // gather units of the block
+    const int tot = (d.w - d.z) * GU;  // gather units of the block
     if (t < (kBlock / 64) * C) red[t] = 0.0;
     // Phase 1.  Load order matters: the col_idx stream first, then the row
     // pointers and epilogue masks of the block, then the gathers (which wait
@@ -304,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     int u[PT];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-      u[q] = __builtin_nontemporal_load(a.ci + min(jlo + (t + q * kBlock) / CU, jmax));
+      u[q] = __builtin_nontemporal_load(a.ci + min(jlo + (t + q * kBlock) / GU, jmax));
       if (tot == 0) u[q] = 0;
     }
     int rv[RT];
@@ -328,11 +413,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     const int rl0 = (t / tpr) / C;
     CombineFor<C, OUT> pf;
     if constexpr (CB) pf.load(a, r0 + min(rl0, nrows - 1), (t / tpr) & (C - 1));
-    double v[NP ? 1 : PT];
-    uint2 v2[NP ? PT : 1];
+    double v[NP || Q4 ? 1 : PT];
+    uint2 v2[NP || Q4 ? PT : 1];
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
-      if constexpr (NP) {
+      if constexpr (Q4) {
+        v2[q] = load_pk16<C>(a, u[q], (t + q * kBlock) & (GU - 1));
+      } else if constexpr (NP) {
         v2[q] = *reinterpret_cast<const uint2 *>(a.Xc32 + (size_t)u[q] * C +
                                                  2 * ((t + q * kBlock) & (CU - 1)));
       } else {
@@ -354,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int f = t + q * kBlock;
-      if constexpr (NP)
+      if constexpr (NP || Q4)
         reinterpret_cast<uint2 *>(vals)[f < tot ? f : LV + t] = v2[q];
       else
         vals[f < tot ? f : LV + t] = v[q];
@@ -369,7 +456,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     for (int rl = pair / C; rl < nrows; rl += rstep) {
       const int j0 = rps[rl], j1 = rps[rl + 1];
       double acc = 0.0;
-      for (int j = j0 + s; j < j1; j += tpr) acc += (double)vals[j * C + c];
+      if constexpr (NP || Q4)
+        acc = sum_staged_counts<C, Q4>(a, vals, j0, j1, s, tpr, c, a.ci + p0);
+      else
+        for (int j = j0 + s; j < j1; j += tpr) acc += (double)vals[j * C + c];
       for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
       if (s == 0) {
         const int r = r0 + rl;
@@ -430,20 +520,22 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     if constexpr (!WGT) {
       const int4 d = segs[b - n_blocks];
       const int s0 = d.x, np = d.y - d.x, p0 = d.z;
-      const int tot = (d.w - d.z) * CU;  // >= CU: every piece has an arc
+      const int tot = (d.w - d.z) * GU;  // >= GU: every piece has an arc
       const int jmax = d.w - 1;
       int u[PT];
 #pragma unroll
       for (int q = 0; q < PT; ++q)
-        u[q] = __builtin_nontemporal_load(a.bk_ci + min(p0 + (t + q * kBlock) / CU, jmax));
+        u[q] = __builtin_nontemporal_load(a.bk_ci + min(p0 + (t + q * kBlock) / GU, jmax));
       int rv[RT];
 #pragma unroll
       for (int k = 0; k < RT; ++k) rv[k] = a.bk_ptr[s0 + min(t + k * kBlock, np)];
-      double v[NP ? 1 : PT];
-      uint2 v2[NP ? PT : 1];
+      double v[NP || Q4 ? 1 : PT];
+      uint2 v2[NP || Q4 ? PT : 1];
 #pragma unroll
       for (int q = 0; q < PT; ++q) {
-        if constexpr (NP)
+        if constexpr (Q4)
+          v2[q] = load_pk16<C>(a, u[q], (t + q * kBlock) & (GU - 1));
+        else if constexpr (NP)
           v2[q] = *reinterpret_cast<const uint2 *>(a.Xc32 + (size_t)u[q] * C +
                                                    2 * ((t + q * kBlock) & (CU - 1)));
         else
@@ -455,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
       for (int q = 0; q < PT; ++q) {
         const int f = t + q * kBlock;
-        if constexpr (NP)
+        if constexpr (NP || Q4)
           reinterpret_cast<uint2 *>(vals)[f < tot ? f : LV + t] = v2[q];
         else
           vals[f < tot ? f : LV + t] = v[q];
@@ -470,11 +562,40 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
       for (int rl = pair / C; rl < np; rl += rstep) {
         const int j0 = rps[rl], j1 = rps[rl + 1];
         double acc = 0.0;
-        for (int j = j0 + s; j < j1; j += tpr) acc += (double)vals[j * C + c];
+        if constexpr (NP || Q4)
+          acc = sum_staged_counts<C, Q4>(a, vals, j0, j1, s, tpr, c, a.bk_ci + p0);
+        else
+          for (int j = j0 + s; j < j1; j += tpr) acc += (double)vals[j * C + c];
         for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (s == 0) a.seg_out[(size_t)(s0 + rl) * C + c] = acc;
       }
     }
+  } else if constexpr (Q4) {
+    // One segment of a long row, four columns per lane: kBlock / GU lanes per
+    // 4-column unit.
+    const int4 sd = segs[b - n_blocks];
+    const int k = t & (GU - 1);
+    const int s = t / GU;
+    constexpr int LPU = kBlock / GU;
+    constexpr int U = 8;  // arcs in flight per lane
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j0 = sd.y + s; j0 < sd.z; j0 += U * LPU) {
+      int u[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) u[q] = __builtin_nontemporal_load(a.ci + min(j0 + q * LPU, sd.z - 1));
+      uint4 v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) v[q] = load_quad16<C>(a, u[q], k);
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const bool ok = j0 + q * LPU < sd.z;
+        acc[0] += ok ? (double)v[q].x : 0.0;
+        acc[1] += ok ? (double)v[q].y : 0.0;
+        acc[2] += ok ? (double)v[q].z : 0.0;
+        acc[3] += ok ? (double)v[q].w : 0.0;
+      }
+    }
+    block_colsum_quads<C>(acc, red, a.seg_out + (size_t)(b - n_blocks) * C);
   } else if constexpr (NP) {
     // One segment of a long row, column pairs: kBlock / CU lanes per pair.
     const int4 sd = segs[b - n_blocks];
@@ -707,6 +828,11 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_VEC, OUT_COMBINE32)
     GED_CASE(IN_CNT32, OUT_TILE32)
     GED_CASE(IN_CNT32, OUT_COMBINE32L)
+    if constexpr (C >= 4) {  // 16-bit level-2 counts of batch tiles
+      GED_CASE(IN_CNT16, OUT_TILE32)
+      GED_CASE(IN_CNT16, OUT_COMBINE16)
+      GED_CASE(IN_CNT32, OUT_COMBINE16)
+    }
   }
   if constexpr (C == 2 || C == 4 || C == 8 || C == 16) {  // the greedy's candidate batches
     GED_CASE(IN_ONEHOT, OUT_GAINCOMB)
@@ -754,7 +880,10 @@ static bool dispatch_c(int C, int in, int out, const Partition &p, const StepArg
 void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
                  hipStream_t st, hipEvent_t after_main) {
   if (a.C != p.C) throw HipError{GED_ERR_ARG, "step column count does not match partition"};
-  const int units = narrow_gather(a.C, in_mode, a.w != nullptr) ? a.C / 2 : a.C;
+  if ((in_mode == IN_CNT16 || out_mode == OUT_COMBINE16) &&
+      (a.C < 4 || a.w || !a.Xc16 || a.hub < 0 || a.hub >= a.n))
+    throw HipError{GED_ERR_ARG, "16-bit counts need C >= 4, an unweighted graph and a cut below n"};
+  const int units = gather_units(a.C, in_mode, a.w != nullptr);
   if (p.units != units)
     throw HipError{GED_ERR_ARG, "step gather width does not match partition"};
   const bool ok = a.w ? dispatch_c<true>(a.C, in_mode, out_mode, p, a, st, after_main)

@@ -79,6 +79,67 @@ size_t split_wl_need(const ged_graph *g, int64_t deg_sum) {
 
 // --------------------------------------------------------------- kernels --
 
+// The level-2 count array in either layout: plain CT[n*C] (h16 < 0), or the
+// 16-bit layout with hub cut h16 (32-bit counts only; c16_pk_offset).  In the
+// packed part a column's count is one half of a 32-bit word, so it is added
+// to, read from and set through that word.
+template <class CT>
+__device__ __forceinline__ void c16_word(CT *p, int h16, int C, int v, int c, uint32_t *&w,
+                                         int &sh) {
+  uint16_t *pk = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(p) + c16_pk_offset(h16, C));
+  const size_t o = (size_t)v * C + c;  // C is even: o is odd iff c is
+  w = reinterpret_cast<uint32_t *>(pk + (o & ~(size_t)1));
+  sh = (int)(o & 1) << 4;
+}
+
+// Add val at (v, c); returns the count before the add.
+template <class CT>
+__device__ __forceinline__ CT cnt2_add(CT *p, int h16, int C, int v, int c, CT val) {
+  if constexpr (sizeof(CT) == 4) {
+    if (h16 >= 0 && v >= h16) {
+      uint32_t *w;
+      int sh;
+      c16_word(p, h16, C, v, c, w, sh);
+      return (CT)((atomicAdd(w, (uint32_t)val << sh) >> sh) & 0xffffu);
+    }
+  }
+  return atomicAdd(&p[(size_t)v * C + c], val);
+}
+
+// Store 0 at (v, c) (a 16-bit store in the packed part: the other half of
+// its word is left as it is).
+template <class CT>
+__device__ __forceinline__ void cnt2_zero(CT *p, int h16, int C, int v, int c) {
+  if constexpr (sizeof(CT) == 4) {
+    if (h16 >= 0 && v >= h16) {
+      uint16_t *pk =
+          reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(p) + c16_pk_offset(h16, C));
+      pk[(size_t)v * C + c] = 0;
+      return;
+    }
+  }
+  p[(size_t)v * C + c] = 0;
+}
+
+// Set (v, c) to val >= its current count while other threads may add to the
+// other half of its word (member rows are fixed inside the level-2 push,
+// whose adds skip the row's own column): read the half, add the difference.
+template <class CT>
+__device__ __forceinline__ void cnt2_raise(CT *p, int h16, int C, int v, int c, CT val) {
+  if constexpr (sizeof(CT) == 4) {
+    if (h16 >= 0 && v >= h16) {
+      uint32_t *w;
+      int sh;
+      c16_word(p, h16, C, v, c, w, sh);
+      const uint32_t cur =
+          (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> sh) & 0xffffu;
+      atomicAdd(w, ((uint32_t)val - cur) << sh);
+      return;
+    }
+  }
+  p[(size_t)v * C + c] = val;
+}
+
 // Members of groups g0 .. g0+nc-1, one block per member: level-1 counts, the
 // level-2 contributions of paths through the member, and worklist entries for
 // the non-members they reach first.  With wl3 (single group, pushed level 3)
@@ -93,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
                                                  const int *mcol, int g0, int nc, int C, CT *cnt1,
                                                  CT *cnt2, uint64_t *wl, unsigned *wl_n,
                                                  unsigned wl_cap, uint64_t *wl3, unsigned *wl3_n,
-                                                 unsigned wl3_cap) {
+                                                 unsigned wl3_cap, int h16) {
   const int64_t jb = offsets[g0], je = offsets[g0 + nc];
   for (int64_t j = jb + blockIdx.x; j < je; j += gridDim.x) {
     const int s = members[j];
@@ -115,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_push(const int *__restrict__ rp,
         const size_t o = (size_t)y * C + c;
         const CT old = atomicAdd(&cnt1[o], (CT)1);
         if (cnt2) {
-          const CT old2 = atomicAdd(&cnt2[o], ds);
+          const CT old2 = cnt2_add(cnt2, h16, C, y, c, ds);
           if (!((tmask[y] >> c) & 1ull)) {
             const unsigned ch = wl_chunks(rp, y);
             if (old == 0) nch = ch;
@@ -141,6 +202,7 @@ struct MemberFix {
   int g0 = 0, nc = 0, C = 1;
   CT *cnt1 = nullptr, *cnt2 = nullptr, *lv3 = nullptr;
   const double *om3 = nullptr;
+  int h16 = -1;  // cnt2 layout
 };
 
 // All threads of the launch, grid-stride over the members.
@@ -153,7 +215,7 @@ __device__ __forceinline__ void fix_members(const MemberFix<CT> &f) {
     const int s = f.members[j];
     const size_t o = (size_t)s * f.C + (f.mcol[j] - f.g0);
     f.cnt1[o] = (CT)(f.rp[s + 1] - f.rp[s]);
-    if (f.cnt2) f.cnt2[o] = (CT)f.omega2[s];
+    if (f.cnt2) cnt2_raise(f.cnt2, f.h16, f.C, s, f.mcol[j] - f.g0, (CT)f.omega2[s]);
     if (f.lv3) f.lv3[o] = (CT)f.om3[s];
   }
 }
@@ -163,7 +225,7 @@ __device__ __forceinline__ void fix_members(const MemberFix<CT> &f) {
 template <class CT>
 __device__ __forceinline__ void clear_entry(const int *__restrict__ rp,
                                             const int *__restrict__ ci, int C, CT *dst,
-                                            uint64_t e) {
+                                            uint64_t e, int h16 = -1) {
   constexpr int U = kWlChunk / 64;
   const int lane = threadIdx.x & 63;
   const int y = (int)(e >> 32);
@@ -175,7 +237,7 @@ __device__ __forceinline__ void clear_entry(const int *__restrict__ rp,
   for (int k = 0; k < U; ++k) x[k] = j0 + 64 * k < j1 ? ci[j0 + 64 * k] : -1;
 #pragma unroll
   for (int k = 0; k < U; ++k)
-    if (x[k] >= 0) dst[(size_t)x[k] * C + c] = 0;
+    if (x[k] >= 0) cnt2_zero(dst, h16, C, x[k], c);
 }
 
 // Worklist entries, one wavefront each: src(y) (the next lower level's
@@ -194,7 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
                                                     const unsigned *wl_n, unsigned wl_cap,
                                                     const uint64_t *__restrict__ tmask,
                                                     uint64_t *wl_next, unsigned *wl_next_n,
-                                                    unsigned wl_next_cap, MemberFix<CT> fx) {
+                                                    unsigned wl_next_cap, MemberFix<CT> fx,
+                                                    int h16) {
   fix_members(fx);
   const unsigned count = min(*wl_n, wl_cap);  // capacities are sized to never overflow
   // A chunk is at most U arcs per lane: every col_idx load of the chunk is
@@ -209,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
     const int c = (int)((e >> 24) & 0xffu);
     const int q = (int)(e & 0xffffffu);
     if (CLEAR) {
-      clear_entry(rp, ci, C, dst, e);
+      clear_entry(rp, ci, C, dst, e, h16);
       continue;
     }
     const int j0 = rp[y] + q * kWlChunk + lane, j1 = min(rp[y] + (q + 1) * kWlChunk, rp[y + 1]);
@@ -223,13 +286,13 @@ __global__ __launch_bounds__(kBlock) void k_push_wl(const int *__restrict__ rp,
     if (!NEXT) {
 #pragma unroll
       for (int k = 0; k < U; ++k)
-        if (out[k]) atomicAdd(&dst[(size_t)x[k] * C + c], v);
+        if (out[k]) cnt2_add(dst, h16, C, x[k], c, v);
       continue;
     }
     bool first[U];
 #pragma unroll
     for (int k = 0; k < U; ++k)
-      first[k] = out[k] && atomicAdd(&dst[(size_t)x[k] * C + c], v) == 0;
+      first[k] = out[k] && cnt2_add(dst, h16, C, x[k], c, v) == 0;
     unsigned nch[U], tot = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
@@ -285,7 +348,8 @@ __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict_
                                                           int g0, int nc, int C, CT *cnt1,
                                                           CT *cnt2, CT *lv3,
                                                           unsigned long long *tmask,
-                                                          unsigned *wl_n, unsigned *wl3_n) {
+                                                          unsigned *wl_n, unsigned *wl3_n,
+                                                          int h16) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (wl_n) *wl_n = 0;
     if (wl3_n) *wl3_n = 0;
@@ -296,14 +360,14 @@ __global__ __launch_bounds__(kBlock) void k_clear_members(const int *__restrict_
     const int c = mcol[j] - g0;
     if (threadIdx.x == 0) {
       cnt1[(size_t)s * C + c] = 0;
-      if (cnt2) cnt2[(size_t)s * C + c] = 0;
+      if (cnt2) cnt2_zero(cnt2, h16, C, s, c);
       if (lv3) lv3[(size_t)s * C + c] = 0;
       atomicAnd(&tmask[s], ~(1ull << c));
     }
     for (int k = rp[s] + (int)threadIdx.x; k < rp[s + 1]; k += kBlock) {
-      const size_t o = (size_t)ci[k] * C + c;
-      cnt1[o] = 0;
-      if (cnt2) cnt2[o] = 0;
+      const int y = ci[k];
+      cnt1[(size_t)y * C + c] = 0;
+      if (cnt2) cnt2_zero(cnt2, h16, C, y, c);
     }
   }
 }
@@ -610,6 +674,7 @@ void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st) {
 // Gather of the last (combining) dense level of a tile.
 static int final_in(const SplitPlan &pl) {
   if (pl.lv32) return IN_CNT32;
+  if (pl.c16_hub >= 0 && pl.a == pl.s + 1) return IN_CNT16;
   if (pl.a == 1) return IN_TILEMASK;
   if (pl.a == pl.s + 1) return pl.c32 ? IN_CNT32 : IN_CNT;
   return IN_VEC;
@@ -617,6 +682,7 @@ static int final_in(const SplitPlan &pl) {
 
 // Partition of a step gathering `in` at C columns (row-split threshold of pl).
 static Partition &step_partition(ged_graph *g, const SplitPlan &pl, int C, int in) {
+  if (in == IN_CNT16) return partition_quad(g, C, pl.cut_div);
   return narrow_gather(C, in, g->weighted) ? partition_narrow(g, C, pl.cut_div)
                                            : partition(g, C, false, pl.cut_div);
 }
@@ -649,6 +715,24 @@ const std::vector<double> &omega2_host(ged_graph *g, hipStream_t st) {
   for (size_t v = 0; v < n; ++v) h[v] = (double)om2[v];
   g->h_omega2.swap(h);
   return g->h_omega2;
+}
+
+int least_c16_hub(ged_graph *g, hipStream_t st) {
+  if (g->c16_least_hub >= 0) return g->c16_least_hub;
+  const std::vector<double> &om2 = omega2_host(g, st);
+  int64_t last = -1;
+  for (int64_t v = 0; v < g->n; ++v)
+    if (om2[(size_t)v] > (double)kC16Max) last = v;
+  g->c16_least_hub = (int)(last + 1);
+  return g->c16_least_hub;
+}
+
+int split_c16_hub(ged_graph *g, const SplitPlan &pl, int C, hipStream_t st) {
+  if (g->count16 < 0 || g->weighted || !split_ok(g) || C < 4) return -1;
+  if (!pl.c32 || pl.s != 2 || pl.push3 || !(pl.lv32 || pl.nlv == 0)) return -1;
+  const int least = least_c16_hub(g, st);
+  if (g->count16 > 0) return g->count16;  // checked against least when set
+  return (int64_t)least * 8 <= g->n && least < g->n ? least : -1;
 }
 
 // Host table of deg(v) + omega_2(v) + omega_3(v), which bounds the degrees
@@ -734,12 +818,16 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
   if (!counts_only) {
     w.ws.fit(partition(g, C, false, pl.cut_div));
     if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, pl, C, IN_CNT32));
+    if (pl.c16_hub >= 0) w.ws.fit(step_partition(g, pl, C, IN_CNT16));
   }
   if (pl.s >= 1) {
     const size_t cb = (pl.c32 ? sizeof(uint32_t) : sizeof(uint64_t)) * nC;
-    if (w.cnt1.bytes < cb || w.cnt2.bytes < cb) {
+    // the 16-bit layout's packed part starts on a 256-byte boundary, which on
+    // a tiny graph can reach past 4nC bytes
+    const size_t cb2 = pl.c16_hub >= 0 ? std::max(cb, c16_bytes(g->n, pl.c16_hub, C)) : cb;
+    if (w.cnt1.bytes < cb || w.cnt2.bytes < cb2) {
       w.cnt1.ensure(cb);
-      w.cnt2.ensure(cb);
+      w.cnt2.ensure(cb2);
       w.zero = false;
     }
     if (!w.zero || w.cnt_bytes != cb) {
@@ -786,6 +874,7 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
 void split_fit_width(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C) {
   w.ws.fit(partition(g, C, false, pl.cut_div));
   if (pl.s >= 1 && pl.c32) w.ws.fit(step_partition(g, pl, C, IN_CNT32));
+  if (pl.c16_hub >= 0) w.ws.fit(step_partition(g, pl, C, IN_CNT16));
   w.ws.fit(step_partition(g, pl, C, final_in(pl)));
 }
 
@@ -800,9 +889,10 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
   CT *l3 = pl.push3 ? w.lv.as<CT>() : nullptr;
   uint64_t *wl3 = l3 ? w.wl3.as<uint64_t>() : nullptr;
   unsigned *wl3_n = l3 ? w.wl3_n.as<unsigned>() : nullptr;
+  const int h16 = sizeof(CT) == 4 ? pl.c16_hub : -1;
   hipLaunchKernelGGL(k_push<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, tmask, offs, mem,
                      mcol, g0, nc, C, c1, c2, w.wl.as<uint64_t>(), w.wl_n.as<unsigned>(),
-                     w.wl_cap, wl3, wl3_n, w.wl3_cap);
+                     w.wl_cap, wl3, wl3_n, w.wl3_cap, h16);
   GED_HIP(hipGetLastError());
   MemberFix<CT> fx;
   fx.rp = rp;
@@ -817,16 +907,17 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
   fx.cnt2 = c2;
   fx.lv3 = l3;
   fx.om3 = l3 ? g->omega_lv.as<const double>() : nullptr;  // omega_3 is level 0
+  fx.h16 = h16;
   if (c2) {  // level 2, with the member rows
     if (wl3)
       hipLaunchKernelGGL((k_push_wl<CT, false, true>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp,
                          ci, C, c1, c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(),
-                         w.wl_cap, tmask, wl3, wl3_n, w.wl3_cap, fx);
+                         w.wl_cap, tmask, wl3, wl3_n, w.wl3_cap, fx, h16);
     else
       hipLaunchKernelGGL((k_push_wl<CT, false, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st,
                          rp, ci, C, c1, c2, w.wl.as<const uint64_t>(),
                          w.wl_n.as<const unsigned>(), w.wl_cap, tmask, (uint64_t *)nullptr,
-                         (unsigned *)nullptr, 0u, fx);
+                         (unsigned *)nullptr, 0u, fx, h16);
   } else {
     hipLaunchKernelGGL(k_fix_members<CT>, dim3(grid_for((tile_members + kBlock - 1) / kBlock, 256)),
                        dim3(kBlock), 0, st, fx);
@@ -836,7 +927,7 @@ static void push_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, con
     hipLaunchKernelGGL((k_push_wl<CT, false, false>), dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C,
                        static_cast<const CT *>(c2), l3, w.wl3.as<const uint64_t>(),
                        w.wl3_n.as<const unsigned>(), w.wl3_cap, tmask, (uint64_t *)nullptr,
-                       (unsigned *)nullptr, 0u, MemberFix<CT>());
+                       (unsigned *)nullptr, 0u, MemberFix<CT>(), -1);
     GED_HIP(hipGetLastError());
   }
 }
@@ -849,6 +940,7 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
   CT *c1 = w.cnt1.as<CT>();
   CT *c2 = pl.s >= 2 ? w.cnt2.as<CT>() : nullptr;
   CT *l3 = pl.push3 ? w.lv.as<CT>() : nullptr;
+  const int h16 = sizeof(CT) == 4 ? pl.c16_hub : -1;
   if (l3) {  // level-2 and pushed level-3 targets in one launch
     hipLaunchKernelGGL(k_clear_two<CT>, dim3(kWl3Grid), dim3(kBlock), 0, st, rp, ci, C, c2,
                        w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap, l3,
@@ -857,12 +949,14 @@ static void clear_phase(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C,
   } else if (c2) {
     hipLaunchKernelGGL((k_push_wl<CT, true, false>), dim3(w.wl_blocks), dim3(kBlock), 0, st, rp, ci, C,
                        c1, c2, w.wl.as<const uint64_t>(), w.wl_n.as<const unsigned>(), w.wl_cap,
-                       tmask, (uint64_t *)nullptr, (unsigned *)nullptr, 0u, MemberFix<CT>());
+                       tmask, (uint64_t *)nullptr, (unsigned *)nullptr, 0u, MemberFix<CT>(),
+                       h16);
     GED_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_clear_members<CT>, dim3(mgrid), dim3(kBlock), 0, st, rp, ci, offs, mem,
                      mcol, g0, nc, C, c1, c2, l3, reinterpret_cast<unsigned long long *>(tmask),
-                     c2 ? w.wl_n.as<unsigned>() : nullptr, l3 ? w.wl3_n.as<unsigned>() : nullptr);
+                     c2 ? w.wl_n.as<unsigned>() : nullptr, l3 ? w.wl3_n.as<unsigned>() : nullptr,
+                     h16);
   GED_HIP(hipGetLastError());
 }
 
@@ -887,6 +981,14 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
   a.C = C;
   a.tmask = tmask;
   a.accum = 0;
+  // 16-bit level-2 counts: the level-3 gather reads them (IN_CNT16), and the
+  // combining step reads their rows (OUT_COMBINE16)
+  const bool c16 = pl.c16_hub >= 0;
+  if (c16) {
+    a.hub = pl.c16_hub;
+    a.Xc16 = reinterpret_cast<const uint16_t *>(static_cast<const char *>(c2) +
+                                                c16_pk_offset(pl.c16_hub, C));
+  }
   if (pl.lv32) {
     // unscaled 32-bit counts for levels s+1 .. a-1 (members: omega_i), then
     // h_a = alpha^a * (sum of level a-1 counts) in the combining step
@@ -895,15 +997,17 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
     for (int i = pl.s + 1; i < pl.a; ++i) alpha_a *= alpha;
     for (int i = pl.s + 1; i <= pl.a; ++i) {
       a.Xc32 = i == pl.s + 1 ? static_cast<const uint32_t *>(c2) : lv32 + (size_t)(i - 2 - pl.s) * nC;
+      const int in = c16 && i == pl.s + 1 ? IN_CNT16 : IN_CNT32;
+      Partition &pi = in == IN_CNT16 ? step_partition(g, pl, C, IN_CNT16) : pn;
       if (i < pl.a) {
         a.alpha = 1.0;
         a.inj = om + (size_t)(i - 3) * n;
         a.Y32 = lv32 + (size_t)(i - 1 - pl.s) * nC;
         if (pl.push3 && i == pl.s + 1) continue;  // pushed with the first levels
         if (profile)
-          run_step(g, pn, a, IN_CNT32, OUT_TILE32, st);
+          run_step(g, pi, a, in, OUT_TILE32, st);
         else
-          launch_step(pn, a, IN_CNT32, OUT_TILE32, st);
+          launch_step(pi, a, in, OUT_TILE32, st);
       } else {
         a.alpha = alpha_a;
         a.inj = T + (size_t)i * n;
@@ -922,10 +1026,11 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
         a.q_alpha = alpha;
         a.q_nlv = pl.nlv;
         a.q_even = pl.even ? 1 : 0;
+        const int out = c16 ? OUT_COMBINE16 : OUT_COMBINE32L;
         if (profile)
-          run_step(g, pn, a, IN_CNT32, OUT_COMBINE32L, st, 0.5 * (pl.s + pl.nlv));
+          run_step(g, pi, a, in, out, st, c16 ? 0.75 + 0.5 * pl.nlv : 0.5 * (pl.s + pl.nlv));
         else
-          launch_step(pn, a, IN_CNT32, OUT_COMBINE32L, st);
+          launch_step(pi, a, in, out, st);
       }
     }
     return;
@@ -937,7 +1042,10 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
       a.alpha = alpha;
     } else if (i == pl.s + 1) {
       const void *src = pl.s == 1 ? c1 : c2;
-      if (pl.c32) {
+      if (c16) {  // a = 3: the combining step gathers the 16-bit level 2
+        in = IN_CNT16;
+        a.Xc32 = static_cast<const uint32_t *>(src);
+      } else if (pl.c32) {
         in = IN_CNT32;
         a.Xc32 = static_cast<const uint32_t *>(src);
       } else {
@@ -951,7 +1059,7 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
       a.alpha = alpha;
     }
     a.inj = T + (size_t)i * n;
-    Partition &ps = in == IN_CNT32 ? pn : p;
+    Partition &ps = in == IN_CNT16 ? step_partition(g, pl, C, IN_CNT16) : in == IN_CNT32 ? pn : p;
     if (i < pl.a) {
       a.Y = lv + (size_t)(i - 1 - pl.s) * nC;
       if (profile)
@@ -974,9 +1082,9 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
       a.q_slv = pl.nlv > 0 ? 1.0 : 0.0;
       a.q_nlv = pl.nlv;
       a.q_even = pl.even ? 1 : 0;
-      const int out = (pl.c32 && pl.s >= 1) ? OUT_COMBINE32 : OUT_COMBINE;
+      const int out = c16 ? OUT_COMBINE16 : (pl.c32 && pl.s >= 1) ? OUT_COMBINE32 : OUT_COMBINE;
       if (profile)
-        run_step(g, ps, a, in, out, st, pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
+        run_step(g, ps, a, in, out, st, c16 ? 0.75 : pl.s * (pl.c32 ? 0.5 : 1.0) + pl.nlv);
       else
         launch_step(ps, a, in, out, st);
     }
@@ -1003,7 +1111,8 @@ void split_tile_push(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const
 bool split_clear_by_fill(const ged_graph *g, const SplitPlan &pl, int C, double push2_arcs) {
   if (pl.s < 2 || pl.push3) return false;
   const double cb = pl.c32 ? 4.0 : 8.0;
-  return push2_arcs * 64.0 > 2.0 * (double)g->n * C * cb;
+  const double cb2 = pl.c16_hub >= 0 ? 2.0 : cb;  // level 2 in the 16-bit layout
+  return push2_arcs * 64.0 > (double)g->n * C * (cb + cb2);
 }
 
 void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const int64_t *offs,
@@ -1015,7 +1124,8 @@ void split_tile_clear(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, cons
     // worklist length: everything the pushes wrote
     const size_t words = (size_t)g->n * C * (pl.c32 ? 1 : 2);
     launch_fill_i32(w.cnt1.as<int>(), 0, words, st);
-    launch_fill_i32(w.cnt2.as<int>(), 0, words, st);
+    launch_fill_i32(w.cnt2.as<int>(), 0,
+                    pl.c16_hub >= 0 ? (c16_bytes(g->n, pl.c16_hub, C) + 3) / 4 : words, st);
     launch_fill_i32(w.wl_n.as<int>(), 0, 1, st);
     launch_tmask_set(tmask, offs, mem, g0, nc, 0, st);
   } else if (pl.s >= 1) {  // clears the members' tmask bits too

@@ -102,6 +102,8 @@ _sig("ged_partition_plan", ctypes.c_int,
 _sig("ged_set_batch_row_cut", ctypes.c_int, [c_graph_p, ctypes.c_int32])
 _sig("ged_batch_row_cut", ctypes.c_int32, [c_graph_p])
 _sig("ged_set_greedy_width", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_set_count16", ctypes.c_int, [c_graph_p, ctypes.c_int32])
+_sig("ged_count16_hub", ctypes.c_int32, [c_graph_p])
 _sig("ged_greedy_width", ctypes.c_int32, [c_graph_p])
 _sig("ged_greedy_footprint", ctypes.c_int, [c_graph_p, ctypes.c_int32, ctypes.c_double,
                                             ctypes.c_double, P_I64, P_I64])
@@ -304,6 +306,15 @@ class GedGraph:
     def source_buckets(self):
         return _lib.ged_source_buckets(self.handle)
 
+    def set_count16(self, hub):
+        """Level-2 counts of batch tiles in 16 bits below a hub cut (0 = library's
+        choice, -1 = off, > 0 = this cut)."""
+        _ck(_lib.ged_set_count16(self.handle, int(hub)), "ged_set_count16")
+
+    def count16_hub(self):
+        """Hub cut of the last batch's 16-bit level-2 counts, -1 if 32-bit."""
+        return _lib.ged_count16_hub(self.handle)
+
     def set_greedy_width(self, width):
         """Candidates per gain SpMM of the greedy (2, 4, 8, 16; 0 = library's choice)."""
         _ck(_lib.ged_set_greedy_width(self.handle, int(width)), "ged_set_greedy_width")
@@ -442,7 +453,7 @@ class Server:
 IN_MODES = ["vec", "ones", "notmask", "mask", "tilemask", "onehot", "fresh", "cnt", "cnt32"]
 OUT_MODES = ["plain", "inj", "zero", "tile", "gain", "pool", "combine", "combine32", "gaincomb",
              "tile32", "combine32l", "gain32", "gaincomb32l", "zero32", "gain32d", "gaincomb32s"]
-KIND_BASE = 16  # a profile record's kind is input mode * KIND_BASE + output mode
+KIND_BASE = 32  # a profile record's kind is input mode * KIND_BASE + output mode
 
 
 def partition_plan(row_ptr, col_idx, n, units, cut_div=1, bucket_rows=0):

@@ -1002,6 +1002,64 @@ def test_batch_row_cuts(ged, name):
     gg.close()
 
 
+@pytest.mark.parametrize("ell", [5, 8])
+def test_batch_count16(ged, ell):
+    """Level-2 counts of batch tiles in the 16-bit layout (rows below the hub
+    cut stay 32-bit).  On BA n=200,000, m=8 (ten vertices with omega_2 above
+    2^16 - 2, all among the first eleven by degree) the batch at the
+    library's cut and at a cut of n/4 (a quarter of the rows in the 32-bit
+    table) is bit for bit the same, at tile widths 4, 8 and 32 (one, two and
+    eight 4-column units per arc), with the row partition's long-row
+    segments and, on a second handle, with source buckets forced on; sampled
+    columns equal the oracle to 1e-9.  ell* = 8 has one 32-bit stored level
+    (level 3 gathers the 16-bit level and is exact): bit for bit the same as
+    with the layout off.  ell* = 5 has none (the combining step gathers the
+    16-bit level, on a partition of twice the arcs per block): the same as
+    with it off up to the column sums' rounding."""
+    g = inputs.barabasi_albert(200000, 8, 5)
+    alpha = oracle.default_alpha(g, None)
+    B = oracle.comb_bound(g, alpha, ell, None)
+    eps = float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, None)))
+    G = 80
+    off, mem = inputs.groups(g.n, G, 1, 200, 177)
+    say(f"[count16] n={g.n} nnz={g.nnz} ell*={ell} eps={eps:.3e}")
+    ref = {}
+    for j in (0, 37, G - 1):
+        c, ell_o, _, _ = oracle.score(g, mem[off[j]:off[j + 1]], alpha, eps)
+        assert ell_o == ell
+        ref[j] = c
+    for buckets in (0, 1 << 16):
+        gg = ged.GedGraph.from_graph(g)
+        if buckets:
+            gg.set_source_buckets(buckets)
+        for tile in (4, 8, 32):
+            gg.set_batch_tile(tile)
+            gg.set_batch_row_cut(1)
+            out = []
+            for hub in (-1, 0, g.n // 4):
+                gg.set_count16(hub)
+                b = gg.score_batch(off, mem, alpha, eps)
+                used = gg.count16_hub()
+                say(f"  buckets={buckets} tile={tile} setting={hub}: cut {used}")
+                if hub == -1:
+                    assert used == -1
+                elif hub == 0:
+                    assert 0 < used <= 64, used
+                else:
+                    assert used == hub
+                out.append(b)
+            np.testing.assert_array_equal(out[2], out[1])
+            if ell == 8:
+                np.testing.assert_array_equal(out[1], out[0])
+            else:
+                assert max(rel(x, y) for x, y in zip(out[1], out[0])) <= 1e-14
+            for j, c in ref.items():
+                assert rel(out[1][j], c) <= REL, (tile, buckets, j, out[1][j], c)
+        with pytest.raises(ged.GedError):
+            gg.set_count16(5)  # below the least cut
+        gg.close()
+
+
 @pytest.mark.parametrize("name", ["ba", "directed", "weighted"])
 def test_spectral_bound(ged, name):
     """sigma_max estimate, ell* and scores / greedy under the spectral tail bound

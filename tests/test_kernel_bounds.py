@@ -51,12 +51,20 @@ def partition(rp, C, units=None, cut_div=1):
     return blocks, segs, lrows
 
 
-def check_step(rp, ci, n, C, pairs=False, cut_div=1):
+def check_step(rp, ci, n, C, pairs=False, cut_div=1, hub=None):
     """pairs: 32-bit input gathered as column pairs (C >= 2): unit q of thread
     t loads elements u*C + 2k, +1 with k = unit mod C/2, staged as two 32-bit
-    LDS slots; phase 2 reads slot j*C + c."""
+    LDS slots; phase 2 reads slot j*C + c.  hub (with pairs, C >= 4): 16-bit
+    level-2 counts gathered as 4-column units on the same partition, half
+    as many units per thread: rows u < hub from the 32-bit table (elements
+    u*C + 4k .. +3), every lane from the packed rows (elements (u - hub)*C +
+    4k .. +3, row 0 for hub lanes), staged as four 32-bit LDS slots."""
     nnz = int(rp[-1])
     ci_alloc = max(1, nnz)
+    if hub is not None:
+        assert pairs and C >= 4 and 0 <= hub < n
+        check_quads(rp, ci, n, C, cut_div, hub)
+        return
     U = C // 2 if pairs else C
     blocks, segs, lrows = partition(rp, C, U, cut_div)
     cut = max(1, K_LDS // U // cut_div)
@@ -116,6 +124,69 @@ def check_step(rp, ci, n, C, pairs=False, cut_div=1):
             j0 = j0 + 8 * lpc
 
 
+def check_quads(rp, ci, n, C, cut_div, hub):
+    """Index arithmetic of the 16-bit (IN_CNT16) gather on its own partition
+    (C/4 eight-byte units per arc): row blocks stage every arc's packed
+    8 bytes (elements u*C + 4k .. +3 of the packed rows, which cover every
+    row) as 16-bit LDS values, and the per-row sums fetch a hub row's 32-bit
+    count from the table at src*C + c, src read back from col_idx at the
+    block's arc; long-row segments load the packed unit and, for hub rows,
+    16 bytes of the table (bucket blocks use the row blocks' formulas on the
+    copied col_idx).  Also the byte extent of the layout against its
+    allocation and the pushes' 32-bit words."""
+    nnz = int(rp[-1])
+    GU = C // 4
+    blocks, segs, _ = partition(rp, C, GU, cut_div)
+    PT = K_LDS // K_BLOCK
+    t = np.arange(K_BLOCK)
+    pk_off = (hub * C * 4 + 255) // 256 * 256
+    alloc = max(4 * n * C, pk_off + 2 * n * C)
+
+    def packed(u, k):
+        e16 = u * C + 4 * k
+        assert e16.min() >= 0 and (e16 + 3).max() < n * C and (e16 % 4 == 0).all()
+        assert pk_off + 2 * ((e16 + 3).max() + 1) <= alloc
+
+    def table(u, k_or_c, width):
+        hb = u < hub
+        if hb.any():
+            e32 = u[hb] * C + k_or_c[hb] if np.ndim(k_or_c) else u[hb] * C + k_or_c
+            assert e32.min() >= 0 and (e32 + width - 1).max() < hub * C
+
+    for (r0, r1, p0, p1) in blocks:
+        tot = (p1 - p0) * GU
+        assert tot <= K_LDS
+        jlo = p0 if tot > 0 else 0
+        jmax = p1 - 1 if tot > 0 else 0
+        for q in range(PT):
+            f = t + q * K_BLOCK
+            j = np.minimum(jlo + f // GU, jmax)
+            assert j.min() >= 0 and j.max() < max(1, nnz)
+            u = ci[j] if tot > 0 else np.zeros_like(j)
+            packed(u, f & (GU - 1))
+            slot = np.where(f < tot, f, K_LDS + t)  # 8-byte slots of four 16-bit values
+            assert 4 * slot.max() + 3 < 4 * (K_LDS + K_BLOCK)
+        if tot > 0:  # phase 2: 16-bit slot j*C + c; hub rows from the table
+            assert (p1 - p0 - 1) * C + C - 1 < 4 * tot
+            src = ci[p0:p1]
+            for c in (0, C - 1):
+                table(src, c, 1)
+    for (r, y, z) in segs:
+        lpu = K_BLOCK // GU
+        j0 = y + t // GU
+        while j0.min() < z:
+            for q in range(8):
+                jj = np.minimum(j0 + q * lpu, z - 1)
+                assert jj.min() >= y and jj.max() < nnz
+                u = ci[jj].astype(np.int64)
+                packed(u, t & (GU - 1))
+                table(u, 4 * (t & (GU - 1)), 4)
+            j0 = j0 + 8 * lpu
+    # the pushes' 32-bit words of packed entries (v >= hub, any column)
+    o = (n - 1) * C + (C - 1)
+    assert pk_off + 2 * (o & ~1) + 4 <= alloc
+
+
 def internal_csr(g):
     """The library's storage: vertices by decreasing out-degree (stable),
     rows = in-neighbours, sorted."""
@@ -156,6 +227,9 @@ def test_step_indices_in_bounds(g):
                 check_step(rp, ci, g.n, C, cut_div=cut_div)
                 if C >= 2:
                     check_step(rp, ci, g.n, C, pairs=True, cut_div=cut_div)
+                if C in (4, 8, 32):  # 16-bit gathers: one and two units per arc, and 8
+                    for hub in sorted({0, g.n // 8, g.n - 1}):
+                        check_quads(rp, ci, g.n, C, cut_div, hub)
 
 
 def wl_need(n, nnz, deg_sum):
