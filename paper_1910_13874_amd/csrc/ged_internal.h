@@ -151,7 +151,7 @@ constexpr int kLdsDoubles = 2048;      // LDS staging per block (16 KiB)
 // blocks for wide steps were measured slower on BA n=2e6: 816 vs 764 us at
 // C = 16.)
 __host__ __device__ constexpr int lds_values(int) { return kLdsDoubles; }
-constexpr int kRowsPerBlock = 511;     // max rows of one row block (row_ptr slice: 2 loads per thread)
+constexpr int kRowsPerBlock = 255;     // max rows of one row block (row_ptr slice: 1 load per thread)
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 
 // Row partition for a step with C columns: row blocks of consecutive short

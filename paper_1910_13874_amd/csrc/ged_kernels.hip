@@ -258,8 +258,9 @@ __device__ __forceinline__ double epilogue(const StepArgs &a, int v, int c, doub
 // butterfly shuffles inside each wavefront, then the four wavefront partials
 // are added in a fixed order.  The thread -> column map is
 // c = (t / tpr) & (C - 1) with tpr lanes per (row, column) pair; only lanes
-// with s = t % tpr == 0 carry values.  red must hold 4*C zeros (or every
-// column of every wavefront must be written, which holds for tpr == 1).
+// with s = t % tpr == 0 carry values.  red (4*C doubles) may hold anything:
+// each wavefront first zeroes its own row, since its lanes may cover only
+// part of the columns (a wavefront's LDS writes take effect in order).
 template <int C>
 __device__ __forceinline__ void block_colsum(double v, int tpr, double *red, double *out,
                                              int accum) {
@@ -267,6 +268,7 @@ __device__ __forceinline__ void block_colsum(double v, int tpr, double *red, dou
   for (int o = 1; o < tpr; o <<= 1) v += __shfl_xor(v, o, 64);
   const int G = tpr * C;
   for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+  if (lane < C) red[w * C + lane] = 0.0;
   if ((lane & (tpr - 1)) == 0 && lane < G) red[w * C + ((t / tpr) & (C - 1))] = v;
   __syncthreads();
   if (t < C) {
@@ -295,32 +297,50 @@ __device__ __forceinline__ void block_colsum_pairs(double v0, double v1, double 
 }
 
 // Per-row sum of staged integer counts (32-bit pairs or 16-bit units) over
-// arcs j0 + s, j0 + s + tpr, .. < j1 of column c: four independent 64-bit
-// partials keep four LDS reads in flight, and integer sums are exact in any
-// order, so the result is the exact count (converted once; exact below 2^53).
-// Q4: a staged kC16Hub stands for a row below the hub cut, fetched from the
-// 32-bit table at the arc's source src[j].
+// arcs j0 + s, j0 + s + tpr, .. < j1 of column c: four independent partials
+// keep four LDS reads in flight, and integer sums are exact in any order, so
+// the result is the exact count (converted once; exact below 2^53).  Q4: the
+// partials are 32-bit (a block stages at most 2048 arcs of 16-bit values), a
+// staged kC16Hub stands for a row below the hub cut, and the loop only counts
+// those; a row that met any sums again with their 32-bit counts, fetched from
+// the table at the arc's source src[j] (branch-free main loop: no memory wait
+// inside it).
 template <int C, bool Q4, class SV>
 __device__ __forceinline__ double sum_staged_counts(const StepArgs &a, const SV *vals, int j0,
                                                    int j1, int s, int tpr, int c,
                                                    const int *src) {
-  uint64_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-  auto val = [&](int j) -> uint32_t {
-    uint32_t x = vals[j * C + c];
-    if constexpr (Q4)
-      if (x == kC16Hub) x = a.Xc32[(size_t)src[j] * C + c];
-    return x;
-  };
+  using AT = typename std::conditional<Q4, uint32_t, uint64_t>::type;
+  AT q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+  uint32_t nh = 0;
   int j = j0 + s;
   for (; j + 3 * tpr < j1; j += 4 * tpr) {
-    const uint32_t x0 = val(j), x1 = val(j + tpr), x2 = val(j + 2 * tpr), x3 = val(j + 3 * tpr);
+    const uint32_t x0 = vals[j * C + c], x1 = vals[(j + tpr) * C + c];
+    const uint32_t x2 = vals[(j + 2 * tpr) * C + c], x3 = vals[(j + 3 * tpr) * C + c];
+    if constexpr (Q4)
+      nh += (uint32_t)(x0 == kC16Hub) + (uint32_t)(x1 == kC16Hub) + (uint32_t)(x2 == kC16Hub) +
+            (uint32_t)(x3 == kC16Hub);
     q0 += x0;
     q1 += x1;
     q2 += x2;
     q3 += x3;
   }
-  for (; j < j1; j += tpr) q0 += val(j);
-  return (double)((q0 + q1) + (q2 + q3));
+  for (; j < j1; j += tpr) {
+    const uint32_t x = vals[j * C + c];
+    if constexpr (Q4) nh += (uint32_t)(x == kC16Hub);
+    q0 += x;
+  }
+  uint64_t sum = (uint64_t)((q0 + q1) + (q2 + q3));
+  if constexpr (Q4) {
+    if (nh != 0) {
+      sum = 0;
+      for (j = j0 + s; j < j1; j += tpr) {
+        uint32_t x = vals[j * C + c];
+        if (x == kC16Hub) x = a.Xc32[(size_t)src[j] * C + c];
+        sum += x;
+      }
+    }
+  }
+  return (double)sum;
 }
 
 // The same for lanes holding four columns (4k .. 4k+3), k = t % (C/4).
@@ -360,14 +380,19 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
   constexpr int PT = LV / kBlock;            // gather units per thread
   constexpr int GU = Q4 ? C / 4 : CU;        // gather units per arc
   constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
+  constexpr int RB = (kRowsPerBlock + kBlock - 1) / kBlock;  // rows per thread (masks)
   using SV = typename std::conditional<Q4, uint16_t,
                                        typename std::conditional<NP, uint32_t, double>::type>::type;
-  // vals has one spare unit per thread so every phase-1 store is unconditional
-  __shared__ alignas(16) SV vals[(Q4 ? 4 : NP ? 2 : 1) * (LV + kBlock)];
+  // per-row column bits: the columns of a tile of C <= 32 fit 32 bits
+  using TW = typename std::conditional<(C <= 32), uint32_t, uint64_t>::type;
+  // LDS is what bounds the resident blocks (latency-bound gathers want as
+  // many as fit): 16 KiB of staged values, the column-sum scratch sharing
+  // their storage once phase 2 has read them, and one or two words per row.
+  __shared__ alignas(16) SV vals[(Q4 ? 4 : NP ? 2 : 1) * LV];
+  double *const red = reinterpret_cast<double *>(vals);  // (kBlock / 64) * C doubles
   __shared__ int rps[kRowsPerBlock + 1];
-  __shared__ double red[(kBlock / 64) * C];
   __shared__ uint32_t mw[M1 ? kRowsPerBlock / 32 + 2 : 1];
-  __shared__ uint64_t tmw[TM ? kRowsPerBlock : 1];
+  __shared__ TW tmw[TM ? kRowsPerBlock : 1];
   __shared__ int cw[CA ? kRowsPerBlock : 1];
   constexpr int LPC = kBlock / C;  // lanes per column in a segment
   const int t = threadIdx.x;
@@ -377,7 +402,6 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     const int4 d = blocks[b];
     const int r0 = d.x, nrows = d.y - d.x, p0 = d.z;
     const int tot = (d.w - d.z) * GU;  // gather units of the block
-    if (t < (kBlock / 64) * C) red[t] = 0.0;
     // Phase 1.  Load order matters: the col_idx stream first, then the row
     // pointers and epilogue masks of the block, then the gathers (which wait
     // only for col_idx), so a block pays two dependent memory round trips.
@@ -398,12 +422,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     const int nw = ((r0 + nrows - 1) >> 5) - (r0 >> 5) + 1;
     uint32_t mv = 0;
     if constexpr (M1) mv = a.smask[(r0 >> 5) + min(t, nw - 1)];
-    uint64_t tv[2] = {0, 0};
-    int cv[2] = {-1, -1};
+    TW tv[RB];
+    int cv[RB];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < RB; ++k) {
       const int rr = r0 + min(t + k * kBlock, nrows - 1);
-      if constexpr (TM) tv[k] = a.tmask[rr];
+      tv[k] = 0;
+      cv[k] = -1;
+      if constexpr (TM) tv[k] = (TW)a.tmask[rr];
       if constexpr (CA) cv[k] = a.cand_col[rr];
     }
     // The combining epilogue's row data for this thread's first (row, column)
@@ -433,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
     if constexpr (M1)
       if (t < nw) mw[t] = mv;
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < RB; ++k)
       if (t + k * kBlock < nrows) {
         if constexpr (TM) tmw[t + k * kBlock] = tv[k];
         if constexpr (CA) cw[t + k * kBlock] = cv[k];
@@ -441,10 +467,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int f = t + q * kBlock;
-      if constexpr (NP || Q4)
-        reinterpret_cast<uint2 *>(vals)[f < tot ? f : LV + t] = v2[q];
-      else
-        vals[f < tot ? f : LV + t] = v[q];
+      if (f < tot) {
+        if constexpr (NP || Q4)
+          reinterpret_cast<uint2 *>(vals)[f] = v2[q];
+        else
+          vals[f] = v[q];
+      }
     }
     __syncthreads();
     // Phase 2: tpr lanes per (row, column), as many as the row count allows.
@@ -511,6 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
         }
       }
     }
+    __syncthreads();  // red shares the staged values' storage
     block_colsum<C>(colsum, tpr, red, a.blk_part + (size_t)b * C, a.accum);
   } else if (a.bk_ci != nullptr) {
     // Bucket block: pieces [s0, s0 + np) of long rows, all of whose sources
@@ -547,10 +576,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
 #pragma unroll
       for (int q = 0; q < PT; ++q) {
         const int f = t + q * kBlock;
-        if constexpr (NP || Q4)
-          reinterpret_cast<uint2 *>(vals)[f < tot ? f : LV + t] = v2[q];
-        else
-          vals[f < tot ? f : LV + t] = v[q];
+        if (f < tot) {  // vals holds exactly LV units
+          if constexpr (NP || Q4)
+            reinterpret_cast<uint2 *>(vals)[f] = v2[q];
+          else
+            vals[f] = v[q];
+        }
       }
       __syncthreads();
       int tpr = (kBlock / C < 64) ? kBlock / C : 64;

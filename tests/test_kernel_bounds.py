@@ -1,7 +1,7 @@
 """Index arithmetic of the HIP kernels, emulated on the CPU (no GPU).
 
 Mirrors the row partition the library builds (row blocks of at most
-2048/C/cut_div arcs and 511 rows, rows above that row-split threshold split
+2048/C/cut_div arcs and 255 rows, rows above that row-split threshold split
 into segments of 8192/C arcs, for the divisors 1, 2 and 4 the batch
 autotuner races) and every
 index formula of the step kernel, on CSRs in the library's internal vertex
@@ -19,7 +19,7 @@ import pytest
 
 from paper_1910_13874_amd import inputs
 
-K_BLOCK, K_ROWS, K_SEG, K_LDS = 256, 511, 8192, 2048
+K_BLOCK, K_ROWS, K_SEG, K_LDS = 256, 255, 8192, 2048
 WL_CHUNK = 512
 
 
@@ -92,15 +92,15 @@ def check_step(rp, ci, n, C, pairs=False, cut_div=1, hub=None):
                 e = u * C + 2 * ((t + q * K_BLOCK) & (U - 1))
                 assert e.min() >= 0 and (e + 1).max() < n * C and (e % 2 == 0).all()
             f = t + q * K_BLOCK
-            slot = np.where(f < tot, f, K_LDS + t)
-            assert slot.max() < K_LDS + K_BLOCK
+            slot = f[f < tot]  # staged only below the block's units
+            assert slot.size == 0 or slot.max() < K_LDS
         if pairs and tot > 0:  # phase 2 reads 32-bit slot j*C + c of the staged arcs
             assert (p1 - p0 - 1) * C + C - 1 < 2 * tot
         for k in range(RT):  # row_ptr slice
             assert (r0 + np.minimum(t + k * K_BLOCK, nrows)).max() <= n
         nw = ((r0 + nrows - 1) >> 5) - (r0 >> 5) + 1
         assert ((r0 >> 5) + np.minimum(t, nw - 1)).max() < mask_words
-        for k in range(2):  # per-row masks
+        for k in range((K_ROWS + K_BLOCK - 1) // K_BLOCK):  # per-row masks
             rr = r0 + np.minimum(t + k * K_BLOCK, nrows - 1)
             assert rr.min() >= 0 and rr.max() < n
         # combining epilogue's early loads: row r0 + min((t/tpr)/C, nrows-1)
@@ -164,8 +164,8 @@ def check_quads(rp, ci, n, C, cut_div, hub):
             assert j.min() >= 0 and j.max() < max(1, nnz)
             u = ci[j] if tot > 0 else np.zeros_like(j)
             packed(u, f & (GU - 1))
-            slot = np.where(f < tot, f, K_LDS + t)  # 8-byte slots of four 16-bit values
-            assert 4 * slot.max() + 3 < 4 * (K_LDS + K_BLOCK)
+            slot = f[f < tot]  # 8-byte slots of four 16-bit values
+            assert slot.size == 0 or 4 * slot.max() + 3 < 4 * K_LDS
         if tot > 0:  # phase 2: 16-bit slot j*C + c; hub rows from the table
             assert (p1 - p0 - 1) * C + C - 1 < 4 * tot
             src = ci[p0:p1]
@@ -291,8 +291,11 @@ def check_buckets(ged, rp, ci, n, C, pairs, cut_div, bucket_rows, rng):
     by the fix-up's piece lists; bucket blocks respect the block limits and
     are dealt to the XCDs (grid position n_blocks + i runs on XCD
     (n_blocks + i) mod 8) in eight contiguous runs; and every index the step
-    kernel's bucket blocks and the fix-up form stays inside its buffer."""
-    U = C // 2 if pairs else C
+    kernel's bucket blocks and the fix-up form stays inside its buffer.
+    pairs == "quad": 16-bit inputs, C/4 four-column units per arc (staged
+    as four 16-bit values; the packed rows cover every vertex)."""
+    quad = pairs == "quad"
+    U = C // 4 if quad else C // 2 if pairs else C
     pl = ged.partition_plan(rp, ci, n, U, cut_div, bucket_rows)
     cut = pl["cut"]
     deg = np.diff(rp)
@@ -345,15 +348,18 @@ def check_buckets(ged, rp, ci, n, C, pairs, cut_div, bucket_rows, rng):
             assert j.min() >= 0 and j.max() < len(bk_ci)
             u = bk_ci[j]
             assert u.min() >= 0 and u.max() < n
-            if pairs:
+            if quad:
+                e = u.astype(np.int64) * C + 4 * ((t + q * K_BLOCK) & (U - 1))
+                assert (e + 3).max() < n * C
+            elif pairs:
                 e = u.astype(np.int64) * C + 2 * ((t + q * K_BLOCK) & (U - 1))
                 assert (e + 1).max() < n * C
             f = t + q * K_BLOCK
-            assert np.where(f < tot, f, K_LDS + t).max() < K_LDS + K_BLOCK
+            assert f[f < tot].max(initial=0) < K_LDS
         for k in range(RT):
             assert (s0 + np.minimum(t + k * K_BLOCK, npc)).max() <= nseg
         # phase 2: arc slots j*C + c of the staged values, piece sums to seg_out
-        assert (a1 - a0) * C <= (2 if pairs else 1) * K_LDS
+        assert (a1 - a0) * C <= (4 if quad else 2 if pairs else 1) * K_LDS
         assert s1 <= nseg
     # fix-up: entries of the piece lists name seg_out slots
     assert lsub.max() < nseg and lf.max() <= len(lsub)
@@ -366,7 +372,8 @@ def test_bucket_plan_in_bounds(g):
     rp, ci = internal_csr(g)
     for U, cut_div in ((1, 1), (2, 1), (4, 1), (4, 2), (8, 4), (32, 1)):
         check_plan_matches_emulation(ged, rp, ci, g.n, U, cut_div)
-    for C, pairs in ((1, False), (2, False), (4, False), (2, True), (4, True), (8, True)):
+    for C, pairs in ((1, False), (2, False), (4, False), (2, True), (4, True), (8, True),
+                     (4, "quad"), (8, "quad")):
         for cut_div in (1, 2, 4):
             for br in (1, 7, 64, 4096, 1 << 20):
                 check_buckets(ged, rp, ci, g.n, C, pairs, cut_div, br, rng)
