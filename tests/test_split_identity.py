@@ -313,3 +313,108 @@ def test_miss_counts_by_subtraction(seed):
                 for v in range(g.n):
                     assert m2[i][v] == tab.miss_end(i, S + [x], v)
                     assert d[i][v] == (tab.miss_end(i, S, v) - tab.miss_end(i, S + [x], v))
+
+
+def _wide_prefix_graph():
+    """K_{300,300} (omega_2 = 90,000 at each of its 600 vertices: degree 300,
+    neighbours of degree 300) joined by a few edges to a BA graph of 4,000
+    vertices: the vertices with omega_2 above 2^16 - 2 are exactly the
+    K_{300,300} ones, which are also the 600 of highest degree."""
+    ba = inputs.barabasi_albert(4000, 3, 91)
+    rows = np.repeat(np.arange(ba.n), np.diff(ba.row_ptr))
+    src = [rows + 600, []]
+    dst = [ba.col_idx.astype(np.int64) + 600, []]
+    a, b = np.meshgrid(np.arange(300), np.arange(300, 600), indexing="ij")
+    src[1] = np.concatenate([a.ravel(), np.arange(0, 600, 50)])
+    dst[1] = np.concatenate([b.ravel(), 600 + np.arange(0, 600, 50) * 3])
+    s = np.concatenate([np.asarray(x, dtype=np.int32) for x in src])
+    d = np.concatenate([np.asarray(x, dtype=np.int32) for x in dst])
+    return inputs.from_edges(4600, s, d, symmetrize=True, name="wide_prefix")
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_count16_packed_pushes(forced):
+    """The 16-bit level-2 layout of batch tiles, emulated on the CPU in the
+    library's vertex order (decreasing degree, stable): rows below the cut in
+    a 32-bit table, every other row's count as one 16-bit half of a 32-bit
+    word shared with the adjacent column.  The kernels' pushes add value <<
+    16*(c & 1) to the word (member pushes of deg(s), then the level-2 push of
+    count_1(y) from each non-member y reached first, skipping member targets),
+    and member rows are raised to omega_2 by adding the difference.  Pinned
+    here: no half ever exceeds 2^16 - 2 (so no add carries into the other
+    column and the gather's 2^16 - 1 marker is never a count), the raise adds
+    a nonnegative difference, and the decoded counts (marker rows read from
+    the table, as the gather does) equal the plain level-2 counts of every
+    column.  forced: a cut of n/4, above the least one."""
+    g = _wide_prefix_graph()
+    rp0, ci0 = np.asarray(g.row_ptr, np.int64), np.asarray(g.col_idx, np.int64)
+    n = g.n
+    deg0 = np.diff(rp0)
+    order = np.argsort(-deg0, kind="stable")
+    new = np.empty(n, np.int64)
+    new[order] = np.arange(n)
+    rows = new[np.repeat(np.arange(n), deg0)]
+    cols = new[ci0]
+    idx = np.lexsort((cols, rows))
+    ci = cols[idx]
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp)
+    deg = np.diff(rp)
+    omega2 = np.array([deg[ci[rp[v]:rp[v + 1]]].sum() for v in range(n)], dtype=np.int64)
+    wide = np.nonzero(omega2 > 0xFFFE)[0]
+    least = int(wide.max()) + 1 if wide.size else 0
+    assert least == 600 and wide.size == 600
+    cut = n // 4 if forced else least
+    C = 8
+    rng = np.random.default_rng(17)
+    groups = [np.unique(rng.integers(0, n, int(rng.integers(1, 80)))) for _ in range(C)]
+    groups[0] = np.array([0, 1, 300])  # members inside the wide prefix
+    hub = np.zeros((cut, C), np.uint32)
+    words = np.zeros((n, C // 2), np.uint32)
+
+    def add(v, c, val):
+        if v < cut:
+            hub[v, c] += np.uint32(val)
+        else:
+            words[v, c // 2] += np.uint32(int(val) << (16 * (c & 1)))
+
+    def half(v, c):
+        return int(words[v, c // 2] >> np.uint32(16 * (c & 1))) & 0xFFFF
+
+    def check_halves():
+        assert int((words & 0xFFFF).max()) <= 0xFFFE and int((words >> 16).max()) <= 0xFFFE
+
+    cnt1 = np.zeros((n, C), np.int64)
+    inS = np.zeros((n, C), bool)
+    claimed = [[] for _ in range(C)]
+    for c, S in enumerate(groups):
+        inS[S, c] = True
+    for c, S in enumerate(groups):  # member pushes (k_push)
+        for s in S:
+            for y in ci[rp[s]:rp[s + 1]]:
+                old = cnt1[y, c]
+                cnt1[y, c] += 1
+                add(int(y), c, deg[s])
+                if old == 0 and not inS[y, c]:
+                    claimed[c].append(int(y))
+    check_halves()
+    for c in range(C):  # level-2 push (k_push_wl) and the member raise
+        for s in groups[c]:
+            cur = int(hub[s, c]) if s < cut else half(s, c)
+            assert omega2[s] >= cur
+            if s < cut:
+                hub[s, c] = omega2[s]
+            else:
+                add(int(s), c, omega2[s] - cur)
+        for y in claimed[c]:
+            for x in ci[rp[y]:rp[y + 1]]:
+                if not inS[x, c]:
+                    add(int(x), c, cnt1[y, c])
+        check_halves()
+    # the gather's decode: 16-bit halves, rows below the cut from the table
+    for c, S in enumerate(groups):
+        _, want = push_counts(rp, ci, S, 2)
+        got = np.array([int(hub[v, c]) if v < cut else half(v, c) for v in range(n)])
+        np.testing.assert_array_equal(got, want)
+        assert (want[cut:] <= omega2[cut:]).all()
