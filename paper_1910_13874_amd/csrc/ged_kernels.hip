@@ -16,7 +16,12 @@
 //     to blk_part in a fixed tree order.
 //     32-bit inputs at C >= 2 (integer walk counts) are gathered as pairs of
 //     adjacent columns, 8 bytes per lane like an FP64 value, into blocks of
-//     twice the arcs, so each wavefront keeps as many cache lines in flight.
+//     twice the arcs, so each wavefront keeps as many cache lines in flight;
+//     16-bit level-2 counts (batch tiles, C >= 4) as units of four columns
+//     into blocks of four times the arcs.  A block's LDS (16 KiB of staged
+//     values plus a few words per row) is sized so that eight blocks fit a
+//     CU: the random gathers are latency-bound, and more resident blocks
+//     keep more of them in flight.
 //   * long rows (more arcs than a row block holds, the power-law hubs): split
 //     into fixed segments, one block each, whose raw sums go to seg_out; a
 //     fix-up kernel adds the segments of each row in order.
