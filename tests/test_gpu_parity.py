@@ -1060,6 +1060,65 @@ def test_batch_count16(ged, ell):
         gg.close()
 
 
+def test_batch_count16_wide_rows(ged):
+    """The 16-bit level-2 layout with members among the rows kept in 32 bits.
+    The graph's 600 highest-degree vertices (a K_{300,300} core, omega_2 =
+    90,000) are exactly those above 2^16 - 2, more than n/8, so the library
+    leaves the layout off by itself; forced cuts of 600 (the least) and n - 1
+    put them, and then almost every row, in the 32-bit table.  Groups hold
+    core vertices, an empty group and single members; tiles of 8 and 32
+    columns; ell* = 5 and 8.  Scores equal the oracle to 1e-9, the two cuts
+    agree bit for bit, and with the layout off the batch agrees bit for bit
+    at ell* = 8 (to the column sums' rounding at 5); a cut below 600 is
+    refused."""
+    from wide_prefix import wide_prefix_graph
+    g = wide_prefix_graph()
+    alpha = oracle.default_alpha(g, None)
+    core = np.argsort(-g.degrees, kind="stable")[:600].astype(np.int32)
+    assert sorted(core.tolist()) == list(range(600))
+    groups = [core[:3], np.zeros(0, np.int32), core[599:600], np.arange(650, 651, dtype=np.int32),
+              np.concatenate([core[100:140], np.arange(600, 700, dtype=np.int32)]),
+              inputs.group(g.n, 50, 7), inputs.group(g.n, 200, 8), core[:300]]
+    off = np.zeros(len(groups) + 1, np.int64)
+    for j, S in enumerate(groups):
+        off[j + 1] = off[j] + S.size
+    mem = np.concatenate(groups).astype(np.int32)
+    say(f"[count16 wide rows] n={g.n} nnz={g.nnz} groups={len(groups)}")
+    gg = ged.GedGraph.from_graph(g)
+    with pytest.raises(ged.GedError):
+        gg.set_count16(599)
+    for ell in (5, 8):
+        B = oracle.comb_bound(g, alpha, ell, None)
+        eps = float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, None)))
+        ref = []
+        for S in groups:
+            c, ell_o, _, _ = oracle.score(g, S, alpha, eps)
+            assert ell_o == ell
+            ref.append(c)
+        for tile in (8, 32):
+            gg.set_batch_tile(tile)
+            gg.set_batch_row_cut(1)
+            out = {}
+            for hub in (-1, 0, 600, g.n - 1):
+                gg.set_count16(hub)
+                out[hub] = gg.score_batch(off, mem, alpha, eps)
+                used = gg.count16_hub()
+                say(f"  ell*={ell} tile={tile} setting={hub}: cut {used}")
+                assert used == (-1 if hub in (-1, 0) else hub)
+            np.testing.assert_array_equal(out[600], out[g.n - 1])
+            np.testing.assert_array_equal(out[0], out[-1])
+            if ell == 8:
+                np.testing.assert_array_equal(out[600], out[-1])
+            else:
+                assert max(rel(x, y) for x, y in zip(out[600], out[-1]) if y) <= 1e-14
+            for j, c in enumerate(ref):
+                if c == 0.0:
+                    assert out[600][j] == 0.0
+                else:
+                    assert rel(out[600][j], c) <= REL, (ell, tile, j, out[600][j], c)
+    gg.close()
+
+
 @pytest.mark.parametrize("name", ["ba", "directed", "weighted"])
 def test_spectral_bound(ged, name):
     """sigma_max estimate, ell* and scores / greedy under the spectral tail bound

@@ -18,6 +18,7 @@ import pytest
 import oracle
 from exact import WalkTable
 from paper_1910_13874_amd import inputs
+from wide_prefix import wide_prefix_graph
 from split_model import (count_levels, push3_bound, push3_counts, push_counts, split_gain,
                          split_gain_counts, split_score, split_score_counts)
 
@@ -315,23 +316,6 @@ def test_miss_counts_by_subtraction(seed):
                     assert d[i][v] == (tab.miss_end(i, S, v) - tab.miss_end(i, S + [x], v))
 
 
-def _wide_prefix_graph():
-    """K_{300,300} (omega_2 = 90,000 at each of its 600 vertices: degree 300,
-    neighbours of degree 300) joined by a few edges to a BA graph of 4,000
-    vertices: the vertices with omega_2 above 2^16 - 2 are exactly the
-    K_{300,300} ones, which are also the 600 of highest degree."""
-    ba = inputs.barabasi_albert(4000, 3, 91)
-    rows = np.repeat(np.arange(ba.n), np.diff(ba.row_ptr))
-    src = [rows + 600, []]
-    dst = [ba.col_idx.astype(np.int64) + 600, []]
-    a, b = np.meshgrid(np.arange(300), np.arange(300, 600), indexing="ij")
-    src[1] = np.concatenate([a.ravel(), np.arange(0, 600, 50)])
-    dst[1] = np.concatenate([b.ravel(), 600 + np.arange(0, 600, 50) * 3])
-    s = np.concatenate([np.asarray(x, dtype=np.int32) for x in src])
-    d = np.concatenate([np.asarray(x, dtype=np.int32) for x in dst])
-    return inputs.from_edges(4600, s, d, symmetrize=True, name="wide_prefix")
-
-
 @pytest.mark.parametrize("forced", [False, True])
 def test_count16_packed_pushes(forced):
     """The 16-bit level-2 layout of batch tiles, emulated on the CPU in the
@@ -346,7 +330,7 @@ def test_count16_packed_pushes(forced):
     a nonnegative difference, and the decoded counts (marker rows read from
     the table, as the gather does) equal the plain level-2 counts of every
     column.  forced: a cut of n/4, above the least one."""
-    g = _wide_prefix_graph()
+    g = wide_prefix_graph()
     rp0, ci0 = np.asarray(g.row_ptr, np.int64), np.asarray(g.col_idx, np.int64)
     n = g.n
     deg0 = np.diff(rp0)
