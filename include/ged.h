@@ -205,14 +205,14 @@ int32_t ged_batch_row_cut(const ged_graph *g);
  * hub = 0 (default): the least such cut, when it is at most n/8, for tiles
  * of at least 4 columns whose plan stores its deeper levels as 32-bit counts
  * (or has none); -1: never; hub > 0: that cut (GED_ERR_ARG if it is below
- * the least cut or not below n).  The counts are exact integers either
- * way.  When the plan stores a level above 2 (the 16-bit level feeds that
- * exact level), scores are bit-identical for every setting; when the
- * combining step gathers level 2 itself, its 16-bit form sums the rows in
- * blocks of twice the arcs, so scores with and without it differ by the
- * rounding of the column sums (~1e-16 relative), and are bit-identical among
- * the 16-bit settings.  ged_count16_hub returns the cut the last
- * ged_score_batch used, -1 for 32-bit counts.
+ * the least cut or not below n).  With the layout the last stored level
+ * (above 2) also keeps a 16-bit copy of its exact counts, marking those
+ * above 2^16 - 2, and the combining step gathers that copy.  The counts are
+ * exact integers either way, but the 16-bit steps sum rows in blocks of
+ * more arcs, so scores with and without the layout differ by the rounding of
+ * the column sums (~1e-16 relative); they are bit-identical among the 16-bit
+ * settings.  ged_count16_hub returns the cut the last ged_score_batch used,
+ * -1 for 32-bit counts.
  */
 int ged_set_count16(ged_graph *g, int32_t hub);
 int32_t ged_count16_hub(const ged_graph *g);

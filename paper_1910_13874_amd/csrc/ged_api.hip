@@ -125,6 +125,8 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
   double b = 4.0 * (n + 1) + 4.0 * nnz;  // row_ptr, col_idx
   if (out == OUT_TILE32 || out == OUT_GAIN32 || out == OUT_GAINCOMB32S)
     b += 4.0 * n * C;  // Y32
+  else if (out == OUT_TILE32H)
+    b += 6.0 * n * C;  // Y32 and Y16
   else if (out == OUT_ZERO32 || out == OUT_GAIN32D)
     b += 12.0 * n * C;  // Y32 and Y
   else if (out != OUT_COMBINE && out != OUT_COMBINE32 && out != OUT_COMBINE32L &&
@@ -150,6 +152,7 @@ double algo_bytes(const ged_graph *g, int C, int in, int out, double extra_rows)
     case OUT_ZERO32: b += n / 8.0; break;
     case OUT_TILE:
     case OUT_TILE32:
+    case OUT_TILE32H:
     case OUT_POOL: b += 8.0 * n; break;
     case OUT_GAIN:
     case OUT_GAIN32:

@@ -255,8 +255,10 @@ enum OutMode : int {
   OUT_GAIN32D = 14,     // OUT_GAIN32 that also stores alpha * y to Y (the FP64 level)
   OUT_GAINCOMB32S = 15, // OUT_GAINCOMB32L that also stores y's count to Y32: 0 on S, the
                         // candidate's miss count (inj / alpha) at it, else the sum
-  OUT_COMBINE16 = 16    // OUT_COMBINE32L (32-bit stored levels, or none) whose level-2
-                        // counts q_cnt2 are in the 16-bit layout (hub table q_cnt2, Xc16)
+  OUT_COMBINE16 = 16,   // OUT_COMBINE32L (32-bit stored levels, or none) whose level-2
+                        // counts q_cnt2 are in the 16-bit layout (hub table q_cnt2, q_pk2)
+  OUT_TILE32H = 17      // OUT_TILE32 that also stores a 16-bit copy of the count to Y16,
+                        // kC16Hub where the count exceeds kC16Max
 };
 // Profile records and kernel names encode a (gather, epilogue) pair as
 // in * kKindBase + out.
@@ -286,9 +288,15 @@ struct StepArgs {
   // IN_CNT / IN_CNT32 source
   const uint64_t *Xc = nullptr;    // [n*C]
   const uint32_t *Xc32 = nullptr;  // [n*C]
-  // IN_CNT16 / OUT_COMBINE16: rows v >= hub of the level-2 counts, 16-bit
-  const uint16_t *Xc16 = nullptr;  // [n*C]
+  // IN_CNT16: the 16-bit copy of the gathered level ([n*C]; rows below hub, and
+  // values marked kC16Hub, are read from Xc32)
+  const uint16_t *Xc16 = nullptr;
   int hub = 0;
+  uint16_t *Y16 = nullptr;         // [n*C] (OUT_TILE32H)
+  // OUT_COMBINE16: the level-2 rows in the 16-bit layout (table q_cnt2, packed
+  // rows q_pk2, cut q_hub2)
+  const uint16_t *q_pk2 = nullptr;
+  int q_hub2 = 0;
   // OUT_COMBINE(32): per row v and column c the column sum takes
   //   q + y + y*tr[v] + [v not in S](inj[v] - y) * (q_even ? q + y : q),
   // q = q_s1*q_cnt1[v,c] + q_s2*q_cnt2[v,c] + sum_l q_lv[l][v,c]
@@ -355,6 +363,10 @@ __host__ __device__ constexpr bool narrow_gather(int C, int in_mode, bool weight
 // bytes instead of 128.  The gather (IN_CNT16) stages the packed values in
 // LDS, with the value 2^16 - 1 -- which no packed count takes -- standing for
 // rows below the cut, whose 32-bit counts the per-row sums fetch instead.
+// The last stored dense level (a walk-count level the step computes exactly)
+// gets a 16-bit copy with the same marker where its count exceeds kC16Max
+// (cut 0: any row may carry it), so the combining step gathers it the same
+// way, reading marked values from the 32-bit level.
 constexpr uint32_t kC16Max = 0xfffe;    // largest count the packed rows hold
 constexpr uint32_t kC16Hub = 0xffff;    // staged in place of a hub row's value
 __host__ __device__ constexpr size_t c16_pk_offset(int hub, int C) {
@@ -449,6 +461,7 @@ struct SplitWs {
   DBuf cnt1, cnt2;       // [n*C] walk counts of levels 1, 2 (uint32 or uint64); zero
                          // between tiles
   DBuf lv;               // [nlv*n*C] stored dense levels (double, or uint32 counts)
+  DBuf lv16;             // [n*C] 16-bit copy of the last stored level (16-bit layout)
   DBuf wl, wl_n;         // uint64 worklist [wl_cap], uint32 length
   unsigned wl_cap = 0;
   DBuf wl3, wl3_n;       // sources of the pushed level 3 (push3)

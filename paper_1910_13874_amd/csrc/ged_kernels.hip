@@ -67,14 +67,16 @@ __device__ __forceinline__ double load_in(const StepArgs &a, int u, int c) {
   }
 }
 
-// Columns 4k .. 4k+3 of row u of 16-bit level-2 counts (IN_CNT16), as 32-bit
-// values: the packed row's 8 bytes, or -- rows below the hub cut -- 16 bytes
-// of the 32-bit table (long-row segments, which sum in registers).
+// Columns 4k .. 4k+3 of row u of a 16-bit level (IN_CNT16), as 32-bit values:
+// the packed row's 8 bytes, or -- rows below the hub cut, or a unit holding
+// a marked value -- 16 bytes of the 32-bit level (long-row segments, which
+// sum in registers).
 template <int C>
 __device__ __forceinline__ uint4 load_quad16(const StepArgs &a, int u, int k) {
   const uint2 p = *reinterpret_cast<const uint2 *>(a.Xc16 + (size_t)u * C + 4 * k);
   uint4 r = make_uint4(p.x & 0xffffu, p.x >> 16, p.y & 0xffffu, p.y >> 16);
-  if (u < a.hub) r = *reinterpret_cast<const uint4 *>(a.Xc32 + (size_t)u * C + 4 * k);
+  const bool marked = r.x == kC16Hub || r.y == kC16Hub || r.z == kC16Hub || r.w == kC16Hub;
+  if (u < a.hub || marked) r = *reinterpret_cast<const uint4 *>(a.Xc32 + (size_t)u * C + 4 * k);
   return r;
 }
 
@@ -101,7 +103,8 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
   } else if constexpr (OUT == OUT_ZERO32) {
     return inS ? 0.0 : sum;  // the count; the caller also stores alpha * it
   } else if constexpr (OUT == OUT_TILE || OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
-                       OUT == OUT_TILE32 || OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16) {
+                       OUT == OUT_TILE32 || OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16 ||
+                       OUT == OUT_TILE32H) {
     return ((tbits >> c) & 1ull) ? a.inj[v] : y;
   } else if constexpr (OUT == OUT_GAIN || OUT == OUT_GAINCOMB) {
     if (c >= a.spec_from) return (inS || cand == c - a.spec_from) ? 0.0 : y;  // miss column
@@ -135,7 +138,7 @@ __device__ __forceinline__ double epilogue_v(const StepArgs &a, int v, int c, do
 // 32-bit.  LV32: the stored levels are unscaled 32-bit counts too, level l
 // weighted by q_slv * q_alpha^l; otherwise they hold h_i itself (weight 1).
 // C16: the level-2 counts are in the 16-bit layout (q_cnt2 is the hub table,
-// Xc16 the packed rows); both loads are issued, the one not needed at index 0.
+// q_pk2 the packed rows); both loads are issued, the one not needed at index 0.
 template <int C, bool C32, bool LV32, bool C16 = false>
 struct CombineIn {
   using CT = typename std::conditional<C32, uint32_t, uint64_t>::type;
@@ -149,9 +152,9 @@ struct CombineIn {
     const uint64_t o = (uint64_t)v * C + c;
     c1 = ld(static_cast<const CT *>(a.q_cnt1) + (o & a.q_m1));
     if constexpr (C16) {
-      const bool hb = v < a.hub;
+      const bool hb = v < a.q_hub2;
       const CT h = ld(static_cast<const CT *>(a.q_cnt2) + (hb ? o : 0));
-      const uint16_t pk = ld(a.Xc16 + (hb ? 0 : o));
+      const uint16_t pk = ld(a.q_pk2 + (hb ? 0 : o));
       c2 = hb ? h : (CT)pk;
     } else {
       c2 = ld(static_cast<const CT *>(a.q_cnt2) + (o & a.q_m2));
@@ -225,11 +228,11 @@ struct OutTraits {
   static constexpr bool combine = OUT == OUT_COMBINE || OUT == OUT_COMBINE32 ||
                                   OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16 ||
                                   gaincomb;  // y not stored
-  static constexpr bool store32 = OUT == OUT_TILE32 || OUT == OUT_GAIN32;
+  static constexpr bool store32 = OUT == OUT_TILE32 || OUT == OUT_GAIN32 || OUT == OUT_TILE32H;
   static constexpr bool tile = OUT == OUT_TILE || OUT == OUT_POOL || OUT == OUT_COMBINE ||
                                OUT == OUT_COMBINE32 || OUT == OUT_TILE32 ||
-                               OUT == OUT_COMBINE32L ||
-                               OUT == OUT_COMBINE16;  // per-vertex column bits (tmask)
+                               OUT == OUT_COMBINE32L || OUT == OUT_COMBINE16 ||
+                               OUT == OUT_TILE32H;  // per-vertex column bits (tmask)
 };
 
 // The count behind a gain combination's level value y (OUT_GAINCOMB32S): 0 on
@@ -534,6 +537,9 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restr
               __builtin_nontemporal_store((uint32_t)y, a.Y32 + (size_t)r * C + c);
             else
               a.Y32[(size_t)r * C + c] = (uint32_t)y;
+            if constexpr (OUT == OUT_TILE32H)
+              __builtin_nontemporal_store((uint16_t)(y > (double)kC16Max ? kC16Hub : (uint32_t)y),
+                                          a.Y16 + (size_t)r * C + c);
           } else {
             if constexpr (C >= 8)
               __builtin_nontemporal_store(y, a.Y + (size_t)r * C + c);
@@ -704,6 +710,8 @@ __device__ __forceinline__ void fixup_tail(const StepArgs &a, int l, int r, int 
     a.Y[(size_t)r * C + c] = a.alpha * y;
   } else if constexpr (OutTraits<OUT>::store32) {
     a.Y32[(size_t)r * C + c] = (uint32_t)y;
+    if constexpr (OUT == OUT_TILE32H)
+      a.Y16[(size_t)r * C + c] = (uint16_t)(y > (double)kC16Max ? kC16Hub : (uint32_t)y);
   } else {
     a.Y[(size_t)r * C + c] = y;
   }
@@ -866,6 +874,8 @@ static bool dispatch_multi(int in, int out, const Partition &p, const StepArgs &
     GED_CASE(IN_CNT32, OUT_COMBINE32L)
     if constexpr (C >= 4) {  // 16-bit level-2 counts of batch tiles
       GED_CASE(IN_CNT16, OUT_TILE32)
+      GED_CASE(IN_CNT16, OUT_TILE32H)
+      GED_CASE(IN_CNT32, OUT_TILE32H)
       GED_CASE(IN_CNT16, OUT_COMBINE16)
       GED_CASE(IN_CNT32, OUT_COMBINE16)
     }
@@ -916,9 +926,12 @@ static bool dispatch_c(int C, int in, int out, const Partition &p, const StepArg
 void launch_step(const Partition &p, const StepArgs &a, int in_mode, int out_mode,
                  hipStream_t st, hipEvent_t after_main) {
   if (a.C != p.C) throw HipError{GED_ERR_ARG, "step column count does not match partition"};
-  if ((in_mode == IN_CNT16 || out_mode == OUT_COMBINE16) &&
-      (a.C < 4 || a.w || !a.Xc16 || a.hub < 0 || a.hub >= a.n))
+  if (in_mode == IN_CNT16 && (a.C < 4 || a.w || !a.Xc16 || a.hub < 0 || a.hub >= a.n))
     throw HipError{GED_ERR_ARG, "16-bit counts need C >= 4, an unweighted graph and a cut below n"};
+  if (out_mode == OUT_COMBINE16 && (a.C < 4 || !a.q_pk2 || a.q_hub2 < 0 || a.q_hub2 >= a.n))
+    throw HipError{GED_ERR_ARG, "16-bit level-2 rows need C >= 4 and a cut below n"};
+  if (out_mode == OUT_TILE32H && !a.Y16)
+    throw HipError{GED_ERR_ARG, "no 16-bit output buffer"};
   const int units = gather_units(a.C, in_mode, a.w != nullptr);
   if (p.units != units)
     throw HipError{GED_ERR_ARG, "step gather width does not match partition"};

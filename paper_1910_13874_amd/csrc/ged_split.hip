@@ -673,8 +673,8 @@ void split_tables(ged_graph *g, SplitPlan &pl, hipStream_t st) {
 
 // Gather of the last (combining) dense level of a tile.
 static int final_in(const SplitPlan &pl) {
+  if (pl.c16_hub >= 0) return IN_CNT16;  // level 2, or the 16-bit copy of level a-1
   if (pl.lv32) return IN_CNT32;
-  if (pl.c16_hub >= 0 && pl.a == pl.s + 1) return IN_CNT16;
   if (pl.a == 1) return IN_TILEMASK;
   if (pl.a == pl.s + 1) return pl.c32 ? IN_CNT32 : IN_CNT;
   return IN_VEC;
@@ -849,6 +849,7 @@ void split_fit(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, size_t wl_n
     const void *old = w.lv.p;
     w.lv.ensure((pl.lv32 ? sizeof(uint32_t) : sizeof(double)) * nC * (size_t)pl.nlv);
     if (w.lv.p != old) w.lv_zero = false;
+    if (pl.c16_hub >= 0) w.lv16.ensure(sizeof(uint16_t) * nC);
   }
   if (pl.push3) {
     const size_t cap = push3_cap(g);
@@ -981,13 +982,18 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
   a.C = C;
   a.tmask = tmask;
   a.accum = 0;
-  // 16-bit level-2 counts: the level-3 gather reads them (IN_CNT16), and the
-  // combining step reads their rows (OUT_COMBINE16)
+  // 16-bit level-2 counts: the level-3 gather reads them (IN_CNT16), the
+  // combining step reads their rows (OUT_COMBINE16), and the last stored
+  // level gets a 16-bit copy (OUT_TILE32H) that the combining step gathers
   const bool c16 = pl.c16_hub >= 0;
+  const uint16_t *pk2 = nullptr;
   if (c16) {
+    pk2 = reinterpret_cast<const uint16_t *>(static_cast<const char *>(c2) +
+                                             c16_pk_offset(pl.c16_hub, C));
+    a.q_pk2 = pk2;
+    a.q_hub2 = pl.c16_hub;
     a.hub = pl.c16_hub;
-    a.Xc16 = reinterpret_cast<const uint16_t *>(static_cast<const char *>(c2) +
-                                                c16_pk_offset(pl.c16_hub, C));
+    a.Xc16 = pk2;
   }
   if (pl.lv32) {
     // unscaled 32-bit counts for levels s+1 .. a-1 (members: omega_i), then
@@ -997,17 +1003,26 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
     for (int i = pl.s + 1; i < pl.a; ++i) alpha_a *= alpha;
     for (int i = pl.s + 1; i <= pl.a; ++i) {
       a.Xc32 = i == pl.s + 1 ? static_cast<const uint32_t *>(c2) : lv32 + (size_t)(i - 2 - pl.s) * nC;
-      const int in = c16 && i == pl.s + 1 ? IN_CNT16 : IN_CNT32;
+      // level s+1 gathers the 16-bit level 2 (cut pl.c16_hub), the combining
+      // step the 16-bit copy of level a-1 (cut 0, marked values from lv32)
+      const bool g16 = c16 && (i == pl.s + 1 || i == pl.a);
+      if (c16 && i == pl.a && i > pl.s + 1) {
+        a.Xc16 = w.lv16.as<const uint16_t>();
+        a.hub = 0;
+      }
+      const int in = g16 ? IN_CNT16 : IN_CNT32;
       Partition &pi = in == IN_CNT16 ? step_partition(g, pl, C, IN_CNT16) : pn;
       if (i < pl.a) {
         a.alpha = 1.0;
         a.inj = om + (size_t)(i - 3) * n;
         a.Y32 = lv32 + (size_t)(i - 1 - pl.s) * nC;
+        const int out = c16 && i == pl.a - 1 ? OUT_TILE32H : OUT_TILE32;
+        a.Y16 = w.lv16.as<uint16_t>();
         if (pl.push3 && i == pl.s + 1) continue;  // pushed with the first levels
         if (profile)
-          run_step(g, pi, a, in, OUT_TILE32, st);
+          run_step(g, pi, a, in, out, st);
         else
-          launch_step(pi, a, in, OUT_TILE32, st);
+          launch_step(pi, a, in, out, st);
       } else {
         a.alpha = alpha_a;
         a.inj = T + (size_t)i * n;
@@ -1026,6 +1041,7 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
         a.q_alpha = alpha;
         a.q_nlv = pl.nlv;
         a.q_even = pl.even ? 1 : 0;
+        a.Y16 = nullptr;
         const int out = c16 ? OUT_COMBINE16 : OUT_COMBINE32L;
         if (profile)
           run_step(g, pi, a, in, out, st, c16 ? 0.75 + 0.5 * pl.nlv : 0.5 * (pl.s + pl.nlv));

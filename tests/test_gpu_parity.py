@@ -1011,11 +1011,12 @@ def test_batch_count16(ged, ell):
     table) is bit for bit the same, at tile widths 4, 8 and 32 (one, two and
     eight 4-column units per arc), with the row partition's long-row
     segments and, on a second handle, with source buckets forced on; sampled
-    columns equal the oracle to 1e-9.  ell* = 8 has one 32-bit stored level
-    (level 3 gathers the 16-bit level and is exact): bit for bit the same as
-    with the layout off.  ell* = 5 has none (the combining step gathers the
-    16-bit level, on a partition of twice the arcs per block): the same as
-    with it off up to the column sums' rounding."""
+    columns equal the oracle to 1e-9.  ell* = 8 has one stored level (level 3
+    gathers the 16-bit level 2 and also stores a 16-bit copy of itself, which
+    the combining step gathers, marked values from the 32-bit level); ell* =
+    5 has none (the combining step gathers the 16-bit level 2).  With the
+    layout off the combining step sums its rows in blocks of a quarter of the
+    arcs, so the scores agree to the column sums' rounding."""
     g = inputs.barabasi_albert(200000, 8, 5)
     alpha = oracle.default_alpha(g, None)
     B = oracle.comb_bound(g, alpha, ell, None)
@@ -1049,10 +1050,7 @@ def test_batch_count16(ged, ell):
                     assert used == hub
                 out.append(b)
             np.testing.assert_array_equal(out[2], out[1])
-            if ell == 8:
-                np.testing.assert_array_equal(out[1], out[0])
-            else:
-                assert max(rel(x, y) for x, y in zip(out[1], out[0])) <= 1e-14
+            assert max(rel(x, y) for x, y in zip(out[1], out[0])) <= 1e-14
             for j, c in ref.items():
                 assert rel(out[1][j], c) <= REL, (tile, buckets, j, out[1][j], c)
         with pytest.raises(ged.GedError):
@@ -1068,9 +1066,8 @@ def test_batch_count16_wide_rows(ged):
     put them, and then almost every row, in the 32-bit table.  Groups hold
     core vertices, an empty group and single members; tiles of 8 and 32
     columns; ell* = 5 and 8.  Scores equal the oracle to 1e-9, the two cuts
-    agree bit for bit, and with the layout off the batch agrees bit for bit
-    at ell* = 8 (to the column sums' rounding at 5); a cut below 600 is
-    refused."""
+    agree bit for bit, and with the layout off the batch agrees to the column
+    sums' rounding; a cut below 600 is refused."""
     from wide_prefix import wide_prefix_graph
     g = wide_prefix_graph()
     alpha = oracle.default_alpha(g, None)
@@ -1107,10 +1104,7 @@ def test_batch_count16_wide_rows(ged):
                 assert used == (-1 if hub in (-1, 0) else hub)
             np.testing.assert_array_equal(out[600], out[g.n - 1])
             np.testing.assert_array_equal(out[0], out[-1])
-            if ell == 8:
-                np.testing.assert_array_equal(out[600], out[-1])
-            else:
-                assert max(rel(x, y) for x, y in zip(out[600], out[-1]) if y) <= 1e-14
+            assert max(rel(x, y) for x, y in zip(out[600], out[-1]) if y) <= 1e-14
             for j, c in enumerate(ref):
                 if c == 0.0:
                     assert out[600][j] == 0.0

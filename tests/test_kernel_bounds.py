@@ -124,7 +124,7 @@ def check_step(rp, ci, n, C, pairs=False, cut_div=1, hub=None):
             j0 = j0 + 8 * lpc
 
 
-def check_quads(rp, ci, n, C, cut_div, hub):
+def check_quads(rp, ci, n, C, cut_div, hub, table_rows=None):
     """Index arithmetic of the 16-bit (IN_CNT16) gather on its own partition
     (C/4 eight-byte units per arc): row blocks stage every arc's packed
     8 bytes (elements u*C + 4k .. +3 of the packed rows, which cover every
@@ -133,7 +133,9 @@ def check_quads(rp, ci, n, C, cut_div, hub):
     block's arc; long-row segments load the packed unit and, for hub rows,
     16 bytes of the table (bucket blocks use the row blocks' formulas on the
     copied col_idx).  Also the byte extent of the layout against its
-    allocation and the pushes' 32-bit words."""
+    allocation and the pushes' 32-bit words.  table_rows = n: the 16-bit copy
+    of a stored level (cut 0), whose marked values any row may carry and
+    whose 32-bit level holds every row."""
     nnz = int(rp[-1])
     GU = C // 4
     blocks, segs, _ = partition(rp, C, GU, cut_div)
@@ -147,11 +149,13 @@ def check_quads(rp, ci, n, C, cut_div, hub):
         assert e16.min() >= 0 and (e16 + 3).max() < n * C and (e16 % 4 == 0).all()
         assert pk_off + 2 * ((e16 + 3).max() + 1) <= alloc
 
+    rows32 = hub if table_rows is None else table_rows
+
     def table(u, k_or_c, width):
-        hb = u < hub
+        hb = u < rows32
         if hb.any():
             e32 = u[hb] * C + k_or_c[hb] if np.ndim(k_or_c) else u[hb] * C + k_or_c
-            assert e32.min() >= 0 and (e32 + width - 1).max() < hub * C
+            assert e32.min() >= 0 and (e32 + width - 1).max() < rows32 * C
 
     for (r0, r1, p0, p1) in blocks:
         tot = (p1 - p0) * GU
@@ -230,6 +234,7 @@ def test_step_indices_in_bounds(g):
                 if C in (4, 8, 32):  # 16-bit gathers: one and two units per arc, and 8
                     for hub in sorted({0, g.n // 8, g.n - 1}):
                         check_quads(rp, ci, g.n, C, cut_div, hub)
+                    check_quads(rp, ci, g.n, C, cut_div, 0, table_rows=g.n)
 
 
 def wl_need(n, nnz, deg_sum):
