@@ -81,11 +81,18 @@ __device__ __forceinline__ uint4 load_quad16(const StepArgs &a, int u, int k) {
 }
 
 // The packed 8 bytes of columns 4k .. 4k+3 of row u as staged in LDS: the
-// row's four 16-bit counts, or kC16Hub in each for a row below the hub cut.
+// row's four 16-bit counts; for a row below the hub cut its 32-bit counts,
+// loaded with the other gathers, each staged as itself when it fits 16 bits
+// (most do: the cut is a bound) and as kC16Hub when it does not.
 template <int C>
 __device__ __forceinline__ uint2 load_pk16(const StepArgs &a, int u, int k) {
-  const uint2 p = *reinterpret_cast<const uint2 *>(a.Xc16 + (size_t)u * C + 4 * k);
-  return u < a.hub ? make_uint2(0xffffffffu, 0xffffffffu) : p;
+  uint2 p = *reinterpret_cast<const uint2 *>(a.Xc16 + (size_t)u * C + 4 * k);
+  if (u < a.hub) {
+    const uint4 h = *reinterpret_cast<const uint4 *>(a.Xc32 + (size_t)u * C + 4 * k);
+    auto m = [](uint32_t x) -> uint32_t { return x > kC16Max ? kC16Hub : x; };
+    p = make_uint2(m(h.x) | (m(h.y) << 16), m(h.z) | (m(h.w) << 16));
+  }
+  return p;
 }
 
 // Row epilogue given the row's membership bit (S), column bits (tile/pool
@@ -308,11 +315,14 @@ __device__ __forceinline__ void block_colsum_pairs(double v0, double v1, double 
 // arcs j0 + s, j0 + s + tpr, .. < j1 of column c: four independent partials
 // keep four LDS reads in flight, and integer sums are exact in any order, so
 // the result is the exact count (converted once; exact below 2^53).  Q4: the
-// partials are 32-bit (a block stages at most 2048 arcs of 16-bit values), a
-// staged kC16Hub stands for a row below the hub cut, and the loop only counts
-// those; a row that met any sums again with their 32-bit counts, fetched from
-// the table at the arc's source src[j] (branch-free main loop: no memory wait
-// inside it).
+// partials are 32-bit (a block stages at most 2048 arcs of 16-bit values); a
+// staged kC16Hub counts as 0 in the branch-free main loop, which only
+// counts them, and a row that met any adds their 32-bit counts from Xc32 at
+// the arc's source src[j].  With a cut (a.hub > 0) they can only be arcs
+// from rows below it, which -- rows list their sources in increasing order,
+// and those rows have the smallest ids -- come first in the row (and in
+// every lane's share of it), so only that prefix is walked; marked values
+// of a 16-bit copy (cut 0) may sit anywhere, so the row is scanned again.
 template <int C, bool Q4, class SV>
 __device__ __forceinline__ double sum_staged_counts(const StepArgs &a, const SV *vals, int j0,
                                                    int j1, int s, int tpr, int c,
@@ -320,6 +330,7 @@ __device__ __forceinline__ double sum_staged_counts(const StepArgs &a, const SV 
   using AT = typename std::conditional<Q4, uint32_t, uint64_t>::type;
   AT q0 = 0, q1 = 0, q2 = 0, q3 = 0;
   uint32_t nh = 0;
+  auto keep = [](uint32_t x) -> uint32_t { return (Q4 && x == kC16Hub) ? 0u : x; };
   int j = j0 + s;
   for (; j + 3 * tpr < j1; j += 4 * tpr) {
     const uint32_t x0 = vals[j * C + c], x1 = vals[(j + tpr) * C + c];
@@ -327,24 +338,28 @@ __device__ __forceinline__ double sum_staged_counts(const StepArgs &a, const SV 
     if constexpr (Q4)
       nh += (uint32_t)(x0 == kC16Hub) + (uint32_t)(x1 == kC16Hub) + (uint32_t)(x2 == kC16Hub) +
             (uint32_t)(x3 == kC16Hub);
-    q0 += x0;
-    q1 += x1;
-    q2 += x2;
-    q3 += x3;
+    q0 += keep(x0);
+    q1 += keep(x1);
+    q2 += keep(x2);
+    q3 += keep(x3);
   }
   for (; j < j1; j += tpr) {
     const uint32_t x = vals[j * C + c];
     if constexpr (Q4) nh += (uint32_t)(x == kC16Hub);
-    q0 += x;
+    q0 += keep(x);
   }
   uint64_t sum = (uint64_t)((q0 + q1) + (q2 + q3));
   if constexpr (Q4) {
     if (nh != 0) {
-      sum = 0;
-      for (j = j0 + s; j < j1; j += tpr) {
-        uint32_t x = vals[j * C + c];
-        if (x == kC16Hub) x = a.Xc32[(size_t)src[j] * C + c];
-        sum += x;
+      if (a.hub > 0) {
+        for (j = j0 + s; j < j1; j += tpr) {
+          const int u = src[j];
+          if (u >= a.hub) break;
+          if (vals[j * C + c] == kC16Hub) sum += a.Xc32[(size_t)u * C + c];
+        }
+      } else {
+        for (j = j0 + s; j < j1; j += tpr)
+          if (vals[j * C + c] == kC16Hub) sum += a.Xc32[(size_t)src[j] * C + c];
       }
     }
   }
