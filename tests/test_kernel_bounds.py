@@ -128,11 +128,12 @@ def check_quads(rp, ci, n, C, cut_div, hub, table_rows=None):
     """Index arithmetic of the 16-bit (IN_CNT16) gather on its own partition
     (C/4 eight-byte units per arc): row blocks stage every arc's packed
     8 bytes (elements u*C + 4k .. +3 of the packed rows, which cover every
-    row) as 16-bit LDS values, and the per-row sums fetch a hub row's 32-bit
-    count from the table at src*C + c, src read back from col_idx at the
-    block's arc; long-row segments load the packed unit and, for hub rows,
-    16 bytes of the table (bucket blocks use the row blocks' formulas on the
-    copied col_idx).  Also the byte extent of the layout against its
+    row) as 16-bit LDS values, loading rows below the cut from the 32-bit
+    table (16 bytes at u*C + 4k), and the per-row sums fetch a marked
+    value's 32-bit count at src*C + c, src read back from col_idx at the
+    block's arc; long-row segments load the packed unit and, for hub rows
+    or marked values, 16 bytes of the table (bucket blocks use the row
+    blocks' formulas on the copied col_idx).  Also the byte extent of the layout against its
     allocation and the pushes' 32-bit words.  table_rows = n: the 16-bit copy
     of a stored level (cut 0), whose marked values any row may carry and
     whose 32-bit level holds every row."""
@@ -168,6 +169,7 @@ def check_quads(rp, ci, n, C, cut_div, hub, table_rows=None):
             assert j.min() >= 0 and j.max() < max(1, nnz)
             u = ci[j] if tot > 0 else np.zeros_like(j)
             packed(u, f & (GU - 1))
+            table(u, 4 * (f & (GU - 1)), 4)  # rows below the cut: their 32-bit counts
             slot = f[f < tot]  # 8-byte slots of four 16-bit values
             assert slot.size == 0 or 4 * slot.max() + 3 < 4 * K_LDS
         if tot > 0:  # phase 2: 16-bit slot j*C + c; hub rows from the table
