@@ -1058,6 +1058,44 @@ def test_batch_count16(ged, ell):
         gg.close()
 
 
+def test_batch_count16_not_applicable(ged):
+    """Where the 16-bit level-2 layout does not apply -- a directed graph
+    (level-by-level chains), a weighted graph (no integer levels) and an
+    undirected graph at ell* = 4 (a = 2: level 2 is combined directly, no dense
+    level gathers it) -- the automatic and a forced cut both leave it off: the
+    batch reports no cut and equals the batch with the layout off bit for bit,
+    and sampled columns equal the oracle to 1e-9."""
+    gd = directed_graph()
+    gw = inputs.barabasi_albert(20000, 4, 33)
+    deg = gw.degrees.astype(np.float64)
+    rows = np.repeat(np.arange(gw.n), gw.degrees)
+    w = 1.0 / np.sqrt(deg[rows] * deg[gw.col_idx])
+    gb = inputs.barabasi_albert(20000, 8, 34)
+    a_b = oracle.default_alpha(gb, None)
+    eps_b = float(np.sqrt(oracle.comb_bound(gb, a_b, 4, None) * oracle.comb_bound(gb, a_b, 3, None)))
+    cases = [("directed", gd, None, oracle.default_alpha(gd, None), EPS),
+             ("weighted", gw, w, 0.5 / oracle.max_weighted_out_degree(gw, w), EPS),
+             ("ell4", gb, None, a_b, eps_b)]
+    for name, g, wt, alpha, eps in cases:
+        off, mem = inputs.groups(g.n, 24, 1, 50, 178)
+        gg = ged.GedGraph.from_graph(g, weights=wt)
+        gg.set_batch_tile(8)
+        out = []
+        for hub in (-1, 0, g.n - 1):
+            gg.set_count16(hub)
+            out.append(gg.score_batch(off, mem, alpha, eps))
+            assert gg.count16_hub() == -1, (name, hub)
+        say(f"[count16 n/a] {name}: n={g.n} nnz={g.nnz}")
+        np.testing.assert_array_equal(out[1], out[0])
+        np.testing.assert_array_equal(out[2], out[0])
+        for j in (0, 11, 23):
+            c, ell_o, _, _ = oracle.score(g, mem[off[j]:off[j + 1]], alpha, eps, w=wt)
+            if name == "ell4":
+                assert ell_o == 4
+            assert rel(out[0][j], c) <= REL, (name, j, out[0][j], c)
+        gg.close()
+
+
 def test_batch_count16_wide_rows(ged):
     """The 16-bit level-2 layout with members among the rows kept in 32 bits.
     The graph's 600 highest-degree vertices (a K_{300,300} core, omega_2 =
