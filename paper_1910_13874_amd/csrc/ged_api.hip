@@ -14,6 +14,7 @@
 #include <cstring>
 
 #include "ged_internal.h"
+#include "graph_build.h"
 
 namespace ged {
 
@@ -544,12 +545,6 @@ ged_graph::~ged_graph() {
 
 extern "C" const char *ged_last_error(void) { return g_err.c_str(); }
 
-static uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-  return z ^ (z >> 31);
-}
-
 static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
                        const double *weights, uint32_t flags, ged_graph **out) {
   if (!out) return fail(GED_ERR_ARG, "out is null");
@@ -562,112 +557,23 @@ static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int
   if (flags != GED_UNDIRECTED && flags != GED_DIRECTED)
     return fail(GED_ERR_ARG, "flags must be GED_UNDIRECTED or GED_DIRECTED (| GED_KEEP_ORDER)");
   if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(GED_ERR_GRAPH, "row_ptr ends mismatch");
-  std::vector<int64_t> outdeg((size_t)n, 0);
-  uint64_t h_fwd = 0, h_bwd = 0;
-  for (int64_t v = 0; v < n; ++v) {
-    if (row_ptr[v + 1] < row_ptr[v]) return fail(GED_ERR_GRAPH, "row_ptr decreases");
-    for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
-      const int32_t u = col_idx[j];
-      if (u < 0 || u >= n) return fail(GED_ERR_GRAPH, "col_idx out of range");
-      if (u == v) return fail(GED_ERR_GRAPH, "self-loop");
-      outdeg[u]++;
-      if (weights && !(weights[j] > 0.0 && weights[j] <= 1.0))
-        return fail(GED_ERR_GRAPH, "weights must be in (0, 1]");
-      if (flags == GED_UNDIRECTED) {
-        h_fwd += mix64(((uint64_t)u << 32) | (uint64_t)v);
-        h_bwd += mix64(((uint64_t)v << 32) | (uint64_t)u);
-        if (weights) {
-          uint64_t wb;
-          std::memcpy(&wb, &weights[j], sizeof(wb));
-          h_fwd += mix64((((uint64_t)u << 32) | (uint64_t)v) ^ mix64(wb));
-          h_bwd += mix64((((uint64_t)v << 32) | (uint64_t)u) ^ mix64(wb));
-        }
-      }
-    }
-  }
-  if (flags == GED_UNDIRECTED) {
-    for (int64_t v = 0; v < n; ++v)
-      if (outdeg[v] != row_ptr[v + 1] - row_ptr[v])
-        return fail(GED_ERR_GRAPH, "GED_UNDIRECTED graph is not symmetric");
-    if (h_fwd != h_bwd) return fail(GED_ERR_GRAPH, "GED_UNDIRECTED graph is not symmetric");
-  }
+  // validation, internal order and sorted in/out rows on the host's threads
+  HostCsr hc;
+  if (const char *m = build_host_csr(n, nnz, row_ptr, col_idx, weights, flags == GED_UNDIRECTED,
+                                     keep_order, 0, hc))
+    return fail(GED_ERR_GRAPH, m);
   auto g = std::make_unique<ged_graph>();
   g->n = n;
   g->nnz = nnz;
   g->flags = flags;
   g->weighted = weights != nullptr;
-  int64_t md = 0;
-  for (int64_t v = 0; v < n; ++v) md = std::max(md, outdeg[v]);
-  g->max_deg = (int32_t)md;
-  if (weights) {
-    // maximum weighted out-degree: sum of the weights of the arcs leaving v
-    std::vector<double> wout((size_t)n, 0.0);
-    for (int64_t v = 0; v < n; ++v)
-      for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) wout[col_idx[j]] += weights[j];
-    double m = 0.0;
-    for (double x : wout) m = std::max(m, x);
-    g->max_wdeg = m;
-  }
-  // ---- internal vertex order: stable counting sort by decreasing out-degree
-  const int N = (int)n;
-  g->new_id.resize((size_t)N);
-  g->old_id.resize((size_t)N);
-  if (keep_order) {
-    for (int v = 0; v < N; ++v) g->new_id[v] = g->old_id[v] = v;
-  } else {
-    std::vector<int64_t> cnt((size_t)md + 2, 0);
-    for (int v = 0; v < N; ++v) cnt[(size_t)(md - outdeg[v]) + 1]++;
-    for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
-    for (int v = 0; v < N; ++v) {
-      const int pos = (int)cnt[(size_t)(md - outdeg[v])]++;
-      g->new_id[v] = pos;
-      g->old_id[pos] = v;
-    }
-  }
-  // ---- CSR in internal ids with sorted rows, built by two scatter passes:
-  // scattering the arcs of rows taken in increasing order into buckets keyed
-  // by the other endpoint yields the transposed matrix with sorted rows.
-  // out-rows (reverse graph): row nu lists nv for every arc u -> v.
-  std::vector<int> orp((size_t)N + 1, 0), oci((size_t)std::max<int64_t>(1, nnz));
-  std::vector<double> ow(weights ? (size_t)std::max<int64_t>(1, nnz) : 0);
-  for (int v = 0; v < N; ++v) orp[(size_t)g->new_id[v] + 1] = (int)outdeg[v];
-  for (int v = 0; v < N; ++v) orp[(size_t)v + 1] += orp[v];
-  {
-    std::vector<int> pos(orp.begin(), orp.end() - 1);
-    for (int nv = 0; nv < N; ++nv) {
-      const int v = g->old_id[nv];
-      for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
-        const int nu = g->new_id[col_idx[j]];
-        const int q = pos[nu]++;
-        oci[q] = nv;
-        if (weights) ow[q] = weights[j];
-      }
-    }
-  }
-  // in-rows: row nv lists nu for every arc u -> v (scatter the out-rows back)
-  std::vector<int> irp((size_t)N + 1, 0), ici((size_t)std::max<int64_t>(1, nnz));
-  std::vector<double> iw(weights ? (size_t)std::max<int64_t>(1, nnz) : 0);
-  for (int nv = 0; nv < N; ++nv) {
-    const int v = g->old_id[nv];
-    irp[(size_t)nv + 1] = (int)(row_ptr[v + 1] - row_ptr[v]);
-  }
-  for (int v = 0; v < N; ++v) irp[(size_t)v + 1] += irp[v];
-  {
-    std::vector<int> pos(irp.begin(), irp.end() - 1);
-    for (int nu = 0; nu < N; ++nu)
-      for (int q = orp[nu]; q < orp[nu + 1]; ++q) {
-        const int r = pos[oci[q]]++;
-        ici[r] = nu;
-        if (weights) iw[r] = ow[q];
-      }
-  }
-  g->simple = true;
-  for (int v = 0; v < N && g->simple; ++v)
-    for (int r = irp[v] + 1; r < irp[v + 1]; ++r)
-      if (ici[r] == ici[r - 1]) {
-        g->simple = false;
-        break;
-      }
+  g->max_deg = hc.max_deg;
+  if (weights) g->max_wdeg = hc.max_wdeg;
+  g->simple = hc.simple;
+  g->new_id = std::move(hc.new_id);
+  g->old_id = std::move(hc.old_id);
+  const std::vector<int> &irp = hc.irp, &ici = hc.ici, &orp = hc.orp, &oci = hc.oci;
+  const std::vector<double> &iw = hc.iw, &ow = hc.ow;
   return guarded([&]() -> int {
     GED_HIP(hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking));
     g->stream = g->own_stream;
