@@ -21,6 +21,16 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                       "(the GED-Walk path has no CPU fallback)")
 
+# The library links libamdhip64.so.7, and PyTorch-ROCm ships its own copy of
+# the HIP runtime under that soname.  With torch loaded first the library binds
+# to torch's copy and the process holds one HIP runtime; loaded first, it would
+# bring in the system copy and torch would then add its own, and two runtimes
+# in one process do not share the device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 P_I64 = ctypes.POINTER(ctypes.c_int64)

@@ -1,5 +1,6 @@
 """CPU checks of the boundary: the HIP library loads without a GPU and exports
 every function include/ged.h declares; bench.py refuses more than one GPU."""
+import ast
 import ctypes
 import os
 import re
@@ -34,6 +35,23 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
     exported = set(re.findall(r"\bT (ged_[a-z0-9_]+)$", out, flags=re.M))
     assert set(declared_functions()) <= exported
+
+
+def test_binding_loads_one_hip_runtime():
+    """Importing the binding alone (torch not imported yet) leaves one HIP
+    runtime in the process: torch's copy, which the library binds to."""
+    code = ("import re; from paper_1910_13874_amd import ged; "
+            "maps = open('/proc/self/maps').read(); "
+            "print(sorted(set(re.findall(r'\\S*libamdhip64\\S*', maps))))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         check=True).stdout.strip()
+    paths = ast.literal_eval(out)
+    assert len(paths) == 1, paths
+    try:
+        import torch
+    except ImportError:
+        return
+    assert paths[0].startswith(os.path.dirname(torch.__file__)), paths
 
 
 def test_error_paths_without_gpu_work():
