@@ -72,7 +72,9 @@ typedef struct ged_graph ged_graph;
  * (GED_ERR_GRAPH): row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz,
  * 0 <= col_idx < n, no self-loops, nnz < 2^31; for GED_UNDIRECTED the arc set
  * must be symmetric.  Duplicate arcs count as parallel edges.
- * n must be in [1, 2^31 - 1].
+ * n must be in [1, 2^31 - 2].  The host side of the construction (validation,
+ * the vertex order, sorted rows) runs on up to 16 host threads for graphs of
+ * 2^20 arcs and more; the handle is the same at any thread count.
  */
 int ged_graph_create(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
                      uint32_t flags, ged_graph **out);
