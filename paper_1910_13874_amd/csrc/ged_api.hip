@@ -559,9 +559,13 @@ static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int
   if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(GED_ERR_GRAPH, "row_ptr ends mismatch");
   // validation, internal order and sorted in/out rows on the host's threads
   HostCsr hc;
-  if (const char *m = build_host_csr(n, nnz, row_ptr, col_idx, weights, flags == GED_UNDIRECTED,
-                                     keep_order, 0, hc))
-    return fail(GED_ERR_GRAPH, m);
+  const int brc = guarded([&]() -> int {
+    if (const char *m = build_host_csr(n, nnz, row_ptr, col_idx, weights,
+                                       flags == GED_UNDIRECTED, keep_order, 0, hc))
+      return fail(GED_ERR_GRAPH, m);
+    return GED_OK;
+  });
+  if (brc != GED_OK) return brc;
   auto g = std::make_unique<ged_graph>();
   g->n = n;
   g->nnz = nnz;

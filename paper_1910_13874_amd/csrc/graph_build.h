@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <exception>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -44,18 +46,38 @@ inline uint64_t mix64(uint64_t z) {  // splitmix64 finaliser (Steele et al.)
   return z ^ (z >> 31);
 }
 
-// Run f(t) for t in [0, T): on T - 1 new threads and the caller's.
+// Run f(t) for t in [0, T): on T - 1 new threads and the caller's.  Parts
+// whose thread cannot be started run on the caller's; an exception thrown by
+// any part (a failed allocation) is rethrown here once every thread has
+// joined.
 template <class F>
 void run_threads(int T, F &&f) {
   if (T <= 1) {
     f(0);
     return;
   }
+  std::vector<std::exception_ptr> err((size_t)T);
+  auto part = [&f, &err](int t) {
+    try {
+      f(t);
+    } catch (...) {
+      err[(size_t)t] = std::current_exception();
+    }
+  };
   std::vector<std::thread> th;
+  std::vector<int> here{0};
   th.reserve((size_t)T - 1);
-  for (int t = 1; t < T; ++t) th.emplace_back([&f, t] { f(t); });
-  f(0);
+  for (int t = 1; t < T; ++t) {
+    try {
+      th.emplace_back(part, t);
+    } catch (const std::system_error &) {
+      here.push_back(t);
+    }
+  }
+  for (int t : here) part(t);
   for (auto &x : th) x.join();
+  for (const auto &e : err)
+    if (e) std::rethrow_exception(e);
 }
 
 // Row range bounds [b[t], b[t+1]) splitting rows 0..N-1 of the monotone

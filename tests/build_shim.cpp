@@ -32,3 +32,20 @@ extern "C" const char *gb_build(int64_t n, int64_t nnz, const int64_t *rp, const
 }
 
 extern "C" int gb_threads(int64_t n, int64_t nnz) { return ged::build_threads(n, nnz); }
+
+// run_threads with part `bad` throwing: 1 if the exception reaches the caller
+// after every other part ran, else 0.
+extern "C" int gb_threads_rethrow(int T, int bad) {
+  std::vector<int> ran((size_t)T, 0);
+  try {
+    ged::build_detail::run_threads(T, [&](int t) {
+      if (t == bad) throw std::bad_alloc();
+      ran[(size_t)t] = 1;
+    });
+  } catch (const std::bad_alloc &) {
+    for (int t = 0; t < T; ++t)
+      if (t != bad && !ran[(size_t)t]) return 0;
+    return 1;
+  }
+  return 0;
+}

@@ -32,6 +32,8 @@ def lib(tmp_path_factory):
                            F64P, I32P, F64P, I32P]
     L.gb_threads.restype = ctypes.c_int
     L.gb_threads.argtypes = [ctypes.c_int64, ctypes.c_int64]
+    L.gb_threads_rethrow.restype = ctypes.c_int
+    L.gb_threads_rethrow.argtypes = [ctypes.c_int, ctypes.c_int]
     return L
 
 
@@ -205,3 +207,11 @@ def test_build_errors(lib):
     c4[rp[row]] = (c4[rp[row]] + 1) % n if (c4[rp[row]] + 1) % n != row else (c4[rp[row]] + 2) % n
     expect("GED_UNDIRECTED graph is not symmetric", rp, c4)
     assert isinstance(build(lib, n, rp, c4, None, False, False, 3), dict)  # fine as directed
+
+
+def test_thread_failure_reaches_the_caller(lib):
+    """A part that throws (a failed host allocation) does not end the process:
+    the exception reaches the builder's caller, which turns it into an error
+    code, after the other parts have run."""
+    for T, bad in ((1, 0), (4, 0), (4, 3), (16, 7)):
+        assert lib.gb_threads_rethrow(T, bad) == 1, (T, bad)
