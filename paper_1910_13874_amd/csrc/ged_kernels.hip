@@ -384,8 +384,21 @@ __device__ __forceinline__ void block_colsum_quads(const double (&v)[4], double 
   if (t < C) out[t] = (red[t] + red[C + t]) + (red[2 * C + t] + red[3 * C + t]);
 }
 
+// Waves per SIMD the register allocation must allow (1: the compiler's
+// choice).  The combining steps over 16-bit counts would take 68-70 VGPRs,
+// i.e. seven waves; held to eight (64 VGPRs, no spill) they ran the 4,096-group
+// BA-2M batch 7 % faster, the LDS of eight resident blocks of four waves
+// fitting a CU.  The bound is not set on the other steps: those within 64
+// VGPRs already are scheduled differently under it (the FP64 gain step lost
+// 2 %), and the larger ones would spill.
 template <int C, int IN, int OUT, bool WGT>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs a, const int4 *__restrict__ blocks,
+constexpr int step_waves() {
+  return !WGT && IN == IN_CNT16 && OUT == OUT_COMBINE16 ? 8 : 1;
+}
+
+template <int C, int IN, int OUT, bool WGT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves<C, IN, OUT, WGT>())))
+void k_step(StepArgs a, const int4 *__restrict__ blocks,
                                                  const int4 *__restrict__ segs, int n_blocks) {
   constexpr bool M1 = OUT == OUT_INJ || OUT == OUT_ZERO || OUT == OUT_ZERO32 ||
                       OutTraits<OUT>::gain;
