@@ -293,6 +293,10 @@ struct StepArgs {
   const uint16_t *Xc16 = nullptr;
   int hub = 0;
   uint16_t *Y16 = nullptr;         // [n*C] (OUT_TILE32H)
+  // OUT_TILE32H: 1 = Y32 receives only the counts above kC16Max (those its
+  // 16-bit copy marks); set when the level is the only stored one, which the
+  // combining step then reads through the copy (OUT_COMBINE16, q_nlv == 1)
+  int y32_marked = 0;
   // OUT_COMBINE16: the level-2 rows in the 16-bit layout (table q_cnt2, packed
   // rows q_pk2, cut q_hub2)
   const uint16_t *q_pk2 = nullptr;

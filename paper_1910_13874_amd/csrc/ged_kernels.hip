@@ -68,15 +68,24 @@ __device__ __forceinline__ double load_in(const StepArgs &a, int u, int c) {
 }
 
 // Columns 4k .. 4k+3 of row u of a 16-bit level (IN_CNT16), as 32-bit values:
-// the packed row's 8 bytes, or -- rows below the hub cut, or a unit holding
-// a marked value -- 16 bytes of the 32-bit level (long-row segments, which
-// sum in registers).
+// the packed row's 8 bytes, with -- rows below the hub cut, or the marked
+// values of a unit holding any -- the counts from 16 bytes of the 32-bit level
+// (long-row segments, which sum in registers).
 template <int C>
 __device__ __forceinline__ uint4 load_quad16(const StepArgs &a, int u, int k) {
   const uint2 p = *reinterpret_cast<const uint2 *>(a.Xc16 + (size_t)u * C + 4 * k);
   uint4 r = make_uint4(p.x & 0xffffu, p.x >> 16, p.y & 0xffffu, p.y >> 16);
   const bool marked = r.x == kC16Hub || r.y == kC16Hub || r.z == kC16Hub || r.w == kC16Hub;
-  if (u < a.hub || marked) r = *reinterpret_cast<const uint4 *>(a.Xc32 + (size_t)u * C + 4 * k);
+  if (u < a.hub || marked) {
+    // rows below the cut: every count; otherwise only the marked ones (the
+    // 32-bit level may hold nothing else, see y32_marked)
+    const uint4 h = *reinterpret_cast<const uint4 *>(a.Xc32 + (size_t)u * C + 4 * k);
+    const bool all = u < a.hub;
+    r.x = all || r.x == kC16Hub ? h.x : r.x;
+    r.y = all || r.y == kC16Hub ? h.y : r.y;
+    r.z = all || r.z == kC16Hub ? h.z : r.z;
+    r.w = all || r.w == kC16Hub ? h.w : r.w;
+  }
   return r;
 }
 
@@ -152,6 +161,7 @@ struct CombineIn {
   using LT = typename std::conditional<LV32, uint32_t, double>::type;
   CT c1 = 0, c2 = 0;
   LT lv0 = 0;
+  uint16_t h0 = 0;  // C16 with one stored level: that level's 16-bit copy
   double trv = 0.0, ta = 0.0;
   // Wide tiles stream these rows once: nontemporal loads keep them from
   // displacing the gathered vector in the caches.
@@ -166,7 +176,15 @@ struct CombineIn {
     } else {
       c2 = ld(static_cast<const CT *>(a.q_cnt2) + (o & a.q_m2));
     }
-    lv0 = ld(static_cast<const LT *>(a.q_lv) + (o & a.q_mlv));
+    if constexpr (C16) {
+      // one stored level: its 16-bit copy (the gathered Xc16) stands in for it,
+      // and only its marked values are read from the 32-bit level (in q)
+      const bool cp = a.q_nlv == 1;
+      h0 = ld(a.Xc16 + (cp ? o : 0));
+      lv0 = ld(static_cast<const LT *>(a.q_lv) + (cp ? 0 : (o & a.q_mlv)));
+    } else {
+      lv0 = ld(static_cast<const LT *>(a.q_lv) + (o & a.q_mlv));
+    }
     trv = a.tr[v];
     ta = a.inj[v];
   }
@@ -180,9 +198,12 @@ struct CombineIn {
   // sum_{i<a} h_i(v) for column c (levels beyond the first stored one are
   // loaded here; there are none unless ell > 8)
   __device__ __forceinline__ double q(const StepArgs &a, int v, int c) const {
-    double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * (double)lv0;
     const LT *lv = static_cast<const LT *>(a.q_lv);
     const size_t o = (size_t)v * C + c, ls = (size_t)a.n * C;
+    LT l0 = lv0;
+    if constexpr (C16)
+      if (a.q_nlv == 1) l0 = h0 != kC16Hub ? (LT)h0 : lv[o];
+    double s = (a.q_s1 * (double)c1 + a.q_s2 * (double)c2) + a.q_slv * (double)l0;
     double w = a.q_slv;
     int l = 1;
     for (; l + 3 < a.q_nlv; l += 4) {  // four loads in flight, added in level order
@@ -561,10 +582,12 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
             a.Y32[(size_t)r * C + c] = (uint32_t)y;
             a.Y[(size_t)r * C + c] = a.alpha * y;
           } else if constexpr (OutTraits<OUT>::store32) {
-            if constexpr (C >= 8)
-              __builtin_nontemporal_store((uint32_t)y, a.Y32 + (size_t)r * C + c);
-            else
-              a.Y32[(size_t)r * C + c] = (uint32_t)y;
+            if (OUT != OUT_TILE32H || !a.y32_marked || y > (double)kC16Max) {
+              if constexpr (C >= 8)
+                __builtin_nontemporal_store((uint32_t)y, a.Y32 + (size_t)r * C + c);
+              else
+                a.Y32[(size_t)r * C + c] = (uint32_t)y;
+            }
             if constexpr (OUT == OUT_TILE32H)
               __builtin_nontemporal_store((uint16_t)(y > (double)kC16Max ? kC16Hub : (uint32_t)y),
                                           a.Y16 + (size_t)r * C + c);
@@ -737,7 +760,8 @@ __device__ __forceinline__ void fixup_tail(const StepArgs &a, int l, int r, int 
     a.Y32[(size_t)r * C + c] = (uint32_t)y;
     a.Y[(size_t)r * C + c] = a.alpha * y;
   } else if constexpr (OutTraits<OUT>::store32) {
-    a.Y32[(size_t)r * C + c] = (uint32_t)y;
+    if (OUT != OUT_TILE32H || !a.y32_marked || y > (double)kC16Max)
+      a.Y32[(size_t)r * C + c] = (uint32_t)y;
     if constexpr (OUT == OUT_TILE32H)
       a.Y16[(size_t)r * C + c] = (uint16_t)(y > (double)kC16Max ? kC16Hub : (uint32_t)y);
   } else {

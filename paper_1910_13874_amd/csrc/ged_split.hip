@@ -1018,6 +1018,8 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
         a.Y32 = lv32 + (size_t)(i - 1 - pl.s) * nC;
         const int out = c16 && i == pl.a - 1 ? OUT_TILE32H : OUT_TILE32;
         a.Y16 = w.lv16.as<uint16_t>();
+        // the only stored level: the combining step reads it through the copy
+        a.y32_marked = out == OUT_TILE32H && pl.nlv == 1 ? 1 : 0;
         if (pl.push3 && i == pl.s + 1) continue;  // pushed with the first levels
         if (profile)
           run_step(g, pi, a, in, out, st);
@@ -1042,6 +1044,7 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
         a.q_nlv = pl.nlv;
         a.q_even = pl.even ? 1 : 0;
         a.Y16 = nullptr;
+        a.y32_marked = 0;
         const int out = c16 ? OUT_COMBINE16 : OUT_COMBINE32L;
         if (profile)
           run_step(g, pi, a, in, out, st, c16 ? 0.75 + 0.5 * pl.nlv : 0.5 * (pl.s + pl.nlv));
