@@ -232,8 +232,10 @@ void run_step(ged_graph *g, const Partition &p, const StepArgs &a, int in, int o
   hipEvent_t e0 = prof_event(g), e1 = prof_event(g);
   GED_HIP(hipEventRecord(e0, st));
   launch_step(p, a, in, out, st, e1);
-  g->prof.recs.push_back({e0, e1, a.C, algo_bytes(g, a.C, in, out, extra_rows),
-                          (double)g->nnz * a.C, in * kKindBase + out});
+  double bytes = algo_bytes(g, a.C, in, out, extra_rows);
+  if (out == OUT_TILE32H && a.y32_marked)
+    bytes -= 4.0 * (double)g->n * a.C;  // Y32 only for the counts the copy marks
+  g->prof.recs.push_back({e0, e1, a.C, bytes, (double)g->nnz * a.C, in * kKindBase + out});
 }
 
 // -------------------------------------------------------- precomputation --

@@ -1047,7 +1047,8 @@ void split_dense(ged_graph *g, SplitWs &w, const SplitPlan &pl, int C, const uin
         a.y32_marked = 0;
         const int out = c16 ? OUT_COMBINE16 : OUT_COMBINE32L;
         if (profile)
-          run_step(g, pi, a, in, out, st, c16 ? 0.75 + 0.5 * pl.nlv : 0.5 * (pl.s + pl.nlv));
+          run_step(g, pi, a, in, out, st,
+                   c16 ? 0.75 + (pl.nlv == 1 ? 0.25 : 0.5 * pl.nlv) : 0.5 * (pl.s + pl.nlv));
         else
           launch_step(pi, a, in, out, st);
       }
