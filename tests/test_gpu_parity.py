@@ -1058,6 +1058,47 @@ def test_batch_count16(ged, ell):
         gg.close()
 
 
+@pytest.mark.parametrize("ell", [8, 9])
+def test_batch_count16_stored_levels(ged, ell):
+    """The 16-bit level-2 layout with one and with two stored levels.  On
+    G(n, M) with n = 200,000 and average degree 10 every omega_2 fits 16
+    bits (the library's cut is 0: all rows packed) and the deeper levels stay
+    32-bit counts.  ell* = 8: level 3 is the only stored level, so its 32-bit
+    counts are kept only where its 16-bit copy marks them and the combining
+    step reads the copy; ell* = 9: levels 3 and 4 are stored, both in full,
+    and the combining step gathers the copy of level 4.  Bit-identical among
+    the cuts (0 and n/4), equal to the 32-bit layout to the column sums'
+    rounding, sampled columns equal to the oracle to 1e-9, at tile widths 8
+    and 64."""
+    g = inputs.erdos_renyi(200000, 1000000, 9)
+    alpha = oracle.default_alpha(g, None)
+    B = oracle.comb_bound(g, alpha, ell, None)
+    eps = float(np.sqrt(B * oracle.comb_bound(g, alpha, ell - 1, None)))
+    G = 72
+    off, mem = inputs.groups(g.n, G, 1, 200, 179)
+    say(f"[count16 levels] n={g.n} nnz={g.nnz} ell*={ell} eps={eps:.3e}")
+    ref = {}
+    for j in (0, 35, G - 1):
+        c, ell_o, _, _ = oracle.score(g, mem[off[j]:off[j + 1]], alpha, eps)
+        assert ell_o == ell
+        ref[j] = c
+    gg = ged.GedGraph.from_graph(g)
+    for tile in (8, 64):
+        gg.set_batch_tile(tile)
+        out = []
+        for hub in (-1, 0, g.n // 4):
+            gg.set_count16(hub)
+            out.append(gg.score_batch(off, mem, alpha, eps))
+            used = gg.count16_hub()
+            say(f"  tile={tile} setting={hub}: cut {used}")
+            assert used == (hub if hub != 0 else 0), (tile, hub, used)
+        np.testing.assert_array_equal(out[2], out[1])
+        assert max(rel(x, y) for x, y in zip(out[1], out[0])) <= 1e-14
+        for j, c in ref.items():
+            assert rel(out[1][j], c) <= REL, (tile, j, out[1][j], c)
+    gg.close()
+
+
 def test_batch_count16_not_applicable(ged):
     """Where the 16-bit level-2 layout does not apply -- a directed graph
     (level-by-level chains), a weighted graph (no integer levels) and an
