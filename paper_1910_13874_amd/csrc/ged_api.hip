@@ -118,6 +118,7 @@ StepArgs base_args(ged_graph *g, bool reverse) {
   a.ci = (reverse ? g->ci_r : g->ci).as<const int>();
   a.w = g->weighted ? (reverse ? g->w_r : g->w).as<const double>() : nullptr;
   a.n = (int)g->n;
+  a.hc_rows = reverse ? 0 : g->hc_rows;
   return a;
 }
 
@@ -578,6 +579,14 @@ static int create_impl(int64_t n, int64_t nnz, const int64_t *row_ptr, const int
   g->simple = hc.simple;
   g->new_id = std::move(hc.new_id);
   g->old_id = std::move(hc.old_id);
+  {
+    // the LDS copy of the first rows pays where they are the sources of a
+    // large share of the arcs (skewed degrees, stored by decreasing degree)
+    const int h = (int)std::min<int64_t>(kHubRows, n);
+    if (flags == GED_UNDIRECTED && !weights && nnz > 0 &&
+        (int64_t)hc.irp[(size_t)h] * kHubShareDiv >= nnz)
+      g->hc_rows = h;
+  }
   const std::vector<int> &irp = hc.irp, &ici = hc.ici, &orp = hc.orp, &oci = hc.oci;
   const std::vector<double> &iw = hc.iw, &ow = hc.ow;
   return guarded([&]() -> int {

@@ -152,6 +152,12 @@ constexpr int kLdsDoubles = 2048;      // LDS staging per block (16 KiB)
 // C = 16.)
 __host__ __device__ constexpr int lds_values(int) { return kLdsDoubles; }
 constexpr int kRowsPerBlock = 255;     // max rows of one row block (row_ptr slice: 1 load per thread)
+// Single-column steps over 32-bit counts keep the counts of the first
+// kHubRows vertices (the highest degrees under the library's order) in LDS,
+// loaded once per row block, when those rows are the sources of at least
+// 1/kHubShareDiv of the arcs (StepArgs::hc_rows).
+constexpr int kHubRows = 2048;
+constexpr int kHubShareDiv = 10;
 constexpr int kSegDoubles = 8192;      // nnz*C handled by one long-row segment
 
 // Row partition for a step with C columns: row blocks of consecutive short
@@ -297,6 +303,9 @@ struct StepArgs {
   // 16-bit copy marks); set when the level is the only stored one, which the
   // combining step then reads through the copy (OUT_COMBINE16, q_nlv == 1)
   int y32_marked = 0;
+  // C = 1 steps over 32-bit counts (IN_CNT32): rows [0, hc_rows) of Xc32 are
+  // read from an LDS copy (0: none)
+  int hc_rows = 0;
   // OUT_COMBINE16: the level-2 rows in the 16-bit layout (table q_cnt2, packed
   // rows q_pk2, cut q_hub2)
   const uint16_t *q_pk2 = nullptr;
@@ -567,6 +576,7 @@ struct ged_graph {
   int32_t count16 = 0;
   int c16_least_hub = -1;       // 1 + the last vertex with omega_2 > kC16Max (-1: not known)
   int c16_used = -1;            // hub cut of the last batch's tiles (-1: 32-bit counts)
+  int hc_rows = 0;              // rows of the LDS copy in C = 1 count steps (kHubRows or 0)
   // registered with a server at (served_alpha, served_eps): other values,
   // invalidation and a change of tail bound are refused until it is destroyed
   bool served = false;

@@ -438,8 +438,11 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
   constexpr int GU = Q4 ? C / 4 : CU;        // gather units per arc
   constexpr int RT = (kRowsPerBlock + kBlock) / kBlock;  // row_ptr entries per thread
   constexpr int RB = (kRowsPerBlock + kBlock - 1) / kBlock;  // rows per thread (masks)
-  using SV = typename std::conditional<Q4, uint16_t,
-                                       typename std::conditional<NP, uint32_t, double>::type>::type;
+  // HC: a single column of 32-bit counts; rows below hc_rows are read from
+  // an LDS copy filled once per row block, and values are staged as 32 bits
+  constexpr bool HC = C == 1 && IN == IN_CNT32 && !WGT;
+  using SV = typename std::conditional<
+      Q4, uint16_t, typename std::conditional<NP || HC, uint32_t, double>::type>::type;
   // per-row column bits: the columns of a tile of C <= 32 fit 32 bits
   using TW = typename std::conditional<(C <= 32), uint32_t, uint64_t>::type;
   // LDS is what bounds the resident blocks (latency-bound gathers want as
@@ -448,6 +451,7 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
   __shared__ alignas(16) SV vals[(Q4 ? 4 : NP ? 2 : 1) * LV];
   double *const red = reinterpret_cast<double *>(vals);  // (kBlock / 64) * C doubles
   __shared__ int rps[kRowsPerBlock + 1];
+  __shared__ uint32_t hubv[HC ? kHubRows : 1];
   __shared__ uint32_t mw[M1 ? kRowsPerBlock / 32 + 2 : 1];
   __shared__ TW tmw[TM ? kRowsPerBlock : 1];
   __shared__ int cw[CA ? kRowsPerBlock : 1];
@@ -473,6 +477,14 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
       u[q] = __builtin_nontemporal_load(a.ci + min(jlo + (t + q * kBlock) / GU, jmax));
       if (tot == 0) u[q] = 0;
     }
+    // HC: the first rows' counts, requested right behind the col_idx stream
+    // (unconditional loads of clamped rows; unused when hc_rows is 0)
+    uint32_t hv[HC ? kHubRows / kBlock : 1];
+    if constexpr (HC) {
+#pragma unroll
+      for (int q = 0; q < kHubRows / kBlock; ++q)
+        hv[q] = a.Xc32[min(t + q * kBlock, max(a.hc_rows - 1, 0))];
+    }
     int rv[RT];
 #pragma unroll
     for (int k = 0; k < RT; ++k) rv[k] = a.rp[r0 + min(t + k * kBlock, nrows)];
@@ -496,6 +508,13 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
     const int rl0 = (t / tpr) / C;
     CombineFor<C, OUT> pf;
     if constexpr (CB) pf.load(a, r0 + min(rl0, nrows - 1), (t / tpr) & (C - 1));
+    if constexpr (HC) {
+      if (a.hc_rows > 0) {  // uniform: the copy of the first rows is in place
+#pragma unroll
+        for (int q = 0; q < kHubRows / kBlock; ++q) hubv[t + q * kBlock] = hv[q];
+        __syncthreads();
+      }
+    }
     double v[NP || Q4 ? 1 : PT];
     uint2 v2[NP || Q4 ? PT : 1];
 #pragma unroll
@@ -505,6 +524,13 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
       } else if constexpr (NP) {
         v2[q] = *reinterpret_cast<const uint2 *>(a.Xc32 + (size_t)u[q] * C +
                                                  2 * ((t + q * kBlock) & (CU - 1)));
+      } else if constexpr (HC) {
+        // separate registers for the two sources: a shared one would make
+        // the LDS read wait for every gather in flight
+        uint32_t g = 0;
+        if (u[q] >= a.hc_rows) g = a.Xc32[u[q]];
+        const uint32_t h = hubv[min(u[q], kHubRows - 1)];
+        v[q] = (double)(u[q] < a.hc_rows ? h : g);
       } else {
         v[q] = load_in<C, IN>(a, u[q], (t + q * kBlock) & (C - 1));
         if constexpr (WGT) v[q] *= a.w[min(jlo + (t + q * kBlock) / C, jmax)];
@@ -528,7 +554,7 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
         if constexpr (NP || Q4)
           reinterpret_cast<uint2 *>(vals)[f] = v2[q];
         else
-          vals[f] = v[q];
+          vals[f] = (SV)v[q];
       }
     }
     __syncthreads();
@@ -642,7 +668,7 @@ void k_step(StepArgs a, const int4 *__restrict__ blocks,
           if constexpr (NP || Q4)
             reinterpret_cast<uint2 *>(vals)[f] = v2[q];
           else
-            vals[f] = v[q];
+            vals[f] = (SV)v[q];
         }
       }
       __syncthreads();
