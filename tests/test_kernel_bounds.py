@@ -239,6 +239,42 @@ def test_step_indices_in_bounds(g):
                     check_quads(rp, ci, g.n, C, cut_div, 0, table_rows=g.n)
 
 
+K_HUB_ROWS, K_HUB_SHARE_DIV = 2048, 10
+
+
+def hub_copy_rows(g, rp):
+    """Rows of the LDS copy in single-column count steps, as graph creation
+    sets them: the first kHubRows internal rows (kHubRows or n) when they are
+    the sources of at least 1/kHubShareDiv of the arcs of an undirected
+    unweighted graph, else 0."""
+    h = min(K_HUB_ROWS, g.n)
+    nnz = int(rp[-1])
+    if g.directed or nnz == 0 or int(rp[h]) * K_HUB_SHARE_DIV < nnz:
+        return 0
+    return h
+
+
+@pytest.mark.parametrize("g", graphs(), ids=lambda g: g.name or str(g.n))
+def test_hub_copy_indices(g):
+    """The copy's loads (clamped rows, also when it is off), its LDS slots and
+    the reads of gathered sources stay in bounds; R-MAT takes the copy (on
+    BA n=20,000 too: its 2,048 rows are a tenth of the vertices)."""
+    rp, ci = internal_csr(g)
+    hc = hub_copy_rows(g, rp)
+    assert 0 <= hc <= min(K_HUB_ROWS, g.n)
+    t = np.arange(K_BLOCK)
+    for q in range(K_HUB_ROWS // K_BLOCK):
+        rows = np.minimum(t + q * K_BLOCK, max(hc - 1, 0))
+        assert rows.max() < g.n
+        assert (t + q * K_BLOCK).max() < K_HUB_ROWS  # LDS slot
+    if ci.size:
+        src = ci
+        assert np.minimum(src, K_HUB_ROWS - 1).max() < K_HUB_ROWS
+        assert (src[src < hc] < g.n).all()
+    if g.name and g.name.startswith("rmat"):
+        assert hc == K_HUB_ROWS
+
+
 def wl_need(n, nnz, deg_sum):
     return min(n, deg_sum) + nnz // WL_CHUNK + 1
 
